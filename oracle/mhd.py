@@ -1,0 +1,510 @@
+"""Compressible MHD right-hand side on the staggered mesh, ghost-zone fill,
+low-storage RK3 time step, Courant time step, conserved totals and the
+discrete adjoint of one step.  Plain float64 CPU reference.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+State: a tuple of 8 float64 tensors ``[nzt, ny, nx]`` in the order
+``rho, px, py, pz, e, bx, by, bz`` where ``e`` is the internal energy per
+unit volume (rho times the energy per unit mass of eq. ien) and ``p`` the
+momentum density.  ``nzt = nz + 2*ngz``; ``ngz = 0`` for a periodic z axis.
+
+Readings of the paper taken here (each is listed with its reason in the
+design notes of the repository):
+
+* eq. mom, eq. itv: the viscous stress enters the momentum equation with the
+  dissipative sign (+div tau with tau = +rho nu S), so that the viscous
+  dissipation Q_visc of eq. vdiss is a heating term.
+* eq. ohm: ``eta`` is a magnetic diffusivity, E = -u x B + eta curl B, and the
+  Joule heating is eta |curl B|^2 / mu, which is eta J^2 with J = curl B/mu
+  and resistivity mu*eta.
+* eq. RMnu: the shock term is nu2 * h * max(0, -div u) (a length h = the
+  smallest grid spacing turns the rate into a speed, and it acts only in
+  compression); the viscosity is spread by a maximum over three cells and
+  smoothed by a three-cell mean along x, then y, then z.
+* eq. nuij: off-diagonal (edge) viscosities average ln(nu) and exponentiate.
+* eq. ediffuse: the diffusive energy flux is nuE * rho * nu_ii * e_m *
+  d(ln e_m)/dx_i with nu_ii = dx_i <nu>; the paper's extra factor dx_i would
+  give the flux the wrong dimension and is dropped.
+* Resistivity: eta = nuB * (edge viscosity), or a constant.
+* Ideal-gas EOS: P = (gamma - 1) e.
+"""
+from dataclasses import dataclass, field, replace
+import math
+
+import torch
+
+from .stagger import Ops, AX_X, AX_Y, AX_Z
+
+__all__ = [
+    "T_CONT", "T_ADV", "T_PRES", "T_VISC", "T_LORENTZ", "T_INDUCT",
+    "T_RESIST", "T_EDIFF", "T_GRAV", "T_ALL", "T_HD", "T_IDEAL",
+    "ALPHA", "BETA", "Grid", "Params", "ghost_fill", "rhs", "rhs_nofill",
+    "step", "rk3", "courant", "stats", "step_vjp", "rhs_vjp", "FIELDS",
+    "interior_slices", "smoothed_viscosity",
+]
+
+FIELDS = ("rho", "px", "py", "pz", "e", "bx", "by", "bz")
+
+# Term switches (finer than, and implying, the &vars namelist switches
+# do_density / do_momenta / do_energy / do_mhd of the paper's appendix).
+T_CONT = 1 << 0      # eq. mass
+T_ADV = 1 << 1       # advection: -div(rho u u) and -div(e u)
+T_PRES = 1 << 2      # -grad P and -P div u
+T_VISC = 1 << 3      # div tau (eq. itv) and Q_visc (eq. vdiss)
+T_LORENTZ = 1 << 4   # J x B
+T_INDUCT = 1 << 5    # ideal part of E (eq. ohm: -u x B)
+T_RESIST = 1 << 6    # eta J in E and Joule heating
+T_EDIFF = 1 << 7     # energy diffusion (eq. ediffuse)
+T_GRAV = 1 << 8      # constant gravity along -z (Forcing, Table 1)
+T_ALL = (1 << 9) - 1
+T_HD = T_CONT | T_ADV | T_PRES | T_VISC | T_EDIFF
+T_IDEAL = T_CONT | T_ADV | T_PRES | T_LORENTZ | T_INDUCT
+
+# eq. tconst (as printed, six digits)
+ALPHA = (0.0, -0.641874, -1.31021)
+BETA = (0.46173, 0.924087, 0.390614)
+
+NU_FLOOR = 1e-30
+
+
+@dataclass(frozen=True)
+class Grid:
+    nx: int
+    ny: int
+    nz: int
+    ngz: int = 0          # ghost planes per z side (5 with walls)
+    wall: bool = False    # z bounded by closed walls (else periodic)
+    Lx: float = 1.0
+    Ly: float = 1.0
+    Lz: float = 1.0
+
+    @property
+    def nzt(self):
+        return self.nz + 2 * self.ngz
+
+    @property
+    def dx(self):
+        return self.Lx / self.nx
+
+    @property
+    def dy(self):
+        return self.Ly / self.ny
+
+    @property
+    def dz(self):
+        return self.Lz / self.nz
+
+    @property
+    def hmin(self):
+        return min(self.dx, self.dy, self.dz)
+
+    @property
+    def hmax(self):
+        return max(self.dx, self.dy, self.dz)
+
+    def ops(self):
+        return Ops(self.dx, self.dy, self.dz, wall_z=self.wall)
+
+
+@dataclass(frozen=True)
+class Params:
+    gamma: float = 5.0 / 3.0
+    mu: float = 1.0
+    gz: float = 0.0           # gravity acceleration along -z
+    nu1: float = 0.02         # c_v   (eq. RMnu)
+    nu2: float = 1.0          # c_sh
+    nu3: float = 0.02         # c_w
+    nu_const: float = 0.0     # >0: constant viscosity nu_ii = nu_const
+    c1: float = 0.0           # eq. itv
+    nuE: float = 1.0          # eq. ediffuse
+    nuB: float = 1.0          # eta = nuB * edge viscosity
+    eta_const: float = 0.0    # >0: constant magnetic diffusivity
+    Cdt: float = 0.3          # eq. courantcond
+    Cdtd: float = 0.7
+    Cdtr: float = 0.1
+    terms: int = T_ALL
+
+
+def interior_slices(grid):
+    """z-plane ranges of the interior: (centred-in-z fields, z-face fields)."""
+    if not grid.wall:
+        return slice(0, grid.nzt), slice(0, grid.nzt)
+    g0, g1 = grid.ngz, grid.ngz + grid.nz
+    return slice(g0, g1), slice(g0, g1)
+
+
+# ---------------------------------------------------------------------------
+def _safe_norm3(a, b, c):
+    """sqrt(a^2+b^2+c^2) with zero derivative where the vector vanishes."""
+    s = a * a + b * b + c * c
+    pos = s > 0
+    return torch.where(pos, torch.sqrt(torch.where(pos, s, torch.ones_like(s))),
+                       torch.zeros_like(s))
+
+
+def _relu(x):
+    """max(0, x); derivative 1 where x > 0 and 0 elsewhere."""
+    return torch.where(x > 0, x, torch.zeros_like(x))
+
+
+def smoothed_viscosity(f, grid, par, O=None):
+    """The viscosity <nu>_{max smooth} at cell centres (Section 6.1.1).
+
+    Returns (nu_tilde, pieces) where pieces holds the centred primitives the
+    Courant condition reuses.
+    """
+    O = O or grid.ops()
+    rho, px, py, pz, e, bx, by, bz = f
+    h = grid.hmin
+    P = (par.gamma - 1.0) * e
+    ux, uy, uz = px / O.xdn(rho), py / O.ydn(rho), pz / O.zdn(rho)
+    ubx, uby, ubz = O.xup(ux), O.yup(uy), O.zup(uz)
+    bbx, bby, bbz = O.xup(bx), O.yup(by), O.zup(bz)
+    D = O.ddxup(ux) + O.ddyup(uy) + O.ddzup(uz)
+    cs = torch.sqrt(par.gamma * P / rho)
+    ca = _safe_norm3(bbx, bby, bbz) / torch.sqrt(par.mu * rho)
+    if par.nu_const > 0:
+        nus = torch.full_like(rho, par.nu_const / h)
+    else:
+        nus = (par.nu1 * _safe_norm3(ubx, uby, ubz)
+               + par.nu3 * (cs + ca)
+               + par.nu2 * h * _relu(-D))
+    m = O.max3(O.max3(O.max3(nus, AX_X), AX_Y), AX_Z)
+    nt = O.mean3(O.mean3(O.mean3(m, AX_X), AX_Y), AX_Z)
+    nt = torch.where(nt > NU_FLOOR, nt, torch.full_like(nt, NU_FLOOR))
+    pieces = dict(P=P, ux=ux, uy=uy, uz=uz, ub=(ubx, uby, ubz),
+                  bb=(bbx, bby, bbz), D=D, cs=cs, ca=ca, nus=nus)
+    return nt, pieces
+
+
+def rhs_nofill(f, grid, par):
+    """Time derivatives of the 8 variables (eqs. mass, mom, ien, indu, ohm,
+    itv, vdiss, RMnu, nuij, ediffuse), evaluated on every plane of the array
+    and then zeroed where Section 10 requires (ghost planes, wall faces)."""
+    O = grid.ops()
+    T = par.terms
+    rho, px, py, pz, e, bx, by, bz = f
+    dx, dy, dz = grid.dx, grid.dy, grid.dz
+    mu = par.mu
+    zero = torch.zeros_like(rho)
+
+    # -- primitives (Section 4.1; eq. ien; ideal gas) ------------------------
+    nt, pc = smoothed_viscosity(f, grid, par, O)
+    P, ux, uy, uz, D = pc["P"], pc["ux"], pc["uy"], pc["uz"], pc["D"]
+    em = e / rho                          # energy per unit mass
+    lnt = torch.log(nt)
+
+    # -- viscosities and densities on edges (eq. nuij) -----------------------
+    nxy = max(dx, dy) * torch.exp(O.ydn(O.xdn(lnt)))    # z-edge
+    nxz = max(dx, dz) * torch.exp(O.zdn(O.xdn(lnt)))    # y-edge
+    nyz = max(dy, dz) * torch.exp(O.zdn(O.ydn(lnt)))    # x-edge
+    rxy = O.ydn(O.xdn(rho))
+    rxz = O.zdn(O.xdn(rho))
+    ryz = O.zdn(O.ydn(rho))
+
+    # -- strain and viscous stress (eq. itv) ---------------------------------
+    sxx, syy, szz = O.ddxup(ux), O.ddyup(uy), O.ddzup(uz)
+    sxy = 0.5 * (O.ddydn(ux) + O.ddxdn(uy))
+    sxz = 0.5 * (O.ddzdn(ux) + O.ddxdn(uz))
+    syz = 0.5 * (O.ddzdn(uy) + O.ddydn(uz))
+    txx = rho * (dx * nt) * (sxx + par.c1 * D)
+    tyy = rho * (dy * nt) * (syy + par.c1 * D)
+    tzz = rho * (dz * nt) * (szz + par.c1 * D)
+    txy = rxy * nxy * sxy
+    txz = rxz * nxz * sxz
+    tyz = ryz * nyz * syz
+
+    # -- current and electric field (eq. ohm, J = curl B) ---------------------
+    jx = O.ddydn(bz) - O.ddzdn(by)
+    jy = O.ddzdn(bx) - O.ddxdn(bz)
+    jz = O.ddxdn(by) - O.ddydn(bx)
+    if par.eta_const > 0:
+        etx = ety = etz = torch.full_like(rho, par.eta_const)
+    else:
+        etx, ety, etz = par.nuB * nyz, par.nuB * nxz, par.nuB * nxy
+    ex, ey, ez = zero, zero, zero
+    if T & T_INDUCT:
+        ex = ex - (O.zdn(uy) * O.ydn(bz) - O.ydn(uz) * O.zdn(by))
+        ey = ey - (O.xdn(uz) * O.zdn(bx) - O.zdn(ux) * O.xdn(bz))
+        ez = ez - (O.ydn(ux) * O.xdn(by) - O.xdn(uy) * O.ydn(bx))
+    if T & T_RESIST:
+        ex = ex + etx * jx
+        ey = ey + ety * jy
+        ez = ez + etz * jz
+
+    # -- mass (eq. mass) -------------------------------------------------------
+    drho = zero
+    if T & T_CONT:
+        drho = -(O.ddxup(px) + O.ddyup(py) + O.ddzup(pz))
+
+    # -- momentum (eq. mom) ---------------------------------------------------
+    dpx, dpy, dpz = zero, zero, zero
+    if T & T_ADV:
+        dpx = dpx - (O.ddxdn(O.xup(px) * O.xup(ux))
+                     + O.ddyup(O.ydn(px) * O.xdn(uy))
+                     + O.ddzup(O.zdn(px) * O.xdn(uz)))
+        dpy = dpy - (O.ddydn(O.yup(py) * O.yup(uy))
+                     + O.ddzup(O.zdn(py) * O.ydn(uz))
+                     + O.ddxup(O.xdn(py) * O.ydn(ux)))
+        dpz = dpz - (O.ddzdn(O.zup(pz) * O.zup(uz))
+                     + O.ddxup(O.xdn(pz) * O.zdn(ux))
+                     + O.ddyup(O.ydn(pz) * O.zdn(uy)))
+    if T & T_PRES:
+        dpx = dpx - O.ddxdn(P)
+        dpy = dpy - O.ddydn(P)
+        dpz = dpz - O.ddzdn(P)
+    if T & T_LORENTZ:
+        dpx = dpx + (O.zup(jy * O.xdn(bz)) - O.yup(jz * O.xdn(by))) / mu
+        dpy = dpy + (O.xup(jz * O.ydn(bx)) - O.zup(jx * O.ydn(bz))) / mu
+        dpz = dpz + (O.yup(jx * O.zdn(by)) - O.xup(jy * O.zdn(bx))) / mu
+    if T & T_VISC:
+        dpx = dpx + O.ddxdn(txx) + O.ddyup(txy) + O.ddzup(txz)
+        dpy = dpy + O.ddydn(tyy) + O.ddzup(tyz) + O.ddxup(txy)
+        dpz = dpz + O.ddzdn(tzz) + O.ddxup(txz) + O.ddyup(tyz)
+    if T & T_GRAV:
+        dpz = dpz - O.zdn(rho) * par.gz
+
+    # -- internal energy (eq. ien, eq. vdiss, eq. ediffuse) --------------------
+    de = zero
+    if T & T_ADV:
+        de = de - (O.ddxup(O.xdn(e) * ux) + O.ddyup(O.ydn(e) * uy)
+                   + O.ddzup(O.zdn(e) * uz))
+    if T & T_PRES:
+        de = de - P * D
+    if T & T_VISC:
+        qv = txx * sxx + tyy * syy + tzz * szz
+        qv = qv + 2.0 * (O.yup(O.xup(txy * sxy)) + O.zup(O.xup(txz * sxz))
+                         + O.zup(O.yup(tyz * syz)))
+        de = de + qv
+    if T & T_RESIST:
+        qj = (O.zup(O.yup(etx * jx * jx)) + O.zup(O.xup(ety * jy * jy))
+              + O.yup(O.xup(etz * jz * jz))) / mu
+        de = de + qj
+    if T & T_EDIFF:
+        lne = torch.log(em)
+        fx = par.nuE * O.xdn(rho) * (dx * O.xdn(nt)) * O.xdn(em) * O.ddxdn(lne)
+        fy = par.nuE * O.ydn(rho) * (dy * O.ydn(nt)) * O.ydn(em) * O.ddydn(lne)
+        fz = par.nuE * O.zdn(rho) * (dz * O.zdn(nt)) * O.zdn(em) * O.ddzdn(lne)
+        de = de + O.ddxup(fx) + O.ddyup(fy) + O.ddzup(fz)
+
+    # -- induction (eq. indu) ---------------------------------------------------
+    dbx = -(O.ddyup(ez) - O.ddzup(ey))
+    dby = -(O.ddzup(ex) - O.ddxup(ez))
+    dbz = -(O.ddxup(ey) - O.ddyup(ex))
+
+    out = [drho, dpx, dpy, dpz, de, dbx, dby, dbz]
+    if grid.wall:
+        out = _zero_ghost_rhs(out, grid)
+    return tuple(out)
+
+
+def _zero_ghost_rhs(out, grid):
+    """Section 10: time derivatives vanish in the ghost zones; the normal
+    momentum on the two wall faces stays zero."""
+    g0, g1, n = grid.ngz, grid.ngz + grid.nz, grid.nzt
+    k = torch.arange(n, dtype=torch.float64).view(n, 1, 1)
+    centred = ((k >= g0) & (k < g1)).to(torch.float64)
+    zface = ((k >= g0) & (k <= g1)).to(torch.float64)
+    pz_mask = ((k > g0) & (k < g1)).to(torch.float64)
+    res = []
+    for i, d in enumerate(out):
+        if i == 3:
+            res.append(d * pz_mask)
+        elif i == 7:
+            res.append(d * zface)
+        else:
+            res.append(d * centred)
+    return res
+
+
+def ghost_fill(f, grid):
+    """Closed-wall ghost zones (Section 10 "Closed" and the ghost-zone
+    description): ln rho and ln(e per mass) extrapolated linearly from the two
+    nearest interior cells; energy per volume = density x energy per mass;
+    parallel velocities symmetric and parallel field antisymmetric about the
+    wall; normal mass flux antisymmetric (zero on the wall face, so no mass
+    crosses it); normal field symmetric.  The lower wall is the face between
+    ghost plane ngz-1 and interior plane ngz; the upper wall is the face at
+    plane ngz+nz.  Interior values are never modified.  Periodic grids are
+    returned unchanged."""
+    if not grid.wall:
+        return tuple(f)
+    O = grid.ops()
+    rho, px, py, pz, e, bx, by, bz = f
+    g0, g1, n = grid.ngz, grid.ngz + grid.nz, grid.nzt
+    lnr = torch.log(rho)
+    lnm = torch.log(e / rho)
+
+    def extrap(q, k):
+        if k < g0:
+            d = g0 - k
+            return q[g0] + d * (q[g0] - q[g0 + 1])
+        d = k - g1 + 1
+        return q[g1 - 1] + d * (q[g1 - 1] - q[g1 - 2])
+
+    ghosts = list(range(0, g0)) + list(range(g1, n))
+    rho_p = [rho[k] for k in range(n)]
+    e_p = [e[k] for k in range(n)]
+    for k in ghosts:
+        r = torch.exp(extrap(lnr, k))
+        rho_p[k] = r
+        e_p[k] = r * torch.exp(extrap(lnm, k))
+    rho_n = torch.stack(rho_p)
+    e_n = torch.stack(e_p)
+
+    def mirror_c(k):          # centred-in-z partner plane
+        return 2 * g0 - 1 - k if k < g0 else 2 * g1 - 1 - k
+
+    rxn, ryn = O.xdn(rho_n), O.ydn(rho_n)
+    px_p = [px[k] for k in range(n)]
+    py_p = [py[k] for k in range(n)]
+    bx_p = [bx[k] for k in range(n)]
+    by_p = [by[k] for k in range(n)]
+    for k in ghosts:
+        m = mirror_c(k)
+        px_p[k] = rxn[k] * (px[m] / rxn[m])
+        py_p[k] = ryn[k] * (py[m] / ryn[m])
+        bx_p[k] = -bx[m]
+        by_p[k] = -by[m]
+    pz_p = [pz[k] for k in range(n)]
+    bz_p = [bz[k] for k in range(n)]
+    pz_p[g0] = torch.zeros_like(pz[g0])
+    pz_p[g1] = torch.zeros_like(pz[g1])
+    for k in range(0, g0):
+        pz_p[k] = -pz[2 * g0 - k]
+        bz_p[k] = bz[2 * g0 - k]
+    for k in range(g1 + 1, n):
+        pz_p[k] = -pz[2 * g1 - k]
+        bz_p[k] = bz[2 * g1 - k]
+    return (rho_n, torch.stack(px_p), torch.stack(py_p), torch.stack(pz_p),
+            e_n, torch.stack(bx_p), torch.stack(by_p), torch.stack(bz_p))
+
+
+def rhs(f, grid, par):
+    """F(f): ghost zones filled first (wall grids), then rhs_nofill."""
+    return rhs_nofill(ghost_fill(f, grid), grid, par)
+
+
+def rk3(f, rhs_fn, dt, nsteps=1, fill_fn=None):
+    """Low-storage RK3 (eqs. dfdt, ddt, tupdate, tconst) at fixed dt on any
+    tuple of arrays: for i = 1..3, dU <- alpha_i dU + F(f) (alpha_1 = 0, so
+    dU starts as F), then f <- f + beta_i dt dU.  ``fill_fn`` (boundary
+    conditions) is applied before the first evaluation and after every
+    update."""
+    fill = fill_fn or (lambda t: t)
+    f = fill(tuple(f))
+    for _ in range(nsteps):
+        U = None
+        for i in range(3):
+            F = rhs_fn(f)
+            U = list(F) if i == 0 else [ALPHA[i] * u + q for u, q in zip(U, F)]
+            bdt = BETA[i] * dt
+            f = fill(tuple(a + bdt * u for a, u in zip(f, U)))
+    return f
+
+
+def step(f, grid, par, dt, nsteps=1):
+    """nsteps RK3 steps of the MHD system; ghost zones are refilled before
+    every evaluation of F and after the last stage."""
+    return rk3(f, lambda s: rhs_nofill(s, grid, par), dt, nsteps,
+               fill_fn=lambda s: ghost_fill(s, grid))
+
+
+# ---------------------------------------------------------------------------
+def courant(f, grid, par, dfdt=None):
+    """Time step from eq. courantcond, evaluated on the interior cells:
+
+    dt = min( Cdt  * dl_min / max(c_s + c_A + |u_perp|),
+              Cdtd * dl_min / max(nu, eta * dl_max/dl_min),
+              Cdtr / max(|drho/dt|/rho, |d e_m/dt|/e_m) )
+
+    with nu the smoothed (speed-like) viscosity and eta its magnetic
+    counterpart in the same units; the third limit only when ``dfdt`` (the
+    time derivatives of f) is given.  Returns (dt, flat index of the cell that
+    sets it, which limit: 0 wave, 1 diffusion, 2 rate)."""
+    f = ghost_fill(tuple(f), grid)
+    nt, pc = smoothed_viscosity(f, grid, par)
+    rho, e = f[0], f[4]
+    ubx, uby, ubz = pc["ub"]
+    bbx, bby, bbz = pc["bb"]
+    bb = _safe_norm3(bbx, bby, bbz)
+    udotb = torch.where(bb > 0, (ubx * bbx + uby * bby + ubz * bbz) / torch.where(bb > 0, bb, torch.ones_like(bb)),
+                        torch.zeros_like(bb))
+    uu = ubx * ubx + uby * uby + ubz * ubz
+    uperp = torch.sqrt(torch.clamp(uu - udotb * udotb, min=0.0))
+    speed = pc["cs"] + pc["ca"] + uperp
+    if par.eta_const > 0:
+        eta_speed = torch.full_like(nt, par.eta_const / grid.hmin)
+    else:
+        eta_speed = par.nuB * nt
+    diff = torch.maximum(nt, eta_speed * (grid.hmax / grid.hmin))
+    sc, _ = interior_slices(grid)
+    h = grid.hmin
+    speed_i, diff_i = speed[sc], diff[sc]
+    cand = []
+    wmax = speed_i.max()
+    cand.append((par.Cdt * h / wmax.item(), int(torch.argmax(speed_i)), 0))
+    dmax = diff_i.max()
+    cand.append((par.Cdtd * h / dmax.item(), int(torch.argmax(diff_i)), 1))
+    if dfdt is not None:
+        dr = (dfdt[0] / rho)[sc]
+        dem = (dfdt[4] / e)[sc] - dr
+        rate = torch.maximum(dr.abs(), dem.abs())
+        rmax = rate.max().item()
+        if rmax > 0:
+            cand.append((par.Cdtr / rmax, int(torch.argmax(rate)), 2))
+    return min(cand, key=lambda c: c[0])
+
+
+def stats(f, grid, par):
+    """Conserved totals and diagnostics over the interior (float64):
+    mass, momentum, kinetic / magnetic / internal energy, max and rms of
+    div B (at centres, sum of ddaup B_a), max |B| component, max |u|, and the
+    counts of non-finite values and of cells with rho <= 0 or e <= 0."""
+    O = grid.ops()
+    rho, px, py, pz, e, bx, by, bz = f
+    dV = grid.dx * grid.dy * grid.dz
+    sc, _ = interior_slices(grid)
+    out = {}
+    out["mass"] = rho[sc].sum().item() * dV
+    out["mom"] = [q[sc].sum().item() * dV for q in (px, py, pz)]
+    ekin = 0.0
+    for q, r in ((px, O.xdn(rho)), (py, O.ydn(rho)), (pz, O.zdn(rho))):
+        ekin += (0.5 * q * q / r)[sc].sum().item()
+    out["ekin"] = ekin * dV
+    out["emag"] = sum((q * q)[sc].sum().item() for q in (bx, by, bz)) * dV / (2 * par.mu)
+    out["eint"] = e[sc].sum().item() * dV
+    divb = (O.ddxup(bx) + O.ddyup(by) + O.ddzup(bz))[sc]
+    out["divb_max"] = divb.abs().max().item()
+    out["divb_rms"] = math.sqrt((divb * divb).mean().item())
+    out["bmax"] = max(q[sc].abs().max().item() for q in (bx, by, bz))
+    umax = 0.0
+    for q, r in ((px, O.xdn(rho)), (py, O.ydn(rho)), (pz, O.zdn(rho))):
+        umax = max(umax, (q / r)[sc].abs().max().item())
+    out["umax"] = umax
+    nf = 0
+    for q in f:
+        nf += int((~torch.isfinite(q[sc])).sum())
+    out["n_nonfinite"] = nf
+    out["n_nonpositive"] = int(((rho[sc] <= 0) | (e[sc] <= 0)).sum())
+    return out
+
+
+# ---------------------------------------------------------------------------
+def step_vjp(f, grid, par, dt, gbar, nsteps=1):
+    """Discrete adjoint of ``step``: returns (df_end/df)^T gbar at fixed dt.
+    Non-smooth choices: max3 routes to the first maximal cell; max(0,x),
+    |v| and the viscosity floor have zero derivative on their flat side."""
+    x = tuple(t.detach().clone().requires_grad_(True) for t in f)
+    y = step(x, grid, par, dt, nsteps)
+    g = torch.autograd.grad(y, x, grad_outputs=tuple(gbar), allow_unused=True)
+    return tuple(torch.zeros_like(a) if b is None else b for a, b in zip(f, g))
+
+
+def rhs_vjp(f, grid, par, wbar):
+    """(dF/df)^T wbar for F = rhs_nofill (no ghost fill)."""
+    x = tuple(t.detach().clone().requires_grad_(True) for t in f)
+    y = rhs_nofill(x, grid, par)
+    g = torch.autograd.grad(y, x, grad_outputs=tuple(wbar), allow_unused=True)
+    return tuple(torch.zeros_like(a) if b is None else b for a, b in zip(f, g))

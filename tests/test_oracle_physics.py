@@ -1,0 +1,475 @@
+"""Pins of the oracle's right-hand side, RK3, walls, Courant step and adjoint
+against what the paper and the mathematics fix.
+
+Linear-mode tests compare with closed forms built from the operator symbols
+K(k) = (2/h) sum_p d_p sin((2p-1)kh/2) and I(k) = 2 sum_p w_p cos((2p-1)kh/2)
+(trigonometric identities of eq. deriv / eq. interp), so a dropped term, a
+wrong sign, a wrong staggering or a wrong coefficient fails one of them.
+Energy-exchange identities are discrete summation-by-parts facts: the work
+done by a force on the momentum equals, with opposite sign, what the same
+term puts into internal or magnetic energy (eqs. mom, ien, vdiss, indu, ohm).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from oracle.stagger import AX_X, AX_Y, AX_Z
+from paper_2405_02483_amd import inputs
+
+D = torch.float64
+
+
+def T(f):
+    return tuple(torch.from_numpy(np.ascontiguousarray(a)) for a in f)
+
+
+def K(k, h):
+    return (2.0 / h) * sum(w * math.sin((2 * p - 1) * k * h / 2)
+                           for p, w in enumerate(O.DERIV6, 1))
+
+
+def I(k, h):
+    return 2.0 * sum(w * math.cos((2 * p - 1) * k * h / 2)
+                     for p, w in enumerate(O.INTERP6, 1))
+
+
+def xs(n):
+    h = 1.0 / n
+    return ((torch.arange(n, dtype=D) + 0.5) * h).view(1, 1, n), (torch.arange(n, dtype=D) * h).view(1, 1, n), h
+
+
+def uniform_state(n, rho=1.0, p=(0.0, 0.0, 0.0), e=1.5, b=(0.0, 0.0, 0.0)):
+    s = (n, n, n)
+    return [torch.full(s, rho, dtype=D), torch.full(s, p[0], dtype=D),
+            torch.full(s, p[1], dtype=D), torch.full(s, p[2], dtype=D),
+            torch.full(s, e, dtype=D), torch.full(s, b[0], dtype=D),
+            torch.full(s, b[1], dtype=D), torch.full(s, b[2], dtype=D)]
+
+
+def turb(n=16, seed=7):
+    f, box, prm = inputs.turbulent(n=n, seed=seed)
+    return T(f), O.Grid(**box), O.Params(**prm)
+
+
+# ---------------------------------------------------------------------------
+def test_uniform_state_has_zero_rhs():
+    g = O.Grid(8, 8, 8)
+    p = O.Params()
+    f = uniform_state(8, 1.3, (0.2, -0.1, 0.3), 2.0, (0.5, 0.7, -0.2))
+    for d in O.rhs(f, g, p):
+        assert float(d.abs().max()) == 0.0
+
+
+def test_gravity_on_uniform_state():
+    g = O.Grid(8, 8, 8)
+    p = O.Params(gz=2.5, terms=O.T_ALL)
+    f = uniform_state(8, 1.3)
+    F = O.rhs(f, g, p)
+    assert torch.allclose(F[3], torch.full_like(F[3], -1.3 * 2.5), rtol=1e-15, atol=0)
+
+
+EPS = 1e-7
+
+
+def test_linear_sound_terms():
+    """Small ux = eps sin(k x_f): drho/dt = -rho0 eps K cos(k x_c) and
+    de/dt = -(e0 + P0) eps K cos(k x_c); small e = e0 (1 + eps sin(k x_c)):
+    dpx/dt = -(gamma-1) e0 eps K cos(k x_f)."""
+    n, m = 32, 3
+    xc, xf, h = xs(n)
+    k = 2 * math.pi * m
+    p = O.Params(nu1=0, nu2=0, nu3=0, nuE=0, terms=O.T_CONT | O.T_ADV | O.T_PRES)
+    g = O.Grid(n, n, n)
+    rho0, e0 = 1.2, 2.0
+    P0 = (p.gamma - 1) * e0
+    f = uniform_state(n, rho0, e=e0)
+    f[1] = (rho0 * EPS * torch.sin(k * xf)).expand(n, n, n).contiguous()
+    F = O.rhs(f, g, p)
+    want = -rho0 * EPS * K(k, h) * torch.cos(k * xc)
+    assert torch.allclose(F[0], want.expand_as(F[0]), rtol=0, atol=1e-12 * EPS * K(k, h))
+    want = -(e0 + P0) * EPS * K(k, h) * torch.cos(k * xc)
+    assert torch.allclose(F[4], want.expand_as(F[4]), rtol=0, atol=1e-6 * EPS * K(k, h))
+    f = uniform_state(n, rho0, e=e0)
+    f[4] = (e0 * (1 + EPS * torch.sin(k * xc))).expand(n, n, n).contiguous()
+    F = O.rhs(f, g, p)
+    want = -(p.gamma - 1) * e0 * EPS * K(k, h) * torch.cos(k * xf)
+    assert torch.allclose(F[1], want.expand_as(F[1]), rtol=0, atol=1e-6 * EPS * e0 * K(k, h))
+
+
+def test_linear_alfven_terms():
+    """B = B0 x + eps sin(k x_c) y and uy = eps sin(k x_c):
+    dpy/dt = (B0/mu) eps K I cos(k x_c) (Lorentz, edge product) and
+    dBy/dt = B0 eps K I cos(k x_c) (induction through edge E)."""
+    n, m = 32, 5
+    xc, xf, h = xs(n)
+    k = 2 * math.pi * m
+    mu, B0 = 1.7, 0.8
+    g = O.Grid(n, n, n)
+    p = O.Params(mu=mu, terms=O.T_LORENTZ | O.T_INDUCT)
+    f = uniform_state(n, 1.0, b=(B0, 0.0, 0.0))
+    f[6] = (EPS * torch.sin(k * xc)).expand(n, n, n).contiguous()
+    F = O.rhs(f, g, p)
+    want = (B0 / mu) * EPS * K(k, h) * I(k, h) * torch.cos(k * xc)
+    assert torch.allclose(F[2], want.expand_as(F[2]), rtol=0, atol=1e-6 * EPS * K(k, h))
+    f = uniform_state(n, 1.0, b=(B0, 0.0, 0.0))
+    f[2] = (EPS * torch.sin(k * xc)).expand(n, n, n).contiguous()
+    F = O.rhs(f, g, p)
+    want = B0 * EPS * K(k, h) * I(k, h) * torch.cos(k * xc)
+    assert torch.allclose(F[6], want.expand_as(F[6]), rtol=0, atol=1e-6 * EPS * K(k, h))
+
+
+@pytest.mark.parametrize("c1", [0.0, -1.0 / 3.0])
+def test_viscous_decay_rates(c1):
+    """Constant nu: shear ux = eps sin(k y_c) decays as -(nu/2) K^2 (tau has no
+    factor 2, eq. itv); compression ux = eps sin(k x_f) as -nu (1 + c1) K^2."""
+    n, m = 32, 4
+    xc, xf, h = xs(n)
+    k = 2 * math.pi * m
+    nu, rho0 = 0.013, 1.4
+    g = O.Grid(n, n, n)
+    p = O.Params(nu_const=nu, c1=c1, terms=O.T_VISC)
+    f = uniform_state(n, rho0)
+    yc = xc.view(1, n, 1)
+    f[1] = (rho0 * EPS * torch.sin(k * yc)).expand(n, n, n).contiguous()
+    F = O.rhs(f, g, p)
+    want = -0.5 * nu * rho0 * EPS * K(k, h) ** 2 * torch.sin(k * yc)
+    assert torch.allclose(F[1], want.expand_as(F[1]), rtol=0, atol=1e-9 * abs(float(want.abs().max())))
+    f = uniform_state(n, rho0)
+    f[1] = (rho0 * EPS * torch.sin(k * xf)).expand(n, n, n).contiguous()
+    F = O.rhs(f, g, p)
+    want = -nu * (1 + c1) * rho0 * EPS * K(k, h) ** 2 * torch.sin(k * xf)
+    assert torch.allclose(F[1], want.expand_as(F[1]), rtol=0, atol=1e-9 * abs(float(want.abs().max())))
+
+
+def test_resistive_decay_rate():
+    """Constant eta, u = 0: Bz = eps sin(k x_c) decays as -eta K^2."""
+    n, m = 32, 6
+    xc, xf, h = xs(n)
+    k = 2 * math.pi * m
+    eta = 0.021
+    g = O.Grid(n, n, n)
+    p = O.Params(eta_const=eta, terms=O.T_RESIST)
+    f = uniform_state(n)
+    f[7] = (EPS * torch.sin(k * xc)).expand(n, n, n).contiguous()
+    F = O.rhs(f, g, p)
+    want = -eta * EPS * K(k, h) ** 2 * torch.sin(k * xc)
+    assert torch.allclose(F[7], want.expand_as(F[7]), rtol=0, atol=1e-9 * abs(float(want.abs().max())))
+
+
+def test_energy_diffusion_rate():
+    """Constant nu, uniform rho: e = e0(1 + eps sin(k x_c)) relaxes as
+    d e/dt = -nuE nu e0 eps K^2 sin(k x_c) (eq. ediffuse, linearised)."""
+    n, m = 32, 3
+    xc, xf, h = xs(n)
+    k = 2 * math.pi * m
+    nu, nuE, e0 = 0.011, 0.7, 1.9
+    g = O.Grid(n, n, n)
+    p = O.Params(nu_const=nu, nuE=nuE, terms=O.T_EDIFF)
+    f = uniform_state(n, 1.3, e=e0)
+    f[4] = (e0 * (1 + EPS * torch.sin(k * xc))).expand(n, n, n).contiguous()
+    F = O.rhs(f, g, p)
+    want = -nuE * nu * e0 * EPS * K(k, h) ** 2 * torch.sin(k * xc)
+    assert torch.allclose(F[4], want.expand_as(F[4]), rtol=0, atol=1e-6 * abs(float(want.abs().max())))
+
+
+def test_advection_is_non_dissipative():
+    """Continuity alone with uniform velocity u0 (Section 11.1): a density
+    mode moves with the purely imaginary symbol -i u0 K I (no damping,
+    dispersive): drho/dt = -u0 eps K I cos(k x_c)."""
+    n, m = 32, 7
+    xc, xf, h = xs(n)
+    k = 2 * math.pi * m
+    u0 = 0.9
+    g = O.Grid(n, n, n)
+    p = O.Params(terms=O.T_CONT)
+    rho = 1.0 + EPS * torch.sin(k * xc)
+    f = uniform_state(n)
+    f[0] = rho.expand(n, n, n).contiguous()
+    ops = g.ops()
+    f[1] = u0 * ops.xdn(f[0])
+    F = O.rhs(f, g, p)
+    want = -u0 * EPS * K(k, h) * I(k, h) * torch.cos(k * xc)
+    assert torch.allclose(F[0], want.expand_as(F[0]), rtol=0, atol=1e-12)
+    # shorter waves travel slower (dispersive) and the phase speed is below u0
+    speeds = [u0 * K(2 * math.pi * mm, h) * I(2 * math.pi * mm, h) / (2 * math.pi * mm) for mm in (1, 4, 8, 12)]
+    assert all(a > b for a, b in zip(speeds, speeds[1:])) and speeds[0] < u0
+
+
+# ---------------------------------------------------------------------------
+def _face_u(f, g):
+    ops = g.ops()
+    return f[1] / ops.xdn(f[0]), f[2] / ops.ydn(f[0]), f[3] / ops.zdn(f[0])
+
+
+def _terms(par, mask):
+    return O.Params(**{**par.__dict__, "terms": mask})
+
+
+def test_energy_exchange_identities():
+    """Summation by parts, exact up to round-off:
+    pressure: sum u.dp|P + sum de|P = 0;  viscosity: sum u.dp|visc + sum
+    de|visc = 0;  Lorentz vs ideal induction: sum u.dp|JxB + sum B.dB|ideal/mu
+    = 0;  resistivity: sum B.dB|res/mu + sum de|res = 0;  and the flux-form
+    terms (advection of e, energy diffusion) sum to zero."""
+    f, g, par = turb(16)
+    gen = torch.Generator().manual_seed(9)
+    f = list(f)
+    f[4] = f[4] * (1.0 + 0.2 * torch.rand(f[4].shape, generator=gen, dtype=D))
+    par = O.Params(**{**par.__dict__, "mu": 1.3, "c1": -1.0 / 3.0})
+    u = _face_u(f, g)
+    B = f[5:8]
+
+    def pair(mask):
+        return O.rhs(f, g, _terms(par, mask))
+
+    def udp(F):
+        return sum(float((a * b).sum()) for a, b in zip(u, F[1:4]))
+
+    def bdb(F):
+        return sum(float((a * b).sum()) for a, b in zip(B, F[5:8])) / par.mu
+
+    for mask, a, b in ((O.T_PRES, udp, lambda F: float(F[4].sum())),
+                       (O.T_VISC, udp, lambda F: float(F[4].sum())),
+                       (O.T_RESIST, bdb, lambda F: float(F[4].sum()))):
+        F = pair(mask)
+        x, y = a(F), b(F)
+        assert abs(x + y) < 1e-12 * (abs(x) + abs(y)), (mask, x, y)
+    F1, F2 = pair(O.T_LORENTZ), pair(O.T_INDUCT)
+    x, y = udp(F1), bdb(F2)
+    assert abs(x + y) < 1e-12 * (abs(x) + abs(y))
+    for mask in (O.T_ADV, O.T_EDIFF):
+        F = pair(mask)
+        assert abs(float(F[4].sum())) < 1e-12 * float(F[4].abs().sum())
+    # viscous dissipation heats, resistivity heats
+    assert float(pair(O.T_VISC)[4].sum()) > 0 and float(pair(O.T_RESIST)[4].sum()) > 0
+
+
+def _discrete_solenoidal_b(n, seed):
+    """B = curl_up A for a random edge vector potential (test fixture)."""
+    g = O.Grid(n, n, n)
+    ops = g.ops()
+    gen = torch.Generator().manual_seed(seed)
+    A = [torch.randn(n, n, n, generator=gen, dtype=D) * (0.05 * g.dx) for _ in range(3)]
+    bx = ops.ddyup(A[2]) - ops.ddzup(A[1])
+    by = ops.ddzup(A[0]) - ops.ddxup(A[2])
+    bz = ops.ddxup(A[1]) - ops.ddyup(A[0])
+    return bx, by, bz
+
+
+def test_conservation_and_divb_periodic():
+    """Periodic box: sum of drho/dt and of dp/dt vanish (flux forms, and the
+    edge-product Lorentz force with a discretely solenoidal B); d(div B)/dt
+    vanishes for any B; and after steps mass, momentum and div B hold."""
+    f, g, par = turb(16, seed=11)
+    bx, by, bz = _discrete_solenoidal_b(16, 3)
+    f = list(f[:5]) + [bx, by, bz]
+    F = O.rhs(f, g, par)
+    scale = float(f[1].abs().sum())
+    assert abs(float(F[0].sum())) < 1e-13 * float(F[0].abs().sum())
+    for a in (1, 2, 3):
+        assert abs(float(F[a].sum())) < 1e-12 * float(F[a].abs().sum()), a
+    ops = g.ops()
+    # divergence of the induction update vanishes for an arbitrary B
+    f2 = list(turb(16, seed=12)[0])
+    F2 = O.rhs(f2, g, par)
+    ddiv = ops.ddxup(F2[5]) + ops.ddyup(F2[6]) + ops.ddzup(F2[7])
+    assert float(ddiv.abs().max()) < 1e-10 * float(F2[5].abs().max()) * 16
+    dt = O.courant(f, g, par)[0]
+    s0 = O.stats(f, g, par)
+    f1 = O.step(f, g, par, dt, 3)
+    s1 = O.stats(f1, g, par)
+    assert abs(s1["mass"] - s0["mass"]) < 1e-13 * s0["mass"]
+    for a in range(3):
+        assert abs(s1["mom"][a] - s0["mom"][a]) < 1e-13 * scale / 16 ** 3
+    bmax = max(float(q.abs().max()) for q in f1[5:8])
+    assert s1["divb_max"] * g.dx < 1e-12 * bmax
+
+
+def _rotate(f):
+    """Cyclic relabelling of axes: new (x, y, z) = old (y, z, x)."""
+    def r(a):
+        return a.permute(2, 0, 1).contiguous()
+    rho, px, py, pz, e, bx, by, bz = f
+    return [r(rho), r(py), r(pz), r(px), r(e), r(by), r(bz), r(bx)]
+
+
+def _mirror_x(f):
+    """Reflection x -> -x of the periodic box; centres i -> n-1-i, x-faces
+    i -> (n - i) mod n, x components change sign."""
+    n = f[0].shape[2]
+    ic = torch.arange(n - 1, -1, -1)
+    iface = (n - torch.arange(n)) % n
+    rho, px, py, pz, e, bx, by, bz = f
+    return [rho[..., ic], -px[..., iface], py[..., ic], pz[..., ic], e[..., ic],
+            -bx[..., iface], by[..., ic], bz[..., ic]]
+
+
+def test_cyclic_and_mirror_symmetry():
+    f, g, par = turb(16, seed=13)
+    F = O.rhs(f, g, par)
+    Fr = O.rhs(_rotate(list(f)), g, par)
+    for a, b in zip(_rotate(list(F)), Fr):
+        assert torch.allclose(a, b, rtol=0, atol=1e-11 * float(b.abs().max()))
+    Fm = O.rhs(_mirror_x(list(f)), g, par)
+    for a, b in zip(_mirror_x(list(F)), Fm):
+        assert torch.allclose(a, b, rtol=0, atol=1e-11 * float(b.abs().max()))
+
+
+def test_viscosity_formula_uniform_and_compressive():
+    """eq. RMnu on a uniform state: nu = nu1 |u| + nu3 (c_s + c_A); shock term
+    nu2 h max(0, -div u) on a compression wave."""
+    g = O.Grid(8, 8, 8)
+    p = O.Params(nu1=0.03, nu2=0.0, nu3=0.05, gamma=1.4, mu=1.0)
+    rho, e, ux, bx = 1.3, 2.1, 0.4, 0.6
+    f = uniform_state(8, rho, (rho * ux, 0, 0), e, (bx, 0, 0))
+    nt, pc = O.smoothed_viscosity(f, g, p)
+    cs = math.sqrt(p.gamma * (p.gamma - 1) * e / rho)
+    ca = bx / math.sqrt(rho)
+    assert torch.allclose(nt, torch.full_like(nt, 0.03 * ux + 0.05 * (cs + ca)), rtol=1e-14, atol=0)
+    n, m = 32, 2
+    xc, xf, h = xs(n)
+    k = 2 * math.pi * m
+    g = O.Grid(n, n, n)
+    p = O.Params(nu1=0.0, nu2=1.7, nu3=0.0)
+    f = uniform_state(n)
+    f[1] = (0.01 * torch.sin(k * xf)).expand(n, n, n).contiguous()
+    nt, pc = O.smoothed_viscosity(f, g, p)
+    Dx = 0.01 * K(k, h) * torch.cos(k * xc)
+    want = 1.7 * h * torch.clamp(-Dx, min=0).expand(n, n, n)
+    assert torch.allclose(pc["nus"], want, rtol=0, atol=1e-14)
+
+
+def test_courant_uniform_state():
+    """eq. courantcond on a uniform state with u perpendicular to B."""
+    g = O.Grid(8, 8, 8)
+    p = O.Params(nu1=0.03, nu3=0.05, nuB=1.5, Cdt=0.4, Cdtd=0.6)
+    rho, e, uy, bx = 1.3, 2.1, 0.4, 0.6
+    f = uniform_state(8, rho, (0, rho * uy, 0), e, (bx, 0, 0))
+    cs = math.sqrt(p.gamma * (p.gamma - 1) * e / rho)
+    ca = bx / math.sqrt(rho)
+    dtw = 0.4 * g.dx / (cs + ca + uy)
+    nu = 0.03 * uy + 0.05 * (cs + ca)
+    dtd = 0.6 * g.dx / (1.5 * nu)
+    dt, idx, which = O.courant(f, g, p)
+    assert math.isclose(dt, min(dtw, dtd), rel_tol=1e-14)
+    assert which == (0 if dtw < dtd else 1)
+
+
+# ---------------------------------------------------------------------------
+def test_rk3_is_third_order_to_printed_precision(golden_dir):
+    """For y' = lambda y one step multiplies by a cubic R(z), z = lambda dt.
+    Fit R from four evaluations: coefficients must be those of exp(z) to
+    third order within the six printed digits of eq. tconst."""
+    import json
+    import os
+    gj = json.load(open(os.path.join(golden_dir, "paper_constants.json")))
+    assert list(O.ALPHA) == gj["rk3"]["alpha"] and list(O.BETA) == gj["rk3"]["beta"]
+    zs = [-0.5, -0.2, 0.1, 0.3]
+    rows, vals = [], []
+    for z in zs:
+        y = O.rk3((torch.ones(1, dtype=D),), lambda s: (z * s[0],), 1.0)[0]
+        rows.append([1, z, z * z, z ** 3])
+        vals.append(float(y))
+    c = np.linalg.solve(np.array(rows), np.array(vals))
+    assert np.allclose(c, [1, 1, 0.5, 1 / 6], atol=1e-6), c
+    # a 2-variable harmonic oscillator converges at third order in dt (down
+    # to the ~5e-7 floor that the six printed digits leave)
+    errs = []
+    for nst in (5, 10, 20):
+        dt = 1.0 / nst
+        y = O.rk3((torch.ones(1, dtype=D), torch.zeros(1, dtype=D)),
+                  lambda s: (s[1], -s[0]), dt, nst)
+        errs.append(abs(float(y[0]) - math.cos(1.0)) + abs(float(y[1]) + math.sin(1.0)))
+    assert 7 < errs[0] / errs[1] < 9 and 7 < errs[1] / errs[2] < 9, errs
+
+
+# ---------------------------------------------------------------------------
+def strat(nx=6, nz=32, noise=0.0, seed=3):
+    f, box, prm = inputs.stratified(nx, nx, nz, noise=noise, seed=seed)
+    return T(f), O.Grid(**box), O.Params(**prm)
+
+
+def test_ghost_fill_rules():
+    f, g, p = strat(noise=1e-3)
+    f = O.ghost_fill(f, g)
+    ops = g.ops()
+    g0, g1, n = g.ngz, g.ngz + g.nz, g.nzt
+    lnr = torch.log(f[0][:, 0, 0])
+    # isothermal exponential atmosphere: ghosts continue ln rho exactly
+    zc = (torch.arange(n, dtype=D) - g0 + 0.5) * g.dz
+    assert torch.allclose(lnr, -4.0 * zc, atol=1e-12)
+    assert torch.allclose(f[4] / f[0], torch.full_like(f[0], 1.5), rtol=1e-12)
+    ux = f[1] / ops.xdn(f[0])
+    uy = f[2] / ops.ydn(f[0])
+    for k in range(g0):
+        m = 2 * g0 - 1 - k
+        assert torch.allclose(ux[k], ux[m], rtol=1e-13) and torch.allclose(uy[k], uy[m], rtol=1e-13)
+        assert torch.equal(f[5][k], -f[5][m]) and torch.equal(f[6][k], -f[6][m])
+        assert torch.equal(f[3][k], -f[3][2 * g0 - k]) and torch.equal(f[7][k], f[7][2 * g0 - k])
+    for k in range(g1, n):
+        m = 2 * g1 - 1 - k
+        assert torch.allclose(ux[k], ux[m], rtol=1e-13)
+        assert torch.equal(f[5][k], -f[5][m])
+        if k > g1:
+            assert torch.equal(f[3][k], -f[3][2 * g1 - k]) and torch.equal(f[7][k], f[7][2 * g1 - k])
+    assert float(f[3][g0].abs().max()) == 0.0 and float(f[3][g1].abs().max()) == 0.0
+
+
+def test_static_atmosphere_converges_at_sixth_order():
+    """Hydrostatic isothermal state with walls: the residual momentum
+    derivative is pure truncation error and drops ~64x per doubling."""
+    res = []
+    for nz in (32, 64, 128):
+        f, g, p = strat(4, nz)
+        F = O.rhs(f, g, p)
+        res.append(float(F[3].abs().max()))
+        assert float(F[0].abs().max()) == 0.0
+    assert 50 < res[0] / res[1] < 70 and 50 < res[1] / res[2] < 70, res
+
+
+def test_walls_conserve_mass_and_keep_zero_normal_flux():
+    f, g, p = strat(6, 32, noise=1e-3)
+    s0 = O.stats(f, g, p)
+    dt = O.courant(f, g, p)[0]
+    f1 = O.step(f, g, p, dt, 3)
+    s1 = O.stats(f1, g, p)
+    assert abs(s1["mass"] - s0["mass"]) < 1e-14 * s0["mass"]
+    assert float(f1[3][g.ngz].abs().max()) == 0.0
+    assert float(f1[3][g.ngz + g.nz].abs().max()) == 0.0
+
+
+# ---------------------------------------------------------------------------
+def _dot(a, b):
+    return sum(float((x * y).sum()) for x, y in zip(a, b))
+
+
+@pytest.mark.parametrize("kind", ["periodic", "wall"])
+def test_adjoint_matches_central_differences(kind):
+    """<(d step/d f)^T gbar, v> against (step(f + eps v) - step(f - eps v))/2eps
+    dotted with gbar, for random directions v.  The step is only piecewise
+    smooth (max over three cells, max(0, -div u)), so eps is kept small enough
+    not to cross a kink."""
+    if kind == "periodic":
+        f, g, p = turb(8, seed=21)
+    else:
+        f, g, p = strat(6, 16, noise=1e-3)
+        f = O.ghost_fill(f, g)
+    dt = 0.5 * O.courant(f, g, p)[0]
+    gen = torch.Generator().manual_seed(5)
+    gbar = tuple(torch.randn(a.shape, generator=gen, dtype=D) for a in f)
+    adj = O.step_vjp(f, g, p, dt, gbar, nsteps=2)
+    for _ in range(3):
+        v = tuple(torch.randn(a.shape, generator=gen, dtype=D) * a.abs().mean() for a in f)
+        if kind == "wall":
+            # perturb interior only: ghost values are overwritten by the fill
+            sc = slice(g.ngz, g.ngz + g.nz)
+            v = tuple(torch.zeros_like(a).index_copy(0, torch.arange(sc.start, sc.stop), a[sc]) for a in v)
+        eps = 1e-7
+        fp = O.step(tuple(a + eps * b for a, b in zip(f, v)), g, p, dt, 2)
+        fm = O.step(tuple(a - eps * b for a, b in zip(f, v)), g, p, dt, 2)
+        fd = _dot(gbar, [(a - b) / (2 * eps) for a, b in zip(fp, fm)])
+        ad = _dot(adj, v)
+        assert abs(fd - ad) < 1e-6 * abs(fd), (fd, ad)
