@@ -1,0 +1,190 @@
+/*
+ * mhd.h - C ABI of libstaggermhd: the staggered-mesh compressible MHD
+ * right-hand side and its low-storage third-order Runge-Kutta advance on
+ * AMD Instinct MI355X (gfx950), after Stein, Nordlund, Collet & Trampedach,
+ * "The Stagger Code for Accurate and Efficient, Radiation-Coupled MHD
+ * Simulations" (arXiv:2405.02483).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * State.  Eight arrays, always in this order (Section 4.1 "Centering"):
+ *     0 rho   density                        cell centre
+ *     1 px    momentum density, x            x-face at the lower index side
+ *     2 py    momentum density, y            y-face
+ *     3 pz    momentum density, z            z-face
+ *     4 e     internal energy per volume     cell centre   (eq. ien: rho*e)
+ *     5 bx    magnetic field, x              x-face
+ *     6 by    magnetic field, y              y-face
+ *     7 bz    magnetic field, z              z-face
+ *   Element (i, j, k) of box b sits at offset box_offset(b) + (k*ny + j)*nx + i
+ *   (x fastest), k = 0 .. nz + 2*ngz - 1 counting ghost planes.  A face
+ *   array's element i is the face between cells i-1 and i.
+ *   Boxes of a context are packed back to back in the same eight arrays
+ *   (ensembles); mhd_box_offset() gives each box's first element.
+ * Memory.  Every field pointer is a DEVICE pointer to a caller-owned array of
+ *   mhd_field_elems() elements of the context's dtype (float or double),
+ *   at least 16-byte aligned.  The library never frees caller memory.  The
+ *   context owns its own device workspace (intermediate arrays, reduction
+ *   partials), allocated in mhd_init / on first use and freed by
+ *   mhd_destroy.
+ * Streams.  All calls enqueue work on the HIP stream given to mhd_init and
+ *   return without waiting, except mhd_reductions, which waits for its own
+ *   result.  Calls that share one context must not run concurrently.
+ * Errors.  Every int-returning call returns MHD_OK (0) or a negative code and
+ *   never aborts; mhd_last_error() describes the last failure of the context.
+ *   Argument checks (null pointers, sizes, dtype) happen before any work is
+ *   enqueued.
+ */
+#ifndef STAGGER_MHD_H
+#define STAGGER_MHD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    MHD_OK = 0,
+    MHD_EINVAL = -1,        /* bad argument (null pointer, size, parameter)   */
+    MHD_ENOMEM = -2,        /* device allocation failed                       */
+    MHD_EHIP = -3,          /* a HIP runtime call failed                      */
+    MHD_EDTYPE = -4,        /* unknown dtype                                  */
+    MHD_ENONFINITE = -5,    /* non-finite or non-positive state detected      */
+    MHD_EUNSUPPORTED = -6   /* valid request this build does not implement    */
+};
+
+enum { MHD_F32 = 0, MHD_F64 = 1 };
+
+/* z boundary.  x and y are always periodic (Section 10). */
+enum {
+    MHD_BC_PERIODIC = 0,    /* periodic z, ngz must be 0                       */
+    MHD_BC_WALL = 1         /* closed walls with ngz >= 5 ghost planes per side */
+};
+
+/* Term switches (a finer form of the &vars namelist switches do_density,
+ * do_momenta, do_energy, do_mhd of the paper's appendix).                    */
+#define MHD_T_CONT     (1u << 0)   /* eq. mass                                 */
+#define MHD_T_ADV      (1u << 1)   /* -div(rho u u), -div(e u)                 */
+#define MHD_T_PRES     (1u << 2)   /* -grad P, -P div u                        */
+#define MHD_T_VISC     (1u << 3)   /* div tau (eq. itv), Q_visc (eq. vdiss)    */
+#define MHD_T_LORENTZ  (1u << 4)   /* J x B                                    */
+#define MHD_T_INDUCT   (1u << 5)   /* -u x B in E (eq. ohm)                    */
+#define MHD_T_RESIST   (1u << 6)   /* eta J in E and Joule heating             */
+#define MHD_T_EDIFF    (1u << 7)   /* energy diffusion (eq. ediffuse)          */
+#define MHD_T_GRAV     (1u << 8)   /* constant gravity along -z (Table 1)      */
+#define MHD_T_ALL      ((1u << 9) - 1u)
+
+/* One box of the mesh (&grid namelist: mx, my, mz, sx, sy, sz). */
+typedef struct {
+    int32_t nx, ny, nz;     /* interior cells; each >= 6                       */
+    int32_t ngz;            /* ghost planes per z side: 0 periodic; walls: 5 <= ngz <= nz */
+    int32_t bc_z;           /* MHD_BC_PERIODIC or MHD_BC_WALL                  */
+    int32_t reserved;       /* must be 0                                       */
+    double Lx, Ly, Lz;      /* box size; dx = Lx/nx, dy = Ly/ny, dz = Lz/nz    */
+} mhd_box;
+
+/* Physical and numerical parameters (&pde, &run, &force namelists).         */
+typedef struct {
+    int32_t dtype;          /* MHD_F32 or MHD_F64: storage and arithmetic      */
+    int32_t nbox;           /* number of boxes (>1: packed ensemble)           */
+    const mhd_box* boxes;   /* host array of nbox boxes, copied by mhd_init    */
+    double gamma;           /* ideal-gas ratio of specific heats, > 1          */
+    double mu;              /* permeability; J = curl B / mu (eq. mom)         */
+    double gz;              /* gravity along -z (with MHD_T_GRAV)              */
+    double nu1, nu2, nu3;   /* eq. RMnu: c_v, c_sh, c_w                        */
+    double nu_const;        /* > 0: constant viscosity nu_ii = nu_const        */
+    double c1;              /* eq. itv                                         */
+    double nuE;             /* eq. ediffuse: c_E                               */
+    double nuB;             /* magnetic diffusivity = nuB * edge viscosity     */
+    double eta_const;       /* > 0: constant magnetic diffusivity instead      */
+    double Cdt, Cdtd, Cdtr; /* eq. courantcond                                 */
+    uint32_t terms;         /* MHD_T_* bit set                                 */
+    int32_t reserved;       /* must be 0                                       */
+} mhd_params;
+
+/* Conserved totals and diagnostics over the interior cells (float64).     */
+typedef struct {
+    double mass;            /* sum rho dV                                      */
+    double mom[3];          /* sum p_a dV                                      */
+    double ekin;            /* sum over faces of p_a^2 / (2 rho_a) dV           */
+    double emag;            /* sum over faces of B_a^2 / (2 mu) dV              */
+    double eint;            /* sum e dV                                        */
+    double divb_max;        /* max |div B| at centres                          */
+    double divb_rms;        /* rms of div B                                    */
+    double bmax;            /* max |B_a| over face components                  */
+    double umax;            /* max |u_a| over face components                  */
+    double cmax;            /* max (c_s + c_A + |u_perp B|) at centres         */
+    double numax;           /* max diffusion speed max(nu, eta hmax/hmin), with
+                               nu, eta the speed-like viscosity and resistivity */
+    double ratemax;         /* max(|drho/dt|/rho, |d e_m/dt|/e_m); 0 if no dfdt */
+    double dt;              /* eq. courantcond: min of the limits below        */
+    double dt_wave, dt_diff, dt_rate;   /* each limit (dt_rate = inf if none)  */
+    int64_t dt_argmax;      /* box-local flat index of the cell setting dt     */
+    int32_t dt_box;         /* box of that cell                                */
+    int32_t dt_limit;       /* 0 wave, 1 diffusion, 2 rate                     */
+    int64_t n_nonfinite;    /* non-finite values among the 8 fields            */
+    int64_t n_nonpositive;  /* cells with rho <= 0 or e <= 0                    */
+} mhd_stats;
+
+typedef struct mhd_ctx mhd_ctx;
+
+/* Create a context for the boxes and parameters in *p, bound to hip_stream
+ * (a hipStream_t; NULL = the null stream) on the current device.  Checks
+ * every box (n >= 6; walls need ngz >= 5 and ngz == 0 otherwise) and
+ * parameter (gamma > 1, mu > 0, viscosity and diffusion coefficients >= 0)
+ * and allocates the workspace.  On success *out owns it.                   */
+int mhd_init(const mhd_params* p, void* hip_stream, mhd_ctx** out);
+
+/* Release the context and its workspace (waits for the stream).  NULL ok.  */
+void mhd_destroy(mhd_ctx* ctx);
+
+/* Text of the last error of ctx (or of the last failed mhd_init if NULL).  */
+const char* mhd_last_error(const mhd_ctx* ctx);
+
+/* Elements per field array (all boxes, ghost planes included).             */
+int64_t mhd_field_elems(const mhd_ctx* ctx);
+
+/* First element of box b in the packed arrays; -1 if b is out of range.    */
+int64_t mhd_box_offset(const mhd_ctx* ctx, int32_t b);
+
+/* dfdt = F(f): the time derivatives of the eight variables (eqs. mass, mom,
+ * ien, indu, ohm, itv, vdiss, RMnu, nuij, ediffuse).  With walls the ghost
+ * planes of f are filled first (written in place; interior untouched) and
+ * dfdt is zero in ghost planes and for pz on the wall faces (Section 10).
+ * f and dfdt must not overlap.                                             */
+int mhd_rhs(mhd_ctx* ctx, void* const f[8], void* const dfdt[8]);
+
+/* Advance f by nsteps steps of the low-storage RK3 scheme (eqs. ddt,
+ * tupdate, tconst) at fixed dt:  per stage i, dU <- alpha_i dU + F(f),
+ * f <- f + beta_i dt dU.  The result is in f.  tmp1, tmp2 (8 arrays each)
+ * hold the stage states, dU the 2N-storage derivative; their contents on
+ * return are unspecified.  With walls, ghost planes are refilled before
+ * every evaluation of F and after the last stage.                          */
+int mhd_step(mhd_ctx* ctx, void* const f[8], void* const tmp1[8],
+             void* const tmp2[8], void* const dU[8], double dt, int32_t nsteps);
+
+/* Discrete adjoint of one mhd_step at fixed dt (dt is not differentiated):
+ * gbar_out = (d f_{n+1} / d f_n)^T gbar_in, evaluated at the state f_n.
+ * Non-smooth points use: max over three cells routes to the first maximal
+ * cell (order i-1, i, i+1; passes along x, then y, then z); max(0, x), |v|
+ * and the viscosity floor have zero derivative on their flat side.
+ * Periodic boxes only (MHD_EUNSUPPORTED with walls).  f_n is not modified;
+ * gbar_in and gbar_out must not overlap.                                   */
+int mhd_step_adjoint(mhd_ctx* ctx, void* const f_n[8], double dt,
+                     void* const gbar_in[8], void* const gbar_out[8]);
+
+/* Float64 totals, diagnostics and the Courant time step (eq. courantcond)
+ * of state f over the interior of all boxes; writes *out (host memory) and
+ * waits for the stream.  dfdt may be NULL; if given (the time derivatives of
+ * f) the rate limit Cdtr enters dt.  With walls, ghost planes of f are
+ * filled first.  Returns MHD_ENONFINITE (after filling *out) when a
+ * non-finite value or a non-positive rho or e is present.                  */
+int mhd_reductions(mhd_ctx* ctx, void* const f[8], void* const dfdt[8],
+                   mhd_stats* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STAGGER_MHD_H */

@@ -1,0 +1,444 @@
+// C ABI of libstaggermhd (declared in include/mhd.h): context set-up,
+// argument checks, workspace ownership and the sequencing of the kernel
+// passes for mhd_rhs, mhd_step, mhd_step_adjoint and mhd_reductions.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/mhd.h"
+#include "mhd_kernels.hpp"
+
+using namespace smhd;
+
+struct mhd_ctx {
+  mhd_params p;
+  std::vector<mhd_box> boxes;
+  std::vector<long long> offsets;
+  long long nelem = 0;
+  size_t esize = 0;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  std::string err;
+  // device tables
+  BoxDev* d_boxes = nullptr;
+  Blk* d_tab = nullptr;
+  int nblk = 0;
+  Blk* d_gtab = nullptr;
+  int ngblk = 0;
+  std::vector<BoxDev> h_boxes;
+  // workspace
+  void* work = nullptr;            // kWorkArrays * nelem elements
+  RedPartial* d_part = nullptr;    // nblk + 1 records (last = total)
+  void* adj = nullptr;             // adjoint workspace (allocated on first use)
+  size_t adj_bytes = 0;
+};
+
+static std::string g_init_err;
+static constexpr int kWorkArrays = 32;
+
+static int fail(mhd_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg; else g_init_err = msg;
+  return code;
+}
+
+static int hipfail(mhd_ctx* c, hipError_t e, const char* what) {
+  return fail(c, MHD_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+template <class T> static Phys<T> make_phys(const mhd_params& p) {
+  Phys<T> ph;
+  ph.gamma = T(p.gamma);
+  ph.gamma1 = T(p.gamma - 1.0);
+  ph.mu = T(p.mu);
+  ph.inv_mu = T(1.0 / p.mu);
+  ph.gz = T(p.gz);
+  ph.nu1 = T(p.nu1);
+  ph.nu2 = T(p.nu2);
+  ph.nu3 = T(p.nu3);
+  ph.nu_const = T(p.nu_const);
+  ph.c1 = T(p.c1);
+  ph.nuE = T(p.nuE);
+  ph.nuB = T(p.nuB);
+  ph.eta_const = T(p.eta_const);
+  ph.terms = p.terms;
+  return ph;
+}
+
+template <class T> static Work<T> make_work(const mhd_ctx* c) {
+  T* base = static_cast<T*>(c->work);
+  const long long n = c->nelem;
+  auto a = [&](int q) { return base + (long long)q * n; };
+  Work<T> w;
+  w.ux = a(0);
+  w.uy = a(1);
+  w.uz = a(2);
+  w.nus = a(3);
+  w.nmax = a(4);
+  w.nt = a(5);
+  w.lnt = a(6);
+  for (int q = 0; q < 8; ++q) {
+    w.ez.p[q] = q < 6 ? a(7 + q) : nullptr;
+    w.ey.p[q] = q < 6 ? a(13 + q) : nullptr;
+    w.ex.p[q] = q < 6 ? a(19 + q) : nullptr;
+    w.cf.p[q] = q < 7 ? a(25 + q) : nullptr;
+  }
+  return w;
+}
+
+static Launch make_launch(const mhd_ctx* c) {
+  Launch L;
+  L.boxes = c->d_boxes;
+  L.tab = c->d_tab;
+  L.nblk = c->nblk;
+  L.gtab = c->d_gtab;
+  L.nghost_blk = c->ngblk;
+  L.stream = c->stream;
+  return L;
+}
+
+template <class T> static P8<T> p8(void* const f[8]) {
+  P8<T> r;
+  for (int q = 0; q < 8; ++q) r.p[q] = static_cast<T*>(f[q]);
+  return r;
+}
+template <class T> static CP8<T> cp8(void* const f[8]) {
+  CP8<T> r;
+  for (int q = 0; q < 8; ++q) r.p[q] = static_cast<const T*>(f ? f[q] : nullptr);
+  return r;
+}
+template <class T> static CP8<T> cp8(const P8<T>& f) {
+  CP8<T> r;
+  for (int q = 0; q < 8; ++q) r.p[q] = f.p[q];
+  return r;
+}
+template <class T> static P8<T> p8null() {
+  P8<T> r;
+  for (int q = 0; q < 8; ++q) r.p[q] = nullptr;
+  return r;
+}
+
+static int check8(mhd_ctx* c, void* const f[8], const char* name) {
+  if (!f) return fail(c, MHD_EINVAL, std::string(name) + " is NULL");
+  for (int q = 0; q < 8; ++q) {
+    if (!f[q]) return fail(c, MHD_EINVAL, std::string(name) + "[" + std::to_string(q) + "] is NULL");
+    if (reinterpret_cast<uintptr_t>(f[q]) % 16 != 0)
+      return fail(c, MHD_EINVAL, std::string(name) + " pointer not 16-byte aligned");
+  }
+  return MHD_OK;
+}
+
+static int check_launch(mhd_ctx* c, const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hipfail(c, e, what);
+  return MHD_OK;
+}
+
+// Block table: kBlock consecutive cells of one box per entry.
+static void build_tables(mhd_ctx* c, std::vector<Blk>& tab, std::vector<Blk>& gtab) {
+  for (int b = 0; b < (int)c->boxes.size(); ++b) {
+    const BoxDev& d = c->h_boxes[b];
+    for (long long s = 0; s < d.ncell; s += kBlock) {
+      Blk t;
+      t.box = b;
+      t.start = s;
+      t.n = (int)std::min<long long>(kBlock, d.ncell - s);
+      tab.push_back(t);
+    }
+    if (d.wall) {
+      const long long ng = (long long)d.nx * d.ny * 2 * d.ngz;
+      for (long long s = 0; s < ng; s += kBlock) {
+        Blk t;
+        t.box = b;
+        t.start = s;
+        t.n = (int)std::min<long long>(kBlock, ng - s);
+        gtab.push_back(t);
+      }
+    }
+  }
+}
+
+extern "C" {
+
+const char* mhd_last_error(const mhd_ctx* c) { return c ? c->err.c_str() : g_init_err.c_str(); }
+
+int64_t mhd_field_elems(const mhd_ctx* c) { return c ? c->nelem : -1; }
+
+int64_t mhd_box_offset(const mhd_ctx* c, int32_t b) {
+  if (!c || b < 0 || b >= (int)c->offsets.size()) return -1;
+  return c->offsets[b];
+}
+
+void mhd_destroy(mhd_ctx* c) {
+  if (!c) return;
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  else (void)hipDeviceSynchronize();
+  (void)hipFree(c->d_boxes);
+  (void)hipFree(c->d_tab);
+  (void)hipFree(c->d_gtab);
+  (void)hipFree(c->work);
+  (void)hipFree(c->d_part);
+  (void)hipFree(c->adj);
+  delete c;
+}
+
+int mhd_init(const mhd_params* p, void* hip_stream, mhd_ctx** out) {
+  if (!out) return fail(nullptr, MHD_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!p) return fail(nullptr, MHD_EINVAL, "params is NULL");
+  if (p->dtype != MHD_F32 && p->dtype != MHD_F64) return fail(nullptr, MHD_EDTYPE, "unknown dtype");
+  if (p->nbox < 1 || !p->boxes) return fail(nullptr, MHD_EINVAL, "need nbox >= 1 and a box array");
+  if (!(p->gamma > 1.0) || !(p->mu > 0.0)) return fail(nullptr, MHD_EINVAL, "need gamma > 1 and mu > 0");
+  const double nn[] = {p->nu1, p->nu2, p->nu3, p->nu_const, p->nuE, p->nuB, p->eta_const,
+                       p->Cdt, p->Cdtd, p->Cdtr};
+  for (double v : nn)
+    if (!(v >= 0.0) || !std::isfinite(v)) return fail(nullptr, MHD_EINVAL, "viscosity, diffusion and Courant coefficients must be finite and >= 0");
+  if (!std::isfinite(p->gz) || !std::isfinite(p->c1)) return fail(nullptr, MHD_EINVAL, "gz and c1 must be finite");
+  if (p->terms & ~MHD_T_ALL) return fail(nullptr, MHD_EINVAL, "unknown term bits");
+  if (p->reserved != 0) return fail(nullptr, MHD_EINVAL, "reserved field must be 0");
+
+  mhd_ctx* c = new (std::nothrow) mhd_ctx();
+  if (!c) return fail(nullptr, MHD_ENOMEM, "host allocation failed");
+  c->p = *p;
+  c->p.boxes = nullptr;
+  c->esize = p->dtype == MHD_F32 ? sizeof(float) : sizeof(double);
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  (void)hipGetDevice(&c->device);
+  long long off = 0;
+  for (int b = 0; b < p->nbox; ++b) {
+    const mhd_box& x = p->boxes[b];
+    std::string where = "box " + std::to_string(b) + ": ";
+    if (x.nx < 6 || x.ny < 6 || x.nz < 6) { delete c; return fail(nullptr, MHD_EINVAL, where + "need nx, ny, nz >= 6"); }
+    if (x.reserved != 0) { delete c; return fail(nullptr, MHD_EINVAL, where + "reserved must be 0"); }
+    if (x.bc_z == MHD_BC_PERIODIC) {
+      if (x.ngz != 0) { delete c; return fail(nullptr, MHD_EINVAL, where + "periodic z needs ngz = 0"); }
+    } else if (x.bc_z == MHD_BC_WALL) {
+      if (x.ngz < 5) { delete c; return fail(nullptr, MHD_EINVAL, where + "walls need ngz >= 5"); }
+      if (x.nz < x.ngz) { delete c; return fail(nullptr, MHD_EINVAL, where + "walls need nz >= ngz"); }
+    } else {
+      delete c;
+      return fail(nullptr, MHD_EINVAL, where + "unknown bc_z");
+    }
+    if (!(x.Lx > 0) || !(x.Ly > 0) || !(x.Lz > 0)) { delete c; return fail(nullptr, MHD_EINVAL, where + "box sizes must be > 0"); }
+    c->boxes.push_back(x);
+    BoxDev d;
+    d.nx = x.nx;
+    d.ny = x.ny;
+    d.nzt = x.nz + 2 * x.ngz;
+    d.ngz = x.ngz;
+    d.wall = x.bc_z == MHD_BC_WALL;
+    d.g0 = x.ngz;
+    d.g1 = x.ngz + x.nz;
+    d.pad = 0;
+    d.off = off;
+    d.ncell = (long long)d.nx * d.ny * d.nzt;
+    d.dx = x.Lx / x.nx;
+    d.dy = x.Ly / x.ny;
+    d.dz = x.Lz / x.nz;
+    d.hmin = std::min(d.dx, std::min(d.dy, d.dz));
+    d.hmax = std::max(d.dx, std::max(d.dy, d.dz));
+    c->h_boxes.push_back(d);
+    c->offsets.push_back(off);
+    off += d.ncell;
+  }
+  c->nelem = off;
+  std::vector<Blk> tab, gtab;
+  build_tables(c, tab, gtab);
+  c->nblk = (int)tab.size();
+  c->ngblk = (int)gtab.size();
+  hipError_t e;
+  if ((e = hipMalloc(&c->d_boxes, sizeof(BoxDev) * c->h_boxes.size())) != hipSuccess ||
+      (e = hipMalloc(&c->d_tab, sizeof(Blk) * tab.size())) != hipSuccess ||
+      (c->ngblk && (e = hipMalloc(&c->d_gtab, sizeof(Blk) * gtab.size())) != hipSuccess) ||
+      (e = hipMalloc(&c->d_part, sizeof(RedPartial) * (c->nblk + 1))) != hipSuccess ||
+      (e = hipMalloc(&c->work, (size_t)kWorkArrays * c->nelem * c->esize)) != hipSuccess) {
+    g_init_err = std::string("device allocation failed: ") + hipGetErrorString(e);
+    mhd_destroy(c);
+    return MHD_ENOMEM;
+  }
+  if ((e = hipMemcpy(c->d_boxes, c->h_boxes.data(), sizeof(BoxDev) * c->h_boxes.size(), hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(c->d_tab, tab.data(), sizeof(Blk) * tab.size(), hipMemcpyHostToDevice)) != hipSuccess ||
+      (c->ngblk && (e = hipMemcpy(c->d_gtab, gtab.data(), sizeof(Blk) * gtab.size(), hipMemcpyHostToDevice)) != hipSuccess)) {
+    g_init_err = std::string("table upload failed: ") + hipGetErrorString(e);
+    mhd_destroy(c);
+    return MHD_EHIP;
+  }
+  *out = c;
+  return MHD_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+template <class T>
+static int do_rhs(mhd_ctx* c, void* const f[8], void* const dfdt[8]) {
+  const Launch L = make_launch(c);
+  launch_ghost<T>(L, p8<T>(f));
+  StageArgs<T> a;
+  a.f = cp8<T>(f);
+  a.w = make_work<T>(c);
+  a.ph = make_phys<T>(c->p);
+  a.du_in = cp8<T>(nullptr);
+  a.du_out = p8<T>(dfdt);
+  a.f_out = p8null<T>();
+  a.alpha = T(0);
+  a.bdt = T(0);
+  launch_stage<T>(L, a);
+  return check_launch(c, "mhd_rhs launch");
+}
+
+static const double kAlpha[3] = {0.0, -0.641874, -1.31021};   // eq. tconst
+static const double kBeta[3] = {0.46173, 0.924087, 0.390614};
+
+template <class T>
+static int do_step(mhd_ctx* c, void* const f[8], void* const t1[8], void* const t2[8],
+                   void* const du[8], double dt, int nsteps) {
+  const Launch L = make_launch(c);
+  const Work<T> w = make_work<T>(c);
+  const Phys<T> ph = make_phys<T>(c->p);
+  const P8<T> F = p8<T>(f), A = p8<T>(t1), B = p8<T>(t2), U = p8<T>(du);
+  launch_ghost<T>(L, F);
+  for (int n = 0; n < nsteps; ++n) {
+    // stage states: f -> t1 -> t2 -> f (the stage input is never written)
+    const P8<T> src[3] = {F, A, B};
+    const P8<T> dst[3] = {A, B, F};
+    for (int s = 0; s < 3; ++s) {
+      StageArgs<T> a;
+      a.f = cp8<T>(src[s]);
+      a.w = w;
+      a.ph = ph;
+      a.du_in = s == 0 ? cp8<T>(nullptr) : cp8<T>(U);
+      a.du_out = s == 2 ? p8null<T>() : U;
+      a.f_out = dst[s];
+      a.alpha = T(kAlpha[s]);
+      a.bdt = T(kBeta[s] * dt);
+      launch_stage<T>(L, a);
+      launch_ghost<T>(L, dst[s]);
+    }
+  }
+  return check_launch(c, "mhd_step launch");
+}
+
+template <class T>
+static int do_reduce(mhd_ctx* c, void* const f[8], void* const dfdt[8], mhd_stats* out) {
+  const Launch L = make_launch(c);
+  const Work<T> w = make_work<T>(c);
+  const Phys<T> ph = make_phys<T>(c->p);
+  launch_ghost<T>(L, p8<T>(f));
+  launch_nu<T>(L, cp8<T>(f), w, ph);
+  launch_reduce<T>(L, cp8<T>(f), cp8<T>(dfdt), w, ph, c->d_part, c->d_part + c->nblk);
+  int rc = check_launch(c, "mhd_reductions launch");
+  if (rc) return rc;
+  RedPartial tot;
+  hipError_t e = hipMemcpyAsync(&tot, c->d_part + c->nblk, sizeof(RedPartial),
+                                hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hipfail(c, e, "mhd_reductions readback");
+  // the kernel already weights the totals by each box's cell volume
+  const BoxDev& b0 = c->h_boxes[0];
+  memset(out, 0, sizeof(*out));
+  out->mass = tot.sum[0];
+  out->mom[0] = tot.sum[1];
+  out->mom[1] = tot.sum[2];
+  out->mom[2] = tot.sum[3];
+  out->ekin = tot.sum[4];
+  out->emag = tot.sum[5] / (2.0 * c->p.mu);
+  out->eint = tot.sum[6];
+  long long ninter = 0;
+  for (const auto& b : c->boxes) ninter += (long long)b.nx * b.ny * b.nz;
+  out->divb_max = tot.mx[0];
+  out->divb_rms = std::sqrt(tot.sum[7] / (double)ninter);
+  out->bmax = tot.mx[1];
+  out->umax = tot.mx[2];
+  out->cmax = tot.mx[3];
+  out->numax = tot.mx[4];
+  out->ratemax = tot.mx[5];
+  double hmin = b0.hmin;
+  for (const auto& b : c->h_boxes) hmin = std::min(hmin, b.hmin);
+  const double inf = std::numeric_limits<double>::infinity();
+  out->dt_wave = tot.mx[3] > 0 ? c->p.Cdt * hmin / tot.mx[3] : inf;
+  out->dt_diff = tot.mx[4] > 0 ? c->p.Cdtd * hmin / tot.mx[4] : inf;
+  out->dt_rate = (dfdt && tot.mx[5] > 0) ? c->p.Cdtr / tot.mx[5] : inf;
+  long long arg = tot.arg[0];
+  out->dt = out->dt_wave;
+  out->dt_limit = 0;
+  if (out->dt_diff < out->dt) { out->dt = out->dt_diff; out->dt_limit = 1; arg = tot.arg[1]; }
+  if (out->dt_rate < out->dt) { out->dt = out->dt_rate; out->dt_limit = 2; arg = tot.arg[2]; }
+  int box = 0;
+  for (int b = 0; b < (int)c->offsets.size(); ++b)
+    if (arg >= c->offsets[b]) box = b;
+  out->dt_box = box;
+  out->dt_argmax = arg - c->offsets[box];
+  out->n_nonfinite = tot.nonfinite;
+  out->n_nonpositive = tot.nonpositive;
+  if (tot.nonfinite || tot.nonpositive) {
+    c->err = "non-finite or non-positive state";
+    return MHD_ENONFINITE;
+  }
+  return MHD_OK;
+}
+
+extern "C" {
+
+int mhd_rhs(mhd_ctx* c, void* const f[8], void* const dfdt[8]) {
+  if (!c) return fail(nullptr, MHD_EINVAL, "ctx is NULL");
+  int rc;
+  if ((rc = check8(c, f, "f")) || (rc = check8(c, dfdt, "dfdt"))) return rc;
+  for (int a = 0; a < 8; ++a)
+    for (int b = 0; b < 8; ++b)
+      if (f[a] == dfdt[b]) return fail(c, MHD_EINVAL, "f and dfdt overlap");
+  return c->p.dtype == MHD_F32 ? do_rhs<float>(c, f, dfdt) : do_rhs<double>(c, f, dfdt);
+}
+
+int mhd_step(mhd_ctx* c, void* const f[8], void* const t1[8], void* const t2[8],
+             void* const du[8], double dt, int32_t nsteps) {
+  if (!c) return fail(nullptr, MHD_EINVAL, "ctx is NULL");
+  int rc;
+  if ((rc = check8(c, f, "f")) || (rc = check8(c, t1, "tmp1")) || (rc = check8(c, t2, "tmp2")) ||
+      (rc = check8(c, du, "dU")))
+    return rc;
+  if (nsteps < 0) return fail(c, MHD_EINVAL, "nsteps < 0");
+  if (!std::isfinite(dt)) return fail(c, MHD_EINVAL, "dt not finite");
+  void* const* sets[4] = {f, t1, t2, du};
+  for (int x = 0; x < 4; ++x)
+    for (int y = x + 1; y < 4; ++y)
+      for (int a = 0; a < 8; ++a)
+        for (int b = 0; b < 8; ++b)
+          if (sets[x][a] == sets[y][b]) return fail(c, MHD_EINVAL, "state, temporaries and dU must not overlap");
+  if (nsteps == 0) return MHD_OK;
+  return c->p.dtype == MHD_F32 ? do_step<float>(c, f, t1, t2, du, dt, nsteps)
+                               : do_step<double>(c, f, t1, t2, du, dt, nsteps);
+}
+
+int mhd_reductions(mhd_ctx* c, void* const f[8], void* const dfdt[8], mhd_stats* out) {
+  if (!c) return fail(nullptr, MHD_EINVAL, "ctx is NULL");
+  if (!out) return fail(c, MHD_EINVAL, "out is NULL");
+  int rc;
+  if ((rc = check8(c, f, "f"))) return rc;
+  if (dfdt && (rc = check8(c, dfdt, "dfdt"))) return rc;
+  return c->p.dtype == MHD_F32 ? do_reduce<float>(c, f, dfdt, out)
+                               : do_reduce<double>(c, f, dfdt, out);
+}
+
+int mhd_step_adjoint(mhd_ctx* c, void* const f_n[8], double dt, void* const gin[8],
+                     void* const gout[8]) {
+  if (!c) return fail(nullptr, MHD_EINVAL, "ctx is NULL");
+  int rc;
+  if ((rc = check8(c, f_n, "f_n")) || (rc = check8(c, gin, "gbar_in")) ||
+      (rc = check8(c, gout, "gbar_out")))
+    return rc;
+  for (const auto& b : c->boxes)
+    if (b.bc_z != MHD_BC_PERIODIC) return fail(c, MHD_EUNSUPPORTED, "adjoint supports periodic boxes only");
+  if (!std::isfinite(dt)) return fail(c, MHD_EINVAL, "dt not finite");
+  for (int a = 0; a < 8; ++a)
+    for (int b = 0; b < 8; ++b)
+      if (gin[a] == gout[b] || f_n[a] == gout[b]) return fail(c, MHD_EINVAL, "gbar_out overlaps an input");
+  return fail(c, MHD_EUNSUPPORTED, "adjoint not available in this build");
+}
+
+}  // extern "C"

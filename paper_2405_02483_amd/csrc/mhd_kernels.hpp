@@ -1,0 +1,61 @@
+// Host-visible declarations shared by the kernel files and the C ABI layer.
+#pragma once
+
+#include "mhd_common.hpp"
+
+namespace smhd {
+
+// Physical parameters in the arithmetic type of the kernels.
+template <class T> struct Phys {
+  T gamma, gamma1, mu, inv_mu, gz;
+  T nu1, nu2, nu3, nu_const, c1, nuE, nuB, eta_const;
+  unsigned terms;
+};
+
+// Intermediate arrays of one RK stage (context-owned device workspace).
+template <class T> struct Work {
+  T *ux, *uy, *uz;        // face velocities
+  T *nus, *nmax, *nt, *lnt;
+  P8<T> ez, ey, ex;       // 6 arrays per edge set (only p[0..5] used)
+  P8<T> cf;               // Gxx Gyy Gzz Qc Hx Hy Hz (p[0..6])
+};
+
+// Launch geometry shared by all cell kernels of a context.
+struct Launch {
+  const BoxDev* boxes;    // device
+  const Blk* tab;         // device, nblk entries covering every cell
+  int nblk;
+  const Blk* gtab;        // device, blocks over the ghost planes of wall boxes
+  int nghost_blk;
+  hipStream_t stream;
+};
+
+template <class T> struct StageArgs {
+  CP8<T> f;               // stage input state (ghosts already filled)
+  Work<T> w;
+  Phys<T> ph;
+  CP8<T> du_in;           // nullptr in p[0]: first stage (alpha_1 = 0)
+  P8<T> du_out;           // nullptr in p[0]: do not store dU (last stage)
+  P8<T> f_out;            // nullptr in p[0]: write F to du_out instead
+  T alpha, bdt;
+};
+
+// Per-block partial results of the float64 reductions.
+constexpr int kNSum = 8;   // mass, px, py, pz, ekin, emag(B^2), eint, divb^2
+constexpr int kNMax = 7;   // |divb|, bmax, umax, cmax, numax, ratemax, (spare)
+constexpr int kNArg = 3;   // argmax of cmax, numax, ratemax (packed index)
+struct RedPartial {
+  double sum[kNSum];
+  double mx[kNMax];
+  long long arg[kNArg];
+  long long nonfinite, nonpositive;
+};
+
+template <class T> void launch_stage(const Launch& L, const StageArgs<T>& a);
+template <class T> void launch_nu(const Launch& L, CP8<T> f, const Work<T>& w, const Phys<T>& ph);
+template <class T> void launch_ghost(const Launch& L, P8<T> f);
+template <class T>
+void launch_reduce(const Launch& L, CP8<T> f, CP8<T> dfdt, const Work<T>& w, const Phys<T>& ph,
+                   RedPartial* partial, RedPartial* total);
+
+}  // namespace smhd

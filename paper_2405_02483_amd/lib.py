@@ -1,0 +1,289 @@
+"""ctypes binding of libstaggermhd.so, the C ABI declared in include/mhd.h.
+
+Argument marshalling only: every computation runs in the HIP kernels of the
+library.  Field arguments are sequences of 8 contiguous torch tensors on the
+GPU (rho, px, py, pz, e, bx, by, bz) of the context's dtype and
+``mhd_field_elems`` elements each (any shape).  If the library has not been
+built, importing this module raises; there is no CPU fallback.
+"""
+import ctypes
+import os
+
+import torch
+
+__all__ = [
+    "MHD_OK", "MHD_EINVAL", "MHD_ENOMEM", "MHD_EHIP", "MHD_EDTYPE",
+    "MHD_ENONFINITE", "MHD_EUNSUPPORTED", "MHD_F32", "MHD_F64",
+    "MHD_BC_PERIODIC", "MHD_BC_WALL", "T_CONT", "T_ADV", "T_PRES", "T_VISC",
+    "T_LORENTZ", "T_INDUCT", "T_RESIST", "T_EDIFF", "T_GRAV", "T_ALL",
+    "MhdBox", "MhdParams", "MhdStats", "MhdError", "lib_path", "load",
+    "mhd_init", "mhd_destroy", "mhd_last_error", "mhd_field_elems",
+    "mhd_box_offset", "mhd_rhs", "mhd_step", "mhd_step_adjoint",
+    "mhd_reductions", "Context",
+]
+
+MHD_OK, MHD_EINVAL, MHD_ENOMEM, MHD_EHIP, MHD_EDTYPE, MHD_ENONFINITE, MHD_EUNSUPPORTED = \
+    0, -1, -2, -3, -4, -5, -6
+MHD_F32, MHD_F64 = 0, 1
+MHD_BC_PERIODIC, MHD_BC_WALL = 0, 1
+T_CONT, T_ADV, T_PRES, T_VISC, T_LORENTZ, T_INDUCT, T_RESIST, T_EDIFF, T_GRAV = \
+    (1 << i for i in range(9))
+T_ALL = (1 << 9) - 1
+
+
+class MhdBox(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("ngz", ctypes.c_int32), ("bc_z", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("Lx", ctypes.c_double), ("Ly", ctypes.c_double), ("Lz", ctypes.c_double)]
+
+
+class MhdParams(ctypes.Structure):
+    _fields_ = [("dtype", ctypes.c_int32), ("nbox", ctypes.c_int32),
+                ("boxes", ctypes.POINTER(MhdBox)),
+                ("gamma", ctypes.c_double), ("mu", ctypes.c_double), ("gz", ctypes.c_double),
+                ("nu1", ctypes.c_double), ("nu2", ctypes.c_double), ("nu3", ctypes.c_double),
+                ("nu_const", ctypes.c_double), ("c1", ctypes.c_double), ("nuE", ctypes.c_double),
+                ("nuB", ctypes.c_double), ("eta_const", ctypes.c_double),
+                ("Cdt", ctypes.c_double), ("Cdtd", ctypes.c_double), ("Cdtr", ctypes.c_double),
+                ("terms", ctypes.c_uint32), ("reserved", ctypes.c_int32)]
+
+
+class MhdStats(ctypes.Structure):
+    _fields_ = [("mass", ctypes.c_double), ("mom", ctypes.c_double * 3),
+                ("ekin", ctypes.c_double), ("emag", ctypes.c_double), ("eint", ctypes.c_double),
+                ("divb_max", ctypes.c_double), ("divb_rms", ctypes.c_double),
+                ("bmax", ctypes.c_double), ("umax", ctypes.c_double), ("cmax", ctypes.c_double),
+                ("numax", ctypes.c_double), ("ratemax", ctypes.c_double), ("dt", ctypes.c_double),
+                ("dt_wave", ctypes.c_double), ("dt_diff", ctypes.c_double),
+                ("dt_rate", ctypes.c_double), ("dt_argmax", ctypes.c_int64),
+                ("dt_box", ctypes.c_int32), ("dt_limit", ctypes.c_int32),
+                ("n_nonfinite", ctypes.c_int64), ("n_nonpositive", ctypes.c_int64)]
+
+    def as_dict(self):
+        d = {}
+        for name, _ in self._fields_:
+            v = getattr(self, name)
+            d[name] = list(v) if name == "mom" else v
+        return d
+
+
+class MhdError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("mhd error %d: %s" % (code, msg))
+        self.code = code
+
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def lib_path():
+    return os.path.join(_HERE, "libstaggermhd.so")
+
+
+_LIB = None
+_P8 = ctypes.c_void_p * 8
+
+
+def load():
+    """Load (once) and return the ctypes handle of the library."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    path = lib_path()
+    if not os.path.exists(path):
+        raise RuntimeError("libstaggermhd.so is not built (%s); run "
+                           "`python -m paper_2405_02483_amd.csrc.build`" % path)
+    L = ctypes.CDLL(path)
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    L.mhd_init.argtypes = [ctypes.POINTER(MhdParams), vp, ctypes.POINTER(vp)]
+    L.mhd_init.restype = ctypes.c_int
+    L.mhd_destroy.argtypes = [vp]
+    L.mhd_destroy.restype = None
+    L.mhd_last_error.argtypes = [vp]
+    L.mhd_last_error.restype = ctypes.c_char_p
+    L.mhd_field_elems.argtypes = [vp]
+    L.mhd_field_elems.restype = i64
+    L.mhd_box_offset.argtypes = [vp, i32]
+    L.mhd_box_offset.restype = i64
+    L.mhd_rhs.argtypes = [vp, _P8, _P8]
+    L.mhd_rhs.restype = ctypes.c_int
+    L.mhd_step.argtypes = [vp, _P8, _P8, _P8, _P8, ctypes.c_double, i32]
+    L.mhd_step.restype = ctypes.c_int
+    L.mhd_step_adjoint.argtypes = [vp, _P8, ctypes.c_double, _P8, _P8]
+    L.mhd_step_adjoint.restype = ctypes.c_int
+    L.mhd_reductions.argtypes = [vp, _P8, ctypes.c_void_p, ctypes.POINTER(MhdStats)]
+    L.mhd_reductions.restype = ctypes.c_int
+    _LIB = L
+    return L
+
+
+def _check(rc, ctx):
+    if rc != MHD_OK:
+        msg = load().mhd_last_error(ctx).decode(errors="replace")
+        raise MhdError(rc, msg)
+
+
+# ---------------------------------------------------------------------------
+# Thin wrappers with the C names.
+def mhd_init(params, stream=None):
+    """params: MhdParams (with .boxes set).  Returns the context handle."""
+    L = load()
+    ctx = ctypes.c_void_p()
+    s = ctypes.c_void_p(stream if stream is not None else torch.cuda.current_stream().cuda_stream)
+    rc = L.mhd_init(ctypes.byref(params), s, ctypes.byref(ctx))
+    _check(rc, None)
+    return ctx
+
+
+def mhd_destroy(ctx):
+    load().mhd_destroy(ctx)
+
+
+def mhd_last_error(ctx):
+    return load().mhd_last_error(ctx).decode(errors="replace")
+
+
+def mhd_field_elems(ctx):
+    return int(load().mhd_field_elems(ctx))
+
+
+def mhd_box_offset(ctx, b):
+    return int(load().mhd_box_offset(ctx, b))
+
+
+def _ptrs(ts, n, dtype, name):
+    if ts is None:
+        return None
+    if len(ts) != 8:
+        raise ValueError("%s: need 8 arrays" % name)
+    for t in ts:
+        if not (t.is_cuda and t.dtype == dtype and t.is_contiguous() and t.numel() == n):
+            raise ValueError("%s: need contiguous %s GPU tensors of %d elements" % (name, dtype, n))
+    return _P8(*[t.data_ptr() for t in ts])
+
+
+def mhd_rhs(ctx, f, dfdt, *, dtype, n):
+    _check(load().mhd_rhs(ctx, _ptrs(f, n, dtype, "f"), _ptrs(dfdt, n, dtype, "dfdt")), ctx)
+
+
+def mhd_step(ctx, f, tmp1, tmp2, du, dt, nsteps, *, dtype, n):
+    _check(load().mhd_step(ctx, _ptrs(f, n, dtype, "f"), _ptrs(tmp1, n, dtype, "tmp1"),
+                           _ptrs(tmp2, n, dtype, "tmp2"), _ptrs(du, n, dtype, "dU"),
+                           float(dt), int(nsteps)), ctx)
+
+
+def mhd_step_adjoint(ctx, f_n, dt, gbar_in, gbar_out, *, dtype, n):
+    _check(load().mhd_step_adjoint(ctx, _ptrs(f_n, n, dtype, "f_n"), float(dt),
+                                   _ptrs(gbar_in, n, dtype, "gbar_in"),
+                                   _ptrs(gbar_out, n, dtype, "gbar_out")), ctx)
+
+
+def mhd_reductions(ctx, f, dfdt=None, *, dtype, n, allow_nonfinite=False):
+    st = MhdStats()
+    pd = _ptrs(dfdt, n, dtype, "dfdt")
+    rc = load().mhd_reductions(ctx, _ptrs(f, n, dtype, "f"),
+                               ctypes.cast(pd, ctypes.c_void_p) if pd is not None else None,
+                               ctypes.byref(st))
+    if rc == MHD_ENONFINITE and allow_nonfinite:
+        return st.as_dict()
+    _check(rc, ctx)
+    return st.as_dict()
+
+
+# ---------------------------------------------------------------------------
+_PARAM_KEYS = ("gamma", "mu", "gz", "nu1", "nu2", "nu3", "nu_const", "c1", "nuE", "nuB",
+               "eta_const", "Cdt", "Cdtd", "Cdtr")
+
+
+class Context:
+    """Owns one mhd_ctx.  ``boxes``: list of dicts with nx, ny, nz, ngz,
+    wall (bool), Lx, Ly, Lz; ``params``: dict of physical parameters."""
+
+    def __init__(self, boxes, params, dtype=torch.float32, terms=T_ALL, stream=None,
+                 device="cuda"):
+        if isinstance(boxes, dict):
+            boxes = [boxes]
+        self.dtype = dtype
+        self.device = torch.device(device)
+        self.boxes = [dict(b) for b in boxes]
+        arr = (MhdBox * len(boxes))()
+        for a, b in zip(arr, boxes):
+            a.nx, a.ny, a.nz = b["nx"], b["ny"], b["nz"]
+            a.ngz = b.get("ngz", 0)
+            a.bc_z = MHD_BC_WALL if b.get("wall", False) else MHD_BC_PERIODIC
+            a.reserved = 0
+            a.Lx, a.Ly, a.Lz = b.get("Lx", 1.0), b.get("Ly", 1.0), b.get("Lz", 1.0)
+        self._boxes_c = arr
+        p = MhdParams()
+        p.dtype = MHD_F32 if dtype == torch.float32 else MHD_F64
+        if dtype not in (torch.float32, torch.float64):
+            raise ValueError("dtype must be float32 or float64")
+        p.nbox = len(boxes)
+        p.boxes = ctypes.cast(arr, ctypes.POINTER(MhdBox))
+        defaults = dict(gamma=5.0 / 3.0, mu=1.0, gz=0.0, nu1=0.02, nu2=1.0, nu3=0.02,
+                        nu_const=0.0, c1=0.0, nuE=1.0, nuB=1.0, eta_const=0.0,
+                        Cdt=0.3, Cdtd=0.7, Cdtr=0.1)
+        defaults.update({k: v for k, v in params.items() if k in _PARAM_KEYS})
+        for k in _PARAM_KEYS:
+            setattr(p, k, float(defaults[k]))
+        p.terms = int(params.get("terms", terms))
+        p.reserved = 0
+        self.params = p
+        self.ctx = mhd_init(p, stream)
+        self.n = mhd_field_elems(self.ctx)
+        self.offsets = [mhd_box_offset(self.ctx, b) for b in range(len(boxes))]
+
+    def close(self):
+        if getattr(self, "ctx", None) is not None:
+            mhd_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- allocation helpers (torch owns all field memory) --------------------
+    def empty(self):
+        return [torch.empty(self.n, dtype=self.dtype, device=self.device) for _ in range(8)]
+
+    def zeros(self):
+        return [torch.zeros(self.n, dtype=self.dtype, device=self.device) for _ in range(8)]
+
+    def upload(self, per_box_fields):
+        """per_box_fields: list over boxes of 8 numpy/torch arrays [nzt, ny, nx]."""
+        out = self.empty()
+        for b, fields in enumerate(per_box_fields):
+            o = self.offsets[b]
+            for q in range(8):
+                src = torch.as_tensor(fields[q]).reshape(-1)
+                out[q][o:o + src.numel()].copy_(src.to(self.dtype))
+        return out
+
+    def box_view(self, fields, b):
+        bx = self.boxes[b]
+        nzt = bx["nz"] + 2 * bx.get("ngz", 0)
+        o = self.offsets[b]
+        n = nzt * bx["ny"] * bx["nx"]
+        return [t[o:o + n].view(nzt, bx["ny"], bx["nx"]) for t in fields]
+
+    # -- the entry points ------------------------------------------------------
+    def rhs(self, f, dfdt=None):
+        dfdt = dfdt if dfdt is not None else self.empty()
+        mhd_rhs(self.ctx, f, dfdt, dtype=self.dtype, n=self.n)
+        return dfdt
+
+    def step(self, f, dt, nsteps=1, work=None):
+        work = work or (self.empty(), self.empty(), self.empty())
+        mhd_step(self.ctx, f, work[0], work[1], work[2], dt, nsteps, dtype=self.dtype, n=self.n)
+        return f
+
+    def step_adjoint(self, f_n, dt, gbar_in, gbar_out=None):
+        gbar_out = gbar_out if gbar_out is not None else self.empty()
+        mhd_step_adjoint(self.ctx, f_n, dt, gbar_in, gbar_out, dtype=self.dtype, n=self.n)
+        return gbar_out
+
+    def reductions(self, f, dfdt=None, allow_nonfinite=False):
+        return mhd_reductions(self.ctx, f, dfdt, dtype=self.dtype, n=self.n,
+                              allow_nonfinite=allow_nonfinite)

@@ -1,0 +1,66 @@
+"""Argument checking of mhd_init: every rejected request returns its error
+code before any HIP call, so these run without a GPU."""
+import ctypes
+
+import pytest
+
+from paper_2405_02483_amd import lib
+
+
+def _params(**over):
+    boxes = over.pop("boxes", [dict(nx=8, ny=8, nz=8, ngz=0, bc_z=0)])
+    arr = (lib.MhdBox * len(boxes))()
+    for a, b in zip(arr, boxes):
+        a.nx, a.ny, a.nz = b["nx"], b["ny"], b["nz"]
+        a.ngz, a.bc_z, a.reserved = b.get("ngz", 0), b.get("bc_z", 0), b.get("reserved", 0)
+        a.Lx = a.Ly = a.Lz = b.get("L", 1.0)
+    p = lib.MhdParams()
+    p.dtype = over.pop("dtype", lib.MHD_F64)
+    p.nbox = over.pop("nbox", len(boxes))
+    p.boxes = ctypes.cast(arr, ctypes.POINTER(lib.MhdBox))
+    vals = dict(gamma=5 / 3, mu=1.0, gz=0.0, nu1=0.02, nu2=1.0, nu3=0.02, nu_const=0.0,
+                c1=0.0, nuE=1.0, nuB=1.0, eta_const=0.0, Cdt=0.3, Cdtd=0.7, Cdtr=0.1)
+    vals.update(over)
+    for k, v in vals.items():
+        if k not in ("terms", "reserved"):
+            setattr(p, k, v)
+    p.terms = vals.get("terms", lib.T_ALL)
+    p.reserved = vals.get("reserved", 0)
+    return p, arr
+
+
+@pytest.mark.parametrize("over,code", [
+    (dict(dtype=7), lib.MHD_EDTYPE),
+    (dict(gamma=1.0), lib.MHD_EINVAL),
+    (dict(mu=0.0), lib.MHD_EINVAL),
+    (dict(nu1=-0.1), lib.MHD_EINVAL),
+    (dict(Cdt=float("nan")), lib.MHD_EINVAL),
+    (dict(terms=1 << 12), lib.MHD_EINVAL),
+    (dict(nbox=0), lib.MHD_EINVAL),
+    (dict(boxes=[dict(nx=5, ny=8, nz=8)]), lib.MHD_EINVAL),
+    (dict(boxes=[dict(nx=8, ny=8, nz=8, ngz=5, bc_z=0)]), lib.MHD_EINVAL),
+    (dict(boxes=[dict(nx=8, ny=8, nz=8, ngz=4, bc_z=1)]), lib.MHD_EINVAL),
+    (dict(boxes=[dict(nx=8, ny=8, nz=6, ngz=7, bc_z=1)]), lib.MHD_EINVAL),
+    (dict(boxes=[dict(nx=8, ny=8, nz=8, bc_z=3)]), lib.MHD_EINVAL),
+    (dict(boxes=[dict(nx=8, ny=8, nz=8, L=0.0)]), lib.MHD_EINVAL),
+])
+def test_init_rejects_bad_arguments(over, code):
+    L = lib.load()
+    p, keep = _params(**over)
+    ctx = ctypes.c_void_p()
+    rc = L.mhd_init(ctypes.byref(p), None, ctypes.byref(ctx))
+    assert rc == code
+    assert ctx.value is None
+    assert len(L.mhd_last_error(None)) > 0
+
+
+def test_null_arguments():
+    L = lib.load()
+    ctx = ctypes.c_void_p()
+    assert L.mhd_init(None, None, ctypes.byref(ctx)) == lib.MHD_EINVAL
+    p, keep = _params()
+    assert L.mhd_init(ctypes.byref(p), None, None) == lib.MHD_EINVAL
+    null8 = (ctypes.c_void_p * 8)()
+    assert L.mhd_rhs(None, null8, null8) == lib.MHD_EINVAL
+    assert L.mhd_field_elems(None) == -1
+    L.mhd_destroy(None)
