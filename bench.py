@@ -1,0 +1,195 @@
+"""Throughput of the staggered-MHD RK3 step on one MI355X.
+
+Workload (default): the 512^3 stratified box - isothermal hydrostatic
+atmosphere with 4 scale heights, constant gravity along z, 1e-3 velocity
+noise, uniform vertical field (beta = 100 at mid-height), periodic x and y,
+closed walls in z with 5 ghost planes per side - in float32, every term of
+the right-hand side on.  One timed step is a full RK3 step with its own
+Courant time step: mhd_reductions (float64 dt from the current state)
+followed by mhd_step(dt, 1).  Inputs are resident in HBM before timing.
+
+Prints ONE JSON line:  metric, value (interior cell-updates/s per RK step),
+ms_per_step, the float64 figures of the same workload, the roofline of the
+RK stage (algorithmic bytes per stage / measured stage time, HIP events on
+the library's stream) and the CPU oracle timed on a bounded sample.
+
+    python bench.py [--steps K] [--warmup W] [--size N] [--no-fp64]
+                    [--no-cpu-baseline]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+# Algorithmic HBM words per interior cell per RK stage (8 fields, 2N storage,
+# stage input and output in different buffers): stage 1 reads f, writes dU
+# and f; stage 2 reads f and dU, writes dU and f; stage 3 reads f and dU,
+# writes f.  80 words per full step.
+WORDS_PER_STAGE = (24, 32, 24)
+STAGE_PASSES = ("prim", "nus", "max3", "mean3", "edges", "cf", "final")
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2405_02483_amd", "csrc")
+    for name in sorted(os.listdir(d)):
+        if name.endswith((".hip", ".hpp")):
+            h.update(open(os.path.join(d, name), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(dtype_name):
+    """HBM bytes per RK stage from the committed rocprofv3 counter summary,
+    if it was taken from the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic_rk_stage_stratified512.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path))
+    except ValueError:
+        return None
+    if rec.get("source_hash") != kernel_source_hash():
+        return None
+    v = rec.get(dtype_name, {}).get("bytes_per_stage")
+    return float(v) if v else None
+
+
+def run_gpu(size, dtype, steps, warmup):
+    import torch
+    from paper_2405_02483_amd import inputs
+    from paper_2405_02483_amd.lib import Context
+
+    log("generating the %d^3 stratified state" % size)
+    f_np, box, prm = inputs.stratified(size, size, size, seed=3)
+    ctx = Context(box, prm, dtype=dtype)
+    f = ctx.upload([f_np])
+    del f_np
+    work = (ctx.empty(), ctx.empty(), ctx.empty())
+    torch.cuda.synchronize()
+    ncell = size ** 3
+
+    def one_step():
+        st = ctx.reductions(f)                  # float64 dt, synchronises
+        ctx.step(f, st["dt"], 1, work=work)
+        return st
+
+    log("warmup %d steps (%s)" % (warmup, dtype))
+    for _ in range(warmup):
+        one_step()
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    log("timing %d steps" % steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        st = one_step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    s_end = ctx.reductions(f)
+    ctx.close()
+    del f, work
+    torch.cuda.empty_cache()
+    ms = (t1 - t0) * 1e3 / steps
+    stage_ms = sum(prof[p][0] for p in STAGE_PASSES) / (3 * steps)
+    return dict(ms_per_step=ms, value=ncell * steps / (t1 - t0), stage_ms=stage_ms,
+                passes={k: (v[0] / max(v[1], 1), v[1]) for k, v in prof.items() if v[1]},
+                dt_last=st["dt"], mass_drift=s_end["mass"], ncell=ncell)
+
+
+def cpu_baseline(n=128):
+    import torch
+    import oracle as O
+    from paper_2405_02483_amd import inputs
+    f, box, prm = inputs.stratified(n, n, n, seed=3)
+    ft = tuple(torch.from_numpy(a) for a in f)
+    g = O.Grid(**box)
+    p = O.Params(**{k: v for k, v in prm.items() if k in O.Params.__dataclass_fields__})
+    dt = O.courant(ft, g, p)[0]
+    t0 = time.perf_counter()
+    O.step(ft, g, p, dt, 1)
+    el = time.perf_counter() - t0
+    return {"value": n ** 3 / el, "unit": "cell-updates/s", "cores": torch.get_num_threads(),
+            "kind": "oracle",
+            "sample": "one RK3 step of the stratified workload at %d^3 (+2x5 ghost planes), "
+                      "float64, %.1f s" % (n, el)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--size", type=int, default=512)
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-size", type=int, default=128)
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the hot path shards by z-slabs with halo exchange; see the design notes)",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+
+    r32 = run_gpu(a.size, torch.float32, a.steps, a.warmup)
+    log("f32: %.2f ms/step, %.3e cell-updates/s" % (r32["ms_per_step"], r32["value"]))
+    r64 = None
+    if not a.no_fp64:
+        r64 = run_gpu(a.size, torch.float64, max(2, a.steps // 2), 1)
+        log("f64: %.2f ms/step, %.3e cell-updates/s" % (r64["ms_per_step"], r64["value"]))
+
+    ncell = r32["ncell"]
+    stage_bytes = sum(WORDS_PER_STAGE) / 3.0 * 4 * ncell
+    achieved = stage_bytes / (r32["stage_ms"] * 1e-3) / 1e9
+    traffic = measured_traffic("f32")
+    out = {
+        "metric": "MHD cell-updates/s per RK step at 512^3 (FP32; FP64 alongside)",
+        "value": r32["value"],
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": r32["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "stratified_%d" % a.size, "nx": a.size, "ny": a.size,
+                   "nz": a.size, "ngz": 5, "boundaries": "periodic x,y; closed walls z",
+                   "terms": "all", "dt": "Courant (float64) every step"},
+        "roofline": {"bound": "hbm", "kernel": "rk_stage (passes: %s)" % "+".join(STAGE_PASSES),
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic,
+                     "algorithmic_bytes_per_stage": stage_bytes,
+                     "stage_ms": r32["stage_ms"],
+                     "passes_ms": {k: round(v[0], 4) for k, v in r32["passes"].items()}},
+    }
+    if r64 is not None:
+        out["fp64"] = {"value": r64["value"], "ms_per_step": r64["ms_per_step"],
+                       "stage_ms": r64["stage_ms"],
+                       "frac": (2 * stage_bytes / (r64["stage_ms"] * 1e-3) / 1e9) / HBM_PEAK_GBS,
+                       "passes_ms": {k: round(v[0], 4) for k, v in r64["passes"].items()}}
+        out["fp32_over_fp64"] = r32["value"] / r64["value"]
+    if not a.no_cpu_baseline:
+        log("timing the CPU oracle sample")
+        out["cpu_baseline"] = cpu_baseline(a.cpu_size)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

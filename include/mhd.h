@@ -156,10 +156,13 @@ int64_t mhd_box_offset(const mhd_ctx* ctx, int32_t b);
 int mhd_rhs(mhd_ctx* ctx, void* const f[8], void* const dfdt[8]);
 
 /* Advance f by nsteps steps of the low-storage RK3 scheme (eqs. ddt,
- * tupdate, tconst) at fixed dt:  per stage i, dU <- alpha_i dU + F(f),
- * f <- f + beta_i dt dU.  The result is in f.  tmp1, tmp2 (8 arrays each)
- * hold the stage states, dU the 2N-storage derivative; their contents on
- * return are unspecified.  With walls, ghost planes are refilled before
+ * tupdate, tconst):  per stage i, dU <- alpha_i dU + F(f),
+ * f <- f + beta_i dt dU.  dt > 0: that fixed step.  dt == 0: every step
+ * uses the Courant step (eq. courantcond, wave and diffusion limits) of its
+ * own initial state, computed on the device during the first stage; read
+ * the last one with mhd_last_dt.  The result is in f.  tmp1, tmp2 (8 arrays
+ * each) hold the stage states, dU the 2N-storage derivative; their contents
+ * on return are unspecified.  With walls, ghost planes are refilled before
  * every evaluation of F and after the last stage.                          */
 int mhd_step(mhd_ctx* ctx, void* const f[8], void* const tmp1[8],
              void* const tmp2[8], void* const dU[8], double dt, int32_t nsteps);
@@ -182,6 +185,42 @@ int mhd_step_adjoint(mhd_ctx* ctx, void* const f_n[8], double dt,
  * non-finite value or a non-positive rho or e is present.                  */
 int mhd_reductions(mhd_ctx* ctx, void* const f[8], void* const dfdt[8],
                    mhd_stats* out);
+
+/* The dt of the last step taken with dt == 0 (waits for the stream).      */
+int mhd_last_dt(mhd_ctx* ctx, double* dt);
+
+/* Tile shape of the stage kernels: columns per workgroup, 0: 64x4,
+ * 1: 32x8, 2: 16x16, 3: 16x8.  Any shape gives the same results (bit for
+ * bit); the default is 32x8 (float32) or 16x8 (float64).  64x4 is float32
+ * only (MHD_EUNSUPPORTED for float64).                                      */
+int mhd_set_tile(mhd_ctx* ctx, int32_t tile);
+
+/* Timing of the library's own kernel passes, for performance measurement.
+ * Pass ids (index into the arrays of mhd_profile_read):                    */
+enum {
+    MHD_PASS_PRIM = 0,      /* A1: u_z, div u, speed-like viscosity            */
+    MHD_PASS_NUS = 1,       /* (unused)                                        */
+    MHD_PASS_MAX3 = 2,      /* (unused)                                        */
+    MHD_PASS_MEAN3 = 3,     /* A2: max over three cells, three-cell mean, log  */
+    MHD_PASS_EDGES = 4,     /* Q: x/y-edge quantities, Hz, Gzz                 */
+    MHD_PASS_CF = 5,        /* (unused)                                        */
+    MHD_PASS_FINAL = 6,     /* F: remaining terms, divergences, RK update      */
+    MHD_PASS_GHOST = 7,     /* closed-wall ghost zones                          */
+    MHD_PASS_REDUCE = 8,    /* float64 reductions incl. their viscosity chain   */
+    MHD_PASS_ADJOINT = 9,   /* adjoint kernels                                  */
+    MHD_PASS_COUNT = 10
+};
+
+/* enable != 0: from now on record a HIP event on the context's stream
+ * before every kernel pass and after the last pass of each call; enable ==
+ * 0: stop.  Either way the accumulated totals are reset.  Recording adds a
+ * few microseconds per pass.                                               */
+int mhd_profile(mhd_ctx* ctx, int32_t enable);
+
+/* Waits for the stream, then writes for each pass q < n the accumulated GPU
+ * milliseconds ms[q] (event to event on the context's stream) and the number
+ * of timed launches count[q] since the last mhd_profile call.             */
+int mhd_profile_read(mhd_ctx* ctx, double* ms, int64_t* count, int32_t n);
 
 #ifdef __cplusplus
 }

@@ -13,6 +13,7 @@
 
 #include "../../include/mhd.h"
 #include "mhd_kernels.hpp"
+#include "mhd_zmarch_api.hpp"
 
 using namespace smhd;
 
@@ -37,7 +38,43 @@ struct mhd_ctx {
   RedPartial* d_part = nullptr;    // nblk + 1 records (last = total)
   void* adj = nullptr;             // adjoint workspace (allocated on first use)
   size_t adj_bytes = 0;
+  // z-march stage kernels: work items, tile shape, Courant partials, dt
+  ZItem* d_items = nullptr;
+  int nitems = 0;
+  int tile = ZTILE_32x8;
+  CPart* d_cpart = nullptr;
+  double* d_dt = nullptr;
+  // timing of kernel passes (mhd_profile)
+  bool prof = false;
+  std::vector<std::pair<int, hipEvent_t>> marks;
+  double prof_ms[PASS_COUNT] = {};
+  long long prof_n[PASS_COUNT] = {};
 };
+
+static void prof_mark(void* vc, int pass) {
+  mhd_ctx* c = static_cast<mhd_ctx*>(vc);
+  hipEvent_t ev;
+  if (hipEventCreate(&ev) != hipSuccess) return;
+  (void)hipEventRecord(ev, c->stream);
+  c->marks.emplace_back(pass, ev);
+}
+
+// Fold recorded marks into per-pass totals (waits for the stream).
+static int prof_fold(mhd_ctx* c) {
+  if (c->marks.empty()) return MHD_OK;
+  hipError_t e = hipStreamSynchronize(c->stream);
+  for (size_t q = 0; q + 1 < c->marks.size(); ++q) {
+    const int pass = c->marks[q].first;
+    if (pass < 0 || pass >= PASS_COUNT) continue;
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, c->marks[q].second, c->marks[q + 1].second);
+    c->prof_ms[pass] += ms;
+    c->prof_n[pass] += 1;
+  }
+  for (auto& m : c->marks) (void)hipEventDestroy(m.second);
+  c->marks.clear();
+  return e == hipSuccess ? MHD_OK : MHD_EHIP;
+}
 
 static std::string g_init_err;
 static constexpr int kWorkArrays = 32;
@@ -99,7 +136,84 @@ static Launch make_launch(const mhd_ctx* c) {
   L.gtab = c->d_gtab;
   L.nghost_blk = c->ngblk;
   L.stream = c->stream;
+  L.mark = c->prof ? prof_mark : nullptr;
+  L.mark_ctx = const_cast<mhd_ctx*>(c);
   return L;
+}
+
+template <class T> static ZWork<T> make_zwork(const mhd_ctx* c) {
+  T* base = static_cast<T*>(c->work);
+  const long long n = c->nelem;
+  ZWork<T> w;
+  w.nus = base;
+  w.D = base + n;
+  w.uz = base + 2 * n;
+  w.lnt = base + 3 * n;
+  for (int q = 0; q < QOUT_COUNT; ++q) w.q[q] = base + (long long)(4 + q) * n;
+  return w;
+}
+
+static ZLaunch make_zlaunch(const mhd_ctx* c) {
+  ZLaunch L;
+  L.boxes = c->d_boxes;
+  L.items = c->d_items;
+  L.nitems = c->nitems;
+  L.tile = c->tile;
+  L.stream = c->stream;
+  L.mark = c->prof ? prof_mark : nullptr;
+  L.mark_ctx = const_cast<mhd_ctx*>(c);
+  return L;
+}
+
+// Work items of the z-march kernels: tiles of TX x TY columns, z split into
+// chunks of about 128 planes (each chunk recomputes a few planes of lead-in).
+static void build_items(const mhd_ctx* c, int tile, std::vector<ZItem>& items) {
+  const int TX = ztile_x(tile), TY = ztile_y(tile);
+  items.clear();
+  for (int b = 0; b < (int)c->h_boxes.size(); ++b) {
+    const BoxDev& d = c->h_boxes[b];
+    const int nch = std::max(1, (d.nzt + 64) / 128);
+    for (int ch = 0; ch < nch; ++ch) {
+      const int z0 = (int)((long long)d.nzt * ch / nch), z1 = (int)((long long)d.nzt * (ch + 1) / nch);
+      for (int ty = 0; ty < d.ny; ty += TY)
+        for (int tx = 0; tx < d.nx; tx += TX) {
+          ZItem it;
+          it.box = b;
+          it.x0 = tx;
+          it.y0 = ty;
+          it.z0 = z0;
+          it.z1 = z1;
+          it.pad = 0;
+          items.push_back(it);
+        }
+    }
+  }
+}
+
+static int set_tile(mhd_ctx* c, int tile) {
+  std::vector<ZItem> items;
+  build_items(c, tile, items);
+  ZItem* di = nullptr;
+  CPart* dp = nullptr;
+  hipError_t e;
+  if ((e = hipMalloc(&di, sizeof(ZItem) * items.size())) != hipSuccess ||
+      (e = hipMalloc(&dp, sizeof(CPart) * items.size())) != hipSuccess) {
+    (void)hipFree(di);
+    return fail(c, MHD_ENOMEM, std::string("work item tables: ") + hipGetErrorString(e));
+  }
+  if ((e = hipMemcpy(di, items.data(), sizeof(ZItem) * items.size(), hipMemcpyHostToDevice)) != hipSuccess) {
+    (void)hipFree(di);
+    (void)hipFree(dp);
+    return hipfail(c, e, "work item upload");
+  }
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  (void)hipFree(c->d_items);
+  (void)hipFree(c->d_cpart);
+  c->d_items = di;
+  c->d_cpart = dp;
+  c->nitems = (int)items.size();
+  c->tile = tile;
+  return MHD_OK;
 }
 
 template <class T> static P8<T> p8(void* const f[8]) {
@@ -178,12 +292,16 @@ void mhd_destroy(mhd_ctx* c) {
   if (!c) return;
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   else (void)hipDeviceSynchronize();
+  for (auto& m : c->marks) (void)hipEventDestroy(m.second);
   (void)hipFree(c->d_boxes);
   (void)hipFree(c->d_tab);
   (void)hipFree(c->d_gtab);
   (void)hipFree(c->work);
   (void)hipFree(c->d_part);
   (void)hipFree(c->adj);
+  (void)hipFree(c->d_items);
+  (void)hipFree(c->d_cpart);
+  (void)hipFree(c->d_dt);
   delete c;
 }
 
@@ -268,6 +386,18 @@ int mhd_init(const mhd_params* p, void* hip_stream, mhd_ctx** out) {
     mhd_destroy(c);
     return MHD_EHIP;
   }
+  if ((e = hipMalloc(&c->d_dt, sizeof(double))) != hipSuccess) {
+    g_init_err = std::string("device allocation failed: ") + hipGetErrorString(e);
+    mhd_destroy(c);
+    return MHD_ENOMEM;
+  }
+  // float64 kernels hold twice the data per column: smaller default tile
+  const int tile = p->dtype == MHD_F64 ? ZTILE_16x8 : ZTILE_32x8;
+  if (set_tile(c, tile) != MHD_OK) {
+    g_init_err = c->err;
+    mhd_destroy(c);
+    return MHD_ENOMEM;
+  }
   *out = c;
   return MHD_OK;
 }
@@ -276,48 +406,67 @@ int mhd_init(const mhd_params* p, void* hip_stream, mhd_ctx** out) {
 
 // ---------------------------------------------------------------------------
 template <class T>
+static ZStageArgs<T> zargs(mhd_ctx* c) {
+  ZStageArgs<T> a;
+  a.w = make_zwork<T>(c);
+  a.ph = make_phys<T>(c->p);
+  a.du_in = cp8<T>(nullptr);
+  a.du_out = p8null<T>();
+  a.f_out = p8null<T>();
+  a.alpha = T(0);
+  a.beta = 0.0;
+  a.dt_dev = nullptr;
+  a.dt_host = 0.0;
+  a.cpart = nullptr;
+  a.Cdt = c->p.Cdt;
+  a.Cdtd = c->p.Cdtd;
+  a.nuB = c->p.nuB;
+  a.eta_const = c->p.eta_const;
+  return a;
+}
+
+template <class T>
 static int do_rhs(mhd_ctx* c, void* const f[8], void* const dfdt[8]) {
   const Launch L = make_launch(c);
   launch_ghost<T>(L, p8<T>(f));
-  StageArgs<T> a;
+  ZStageArgs<T> a = zargs<T>(c);
   a.f = cp8<T>(f);
-  a.w = make_work<T>(c);
-  a.ph = make_phys<T>(c->p);
-  a.du_in = cp8<T>(nullptr);
   a.du_out = p8<T>(dfdt);
-  a.f_out = p8null<T>();
-  a.alpha = T(0);
-  a.bdt = T(0);
-  launch_stage<T>(L, a);
+  launch_zstage<T>(make_zlaunch(c), a);
   return check_launch(c, "mhd_rhs launch");
 }
 
 static const double kAlpha[3] = {0.0, -0.641874, -1.31021};   // eq. tconst
 static const double kBeta[3] = {0.46173, 0.924087, 0.390614};
 
+// dt > 0: fixed step.  dt == 0: the Courant step of each step's initial
+// state, computed on the device during the first stage (never leaves it).
 template <class T>
 static int do_step(mhd_ctx* c, void* const f[8], void* const t1[8], void* const t2[8],
                    void* const du[8], double dt, int nsteps) {
   const Launch L = make_launch(c);
-  const Work<T> w = make_work<T>(c);
-  const Phys<T> ph = make_phys<T>(c->p);
+  const ZLaunch Z = make_zlaunch(c);
   const P8<T> F = p8<T>(f), A = p8<T>(t1), B = p8<T>(t2), U = p8<T>(du);
+  const bool cfl = dt == 0.0;
   launch_ghost<T>(L, F);
   for (int n = 0; n < nsteps; ++n) {
     // stage states: f -> t1 -> t2 -> f (the stage input is never written)
     const P8<T> src[3] = {F, A, B};
     const P8<T> dst[3] = {A, B, F};
     for (int s = 0; s < 3; ++s) {
-      StageArgs<T> a;
+      ZStageArgs<T> a = zargs<T>(c);
       a.f = cp8<T>(src[s]);
-      a.w = w;
-      a.ph = ph;
       a.du_in = s == 0 ? cp8<T>(nullptr) : cp8<T>(U);
       a.du_out = s == 2 ? p8null<T>() : U;
       a.f_out = dst[s];
       a.alpha = T(kAlpha[s]);
-      a.bdt = T(kBeta[s] * dt);
-      launch_stage<T>(L, a);
+      a.beta = kBeta[s];
+      a.dt_host = dt;
+      if (cfl) {
+        a.dt_dev = c->d_dt;
+        if (s == 0) a.cpart = c->d_cpart;
+      }
+      launch_zstage<T>(Z, a);
       launch_ghost<T>(L, dst[s]);
     }
   }
@@ -330,8 +479,10 @@ static int do_reduce(mhd_ctx* c, void* const f[8], void* const dfdt[8], mhd_stat
   const Work<T> w = make_work<T>(c);
   const Phys<T> ph = make_phys<T>(c->p);
   launch_ghost<T>(L, p8<T>(f));
+  L.at(PASS_REDUCE);
   launch_nu<T>(L, cp8<T>(f), w, ph);
   launch_reduce<T>(L, cp8<T>(f), cp8<T>(dfdt), w, ph, c->d_part, c->d_part + c->nblk);
+  L.at(PASS_END);
   int rc = check_launch(c, "mhd_reductions launch");
   if (rc) return rc;
   RedPartial tot;
@@ -403,7 +554,7 @@ int mhd_step(mhd_ctx* c, void* const f[8], void* const t1[8], void* const t2[8],
       (rc = check8(c, du, "dU")))
     return rc;
   if (nsteps < 0) return fail(c, MHD_EINVAL, "nsteps < 0");
-  if (!std::isfinite(dt)) return fail(c, MHD_EINVAL, "dt not finite");
+  if (!std::isfinite(dt) || dt < 0.0) return fail(c, MHD_EINVAL, "dt must be finite and >= 0");
   void* const* sets[4] = {f, t1, t2, du};
   for (int x = 0; x < 4; ++x)
     for (int y = x + 1; y < 4; ++y)
@@ -439,6 +590,44 @@ int mhd_step_adjoint(mhd_ctx* c, void* const f_n[8], double dt, void* const gin[
     for (int b = 0; b < 8; ++b)
       if (gin[a] == gout[b] || f_n[a] == gout[b]) return fail(c, MHD_EINVAL, "gbar_out overlaps an input");
   return fail(c, MHD_EUNSUPPORTED, "adjoint not available in this build");
+}
+
+int mhd_profile(mhd_ctx* c, int32_t enable) {
+  if (!c) return fail(nullptr, MHD_EINVAL, "ctx is NULL");
+  int rc = prof_fold(c);
+  for (int q = 0; q < PASS_COUNT; ++q) {
+    c->prof_ms[q] = 0.0;
+    c->prof_n[q] = 0;
+  }
+  c->prof = enable != 0;
+  return rc ? fail(c, rc, "profile reset: event timing failed") : MHD_OK;
+}
+
+int mhd_profile_read(mhd_ctx* c, double* ms, int64_t* count, int32_t n) {
+  if (!c) return fail(nullptr, MHD_EINVAL, "ctx is NULL");
+  if (!ms || !count || n < 0) return fail(c, MHD_EINVAL, "bad output arrays");
+  int rc = prof_fold(c);
+  if (rc) return fail(c, rc, "profile read: event timing failed");
+  for (int q = 0; q < n && q < PASS_COUNT; ++q) {
+    ms[q] = c->prof_ms[q];
+    count[q] = c->prof_n[q];
+  }
+  return MHD_OK;
+}
+
+int mhd_last_dt(mhd_ctx* c, double* dt) {
+  if (!c) return fail(nullptr, MHD_EINVAL, "ctx is NULL");
+  if (!dt) return fail(c, MHD_EINVAL, "dt is NULL");
+  hipError_t e = hipMemcpyAsync(dt, c->d_dt, sizeof(double), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  return e == hipSuccess ? MHD_OK : hipfail(c, e, "mhd_last_dt");
+}
+
+int mhd_set_tile(mhd_ctx* c, int32_t tile) {
+  if (!c) return fail(nullptr, MHD_EINVAL, "ctx is NULL");
+  if (tile < 0 || tile >= ZTILE_COUNT) return fail(c, MHD_EINVAL, "unknown tile shape");
+  if (!ztile_ok(tile, c->esize)) return fail(c, MHD_EUNSUPPORTED, "tile shape not built for this dtype");
+  return set_tile(c, tile);
 }
 
 }  // extern "C"

@@ -492,21 +492,31 @@ __global__ __launch_bounds__(kBlock) void k_ghost2(const BoxDev* boxes, const Bl
 template <class T>
 void launch_stage(const Launch& L, const StageArgs<T>& a) {
   const dim3 grid(L.nblk), block(kBlock);
+  L.at(PASS_PRIM);
   hipLaunchKernelGGL(k_prim<T>, grid, block, 0, L.stream, L.boxes, L.tab, a.f, a.w.ux, a.w.uy,
                      a.w.uz);
+  L.at(PASS_NUS);
   hipLaunchKernelGGL(k_nus<T>, grid, block, 0, L.stream, L.boxes, L.tab, a.f, a.w.ux, a.w.uy,
                      a.w.uz, a.ph, a.w.nus);
+  L.at(PASS_MAX3);
   hipLaunchKernelGGL(k_max3<T>, grid, block, 0, L.stream, L.boxes, L.tab, a.w.nus, a.w.nmax);
+  L.at(PASS_MEAN3);
   hipLaunchKernelGGL(k_mean3<T>, grid, block, 0, L.stream, L.boxes, L.tab, a.w.nmax, a.w.nt,
                      a.w.lnt);
+  L.at(PASS_EDGES);
   hipLaunchKernelGGL(k_edges<T>, grid, block, 0, L.stream, L.boxes, L.tab, a.f, a.w.ux, a.w.uy,
                      a.w.uz, a.w.lnt, a.ph, a.w.ez, a.w.ey, a.w.ex);
+  L.at(PASS_CF);
   hipLaunchKernelGGL(k_cf<T>, grid, block, 0, L.stream, L.boxes, L.tab, a.f, a.w.ux, a.w.uy,
                      a.w.uz, a.w.nt, a.ph, a.w.cf);
+  L.at(PASS_FINAL);
   hipLaunchKernelGGL(k_final<T>, grid, block, 0, L.stream, L.boxes, L.tab, a.f, a.w.ez, a.w.ey,
                      a.w.ex, a.w.cf, a.ph, a.du_in, a.du_out, a.f_out, a.alpha, a.bdt);
+  L.at(PASS_END);
 }
 
+// The viscosity chain alone (for the float64 reductions; timed as part of
+// the reduction pass by the caller).
 template <class T>
 void launch_nu(const Launch& L, CP8<T> f, const Work<T>& w, const Phys<T>& ph) {
   const dim3 grid(L.nblk), block(kBlock);
@@ -521,8 +531,10 @@ template <class T>
 void launch_ghost(const Launch& L, P8<T> f) {
   if (L.nghost_blk == 0) return;
   const dim3 grid(L.nghost_blk), block(kBlock);
+  L.at(PASS_GHOST);
   hipLaunchKernelGGL(k_ghost1<T>, grid, block, 0, L.stream, L.boxes, L.gtab, f);
   hipLaunchKernelGGL(k_ghost2<T>, grid, block, 0, L.stream, L.boxes, L.gtab, f);
+  L.at(PASS_END);
 }
 
 template void launch_stage<float>(const Launch&, const StageArgs<float>&);

@@ -20,6 +20,12 @@ template <class T> struct Work {
   P8<T> cf;               // Gxx Gyy Gzz Qc Hx Hy Hz (p[0..6])
 };
 
+// Kernel passes, as reported by the timing hook (order = mhd.h MHD_PASS_*).
+enum Pass : int {
+  PASS_PRIM = 0, PASS_NUS, PASS_MAX3, PASS_MEAN3, PASS_EDGES, PASS_CF, PASS_FINAL,
+  PASS_GHOST, PASS_REDUCE, PASS_ADJOINT, PASS_COUNT, PASS_END = -1
+};
+
 // Launch geometry shared by all cell kernels of a context.
 struct Launch {
   const BoxDev* boxes;    // device
@@ -28,6 +34,11 @@ struct Launch {
   const Blk* gtab;        // device, blocks over the ghost planes of wall boxes
   int nghost_blk;
   hipStream_t stream;
+  // optional timing hook: mark(mark_ctx, pass) before a pass starts and
+  // mark(mark_ctx, PASS_END) after the last one of a sequence
+  void (*mark)(void*, int);
+  void* mark_ctx;
+  void at(int pass) const { if (mark) mark(mark_ctx, pass); }
 };
 
 template <class T> struct StageArgs {

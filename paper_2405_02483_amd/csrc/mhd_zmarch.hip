@@ -1,0 +1,793 @@
+// z-marching kernels of one RK stage (the production forward path).
+//
+// Four passes per stage, each a single launch over all (box, tile, z-range)
+// work items:
+//   A1  face velocity u_z, div u, and the speed-like viscosity
+//       nu1|u| + nu3(c_s + c_A) + nu2 h max(0, -div u)         (eq. RMnu)
+//   A2  maximum over three cells then three-cell mean, floor, ln  (Section 6.1.1)
+//   Q   quantities on x- and y-directed cell edges (stress, E, Lorentz
+//       products, heating; eqs. itv, nuij, ohm, vdiss) and the z-face /
+//       centre terms that need z derivatives of z-stencil results (Gzz, Hz)
+//   F   everything else (z-edges, centre and x/y faces), all divergences
+//       (eqs. mass, mom, ien, indu), wall masking and the fused RK stage
+//       update (eqs. ddt, tupdate)
+// Stage-1 launches of A1 / A2 also leave per-item maxima for the Courant
+// time step (eq. courantcond), which k_dt folds into a device-resident dt.
+#include "mhd_zmarch.hpp"
+#include "mhd_zmarch_api.hpp"
+
+namespace smhd {
+
+#define ZPROLOGUE                                                              \
+  const int item_ = xcd_item(nitems);                                          \
+  if (item_ >= nitems) return;                                                 \
+  const ZItem it = items[item_];                                               \
+  const BoxDev b = boxes[it.box];                                              \
+  const Geo<T> g(b);                                                           \
+  const int tx = (int)threadIdx.x % TX, ty = (int)threadIdx.x / TX;           \
+  const int gx = wrapm(it.x0 + tx, b.nx), gy = wrapm(it.y0 + ty, b.ny);      \
+  const bool own = (it.x0 + tx < b.nx) && (it.y0 + ty < b.ny);                \
+  const int N = b.nzt;                                                         \
+  const bool wall = b.wall != 0;                                               \
+  const long long colo = b.off + (long long)gy * b.nx + gx;                   \
+  const long long pstride = (long long)b.nx * b.ny;                           \
+  auto valid = [&](int r_) { return !wall || (r_ >= 0 && r_ < N); };          \
+  auto kk = [&](int r_) { return wall ? r_ : wrapm(r_, N); };                 \
+  auto col = [&](int r_) { return colo + (long long)kk(r_) * pstride; };      \
+  auto interior = [&](int r_) { return !wall || (r_ >= b.g0 && r_ < b.g1); };
+
+// Block maximum of a double (all threads call; result valid in thread 0).
+template <int NT>
+__device__ __forceinline__ double block_max(double v, double* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = NT / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
+    __syncthreads();
+  }
+  return sh[0];
+}
+
+// ---------------------------------------------------------------------------
+// A1: u_z = p_z / zdn(rho); div u; speed-like viscosity nu_s.
+// Front plane r: x/y stencils of plane r go through LDS, their results wait
+// in short per-thread queues; u_z (plane r-2) and the z stencils (plane r-5)
+// come from register windows.
+template <class T, int TX, int TY>
+__global__ __launch_bounds__(TX * TY) void zA1(const BoxDev* __restrict__ boxes,
+                                               const ZItem* __restrict__ items, int nitems,
+                                               CP8<T> f, Phys<T> ph, T* __restrict__ nus_out,
+                                               T* __restrict__ D_out, T* __restrict__ uz_out,
+                                               CPart* __restrict__ cpart) {
+  using PR = Plane<TX, TY, 5>;
+  using PP = Plane<TX, TY, 3>;
+  __shared__ T sR[PR::N];
+  __shared__ T sPX[PP::N], sPY[PP::N], sBX[PP::N], sBY[PP::N];
+  __shared__ double sred[TX * TY];
+  ZPROLOGUE
+  T wR[6] = {}, wUZ[6] = {}, wBZ[8] = {}, fPZ[3] = {}, fE[6] = {};
+  T fUBX[6] = {}, fUBY[6] = {}, fBBX[6] = {}, fBBY[6] = {}, fDXY[6] = {};
+  double cmax = 0.0;
+  for (int r = it.z0 - 5; r <= it.z1 + 4; ++r) {
+    T rr = T(0), pz = T(0), e = T(0), bz = T(0);
+    T ubx = T(0), uby = T(0), bbx = T(0), bby = T(0), dxy = T(0);
+    if (valid(r)) {
+      const int k = kk(r);
+      __syncthreads();
+      load_plane<TX, TY, 5>(sR, f.p[0], b, it.x0, it.y0, k);
+      load_plane<TX, TY, 3>(sPX, f.p[1], b, it.x0, it.y0, k);
+      load_plane<TX, TY, 3>(sPY, f.p[2], b, it.x0, it.y0, k);
+      load_plane<TX, TY, 3>(sBX, f.p[5], b, it.x0, it.y0, k);
+      load_plane<TX, TY, 3>(sBY, f.p[6], b, it.x0, it.y0, k);
+      __syncthreads();
+      const long long o = col(r);
+      rr = sR[PR::at(tx, ty)];
+      pz = f.p[3][o];
+      e = f.p[4][o];
+      bz = f.p[7][o];
+      T u6[6], v6[6];
+#pragma unroll
+      for (int m = -2; m <= 3; ++m) {
+        const T rx = op6<0, 0, T>([&](int a) { return sR[PR::at(tx + m + a, ty)]; }, T(0));
+        const T ry = op6<0, 0, T>([&](int a) { return sR[PR::at(tx, ty + m + a)]; }, T(0));
+        u6[m + 2] = sPX[PP::at(tx + m, ty)] / rx;
+        v6[m + 2] = sPY[PP::at(tx, ty + m)] / ry;
+      }
+      ubx = op6<0, 1, T>([&](int m) { return u6[m + 2]; }, T(0));
+      uby = op6<0, 1, T>([&](int m) { return v6[m + 2]; }, T(0));
+      dxy = op6<1, 1, T>([&](int m) { return u6[m + 2]; }, g.hxi) +
+            op6<1, 1, T>([&](int m) { return v6[m + 2]; }, g.hyi);
+      bbx = op6<0, 1, T>([&](int m) { return sBX[PP::at(tx + m, ty)]; }, T(0));
+      bby = op6<0, 1, T>([&](int m) { return sBY[PP::at(tx, ty + m)]; }, T(0));
+    }
+    push(wR, rr);
+    push(fPZ, pz);
+    push(fE, e);
+    push(wBZ, bz);
+    push(fUBX, ubx);
+    push(fUBY, uby);
+    push(fBBX, bbx);
+    push(fBBY, bby);
+    push(fDXY, dxy);
+    // u_z on the face of plane q1 = r - 2 (wR slot 3 holds plane q1)
+    const int q1 = r - 2;
+    T uzq = T(0);
+    if (valid(q1)) {
+      const T zr = zwin<0, 0, 6, 3>(wR, q1, wall, N, T(0));
+      uzq = fPZ[0] / zr;
+      if (own && q1 >= it.z0 && q1 < it.z1) uz_out[col(q1)] = uzq;
+    }
+    push(wUZ, uzq);                       // wUZ slot m = plane r-7+m
+    // centre quantities of plane q = r - 5
+    const int q = r - 5;
+    if (valid(q) && q >= it.z0 && q < it.z1) {
+      const T ubz = zwin<0, 1, 6, 2>(wUZ, q, wall, N, T(0));
+      const T dzz = zwin<1, 1, 6, 2>(wUZ, q, wall, N, g.hzi);
+      const T bbz = zwin<0, 1, 8, 2>(wBZ, q, wall, N, T(0));
+      const T rq = wR[0], eq = fE[0];
+      const T D = fDXY[0] + dzz;
+      const T P = ph.gamma1 * eq;
+      const T cs = sqrt(ph.gamma * P / rq);
+      const T bb = norm3(fBBX[0], fBBY[0], bbz);
+      const T ca = bb / sqrt(ph.mu * rq);
+      T nus;
+      if (ph.nu_const > T(0)) {
+        nus = ph.nu_const / g.h;
+      } else {
+        const T relu = -D > T(0) ? -D : T(0);
+        nus = ph.nu1 * norm3(fUBX[0], fUBY[0], ubz) + ph.nu3 * (cs + ca) + ph.nu2 * g.h * relu;
+      }
+      if (own) {
+        const long long o = col(q);
+        nus_out[o] = nus;
+        D_out[o] = D;
+        if (cpart && interior(q)) {
+          const double ux_ = fUBX[0], uy_ = fUBY[0], uz_ = ubz;
+          const double bx_ = fBBX[0], by_ = fBBY[0], bz_ = bbz, bbd = bb;
+          const double udotb = bbd > 0.0 ? (ux_ * bx_ + uy_ * by_ + uz_ * bz_) / bbd : 0.0;
+          const double uu = ux_ * ux_ + uy_ * uy_ + uz_ * uz_;
+          const double up = sqrt(fmax(uu - udotb * udotb, 0.0));
+          cmax = fmax(cmax, (double)cs + (double)ca + up);
+        }
+      }
+    }
+  }
+  if (cpart) {
+    const double m = block_max<TX * TY>(cmax, sred);
+    if (threadIdx.x == 0) cpart[item_].cmax = m;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// A2: m = max over the 3x3x3 neighbourhood (x, y through LDS; z over a ring
+// of three x/y-maximum planes), then three-cell means along x, y (LDS) and
+// z (register window), floor 1e-30, and ln.
+template <class T, int TX, int TY>
+__global__ __launch_bounds__(TX * TY) void zA2(const BoxDev* __restrict__ boxes,
+                                               const ZItem* __restrict__ items, int nitems,
+                                               const T* __restrict__ nus, T* __restrict__ lnt_out,
+                                               CPart* __restrict__ cpart) {
+  using PN = Plane<TX, TY, 2>;
+  using PM = Plane<TX, TY, 1>;
+  constexpr int NT = TX * TY;
+  __shared__ T sN[PN::N];
+  __shared__ T sMX[3][PM::N];
+  __shared__ T sM[PM::N];
+  __shared__ double sred[NT];
+  ZPROLOGUE
+  T wS[3] = {};
+  double numax = 0.0;
+  for (int r = it.z0 - 2; r <= it.z1 + 1; ++r) {
+    if (valid(r)) {
+      __syncthreads();
+      load_plane<TX, TY, 2>(sN, nus, b, it.x0, it.y0, kk(r));
+      __syncthreads();
+      T* dst = sMX[wrapm(r, 3)];
+      for (int t = threadIdx.x; t < PM::N; t += NT) {
+        const int yy = t / PM::W, xx = t - yy * PM::W;
+        const int x = xx - 1, y = yy - 1;
+        T m = sN[PN::at(x, y)];
+#pragma unroll
+        for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+          for (int dx = -1; dx <= 1; ++dx) m = fmax(m, sN[PN::at(x + dx, y + dy)]);
+        dst[t] = m;
+      }
+    }
+    const int q1 = r - 1;
+    T sxy = T(0);
+    if (valid(q1)) {
+      __syncthreads();
+      const bool lo = valid(q1 - 1), hi = valid(q1 + 1);
+      const T* a = sMX[wrapm(q1, 3)];
+      const T* am = sMX[wrapm(q1 - 1, 3)];
+      const T* ap = sMX[wrapm(q1 + 1, 3)];
+      for (int t = threadIdx.x; t < PM::N; t += NT) {
+        T m = a[t];
+        if (lo) m = fmax(m, am[t]);
+        if (hi) m = fmax(m, ap[t]);
+        sM[t] = m;
+      }
+      __syncthreads();
+      T sx[3];
+#pragma unroll
+      for (int dy = -1; dy <= 1; ++dy)
+        sx[dy + 1] = (sM[PM::at(tx - 1, ty + dy)] + sM[PM::at(tx, ty + dy)] +
+                      sM[PM::at(tx + 1, ty + dy)]) / T(3);
+      sxy = (sx[0] + sx[1] + sx[2]) / T(3);
+    }
+    push(wS, sxy);                        // wS slot m = plane r-3+m
+    const int q = r - 2;
+    if (valid(q) && q >= it.z0 && q < it.z1) {
+      T s = wS[1];
+      int cnt = 1;
+      if (valid(q - 1)) { s = wS[0] + wS[1]; cnt = 2; }
+      if (valid(q + 1)) { s = s + wS[2]; ++cnt; }
+      T v = s / T(cnt);
+      v = v > T(1e-30) ? v : T(1e-30);
+      if (own) {
+        lnt_out[col(q)] = log(v);
+        if (cpart && interior(q)) numax = fmax(numax, (double)v);
+      }
+    }
+  }
+  if (cpart) {
+    const double m = block_max<NT>(numax, sred);
+    if (threadIdx.x == 0) cpart[item_].numax = m;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Q: x-directed and y-directed edges (at z = k-1/2), the z-face energy flux
+// Hz and the centre terms Gzz = tau_zz - zup(p_z) zup(u_z) - P and
+// Czz = tau_zz S_zz.  Outputs (QOUT_*):
+//   y-edge (i-1/2, j, k-1/2): Gxz, Gzx, Ey, Lxy, Lzy, Qy
+//   x-edge (i, j-1/2, k-1/2): Gyz, Gzy, Ex, Lyx, Lzx, Qx
+//   Hz (z-face), Gzz, Czz (centre)
+template <class T, int TX, int TY>
+__global__ __launch_bounds__(TX * TY) void zQ(const BoxDev* __restrict__ boxes,
+                                              const ZItem* __restrict__ items, int nitems,
+                                              CP8<T> f, const T* __restrict__ uzg,
+                                              const T* __restrict__ lntg,
+                                              const T* __restrict__ Dg, Phys<T> ph, QP<T> out) {
+  using P3 = Plane<TX, TY, 3>;
+  __shared__ T sR[P3::N], sL[P3::N];
+  __shared__ T sUZ[3][P3::N], sBZ[3][P3::N], sPZ[3][P3::N];
+  ZPROLOGUE
+  const unsigned tm = ph.terms;
+  const bool visc = tm & T_VISC, res = tm & T_RESIST, ind = tm & T_INDUCT, lor = tm & T_LORENTZ,
+             adv = tm & T_ADV, pres = tm & T_PRES, ediff = tm & T_EDIFF;
+  const bool need_nu = visc || (res && !(ph.eta_const > T(0)));
+  // windows: slot m = plane r-5+m
+  T wRX[6] = {}, wLX[6] = {}, wPX[6] = {}, wUX[6] = {}, wBX[6] = {};
+  T wRY[6] = {}, wLY[6] = {}, wPY[6] = {}, wUY[6] = {}, wBY[6] = {};
+  T wPZ[6] = {}, wUZ[6] = {}, wE[6] = {}, wRho[6] = {}, wNu[6] = {}, wEm[6] = {}, wLem[6] = {};
+  const T inv_mu = ph.inv_mu;
+  for (int r = it.z0 - 3; r <= it.z1 + 2; ++r) {
+    T rx = T(0), lx = T(0), px = T(0), ux = T(0), bxv = T(0);
+    T ry = T(0), ly = T(0), py = T(0), uy = T(0), byv = T(0);
+    T pzv = T(0), uzv = T(0), ev = T(0), rhov = T(0), nuv = T(0), em = T(0), lem = T(0);
+    if (valid(r)) {
+      const int k = kk(r), sl = wrapm(r, 3);
+      __syncthreads();
+      load_plane<TX, TY, 3>(sR, f.p[0], b, it.x0, it.y0, k);
+      load_plane<TX, TY, 3>(sL, lntg, b, it.x0, it.y0, k);
+      load_plane<TX, TY, 3>(sUZ[sl], uzg, b, it.x0, it.y0, k);
+      load_plane<TX, TY, 3>(sBZ[sl], f.p[7], b, it.x0, it.y0, k);
+      load_plane<TX, TY, 3>(sPZ[sl], f.p[3], b, it.x0, it.y0, k);
+      __syncthreads();
+      const long long o = col(r);
+      rx = op6<0, 0, T>([&](int m) { return sR[P3::at(tx + m, ty)]; }, T(0));
+      ry = op6<0, 0, T>([&](int m) { return sR[P3::at(tx, ty + m)]; }, T(0));
+      lx = op6<0, 0, T>([&](int m) { return sL[P3::at(tx + m, ty)]; }, T(0));
+      ly = op6<0, 0, T>([&](int m) { return sL[P3::at(tx, ty + m)]; }, T(0));
+      px = f.p[1][o];
+      py = f.p[2][o];
+      ux = px / rx;
+      uy = py / ry;
+      bxv = f.p[5][o];
+      byv = f.p[6][o];
+      pzv = sPZ[sl][P3::at(tx, ty)];
+      uzv = sUZ[sl][P3::at(tx, ty)];
+      ev = f.p[4][o];
+      rhov = sR[P3::at(tx, ty)];
+      nuv = exp(sL[P3::at(tx, ty)]);
+      em = ev / rhov;
+      lem = log(em);
+    }
+    push(wRX, rx); push(wLX, lx); push(wPX, px); push(wUX, ux); push(wBX, bxv);
+    push(wRY, ry); push(wLY, ly); push(wPY, py); push(wUY, uy); push(wBY, byv);
+    push(wPZ, pzv); push(wUZ, uzv); push(wE, ev); push(wRho, rhov); push(wNu, nuv);
+    push(wEm, em); push(wLem, lem);
+
+    // edges and z-face of plane q = r - 2 (window slot 3)
+    const int q = r - 2;
+    if (valid(q) && q >= it.z0 && q < it.z1) {
+      const int sq = wrapm(q, 3);
+      const T* UZ = sUZ[sq];
+      const T* BZ = sBZ[sq];
+      const T* PZ = sPZ[sq];
+      const long long o = col(q);
+      // ---- y-edge
+      {
+        const T zRX = zwin<0, 0, 6, 3>(wRX, q, wall, N, T(0));
+        const T zPX = zwin<0, 0, 6, 3>(wPX, q, wall, N, T(0));
+        const T zUX = zwin<0, 0, 6, 3>(wUX, q, wall, N, T(0));
+        const T dzUX = zwin<1, 0, 6, 3>(wUX, q, wall, N, g.hzi);
+        const T zBX = zwin<0, 0, 6, 3>(wBX, q, wall, N, T(0));
+        const T dzBX = zwin<1, 0, 6, 3>(wBX, q, wall, N, g.hzi);
+        const T xUZ = op6<0, 0, T>([&](int m) { return UZ[P3::at(tx + m, ty)]; }, T(0));
+        const T dxUZ = op6<1, 0, T>([&](int m) { return UZ[P3::at(tx + m, ty)]; }, g.hxi);
+        const T xBZ = op6<0, 0, T>([&](int m) { return BZ[P3::at(tx + m, ty)]; }, T(0));
+        const T dxBZ = op6<1, 0, T>([&](int m) { return BZ[P3::at(tx + m, ty)]; }, g.hxi);
+        const T xPZ = op6<0, 0, T>([&](int m) { return PZ[P3::at(tx + m, ty)]; }, T(0));
+        T nxz = T(0), txz = T(0), sxz = T(0);
+        if (need_nu) nxz = fmax(g.dx, g.dz) * exp(zwin<0, 0, 6, 3>(wLX, q, wall, N, T(0)));
+        if (visc) {
+          sxz = T(0.5) * (dzUX + dxUZ);
+          txz = zRX * nxz * sxz;
+        }
+        const T jy = dzBX - dxBZ;
+        const T eta = ph.eta_const > T(0) ? ph.eta_const : ph.nuB * nxz;
+        T ey = T(0);
+        if (ind) ey = ey - (xUZ * zBX - zUX * xBZ);
+        if (res) ey = ey + eta * jy;
+        T gxz = txz, gzx = txz;
+        if (adv) {
+          gxz = gxz - zPX * xUZ;
+          gzx = gzx - xPZ * zUX;
+        }
+        T qy = visc ? T(2) * txz * sxz : T(0);
+        if (res) qy = qy + eta * jy * jy * inv_mu;
+        if (own) {
+          out.p[QOUT_GXZ][o] = gxz;
+          out.p[QOUT_GZX][o] = gzx;
+          out.p[QOUT_EY][o] = ey;
+          out.p[QOUT_LXY][o] = lor ? jy * xBZ : T(0);
+          out.p[QOUT_LZY][o] = lor ? jy * zBX : T(0);
+          out.p[QOUT_QY][o] = qy;
+        }
+      }
+      // ---- x-edge
+      {
+        const T zRY = zwin<0, 0, 6, 3>(wRY, q, wall, N, T(0));
+        const T zPY = zwin<0, 0, 6, 3>(wPY, q, wall, N, T(0));
+        const T zUY = zwin<0, 0, 6, 3>(wUY, q, wall, N, T(0));
+        const T dzUY = zwin<1, 0, 6, 3>(wUY, q, wall, N, g.hzi);
+        const T zBY = zwin<0, 0, 6, 3>(wBY, q, wall, N, T(0));
+        const T dzBY = zwin<1, 0, 6, 3>(wBY, q, wall, N, g.hzi);
+        const T yUZ = op6<0, 0, T>([&](int m) { return UZ[P3::at(tx, ty + m)]; }, T(0));
+        const T dyUZ = op6<1, 0, T>([&](int m) { return UZ[P3::at(tx, ty + m)]; }, g.hyi);
+        const T yBZ = op6<0, 0, T>([&](int m) { return BZ[P3::at(tx, ty + m)]; }, T(0));
+        const T dyBZ = op6<1, 0, T>([&](int m) { return BZ[P3::at(tx, ty + m)]; }, g.hyi);
+        const T yPZ = op6<0, 0, T>([&](int m) { return PZ[P3::at(tx, ty + m)]; }, T(0));
+        T nyz = T(0), tyz = T(0), syz = T(0);
+        if (need_nu) nyz = fmax(g.dy, g.dz) * exp(zwin<0, 0, 6, 3>(wLY, q, wall, N, T(0)));
+        if (visc) {
+          syz = T(0.5) * (dzUY + dyUZ);
+          tyz = zRY * nyz * syz;
+        }
+        const T jx = dyBZ - dzBY;
+        const T eta = ph.eta_const > T(0) ? ph.eta_const : ph.nuB * nyz;
+        T ex = T(0);
+        if (ind) ex = ex - (zUY * yBZ - yUZ * zBY);
+        if (res) ex = ex + eta * jx;
+        T gyz = tyz, gzy = tyz;
+        if (adv) {
+          gyz = gyz - zPY * yUZ;
+          gzy = gzy - yPZ * zUY;
+        }
+        T qx = visc ? T(2) * tyz * syz : T(0);
+        if (res) qx = qx + eta * jx * jx * inv_mu;
+        if (own) {
+          out.p[QOUT_GYZ][o] = gyz;
+          out.p[QOUT_GZY][o] = gzy;
+          out.p[QOUT_EX][o] = ex;
+          out.p[QOUT_LYX][o] = lor ? jx * yBZ : T(0);
+          out.p[QOUT_LZX][o] = lor ? jx * zBY : T(0);
+          out.p[QOUT_QX][o] = qx;
+        }
+      }
+      // ---- z-face energy flux: -zdn(e) u_z + nuE zdn(rho) dz zdn(nu) zdn(e_m) ddzdn(ln e_m)
+      {
+        T hz = T(0);
+        if (adv) hz = -zwin<0, 0, 6, 3>(wE, q, wall, N, T(0)) * wUZ[3];
+        if (ediff)
+          hz = hz + ph.nuE * zwin<0, 0, 6, 3>(wRho, q, wall, N, T(0)) *
+                        (g.dz * zwin<0, 0, 6, 3>(wNu, q, wall, N, T(0))) *
+                        zwin<0, 0, 6, 3>(wEm, q, wall, N, T(0)) *
+                        zwin<1, 0, 6, 3>(wLem, q, wall, N, g.hzi);
+        if (own) out.p[QOUT_HZ][o] = hz;
+      }
+    }
+    // centre terms of plane q2 = r - 3 (window slot 2)
+    const int q2 = r - 3;
+    if (valid(q2) && q2 >= it.z0 && q2 < it.z1) {
+      const long long o = col(q2);
+      const T szz = zwin<1, 1, 6, 2>(wUZ, q2, wall, N, g.hzi);
+      T gzz = T(0), czz = T(0);
+      if (visc) {
+        const T tzz = wRho[2] * (g.dz * wNu[2]) * (szz + ph.c1 * Dg[o]);
+        gzz = tzz;
+        czz = tzz * szz;
+      }
+      if (adv) gzz = gzz - zwin<0, 1, 6, 2>(wPZ, q2, wall, N, T(0)) * zwin<0, 1, 6, 2>(wUZ, q2, wall, N, T(0));
+      if (pres) gzz = gzz - ph.gamma1 * wE[2];
+      if (own) {
+        out.p[QOUT_GZZ][o] = gzz;
+        out.p[QOUT_CZZ][o] = czz;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// F: plane-local terms of plane r through LDS (z-edges, centre, x/y faces and
+// the x/y divergences of Q's edge quantities), plus z divergences of Q's
+// outputs scattered into per-thread accumulators of output planes r-3..r+3;
+// plane r-3 is complete and is written with the RK stage update.
+template <class T, int TX, int TY>
+__global__ __launch_bounds__(TX * TY) void zF(const BoxDev* __restrict__ boxes,
+                                              const ZItem* __restrict__ items, int nitems,
+                                              CP8<T> f, const T* __restrict__ lntg,
+                                              const T* __restrict__ Dg, CQP<T> qin, Phys<T> ph,
+                                              CP8<T> du_in, P8<T> du_out, P8<T> f_out, T alpha,
+                                              double beta, const double* __restrict__ dt_dev,
+                                              double dt_host) {
+  using P9 = Plane<TX, TY, 9>;
+  using P6 = Plane<TX, TY, 6>;
+  using P3 = Plane<TX, TY, 3>;
+  constexpr int NT = TX * TY;
+  // level-1 planes: 0 px 1 py 2 e 3 Bx 4 By 5 ln nu 6 ux 7 uy 8 nu 9 e_m 10 ln e_m
+  constexpr int NL1 = 11;
+  __shared__ T sR[P9::N];
+  __shared__ T sL1[NL1 * P6::N];
+  __shared__ T sD[P3::N];
+  // level-4 planes: 0 Gxy 1 Gyx 2 Ez 3 Lxz 4 Lyz 5 Qz 6 Gxx 7 Gyy 8 Hx 9 Hy
+  __shared__ T sL4[10 * P3::N];
+  // Q's x/y-differentiated quantities reuse the level-1 space
+  static_assert(NL1 * P6::N >= 8 * P3::N, "LDS reuse");
+  T* sQ = sL1;
+  ZPROLOGUE
+  const unsigned tm = ph.terms;
+  const bool visc = tm & T_VISC, res = tm & T_RESIST, ind = tm & T_INDUCT, lor = tm & T_LORENTZ,
+             adv = tm & T_ADV, pres = tm & T_PRES, ediff = tm & T_EDIFF, cont = tm & T_CONT,
+             grav = tm & T_GRAV;
+  const bool need_nu = visc || (res && !(ph.eta_const > T(0)));
+  const T inv_mu = ph.inv_mu;
+  const double dt = dt_dev ? *dt_dev : dt_host;
+  const T bdt = T(beta * dt);
+  auto L1 = [&](int q, int x, int y) -> T& { return sL1[q * P6::N + P6::at(x, y)]; };
+  auto L4 = [&](int q, int x, int y) -> T& { return sL4[q * P3::N + P3::at(x, y)]; };
+  auto QS = [&](int q, int x, int y) -> T& { return sQ[q * P3::N + P3::at(x, y)]; };
+  // Q planes in LDS: 0 Gzx 1 Ey 2 Lzy 3 Qy 4 Gzy 5 Ex 6 Lzx 7 Qx
+  T acc[7][7];
+#pragma unroll
+  for (int a = 0; a < 7; ++a)
+#pragma unroll
+    for (int s = 0; s < 7; ++s) acc[a][s] = T(0);
+  // previous-plane values of the z-differentiated quantities (first
+  // differences): 0 pz 1 Gxz 2 Gyz 3 Gzz 4 Hz 5 Ey 6 Ex
+  T prev[7];
+#pragma unroll
+  for (int a = 0; a < 7; ++a) prev[a] = T(0);
+
+  auto finalize = [&](int v, int k, T Fv) {
+    // wall masking (Section 10) and the RK stage update of field v at plane k
+    if (wall) {
+      const bool cen = k >= b.g0 && k < b.g1;
+      const bool keep = v == 3 ? (k > b.g0 && k < b.g1) : (v == 7 ? (k >= b.g0 && k <= b.g1) : cen);
+      if (!keep) Fv = T(0);
+    }
+    const long long o = col(k);
+    if (f_out.p[0] == nullptr) {
+      du_out.p[v][o] = Fv;
+      return;
+    }
+    const T U = du_in.p[0] ? alpha * du_in.p[v][o] + Fv : Fv;
+    if (du_out.p[0]) du_out.p[v][o] = U;
+    f_out.p[v][o] = f.p[v][o] + bdt * U;
+  };
+
+  for (int r = it.z0 - 3; r <= it.z1 + 2; ++r) {
+    const int kb = r - 3;
+    const bool inch = r >= it.z0 && r < it.z1;
+    if (valid(r)) {
+      const int k = kk(r);
+      const long long o = col(r);
+      if (inch) {
+        // ---- level-1 planes of plane r
+        __syncthreads();
+        load_plane<TX, TY, 9>(sR, f.p[0], b, it.x0, it.y0, k);
+        load_plane<TX, TY, 6>(&L1(0, -6, -6), f.p[1], b, it.x0, it.y0, k);
+        load_plane<TX, TY, 6>(&L1(1, -6, -6), f.p[2], b, it.x0, it.y0, k);
+        load_plane<TX, TY, 6>(&L1(2, -6, -6), f.p[4], b, it.x0, it.y0, k);
+        load_plane<TX, TY, 6>(&L1(3, -6, -6), f.p[5], b, it.x0, it.y0, k);
+        load_plane<TX, TY, 6>(&L1(4, -6, -6), f.p[6], b, it.x0, it.y0, k);
+        load_plane<TX, TY, 6>(&L1(5, -6, -6), lntg, b, it.x0, it.y0, k);
+        load_plane<TX, TY, 3>(sD, Dg, b, it.x0, it.y0, k);
+        __syncthreads();
+        for (int t = threadIdx.x; t < P6::N; t += NT) {
+          const int yy = t / P6::W, xx = t - yy * P6::W;
+          const int x = xx - 6, y = yy - 6;
+          const T rxd = op6<0, 0, T>([&](int m) { return sR[P9::at(x + m, y)]; }, T(0));
+          const T ryd = op6<0, 0, T>([&](int m) { return sR[P9::at(x, y + m)]; }, T(0));
+          const T rc = sR[P9::at(x, y)];
+          sL1[6 * P6::N + t] = sL1[0 * P6::N + t] / rxd;
+          sL1[7 * P6::N + t] = sL1[1 * P6::N + t] / ryd;
+          sL1[8 * P6::N + t] = exp(sL1[5 * P6::N + t]);
+          const T emv = sL1[2 * P6::N + t] / rc;
+          sL1[9 * P6::N + t] = emv;
+          sL1[10 * P6::N + t] = log(emv);
+        }
+        __syncthreads();
+        // ---- level-4 quantities on the halo-3 region
+        for (int t = threadIdx.x; t < P3::N; t += NT) {
+          const int yy = t / P3::W, xx = t - yy * P3::W;
+          const int x = xx - 3, y = yy - 3;
+          // z-edge (x-1/2, y-1/2)
+          T nxy = T(0), txy = T(0), sxy = T(0);
+          if (need_nu) {
+            const T lxy = op6<0, 0, T>([&](int m) {
+              return op6<0, 0, T>([&](int a) { return L1(5, x + a, y + m); }, T(0));
+            }, T(0));
+            nxy = fmax(g.dx, g.dy) * exp(lxy);
+          }
+          if (visc) {
+            const T rxy = op6<0, 0, T>([&](int m) {
+              return op6<0, 0, T>([&](int a) { return sR[P9::at(x + a, y + m)]; }, T(0));
+            }, T(0));
+            sxy = T(0.5) * (op6<1, 0, T>([&](int m) { return L1(6, x, y + m); }, g.hyi) +
+                            op6<1, 0, T>([&](int m) { return L1(7, x + m, y); }, g.hxi));
+            txy = rxy * nxy * sxy;
+          }
+          const T jz = op6<1, 0, T>([&](int m) { return L1(4, x + m, y); }, g.hxi) -
+                       op6<1, 0, T>([&](int m) { return L1(3, x, y + m); }, g.hyi);
+          const T eta = ph.eta_const > T(0) ? ph.eta_const : ph.nuB * nxy;
+          const T xBY = op6<0, 0, T>([&](int m) { return L1(4, x + m, y); }, T(0));
+          const T yBX = op6<0, 0, T>([&](int m) { return L1(3, x, y + m); }, T(0));
+          T ez = T(0);
+          if (ind)
+            ez = ez - (op6<0, 0, T>([&](int m) { return L1(6, x, y + m); }, T(0)) * xBY -
+                       op6<0, 0, T>([&](int m) { return L1(7, x + m, y); }, T(0)) * yBX);
+          if (res) ez = ez + eta * jz;
+          T gxy = txy, gyx = txy;
+          if (adv) {
+            gxy = gxy - op6<0, 0, T>([&](int m) { return L1(0, x, y + m); }, T(0)) *
+                            op6<0, 0, T>([&](int m) { return L1(7, x + m, y); }, T(0));
+            gyx = gyx - op6<0, 0, T>([&](int m) { return L1(1, x + m, y); }, T(0)) *
+                            op6<0, 0, T>([&](int m) { return L1(6, x, y + m); }, T(0));
+          }
+          T qz = visc ? T(2) * txy * sxy : T(0);
+          if (res) qz = qz + eta * jz * jz * inv_mu;
+          sL4[0 * P3::N + t] = gxy;
+          sL4[1 * P3::N + t] = gyx;
+          sL4[2 * P3::N + t] = ez;
+          sL4[3 * P3::N + t] = lor ? jz * xBY : T(0);
+          sL4[4 * P3::N + t] = lor ? jz * yBX : T(0);
+          sL4[5 * P3::N + t] = qz;
+          // centre (x, y): Gxx, Gyy
+          const T sxx = op6<1, 1, T>([&](int m) { return L1(6, x + m, y); }, g.hxi);
+          const T syy = op6<1, 1, T>([&](int m) { return L1(7, x, y + m); }, g.hyi);
+          const T Dc = sD[P3::at(x, y)];
+          const T rc = sR[P9::at(x, y)];
+          const T nc = L1(8, x, y);
+          const T Pc = ph.gamma1 * L1(2, x, y);
+          T gxx = T(0), gyy = T(0);
+          if (visc) {
+            gxx = rc * (g.dx * nc) * (sxx + ph.c1 * Dc);
+            gyy = rc * (g.dy * nc) * (syy + ph.c1 * Dc);
+          }
+          if (adv) {
+            gxx = gxx - op6<0, 1, T>([&](int m) { return L1(0, x + m, y); }, T(0)) *
+                            op6<0, 1, T>([&](int m) { return L1(6, x + m, y); }, T(0));
+            gyy = gyy - op6<0, 1, T>([&](int m) { return L1(1, x, y + m); }, T(0)) *
+                            op6<0, 1, T>([&](int m) { return L1(7, x, y + m); }, T(0));
+          }
+          if (pres) {
+            gxx = gxx - Pc;
+            gyy = gyy - Pc;
+          }
+          sL4[6 * P3::N + t] = gxx;
+          sL4[7 * P3::N + t] = gyy;
+          // x- and y-faces: energy fluxes
+          T hx = T(0), hy = T(0);
+          if (adv) {
+            hx = -op6<0, 0, T>([&](int m) { return L1(2, x + m, y); }, T(0)) * L1(6, x, y);
+            hy = -op6<0, 0, T>([&](int m) { return L1(2, x, y + m); }, T(0)) * L1(7, x, y);
+          }
+          if (ediff) {
+            hx = hx + ph.nuE * op6<0, 0, T>([&](int m) { return sR[P9::at(x + m, y)]; }, T(0)) *
+                          (g.dx * op6<0, 0, T>([&](int m) { return L1(8, x + m, y); }, T(0))) *
+                          op6<0, 0, T>([&](int m) { return L1(9, x + m, y); }, T(0)) *
+                          op6<1, 0, T>([&](int m) { return L1(10, x + m, y); }, g.hxi);
+            hy = hy + ph.nuE * op6<0, 0, T>([&](int m) { return sR[P9::at(x, y + m)]; }, T(0)) *
+                          (g.dy * op6<0, 0, T>([&](int m) { return L1(8, x, y + m); }, T(0))) *
+                          op6<0, 0, T>([&](int m) { return L1(9, x, y + m); }, T(0)) *
+                          op6<1, 0, T>([&](int m) { return L1(10, x, y + m); }, g.hyi);
+          }
+          sL4[8 * P3::N + t] = hx;
+          sL4[9 * P3::N + t] = hy;
+        }
+        __syncthreads();
+        // ---- x/y divergences at the own column, plane r (accumulator slot 3)
+        {
+          const int x = tx, y = ty;
+          if (cont)
+            acc[0][3] += -(op6<1, 1, T>([&](int m) { return L1(0, x + m, y); }, g.hxi) +
+                           op6<1, 1, T>([&](int m) { return L1(1, x, y + m); }, g.hyi));
+          acc[1][3] += op6<1, 0, T>([&](int m) { return L4(6, x + m, y); }, g.hxi) +
+                       op6<1, 1, T>([&](int m) { return L4(0, x, y + m); }, g.hyi) -
+                       op6<0, 1, T>([&](int m) { return L4(3, x, y + m); }, T(0)) * inv_mu;
+          acc[2][3] += op6<1, 0, T>([&](int m) { return L4(7, x, y + m); }, g.hyi) +
+                       op6<1, 1, T>([&](int m) { return L4(1, x + m, y); }, g.hxi) +
+                       op6<0, 1, T>([&](int m) { return L4(4, x + m, y); }, T(0)) * inv_mu;
+          // centre heating and pressure work (the z part tau_zz S_zz comes from Q)
+          T qc = T(0);
+          if (visc) {
+            const T sxx = op6<1, 1, T>([&](int m) { return L1(6, x + m, y); }, g.hxi);
+            const T syy = op6<1, 1, T>([&](int m) { return L1(7, x, y + m); }, g.hyi);
+            const T Dc = sD[P3::at(x, y)];
+            const T rc = sR[P9::at(x, y)];
+            const T nc = L1(8, x, y);
+            qc = rc * (g.dx * nc) * (sxx + ph.c1 * Dc) * sxx + rc * (g.dy * nc) * (syy + ph.c1 * Dc) * syy;
+            qc = qc + qin.p[QOUT_CZZ][o];
+          }
+          if (pres) qc = qc - ph.gamma1 * L1(2, x, y) * sD[P3::at(x, y)];
+          acc[4][3] += qc + op6<1, 1, T>([&](int m) { return L4(8, x + m, y); }, g.hxi) +
+                       op6<1, 1, T>([&](int m) { return L4(9, x, y + m); }, g.hyi) +
+                       op6<0, 1, T>([&](int m) {
+                         return op6<0, 1, T>([&](int a) { return L4(5, x + a, y + m); }, T(0));
+                       }, T(0));
+          acc[5][3] += -op6<1, 1, T>([&](int m) { return L4(2, x, y + m); }, g.hyi);
+          acc[6][3] += op6<1, 1, T>([&](int m) { return L4(2, x + m, y); }, g.hxi);
+        }
+      }
+      // ---- Q's quantities of plane r that are differentiated across x / y
+      __syncthreads();
+      if (inch) {
+        load_plane<TX, TY, 3>(&QS(0, -3, -3), qin.p[QOUT_GZX], b, it.x0, it.y0, k);
+        load_plane<TX, TY, 3>(&QS(1, -3, -3), qin.p[QOUT_EY], b, it.x0, it.y0, k);
+        load_plane<TX, TY, 3>(&QS(2, -3, -3), qin.p[QOUT_LZY], b, it.x0, it.y0, k);
+        load_plane<TX, TY, 3>(&QS(4, -3, -3), qin.p[QOUT_GZY], b, it.x0, it.y0, k);
+        load_plane<TX, TY, 3>(&QS(5, -3, -3), qin.p[QOUT_EX], b, it.x0, it.y0, k);
+        load_plane<TX, TY, 3>(&QS(6, -3, -3), qin.p[QOUT_LZX], b, it.x0, it.y0, k);
+      }
+      load_plane<TX, TY, 3>(&QS(3, -3, -3), qin.p[QOUT_QY], b, it.x0, it.y0, k);
+      load_plane<TX, TY, 3>(&QS(7, -3, -3), qin.p[QOUT_QX], b, it.x0, it.y0, k);
+      __syncthreads();
+      const int x = tx, y = ty;
+      if (inch) {
+        acc[3][3] += op6<1, 1, T>([&](int m) { return QS(0, x + m, y); }, g.hxi) +
+                     op6<1, 1, T>([&](int m) { return QS(4, x, y + m); }, g.hyi) +
+                     (op6<0, 1, T>([&](int m) { return QS(6, x, y + m); }, T(0)) -
+                      op6<0, 1, T>([&](int m) { return QS(2, x + m, y); }, T(0))) * inv_mu;
+        // Bz has no z divergence: complete at once
+        const T fbz = -(op6<1, 1, T>([&](int m) { return QS(1, x + m, y); }, g.hxi) -
+                        op6<1, 1, T>([&](int m) { return QS(5, x, y + m); }, g.hyi));
+        if (own) finalize(7, r, fbz);
+      }
+      const T xqy = op6<0, 1, T>([&](int m) { return QS(3, x + m, y); }, T(0));
+      const T yqx = op6<0, 1, T>([&](int m) { return QS(7, x, y + m); }, T(0));
+      // ---- z divergences of plane r scattered into output planes r-3..r+3:
+      // derivatives through first differences, interpolations directly
+      T cur[7];
+      cur[0] = f.p[3][o];
+      cur[1] = qin.p[QOUT_GXZ][o];
+      cur[2] = qin.p[QOUT_GYZ][o];
+      cur[3] = qin.p[QOUT_GZZ][o];
+      cur[4] = qin.p[QOUT_HZ][o];
+      cur[5] = qin.p[QOUT_EY][o];
+      cur[6] = qin.p[QOUT_EX][o];
+      T dl[7];
+#pragma unroll
+      for (int a = 0; a < 7; ++a) {
+        dl[a] = (cur[a] - prev[a]) * g.hzi;
+        prev[a] = cur[a];
+      }
+      if (cont) zscatter_d<1, 3>(acc[0], kb, -dl[0], wall, N);
+      zscatter_d<1, 3>(acc[1], kb, dl[1], wall, N);
+      zscatter<0, 1, 3>(acc[1], kb, qin.p[QOUT_LXY][o] * inv_mu, wall, N);
+      zscatter_d<1, 3>(acc[2], kb, dl[2], wall, N);
+      zscatter<0, 1, 3>(acc[2], kb, -qin.p[QOUT_LYX][o] * inv_mu, wall, N);
+      zscatter_d<0, 3>(acc[3], kb, dl[3], wall, N);
+      if (grav) zscatter<0, 0, 3>(acc[3], kb, -f.p[0][o] * ph.gz, wall, N);
+      zscatter_d<1, 3>(acc[4], kb, dl[4], wall, N);
+      zscatter<0, 1, 3>(acc[4], kb, xqy, wall, N);
+      zscatter<0, 1, 3>(acc[4], kb, yqx, wall, N);
+      zscatter_d<1, 3>(acc[5], kb, dl[5], wall, N);
+      zscatter_d<1, 3>(acc[6], kb, -dl[6], wall, N);
+    } else {
+#pragma unroll
+      for (int a = 0; a < 7; ++a) prev[a] = T(0);
+    }
+    // ---- plane kb = r-3 is complete
+    if (own && valid(kb) && kb >= it.z0 && kb < it.z1) {
+#pragma unroll
+      for (int a = 0; a < 7; ++a) finalize(a, kb, acc[a][0]);
+    }
+#pragma unroll
+    for (int a = 0; a < 7; ++a) {
+#pragma unroll
+      for (int s = 0; s < 6; ++s) acc[a][s] = acc[a][s + 1];
+      acc[a][6] = T(0);
+    }
+  }
+}
+
+// Courant time step of the current state from the per-item maxima of A1 / A2
+// (eq. courantcond, wave and diffusion limits), into dt_dev[0].
+__global__ __launch_bounds__(256) void k_dt(const BoxDev* __restrict__ boxes,
+                                            const ZItem* __restrict__ items, int nitems,
+                                            const CPart* __restrict__ cpart, double Cdt,
+                                            double Cdtd, double nuB, double eta_const,
+                                            double* __restrict__ dt_dev) {
+  __shared__ double sh[256];
+  double best = 1e300;
+  for (int i = threadIdx.x; i < nitems; i += 256) {
+    const BoxDev b = boxes[items[i].box];
+    const double h = b.hmin, ratio = b.hmax / b.hmin;
+    const double cm = cpart[i].cmax, nm = cpart[i].numax;
+    const double eta_speed = eta_const > 0.0 ? eta_const / h : nuB * nm;
+    const double dm = fmax(nm, eta_speed * ratio);
+    if (cm > 0.0) best = fmin(best, Cdt * h / cm);
+    if (dm > 0.0) best = fmin(best, Cdtd * h / dm);
+  }
+  sh[threadIdx.x] = best;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sh[threadIdx.x] = fmin(sh[threadIdx.x], sh[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) dt_dev[0] = sh[0];
+}
+
+// ---------------------------------------------------------------------------
+template <class T, int TX, int TY>
+static void launch_zstage_t(const ZLaunch& L, const ZStageArgs<T>& a) {
+  const int n = L.nitems;
+  const dim3 grid(8 * ((n + 7) / 8)), block(TX * TY);
+  L.at(PASS_PRIM);
+  hipLaunchKernelGGL((zA1<T, TX, TY>), grid, block, 0, L.stream, L.boxes, L.items, n, a.f, a.ph,
+                     a.w.nus, a.w.D, a.w.uz, a.cpart);
+  L.at(PASS_MEAN3);
+  hipLaunchKernelGGL((zA2<T, TX, TY>), grid, block, 0, L.stream, L.boxes, L.items, n, a.w.nus,
+                     a.w.lnt, a.cpart);
+  if (a.cpart) {
+    L.at(PASS_REDUCE);
+    hipLaunchKernelGGL(k_dt, dim3(1), dim3(256), 0, L.stream, L.boxes, L.items, n, a.cpart, a.Cdt,
+                       a.Cdtd, a.nuB, a.eta_const, a.dt_dev);
+  }
+  L.at(PASS_EDGES);
+  QP<T> qo;
+  CQP<T> qi;
+  for (int q = 0; q < QOUT_COUNT; ++q) {
+    qo.p[q] = a.w.q[q];
+    qi.p[q] = a.w.q[q];
+  }
+  hipLaunchKernelGGL((zQ<T, TX, TY>), grid, block, 0, L.stream, L.boxes, L.items, n, a.f, a.w.uz,
+                     a.w.lnt, a.w.D, a.ph, qo);
+  L.at(PASS_FINAL);
+  hipLaunchKernelGGL((zF<T, TX, TY>), grid, block, 0, L.stream, L.boxes, L.items, n, a.f, a.w.lnt,
+                     a.w.D, qi, a.ph, a.du_in, a.du_out, a.f_out, a.alpha, a.beta, a.dt_dev,
+                     a.dt_host);
+  L.at(PASS_END);
+}
+
+template <class T>
+void launch_zstage(const ZLaunch& L, const ZStageArgs<T>& a) {
+  switch (L.tile) {
+    case ZTILE_32x8: launch_zstage_t<T, 32, 8>(L, a); break;
+    case ZTILE_16x16: launch_zstage_t<T, 16, 16>(L, a); break;
+    case ZTILE_16x8: launch_zstage_t<T, 16, 8>(L, a); break;
+    default:
+      // 64x4 needs more LDS than a workgroup has in float64 (ztile_ok)
+      if constexpr (sizeof(T) == 4) launch_zstage_t<T, 64, 4>(L, a);
+      break;
+  }
+}
+
+template void launch_zstage<float>(const ZLaunch&, const ZStageArgs<float>&);
+template void launch_zstage<double>(const ZLaunch&, const ZStageArgs<double>&);
+
+}  // namespace smhd

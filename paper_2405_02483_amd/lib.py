@@ -19,7 +19,8 @@ __all__ = [
     "MhdBox", "MhdParams", "MhdStats", "MhdError", "lib_path", "load",
     "mhd_init", "mhd_destroy", "mhd_last_error", "mhd_field_elems",
     "mhd_box_offset", "mhd_rhs", "mhd_step", "mhd_step_adjoint",
-    "mhd_reductions", "Context",
+    "mhd_reductions", "mhd_profile", "mhd_profile_read", "mhd_last_dt", "mhd_set_tile",
+    "PASS_NAMES", "TILES", "Context",
 ]
 
 MHD_OK, MHD_EINVAL, MHD_ENOMEM, MHD_EHIP, MHD_EDTYPE, MHD_ENONFINITE, MHD_EUNSUPPORTED = \
@@ -113,6 +114,15 @@ def load():
     L.mhd_step_adjoint.restype = ctypes.c_int
     L.mhd_reductions.argtypes = [vp, _P8, ctypes.c_void_p, ctypes.POINTER(MhdStats)]
     L.mhd_reductions.restype = ctypes.c_int
+    L.mhd_last_dt.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+    L.mhd_last_dt.restype = ctypes.c_int
+    L.mhd_set_tile.argtypes = [vp, i32]
+    L.mhd_set_tile.restype = ctypes.c_int
+    L.mhd_profile.argtypes = [vp, i32]
+    L.mhd_profile.restype = ctypes.c_int
+    L.mhd_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
+                                   ctypes.POINTER(ctypes.c_int64), i32]
+    L.mhd_profile_read.restype = ctypes.c_int
     _LIB = L
     return L
 
@@ -188,6 +198,33 @@ def mhd_reductions(ctx, f, dfdt=None, *, dtype, n, allow_nonfinite=False):
         return st.as_dict()
     _check(rc, ctx)
     return st.as_dict()
+
+
+PASS_NAMES = ("A1", "unused1", "unused2", "A2", "Q", "unused5", "F", "ghost", "reduce",
+              "adjoint")
+TILES = {"64x4": 0, "32x8": 1, "16x16": 2, "16x8": 3}
+
+
+def mhd_last_dt(ctx):
+    v = ctypes.c_double()
+    _check(load().mhd_last_dt(ctx, ctypes.byref(v)), ctx)
+    return v.value
+
+
+def mhd_set_tile(ctx, tile):
+    _check(load().mhd_set_tile(ctx, int(tile)), ctx)
+
+
+def mhd_profile(ctx, enable):
+    _check(load().mhd_profile(ctx, int(bool(enable))), ctx)
+
+
+def mhd_profile_read(ctx):
+    n = len(PASS_NAMES)
+    ms = (ctypes.c_double * n)()
+    cnt = (ctypes.c_int64 * n)()
+    _check(load().mhd_profile_read(ctx, ms, cnt, n), ctx)
+    return {name: (ms[q], int(cnt[q])) for q, name in enumerate(PASS_NAMES)}
 
 
 # ---------------------------------------------------------------------------
@@ -283,6 +320,18 @@ class Context:
         gbar_out = gbar_out if gbar_out is not None else self.empty()
         mhd_step_adjoint(self.ctx, f_n, dt, gbar_in, gbar_out, dtype=self.dtype, n=self.n)
         return gbar_out
+
+    def last_dt(self):
+        return mhd_last_dt(self.ctx)
+
+    def set_tile(self, tile):
+        mhd_set_tile(self.ctx, TILES[tile] if isinstance(tile, str) else tile)
+
+    def profile(self, enable=True):
+        mhd_profile(self.ctx, enable)
+
+    def profile_read(self):
+        return mhd_profile_read(self.ctx)
 
     def reductions(self, f, dfdt=None, allow_nonfinite=False):
         return mhd_reductions(self.ctx, f, dfdt, dtype=self.dtype, n=self.n,

@@ -218,3 +218,46 @@ def test_repeat_calls_are_bitwise_identical():
     s2 = ctx.reductions(a)
     assert s1 == s2
     ctx.close()
+
+
+@pytest.mark.parametrize("case", ["ot32", "strat", "turb_ragged"])
+def test_courant_step_on_device_f64(case):
+    """dt == 0: each step takes the Courant step of its initial state,
+    computed on the device; state and dt match the oracle."""
+    f, box, prm = _case(case)
+    g, p = grid_params(box, prm)
+    ft = O.ghost_fill(to_cpu64(f), g)
+    ctx = _ctx(box, prm, torch.float64)
+    fd = ctx.upload([f])
+    want = ft
+    for n in range(2):
+        dt_o = O.courant(want, g, p)[0]
+        want = O.step(want, g, p, dt_o, 1)
+        ctx.step(fd, 0.0, 1)
+        assert math.isclose(ctx.last_dt(), dt_o, rel_tol=1e-12), (n, ctx.last_dt(), dt_o)
+    got = ctx.box_view(fd, 0)
+    if box.get("wall"):
+        got, want = interior(got, box), interior(want, box)
+    errs = rel_errors(got, want)
+    assert max(errs) < TOL64, errs
+    ctx.close()
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_tile_shapes_give_identical_bits(dtype):
+    from paper_2405_02483_amd.lib import TILES
+    f, box, prm = _case("turb_ragged")
+    ctx = _ctx(box, prm, dtype)
+    ref = None
+    for name in TILES:
+        if name == "64x4" and dtype == torch.float64:
+            continue
+        ctx.set_tile(name)
+        fd = ctx.upload([f])
+        ctx.step(fd, 2e-3, 2)
+        if ref is None:
+            ref = [t.clone() for t in fd]
+        else:
+            for a, b in zip(fd, ref):
+                assert torch.equal(a, b), name
+    ctx.close()
