@@ -5,8 +5,9 @@ atmosphere with 4 scale heights, constant gravity along z, 1e-3 velocity
 noise, uniform vertical field (beta = 100 at mid-height), periodic x and y,
 closed walls in z with 5 ghost planes per side - in float32, every term of
 the right-hand side on.  One timed step is a full RK3 step with its own
-Courant time step: mhd_reductions (float64 dt from the current state)
-followed by mhd_step(dt, 1).  Inputs are resident in HBM before timing.
+Courant time step: mhd_step(dt = 0, 1), which computes the float64 Courant
+dt of the step's initial state on the device during the first stage.
+Inputs are resident in HBM before timing.
 
 Prints ONE JSON line:  metric, value (interior cell-updates/s per RK step),
 ms_per_step, the float64 figures of the same workload, the roofline of the
@@ -32,7 +33,7 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 # and f; stage 2 reads f and dU, writes dU and f; stage 3 reads f and dU,
 # writes f.  80 words per full step.
 WORDS_PER_STAGE = (24, 32, 24)
-STAGE_PASSES = ("prim", "nus", "max3", "mean3", "edges", "cf", "final")
+STAGE_PASSES = ("A1", "A2", "Q", "P", "F")
 
 
 def log(msg):
@@ -64,14 +65,24 @@ def measured_traffic(dtype_name):
     return float(v) if v else None
 
 
-def run_gpu(size, dtype, steps, warmup):
-    import torch
+def make_state(workload, size):
     from paper_2405_02483_amd import inputs
+    if workload == "stratified":
+        return inputs.stratified(size, size, size, seed=3)
+    if workload == "turbulent":
+        return inputs.turbulent(n=size, seed=2)
+    raise ValueError(workload)
+
+
+def run_gpu(size, dtype, steps, warmup, workload="stratified", tile=None):
+    import torch
     from paper_2405_02483_amd.lib import Context
 
-    log("generating the %d^3 stratified state" % size)
-    f_np, box, prm = inputs.stratified(size, size, size, seed=3)
+    log("generating the %d^3 %s state" % (size, workload))
+    f_np, box, prm = make_state(workload, size)
     ctx = Context(box, prm, dtype=dtype)
+    if tile is not None:
+        ctx.set_tile(tile)
     f = ctx.upload([f_np])
     del f_np
     work = (ctx.empty(), ctx.empty(), ctx.empty())
@@ -79,9 +90,7 @@ def run_gpu(size, dtype, steps, warmup):
     ncell = size ** 3
 
     def one_step():
-        st = ctx.reductions(f)                  # float64 dt, synchronises
-        ctx.step(f, st["dt"], 1, work=work)
-        return st
+        ctx.step(f, 0.0, 1, work=work)          # Courant dt on the device
 
     log("warmup %d steps (%s)" % (warmup, dtype))
     for _ in range(warmup):
@@ -92,11 +101,12 @@ def run_gpu(size, dtype, steps, warmup):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        st = one_step()
+        one_step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     prof = ctx.profile_read()
     ctx.profile(False)
+    dt_last = ctx.last_dt()
     s_end = ctx.reductions(f)
     ctx.close()
     del f, work
@@ -105,7 +115,7 @@ def run_gpu(size, dtype, steps, warmup):
     stage_ms = sum(prof[p][0] for p in STAGE_PASSES) / (3 * steps)
     return dict(ms_per_step=ms, value=ncell * steps / (t1 - t0), stage_ms=stage_ms,
                 passes={k: (v[0] / max(v[1], 1), v[1]) for k, v in prof.items() if v[1]},
-                dt_last=st["dt"], mass_drift=s_end["mass"], ncell=ncell)
+                dt_last=dt_last, mass=s_end["mass"], ncell=ncell)
 
 
 def cpu_baseline(n=128):
@@ -135,6 +145,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-size", type=int, default=128)
+    ap.add_argument("--workload", default="stratified", choices=("stratified", "turbulent"))
+    ap.add_argument("--tile", default=None, help="stage kernel tile shape, e.g. 32x8")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -144,11 +156,11 @@ def main():
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
 
-    r32 = run_gpu(a.size, torch.float32, a.steps, a.warmup)
+    r32 = run_gpu(a.size, torch.float32, a.steps, a.warmup, a.workload, a.tile)
     log("f32: %.2f ms/step, %.3e cell-updates/s" % (r32["ms_per_step"], r32["value"]))
     r64 = None
     if not a.no_fp64:
-        r64 = run_gpu(a.size, torch.float64, max(2, a.steps // 2), 1)
+        r64 = run_gpu(a.size, torch.float64, max(2, a.steps // 2), 1, a.workload)
         log("f64: %.2f ms/step, %.3e cell-updates/s" % (r64["ms_per_step"], r64["value"]))
 
     ncell = r32["ncell"]
@@ -168,9 +180,11 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "stratified_%d" % a.size, "nx": a.size, "ny": a.size,
-                   "nz": a.size, "ngz": 5, "boundaries": "periodic x,y; closed walls z",
-                   "terms": "all", "dt": "Courant (float64) every step"},
+        "config": {"workload": "%s_%d" % (a.workload, a.size), "nx": a.size, "ny": a.size,
+                   "nz": a.size, "ngz": 5 if a.workload == "stratified" else 0,
+                   "boundaries": ("periodic x,y; closed walls z" if a.workload == "stratified"
+                                  else "periodic"),
+                   "terms": "all", "dt": "Courant (float64, on device) every step"},
         "roofline": {"bound": "hbm", "kernel": "rk_stage (passes: %s)" % "+".join(STAGE_PASSES),
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,

@@ -191,8 +191,8 @@ int mhd_last_dt(mhd_ctx* ctx, double* dt);
 
 /* Tile shape of the stage kernels: columns per workgroup, 0: 64x4,
  * 1: 32x8, 2: 16x16, 3: 16x8.  Any shape gives the same results (bit for
- * bit); the default is 32x8 (float32) or 16x8 (float64).  64x4 is float32
- * only (MHD_EUNSUPPORTED for float64).                                      */
+ * bit); the default is 32x8 (float32) or 16x8 (float64).  Other values:
+ * MHD_EINVAL.                                                               */
 int mhd_set_tile(mhd_ctx* ctx, int32_t tile);
 
 /* Timing of the library's own kernel passes, for performance measurement.
@@ -203,7 +203,7 @@ enum {
     MHD_PASS_MAX3 = 2,      /* (unused)                                        */
     MHD_PASS_MEAN3 = 3,     /* A2: max over three cells, three-cell mean, log  */
     MHD_PASS_EDGES = 4,     /* Q: x/y-edge quantities, Hz, Gzz                 */
-    MHD_PASS_CF = 5,        /* (unused)                                        */
+    MHD_PASS_CF = 5,        /* P: z-edge quantities, centre stresses, Hx, Hy   */
     MHD_PASS_FINAL = 6,     /* F: remaining terms, divergences, RK update      */
     MHD_PASS_GHOST = 7,     /* closed-wall ghost zones                          */
     MHD_PASS_REDUCE = 8,    /* float64 reductions incl. their viscosity chain   */

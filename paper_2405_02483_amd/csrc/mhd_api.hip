@@ -44,6 +44,7 @@ struct mhd_ctx {
   int tile = ZTILE_32x8;
   CPart* d_cpart = nullptr;
   double* d_dt = nullptr;
+  void* d_ztab = nullptr;          // z-coefficient tables of wall boxes (ctx dtype)
   // timing of kernel passes (mhd_profile)
   bool prof = false;
   std::vector<std::pair<int, hipEvent_t>> marks;
@@ -77,7 +78,7 @@ static int prof_fold(mhd_ctx* c) {
 }
 
 static std::string g_init_err;
-static constexpr int kWorkArrays = 32;
+static constexpr int kWorkArrays = WS_COUNT;   // 30 arrays
 
 static int fail(mhd_ctx* c, int code, const std::string& msg) {
   if (c) c->err = msg; else g_init_err = msg;
@@ -119,12 +120,6 @@ template <class T> static Work<T> make_work(const mhd_ctx* c) {
   w.nmax = a(4);
   w.nt = a(5);
   w.lnt = a(6);
-  for (int q = 0; q < 8; ++q) {
-    w.ez.p[q] = q < 6 ? a(7 + q) : nullptr;
-    w.ey.p[q] = q < 6 ? a(13 + q) : nullptr;
-    w.ex.p[q] = q < 6 ? a(19 + q) : nullptr;
-    w.cf.p[q] = q < 7 ? a(25 + q) : nullptr;
-  }
   return w;
 }
 
@@ -142,14 +137,9 @@ static Launch make_launch(const mhd_ctx* c) {
 }
 
 template <class T> static ZWork<T> make_zwork(const mhd_ctx* c) {
-  T* base = static_cast<T*>(c->work);
-  const long long n = c->nelem;
   ZWork<T> w;
-  w.nus = base;
-  w.D = base + n;
-  w.uz = base + 2 * n;
-  w.lnt = base + 3 * n;
-  for (int q = 0; q < QOUT_COUNT; ++q) w.q[q] = base + (long long)(4 + q) * n;
+  w.base = static_cast<T*>(c->work);
+  w.stride = c->nelem;
   return w;
 }
 
@@ -302,6 +292,7 @@ void mhd_destroy(mhd_ctx* c) {
   (void)hipFree(c->d_items);
   (void)hipFree(c->d_cpart);
   (void)hipFree(c->d_dt);
+  (void)hipFree(c->d_ztab);
   delete c;
 }
 
@@ -360,11 +351,24 @@ int mhd_init(const mhd_params* p, void* hip_stream, mhd_ctx** out) {
     d.dz = x.Lz / x.nz;
     d.hmin = std::min(d.dx, std::min(d.dy, d.dz));
     d.hmax = std::max(d.dx, std::max(d.dy, d.dz));
+    d.zoff = -1;
     c->h_boxes.push_back(d);
     c->offsets.push_back(off);
     off += d.ncell;
   }
   c->nelem = off;
+  // z-coefficient tables of the wall boxes
+  std::vector<double> ztab;
+  for (auto& d : c->h_boxes) {
+    if (!d.wall) continue;
+    d.zoff = (long long)ztab.size();
+    for (int t = 0; t < ZT_COUNT; ++t)
+      for (int k = 0; k < d.nzt; ++k)
+        for (int dd = -3; dd <= 3; ++dd) {
+          const int p = k + dd;
+          ztab.push_back(p >= 0 && p < d.nzt ? zwall_coef(t, k, p, d.nzt) : 0.0);
+        }
+  }
   std::vector<Blk> tab, gtab;
   build_tables(c, tab, gtab);
   c->nblk = (int)tab.size();
@@ -385,6 +389,22 @@ int mhd_init(const mhd_params* p, void* hip_stream, mhd_ctx** out) {
     g_init_err = std::string("table upload failed: ") + hipGetErrorString(e);
     mhd_destroy(c);
     return MHD_EHIP;
+  }
+  if (!ztab.empty()) {
+    const size_t nb = ztab.size() * c->esize;
+    if ((e = hipMalloc(&c->d_ztab, nb)) != hipSuccess) {
+      g_init_err = std::string("device allocation failed: ") + hipGetErrorString(e);
+      mhd_destroy(c);
+      return MHD_ENOMEM;
+    }
+    std::vector<float> zf(ztab.begin(), ztab.end());
+    e = hipMemcpy(c->d_ztab, c->esize == 4 ? (const void*)zf.data() : (const void*)ztab.data(), nb,
+                  hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      g_init_err = std::string("table upload failed: ") + hipGetErrorString(e);
+      mhd_destroy(c);
+      return MHD_EHIP;
+    }
   }
   if ((e = hipMalloc(&c->d_dt, sizeof(double))) != hipSuccess) {
     g_init_err = std::string("device allocation failed: ") + hipGetErrorString(e);
@@ -410,14 +430,15 @@ static ZStageArgs<T> zargs(mhd_ctx* c) {
   ZStageArgs<T> a;
   a.w = make_zwork<T>(c);
   a.ph = make_phys<T>(c->p);
-  a.du_in = cp8<T>(nullptr);
-  a.du_out = p8null<T>();
+  a.du = p8null<T>();
+  a.du_mode = 0;
   a.f_out = p8null<T>();
   a.alpha = T(0);
   a.beta = 0.0;
   a.dt_dev = nullptr;
   a.dt_host = 0.0;
   a.cpart = nullptr;
+  a.ztab = static_cast<const T*>(c->d_ztab);
   a.Cdt = c->p.Cdt;
   a.Cdtd = c->p.Cdtd;
   a.nuB = c->p.nuB;
@@ -431,7 +452,7 @@ static int do_rhs(mhd_ctx* c, void* const f[8], void* const dfdt[8]) {
   launch_ghost<T>(L, p8<T>(f));
   ZStageArgs<T> a = zargs<T>(c);
   a.f = cp8<T>(f);
-  a.du_out = p8<T>(dfdt);
+  a.du = p8<T>(dfdt);
   launch_zstage<T>(make_zlaunch(c), a);
   return check_launch(c, "mhd_rhs launch");
 }
@@ -456,8 +477,8 @@ static int do_step(mhd_ctx* c, void* const f[8], void* const t1[8], void* const 
     for (int s = 0; s < 3; ++s) {
       ZStageArgs<T> a = zargs<T>(c);
       a.f = cp8<T>(src[s]);
-      a.du_in = s == 0 ? cp8<T>(nullptr) : cp8<T>(U);
-      a.du_out = s == 2 ? p8null<T>() : U;
+      a.du = U;
+      a.du_mode = (s == 0 ? 0 : DU_READ) | (s == 2 ? 0 : DU_WRITE);
       a.f_out = dst[s];
       a.alpha = T(kAlpha[s]);
       a.beta = kBeta[s];

@@ -42,7 +42,51 @@ struct BoxDev {
   long long off;             // first element in the packed field arrays
   long long ncell;           // nx * ny * nzt
   double dx, dy, dz, hmin, hmax;
+  long long zoff;            // wall boxes: first entry of the z-coefficient table
 };
+
+// z-stencil coefficient tables of wall-bounded boxes: for operator type
+// ZT_*, output plane k and offset d = p - k in [-3, 3], the coefficient of
+// input plane p (entry (ZT * nzt + k) * 7 + d + 3).  Types: interpolation dn
+// / up, derivative dn / up (before 1/h), and the derivative written on first
+// differences d_m = f[m] - f[m-1] (dn / up; d = m - k).
+enum ZType : int { ZT_IDN = 0, ZT_IUP, ZT_DDN, ZT_DUP, ZT_DDDN, ZT_DDUP, ZT_COUNT };
+
+// Order choice at the ends of a wall-bounded axis of N planes: the widest
+// centred stencil (q pairs) around c = k + form whose samples lie in [0, N);
+// the one output no stencil reaches takes its neighbour's stencil.
+inline void zwall_pairs(int k, int form, int N, int& c, int& q) {
+  c = k + form;
+  q = c < N - c ? c : N - c;
+  if (q > 3) q = 3;
+  if (q <= 0) {
+    c = form ? N - 1 : 1;
+    q = 1;
+  }
+}
+
+inline double zwall_coef(int type, int k, int p, int N) {
+  const int form = (type == ZT_IUP || type == ZT_DUP || type == ZT_DDUP) ? 1 : 0;
+  int c, q;
+  zwall_pairs(k, form, N, c, q);
+  static const double I[4][3] = {{0, 0, 0}, {0.5, 0, 0}, {9.0 / 16.0, -1.0 / 16.0, 0},
+                                 {75.0 / 128.0, -25.0 / 256.0, 3.0 / 256.0}};
+  static const double D[4][3] = {{0, 0, 0}, {1.0, 0, 0}, {9.0 / 8.0, -1.0 / 24.0, 0},
+                                 {75.0 / 64.0, -25.0 / 384.0, 3.0 / 640.0}};
+  if (type == ZT_DDDN || type == ZT_DDUP) {
+    // weight of the first difference d_p: sum of d_P over pairs P > |p - c|
+    const int j = p > c ? p - c : c - p;
+    double w = 0.0;
+    for (int P = j + 1; P <= q; ++P) w += D[q][P - 1];
+    return w;
+  }
+  const int d = p - c;
+  const int P = d >= 0 ? d + 1 : -d;
+  if (P > q) return 0.0;
+  const bool der = type == ZT_DDN || type == ZT_DUP;
+  const double w = der ? D[q][P - 1] : I[q][P - 1];
+  return (der && d < 0) ? -w : w;
+}
 
 // A workgroup's share of the cells: kBlock consecutive cells of one box.
 struct Blk {

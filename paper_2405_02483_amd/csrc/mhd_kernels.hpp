@@ -12,12 +12,10 @@ template <class T> struct Phys {
   unsigned terms;
 };
 
-// Intermediate arrays of one RK stage (context-owned device workspace).
+// Intermediate arrays of the viscosity chain (context-owned workspace).
 template <class T> struct Work {
   T *ux, *uy, *uz;        // face velocities
   T *nus, *nmax, *nt, *lnt;
-  P8<T> ez, ey, ex;       // 6 arrays per edge set (only p[0..5] used)
-  P8<T> cf;               // Gxx Gyy Gzz Qc Hx Hy Hz (p[0..6])
 };
 
 // Kernel passes, as reported by the timing hook (order = mhd.h MHD_PASS_*).
@@ -41,16 +39,6 @@ struct Launch {
   void at(int pass) const { if (mark) mark(mark_ctx, pass); }
 };
 
-template <class T> struct StageArgs {
-  CP8<T> f;               // stage input state (ghosts already filled)
-  Work<T> w;
-  Phys<T> ph;
-  CP8<T> du_in;           // nullptr in p[0]: first stage (alpha_1 = 0)
-  P8<T> du_out;           // nullptr in p[0]: do not store dU (last stage)
-  P8<T> f_out;            // nullptr in p[0]: write F to du_out instead
-  T alpha, bdt;
-};
-
 // Per-block partial results of the float64 reductions.
 constexpr int kNSum = 8;   // mass, px, py, pz, ekin, emag(B^2), eint, divb^2
 constexpr int kNMax = 7;   // |divb|, bmax, umax, cmax, numax, ratemax, (spare)
@@ -62,7 +50,6 @@ struct RedPartial {
   long long nonfinite, nonpositive;
 };
 
-template <class T> void launch_stage(const Launch& L, const StageArgs<T>& a);
 template <class T> void launch_nu(const Launch& L, CP8<T> f, const Work<T>& w, const Phys<T>& ph);
 template <class T> void launch_ghost(const Launch& L, P8<T> f);
 template <class T>

@@ -1,6 +1,6 @@
 // z-marching kernels of one RK stage (the production forward path).
 //
-// Four passes per stage, each a single launch over all (box, tile, z-range)
+// Five passes per stage, each a single launch over all (box, tile, z-range)
 // work items:
 //   A1  face velocity u_z, div u, and the speed-like viscosity
 //       nu1|u| + nu3(c_s + c_A) + nu2 h max(0, -div u)         (eq. RMnu)
@@ -8,9 +8,10 @@
 //   Q   quantities on x- and y-directed cell edges (stress, E, Lorentz
 //       products, heating; eqs. itv, nuij, ohm, vdiss) and the z-face /
 //       centre terms that need z derivatives of z-stencil results (Gzz, Hz)
-//   F   everything else (z-edges, centre and x/y faces), all divergences
-//       (eqs. mass, mom, ien, indu), wall masking and the fused RK stage
-//       update (eqs. ddt, tupdate)
+//   P   quantities on z-directed edges and the x/y parts of the centre and
+//       face terms (only x/y stencils)
+//   F   all divergences (eqs. mass, mom, ien, indu), gravity, wall masking
+//       and the fused RK stage update (eqs. ddt, tupdate)
 // Stage-1 launches of A1 / A2 also leave per-item maxima for the Courant
 // time step (eq. courantcond), which k_dt folds into a device-resident dt.
 #include "mhd_zmarch.hpp"
@@ -34,7 +35,9 @@ namespace smhd {
   auto valid = [&](int r_) { return !wall || (r_ >= 0 && r_ < N); };          \
   auto kk = [&](int r_) { return wall ? r_ : wrapm(r_, N); };                 \
   auto col = [&](int r_) { return colo + (long long)kk(r_) * pstride; };      \
-  auto interior = [&](int r_) { return !wall || (r_ >= b.g0 && r_ < b.g1); };
+  auto interior = [&](int r_) { return !wall || (r_ >= b.g0 && r_ < b.g1); };       \
+  const T* __restrict__ zt = wall ? ztab + b.zoff : nullptr;                         \
+  (void)zt;
 
 // Block maximum of a double (all threads call; result valid in thread 0).
 template <int NT>
@@ -55,16 +58,22 @@ __device__ __forceinline__ double block_max(double v, double* sh) {
 // come from register windows.
 template <class T, int TX, int TY>
 __global__ __launch_bounds__(TX * TY) void zA1(const BoxDev* __restrict__ boxes,
-                                               const ZItem* __restrict__ items, int nitems,
-                                               CP8<T> f, Phys<T> ph, T* __restrict__ nus_out,
-                                               T* __restrict__ D_out, T* __restrict__ uz_out,
+                                               const ZItem* __restrict__ items, int nitems, const T* __restrict__ ztab,
+                                               CP8<T> f, Phys<T> ph, ZWork<T> ws,
                                                CPart* __restrict__ cpart) {
+  T* __restrict__ nus_out = ws.arr(WS_NUS);
+  T* __restrict__ D_out = ws.arr(WS_D);
+  T* __restrict__ uz_out = ws.arr(WS_UZ);
   using PR = Plane<TX, TY, 5>;
   using PP = Plane<TX, TY, 3>;
   __shared__ T sR[PR::N];
   __shared__ T sPX[PP::N], sPY[PP::N], sBX[PP::N], sBY[PP::N];
   __shared__ double sred[TX * TY];
   ZPROLOGUE
+  PlaneIdx<TX, TY, 5> i5;
+  PlaneIdx<TX, TY, 3> i3;
+  i5.init(b, it.x0, it.y0);
+  i3.init(b, it.x0, it.y0);
   T wR[6] = {}, wUZ[6] = {}, wBZ[8] = {}, fPZ[3] = {}, fE[6] = {};
   T fUBX[6] = {}, fUBY[6] = {}, fBBX[6] = {}, fBBY[6] = {}, fDXY[6] = {};
   double cmax = 0.0;
@@ -74,11 +83,11 @@ __global__ __launch_bounds__(TX * TY) void zA1(const BoxDev* __restrict__ boxes,
     if (valid(r)) {
       const int k = kk(r);
       __syncthreads();
-      load_plane<TX, TY, 5>(sR, f.p[0], b, it.x0, it.y0, k);
-      load_plane<TX, TY, 3>(sPX, f.p[1], b, it.x0, it.y0, k);
-      load_plane<TX, TY, 3>(sPY, f.p[2], b, it.x0, it.y0, k);
-      load_plane<TX, TY, 3>(sBX, f.p[5], b, it.x0, it.y0, k);
-      load_plane<TX, TY, 3>(sBY, f.p[6], b, it.x0, it.y0, k);
+      load_plane(sR, f.p[0], b, i5, k);
+      load_plane(sPX, f.p[1], b, i3, k);
+      load_plane(sPY, f.p[2], b, i3, k);
+      load_plane(sBX, f.p[5], b, i3, k);
+      load_plane(sBY, f.p[6], b, i3, k);
       __syncthreads();
       const long long o = col(r);
       rr = sR[PR::at(tx, ty)];
@@ -113,7 +122,7 @@ __global__ __launch_bounds__(TX * TY) void zA1(const BoxDev* __restrict__ boxes,
     const int q1 = r - 2;
     T uzq = T(0);
     if (valid(q1)) {
-      const T zr = zwin<0, 0, 6, 3>(wR, q1, wall, N, T(0));
+      const T zr = zwin<0, 0, 6, 3>(wR, q1, wall, N, T(0), zt);
       uzq = fPZ[0] / zr;
       if (own && q1 >= it.z0 && q1 < it.z1) uz_out[col(q1)] = uzq;
     }
@@ -121,9 +130,9 @@ __global__ __launch_bounds__(TX * TY) void zA1(const BoxDev* __restrict__ boxes,
     // centre quantities of plane q = r - 5
     const int q = r - 5;
     if (valid(q) && q >= it.z0 && q < it.z1) {
-      const T ubz = zwin<0, 1, 6, 2>(wUZ, q, wall, N, T(0));
-      const T dzz = zwin<1, 1, 6, 2>(wUZ, q, wall, N, g.hzi);
-      const T bbz = zwin<0, 1, 8, 2>(wBZ, q, wall, N, T(0));
+      const T ubz = zwin<0, 1, 6, 2>(wUZ, q, wall, N, T(0), zt);
+      const T dzz = zwin<1, 1, 6, 2>(wUZ, q, wall, N, g.hzi, zt);
+      const T bbz = zwin<0, 1, 8, 2>(wBZ, q, wall, N, T(0), zt);
       const T rq = wR[0], eq = fE[0];
       const T D = fDXY[0] + dzz;
       const T P = ph.gamma1 * eq;
@@ -164,9 +173,10 @@ __global__ __launch_bounds__(TX * TY) void zA1(const BoxDev* __restrict__ boxes,
 // z (register window), floor 1e-30, and ln.
 template <class T, int TX, int TY>
 __global__ __launch_bounds__(TX * TY) void zA2(const BoxDev* __restrict__ boxes,
-                                               const ZItem* __restrict__ items, int nitems,
-                                               const T* __restrict__ nus, T* __restrict__ lnt_out,
-                                               CPart* __restrict__ cpart) {
+                                               const ZItem* __restrict__ items, int nitems, const T* __restrict__ ztab,
+                                               ZWork<T> ws, CPart* __restrict__ cpart) {
+  const T* __restrict__ nus = ws.arr(WS_NUS);
+  T* __restrict__ lnt_out = ws.arr(WS_LNT);
   using PN = Plane<TX, TY, 2>;
   using PM = Plane<TX, TY, 1>;
   constexpr int NT = TX * TY;
@@ -175,12 +185,14 @@ __global__ __launch_bounds__(TX * TY) void zA2(const BoxDev* __restrict__ boxes,
   __shared__ T sM[PM::N];
   __shared__ double sred[NT];
   ZPROLOGUE
+  PlaneIdx<TX, TY, 2> i2;
+  i2.init(b, it.x0, it.y0);
   T wS[3] = {};
   double numax = 0.0;
   for (int r = it.z0 - 2; r <= it.z1 + 1; ++r) {
     if (valid(r)) {
       __syncthreads();
-      load_plane<TX, TY, 2>(sN, nus, b, it.x0, it.y0, kk(r));
+      load_plane(sN, nus, b, i2, kk(r));
       __syncthreads();
       T* dst = sMX[wrapm(r, 3)];
       for (int t = threadIdx.x; t < PM::N; t += NT) {
@@ -246,14 +258,17 @@ __global__ __launch_bounds__(TX * TY) void zA2(const BoxDev* __restrict__ boxes,
 //   Hz (z-face), Gzz, Czz (centre)
 template <class T, int TX, int TY>
 __global__ __launch_bounds__(TX * TY) void zQ(const BoxDev* __restrict__ boxes,
-                                              const ZItem* __restrict__ items, int nitems,
-                                              CP8<T> f, const T* __restrict__ uzg,
-                                              const T* __restrict__ lntg,
-                                              const T* __restrict__ Dg, Phys<T> ph, QP<T> out) {
+                                              const ZItem* __restrict__ items, int nitems, const T* __restrict__ ztab,
+                                              CP8<T> f, Phys<T> ph, ZWork<T> ws) {
+  const T* __restrict__ uzg = ws.arr(WS_UZ);
+  const T* __restrict__ lntg = ws.arr(WS_LNT);
+  const T* __restrict__ Dg = ws.arr(WS_D);
   using P3 = Plane<TX, TY, 3>;
   __shared__ T sR[P3::N], sL[P3::N];
   __shared__ T sUZ[3][P3::N], sBZ[3][P3::N], sPZ[3][P3::N];
   ZPROLOGUE
+  PlaneIdx<TX, TY, 3> i3;
+  i3.init(b, it.x0, it.y0);
   const unsigned tm = ph.terms;
   const bool visc = tm & T_VISC, res = tm & T_RESIST, ind = tm & T_INDUCT, lor = tm & T_LORENTZ,
              adv = tm & T_ADV, pres = tm & T_PRES, ediff = tm & T_EDIFF;
@@ -270,11 +285,11 @@ __global__ __launch_bounds__(TX * TY) void zQ(const BoxDev* __restrict__ boxes,
     if (valid(r)) {
       const int k = kk(r), sl = wrapm(r, 3);
       __syncthreads();
-      load_plane<TX, TY, 3>(sR, f.p[0], b, it.x0, it.y0, k);
-      load_plane<TX, TY, 3>(sL, lntg, b, it.x0, it.y0, k);
-      load_plane<TX, TY, 3>(sUZ[sl], uzg, b, it.x0, it.y0, k);
-      load_plane<TX, TY, 3>(sBZ[sl], f.p[7], b, it.x0, it.y0, k);
-      load_plane<TX, TY, 3>(sPZ[sl], f.p[3], b, it.x0, it.y0, k);
+      load_plane(sR, f.p[0], b, i3, k);
+      load_plane(sL, lntg, b, i3, k);
+      load_plane(sUZ[sl], uzg, b, i3, k);
+      load_plane(sBZ[sl], f.p[7], b, i3, k);
+      load_plane(sPZ[sl], f.p[3], b, i3, k);
       __syncthreads();
       const long long o = col(r);
       rx = op6<0, 0, T>([&](int m) { return sR[P3::at(tx + m, ty)]; }, T(0));
@@ -310,19 +325,19 @@ __global__ __launch_bounds__(TX * TY) void zQ(const BoxDev* __restrict__ boxes,
       const long long o = col(q);
       // ---- y-edge
       {
-        const T zRX = zwin<0, 0, 6, 3>(wRX, q, wall, N, T(0));
-        const T zPX = zwin<0, 0, 6, 3>(wPX, q, wall, N, T(0));
-        const T zUX = zwin<0, 0, 6, 3>(wUX, q, wall, N, T(0));
-        const T dzUX = zwin<1, 0, 6, 3>(wUX, q, wall, N, g.hzi);
-        const T zBX = zwin<0, 0, 6, 3>(wBX, q, wall, N, T(0));
-        const T dzBX = zwin<1, 0, 6, 3>(wBX, q, wall, N, g.hzi);
+        const T zRX = zwin<0, 0, 6, 3>(wRX, q, wall, N, T(0), zt);
+        const T zPX = zwin<0, 0, 6, 3>(wPX, q, wall, N, T(0), zt);
+        const T zUX = zwin<0, 0, 6, 3>(wUX, q, wall, N, T(0), zt);
+        const T dzUX = zwin<1, 0, 6, 3>(wUX, q, wall, N, g.hzi, zt);
+        const T zBX = zwin<0, 0, 6, 3>(wBX, q, wall, N, T(0), zt);
+        const T dzBX = zwin<1, 0, 6, 3>(wBX, q, wall, N, g.hzi, zt);
         const T xUZ = op6<0, 0, T>([&](int m) { return UZ[P3::at(tx + m, ty)]; }, T(0));
         const T dxUZ = op6<1, 0, T>([&](int m) { return UZ[P3::at(tx + m, ty)]; }, g.hxi);
         const T xBZ = op6<0, 0, T>([&](int m) { return BZ[P3::at(tx + m, ty)]; }, T(0));
         const T dxBZ = op6<1, 0, T>([&](int m) { return BZ[P3::at(tx + m, ty)]; }, g.hxi);
         const T xPZ = op6<0, 0, T>([&](int m) { return PZ[P3::at(tx + m, ty)]; }, T(0));
         T nxz = T(0), txz = T(0), sxz = T(0);
-        if (need_nu) nxz = fmax(g.dx, g.dz) * exp(zwin<0, 0, 6, 3>(wLX, q, wall, N, T(0)));
+        if (need_nu) nxz = fmax(g.dx, g.dz) * exp(zwin<0, 0, 6, 3>(wLX, q, wall, N, T(0), zt));
         if (visc) {
           sxz = T(0.5) * (dzUX + dxUZ);
           txz = zRX * nxz * sxz;
@@ -340,29 +355,29 @@ __global__ __launch_bounds__(TX * TY) void zQ(const BoxDev* __restrict__ boxes,
         T qy = visc ? T(2) * txz * sxz : T(0);
         if (res) qy = qy + eta * jy * jy * inv_mu;
         if (own) {
-          out.p[QOUT_GXZ][o] = gxz;
-          out.p[QOUT_GZX][o] = gzx;
-          out.p[QOUT_EY][o] = ey;
-          out.p[QOUT_LXY][o] = lor ? jy * xBZ : T(0);
-          out.p[QOUT_LZY][o] = lor ? jy * zBX : T(0);
-          out.p[QOUT_QY][o] = qy;
+          ws.q(QOUT_GXZ)[o] = gxz;
+          ws.q(QOUT_GZX)[o] = gzx;
+          ws.q(QOUT_EY)[o] = ey;
+          ws.q(QOUT_LXY)[o] = lor ? jy * xBZ : T(0);
+          ws.q(QOUT_LZY)[o] = lor ? jy * zBX : T(0);
+          ws.q(QOUT_QY)[o] = qy;
         }
       }
       // ---- x-edge
       {
-        const T zRY = zwin<0, 0, 6, 3>(wRY, q, wall, N, T(0));
-        const T zPY = zwin<0, 0, 6, 3>(wPY, q, wall, N, T(0));
-        const T zUY = zwin<0, 0, 6, 3>(wUY, q, wall, N, T(0));
-        const T dzUY = zwin<1, 0, 6, 3>(wUY, q, wall, N, g.hzi);
-        const T zBY = zwin<0, 0, 6, 3>(wBY, q, wall, N, T(0));
-        const T dzBY = zwin<1, 0, 6, 3>(wBY, q, wall, N, g.hzi);
+        const T zRY = zwin<0, 0, 6, 3>(wRY, q, wall, N, T(0), zt);
+        const T zPY = zwin<0, 0, 6, 3>(wPY, q, wall, N, T(0), zt);
+        const T zUY = zwin<0, 0, 6, 3>(wUY, q, wall, N, T(0), zt);
+        const T dzUY = zwin<1, 0, 6, 3>(wUY, q, wall, N, g.hzi, zt);
+        const T zBY = zwin<0, 0, 6, 3>(wBY, q, wall, N, T(0), zt);
+        const T dzBY = zwin<1, 0, 6, 3>(wBY, q, wall, N, g.hzi, zt);
         const T yUZ = op6<0, 0, T>([&](int m) { return UZ[P3::at(tx, ty + m)]; }, T(0));
         const T dyUZ = op6<1, 0, T>([&](int m) { return UZ[P3::at(tx, ty + m)]; }, g.hyi);
         const T yBZ = op6<0, 0, T>([&](int m) { return BZ[P3::at(tx, ty + m)]; }, T(0));
         const T dyBZ = op6<1, 0, T>([&](int m) { return BZ[P3::at(tx, ty + m)]; }, g.hyi);
         const T yPZ = op6<0, 0, T>([&](int m) { return PZ[P3::at(tx, ty + m)]; }, T(0));
         T nyz = T(0), tyz = T(0), syz = T(0);
-        if (need_nu) nyz = fmax(g.dy, g.dz) * exp(zwin<0, 0, 6, 3>(wLY, q, wall, N, T(0)));
+        if (need_nu) nyz = fmax(g.dy, g.dz) * exp(zwin<0, 0, 6, 3>(wLY, q, wall, N, T(0), zt));
         if (visc) {
           syz = T(0.5) * (dzUY + dyUZ);
           tyz = zRY * nyz * syz;
@@ -380,87 +395,233 @@ __global__ __launch_bounds__(TX * TY) void zQ(const BoxDev* __restrict__ boxes,
         T qx = visc ? T(2) * tyz * syz : T(0);
         if (res) qx = qx + eta * jx * jx * inv_mu;
         if (own) {
-          out.p[QOUT_GYZ][o] = gyz;
-          out.p[QOUT_GZY][o] = gzy;
-          out.p[QOUT_EX][o] = ex;
-          out.p[QOUT_LYX][o] = lor ? jx * yBZ : T(0);
-          out.p[QOUT_LZX][o] = lor ? jx * zBY : T(0);
-          out.p[QOUT_QX][o] = qx;
+          ws.q(QOUT_GYZ)[o] = gyz;
+          ws.q(QOUT_GZY)[o] = gzy;
+          ws.q(QOUT_EX)[o] = ex;
+          ws.q(QOUT_LYX)[o] = lor ? jx * yBZ : T(0);
+          ws.q(QOUT_LZX)[o] = lor ? jx * zBY : T(0);
+          ws.q(QOUT_QX)[o] = qx;
         }
       }
       // ---- z-face energy flux: -zdn(e) u_z + nuE zdn(rho) dz zdn(nu) zdn(e_m) ddzdn(ln e_m)
       {
         T hz = T(0);
-        if (adv) hz = -zwin<0, 0, 6, 3>(wE, q, wall, N, T(0)) * wUZ[3];
+        if (adv) hz = -zwin<0, 0, 6, 3>(wE, q, wall, N, T(0), zt) * wUZ[3];
         if (ediff)
-          hz = hz + ph.nuE * zwin<0, 0, 6, 3>(wRho, q, wall, N, T(0)) *
-                        (g.dz * zwin<0, 0, 6, 3>(wNu, q, wall, N, T(0))) *
-                        zwin<0, 0, 6, 3>(wEm, q, wall, N, T(0)) *
-                        zwin<1, 0, 6, 3>(wLem, q, wall, N, g.hzi);
-        if (own) out.p[QOUT_HZ][o] = hz;
+          hz = hz + ph.nuE * zwin<0, 0, 6, 3>(wRho, q, wall, N, T(0), zt) *
+                        (g.dz * zwin<0, 0, 6, 3>(wNu, q, wall, N, T(0), zt)) *
+                        zwin<0, 0, 6, 3>(wEm, q, wall, N, T(0), zt) *
+                        zwin<1, 0, 6, 3>(wLem, q, wall, N, g.hzi, zt);
+        if (own) ws.q(QOUT_HZ)[o] = hz;
       }
     }
     // centre terms of plane q2 = r - 3 (window slot 2)
     const int q2 = r - 3;
     if (valid(q2) && q2 >= it.z0 && q2 < it.z1) {
       const long long o = col(q2);
-      const T szz = zwin<1, 1, 6, 2>(wUZ, q2, wall, N, g.hzi);
+      const T szz = zwin<1, 1, 6, 2>(wUZ, q2, wall, N, g.hzi, zt);
       T gzz = T(0), czz = T(0);
       if (visc) {
         const T tzz = wRho[2] * (g.dz * wNu[2]) * (szz + ph.c1 * Dg[o]);
         gzz = tzz;
         czz = tzz * szz;
       }
-      if (adv) gzz = gzz - zwin<0, 1, 6, 2>(wPZ, q2, wall, N, T(0)) * zwin<0, 1, 6, 2>(wUZ, q2, wall, N, T(0));
+      if (adv) gzz = gzz - zwin<0, 1, 6, 2>(wPZ, q2, wall, N, T(0), zt) * zwin<0, 1, 6, 2>(wUZ, q2, wall, N, T(0), zt);
       if (pres) gzz = gzz - ph.gamma1 * wE[2];
       if (own) {
-        out.p[QOUT_GZZ][o] = gzz;
-        out.p[QOUT_CZZ][o] = czz;
+        ws.q(QOUT_GZZ)[o] = gzz;
+        ws.q(QOUT_CZZ)[o] = czz;
       }
     }
   }
 }
 
 // ---------------------------------------------------------------------------
-// F: plane-local terms of plane r through LDS (z-edges, centre, x/y faces and
-// the x/y divergences of Q's edge quantities), plus z divergences of Q's
-// outputs scattered into per-thread accumulators of output planes r-3..r+3;
-// plane r-3 is complete and is written with the RK stage update.
+// P: everything that needs only x/y stencils, once per cell at its own
+// column: the z-directed edge (x-1/2, y-1/2) quantities Gxy, Gyx, Ez, Lxz,
+// Lyz, Qz (as in Q), the centre terms Gxx = tau_xx - xup(p_x) xup(u_x) - P,
+// Gyy, Qc = tau_xx S_xx + tau_yy S_yy - P div u, and the x/y-face energy
+// fluxes Hx, Hy (eq. ien, eq. ediffuse).
 template <class T, int TX, int TY>
-__global__ __launch_bounds__(TX * TY) void zF(const BoxDev* __restrict__ boxes,
-                                              const ZItem* __restrict__ items, int nitems,
-                                              CP8<T> f, const T* __restrict__ lntg,
-                                              const T* __restrict__ Dg, CQP<T> qin, Phys<T> ph,
-                                              CP8<T> du_in, P8<T> du_out, P8<T> f_out, T alpha,
-                                              double beta, const double* __restrict__ dt_dev,
-                                              double dt_host) {
-  using P9 = Plane<TX, TY, 9>;
+__global__ __launch_bounds__(TX * TY) void zP(const BoxDev* __restrict__ boxes,
+                                              const ZItem* __restrict__ items, int nitems, const T* __restrict__ ztab,
+                                              CP8<T> f, Phys<T> ph, ZWork<T> ws) {
+  const T* __restrict__ lntg = ws.arr(WS_LNT);
+  const T* __restrict__ Dg = ws.arr(WS_D);
   using P6 = Plane<TX, TY, 6>;
   using P3 = Plane<TX, TY, 3>;
   constexpr int NT = TX * TY;
-  // level-1 planes: 0 px 1 py 2 e 3 Bx 4 By 5 ln nu 6 ux 7 uy 8 nu 9 e_m 10 ln e_m
-  constexpr int NL1 = 11;
-  __shared__ T sR[P9::N];
-  __shared__ T sL1[NL1 * P6::N];
-  __shared__ T sD[P3::N];
-  // level-4 planes: 0 Gxy 1 Gyx 2 Ez 3 Lxz 4 Lyz 5 Qz 6 Gxx 7 Gyy 8 Hx 9 Hy
-  __shared__ T sL4[10 * P3::N];
-  // Q's x/y-differentiated quantities reuse the level-1 space
-  static_assert(NL1 * P6::N >= 8 * P3::N, "LDS reuse");
-  T* sQ = sL1;
+  // halo-3 planes: 0 px 1 py 2 e 3 Bx 4 By 5 ln nu | derived: 6 ux 7 uy 8 nu
+  // 9 e_m 10 ln e_m 11 xdn(rho) 12 ydn(rho) 13 xdn(ln nu)
+  constexpr int NS = 14;
+  __shared__ T sR[P6::N];
+  __shared__ T s3[NS * P3::N];
   ZPROLOGUE
+  PlaneIdx<TX, TY, 6> i6;
+  PlaneIdx<TX, TY, 3> i3;
+  i6.init(b, it.x0, it.y0);
+  i3.init(b, it.x0, it.y0);
   const unsigned tm = ph.terms;
   const bool visc = tm & T_VISC, res = tm & T_RESIST, ind = tm & T_INDUCT, lor = tm & T_LORENTZ,
-             adv = tm & T_ADV, pres = tm & T_PRES, ediff = tm & T_EDIFF, cont = tm & T_CONT,
-             grav = tm & T_GRAV;
+             adv = tm & T_ADV, pres = tm & T_PRES, ediff = tm & T_EDIFF;
   const bool need_nu = visc || (res && !(ph.eta_const > T(0)));
+  const T inv_mu = ph.inv_mu;
+  auto S = [&](int q, int x, int y) -> T& { return s3[q * P3::N + P3::at(x, y)]; };
+  for (int k = it.z0; k < it.z1; ++k) {
+    __syncthreads();
+    load_plane(sR, f.p[0], b, i6, k);
+    load_plane(&S(0, -3, -3), f.p[1], b, i3, k);
+    load_plane(&S(1, -3, -3), f.p[2], b, i3, k);
+    load_plane(&S(2, -3, -3), f.p[4], b, i3, k);
+    load_plane(&S(3, -3, -3), f.p[5], b, i3, k);
+    load_plane(&S(4, -3, -3), f.p[6], b, i3, k);
+    load_plane(&S(5, -3, -3), lntg, b, i3, k);
+    __syncthreads();
+    for (int t = threadIdx.x; t < P3::N; t += NT) {
+      const int yy = t / P3::W, xx = t - yy * P3::W;
+      const int x = xx - 3, y = yy - 3;
+      const T rxd = op6<0, 0, T>([&](int m) { return sR[P6::at(x + m, y)]; }, T(0));
+      const T ryd = op6<0, 0, T>([&](int m) { return sR[P6::at(x, y + m)]; }, T(0));
+      const T rc = sR[P6::at(x, y)];
+      s3[6 * P3::N + t] = s3[0 * P3::N + t] / rxd;
+      s3[7 * P3::N + t] = s3[1 * P3::N + t] / ryd;
+      s3[8 * P3::N + t] = exp(s3[5 * P3::N + t]);
+      const T emv = s3[2 * P3::N + t] / rc;
+      s3[9 * P3::N + t] = emv;
+      s3[10 * P3::N + t] = log(emv);
+      s3[11 * P3::N + t] = rxd;
+      s3[12 * P3::N + t] = ryd;
+      // xdn(ln nu) is only needed on the own columns' y-strip
+      if (x >= 0 && x < TX)
+        s3[13 * P3::N + t] = op6<0, 0, T>([&](int m) { return s3[5 * P3::N + t + m]; }, T(0));
+    }
+    __syncthreads();
+    if (!own) continue;
+    const int x = tx, y = ty;
+    const long long o = colo + (long long)k * pstride;
+    // ---- z-edge (x-1/2, y-1/2)
+    T nxy = T(0), txy = T(0), sxy = T(0);
+    if (need_nu)
+      nxy = fmax(g.dx, g.dy) * exp(op6<0, 0, T>([&](int m) { return S(13, x, y + m); }, T(0)));
+    if (visc) {
+      const T rxy = op6<0, 0, T>([&](int m) { return S(11, x, y + m); }, T(0));
+      sxy = T(0.5) * (op6<1, 0, T>([&](int m) { return S(6, x, y + m); }, g.hyi) +
+                      op6<1, 0, T>([&](int m) { return S(7, x + m, y); }, g.hxi));
+      txy = rxy * nxy * sxy;
+    }
+    const T jz = op6<1, 0, T>([&](int m) { return S(4, x + m, y); }, g.hxi) -
+                 op6<1, 0, T>([&](int m) { return S(3, x, y + m); }, g.hyi);
+    const T eta = ph.eta_const > T(0) ? ph.eta_const : ph.nuB * nxy;
+    const T xBY = op6<0, 0, T>([&](int m) { return S(4, x + m, y); }, T(0));
+    const T yBX = op6<0, 0, T>([&](int m) { return S(3, x, y + m); }, T(0));
+    const T yUX = op6<0, 0, T>([&](int m) { return S(6, x, y + m); }, T(0));
+    const T xUY = op6<0, 0, T>([&](int m) { return S(7, x + m, y); }, T(0));
+    T ez = T(0);
+    if (ind) ez = ez - (yUX * xBY - xUY * yBX);
+    if (res) ez = ez + eta * jz;
+    T gxy = txy, gyx = txy;
+    if (adv) {
+      gxy = gxy - op6<0, 0, T>([&](int m) { return S(0, x, y + m); }, T(0)) * xUY;
+      gyx = gyx - op6<0, 0, T>([&](int m) { return S(1, x + m, y); }, T(0)) * yUX;
+    }
+    T qz = visc ? T(2) * txy * sxy : T(0);
+    if (res) qz = qz + eta * jz * jz * inv_mu;
+    ws.pq(POUT_GXY)[o] = gxy;
+    ws.pq(POUT_GYX)[o] = gyx;
+    ws.pq(POUT_EZ)[o] = ez;
+    ws.pq(POUT_LXZ)[o] = lor ? jz * xBY : T(0);
+    ws.pq(POUT_LYZ)[o] = lor ? jz * yBX : T(0);
+    ws.pq(POUT_QZ)[o] = qz;
+    // ---- centre
+    {
+      const T sxx = op6<1, 1, T>([&](int m) { return S(6, x + m, y); }, g.hxi);
+      const T syy = op6<1, 1, T>([&](int m) { return S(7, x, y + m); }, g.hyi);
+      const T Dc = Dg[o];
+      const T Pc = ph.gamma1 * S(2, x, y);
+      T gxx = T(0), gyy = T(0), qc = T(0);
+      if (visc) {
+        const T rn = sR[P6::at(x, y)] * S(8, x, y);
+        const T txx = rn * g.dx * (sxx + ph.c1 * Dc);
+        const T tyy = rn * g.dy * (syy + ph.c1 * Dc);
+        gxx = txx;
+        gyy = tyy;
+        qc = txx * sxx + tyy * syy;
+      }
+      if (adv) {
+        gxx = gxx - op6<0, 1, T>([&](int m) { return S(0, x + m, y); }, T(0)) *
+                        op6<0, 1, T>([&](int m) { return S(6, x + m, y); }, T(0));
+        gyy = gyy - op6<0, 1, T>([&](int m) { return S(1, x, y + m); }, T(0)) *
+                        op6<0, 1, T>([&](int m) { return S(7, x, y + m); }, T(0));
+      }
+      if (pres) {
+        gxx = gxx - Pc;
+        gyy = gyy - Pc;
+        qc = qc - Pc * Dc;
+      }
+      ws.pq(POUT_GXX)[o] = gxx;
+      ws.pq(POUT_GYY)[o] = gyy;
+      ws.pq(POUT_QC)[o] = qc;
+    }
+    // ---- x- and y-faces: energy fluxes
+    {
+      T hx = T(0), hy = T(0);
+      if (adv) {
+        hx = -op6<0, 0, T>([&](int m) { return S(2, x + m, y); }, T(0)) * S(6, x, y);
+        hy = -op6<0, 0, T>([&](int m) { return S(2, x, y + m); }, T(0)) * S(7, x, y);
+      }
+      if (ediff) {
+        hx = hx + ph.nuE * S(11, x, y) *
+                      (g.dx * op6<0, 0, T>([&](int m) { return S(8, x + m, y); }, T(0))) *
+                      op6<0, 0, T>([&](int m) { return S(9, x + m, y); }, T(0)) *
+                      op6<1, 0, T>([&](int m) { return S(10, x + m, y); }, g.hxi);
+        hy = hy + ph.nuE * S(12, x, y) *
+                      (g.dy * op6<0, 0, T>([&](int m) { return S(8, x, y + m); }, T(0))) *
+                      op6<0, 0, T>([&](int m) { return S(9, x, y + m); }, T(0)) *
+                      op6<1, 0, T>([&](int m) { return S(10, x, y + m); }, g.hyi);
+      }
+      ws.pq(POUT_HX)[o] = hx;
+      ws.pq(POUT_HY)[o] = hy;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// F: all divergences of P's and Q's quantities and of the momenta, the
+// gravity force, wall masking and the RK stage update.  x/y divergences of
+// plane r through LDS strips; z divergences scattered into per-thread
+// accumulators of output planes r-3..r+3 (first differences for
+// derivatives); plane r-3 is then complete.
+template <class T, int TX, int TY>
+__global__ __launch_bounds__(TX * TY) void zF(const BoxDev* __restrict__ boxes,
+                                              const ZItem* __restrict__ items, int nitems, const T* __restrict__ ztab,
+                                              CP8<T> f, ZWork<T> ws, Phys<T> ph, P8<T> du,
+                                              int du_mode, P8<T> f_out, T alpha, double beta,
+                                              const double* __restrict__ dt_dev,
+                                              double dt_host) {
+  using PXs = Plane<TX, TY, 3, 0>;   // x-halo strips
+  using PYs = Plane<TX, TY, 0, 3>;   // y-halo strips
+  using P3 = Plane<TX, TY, 3>;
+  // x strips: 0 px 1 Gxx 2 Gyx 3 Lyz 4 Hx 5 Gzx 6 Lzy 7 Ey 8 Qy
+  // y strips: 0 py 1 Gxy 2 Lxz 3 Gyy 4 Hy 5 Gzy 6 Lzx 7 Ex 8 Qx
+  // full:     0 Qz 1 Ez
+  __shared__ T sx[9 * PXs::N];
+  __shared__ T sy[9 * PYs::N];
+  __shared__ T s2[2 * P3::N];
+  ZPROLOGUE
+  PlaneIdx<TX, TY, 3, 0> ix;
+  PlaneIdx<TX, TY, 0, 3> iy;
+  PlaneIdx<TX, TY, 3> i3;
+  ix.init(b, it.x0, it.y0);
+  iy.init(b, it.x0, it.y0);
+  i3.init(b, it.x0, it.y0);
+  const unsigned tm = ph.terms;
+  const bool cont = tm & T_CONT, grav = tm & T_GRAV;
   const T inv_mu = ph.inv_mu;
   const double dt = dt_dev ? *dt_dev : dt_host;
   const T bdt = T(beta * dt);
-  auto L1 = [&](int q, int x, int y) -> T& { return sL1[q * P6::N + P6::at(x, y)]; };
-  auto L4 = [&](int q, int x, int y) -> T& { return sL4[q * P3::N + P3::at(x, y)]; };
-  auto QS = [&](int q, int x, int y) -> T& { return sQ[q * P3::N + P3::at(x, y)]; };
-  // Q planes in LDS: 0 Gzx 1 Ey 2 Lzy 3 Qy 4 Gzy 5 Ex 6 Lzx 7 Qx
+  auto X = [&](int q, int x) -> T { return sx[q * PXs::N + PXs::at(x, ty)]; };
+  auto Y = [&](int q, int y) -> T { return sy[q * PYs::N + PYs::at(tx, y)]; };
+  auto F2 = [&](int q, int x, int y) -> T { return s2[q * P3::N + P3::at(x, y)]; };
   T acc[7][7];
 #pragma unroll
   for (int a = 0; a < 7; ++a)
@@ -481,11 +642,11 @@ __global__ __launch_bounds__(TX * TY) void zF(const BoxDev* __restrict__ boxes,
     }
     const long long o = col(k);
     if (f_out.p[0] == nullptr) {
-      du_out.p[v][o] = Fv;
+      du.p[v][o] = Fv;
       return;
     }
-    const T U = du_in.p[0] ? alpha * du_in.p[v][o] + Fv : Fv;
-    if (du_out.p[0]) du_out.p[v][o] = U;
+    const T U = (du_mode & DU_READ) ? alpha * du.p[v][o] + Fv : Fv;
+    if (du_mode & DU_WRITE) du.p[v][o] = U;
     f_out.p[v][o] = f.p[v][o] + bdt * U;
   };
 
@@ -495,208 +656,81 @@ __global__ __launch_bounds__(TX * TY) void zF(const BoxDev* __restrict__ boxes,
     if (valid(r)) {
       const int k = kk(r);
       const long long o = col(r);
-      if (inch) {
-        // ---- level-1 planes of plane r
-        __syncthreads();
-        load_plane<TX, TY, 9>(sR, f.p[0], b, it.x0, it.y0, k);
-        load_plane<TX, TY, 6>(&L1(0, -6, -6), f.p[1], b, it.x0, it.y0, k);
-        load_plane<TX, TY, 6>(&L1(1, -6, -6), f.p[2], b, it.x0, it.y0, k);
-        load_plane<TX, TY, 6>(&L1(2, -6, -6), f.p[4], b, it.x0, it.y0, k);
-        load_plane<TX, TY, 6>(&L1(3, -6, -6), f.p[5], b, it.x0, it.y0, k);
-        load_plane<TX, TY, 6>(&L1(4, -6, -6), f.p[6], b, it.x0, it.y0, k);
-        load_plane<TX, TY, 6>(&L1(5, -6, -6), lntg, b, it.x0, it.y0, k);
-        load_plane<TX, TY, 3>(sD, Dg, b, it.x0, it.y0, k);
-        __syncthreads();
-        for (int t = threadIdx.x; t < P6::N; t += NT) {
-          const int yy = t / P6::W, xx = t - yy * P6::W;
-          const int x = xx - 6, y = yy - 6;
-          const T rxd = op6<0, 0, T>([&](int m) { return sR[P9::at(x + m, y)]; }, T(0));
-          const T ryd = op6<0, 0, T>([&](int m) { return sR[P9::at(x, y + m)]; }, T(0));
-          const T rc = sR[P9::at(x, y)];
-          sL1[6 * P6::N + t] = sL1[0 * P6::N + t] / rxd;
-          sL1[7 * P6::N + t] = sL1[1 * P6::N + t] / ryd;
-          sL1[8 * P6::N + t] = exp(sL1[5 * P6::N + t]);
-          const T emv = sL1[2 * P6::N + t] / rc;
-          sL1[9 * P6::N + t] = emv;
-          sL1[10 * P6::N + t] = log(emv);
-        }
-        __syncthreads();
-        // ---- level-4 quantities on the halo-3 region
-        for (int t = threadIdx.x; t < P3::N; t += NT) {
-          const int yy = t / P3::W, xx = t - yy * P3::W;
-          const int x = xx - 3, y = yy - 3;
-          // z-edge (x-1/2, y-1/2)
-          T nxy = T(0), txy = T(0), sxy = T(0);
-          if (need_nu) {
-            const T lxy = op6<0, 0, T>([&](int m) {
-              return op6<0, 0, T>([&](int a) { return L1(5, x + a, y + m); }, T(0));
-            }, T(0));
-            nxy = fmax(g.dx, g.dy) * exp(lxy);
-          }
-          if (visc) {
-            const T rxy = op6<0, 0, T>([&](int m) {
-              return op6<0, 0, T>([&](int a) { return sR[P9::at(x + a, y + m)]; }, T(0));
-            }, T(0));
-            sxy = T(0.5) * (op6<1, 0, T>([&](int m) { return L1(6, x, y + m); }, g.hyi) +
-                            op6<1, 0, T>([&](int m) { return L1(7, x + m, y); }, g.hxi));
-            txy = rxy * nxy * sxy;
-          }
-          const T jz = op6<1, 0, T>([&](int m) { return L1(4, x + m, y); }, g.hxi) -
-                       op6<1, 0, T>([&](int m) { return L1(3, x, y + m); }, g.hyi);
-          const T eta = ph.eta_const > T(0) ? ph.eta_const : ph.nuB * nxy;
-          const T xBY = op6<0, 0, T>([&](int m) { return L1(4, x + m, y); }, T(0));
-          const T yBX = op6<0, 0, T>([&](int m) { return L1(3, x, y + m); }, T(0));
-          T ez = T(0);
-          if (ind)
-            ez = ez - (op6<0, 0, T>([&](int m) { return L1(6, x, y + m); }, T(0)) * xBY -
-                       op6<0, 0, T>([&](int m) { return L1(7, x + m, y); }, T(0)) * yBX);
-          if (res) ez = ez + eta * jz;
-          T gxy = txy, gyx = txy;
-          if (adv) {
-            gxy = gxy - op6<0, 0, T>([&](int m) { return L1(0, x, y + m); }, T(0)) *
-                            op6<0, 0, T>([&](int m) { return L1(7, x + m, y); }, T(0));
-            gyx = gyx - op6<0, 0, T>([&](int m) { return L1(1, x + m, y); }, T(0)) *
-                            op6<0, 0, T>([&](int m) { return L1(6, x, y + m); }, T(0));
-          }
-          T qz = visc ? T(2) * txy * sxy : T(0);
-          if (res) qz = qz + eta * jz * jz * inv_mu;
-          sL4[0 * P3::N + t] = gxy;
-          sL4[1 * P3::N + t] = gyx;
-          sL4[2 * P3::N + t] = ez;
-          sL4[3 * P3::N + t] = lor ? jz * xBY : T(0);
-          sL4[4 * P3::N + t] = lor ? jz * yBX : T(0);
-          sL4[5 * P3::N + t] = qz;
-          // centre (x, y): Gxx, Gyy
-          const T sxx = op6<1, 1, T>([&](int m) { return L1(6, x + m, y); }, g.hxi);
-          const T syy = op6<1, 1, T>([&](int m) { return L1(7, x, y + m); }, g.hyi);
-          const T Dc = sD[P3::at(x, y)];
-          const T rc = sR[P9::at(x, y)];
-          const T nc = L1(8, x, y);
-          const T Pc = ph.gamma1 * L1(2, x, y);
-          T gxx = T(0), gyy = T(0);
-          if (visc) {
-            gxx = rc * (g.dx * nc) * (sxx + ph.c1 * Dc);
-            gyy = rc * (g.dy * nc) * (syy + ph.c1 * Dc);
-          }
-          if (adv) {
-            gxx = gxx - op6<0, 1, T>([&](int m) { return L1(0, x + m, y); }, T(0)) *
-                            op6<0, 1, T>([&](int m) { return L1(6, x + m, y); }, T(0));
-            gyy = gyy - op6<0, 1, T>([&](int m) { return L1(1, x, y + m); }, T(0)) *
-                            op6<0, 1, T>([&](int m) { return L1(7, x, y + m); }, T(0));
-          }
-          if (pres) {
-            gxx = gxx - Pc;
-            gyy = gyy - Pc;
-          }
-          sL4[6 * P3::N + t] = gxx;
-          sL4[7 * P3::N + t] = gyy;
-          // x- and y-faces: energy fluxes
-          T hx = T(0), hy = T(0);
-          if (adv) {
-            hx = -op6<0, 0, T>([&](int m) { return L1(2, x + m, y); }, T(0)) * L1(6, x, y);
-            hy = -op6<0, 0, T>([&](int m) { return L1(2, x, y + m); }, T(0)) * L1(7, x, y);
-          }
-          if (ediff) {
-            hx = hx + ph.nuE * op6<0, 0, T>([&](int m) { return sR[P9::at(x + m, y)]; }, T(0)) *
-                          (g.dx * op6<0, 0, T>([&](int m) { return L1(8, x + m, y); }, T(0))) *
-                          op6<0, 0, T>([&](int m) { return L1(9, x + m, y); }, T(0)) *
-                          op6<1, 0, T>([&](int m) { return L1(10, x + m, y); }, g.hxi);
-            hy = hy + ph.nuE * op6<0, 0, T>([&](int m) { return sR[P9::at(x, y + m)]; }, T(0)) *
-                          (g.dy * op6<0, 0, T>([&](int m) { return L1(8, x, y + m); }, T(0))) *
-                          op6<0, 0, T>([&](int m) { return L1(9, x, y + m); }, T(0)) *
-                          op6<1, 0, T>([&](int m) { return L1(10, x, y + m); }, g.hyi);
-          }
-          sL4[8 * P3::N + t] = hx;
-          sL4[9 * P3::N + t] = hy;
-        }
-        __syncthreads();
-        // ---- x/y divergences at the own column, plane r (accumulator slot 3)
-        {
-          const int x = tx, y = ty;
-          if (cont)
-            acc[0][3] += -(op6<1, 1, T>([&](int m) { return L1(0, x + m, y); }, g.hxi) +
-                           op6<1, 1, T>([&](int m) { return L1(1, x, y + m); }, g.hyi));
-          acc[1][3] += op6<1, 0, T>([&](int m) { return L4(6, x + m, y); }, g.hxi) +
-                       op6<1, 1, T>([&](int m) { return L4(0, x, y + m); }, g.hyi) -
-                       op6<0, 1, T>([&](int m) { return L4(3, x, y + m); }, T(0)) * inv_mu;
-          acc[2][3] += op6<1, 0, T>([&](int m) { return L4(7, x, y + m); }, g.hyi) +
-                       op6<1, 1, T>([&](int m) { return L4(1, x + m, y); }, g.hxi) +
-                       op6<0, 1, T>([&](int m) { return L4(4, x + m, y); }, T(0)) * inv_mu;
-          // centre heating and pressure work (the z part tau_zz S_zz comes from Q)
-          T qc = T(0);
-          if (visc) {
-            const T sxx = op6<1, 1, T>([&](int m) { return L1(6, x + m, y); }, g.hxi);
-            const T syy = op6<1, 1, T>([&](int m) { return L1(7, x, y + m); }, g.hyi);
-            const T Dc = sD[P3::at(x, y)];
-            const T rc = sR[P9::at(x, y)];
-            const T nc = L1(8, x, y);
-            qc = rc * (g.dx * nc) * (sxx + ph.c1 * Dc) * sxx + rc * (g.dy * nc) * (syy + ph.c1 * Dc) * syy;
-            qc = qc + qin.p[QOUT_CZZ][o];
-          }
-          if (pres) qc = qc - ph.gamma1 * L1(2, x, y) * sD[P3::at(x, y)];
-          acc[4][3] += qc + op6<1, 1, T>([&](int m) { return L4(8, x + m, y); }, g.hxi) +
-                       op6<1, 1, T>([&](int m) { return L4(9, x, y + m); }, g.hyi) +
-                       op6<0, 1, T>([&](int m) {
-                         return op6<0, 1, T>([&](int a) { return L4(5, x + a, y + m); }, T(0));
-                       }, T(0));
-          acc[5][3] += -op6<1, 1, T>([&](int m) { return L4(2, x, y + m); }, g.hyi);
-          acc[6][3] += op6<1, 1, T>([&](int m) { return L4(2, x + m, y); }, g.hxi);
-        }
-      }
-      // ---- Q's quantities of plane r that are differentiated across x / y
       __syncthreads();
       if (inch) {
-        load_plane<TX, TY, 3>(&QS(0, -3, -3), qin.p[QOUT_GZX], b, it.x0, it.y0, k);
-        load_plane<TX, TY, 3>(&QS(1, -3, -3), qin.p[QOUT_EY], b, it.x0, it.y0, k);
-        load_plane<TX, TY, 3>(&QS(2, -3, -3), qin.p[QOUT_LZY], b, it.x0, it.y0, k);
-        load_plane<TX, TY, 3>(&QS(4, -3, -3), qin.p[QOUT_GZY], b, it.x0, it.y0, k);
-        load_plane<TX, TY, 3>(&QS(5, -3, -3), qin.p[QOUT_EX], b, it.x0, it.y0, k);
-        load_plane<TX, TY, 3>(&QS(6, -3, -3), qin.p[QOUT_LZX], b, it.x0, it.y0, k);
+        const T* xs[8] = {f.p[1], ws.pq(POUT_GXX), ws.pq(POUT_GYX), ws.pq(POUT_LYZ),
+                          ws.pq(POUT_HX), ws.q(QOUT_GZX), ws.q(QOUT_LZY), ws.q(QOUT_EY)};
+        const T* ys[8] = {f.p[2], ws.pq(POUT_GXY), ws.pq(POUT_LXZ), ws.pq(POUT_GYY),
+                          ws.pq(POUT_HY), ws.q(QOUT_GZY), ws.q(QOUT_LZX), ws.q(QOUT_EX)};
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          load_plane(sx + q * PXs::N, xs[q], b, ix, k);
+          load_plane(sy + q * PYs::N, ys[q], b, iy, k);
+        }
+        load_plane(s2, ws.pq(POUT_QZ), b, i3, k);
+        load_plane(s2 + P3::N, ws.pq(POUT_EZ), b, i3, k);
       }
-      load_plane<TX, TY, 3>(&QS(3, -3, -3), qin.p[QOUT_QY], b, it.x0, it.y0, k);
-      load_plane<TX, TY, 3>(&QS(7, -3, -3), qin.p[QOUT_QX], b, it.x0, it.y0, k);
+      load_plane(sx + 8 * PXs::N, ws.q(QOUT_QY), b, ix, k);
+      load_plane(sy + 8 * PYs::N, ws.q(QOUT_QX), b, iy, k);
       __syncthreads();
       const int x = tx, y = ty;
       if (inch) {
-        acc[3][3] += op6<1, 1, T>([&](int m) { return QS(0, x + m, y); }, g.hxi) +
-                     op6<1, 1, T>([&](int m) { return QS(4, x, y + m); }, g.hyi) +
-                     (op6<0, 1, T>([&](int m) { return QS(6, x, y + m); }, T(0)) -
-                      op6<0, 1, T>([&](int m) { return QS(2, x + m, y); }, T(0))) * inv_mu;
+        if (cont)
+          acc[0][3] += -(op6<1, 1, T>([&](int m) { return X(0, x + m); }, g.hxi) +
+                         op6<1, 1, T>([&](int m) { return Y(0, y + m); }, g.hyi));
+        acc[1][3] += op6<1, 0, T>([&](int m) { return X(1, x + m); }, g.hxi) +
+                     op6<1, 1, T>([&](int m) { return Y(1, y + m); }, g.hyi) -
+                     op6<0, 1, T>([&](int m) { return Y(2, y + m); }, T(0)) * inv_mu;
+        acc[2][3] += op6<1, 0, T>([&](int m) { return Y(3, y + m); }, g.hyi) +
+                     op6<1, 1, T>([&](int m) { return X(2, x + m); }, g.hxi) +
+                     op6<0, 1, T>([&](int m) { return X(3, x + m); }, T(0)) * inv_mu;
+        acc[3][3] += op6<1, 1, T>([&](int m) { return X(5, x + m); }, g.hxi) +
+                     op6<1, 1, T>([&](int m) { return Y(5, y + m); }, g.hyi) +
+                     (op6<0, 1, T>([&](int m) { return Y(6, y + m); }, T(0)) -
+                      op6<0, 1, T>([&](int m) { return X(6, x + m); }, T(0))) * inv_mu;
+        acc[4][3] += ws.pq(POUT_QC)[o] + ws.q(QOUT_CZZ)[o] +
+                     op6<1, 1, T>([&](int m) { return X(4, x + m); }, g.hxi) +
+                     op6<1, 1, T>([&](int m) { return Y(4, y + m); }, g.hyi) +
+                     op6<0, 1, T>([&](int m) {
+                       return op6<0, 1, T>([&](int a) { return F2(0, x + a, y + m); }, T(0));
+                     }, T(0));
+        acc[5][3] += -op6<1, 1, T>([&](int m) { return F2(1, x, y + m); }, g.hyi);
+        acc[6][3] += op6<1, 1, T>([&](int m) { return F2(1, x + m, y); }, g.hxi);
         // Bz has no z divergence: complete at once
-        const T fbz = -(op6<1, 1, T>([&](int m) { return QS(1, x + m, y); }, g.hxi) -
-                        op6<1, 1, T>([&](int m) { return QS(5, x, y + m); }, g.hyi));
+        const T fbz = -(op6<1, 1, T>([&](int m) { return X(7, x + m); }, g.hxi) -
+                        op6<1, 1, T>([&](int m) { return Y(7, y + m); }, g.hyi));
         if (own) finalize(7, r, fbz);
       }
-      const T xqy = op6<0, 1, T>([&](int m) { return QS(3, x + m, y); }, T(0));
-      const T yqx = op6<0, 1, T>([&](int m) { return QS(7, x, y + m); }, T(0));
+      const T xqy = op6<0, 1, T>([&](int m) { return X(8, x + m); }, T(0));
+      const T yqx = op6<0, 1, T>([&](int m) { return Y(8, y + m); }, T(0));
       // ---- z divergences of plane r scattered into output planes r-3..r+3:
       // derivatives through first differences, interpolations directly
       T cur[7];
       cur[0] = f.p[3][o];
-      cur[1] = qin.p[QOUT_GXZ][o];
-      cur[2] = qin.p[QOUT_GYZ][o];
-      cur[3] = qin.p[QOUT_GZZ][o];
-      cur[4] = qin.p[QOUT_HZ][o];
-      cur[5] = qin.p[QOUT_EY][o];
-      cur[6] = qin.p[QOUT_EX][o];
+      cur[1] = ws.q(QOUT_GXZ)[o];
+      cur[2] = ws.q(QOUT_GYZ)[o];
+      cur[3] = ws.q(QOUT_GZZ)[o];
+      cur[4] = ws.q(QOUT_HZ)[o];
+      cur[5] = ws.q(QOUT_EY)[o];
+      cur[6] = ws.q(QOUT_EX)[o];
       T dl[7];
 #pragma unroll
       for (int a = 0; a < 7; ++a) {
         dl[a] = (cur[a] - prev[a]) * g.hzi;
         prev[a] = cur[a];
       }
-      if (cont) zscatter_d<1, 3>(acc[0], kb, -dl[0], wall, N);
-      zscatter_d<1, 3>(acc[1], kb, dl[1], wall, N);
-      zscatter<0, 1, 3>(acc[1], kb, qin.p[QOUT_LXY][o] * inv_mu, wall, N);
-      zscatter_d<1, 3>(acc[2], kb, dl[2], wall, N);
-      zscatter<0, 1, 3>(acc[2], kb, -qin.p[QOUT_LYX][o] * inv_mu, wall, N);
-      zscatter_d<0, 3>(acc[3], kb, dl[3], wall, N);
-      if (grav) zscatter<0, 0, 3>(acc[3], kb, -f.p[0][o] * ph.gz, wall, N);
-      zscatter_d<1, 3>(acc[4], kb, dl[4], wall, N);
-      zscatter<0, 1, 3>(acc[4], kb, xqy, wall, N);
-      zscatter<0, 1, 3>(acc[4], kb, yqx, wall, N);
-      zscatter_d<1, 3>(acc[5], kb, dl[5], wall, N);
-      zscatter_d<1, 3>(acc[6], kb, -dl[6], wall, N);
+      if (cont) zscatter_d<1, 3>(acc[0], kb, -dl[0], wall, N, zt);
+      zscatter_d<1, 3>(acc[1], kb, dl[1], wall, N, zt);
+      zscatter<0, 1, 3>(acc[1], kb, ws.q(QOUT_LXY)[o] * inv_mu, wall, N, zt);
+      zscatter_d<1, 3>(acc[2], kb, dl[2], wall, N, zt);
+      zscatter<0, 1, 3>(acc[2], kb, -ws.q(QOUT_LYX)[o] * inv_mu, wall, N, zt);
+      zscatter_d<0, 3>(acc[3], kb, dl[3], wall, N, zt);
+      if (grav) zscatter<0, 0, 3>(acc[3], kb, -f.p[0][o] * ph.gz, wall, N, zt);
+      zscatter_d<1, 3>(acc[4], kb, dl[4], wall, N, zt);
+      zscatter<0, 1, 3>(acc[4], kb, xqy, wall, N, zt);
+      zscatter<0, 1, 3>(acc[4], kb, yqx, wall, N, zt);
+      zscatter_d<1, 3>(acc[5], kb, dl[5], wall, N, zt);
+      zscatter_d<1, 3>(acc[6], kb, -dl[6], wall, N, zt);
     } else {
 #pragma unroll
       for (int a = 0; a < 7; ++a) prev[a] = T(0);
@@ -748,29 +782,25 @@ static void launch_zstage_t(const ZLaunch& L, const ZStageArgs<T>& a) {
   const int n = L.nitems;
   const dim3 grid(8 * ((n + 7) / 8)), block(TX * TY);
   L.at(PASS_PRIM);
-  hipLaunchKernelGGL((zA1<T, TX, TY>), grid, block, 0, L.stream, L.boxes, L.items, n, a.f, a.ph,
-                     a.w.nus, a.w.D, a.w.uz, a.cpart);
+  hipLaunchKernelGGL((zA1<T, TX, TY>), grid, block, 0, L.stream, L.boxes, L.items, n, a.ztab,
+                     a.f, a.ph, a.w, a.cpart);
   L.at(PASS_MEAN3);
-  hipLaunchKernelGGL((zA2<T, TX, TY>), grid, block, 0, L.stream, L.boxes, L.items, n, a.w.nus,
-                     a.w.lnt, a.cpart);
+  hipLaunchKernelGGL((zA2<T, TX, TY>), grid, block, 0, L.stream, L.boxes, L.items, n, a.ztab,
+                     a.w, a.cpart);
   if (a.cpart) {
     L.at(PASS_REDUCE);
     hipLaunchKernelGGL(k_dt, dim3(1), dim3(256), 0, L.stream, L.boxes, L.items, n, a.cpart, a.Cdt,
                        a.Cdtd, a.nuB, a.eta_const, a.dt_dev);
   }
   L.at(PASS_EDGES);
-  QP<T> qo;
-  CQP<T> qi;
-  for (int q = 0; q < QOUT_COUNT; ++q) {
-    qo.p[q] = a.w.q[q];
-    qi.p[q] = a.w.q[q];
-  }
-  hipLaunchKernelGGL((zQ<T, TX, TY>), grid, block, 0, L.stream, L.boxes, L.items, n, a.f, a.w.uz,
-                     a.w.lnt, a.w.D, a.ph, qo);
+  hipLaunchKernelGGL((zQ<T, TX, TY>), grid, block, 0, L.stream, L.boxes, L.items, n, a.ztab, a.f,
+                     a.ph, a.w);
+  L.at(PASS_CF);
+  hipLaunchKernelGGL((zP<T, TX, TY>), grid, block, 0, L.stream, L.boxes, L.items, n, a.ztab, a.f,
+                     a.ph, a.w);
   L.at(PASS_FINAL);
-  hipLaunchKernelGGL((zF<T, TX, TY>), grid, block, 0, L.stream, L.boxes, L.items, n, a.f, a.w.lnt,
-                     a.w.D, qi, a.ph, a.du_in, a.du_out, a.f_out, a.alpha, a.beta, a.dt_dev,
-                     a.dt_host);
+  hipLaunchKernelGGL((zF<T, TX, TY>), grid, block, 0, L.stream, L.boxes, L.items, n, a.ztab, a.f,
+                     a.w, a.ph, a.du, a.du_mode, a.f_out, a.alpha, a.beta, a.dt_dev, a.dt_host);
   L.at(PASS_END);
 }
 
@@ -781,8 +811,7 @@ void launch_zstage(const ZLaunch& L, const ZStageArgs<T>& a) {
     case ZTILE_16x16: launch_zstage_t<T, 16, 16>(L, a); break;
     case ZTILE_16x8: launch_zstage_t<T, 16, 8>(L, a); break;
     default:
-      // 64x4 needs more LDS than a workgroup has in float64 (ztile_ok)
-      if constexpr (sizeof(T) == 4) launch_zstage_t<T, 64, 4>(L, a);
+      launch_zstage_t<T, 64, 4>(L, a);
       break;
   }
 }

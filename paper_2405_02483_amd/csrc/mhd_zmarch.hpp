@@ -32,31 +32,6 @@ __device__ __forceinline__ int wrapm(int a, int n) {
   return r < 0 ? r + n : r;
 }
 
-// Coefficient of plane p in the output of plane k of a z operator on a
-// wall-bounded axis of N planes (same order choice as opwall).
-template <int FAM, int FORM, class T>
-__device__ __forceinline__ T zcoef_wall(int k, int p, int N) {
-  int c = k + FORM;
-  int q = min(3, min(c, N - c));
-  if (q == 0) {
-    c = FORM ? N - 1 : 1;
-    q = 1;
-  }
-  const int d = p - c;
-  const int P = d >= 0 ? d + 1 : -d;
-  if (P > q) return T(0);
-  T w;
-  if (q == 3) {
-    w = FAM == 0 ? (P == 1 ? Cf<T>::IA : (P == 2 ? Cf<T>::IB : Cf<T>::IC))
-                 : (P == 1 ? Cf<T>::DA : (P == 2 ? Cf<T>::DB : Cf<T>::DC));
-  } else if (q == 2) {
-    w = FAM == 0 ? (P == 1 ? Cf<T>::I4A : Cf<T>::I4B) : (P == 1 ? Cf<T>::D4A : Cf<T>::D4B);
-  } else {
-    w = FAM == 0 ? T(0.5) : T(1);
-  }
-  return (FAM == 1 && d < 0) ? -w : w;
-}
-
 // Sixth-order coefficient for offset d = p - k (periodic axis, or an output
 // plane whose full stencil lies inside the array).
 template <int FAM, int FORM, class T>
@@ -71,18 +46,22 @@ __device__ __forceinline__ constexpr T zcoef6(int d) {
 }
 
 // z operator at output plane q from a register window whose slot LAG holds
-// plane q.  Periodic: the fixed sixth-order stencil; wall: coefficient per
-// slot from the plane-dependent order.  FAM 0 interpolation, 1 derivative;
-// FORM 0 dn, 1 up.
+// plane q.  Periodic boxes, and planes whose full stencil lies inside a
+// wall-bounded box: the sixth-order stencil on differences; planes next to a
+// wall end: the box's coefficient table zt (type ZT), read through the
+// scalar cache.  FAM 0 interpolation, 1 derivative; FORM 0 dn, 1 up.
 template <int FAM, int FORM, int W, int LAG, class T>
-__device__ __forceinline__ T zwin(const T (&w)[W], int q, bool wall, int N, T hinv) {
+__device__ __forceinline__ T zwin(const T (&w)[W], int q, bool wall, int N, T hinv,
+                                  const T* __restrict__ zt) {
   static_assert(LAG >= 3 - FORM && W - 1 - LAG >= 2 + FORM, "window too short");
-  if (!wall) {
+  if (!wall || (q >= 3 && q <= N - 4)) {
     return op6<FAM, FORM, T>([&](int m) { return w[LAG + m]; }, hinv);
   }
+  constexpr int type = FAM == 0 ? (FORM ? ZT_IUP : ZT_IDN) : (FORM ? ZT_DUP : ZT_DDN);
+  const T* c = zt + ((long long)type * N + q) * 7 + 3 - LAG;   // c[m]: slot m
   T acc = T(0);
 #pragma unroll
-  for (int m = 0; m < W; ++m) acc += zcoef_wall<FAM, FORM, T>(q, q - LAG + m, N) * w[m];
+  for (int m = (LAG - 3 > 0 ? LAG - 3 : 0); m < (LAG + 4 < W ? LAG + 4 : W); ++m) acc += c[m] * w[m];
   return FAM ? acc * hinv : acc;
 }
 
@@ -96,16 +75,18 @@ template <int W, class T> __device__ __forceinline__ void push(T (&w)[W], T v) {
 // acc[s] of output planes k = kbase + s (s = 0..6) of a z operator (the 1/h
 // of a derivative is folded into v by the caller).
 template <int FAM, int FORM, int PK, class T>
-__device__ __forceinline__ void zscatter(T (&acc)[7], int kbase, T v, bool wall, int N) {
-  if (!wall) {
+__device__ __forceinline__ void zscatter(T (&acc)[7], int kbase, T v, bool wall, int N,
+                                         const T* __restrict__ zt) {
+  if (!wall || (kbase >= 3 && kbase + 6 <= N - 4)) {
 #pragma unroll
     for (int s = 0; s < 7; ++s) acc[s] += zcoef6<FAM, FORM, T>(PK - s) * v;
     return;
   }
+  constexpr int type = FAM == 0 ? (FORM ? ZT_IUP : ZT_IDN) : (FORM ? ZT_DUP : ZT_DDN);
 #pragma unroll
   for (int s = 0; s < 7; ++s) {
     const int k = kbase + s;
-    if (k >= 0 && k < N) acc[s] += zcoef_wall<FAM, FORM, T>(k, kbase + PK, N) * v;
+    if (k >= 0 && k < N) acc[s] += zt[((long long)type * N + k) * 7 + PK - s + 3] * v;
   }
 }
 
@@ -115,29 +96,6 @@ __device__ __forceinline__ void zscatter(T (&acc)[7], int kbase, T v, bool wall,
 // W = sum of the pair coefficients d_P over P > |m - c|.  Scattering d_m
 // (instead of f) keeps the rounding relative to the differences, as in the
 // gather form, where a plain scatter of f would round relative to |f|.
-template <int FORM, class T>
-__device__ __forceinline__ T zdcoef_wall(int k, int m, int N) {
-  int c = k + FORM;
-  int q = min(3, min(c, N - c));
-  if (q == 0) {
-    c = FORM ? N - 1 : 1;
-    q = 1;
-  }
-  const int j = m - c < 0 ? c - m : m - c;
-  T w = T(0);
-  if (q == 3) {
-    if (j <= 0) w += Cf<T>::DA;
-    if (j <= 1) w += Cf<T>::DB;
-    if (j <= 2) w += Cf<T>::DC;
-  } else if (q == 2) {
-    if (j <= 0) w += Cf<T>::D4A;
-    if (j <= 1) w += Cf<T>::D4B;
-  } else {
-    if (j == 0) w = T(1);
-  }
-  return w;
-}
-
 template <int FORM, class T>
 __device__ __forceinline__ constexpr T zdcoef6(int d) {
   // d = m - k; j = |m - c| with c = k + FORM
@@ -150,38 +108,60 @@ __device__ __forceinline__ constexpr T zdcoef6(int d) {
 // p = kbase + PK into the derivative accumulators of output planes
 // kbase + s, s = 0..6.
 template <int FORM, int PK, class T>
-__device__ __forceinline__ void zscatter_d(T (&acc)[7], int kbase, T dv, bool wall, int N) {
-  if (!wall) {
+__device__ __forceinline__ void zscatter_d(T (&acc)[7], int kbase, T dv, bool wall, int N,
+                                           const T* __restrict__ zt) {
+  if (!wall || (kbase >= 3 && kbase + 6 <= N - 4)) {
 #pragma unroll
     for (int s = 0; s < 7; ++s) acc[s] += zdcoef6<FORM, T>(PK - s) * dv;
     return;
   }
+  constexpr int type = FORM ? ZT_DDUP : ZT_DDDN;
 #pragma unroll
   for (int s = 0; s < 7; ++s) {
     const int k = kbase + s;
-    if (k >= 0 && k < N) acc[s] += zdcoef_wall<FORM, T>(k, kbase + PK, N) * dv;
+    if (k >= 0 && k < N) acc[s] += zt[((long long)type * N + k) * 7 + PK - s + 3] * dv;
   }
 }
 
-// Tile plane in LDS: (TX + 2H) x (TY + 2H) values of one plane, element
-// (x, y) of the tile (x, y may be -H .. T+H-1) at (y + H) * W + (x + H).
-template <int TX, int TY, int H> struct Plane {
-  static constexpr int W = TX + 2 * H;
-  static constexpr int HT = TY + 2 * H;
+// Tile plane in LDS: (TX + 2HX) x (TY + 2HY) values of one plane, element
+// (x, y) of the tile (x in -HX .. TX+HX-1, y in -HY .. TY+HY-1) at
+// (y + HY) * W + (x + HX).
+template <int TX, int TY, int HX, int HY = HX> struct Plane {
+  static constexpr int W = TX + 2 * HX;
+  static constexpr int HT = TY + 2 * HY;
   static constexpr int N = W * HT;
-  static __device__ __forceinline__ int at(int x, int y) { return (y + H) * W + (x + H); }
+  static __device__ __forceinline__ int at(int x, int y) { return (y + HY) * W + (x + HX); }
+};
+
+// In-plane offsets (periodic wrap in x and y already applied) of the tile
+// plane elements this thread loads: element t = threadIdx.x + i * (TX*TY).
+// They do not change from plane to plane, so they are computed once.
+template <int TX, int TY, int HX, int HY = HX> struct PlaneIdx {
+  using PL = Plane<TX, TY, HX, HY>;
+  static constexpr int NT = TX * TY;
+  static constexpr int NPER = (PL::N + NT - 1) / NT;
+  int off[NPER];
+  __device__ __forceinline__ void init(const BoxDev& b, int x0, int y0) {
+#pragma unroll
+    for (int i = 0; i < NPER; ++i) {
+      const int t = (int)threadIdx.x + i * NT;
+      const int yy = t / PL::W, xx = t - yy * PL::W;
+      off[i] = t < PL::N ? wrapm(y0 + yy - HY, b.ny) * b.nx + wrapm(x0 + xx - HX, b.nx) : 0;
+    }
+  }
 };
 
 // Cooperative load of plane k of a field into a tile plane buffer.
-template <int TX, int TY, int H, class T>
+template <int TX, int TY, int HX, int HY, class T>
 __device__ __forceinline__ void load_plane(T* __restrict__ dst, const T* __restrict__ src,
-                                           const BoxDev& b, int x0, int y0, int k) {
-  using PL = Plane<TX, TY, H>;
-  const long long base = b.off + (long long)k * b.nx * b.ny;
-  for (int t = threadIdx.x; t < PL::N; t += TX * TY) {
-    const int yy = t / PL::W, xx = t - yy * PL::W;
-    const int gx = wrapm(x0 + xx - H, b.nx), gy = wrapm(y0 + yy - H, b.ny);
-    dst[t] = src[base + (long long)gy * b.nx + gx];
+                                           const BoxDev& b, const PlaneIdx<TX, TY, HX, HY>& ix,
+                                           int k) {
+  using PX = PlaneIdx<TX, TY, HX, HY>;
+  const T* __restrict__ s = src + b.off + (long long)k * b.nx * b.ny;
+#pragma unroll
+  for (int i = 0; i < PX::NPER; ++i) {
+    const int t = (int)threadIdx.x + i * PX::NT;
+    if (t < PX::PL::N) dst[t] = s[ix.off[i]];
   }
 }
 

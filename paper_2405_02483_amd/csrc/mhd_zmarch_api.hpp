@@ -15,19 +15,36 @@ enum QOut : int {
 template <class T> struct QP { T* p[QOUT_COUNT]; };
 template <class T> struct CQP { const T* p[QOUT_COUNT]; };
 
+// Outputs of pass P, in workspace order.
+enum POut : int {
+  POUT_GXY = 0, POUT_GYX, POUT_EZ, POUT_LXZ, POUT_LYZ, POUT_QZ,
+  POUT_GXX, POUT_GYY, POUT_QC, POUT_HX, POUT_HY, POUT_COUNT
+};
+
+template <class T> struct PQ { T* p[POUT_COUNT]; };
+template <class T> struct CPQ { const T* p[POUT_COUNT]; };
+
 // Tile shapes (columns per workgroup, x by y) the stage kernels are built for.
 enum ZTile : int { ZTILE_64x4 = 0, ZTILE_32x8 = 1, ZTILE_16x16 = 2, ZTILE_16x8 = 3, ZTILE_COUNT };
 
-// Whether a tile shape is built for an element size (the 64x4 float64
-// variant of pass F would exceed the 160 KB of LDS of a workgroup).
-inline bool ztile_ok(int t, size_t esize) { return t >= 0 && t < ZTILE_COUNT && !(t == ZTILE_64x4 && esize == 8); }
+// Whether a tile shape is built for an element size (all are).
+inline bool ztile_ok(int t, size_t esize) { (void)esize; return t >= 0 && t < ZTILE_COUNT; }
 
 inline int ztile_x(int t) { return t == ZTILE_64x4 ? 64 : (t == ZTILE_32x8 ? 32 : 16); }
 inline int ztile_y(int t) { return t == ZTILE_64x4 ? 4 : (t == ZTILE_32x8 ? 8 : (t == ZTILE_16x16 ? 16 : 8)); }
 
+// Stage workspace: WS_COUNT arrays of `stride` elements back to back, so a
+// kernel needs one base pointer for all of them (array pointers held in
+// scalar registers would otherwise spill).
+enum WsArr : int { WS_NUS = 0, WS_D, WS_UZ, WS_LNT, WS_Q0, WS_P0 = WS_Q0 + QOUT_COUNT,
+                   WS_COUNT = WS_P0 + POUT_COUNT };
+
 template <class T> struct ZWork {
-  T *nus, *D, *uz, *lnt;
-  T* q[QOUT_COUNT];
+  T* base;
+  long long stride;
+  __host__ __device__ T* arr(int a) const { return base + (long long)a * stride; }
+  __host__ __device__ T* q(int i) const { return arr(WS_Q0 + i); }
+  __host__ __device__ T* pq(int i) const { return arr(WS_P0 + i); }
 };
 
 struct ZLaunch {
@@ -41,18 +58,21 @@ struct ZLaunch {
   void at(int pass) const { if (mark) mark(mark_ctx, pass); }
 };
 
+enum : int { DU_READ = 1, DU_WRITE = 2 };
+
 template <class T> struct ZStageArgs {
   CP8<T> f;               // stage input state (ghosts filled)
   ZWork<T> w;
   Phys<T> ph;
-  CP8<T> du_in;           // p[0] == nullptr: first stage
-  P8<T> du_out;           // p[0] == nullptr: do not store dU
-  P8<T> f_out;            // p[0] == nullptr: write F into du_out
+  P8<T> du;               // the 2N-storage derivative (or dfdt when f_out is null)
+  int du_mode;            // DU_READ: U = alpha dU + F;  DU_WRITE: store U
+  P8<T> f_out;            // p[0] == nullptr: write F into du
   T alpha;
   double beta;            // the stage's beta; f_out = f + beta * dt * U
   double* dt_dev;         // device dt (nullptr: use dt_host)
   double dt_host;
   CPart* cpart;           // non-null: also compute the Courant dt into dt_dev
+  const T* ztab;          // z-coefficient tables of wall boxes (BoxDev::zoff)
   double Cdt, Cdtd, nuB, eta_const;
 };
 

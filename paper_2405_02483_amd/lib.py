@@ -200,7 +200,7 @@ def mhd_reductions(ctx, f, dfdt=None, *, dtype, n, allow_nonfinite=False):
     return st.as_dict()
 
 
-PASS_NAMES = ("A1", "unused1", "unused2", "A2", "Q", "unused5", "F", "ghost", "reduce",
+PASS_NAMES = ("A1", "unused1", "unused2", "A2", "Q", "P", "F", "ghost", "reduce",
               "adjoint")
 TILES = {"64x4": 0, "32x8": 1, "16x16": 2, "16x8": 3}
 

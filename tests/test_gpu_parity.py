@@ -250,8 +250,6 @@ def test_tile_shapes_give_identical_bits(dtype):
     ctx = _ctx(box, prm, dtype)
     ref = None
     for name in TILES:
-        if name == "64x4" and dtype == torch.float64:
-            continue
         ctx.set_tile(name)
         fd = ctx.upload([f])
         ctx.step(fd, 2e-3, 2)
