@@ -1,0 +1,483 @@
+// Discrete adjoint of the right-hand side (see mhd_adjoint.hpp): the program
+// builder (host) and the forward / transposed whole-box kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "mhd_adjoint.hpp"
+
+namespace smhd {
+
+// ---------------------------------------------------------------------------
+// Program builder.  Follows the right-hand side of eqs. mass, mom, ien, indu,
+// ohm, itv, vdiss, RMnu, nuij and ediffuse term by term, with the readings
+// of the float64 reference (dissipative viscous sign, eta a magnetic
+// diffusivity, shock viscosity nu2 h max(0, -div u), edge viscosities by
+// averaging ln nu, the energy-diffusion flux without the extra grid step).
+namespace {
+
+constexpr int ZERO = -1;   // the zero field: never stored, folded away
+
+struct Builder {
+  VProgram P;
+
+  int emit(int op, int a, int b, int c, double k, int geo, int ax, int fam, int form) {
+    VInstr I{};
+    I.op = op;
+    I.out = P.nslots++;
+    I.a = a;
+    I.b = b;
+    I.c = c;
+    I.k = k;
+    I.geo = geo;
+    I.ax = ax;
+    I.fam = fam;
+    I.form = form;
+    P.code.push_back(I);
+    return I.out;
+  }
+  int un(int op, int a, double k = 0.0, int geo = G_ONE) {
+    return emit(op, a, ZERO, ZERO, k, geo, 0, 0, 0);
+  }
+  int st(int a, int ax, int fam, int form) {
+    return a == ZERO ? ZERO : emit(V_STEN, a, ZERO, ZERO, 0.0, G_ONE, ax, fam, form);
+  }
+  // staggered operators (eqs. deriv, interp): fam 0 interpolation, 1 derivative
+  int xdn(int a) { return st(a, VX, 0, 0); }
+  int xup(int a) { return st(a, VX, 0, 1); }
+  int ydn(int a) { return st(a, VY, 0, 0); }
+  int yup(int a) { return st(a, VY, 0, 1); }
+  int zdn(int a) { return st(a, VZ, 0, 0); }
+  int zup(int a) { return st(a, VZ, 0, 1); }
+  int ddxdn(int a) { return st(a, VX, 1, 0); }
+  int ddxup(int a) { return st(a, VX, 1, 1); }
+  int ddydn(int a) { return st(a, VY, 1, 0); }
+  int ddyup(int a) { return st(a, VY, 1, 1); }
+  int ddzdn(int a) { return st(a, VZ, 1, 0); }
+  int ddzup(int a) { return st(a, VZ, 1, 1); }
+
+  int neg(int a) { return a == ZERO ? ZERO : un(V_SCALE, a, -1.0); }
+  int add(int a, int b) {
+    if (a == ZERO) return b;
+    if (b == ZERO) return a;
+    return emit(V_ADD, a, b, ZERO, 0.0, G_ONE, 0, 0, 0);
+  }
+  int sub(int a, int b) {
+    if (b == ZERO) return a;
+    if (a == ZERO) return neg(b);
+    return emit(V_SUB, a, b, ZERO, 0.0, G_ONE, 0, 0, 0);
+  }
+  int mul(int a, int b) {
+    if (a == ZERO || b == ZERO) return ZERO;
+    return emit(V_MUL, a, b, ZERO, 0.0, G_ONE, 0, 0, 0);
+  }
+  int div(int a, int b) {   // b is never the zero field
+    if (a == ZERO) return ZERO;
+    return emit(V_DIV, a, b, ZERO, 0.0, G_ONE, 0, 0, 0);
+  }
+  int scale(int a, double k, int geo = G_ONE) { return a == ZERO ? ZERO : un(V_SCALE, a, k, geo); }
+  int divc(int a, double k) { return a == ZERO ? ZERO : un(V_DIVC, a, k); }
+  int fsqrt(int a) { return un(V_SQRT, a); }
+  int flog(int a) { return un(V_LOG, a); }
+  int fexp(int a) { return un(V_EXP, a); }
+  int relu(int a) { return a == ZERO ? ZERO : un(V_RELU, a); }
+  int floor_at(int a, double k) { return un(V_FLOOR, a, k); }
+  int norm3(int a, int b, int c) { return emit(V_NORM3, a, b, c, 0.0, G_ONE, 0, 0, 0); }
+  int max3(int a, int ax) { return emit(V_MAX3, a, ZERO, ZERO, 0.0, G_ONE, ax, 0, 0); }
+  int mean3(int a, int ax) { return emit(V_MEAN3, a, ZERO, ZERO, 0.0, G_ONE, ax, 0, 0); }
+  int fill(double k, int geo = G_ONE) { return emit(V_FILL, ZERO, ZERO, ZERO, k, geo, 0, 0, 0); }
+};
+
+// Drops instructions whose results never reach an output, renumbers slots
+// densely (0..7 stay the state) and makes every output a slot of its own
+// that no instruction reads.
+VProgram finish(Builder& B, int out[8]) {
+  for (int v = 0; v < 8; ++v) {
+    if (out[v] == ZERO) out[v] = B.fill(0.0);
+    bool shared = out[v] < 8;
+    for (int w = 0; w < v; ++w) shared |= out[w] == out[v];
+    for (const auto& I : B.P.code) shared |= I.a == out[v] || I.b == out[v] || I.c == out[v];
+    if (shared) out[v] = B.un(V_SCALE, out[v], 1.0);
+  }
+  VProgram& P = B.P;
+  std::vector<char> live(P.nslots, 0);
+  for (int v = 0; v < 8; ++v) live[out[v]] = 1;
+  std::vector<char> keep(P.code.size(), 0);
+  for (int n = (int)P.code.size() - 1; n >= 0; --n) {
+    const VInstr& I = P.code[n];
+    if (!live[I.out]) continue;
+    keep[n] = 1;
+    for (int s : {I.a, I.b, I.c})
+      if (s >= 0) live[s] = 1;
+  }
+  std::vector<int> remap(P.nslots, -1);
+  for (int s = 0; s < 8; ++s) remap[s] = s;
+  VProgram R;
+  R.nslots = 8;
+  for (size_t n = 0; n < P.code.size(); ++n) {
+    if (!keep[n]) continue;
+    VInstr I = P.code[n];
+    remap[I.out] = R.nslots++;
+    I.out = remap[I.out];
+    I.a = I.a >= 0 ? remap[I.a] : ZERO;
+    I.b = I.b >= 0 ? remap[I.b] : ZERO;
+    I.c = I.c >= 0 ? remap[I.c] : ZERO;
+    R.code.push_back(I);
+  }
+  for (int v = 0; v < 8; ++v) R.out[v] = remap[out[v]];
+  return R;
+}
+
+}  // namespace
+
+VProgram build_rhs_program(const mhd_params& p) {
+  Builder B;
+  const unsigned T = p.terms;
+  const int rho = 0, px = 1, py = 2, pz = 3, e = 4, bx = 5, by = 6, bz = 7;
+  const int Z = ZERO;
+
+  // primitives and the smoothed viscosity (Section 6.1.1, eq. RMnu)
+  const int P = B.scale(e, p.gamma - 1.0);
+  const int ux = B.div(px, B.xdn(rho)), uy = B.div(py, B.ydn(rho)), uz = B.div(pz, B.zdn(rho));
+  const int sxx = B.ddxup(ux), syy = B.ddyup(uy), szz = B.ddzup(uz);
+  const int D = B.add(B.add(sxx, syy), szz);
+  int nus;
+  if (p.nu_const > 0) {
+    nus = B.fill(p.nu_const, G_HINV);
+  } else {
+    const int ub = B.norm3(B.xup(ux), B.yup(uy), B.zup(uz));
+    const int bb = B.norm3(B.xup(bx), B.yup(by), B.zup(bz));
+    const int cs = B.fsqrt(B.div(B.scale(P, p.gamma), rho));
+    const int ca = B.div(bb, B.fsqrt(B.scale(rho, p.mu)));
+    nus = B.add(B.add(B.scale(ub, p.nu1), B.scale(B.add(cs, ca), p.nu3)),
+                B.scale(B.relu(B.neg(D)), p.nu2, G_H));
+  }
+  int m = B.max3(B.max3(B.max3(nus, VX), VY), VZ);
+  int nt = B.mean3(B.mean3(B.mean3(m, VX), VY), VZ);
+  nt = B.floor_at(nt, 1e-30);
+  const int em = B.div(e, rho);
+  const int lnt = B.flog(nt);
+
+  // edge viscosities and densities (eq. nuij)
+  const int nxy = B.scale(B.fexp(B.ydn(B.xdn(lnt))), 1.0, G_MXY);
+  const int nxz = B.scale(B.fexp(B.zdn(B.xdn(lnt))), 1.0, G_MXZ);
+  const int nyz = B.scale(B.fexp(B.zdn(B.ydn(lnt))), 1.0, G_MYZ);
+  const int rxy = B.ydn(B.xdn(rho)), rxz = B.zdn(B.xdn(rho)), ryz = B.zdn(B.ydn(rho));
+
+  // strain and stress (eq. itv)
+  const int sxy = B.scale(B.add(B.ddydn(ux), B.ddxdn(uy)), 0.5);
+  const int sxz = B.scale(B.add(B.ddzdn(ux), B.ddxdn(uz)), 0.5);
+  const int syz = B.scale(B.add(B.ddzdn(uy), B.ddydn(uz)), 0.5);
+  const int txx = B.mul(B.mul(rho, B.scale(nt, 1.0, G_DX)), B.add(sxx, B.scale(D, p.c1)));
+  const int tyy = B.mul(B.mul(rho, B.scale(nt, 1.0, G_DY)), B.add(syy, B.scale(D, p.c1)));
+  const int tzz = B.mul(B.mul(rho, B.scale(nt, 1.0, G_DZ)), B.add(szz, B.scale(D, p.c1)));
+  const int txy = B.mul(B.mul(rxy, nxy), sxy);
+  const int txz = B.mul(B.mul(rxz, nxz), sxz);
+  const int tyz = B.mul(B.mul(ryz, nyz), syz);
+
+  // current and electric field (eq. ohm)
+  const int jx = B.sub(B.ddydn(bz), B.ddzdn(by));
+  const int jy = B.sub(B.ddzdn(bx), B.ddxdn(bz));
+  const int jz = B.sub(B.ddxdn(by), B.ddydn(bx));
+  int etx, ety, etz;
+  if (p.eta_const > 0) {
+    etx = ety = etz = B.fill(p.eta_const);
+  } else {
+    etx = B.scale(nyz, p.nuB);
+    ety = B.scale(nxz, p.nuB);
+    etz = B.scale(nxy, p.nuB);
+  }
+  int ex = Z, ey = Z, ez = Z;
+  if (T & MHD_T_INDUCT) {
+    ex = B.sub(ex, B.sub(B.mul(B.zdn(uy), B.ydn(bz)), B.mul(B.ydn(uz), B.zdn(by))));
+    ey = B.sub(ey, B.sub(B.mul(B.xdn(uz), B.zdn(bx)), B.mul(B.zdn(ux), B.xdn(bz))));
+    ez = B.sub(ez, B.sub(B.mul(B.ydn(ux), B.xdn(by)), B.mul(B.xdn(uy), B.ydn(bx))));
+  }
+  if (T & MHD_T_RESIST) {
+    ex = B.add(ex, B.mul(etx, jx));
+    ey = B.add(ey, B.mul(ety, jy));
+    ez = B.add(ez, B.mul(etz, jz));
+  }
+
+  // mass (eq. mass)
+  int drho = Z;
+  if (T & MHD_T_CONT) drho = B.neg(B.add(B.add(B.ddxup(px), B.ddyup(py)), B.ddzup(pz)));
+
+  // momentum (eq. mom)
+  int dpx = Z, dpy = Z, dpz = Z;
+  if (T & MHD_T_ADV) {
+    dpx = B.sub(dpx, B.add(B.add(B.ddxdn(B.mul(B.xup(px), B.xup(ux))),
+                                 B.ddyup(B.mul(B.ydn(px), B.xdn(uy)))),
+                           B.ddzup(B.mul(B.zdn(px), B.xdn(uz)))));
+    dpy = B.sub(dpy, B.add(B.add(B.ddydn(B.mul(B.yup(py), B.yup(uy))),
+                                 B.ddzup(B.mul(B.zdn(py), B.ydn(uz)))),
+                           B.ddxup(B.mul(B.xdn(py), B.ydn(ux)))));
+    dpz = B.sub(dpz, B.add(B.add(B.ddzdn(B.mul(B.zup(pz), B.zup(uz))),
+                                 B.ddxup(B.mul(B.xdn(pz), B.zdn(ux)))),
+                           B.ddyup(B.mul(B.ydn(pz), B.zdn(uy)))));
+  }
+  if (T & MHD_T_PRES) {
+    dpx = B.sub(dpx, B.ddxdn(P));
+    dpy = B.sub(dpy, B.ddydn(P));
+    dpz = B.sub(dpz, B.ddzdn(P));
+  }
+  if (T & MHD_T_LORENTZ) {
+    dpx = B.add(dpx, B.divc(B.sub(B.zup(B.mul(jy, B.xdn(bz))), B.yup(B.mul(jz, B.xdn(by)))), p.mu));
+    dpy = B.add(dpy, B.divc(B.sub(B.xup(B.mul(jz, B.ydn(bx))), B.zup(B.mul(jx, B.ydn(bz)))), p.mu));
+    dpz = B.add(dpz, B.divc(B.sub(B.yup(B.mul(jx, B.zdn(by))), B.xup(B.mul(jy, B.zdn(bx)))), p.mu));
+  }
+  if (T & MHD_T_VISC) {
+    dpx = B.add(B.add(B.add(dpx, B.ddxdn(txx)), B.ddyup(txy)), B.ddzup(txz));
+    dpy = B.add(B.add(B.add(dpy, B.ddydn(tyy)), B.ddzup(tyz)), B.ddxup(txy));
+    dpz = B.add(B.add(B.add(dpz, B.ddzdn(tzz)), B.ddxup(txz)), B.ddyup(tyz));
+  }
+  if (T & MHD_T_GRAV) dpz = B.sub(dpz, B.scale(B.zdn(rho), p.gz));
+
+  // internal energy (eqs. ien, vdiss, ediffuse)
+  int de = Z;
+  if (T & MHD_T_ADV)
+    de = B.sub(de, B.add(B.add(B.ddxup(B.mul(B.xdn(e), ux)), B.ddyup(B.mul(B.ydn(e), uy))),
+                         B.ddzup(B.mul(B.zdn(e), uz))));
+  if (T & MHD_T_PRES) de = B.sub(de, B.mul(P, D));
+  if (T & MHD_T_VISC) {
+    int qv = B.add(B.add(B.mul(txx, sxx), B.mul(tyy, syy)), B.mul(tzz, szz));
+    qv = B.add(qv, B.scale(B.add(B.add(B.yup(B.xup(B.mul(txy, sxy))), B.zup(B.xup(B.mul(txz, sxz)))),
+                                 B.zup(B.yup(B.mul(tyz, syz)))),
+                           2.0));
+    de = B.add(de, qv);
+  }
+  if (T & MHD_T_RESIST) {
+    const int qj = B.divc(B.add(B.add(B.zup(B.yup(B.mul(B.mul(etx, jx), jx))),
+                                      B.zup(B.xup(B.mul(B.mul(ety, jy), jy)))),
+                                B.yup(B.xup(B.mul(B.mul(etz, jz), jz)))),
+                          p.mu);
+    de = B.add(de, qj);
+  }
+  if (T & MHD_T_EDIFF) {
+    const int lne = B.flog(em);
+    const int fx = B.mul(B.mul(B.mul(B.scale(B.xdn(rho), p.nuE), B.scale(B.xdn(nt), 1.0, G_DX)), B.xdn(em)),
+                         B.ddxdn(lne));
+    const int fy = B.mul(B.mul(B.mul(B.scale(B.ydn(rho), p.nuE), B.scale(B.ydn(nt), 1.0, G_DY)), B.ydn(em)),
+                         B.ddydn(lne));
+    const int fz = B.mul(B.mul(B.mul(B.scale(B.zdn(rho), p.nuE), B.scale(B.zdn(nt), 1.0, G_DZ)), B.zdn(em)),
+                         B.ddzdn(lne));
+    de = B.add(B.add(B.add(de, B.ddxup(fx)), B.ddyup(fy)), B.ddzup(fz));
+  }
+
+  // induction (eq. indu)
+  const int dbx = B.neg(B.sub(B.ddyup(ez), B.ddzup(ey)));
+  const int dby = B.neg(B.sub(B.ddzup(ex), B.ddxup(ez)));
+  const int dbz = B.neg(B.sub(B.ddxup(ey), B.ddyup(ex)));
+
+  int out[8] = {drho, dpx, dpy, dpz, de, dbx, dby, dbz};
+  return finish(B, out);
+}
+
+// ---------------------------------------------------------------------------
+// Kernels: one thread per cell of the packed boxes (block table as for the
+// other whole-box passes).
+
+#define VM_PROLOGUE                                     \
+  CellIdx ci;                                           \
+  BoxDev bx_;                                           \
+  if (!cell_of(boxes, tab, ci, bx_)) return;            \
+  const Geo<T> g(bx_);                                  \
+  const int i = ci.i, j = ci.j, k = ci.k;               \
+  const long long o = g.at(i, j, k);
+
+namespace {
+
+__device__ __forceinline__ double geo_of(const BoxDev& b, int geo) {
+  switch (geo) {
+    case G_DX: return b.dx;
+    case G_DY: return b.dy;
+    case G_DZ: return b.dz;
+    case G_H: return b.hmin;
+    case G_MXY: return fmax(b.dx, b.dy);
+    case G_MXZ: return fmax(b.dx, b.dz);
+    case G_MYZ: return fmax(b.dy, b.dz);
+    default: return 1.0;
+  }
+}
+
+// Value of a at offset m along axis ax from (i, j, k).
+template <class T>
+__device__ __forceinline__ T along(const T* a, const Geo<T>& g, int ax, int i, int j, int k, int m) {
+  return ax == VX ? a[g.at(i + m, j, k)] : (ax == VY ? a[g.at(i, j + m, k)] : a[g.at(i, j, k + m)]);
+}
+
+template <class T>
+__device__ __forceinline__ T sten(const T* a, const Geo<T>& g, int ax, int fam, int form, int i, int j,
+                                  int k) {
+  auto at = [&](int m) { return along(a, g, ax, i, j, k, m); };
+  const T hinv = ax == VX ? g.hxi : (ax == VY ? g.hyi : g.hzi);
+  if (fam == 0) return form ? op6<0, 1, T>(at, hinv) : op6<0, 0, T>(at, hinv);
+  return form ? op6<1, 1, T>(at, hinv) : op6<1, 0, T>(at, hinv);
+}
+
+// Which of (lo, mid, hi) is the first maximal one: 0, 1 or 2.
+template <class T> __device__ __forceinline__ int first_max(T lo, T mid, T hi) {
+  int s = 0;
+  T v = lo;
+  if (mid > v) { v = mid; s = 1; }
+  if (hi > v) s = 2;
+  return s;
+}
+
+}  // namespace
+
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_vm_fwd(const BoxDev* boxes, const Blk* tab, VInstr I,
+                                                   T* base, long long stride) {
+  VM_PROLOGUE
+  const T* a = I.a >= 0 ? base + I.a * stride : nullptr;
+  const T* b = I.b >= 0 ? base + I.b * stride : nullptr;
+  const T* c = I.c >= 0 ? base + I.c * stride : nullptr;
+  T r;
+  switch (I.op) {
+    case V_STEN: r = sten(a, g, I.ax, I.fam, I.form, i, j, k); break;
+    case V_ADD: r = a[o] + b[o]; break;
+    case V_SUB: r = a[o] - b[o]; break;
+    case V_MUL: r = a[o] * b[o]; break;
+    case V_DIV: r = a[o] / b[o]; break;
+    case V_SCALE: r = T(I.k * geo_of(bx_, I.geo)) * a[o]; break;
+    case V_DIVC: r = a[o] / T(I.k); break;
+    case V_SQRT: r = sqrt(a[o]); break;
+    case V_LOG: r = log(a[o]); break;
+    case V_EXP: r = exp(a[o]); break;
+    case V_RELU: r = a[o] > T(0) ? a[o] : T(0); break;
+    case V_FLOOR: r = a[o] > T(I.k) ? a[o] : T(I.k); break;
+    case V_NORM3: {
+      const T s = a[o] * a[o] + b[o] * b[o] + c[o] * c[o];
+      r = s > T(0) ? sqrt(s) : T(0);
+      break;
+    }
+    case V_MAX3: {
+      const T lo = along(a, g, I.ax, i, j, k, -1), mid = a[o], hi = along(a, g, I.ax, i, j, k, 1);
+      const int s = first_max(lo, mid, hi);
+      r = s == 0 ? lo : (s == 1 ? mid : hi);
+      break;
+    }
+    case V_MEAN3:
+      r = (along(a, g, I.ax, i, j, k, -1) + a[o] + along(a, g, I.ax, i, j, k, 1)) / T(3);
+      break;
+    case V_FILL:
+      r = I.geo == G_HINV ? T(I.k / bx_.hmin) : T(I.k * geo_of(bx_, I.geo));
+      break;
+    default: r = T(0); break;
+  }
+  base[I.out * stride + o] = r;
+}
+
+// Transposes.  Each thread owns the cotangents of its own cell, so the
+// gathers of the stencil, max and mean transposes need no atomics; the
+// pointwise rules update the input cotangents one after the other (an input
+// may appear twice, as in a * a).
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_vm_bwd(const BoxDev* boxes, const Blk* tab, VInstr I,
+                                                   const T* base, T* cbase, long long stride) {
+  VM_PROLOGUE
+  const T* a = I.a >= 0 ? base + I.a * stride : nullptr;
+  const T* b = I.b >= 0 ? base + I.b * stride : nullptr;
+  const T* c = I.c >= 0 ? base + I.c * stride : nullptr;
+  T* ca = I.a >= 0 ? cbase + I.a * stride : nullptr;
+  T* cb = I.b >= 0 ? cbase + I.b * stride : nullptr;
+  T* cc = I.c >= 0 ? cbase + I.c * stride : nullptr;
+  const T* yb = cbase + I.out * stride;
+  switch (I.op) {
+    case V_STEN: {
+      // interpolation: S^T = the opposite stagger; derivative: minus it
+      const T t = sten(yb, g, I.ax, I.fam, 1 - I.form, i, j, k);
+      ca[o] += I.fam ? -t : t;
+      break;
+    }
+    case V_ADD: ca[o] += yb[o]; cb[o] += yb[o]; break;
+    case V_SUB: ca[o] += yb[o]; cb[o] -= yb[o]; break;
+    case V_MUL: {
+      const T y = yb[o], va = a[o], vb = b[o];
+      ca[o] += y * vb;
+      cb[o] += y * va;
+      break;
+    }
+    case V_DIV: {
+      const T y = yb[o], vb = b[o], q = base[I.out * stride + o];
+      ca[o] += y / vb;
+      cb[o] -= y * q / vb;
+      break;
+    }
+    case V_SCALE: ca[o] += T(I.k * geo_of(bx_, I.geo)) * yb[o]; break;
+    case V_DIVC: ca[o] += yb[o] / T(I.k); break;
+    case V_SQRT: ca[o] += yb[o] / (T(2) * base[I.out * stride + o]); break;
+    case V_LOG: ca[o] += yb[o] / a[o]; break;
+    case V_EXP: ca[o] += yb[o] * base[I.out * stride + o]; break;
+    case V_RELU: if (a[o] > T(0)) ca[o] += yb[o]; break;
+    case V_FLOOR: if (a[o] > T(I.k)) ca[o] += yb[o]; break;
+    case V_NORM3: {
+      const T n = base[I.out * stride + o];
+      if (n > T(0)) {
+        const T y = yb[o] / n, va = a[o], vb = b[o], vc = c[o];
+        ca[o] += y * va;
+        cb[o] += y * vb;
+        cc[o] += y * vc;
+      }
+      break;
+    }
+    case V_MAX3: {
+      // cell (i) is the hi neighbour of i-1, the middle of i, the lo of i+1
+      auto v = [&](int m) { return along(a, g, I.ax, i, j, k, m); };
+      auto w = [&](int m) { return along(yb, g, I.ax, i, j, k, m); };
+      const T vm2 = v(-2), vm1 = v(-1), v0 = a[o], vp1 = v(1), vp2 = v(2);
+      T s = T(0);
+      if (first_max(vm2, vm1, v0) == 2) s += w(-1);
+      if (first_max(vm1, v0, vp1) == 1) s += yb[o];
+      if (first_max(v0, vp1, vp2) == 0) s += w(1);
+      ca[o] += s;
+      break;
+    }
+    case V_MEAN3:
+      ca[o] += (along(yb, g, I.ax, i, j, k, -1) + yb[o] + along(yb, g, I.ax, i, j, k, 1)) / T(3);
+      break;
+    default: break;
+  }
+}
+
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_axpby8(const BoxDev* boxes, const Blk* tab, P8<T> y,
+                                                   CP8<T> x, T a, T b) {
+  VM_PROLOGUE
+  (void)g;
+  for (int v = 0; v < 8; ++v) {
+    const T xv = x.p[0] ? x.p[v][o] : T(0);
+    y.p[v][o] = (a == T(0) ? T(0) : a * y.p[v][o]) + b * xv;
+  }
+}
+
+template <class T> void vm_forward(const VLaunch& L, const VProgram& P, T* base, long long stride) {
+  for (const VInstr& I : P.code)
+    hipLaunchKernelGGL(k_vm_fwd<T>, dim3(L.nblk), dim3(kBlock), 0, L.stream, L.boxes, L.tab, I, base,
+                       stride);
+}
+
+template <class T>
+void vm_backward(const VLaunch& L, const VProgram& P, const T* base, T* cbase, long long stride) {
+  for (auto it = P.code.rbegin(); it != P.code.rend(); ++it) {
+    if (it->op == V_FILL) continue;
+    hipLaunchKernelGGL(k_vm_bwd<T>, dim3(L.nblk), dim3(kBlock), 0, L.stream, L.boxes, L.tab, *it, base,
+                       cbase, stride);
+  }
+}
+
+template <class T> void vm_axpby8(const VLaunch& L, P8<T> y, CP8<T> x, double a, double b) {
+  hipLaunchKernelGGL(k_axpby8<T>, dim3(L.nblk), dim3(kBlock), 0, L.stream, L.boxes, L.tab, y, x, T(a),
+                     T(b));
+}
+
+template void vm_forward<float>(const VLaunch&, const VProgram&, float*, long long);
+template void vm_forward<double>(const VLaunch&, const VProgram&, double*, long long);
+template void vm_backward<float>(const VLaunch&, const VProgram&, const float*, float*, long long);
+template void vm_backward<double>(const VLaunch&, const VProgram&, const double*, double*, long long);
+template void vm_axpby8<float>(const VLaunch&, P8<float>, CP8<float>, double, double);
+template void vm_axpby8<double>(const VLaunch&, P8<double>, CP8<double>, double, double);
+
+}  // namespace smhd

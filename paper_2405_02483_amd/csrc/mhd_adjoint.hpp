@@ -1,0 +1,79 @@
+// Discrete adjoint of the right-hand side: the RHS recorded once, on the host,
+// as a straight-line program of whole-box operations (staggered stencils,
+// max/mean over three cells, pointwise arithmetic) in the order of the
+// equations of Sections 3-6 of the paper.  Running it forward keeps every
+// intermediate in its own slot; running it backward applies each
+// operation's transpose.  Periodic boxes only: on a periodic axis the
+// transpose of an interpolation is the interpolation of the opposite
+// stagger, and the transpose of a derivative is minus the derivative of the
+// opposite stagger.
+#pragma once
+
+#include <vector>
+
+#include "../../include/mhd.h"
+#include "mhd_common.hpp"
+
+namespace smhd {
+
+enum VOp : int {
+  V_STEN = 0,   // out = S(a): axis ax, family fam (0 interp, 1 deriv), form (0 dn, 1 up)
+  V_ADD,        // out = a + b
+  V_SUB,        // out = a - b
+  V_MUL,        // out = a * b
+  V_DIV,        // out = a / b
+  V_SCALE,      // out = (k * geo) * a
+  V_DIVC,       // out = a / k
+  V_SQRT,       // out = sqrt(a)
+  V_LOG,        // out = ln(a)
+  V_EXP,        // out = exp(a)
+  V_RELU,       // out = max(0, a)            (derivative 0 at a <= 0)
+  V_FLOOR,      // out = a > k ? a : k        (derivative 0 at a <= k)
+  V_NORM3,      // out = |(a, b, c)|          (derivative 0 at the origin)
+  V_MAX3,       // out = max over cells i-1, i, i+1 along ax (first maximal one)
+  V_MEAN3,      // out = (f[i-1] + f[i] + f[i+1]) / 3 along ax
+  V_FILL,       // out = k * geo (or k / h with G_HINV)
+  V_COUNT
+};
+
+// Per-box geometric factors multiplying the constant k of V_SCALE / V_FILL.
+enum VGeo : int { G_ONE = 0, G_DX, G_DY, G_DZ, G_H, G_HINV, G_MXY, G_MXZ, G_MYZ };
+
+// Axes of V_STEN / V_MAX3 / V_MEAN3.
+enum VAxis : int { VX = 0, VY = 1, VZ = 2 };
+
+struct VInstr {
+  int op, out, a, b, c;
+  int ax, fam, form, geo, pad;
+  double k;
+};
+
+// Slots 0..7 hold the state (rho, px, py, pz, e, bx, by, bz); out[v] is the
+// slot of the time derivative of variable v.
+struct VProgram {
+  std::vector<VInstr> code;
+  int nslots = 8;
+  int out[8];
+};
+
+VProgram build_rhs_program(const mhd_params& p);
+
+struct VLaunch {
+  const BoxDev* boxes;
+  const Blk* tab;
+  int nblk;
+  hipStream_t stream;
+};
+
+// Forward: slots base + s * stride for s < prog.nslots (slots 0..7 filled by
+// the caller).  Backward: cotangent slots cbase + s * stride, all zero except
+// the outputs' (seeded by the caller); afterwards cotangent slots 0..7 hold
+// (dF/df)^T of the seed.
+template <class T> void vm_forward(const VLaunch& L, const VProgram& prog, T* base, long long stride);
+template <class T>
+void vm_backward(const VLaunch& L, const VProgram& prog, const T* base, T* cbase, long long stride);
+
+// y[v] = a * y[v] + b * x[v] for the 8 fields (x may be null: y = a * y).
+template <class T> void vm_axpby8(const VLaunch& L, P8<T> y, CP8<T> x, double a, double b);
+
+}  // namespace smhd

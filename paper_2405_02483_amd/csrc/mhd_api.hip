@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "../../include/mhd.h"
+#include "mhd_adjoint.hpp"
 #include "mhd_kernels.hpp"
 #include "mhd_zmarch_api.hpp"
 
@@ -38,6 +39,7 @@ struct mhd_ctx {
   RedPartial* d_part = nullptr;    // nblk + 1 records (last = total)
   void* adj = nullptr;             // adjoint workspace (allocated on first use)
   size_t adj_bytes = 0;
+  VProgram* prog = nullptr;        // the right-hand side as a program (adjoint)
   // z-march stage kernels: work items, tile shape, Courant partials, dt
   ZItem* d_items = nullptr;
   int nitems = 0;
@@ -289,6 +291,7 @@ void mhd_destroy(mhd_ctx* c) {
   (void)hipFree(c->work);
   (void)hipFree(c->d_part);
   (void)hipFree(c->adj);
+  delete c->prog;
   (void)hipFree(c->d_items);
   (void)hipFree(c->d_cpart);
   (void)hipFree(c->d_dt);
@@ -494,6 +497,89 @@ static int do_step(mhd_ctx* c, void* const f[8], void* const t1[8], void* const 
   return check_launch(c, "mhd_step launch");
 }
 
+// Adjoint of one RK step (dt fixed).  With f_s the stage inputs, U_s the
+// 2N-storage derivative and F_s = F(f_s):
+//   U_s = alpha_s U_{s-1} + F_s,  f_{s+1} = f_s + beta_s dt U_s,
+// so, backwards from gbar = gbar_in (the cotangent of f_3):
+//   Ubar_s = alpha_{s+1} Ubar_{s+1} + beta_s dt gbar,
+//   gbar  += (dF/df at f_s)^T Ubar_s.
+// f_1 and f_2 come from the fused stage kernels; F's intermediates at each
+// f_s from the program's forward run, just before its transpose.
+template <class T>
+static int do_adjoint(mhd_ctx* c, void* const fn[8], double dt, void* const gin[8],
+                      void* const gout[8]) {
+  if (!c->prog) {
+    try {
+      c->prog = new VProgram(build_rhs_program(c->p));
+    } catch (...) {
+      return fail(c, MHD_ENOMEM, "adjoint program");
+    }
+  }
+  const VProgram& P = *c->prog;
+  const long long n = c->nelem;
+  const size_t narr = (size_t)2 * P.nslots + 24;
+  const size_t need = narr * (size_t)n * c->esize;
+  if (c->adj_bytes < need) {
+    (void)hipFree(c->adj);
+    c->adj = nullptr;
+    c->adj_bytes = 0;
+    hipError_t e = hipMalloc(&c->adj, need);
+    if (e != hipSuccess) return fail(c, MHD_ENOMEM, "adjoint workspace");
+    c->adj_bytes = need;
+  }
+  T* base = static_cast<T*>(c->adj);
+  T* cbase = base + (long long)P.nslots * n;
+  T* rest = cbase + (long long)P.nslots * n;
+  auto set8 = [&](int first) {
+    P8<T> q;
+    for (int v = 0; v < 8; ++v) q.p[v] = rest + (long long)(first + v) * n;
+    return q;
+  };
+  const P8<T> F1 = set8(0), F2 = set8(8), U = set8(16);
+  const P8<T> G = p8<T>(gout);
+  const size_t bytes = (size_t)n * c->esize;
+  const Launch L = make_launch(c);
+  // stage states f_1, f_2
+  const ZLaunch Z = make_zlaunch(c);
+  for (int s = 0; s < 2; ++s) {
+    ZStageArgs<T> a = zargs<T>(c);
+    a.f = s == 0 ? cp8<T>(fn) : cp8<T>(F1);
+    a.du = U;
+    a.du_mode = (s == 0 ? 0 : DU_READ) | DU_WRITE;
+    a.f_out = s == 0 ? F1 : F2;
+    a.alpha = T(kAlpha[s]);
+    a.beta = kBeta[s];
+    a.dt_host = dt;
+    launch_zstage<T>(Z, a);
+  }
+  L.at(PASS_ADJOINT);
+  VLaunch V{c->d_boxes, c->d_tab, c->nblk, c->stream};
+  hipError_t e = hipSuccess;
+  for (int v = 0; v < 8 && e == hipSuccess; ++v)
+    e = hipMemcpyAsync(G.p[v], gin[v], bytes, hipMemcpyDeviceToDevice, c->stream);
+  const P8<T> Ub = U;   // U is free again: it becomes Ubar
+  for (int s = 2; s >= 0 && e == hipSuccess; --s) {
+    vm_axpby8<T>(V, Ub, cp8<T>(G), s == 2 ? 0.0 : kAlpha[s + 1], kBeta[s] * dt);
+    const P8<T> fs = s == 0 ? p8<T>(fn) : (s == 1 ? F1 : F2);
+    for (int v = 0; v < 8 && e == hipSuccess; ++v)
+      e = hipMemcpyAsync(base + (long long)v * n, fs.p[v], bytes, hipMemcpyDeviceToDevice, c->stream);
+    if (e != hipSuccess) break;
+    vm_forward<T>(V, P, base, n);
+    e = hipMemsetAsync(cbase, 0, (size_t)P.nslots * bytes, c->stream);
+    for (int v = 0; v < 8 && e == hipSuccess; ++v)
+      e = hipMemcpyAsync(cbase + (long long)P.out[v] * n, Ub.p[v], bytes, hipMemcpyDeviceToDevice,
+                         c->stream);
+    if (e != hipSuccess) break;
+    vm_backward<T>(V, P, base, cbase, n);
+    CP8<T> cin;
+    for (int v = 0; v < 8; ++v) cin.p[v] = cbase + (long long)v * n;
+    vm_axpby8<T>(V, G, cin, 1.0, 1.0);
+  }
+  L.at(PASS_END);
+  if (e != hipSuccess) return fail(c, MHD_EHIP, hipGetErrorString(e));
+  return check_launch(c, "mhd_step_adjoint launch");
+}
+
 template <class T>
 static int do_reduce(mhd_ctx* c, void* const f[8], void* const dfdt[8], mhd_stats* out) {
   const Launch L = make_launch(c);
@@ -610,7 +696,8 @@ int mhd_step_adjoint(mhd_ctx* c, void* const f_n[8], double dt, void* const gin[
   for (int a = 0; a < 8; ++a)
     for (int b = 0; b < 8; ++b)
       if (gin[a] == gout[b] || f_n[a] == gout[b]) return fail(c, MHD_EINVAL, "gbar_out overlaps an input");
-  return fail(c, MHD_EUNSUPPORTED, "adjoint not available in this build");
+  return c->p.dtype == MHD_F32 ? do_adjoint<float>(c, f_n, dt, gin, gout)
+                               : do_adjoint<double>(c, f_n, dt, gin, gout);
 }
 
 int mhd_profile(mhd_ctx* c, int32_t enable) {

@@ -1,0 +1,307 @@
+"""The hand-written adjoint (mhd_step_adjoint, through the C ABI) and the
+checkpointed rollout, against the float64 oracle's discrete adjoint
+(torch.autograd over the oracle step) and against central finite
+differences of the library's own forward step.
+
+Tolerances: float64 adjoint vs oracle adjoint <= 1e-10 relative L2 per field
+(the two linearise at states that differ by rounding, and reverse sweeps
+accumulate in different orders); directional derivatives vs central
+differences <= 1e-4 relative (the target stated for the method), float64
+differences with eps = 1e-8 |x| / |v| (see the 128^3 test for why).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2405_02483_amd import inputs
+from tests.helpers import grid_params, rel_errors, to_cpu64
+
+pytestmark = pytest.mark.gpu
+
+TOL_ADJ64 = 1e-10
+
+
+def _ctx(box, prm, dtype, **over):
+    from paper_2405_02483_amd.lib import Context
+    p = dict(prm)
+    p.update(over)
+    return Context(box, p, dtype=dtype)
+
+
+def _randn_like(f, seed):
+    rng = np.random.default_rng(seed)
+    return [rng.standard_normal(a.shape) for a in f]
+
+
+def _ragged():
+    f, box, prm = inputs.turbulent(n=24, seed=2)
+    f = [a[:, :22, :20].copy() for a in f]
+    box = dict(box, nx=20, ny=22, nz=24, Lx=20 / 24, Ly=22 / 24)
+    return f, box, prm
+
+
+def _adjoint_vs_oracle(f, box, prm, seed=11, **over):
+    g, p = grid_params(box, prm, **over)
+    ft = to_cpu64(f)
+    dt = 0.5 * O.courant(ft, g, p)[0]
+    gbar = _randn_like(f, seed)
+    ctx = _ctx(box, prm, torch.float64, **over)
+    out = ctx.step_adjoint(ctx.upload([f]), dt, ctx.upload([gbar]))
+    got = ctx.box_view(out, 0)
+    want = O.step_vjp(ft, g, p, dt, to_cpu64(gbar))
+    ctx.close()
+    return rel_errors(got, want)
+
+
+@pytest.mark.parametrize("case", ["ragged", "ot16", "min6"])
+def test_step_adjoint_matches_oracle_f64(case):
+    if case == "ragged":
+        f, box, prm = _ragged()
+    elif case == "ot16":
+        f, box, prm = inputs.orszag_tang_3d(n=16, seed=1)
+    else:
+        f, box, prm = inputs.turbulent(n=6, seed=4, kmax=2.0)
+    errs = _adjoint_vs_oracle(f, box, prm)
+    print(case, ["%.2e" % e for e in errs])
+    assert max(errs) < TOL_ADJ64, errs
+
+
+TERM_SETS = {
+    "cont": O.T_CONT, "adv": O.T_ADV, "pres": O.T_PRES, "visc": O.T_VISC,
+    "lorentz": O.T_LORENTZ, "induct": O.T_INDUCT, "resist": O.T_RESIST,
+    "ediff": O.T_EDIFF, "grav": O.T_GRAV,
+}
+
+
+@pytest.mark.parametrize("term", sorted(TERM_SETS))
+def test_step_adjoint_each_term_f64(term):
+    f, box, prm = inputs.turbulent(n=12, seed=8, kmax=3.0)
+    errs = _adjoint_vs_oracle(f, box, prm, terms=TERM_SETS[term], gz=1.7)
+    assert max(errs) < TOL_ADJ64, (term, errs)
+
+
+@pytest.mark.parametrize("mode", ["eta_const", "nu_const"])
+def test_step_adjoint_constant_coefficients_f64(mode):
+    f, box, prm = inputs.turbulent(n=12, seed=9, kmax=3.0)
+    over = {"eta_const": 0.013} if mode == "eta_const" else {"nu_const": 0.011, "c1": -1 / 3}
+    errs = _adjoint_vs_oracle(f, box, prm, **over)
+    assert max(errs) < TOL_ADJ64, errs
+
+
+def test_step_adjoint_ensemble_f64():
+    from paper_2405_02483_amd.lib import Context
+    sizes = [6, 10, 8]
+    cases = [inputs.turbulent(n=n, seed=6000 + b, kmax=3.0) for b, n in enumerate(sizes)]
+    prm = cases[0][2]
+    ctx = Context([c[1] for c in cases], prm, dtype=torch.float64)
+    dt = 0.5 * min(O.courant(to_cpu64(c[0]), *grid_params(c[1], prm))[0] for c in cases)
+    gbars = [_randn_like(c[0], 70 + b) for b, c in enumerate(cases)]
+    out = ctx.step_adjoint(ctx.upload([c[0] for c in cases]), dt, ctx.upload(gbars))
+    for b, (f, box, _) in enumerate(cases):
+        g, p = grid_params(box, prm)
+        want = O.step_vjp(to_cpu64(f), g, p, dt, to_cpu64(gbars[b]))
+        errs = rel_errors(ctx.box_view(out, b), want)
+        assert max(errs) < TOL_ADJ64, (b, errs)
+    ctx.close()
+
+
+def test_step_adjoint_rejects_walls():
+    from paper_2405_02483_amd.lib import MhdError, MHD_EUNSUPPORTED
+    f, box, prm = inputs.stratified(12, 10, 24, seed=3)
+    ctx = _ctx(box, prm, torch.float64)
+    fd = ctx.upload([f])
+    with pytest.raises(MhdError) as ei:
+        ctx.step_adjoint(fd, 1e-3, ctx.zeros())
+    assert ei.value.code == MHD_EUNSUPPORTED
+    ctx.close()
+
+
+def _dot(a, b):
+    return sum(float(torch.dot(x.double().reshape(-1), y.double().reshape(-1))) for x, y in zip(a, b))
+
+
+def test_rollout_matches_oracle_and_finite_differences_f64():
+    from paper_2405_02483_amd.rollout import rollout
+    f, box, prm = _ragged()
+    g, p = grid_params(box, prm)
+    ft = to_cpu64(f)
+    dt = 0.5 * O.courant(ft, g, p)[0]
+    nsteps = 3
+    w = _randn_like(f, 21)
+    ctx = _ctx(box, prm, torch.float64)
+    x = [t.requires_grad_(True) for t in ctx.upload([f])]
+    y = rollout(ctx, x, dt, nsteps, ncheck=1)
+    wd = ctx.upload([w])
+    loss = sum((a * b).sum() for a, b in zip(y, wd))
+    grads = torch.autograd.grad(loss, x)
+    want = O.step_vjp(ft, g, p, dt, to_cpu64(w), nsteps=nsteps)
+    got = ctx.box_view([t.detach() for t in grads], 0)
+    errs = rel_errors(got, want)
+    assert max(errs) < TOL_ADJ64, errs
+    # central differences of the library's forward step along two directions
+    # (per-cell random directions move near-ties of the max over three cells,
+    # a kink error proportional to eps: hence the small eps)
+    x0 = [t.detach() for t in x]
+    for seed in (31, 32):
+        v = ctx.upload([_randn_like(f, seed)])
+        eps = 1e-8 * math.sqrt(_dot(x0, x0) / _dot(v, v))
+        yp = [t.clone() for t in x0]
+        ym = [t.clone() for t in x0]
+        for a, b, d in zip(yp, ym, v):
+            a.add_(eps * d)
+            b.sub_(eps * d)
+        ctx.step(yp, dt, nsteps)
+        ctx.step(ym, dt, nsteps)
+        fd = (_dot(wd, yp) - _dot(wd, ym)) / (2 * eps)
+        ad = _dot(grads, v)
+        assert abs(fd - ad) <= 1e-5 * abs(ad), (seed, fd, ad)
+    ctx.close()
+
+
+def test_rollout_gradients_do_not_depend_on_checkpoints():
+    from paper_2405_02483_amd.rollout import rollout
+    f, box, prm = inputs.turbulent(n=8, seed=5, kmax=2.0)
+    g, p = grid_params(box, prm)
+    dt = 0.5 * O.courant(to_cpu64(f), g, p)[0]
+    w = _randn_like(f, 41)
+    ctx = _ctx(box, prm, torch.float32)
+    wd = ctx.upload([w])
+    ref = None
+    for ncheck in (0, 1, 3, 10):
+        x = [t.requires_grad_(True) for t in ctx.upload([f])]
+        y = rollout(ctx, x, dt, 7, ncheck=ncheck)
+        gr = torch.autograd.grad(sum((a * b).sum() for a, b in zip(y, wd)), x)
+        if ref is None:
+            ref = [t.clone() for t in gr]
+        else:
+            for a, b in zip(gr, ref):
+                assert torch.equal(a, b), ncheck
+    ctx.close()
+
+
+def test_step_adjoint_f32_close_to_f64():
+    f, box, prm = _ragged()
+    g, p = grid_params(box, prm)
+    dt = 0.5 * O.courant(to_cpu64(f), g, p)[0]
+    gbar = _randn_like(f, 12)
+    res = []
+    for dtype in (torch.float32, torch.float64):
+        ctx = _ctx(box, prm, dtype)
+        out = ctx.step_adjoint(ctx.upload([f]), dt, ctx.upload([gbar]))
+        res.append([t.double().cpu() for t in ctx.box_view(out, 0)])
+        ctx.close()
+    errs = rel_errors(res[0], res[1])
+    print("f32 vs f64 adjoint", ["%.2e" % e for e in errs])
+    assert max(errs) < 1e-4, errs
+
+
+# ---------------------------------------------------------------------------
+# Gradient of the final kinetic + magnetic energy after 40 RK steps with
+# respect to the initial velocity and field (density and energy held), on the
+# 128^3 turbulent box (seed 4), checked along 16 random unit directions in
+# (u, B) against float64 central differences with eps = 1e-9 |(u, B)|.
+#
+# * The right-hand side is only piecewise smooth (max over three cells,
+#   max(0, -div u), the viscosity floor), so a central difference picks up an
+#   error proportional to eps from the near-ties it crosses: ~1e-4 at
+#   eps = 1e-6 |x|, ~1e-6..1e-5 at 1e-8..1e-10 |x| on this machine.
+# * A random unit direction changes the loss by only ~1e-11 of itself at
+#   such eps, so the loss is summed in extended precision (float64 pairwise
+#   sums alone leave ~1e-4 of noise in the difference).
+# * float64 adjoint: <= 1e-4 relative (the stated target; ~2e-5 measured).
+# * float32: the float32 trajectory itself moves the gradient by ~1e-4 in
+#   relative L2 (a float64 adjoint run along the float32 states differs from
+#   the float64 gradient by 9e-5; near-ties of the max over three cells that
+#   float32 rounding resolves differently; 8.8e-5 measured for the float32
+#   adjoint), so the float32 adjoint is held to 2e-4 in L2 against the
+#   float64 gradient and to 1e-3 per direction (a direction whose derivative
+#   is small by cancellation shows the same absolute error as a larger
+#   relative one; 9e-4 measured).
+
+def _energy(f, g, mu):
+    """Sum over faces of p_a^2 / (2 adn rho) dV + B_a^2 / (2 mu) dV (float64, CPU)."""
+    Op = g.ops()
+    rho, px, py, pz, e, bx, by, bz = f
+    dV = g.dx * g.dy * g.dz
+    ke = ((px * px / Op.xdn(rho)).sum() + (py * py / Op.ydn(rho)).sum()
+          + (pz * pz / Op.zdn(rho)).sum()) * 0.5 * dV
+    me = ((bx * bx).sum() + (by * by).sum() + (bz * bz).sum()) * dV / (2 * mu)
+    return ke + me
+
+
+def _energy_extended(f, g, mu):
+    """_energy with every sum taken in x87 extended precision."""
+    Op = g.ops()
+    rho, px, py, pz, e, bx, by, bz = f
+    dV = g.dx * g.dy * g.dz
+
+    def lsum(t):
+        return np.sum(t.numpy().astype(np.longdouble))
+    ke = (lsum(px * px / Op.xdn(rho)) + lsum(py * py / Op.ydn(rho))
+          + lsum(pz * pz / Op.zdn(rho))) * np.longdouble(0.5 * dV)
+    me = (lsum(bx * bx) + lsum(by * by) + lsum(bz * bz)) * np.longdouble(dV / (2 * mu))
+    return ke + me
+
+
+def test_energy_gradient_128_cubed_40_steps():
+    from paper_2405_02483_amd.rollout import rollout
+    n, nsteps, ndir = 128, 40, 16
+    f, box, prm = inputs.turbulent(n=n, seed=4)
+    g, p = grid_params(box, prm)
+    ft = to_cpu64(f)
+    dt = O.courant(ft, g, p)[0]
+    Op = g.ops()
+    rho0 = ft[0]
+    faces = (Op.xdn(rho0), Op.ydn(rho0), Op.zdn(rho0))
+    u0 = [ft[1 + a] / faces[a] for a in range(3)]
+    b0 = list(ft[5:8])
+
+    def state(u, b):
+        return [rho0] + [faces[a] * u[a] for a in range(3)] + [ft[4]] + list(b)
+
+    ctx64 = _ctx(box, prm, torch.float64)
+
+    def loss64(u, b):
+        y = ctx64.upload([state(u, b)])
+        ctx64.step(y, dt, nsteps)
+        return _energy_extended(tuple(t.cpu() for t in ctx64.box_view(y, 0)), g, p.mu)
+
+    grads = {}
+    for dtype in (torch.float32, torch.float64):
+        ctx = ctx64 if dtype == torch.float64 else _ctx(box, prm, dtype)
+        x = [t.requires_grad_(True) for t in ctx.upload([state(u0, b0)])]
+        y = rollout(ctx, x, dt, nsteps, ncheck=4)
+        yc = [t.detach().cpu().double().view(n, n, n).requires_grad_(True) for t in y]
+        gy = torch.autograd.grad(_energy(tuple(yc), g, p.mu), yc, allow_unused=True)
+        gy = [torch.zeros_like(a) if b is None else b for a, b in zip(yc, gy)]
+        gx = torch.autograd.grad(y, x, grad_outputs=ctx.upload([[t.numpy() for t in gy]]))
+        gx = [t.detach().cpu().double().view(n, n, n) for t in gx]
+        grads[dtype] = [faces[a] * gx[1 + a] for a in range(3)] + gx[5:8]
+        if ctx is not ctx64:
+            ctx.close()
+    rng = np.random.default_rng(4)
+    xnorm = math.sqrt(sum(float((t * t).sum()) for t in u0 + b0))
+    worst = {torch.float32: 0.0, torch.float64: 0.0}
+    for _ in range(ndir):
+        v = [torch.from_numpy(rng.standard_normal((n, n, n))) for _ in range(6)]
+        vn = math.sqrt(sum(float((t * t).sum()) for t in v))
+        v = [t / vn for t in v]
+        eps = 1e-9 * xnorm
+        lp = loss64([u0[a] + eps * v[a] for a in range(3)], [b0[a] + eps * v[3 + a] for a in range(3)])
+        lm = loss64([u0[a] - eps * v[a] for a in range(3)], [b0[a] - eps * v[3 + a] for a in range(3)])
+        fd = float((lp - lm) / np.longdouble(2 * eps))
+        for dtype, gr in grads.items():
+            ad = sum(float((a * b).sum()) for a, b in zip(gr, v))
+            worst[dtype] = max(worst[dtype], abs(ad - fd) / abs(fd))
+    ctx64.close()
+    g32, g64 = grads[torch.float32], grads[torch.float64]
+    l2 = math.sqrt(sum(float(((a - b) ** 2).sum()) for a, b in zip(g32, g64))
+                   / sum(float((b * b).sum()) for b in g64))
+    print("max relative error over %d directions: float32 %.2e, float64 %.2e; "
+          "float32 vs float64 gradient (L2) %.2e"
+          % (ndir, worst[torch.float32], worst[torch.float64], l2))
+    assert worst[torch.float64] <= 1e-4, worst
+    assert worst[torch.float32] <= 1e-3 and l2 <= 2e-4, (worst, l2)
