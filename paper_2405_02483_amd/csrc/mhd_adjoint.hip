@@ -275,6 +275,95 @@ VProgram build_rhs_program(const mhd_params& p) {
 }
 
 // ---------------------------------------------------------------------------
+// Storage plan.
+VPlan plan_program(const VProgram& P) {
+  const int n = (int)P.code.size(), S = P.nslots;
+  // values some transpose reads: never recycled
+  std::vector<char> keep(S, 0);
+  for (int s = 0; s < 8; ++s) keep[s] = 1;
+  for (const VInstr& I : P.code) {
+    switch (I.op) {
+      case V_MUL: keep[I.a] = keep[I.b] = 1; break;
+      case V_DIV: keep[I.b] = keep[I.out] = 1; break;
+      case V_SQRT: case V_EXP: keep[I.out] = 1; break;
+      case V_LOG: case V_RELU: case V_FLOOR: case V_MAX3: keep[I.a] = 1; break;
+      case V_NORM3: keep[I.a] = keep[I.b] = keep[I.c] = keep[I.out] = 1; break;
+      default: break;
+    }
+  }
+  std::vector<int> last(S, -1);
+  for (int q = 0; q < n; ++q)
+    for (int x : {P.code[q].a, P.code[q].b, P.code[q].c})
+      if (x >= 0) last[x] = q;
+  VPlan R;
+  std::vector<int> vphys(S, -1), freev;
+  for (int x = 0; x < 8; ++x) vphys[x] = x;
+  R.nval = 8;
+  R.steps.resize(n);
+  for (int q = 0; q < n; ++q) {
+    const VInstr& I = P.code[q];
+    int ph;
+    if (!freev.empty()) {
+      ph = freev.back();
+      freev.pop_back();
+    } else {
+      ph = R.nval++;
+    }
+    vphys[I.out] = ph;
+    VInstr F = I;
+    F.out = ph;
+    F.a = I.a >= 0 ? vphys[I.a] : -1;
+    F.b = I.b >= 0 ? vphys[I.b] : -1;
+    F.c = I.c >= 0 ? vphys[I.c] : -1;
+    R.steps[q].f = F;
+    int done[3] = {-1, -1, -1}, nd = 0;
+    for (int x : {I.a, I.b, I.c}) {
+      if (x < 8 || keep[x] || last[x] != q) continue;
+      bool dup = false;
+      for (int m = 0; m < nd; ++m) dup |= done[m] == x;
+      if (dup) continue;
+      done[nd++] = x;
+      freev.push_back(vphys[x]);
+    }
+    if (!keep[I.out] && last[I.out] < 0) freev.push_back(ph);
+  }
+  // cotangents, allocated in the reverse sweep
+  std::vector<int> cphys(S, -1), freec;
+  auto alloc = [&]() {
+    if (!freec.empty()) {
+      const int c = freec.back();
+      freec.pop_back();
+      return c;
+    }
+    return R.ncot++;
+  };
+  for (int v = 0; v < 8; ++v) {
+    R.vout[v] = vphys[P.out[v]];
+    R.cout[v] = cphys[P.out[v]] = alloc();
+  }
+  for (int q = n - 1; q >= 0; --q) {
+    const VInstr& I = P.code[q];
+    VStep& st = R.steps[q];
+    st.cout = cphys[I.out];
+    st.over = 0;
+    int* dst[3] = {&st.ca, &st.cb, &st.cc};
+    const int src[3] = {I.a, I.b, I.c};
+    for (int m = 0; m < 3; ++m) {
+      *dst[m] = -1;
+      if (src[m] < 0) continue;
+      if (cphys[src[m]] < 0) {
+        cphys[src[m]] = alloc();
+        st.over |= 1 << m;
+      }
+      *dst[m] = cphys[src[m]];
+    }
+    freec.push_back(st.cout);
+  }
+  for (int v = 0; v < 8; ++v) R.cin[v] = cphys[v];
+  return R;
+}
+
+// ---------------------------------------------------------------------------
 // Kernels: one thread per cell of the packed boxes (block table as for the
 // other whole-box passes).
 
@@ -373,54 +462,59 @@ __global__ __launch_bounds__(kBlock) void k_vm_fwd(const BoxDev* boxes, const Bl
 // Transposes.  Each thread owns the cotangents of its own cell, so the
 // gathers of the stencil, max and mean transposes need no atomics; the
 // pointwise rules update the input cotangents one after the other (an input
-// may appear twice, as in a * a).
+// may appear twice, as in a * a: its first contribution overwrites, the
+// second adds).
 template <class T>
-__global__ __launch_bounds__(kBlock) void k_vm_bwd(const BoxDev* boxes, const Blk* tab, VInstr I,
+__global__ __launch_bounds__(kBlock) void k_vm_bwd(const BoxDev* boxes, const Blk* tab, VStep S,
                                                    const T* base, T* cbase, long long stride) {
   VM_PROLOGUE
+  const VInstr& I = S.f;
   const T* a = I.a >= 0 ? base + I.a * stride : nullptr;
   const T* b = I.b >= 0 ? base + I.b * stride : nullptr;
   const T* c = I.c >= 0 ? base + I.c * stride : nullptr;
-  T* ca = I.a >= 0 ? cbase + I.a * stride : nullptr;
-  T* cb = I.b >= 0 ? cbase + I.b * stride : nullptr;
-  T* cc = I.c >= 0 ? cbase + I.c * stride : nullptr;
-  const T* yb = cbase + I.out * stride;
+  T* ca = S.ca >= 0 ? cbase + S.ca * stride : nullptr;
+  T* cb = S.cb >= 0 ? cbase + S.cb * stride : nullptr;
+  T* cc = S.cc >= 0 ? cbase + S.cc * stride : nullptr;
+  const T* yb = cbase + S.cout * stride;
+  auto put = [&](T* dst, int bit, T v) {
+    if (S.over & bit) dst[o] = v;
+    else dst[o] += v;
+  };
   switch (I.op) {
     case V_STEN: {
       // interpolation: S^T = the opposite stagger; derivative: minus it
       const T t = sten(yb, g, I.ax, I.fam, 1 - I.form, i, j, k);
-      ca[o] += I.fam ? -t : t;
+      put(ca, 1, I.fam ? -t : t);
       break;
     }
-    case V_ADD: ca[o] += yb[o]; cb[o] += yb[o]; break;
-    case V_SUB: ca[o] += yb[o]; cb[o] -= yb[o]; break;
+    case V_ADD: put(ca, 1, yb[o]); put(cb, 2, yb[o]); break;
+    case V_SUB: put(ca, 1, yb[o]); put(cb, 2, -yb[o]); break;
     case V_MUL: {
       const T y = yb[o], va = a[o], vb = b[o];
-      ca[o] += y * vb;
-      cb[o] += y * va;
+      put(ca, 1, y * vb);
+      put(cb, 2, y * va);
       break;
     }
     case V_DIV: {
       const T y = yb[o], vb = b[o], q = base[I.out * stride + o];
-      ca[o] += y / vb;
-      cb[o] -= y * q / vb;
+      put(ca, 1, y / vb);
+      put(cb, 2, -(y * q / vb));
       break;
     }
-    case V_SCALE: ca[o] += T(I.k * geo_of(bx_, I.geo)) * yb[o]; break;
-    case V_DIVC: ca[o] += yb[o] / T(I.k); break;
-    case V_SQRT: ca[o] += yb[o] / (T(2) * base[I.out * stride + o]); break;
-    case V_LOG: ca[o] += yb[o] / a[o]; break;
-    case V_EXP: ca[o] += yb[o] * base[I.out * stride + o]; break;
-    case V_RELU: if (a[o] > T(0)) ca[o] += yb[o]; break;
-    case V_FLOOR: if (a[o] > T(I.k)) ca[o] += yb[o]; break;
+    case V_SCALE: put(ca, 1, T(I.k * geo_of(bx_, I.geo)) * yb[o]); break;
+    case V_DIVC: put(ca, 1, yb[o] / T(I.k)); break;
+    case V_SQRT: put(ca, 1, yb[o] / (T(2) * base[I.out * stride + o])); break;
+    case V_LOG: put(ca, 1, yb[o] / a[o]); break;
+    case V_EXP: put(ca, 1, yb[o] * base[I.out * stride + o]); break;
+    case V_RELU: put(ca, 1, a[o] > T(0) ? yb[o] : T(0)); break;
+    case V_FLOOR: put(ca, 1, a[o] > T(I.k) ? yb[o] : T(0)); break;
     case V_NORM3: {
-      const T n = base[I.out * stride + o];
-      if (n > T(0)) {
-        const T y = yb[o] / n, va = a[o], vb = b[o], vc = c[o];
-        ca[o] += y * va;
-        cb[o] += y * vb;
-        cc[o] += y * vc;
-      }
+      const T nrm = base[I.out * stride + o];
+      const T y = nrm > T(0) ? yb[o] / nrm : T(0);
+      const T va = a[o], vb = b[o], vc = c[o];
+      put(ca, 1, y * va);
+      put(cb, 2, y * vb);
+      put(cc, 4, y * vc);
       break;
     }
     case V_MAX3: {
@@ -428,15 +522,15 @@ __global__ __launch_bounds__(kBlock) void k_vm_bwd(const BoxDev* boxes, const Bl
       auto v = [&](int m) { return along(a, g, I.ax, i, j, k, m); };
       auto w = [&](int m) { return along(yb, g, I.ax, i, j, k, m); };
       const T vm2 = v(-2), vm1 = v(-1), v0 = a[o], vp1 = v(1), vp2 = v(2);
-      T s = T(0);
-      if (first_max(vm2, vm1, v0) == 2) s += w(-1);
-      if (first_max(vm1, v0, vp1) == 1) s += yb[o];
-      if (first_max(v0, vp1, vp2) == 0) s += w(1);
-      ca[o] += s;
+      T sum = T(0);
+      if (first_max(vm2, vm1, v0) == 2) sum += w(-1);
+      if (first_max(vm1, v0, vp1) == 1) sum += yb[o];
+      if (first_max(v0, vp1, vp2) == 0) sum += w(1);
+      put(ca, 1, sum);
       break;
     }
     case V_MEAN3:
-      ca[o] += (along(yb, g, I.ax, i, j, k, -1) + yb[o] + along(yb, g, I.ax, i, j, k, 1)) / T(3);
+      put(ca, 1, (along(yb, g, I.ax, i, j, k, -1) + yb[o] + along(yb, g, I.ax, i, j, k, 1)) / T(3));
       break;
     default: break;
   }
@@ -453,16 +547,16 @@ __global__ __launch_bounds__(kBlock) void k_axpby8(const BoxDev* boxes, const Bl
   }
 }
 
-template <class T> void vm_forward(const VLaunch& L, const VProgram& P, T* base, long long stride) {
-  for (const VInstr& I : P.code)
-    hipLaunchKernelGGL(k_vm_fwd<T>, dim3(L.nblk), dim3(kBlock), 0, L.stream, L.boxes, L.tab, I, base,
+template <class T> void vm_forward(const VLaunch& L, const VPlan& P, T* base, long long stride) {
+  for (const VStep& S : P.steps)
+    hipLaunchKernelGGL(k_vm_fwd<T>, dim3(L.nblk), dim3(kBlock), 0, L.stream, L.boxes, L.tab, S.f, base,
                        stride);
 }
 
 template <class T>
-void vm_backward(const VLaunch& L, const VProgram& P, const T* base, T* cbase, long long stride) {
-  for (auto it = P.code.rbegin(); it != P.code.rend(); ++it) {
-    if (it->op == V_FILL) continue;
+void vm_backward(const VLaunch& L, const VPlan& P, const T* base, T* cbase, long long stride) {
+  for (auto it = P.steps.rbegin(); it != P.steps.rend(); ++it) {
+    if (it->f.op == V_FILL) continue;
     hipLaunchKernelGGL(k_vm_bwd<T>, dim3(L.nblk), dim3(kBlock), 0, L.stream, L.boxes, L.tab, *it, base,
                        cbase, stride);
   }
@@ -473,10 +567,10 @@ template <class T> void vm_axpby8(const VLaunch& L, P8<T> y, CP8<T> x, double a,
                      T(b));
 }
 
-template void vm_forward<float>(const VLaunch&, const VProgram&, float*, long long);
-template void vm_forward<double>(const VLaunch&, const VProgram&, double*, long long);
-template void vm_backward<float>(const VLaunch&, const VProgram&, const float*, float*, long long);
-template void vm_backward<double>(const VLaunch&, const VProgram&, const double*, double*, long long);
+template void vm_forward<float>(const VLaunch&, const VPlan&, float*, long long);
+template void vm_forward<double>(const VLaunch&, const VPlan&, double*, long long);
+template void vm_backward<float>(const VLaunch&, const VPlan&, const float*, float*, long long);
+template void vm_backward<double>(const VLaunch&, const VPlan&, const double*, double*, long long);
 template void vm_axpby8<float>(const VLaunch&, P8<float>, CP8<float>, double, double);
 template void vm_axpby8<double>(const VLaunch&, P8<double>, CP8<double>, double, double);
 

@@ -58,6 +58,27 @@ struct VProgram {
 
 VProgram build_rhs_program(const mhd_params& p);
 
+// A program with storage assigned.  Forward values that no transpose reads
+// share slots once their last reader has run; cotangents are allocated over
+// their live range in the reverse sweep, and the first contribution to a
+// cotangent overwrites it (no clearing pass).
+struct VStep {
+  VInstr f;                  // forward instruction on value slots
+  int cout, ca, cb, cc;      // cotangent slots of out, a, b, c (-1: none)
+  int over;                  // bit 0/1/2: the contribution to ca/cb/cc overwrites
+};
+
+struct VPlan {
+  std::vector<VStep> steps;
+  int nval = 0;              // value slots (0..7: the state)
+  int ncot = 0;              // cotangent slots
+  int vout[8];               // value slot of each output (unused by the sweeps)
+  int cout[8];               // cotangent slot seeded with each output's cotangent
+  int cin[8];                // cotangent slot of each input (-1: the input is unused)
+};
+
+VPlan plan_program(const VProgram& prog);
+
 struct VLaunch {
   const BoxDev* boxes;
   const Blk* tab;
@@ -65,13 +86,13 @@ struct VLaunch {
   hipStream_t stream;
 };
 
-// Forward: slots base + s * stride for s < prog.nslots (slots 0..7 filled by
-// the caller).  Backward: cotangent slots cbase + s * stride, all zero except
-// the outputs' (seeded by the caller); afterwards cotangent slots 0..7 hold
-// (dF/df)^T of the seed.
-template <class T> void vm_forward(const VLaunch& L, const VProgram& prog, T* base, long long stride);
+// Forward: value slots base + s * stride (slots 0..7 filled by the caller).
+// Backward: cotangent slots cbase + s * stride, with the outputs' slots
+// (plan.cout) seeded by the caller; afterwards slot plan.cin[v] holds
+// (dF/df_v)^T of the seed.
+template <class T> void vm_forward(const VLaunch& L, const VPlan& plan, T* base, long long stride);
 template <class T>
-void vm_backward(const VLaunch& L, const VProgram& prog, const T* base, T* cbase, long long stride);
+void vm_backward(const VLaunch& L, const VPlan& plan, const T* base, T* cbase, long long stride);
 
 // y[v] = a * y[v] + b * x[v] for the 8 fields (x may be null: y = a * y).
 template <class T> void vm_axpby8(const VLaunch& L, P8<T> y, CP8<T> x, double a, double b);

@@ -39,7 +39,7 @@ struct mhd_ctx {
   RedPartial* d_part = nullptr;    // nblk + 1 records (last = total)
   void* adj = nullptr;             // adjoint workspace (allocated on first use)
   size_t adj_bytes = 0;
-  VProgram* prog = nullptr;        // the right-hand side as a program (adjoint)
+  VPlan* prog = nullptr;           // the right-hand side as a program (adjoint)
   // z-march stage kernels: work items, tile shape, Courant partials, dt
   ZItem* d_items = nullptr;
   int nitems = 0;
@@ -510,14 +510,14 @@ static int do_adjoint(mhd_ctx* c, void* const fn[8], double dt, void* const gin[
                       void* const gout[8]) {
   if (!c->prog) {
     try {
-      c->prog = new VProgram(build_rhs_program(c->p));
+      c->prog = new VPlan(plan_program(build_rhs_program(c->p)));
     } catch (...) {
       return fail(c, MHD_ENOMEM, "adjoint program");
     }
   }
-  const VProgram& P = *c->prog;
+  const VPlan& P = *c->prog;
   const long long n = c->nelem;
-  const size_t narr = (size_t)2 * P.nslots + 24;
+  const size_t narr = (size_t)P.nval + P.ncot + 25;
   const size_t need = narr * (size_t)n * c->esize;
   if (c->adj_bytes < need) {
     (void)hipFree(c->adj);
@@ -528,8 +528,8 @@ static int do_adjoint(mhd_ctx* c, void* const fn[8], double dt, void* const gin[
     c->adj_bytes = need;
   }
   T* base = static_cast<T*>(c->adj);
-  T* cbase = base + (long long)P.nslots * n;
-  T* rest = cbase + (long long)P.nslots * n;
+  T* cbase = base + (long long)P.nval * n;
+  T* rest = cbase + (long long)P.ncot * n;
   auto set8 = [&](int first) {
     P8<T> q;
     for (int v = 0; v < 8; ++v) q.p[v] = rest + (long long)(first + v) * n;
@@ -538,6 +538,7 @@ static int do_adjoint(mhd_ctx* c, void* const fn[8], double dt, void* const gin[
   const P8<T> F1 = set8(0), F2 = set8(8), U = set8(16);
   const P8<T> G = p8<T>(gout);
   const size_t bytes = (size_t)n * c->esize;
+  T* zeros = rest + 24LL * n;   // the cotangent of an input F does not read
   const Launch L = make_launch(c);
   // stage states f_1, f_2
   const ZLaunch Z = make_zlaunch(c);
@@ -554,7 +555,7 @@ static int do_adjoint(mhd_ctx* c, void* const fn[8], double dt, void* const gin[
   }
   L.at(PASS_ADJOINT);
   VLaunch V{c->d_boxes, c->d_tab, c->nblk, c->stream};
-  hipError_t e = hipSuccess;
+  hipError_t e = hipMemsetAsync(zeros, 0, bytes, c->stream);
   for (int v = 0; v < 8 && e == hipSuccess; ++v)
     e = hipMemcpyAsync(G.p[v], gin[v], bytes, hipMemcpyDeviceToDevice, c->stream);
   const P8<T> Ub = U;   // U is free again: it becomes Ubar
@@ -565,15 +566,18 @@ static int do_adjoint(mhd_ctx* c, void* const fn[8], double dt, void* const gin[
       e = hipMemcpyAsync(base + (long long)v * n, fs.p[v], bytes, hipMemcpyDeviceToDevice, c->stream);
     if (e != hipSuccess) break;
     vm_forward<T>(V, P, base, n);
-    e = hipMemsetAsync(cbase, 0, (size_t)P.nslots * bytes, c->stream);
     for (int v = 0; v < 8 && e == hipSuccess; ++v)
-      e = hipMemcpyAsync(cbase + (long long)P.out[v] * n, Ub.p[v], bytes, hipMemcpyDeviceToDevice,
+      e = hipMemcpyAsync(cbase + (long long)P.cout[v] * n, Ub.p[v], bytes, hipMemcpyDeviceToDevice,
                          c->stream);
     if (e != hipSuccess) break;
     vm_backward<T>(V, P, base, cbase, n);
     CP8<T> cin;
-    for (int v = 0; v < 8; ++v) cin.p[v] = cbase + (long long)v * n;
-    vm_axpby8<T>(V, G, cin, 1.0, 1.0);
+    bool any = false;
+    for (int v = 0; v < 8; ++v) {
+      cin.p[v] = P.cin[v] >= 0 ? cbase + (long long)P.cin[v] * n : zeros;
+      any |= P.cin[v] >= 0;
+    }
+    if (any) vm_axpby8<T>(V, G, cin, 1.0, 1.0);
   }
   L.at(PASS_END);
   if (e != hipSuccess) return fail(c, MHD_EHIP, hipGetErrorString(e));
