@@ -118,6 +118,83 @@ def run_gpu(size, dtype, steps, warmup, workload="stratified", tile=None):
                 dt_last=dt_last, mass=s_end["mass"], ncell=ncell)
 
 
+def run_adjoint(n=128, nsteps=40, ncheck=4, dtype_name="f32"):
+    """Gradient of a linear functional of the state after nsteps RK steps on
+    the n^3 turbulent box (seed 4): forward time vs checkpointed backward."""
+    import torch
+    from paper_2405_02483_amd import inputs
+    from paper_2405_02483_amd.lib import Context
+    from paper_2405_02483_amd.rollout import reversal_cost, rollout
+    dtype = torch.float32 if dtype_name == "f32" else torch.float64
+    f, box, prm = inputs.turbulent(n=n, seed=4)
+    ctx = Context(box, prm, dtype=dtype)
+    x0 = ctx.upload([f])
+    dt = ctx.reductions(x0)["dt"]
+    w = [torch.ones_like(t) for t in x0]
+    x = [t.clone().requires_grad_(True) for t in x0]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    y = rollout(ctx, x, dt, nsteps, ncheck=ncheck)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    loss = sum((a * b).sum() for a, b in zip(y, w))
+    torch.autograd.grad(loss, x)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    ctx.close()
+    torch.cuda.empty_cache()
+    return {"workload": "turbulent_%d, %d RK steps, %s, %d checkpoints" % (n, nsteps, dtype_name, ncheck),
+            "forward_ms": (t1 - t0) * 1e3, "backward_ms": (t2 - t1) * 1e3,
+            "adjoint_over_forward": (t2 - t1) / (t1 - t0),
+            "recomputed_steps": reversal_cost(nsteps, ncheck)}
+
+
+def run_ensemble(nbox=96, nsteps=20, ncheck=4):
+    """The 96-box ensemble (24 each of 48^3, 64^3, 80^3, 96^3, turbulent
+    init, seeds 5000+b), float32, launch autotuned, nsteps steps forward, then
+    the checkpointed adjoint of the same rollout."""
+    import torch
+    from paper_2405_02483_amd import inputs
+    from paper_2405_02483_amd.lib import Context
+    from paper_2405_02483_amd.rollout import rollout
+    log("generating the %d-box ensemble" % nbox)
+    cases, prm = inputs.ensemble(nbox=nbox)
+    ctx = Context([c[1] for c in cases], prm, dtype=torch.float32)
+    x0 = ctx.upload([c[0] for c in cases])
+    ncell = sum(c[1]["nx"] * c[1]["ny"] * c[1]["nz"] for c in cases)
+    del cases
+    tune = ctx.autotune(x0, reps=2)
+    dt = ctx.reductions(x0)["dt"]
+    work = (ctx.empty(), ctx.empty(), ctx.empty())
+    xf = [t.clone() for t in x0]
+    ctx.step(xf, dt, 1, work=work)                     # warm-up
+    xf = [t.clone() for t in x0]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.step(xf, dt, nsteps, work=work)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    del xf, work
+    x = [t.clone().requires_grad_(True) for t in x0]
+    y = rollout(ctx, x, dt, nsteps, ncheck=ncheck)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    loss = sum((a * a).sum() for a in y)
+    torch.autograd.grad(loss, x)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    tile, mode = ctx.get_launch()
+    ctx.close()
+    torch.cuda.empty_cache()
+    return {"workload": "%d boxes (48/64/80/96)^3 turbulent, float32, %d RK steps" % (nbox, nsteps),
+            "cells": ncell, "value": ncell * nsteps / (t1 - t0), "unit": "cell-updates/s",
+            "forward_ms": (t1 - t0) * 1e3, "rollout_forward_ms": (t2 - t1) * 1e3,
+            "backward_ms": (t3 - t2) * 1e3, "adjoint_over_forward": (t3 - t2) / (t1 - t0),
+            "launch": {"tile": tile, "persistent": mode},
+            "autotune_ms_per_rhs": {"%s/%s" % (k[0], "persistent" if k[1] else "grid"): round(v, 4)
+                                    for k, v in tune.items()}}
+
+
 def cpu_baseline(n=128):
     import torch
     import oracle as O
@@ -147,6 +224,7 @@ def main():
     ap.add_argument("--cpu-size", type=int, default=128)
     ap.add_argument("--workload", default="stratified", choices=("stratified", "turbulent"))
     ap.add_argument("--tile", default=None, help="stage kernel tile shape, e.g. 32x8")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint and ensemble legs")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -199,6 +277,11 @@ def main():
                        "frac": (2 * stage_bytes / (r64["stage_ms"] * 1e-3) / 1e9) / HBM_PEAK_GBS,
                        "passes_ms": {k: round(v[0], 4) for k, v in r64["passes"].items()}}
         out["fp32_over_fp64"] = r32["value"] / r64["value"]
+    if not a.no_adjoint:
+        log("adjoint leg")
+        out["adjoint"] = run_adjoint()
+        log("ensemble leg")
+        out["ensemble"] = run_ensemble()
     if not a.no_cpu_baseline:
         log("timing the CPU oracle sample")
         out["cpu_baseline"] = cpu_baseline(a.cpu_size)

@@ -195,6 +195,25 @@ int mhd_last_dt(mhd_ctx* ctx, double* dt);
  * MHD_EINVAL.                                                               */
 int mhd_set_tile(mhd_ctx* ctx, int32_t tile);
 
+/* Tile shape (as mhd_set_tile) and launch mode of the stage kernels.
+ * persistent = 0: one workgroup per work item (box, column tile, z range).
+ * persistent = 1: about one resident wave of workgroups, each taking work
+ * items from a queue per XCD and from the other XCDs' queues once its own is
+ * empty (load balance for ensembles of uneven boxes).  Results are the same
+ * bit for bit in every tile shape and mode.  MHD_EINVAL on other values.   */
+int mhd_set_launch(mhd_ctx* ctx, int32_t tile, int32_t persistent);
+
+/* Current tile shape and launch mode.                                      */
+int mhd_get_launch(const mhd_ctx* ctx, int32_t* tile, int32_t* persistent);
+
+/* Autotuner: times reps evaluations of mhd_rhs(f, dfdt) (after one warm-up)
+ * in every tile shape and launch mode, keeps the fastest and, if ms is not
+ * NULL, writes the milliseconds per evaluation to ms[2 * tile + persistent]
+ * (8 entries).  dfdt is overwritten; with walls the ghost planes of f are
+ * filled.  Waits for the stream.                                            */
+int mhd_autotune(mhd_ctx* ctx, void* const f[8], void* const dfdt[8], int32_t reps,
+                 double* ms);
+
 /* Timing of the library's own kernel passes, for performance measurement.
  * Pass ids (index into the arrays of mhd_profile_read):                    */
 enum {

@@ -45,6 +45,9 @@ struct mhd_ctx {
   int nitems = 0;
   int tile = ZTILE_32x8;
   CPart* d_cpart = nullptr;
+  int* d_queue = nullptr;          // item queues of the persistent launch mode
+  int persistent = 0;
+  int ncu = 1;
   double* d_dt = nullptr;
   void* d_ztab = nullptr;          // z-coefficient tables of wall boxes (ctx dtype)
   // timing of kernel passes (mhd_profile)
@@ -151,6 +154,9 @@ static ZLaunch make_zlaunch(const mhd_ctx* c) {
   L.items = c->d_items;
   L.nitems = c->nitems;
   L.tile = c->tile;
+  L.queue = c->d_queue;
+  L.persistent = c->persistent;
+  L.ncu = c->ncu;
   L.stream = c->stream;
   L.mark = c->prof ? prof_mark : nullptr;
   L.mark_ctx = const_cast<mhd_ctx*>(c);
@@ -295,6 +301,7 @@ void mhd_destroy(mhd_ctx* c) {
   (void)hipFree(c->d_items);
   (void)hipFree(c->d_cpart);
   (void)hipFree(c->d_dt);
+  (void)hipFree(c->d_queue);
   (void)hipFree(c->d_ztab);
   delete c;
 }
@@ -321,6 +328,9 @@ int mhd_init(const mhd_params* p, void* hip_stream, mhd_ctx** out) {
   c->esize = p->dtype == MHD_F32 ? sizeof(float) : sizeof(double);
   c->stream = static_cast<hipStream_t>(hip_stream);
   (void)hipGetDevice(&c->device);
+  if (hipDeviceGetAttribute(&c->ncu, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess ||
+      c->ncu < 1)
+    c->ncu = 1;
   long long off = 0;
   for (int b = 0; b < p->nbox; ++b) {
     const mhd_box& x = p->boxes[b];
@@ -409,7 +419,8 @@ int mhd_init(const mhd_params* p, void* hip_stream, mhd_ctx** out) {
       return MHD_EHIP;
     }
   }
-  if ((e = hipMalloc(&c->d_dt, sizeof(double))) != hipSuccess) {
+  if ((e = hipMalloc(&c->d_dt, sizeof(double))) != hipSuccess ||
+      (e = hipMalloc(&c->d_queue, sizeof(int) * kQueueInts)) != hipSuccess) {
     g_init_err = std::string("device allocation failed: ") + hipGetErrorString(e);
     mhd_destroy(c);
     return MHD_ENOMEM;
@@ -740,6 +751,66 @@ int mhd_set_tile(mhd_ctx* c, int32_t tile) {
   if (tile < 0 || tile >= ZTILE_COUNT) return fail(c, MHD_EINVAL, "unknown tile shape");
   if (!ztile_ok(tile, c->esize)) return fail(c, MHD_EUNSUPPORTED, "tile shape not built for this dtype");
   return set_tile(c, tile);
+}
+
+int mhd_set_launch(mhd_ctx* c, int32_t tile, int32_t persistent) {
+  if (!c) return fail(nullptr, MHD_EINVAL, "ctx is NULL");
+  if (tile < 0 || tile >= ZTILE_COUNT) return fail(c, MHD_EINVAL, "unknown tile shape");
+  if (persistent != 0 && persistent != 1) return fail(c, MHD_EINVAL, "persistent must be 0 or 1");
+  int rc = set_tile(c, tile);
+  if (rc == MHD_OK) c->persistent = persistent;
+  return rc;
+}
+
+int mhd_get_launch(const mhd_ctx* c, int32_t* tile, int32_t* persistent) {
+  if (!c || !tile || !persistent) return MHD_EINVAL;
+  *tile = c->tile;
+  *persistent = c->persistent;
+  return MHD_OK;
+}
+
+int mhd_autotune(mhd_ctx* c, void* const f[8], void* const dfdt[8], int32_t reps, double* ms) {
+  if (!c) return fail(nullptr, MHD_EINVAL, "ctx is NULL");
+  int rc;
+  if ((rc = check8(c, f, "f")) || (rc = check8(c, dfdt, "dfdt"))) return rc;
+  if (reps < 1) return fail(c, MHD_EINVAL, "reps < 1");
+  for (int a = 0; a < 8; ++a)
+    for (int b = 0; b < 8; ++b)
+      if (f[a] == dfdt[b]) return fail(c, MHD_EINVAL, "f and dfdt overlap");
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return fail(c, MHD_EHIP, "event");
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(c, MHD_EHIP, "event");
+  }
+  const bool prof = c->prof;
+  c->prof = false;
+  double best = -1.0;
+  int bt = c->tile, bp = c->persistent;
+  for (int t = 0; t < ZTILE_COUNT && rc == MHD_OK; ++t)
+    for (int m = 0; m < 2 && rc == MHD_OK; ++m) {
+      if ((rc = mhd_set_launch(c, t, m)) != MHD_OK) break;
+      rc = mhd_rhs(c, f, dfdt);   // warm-up (and, with walls, the ghost fill)
+      (void)hipEventRecord(e0, c->stream);
+      for (int r = 0; r < reps && rc == MHD_OK; ++r) rc = mhd_rhs(c, f, dfdt);
+      (void)hipEventRecord(e1, c->stream);
+      float el = 0.0f;
+      if (rc == MHD_OK && (hipEventSynchronize(e1) != hipSuccess ||
+                           hipEventElapsedTime(&el, e0, e1) != hipSuccess))
+        rc = fail(c, MHD_EHIP, "autotune timing");
+      const double per = (double)el / reps;
+      if (ms) ms[t * 2 + m] = per;
+      if (rc == MHD_OK && (best < 0.0 || per < best)) {
+        best = per;
+        bt = t;
+        bp = m;
+      }
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  c->prof = prof;
+  if (rc != MHD_OK) return rc;
+  return mhd_set_launch(c, bt, bp);
 }
 
 }  // extern "C"

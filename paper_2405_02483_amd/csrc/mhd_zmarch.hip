@@ -14,14 +14,24 @@
 //       and the fused RK stage update (eqs. ddt, tupdate)
 // Stage-1 launches of A1 / A2 also leave per-item maxima for the Courant
 // time step (eq. courantcond), which k_dt folds into a device-resident dt.
+#include <algorithm>
+#include <map>
+#include <mutex>
+
 #include "mhd_zmarch.hpp"
 #include "mhd_zmarch_api.hpp"
 
 namespace smhd {
 
-#define ZPROLOGUE                                                              \
-  const int item_ = xcd_item(nitems);                                          \
-  if (item_ >= nitems) return;                                                 \
+// Item loop of the stage kernels.  Grid mode (PERS false): one item
+// per workgroup, blockIdx mapped XCD-aware.  Persistent mode: a grid of about
+// one resident wave of workgroups; each pulls items from its XCD's queue
+// (queue[x] counts the items of range x taken) and, once that is empty,
+// from the other XCDs' ranges.  Results do not depend on the mode.
+#define ZLOOP_BEGIN                                                            \
+  __shared__ int snext_;                                                       \
+  for (int item_ = zfirst<PERS>(nitems, queue, &snext_); item_ < nitems;      \
+       item_ = znext<PERS>(nitems, queue, &snext_)) {                         \
   const ZItem it = items[item_];                                               \
   const BoxDev b = boxes[it.box];                                              \
   const Geo<T> g(b);                                                           \
@@ -38,6 +48,8 @@ namespace smhd {
   auto interior = [&](int r_) { return !wall || (r_ >= b.g0 && r_ < b.g1); };       \
   const T* __restrict__ zt = wall ? ztab + b.zoff : nullptr;                         \
   (void)zt;
+
+#define ZLOOP_END }
 
 // Block maximum of a double (all threads call; result valid in thread 0).
 template <int NT>
@@ -56,9 +68,10 @@ __device__ __forceinline__ double block_max(double v, double* sh) {
 // Front plane r: x/y stencils of plane r go through LDS, their results wait
 // in short per-thread queues; u_z (plane r-2) and the z stencils (plane r-5)
 // come from register windows.
-template <class T, int TX, int TY>
+template <class T, int TX, int TY, bool PERS>
 __global__ __launch_bounds__(TX * TY) void zA1(const BoxDev* __restrict__ boxes,
                                                const ZItem* __restrict__ items, int nitems, const T* __restrict__ ztab,
+                                               int* __restrict__ queue,
                                                CP8<T> f, Phys<T> ph, ZWork<T> ws,
                                                CPart* __restrict__ cpart) {
   T* __restrict__ nus_out = ws.arr(WS_NUS);
@@ -69,7 +82,7 @@ __global__ __launch_bounds__(TX * TY) void zA1(const BoxDev* __restrict__ boxes,
   __shared__ T sR[PR::N];
   __shared__ T sPX[PP::N], sPY[PP::N], sBX[PP::N], sBY[PP::N];
   __shared__ double sred[TX * TY];
-  ZPROLOGUE
+  ZLOOP_BEGIN
   PlaneIdx<TX, TY, 5> i5;
   PlaneIdx<TX, TY, 3> i3;
   i5.init(b, it.x0, it.y0);
@@ -165,15 +178,17 @@ __global__ __launch_bounds__(TX * TY) void zA1(const BoxDev* __restrict__ boxes,
     const double m = block_max<TX * TY>(cmax, sred);
     if (threadIdx.x == 0) cpart[item_].cmax = m;
   }
+  ZLOOP_END
 }
 
 // ---------------------------------------------------------------------------
 // A2: m = max over the 3x3x3 neighbourhood (x, y through LDS; z over a ring
 // of three x/y-maximum planes), then three-cell means along x, y (LDS) and
 // z (register window), floor 1e-30, and ln.
-template <class T, int TX, int TY>
+template <class T, int TX, int TY, bool PERS>
 __global__ __launch_bounds__(TX * TY) void zA2(const BoxDev* __restrict__ boxes,
                                                const ZItem* __restrict__ items, int nitems, const T* __restrict__ ztab,
+                                               int* __restrict__ queue,
                                                ZWork<T> ws, CPart* __restrict__ cpart) {
   const T* __restrict__ nus = ws.arr(WS_NUS);
   T* __restrict__ lnt_out = ws.arr(WS_LNT);
@@ -184,7 +199,7 @@ __global__ __launch_bounds__(TX * TY) void zA2(const BoxDev* __restrict__ boxes,
   __shared__ T sMX[3][PM::N];
   __shared__ T sM[PM::N];
   __shared__ double sred[NT];
-  ZPROLOGUE
+  ZLOOP_BEGIN
   PlaneIdx<TX, TY, 2> i2;
   i2.init(b, it.x0, it.y0);
   T wS[3] = {};
@@ -247,6 +262,7 @@ __global__ __launch_bounds__(TX * TY) void zA2(const BoxDev* __restrict__ boxes,
     const double m = block_max<NT>(numax, sred);
     if (threadIdx.x == 0) cpart[item_].numax = m;
   }
+  ZLOOP_END
 }
 
 // ---------------------------------------------------------------------------
@@ -256,9 +272,10 @@ __global__ __launch_bounds__(TX * TY) void zA2(const BoxDev* __restrict__ boxes,
 //   y-edge (i-1/2, j, k-1/2): Gxz, Gzx, Ey, Lxy, Lzy, Qy
 //   x-edge (i, j-1/2, k-1/2): Gyz, Gzy, Ex, Lyx, Lzx, Qx
 //   Hz (z-face), Gzz, Czz (centre)
-template <class T, int TX, int TY>
+template <class T, int TX, int TY, bool PERS>
 __global__ __launch_bounds__(TX * TY) void zQ(const BoxDev* __restrict__ boxes,
                                               const ZItem* __restrict__ items, int nitems, const T* __restrict__ ztab,
+                                               int* __restrict__ queue,
                                               CP8<T> f, Phys<T> ph, ZWork<T> ws) {
   const T* __restrict__ uzg = ws.arr(WS_UZ);
   const T* __restrict__ lntg = ws.arr(WS_LNT);
@@ -266,7 +283,7 @@ __global__ __launch_bounds__(TX * TY) void zQ(const BoxDev* __restrict__ boxes,
   using P3 = Plane<TX, TY, 3>;
   __shared__ T sR[P3::N], sL[P3::N];
   __shared__ T sUZ[3][P3::N], sBZ[3][P3::N], sPZ[3][P3::N];
-  ZPROLOGUE
+  ZLOOP_BEGIN
   PlaneIdx<TX, TY, 3> i3;
   i3.init(b, it.x0, it.y0);
   const unsigned tm = ph.terms;
@@ -434,6 +451,7 @@ __global__ __launch_bounds__(TX * TY) void zQ(const BoxDev* __restrict__ boxes,
       }
     }
   }
+  ZLOOP_END
 }
 
 // ---------------------------------------------------------------------------
@@ -442,9 +460,10 @@ __global__ __launch_bounds__(TX * TY) void zQ(const BoxDev* __restrict__ boxes,
 // Lyz, Qz (as in Q), the centre terms Gxx = tau_xx - xup(p_x) xup(u_x) - P,
 // Gyy, Qc = tau_xx S_xx + tau_yy S_yy - P div u, and the x/y-face energy
 // fluxes Hx, Hy (eq. ien, eq. ediffuse).
-template <class T, int TX, int TY>
+template <class T, int TX, int TY, bool PERS>
 __global__ __launch_bounds__(TX * TY) void zP(const BoxDev* __restrict__ boxes,
                                               const ZItem* __restrict__ items, int nitems, const T* __restrict__ ztab,
+                                               int* __restrict__ queue,
                                               CP8<T> f, Phys<T> ph, ZWork<T> ws) {
   const T* __restrict__ lntg = ws.arr(WS_LNT);
   const T* __restrict__ Dg = ws.arr(WS_D);
@@ -456,7 +475,7 @@ __global__ __launch_bounds__(TX * TY) void zP(const BoxDev* __restrict__ boxes,
   constexpr int NS = 14;
   __shared__ T sR[P6::N];
   __shared__ T s3[NS * P3::N];
-  ZPROLOGUE
+  ZLOOP_BEGIN
   PlaneIdx<TX, TY, 6> i6;
   PlaneIdx<TX, TY, 3> i3;
   i6.init(b, it.x0, it.y0);
@@ -583,6 +602,7 @@ __global__ __launch_bounds__(TX * TY) void zP(const BoxDev* __restrict__ boxes,
       ws.pq(POUT_HY)[o] = hy;
     }
   }
+  ZLOOP_END
 }
 
 // ---------------------------------------------------------------------------
@@ -591,9 +611,10 @@ __global__ __launch_bounds__(TX * TY) void zP(const BoxDev* __restrict__ boxes,
 // plane r through LDS strips; z divergences scattered into per-thread
 // accumulators of output planes r-3..r+3 (first differences for
 // derivatives); plane r-3 is then complete.
-template <class T, int TX, int TY>
+template <class T, int TX, int TY, bool PERS>
 __global__ __launch_bounds__(TX * TY) void zF(const BoxDev* __restrict__ boxes,
                                               const ZItem* __restrict__ items, int nitems, const T* __restrict__ ztab,
+                                               int* __restrict__ queue,
                                               CP8<T> f, ZWork<T> ws, Phys<T> ph, P8<T> du,
                                               int du_mode, P8<T> f_out, T alpha, double beta,
                                               const double* __restrict__ dt_dev,
@@ -607,7 +628,7 @@ __global__ __launch_bounds__(TX * TY) void zF(const BoxDev* __restrict__ boxes,
   __shared__ T sx[9 * PXs::N];
   __shared__ T sy[9 * PYs::N];
   __shared__ T s2[2 * P3::N];
-  ZPROLOGUE
+  ZLOOP_BEGIN
   PlaneIdx<TX, TY, 3, 0> ix;
   PlaneIdx<TX, TY, 0, 3> iy;
   PlaneIdx<TX, TY, 3> i3;
@@ -747,6 +768,7 @@ __global__ __launch_bounds__(TX * TY) void zF(const BoxDev* __restrict__ boxes,
       acc[a][6] = T(0);
     }
   }
+  ZLOOP_END
 }
 
 // Courant time step of the current state from the per-item maxima of A1 / A2
@@ -777,31 +799,61 @@ __global__ __launch_bounds__(256) void k_dt(const BoxDev* __restrict__ boxes,
 }
 
 // ---------------------------------------------------------------------------
-template <class T, int TX, int TY>
-static void launch_zstage_t(const ZLaunch& L, const ZStageArgs<T>& a) {
+__global__ void k_qreset(int* q) {
+  if ((int)threadIdx.x < kQueueInts) q[threadIdx.x] = 0;
+}
+
+// Workgroups of a kernel that fit on the device at once (cached per kernel).
+static int resident_groups(const void* kern, int block, int ncu) {
+  static std::mutex mu;
+  static std::map<const void*, int> cache;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = cache.find(kern);
+  if (it != cache.end()) return it->second;
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, block, 0) != hipSuccess || nb < 1) nb = 1;
+  return cache[kern] = nb * ncu;
+}
+
+template <class T, int TX, int TY, bool PERS>
+static void launch_zstage_m(const ZLaunch& L, const ZStageArgs<T>& a) {
   const int n = L.nitems;
-  const dim3 grid(8 * ((n + 7) / 8)), block(TX * TY);
+  const dim3 block(TX * TY);
+  int* q = PERS ? L.queue : nullptr;
+  auto grid = [&](const void* kern) {
+    if (!q) return dim3(8 * ((n + 7) / 8));
+    const int r = std::min(n, resident_groups(kern, TX * TY, L.ncu));
+    return dim3(std::max(8, r - r % 8));
+  };
+  if (q) hipLaunchKernelGGL(k_qreset, dim3(1), dim3(64), 0, L.stream, q);
   L.at(PASS_PRIM);
-  hipLaunchKernelGGL((zA1<T, TX, TY>), grid, block, 0, L.stream, L.boxes, L.items, n, a.ztab,
-                     a.f, a.ph, a.w, a.cpart);
+  hipLaunchKernelGGL((zA1<T, TX, TY, PERS>), grid((const void*)zA1<T, TX, TY, PERS>), block, 0, L.stream, L.boxes,
+                     L.items, n, a.ztab, q, a.f, a.ph, a.w, a.cpart);
   L.at(PASS_MEAN3);
-  hipLaunchKernelGGL((zA2<T, TX, TY>), grid, block, 0, L.stream, L.boxes, L.items, n, a.ztab,
-                     a.w, a.cpart);
+  hipLaunchKernelGGL((zA2<T, TX, TY, PERS>), grid((const void*)zA2<T, TX, TY, PERS>), block, 0, L.stream, L.boxes,
+                     L.items, n, a.ztab, q ? q + 8 : q, a.w, a.cpart);
   if (a.cpart) {
     L.at(PASS_REDUCE);
     hipLaunchKernelGGL(k_dt, dim3(1), dim3(256), 0, L.stream, L.boxes, L.items, n, a.cpart, a.Cdt,
                        a.Cdtd, a.nuB, a.eta_const, a.dt_dev);
   }
   L.at(PASS_EDGES);
-  hipLaunchKernelGGL((zQ<T, TX, TY>), grid, block, 0, L.stream, L.boxes, L.items, n, a.ztab, a.f,
-                     a.ph, a.w);
+  hipLaunchKernelGGL((zQ<T, TX, TY, PERS>), grid((const void*)zQ<T, TX, TY, PERS>), block, 0, L.stream, L.boxes,
+                     L.items, n, a.ztab, q ? q + 16 : q, a.f, a.ph, a.w);
   L.at(PASS_CF);
-  hipLaunchKernelGGL((zP<T, TX, TY>), grid, block, 0, L.stream, L.boxes, L.items, n, a.ztab, a.f,
-                     a.ph, a.w);
+  hipLaunchKernelGGL((zP<T, TX, TY, PERS>), grid((const void*)zP<T, TX, TY, PERS>), block, 0, L.stream, L.boxes,
+                     L.items, n, a.ztab, q ? q + 24 : q, a.f, a.ph, a.w);
   L.at(PASS_FINAL);
-  hipLaunchKernelGGL((zF<T, TX, TY>), grid, block, 0, L.stream, L.boxes, L.items, n, a.ztab, a.f,
-                     a.w, a.ph, a.du, a.du_mode, a.f_out, a.alpha, a.beta, a.dt_dev, a.dt_host);
+  hipLaunchKernelGGL((zF<T, TX, TY, PERS>), grid((const void*)zF<T, TX, TY, PERS>), block, 0, L.stream, L.boxes,
+                     L.items, n, a.ztab, q ? q + 32 : q, a.f, a.w, a.ph, a.du, a.du_mode, a.f_out,
+                     a.alpha, a.beta, a.dt_dev, a.dt_host);
   L.at(PASS_END);
+}
+
+template <class T, int TX, int TY>
+static void launch_zstage_t(const ZLaunch& L, const ZStageArgs<T>& a) {
+  if (L.persistent) launch_zstage_m<T, TX, TY, true>(L, a);
+  else launch_zstage_m<T, TX, TY, false>(L, a);
 }
 
 template <class T>

@@ -172,4 +172,42 @@ __device__ __forceinline__ int xcd_item(int nitems) {
   return (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
 }
 
+// Persistent mode: the next item for this workgroup, from the range of its
+// own XCD first (workgroups are dispatched to the 8 XCDs round-robin, so
+// blockIdx % 8 is the XCD), then from the other ranges in turn.  queue[x]
+// counts the items of range x handed out; nitems when everything is taken.
+__device__ __forceinline__ int zpull(int nitems, int* queue) {
+  const int per = (nitems + 7) / 8;
+  const int x0 = (int)(blockIdx.x % 8);
+  for (int d = 0; d < 8; ++d) {
+    const int x = (x0 + d) % 8;
+    const int lo = x * per;
+    const int cnt = min(per, nitems - lo);
+    if (cnt <= 0) continue;
+    if (__hip_atomic_load(&queue[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= cnt) continue;
+    const int t = atomicAdd(&queue[x], 1);
+    if (t < cnt) return lo + t;
+  }
+  return nitems;
+}
+
+// First and next item of a workgroup (all threads call; thread 0 pulls and
+// broadcasts through LDS).  Grid mode (PERS false): one item each.
+template <bool PERS>
+__device__ __forceinline__ int zfirst(int nitems, int* queue, int* s) {
+  if constexpr (!PERS) return xcd_item(nitems);
+  if (threadIdx.x == 0) *s = zpull(nitems, queue);
+  __syncthreads();
+  return *s;
+}
+
+template <bool PERS>
+__device__ __forceinline__ int znext(int nitems, int* queue, int* s) {
+  if constexpr (!PERS) return nitems;
+  __syncthreads();
+  if (threadIdx.x == 0) *s = zpull(nitems, queue);
+  __syncthreads();
+  return *s;
+}
+
 }  // namespace smhd

@@ -47,11 +47,17 @@ template <class T> struct ZWork {
   __host__ __device__ T* pq(int i) const { return arr(WS_P0 + i); }
 };
 
+// Item queues of the persistent mode: 8 counters per pass, 5 passes.
+constexpr int kQueueInts = 40;
+
 struct ZLaunch {
   const BoxDev* boxes;
   const ZItem* items;     // device
   int nitems;
   int tile;               // ZTile of these items
+  int* queue;             // device, kQueueInts counters (persistent mode)
+  int persistent;         // 0: one workgroup per item; 1: item queues
+  int ncu;                // compute units of the device
   hipStream_t stream;
   void (*mark)(void*, int);
   void* mark_ctx;

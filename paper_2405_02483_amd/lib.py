@@ -20,6 +20,7 @@ __all__ = [
     "mhd_init", "mhd_destroy", "mhd_last_error", "mhd_field_elems",
     "mhd_box_offset", "mhd_rhs", "mhd_step", "mhd_step_adjoint",
     "mhd_reductions", "mhd_profile", "mhd_profile_read", "mhd_last_dt", "mhd_set_tile",
+    "mhd_set_launch", "mhd_get_launch", "mhd_autotune",
     "PASS_NAMES", "TILES", "Context",
 ]
 
@@ -118,6 +119,12 @@ def load():
     L.mhd_last_dt.restype = ctypes.c_int
     L.mhd_set_tile.argtypes = [vp, i32]
     L.mhd_set_tile.restype = ctypes.c_int
+    L.mhd_set_launch.argtypes = [vp, i32, i32]
+    L.mhd_set_launch.restype = ctypes.c_int
+    L.mhd_get_launch.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    L.mhd_get_launch.restype = ctypes.c_int
+    L.mhd_autotune.argtypes = [vp, _P8, _P8, i32, ctypes.POINTER(ctypes.c_double)]
+    L.mhd_autotune.restype = ctypes.c_int
     L.mhd_profile.argtypes = [vp, i32]
     L.mhd_profile.restype = ctypes.c_int
     L.mhd_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
@@ -213,6 +220,23 @@ def mhd_last_dt(ctx):
 
 def mhd_set_tile(ctx, tile):
     _check(load().mhd_set_tile(ctx, int(tile)), ctx)
+
+
+def mhd_set_launch(ctx, tile, persistent):
+    _check(load().mhd_set_launch(ctx, int(tile), int(persistent)), ctx)
+
+
+def mhd_get_launch(ctx):
+    t, m = ctypes.c_int32(), ctypes.c_int32()
+    _check(load().mhd_get_launch(ctx, ctypes.byref(t), ctypes.byref(m)), ctx)
+    return t.value, m.value
+
+
+def mhd_autotune(ctx, f, dfdt, reps, *, dtype, n):
+    ms = (ctypes.c_double * 8)()
+    _check(load().mhd_autotune(ctx, _ptrs(f, n, dtype, "f"), _ptrs(dfdt, n, dtype, "dfdt"),
+                               int(reps), ms), ctx)
+    return list(ms)
 
 
 def mhd_profile(ctx, enable):
@@ -326,6 +350,21 @@ class Context:
 
     def set_tile(self, tile):
         mhd_set_tile(self.ctx, TILES[tile] if isinstance(tile, str) else tile)
+
+    def set_launch(self, tile, persistent):
+        mhd_set_launch(self.ctx, TILES[tile] if isinstance(tile, str) else tile, persistent)
+
+    def get_launch(self):
+        t, m = mhd_get_launch(self.ctx)
+        return {v: k for k, v in TILES.items()}[t], m
+
+    def autotune(self, f, reps=3, dfdt=None):
+        """Times every tile shape and launch mode on f and keeps the fastest;
+        returns {(tile, persistent): ms per right-hand side}."""
+        dfdt = dfdt if dfdt is not None else self.empty()
+        ms = mhd_autotune(self.ctx, f, dfdt, reps, dtype=self.dtype, n=self.n)
+        names = {v: k for k, v in TILES.items()}
+        return {(names[q // 2], q % 2): ms[q] for q in range(8)}
 
     def profile(self, enable=True):
         mhd_profile(self.ctx, enable)

@@ -1,0 +1,85 @@
+"""Batched ensembles of uneven boxes: the persistent launch mode and the
+autotuner (through the C ABI).  Every launch mode and tile shape must give
+the same bits; an autotuned persistent ensemble must match the float64 oracle
+box by box."""
+import pytest
+import torch
+
+import oracle as O
+from paper_2405_02483_amd import inputs
+from tests.helpers import grid_params, rel_errors, to_cpu64
+
+pytestmark = pytest.mark.gpu
+
+
+def _ensemble(sizes, seed0=5000):
+    cases = [inputs.turbulent(n=n, seed=seed0 + b, kmax=3.0) for b, n in enumerate(sizes)]
+    return [c[0] for c in cases], [c[1] for c in cases], cases[0][2]
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_persistent_mode_gives_identical_bits(dtype):
+    from paper_2405_02483_amd.lib import Context, TILES
+    fields, boxes, prm = _ensemble(inputs.ensemble_sizes(8, (6, 8, 12, 16), seed=5))
+    ctx = Context(boxes, prm, dtype=dtype)
+    ref = None
+    for tile in TILES:
+        for persistent in (0, 1):
+            ctx.set_launch(tile, persistent)
+            assert ctx.get_launch() == (tile, persistent)
+            fd = ctx.upload(fields)
+            ctx.step(fd, 0.0, 2)            # Courant dt on the device: exercises the partials
+            dt = ctx.last_dt()
+            if ref is None:
+                ref = ([t.clone() for t in fd], dt)
+            else:
+                assert dt == ref[1], (tile, persistent)
+                for a, b in zip(fd, ref[0]):
+                    assert torch.equal(a, b), (tile, persistent)
+    ctx.close()
+
+
+def test_persistent_mode_walls_identical_bits():
+    from paper_2405_02483_amd.lib import Context
+    f, box, prm = inputs.stratified(12, 10, 24, seed=3)
+    ctx = Context(box, prm, dtype=torch.float32)
+    out = []
+    for persistent in (0, 1):
+        ctx.set_launch("32x8", persistent)
+        fd = ctx.upload([f])
+        ctx.step(fd, 0.0, 2)
+        out.append(fd)
+    for a, b in zip(*out):
+        assert torch.equal(a, b)
+    ctx.close()
+
+
+def test_set_launch_rejects_bad_values():
+    from paper_2405_02483_amd.lib import Context, MhdError, MHD_EINVAL
+    f, box, prm = inputs.turbulent(n=8, seed=3, kmax=2.0)
+    ctx = Context(box, prm, dtype=torch.float32)
+    for tile, mode in ((4, 0), (-1, 0), (0, 2)):
+        with pytest.raises(MhdError) as ei:
+            ctx.set_launch(tile, mode)
+        assert ei.value.code == MHD_EINVAL
+    ctx.close()
+
+
+def test_autotuned_persistent_ensemble_matches_oracle():
+    from paper_2405_02483_amd.lib import Context
+    sizes = inputs.ensemble_sizes(8, (6, 8, 10, 12), seed=5)
+    fields, boxes, prm = _ensemble(sizes)
+    ctx = Context(boxes, prm, dtype=torch.float32)
+    fd = ctx.upload(fields)
+    ms = ctx.autotune(fd, reps=2)
+    assert len(ms) == 8 and all(v > 0 for v in ms.values())
+    assert ms[ctx.get_launch()] == min(ms.values())
+    dt = 0.5 * min(O.courant(to_cpu64(f), *grid_params(b, prm))[0] for f, b in zip(fields, boxes))
+    fd = ctx.upload(fields)
+    ctx.step(fd, dt, 1)
+    for b, (f, box) in enumerate(zip(fields, boxes)):
+        g, p = grid_params(box, prm)
+        want = O.step(to_cpu64(f), g, p, dt, 1)
+        errs = rel_errors(ctx.box_view(fd, b), want)
+        assert max(errs) < 1e-5, (b, sizes[b], errs)
+    ctx.close()
