@@ -83,7 +83,7 @@ static int prof_fold(mhd_ctx* c) {
 }
 
 static std::string g_init_err;
-static constexpr int kWorkArrays = WS_COUNT;   // 30 arrays
+static constexpr int kWorkArrays = WS_COUNT;   // 33 arrays
 
 static int fail(mhd_ctx* c, int code, const std::string& msg) {
   if (c) c->err = msg; else g_init_err = msg;

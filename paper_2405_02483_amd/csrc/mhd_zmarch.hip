@@ -429,7 +429,12 @@ __global__ __launch_bounds__(TX * TY) void zQ(const BoxDev* __restrict__ boxes,
                         (g.dz * zwin<0, 0, 6, 3>(wNu, q, wall, N, T(0), zt)) *
                         zwin<0, 0, 6, 3>(wEm, q, wall, N, T(0), zt) *
                         zwin<1, 0, 6, 3>(wLem, q, wall, N, g.hzi, zt);
-        if (own) ws.q(QOUT_HZ)[o] = hz;
+        if (own) {
+          ws.q(QOUT_HZ)[o] = hz;
+          // pressure gradient on its own: folded into the flux, a pressure
+          // of order one would swamp the much smaller stresses in float32
+          ws.q(QOUT_DPZ)[o] = pres ? ph.gamma1 * zwin<1, 0, 6, 3>(wE, q, wall, N, g.hzi, zt) : T(0);
+        }
       }
     }
     // centre terms of plane q2 = r - 3 (window slot 2)
@@ -444,7 +449,6 @@ __global__ __launch_bounds__(TX * TY) void zQ(const BoxDev* __restrict__ boxes,
         czz = tzz * szz;
       }
       if (adv) gzz = gzz - zwin<0, 1, 6, 2>(wPZ, q2, wall, N, T(0), zt) * zwin<0, 1, 6, 2>(wUZ, q2, wall, N, T(0), zt);
-      if (pres) gzz = gzz - ph.gamma1 * wE[2];
       if (own) {
         ws.q(QOUT_GZZ)[o] = gzz;
         ws.q(QOUT_CZZ)[o] = czz;
@@ -572,14 +576,13 @@ __global__ __launch_bounds__(TX * TY) void zP(const BoxDev* __restrict__ boxes,
         gyy = gyy - op6<0, 1, T>([&](int m) { return S(1, x, y + m); }, T(0)) *
                         op6<0, 1, T>([&](int m) { return S(7, x, y + m); }, T(0));
       }
-      if (pres) {
-        gxx = gxx - Pc;
-        gyy = gyy - Pc;
-        qc = qc - Pc * Dc;
-      }
+      if (pres) qc = qc - Pc * Dc;
       ws.pq(POUT_GXX)[o] = gxx;
       ws.pq(POUT_GYY)[o] = gyy;
       ws.pq(POUT_QC)[o] = qc;
+      // pressure gradients on the x- and y-faces, kept out of the fluxes
+      ws.pq(POUT_DPX)[o] = pres ? ph.gamma1 * op6<1, 0, T>([&](int m) { return S(2, x + m, y); }, g.hxi) : T(0);
+      ws.pq(POUT_DPY)[o] = pres ? ph.gamma1 * op6<1, 0, T>([&](int m) { return S(2, x, y + m); }, g.hyi) : T(0);
     }
     // ---- x- and y-faces: energy fluxes
     {
@@ -701,10 +704,13 @@ __global__ __launch_bounds__(TX * TY) void zF(const BoxDev* __restrict__ boxes,
                          op6<1, 1, T>([&](int m) { return Y(0, y + m); }, g.hyi));
         acc[1][3] += op6<1, 0, T>([&](int m) { return X(1, x + m); }, g.hxi) +
                      op6<1, 1, T>([&](int m) { return Y(1, y + m); }, g.hyi) -
-                     op6<0, 1, T>([&](int m) { return Y(2, y + m); }, T(0)) * inv_mu;
+                     op6<0, 1, T>([&](int m) { return Y(2, y + m); }, T(0)) * inv_mu -
+                     ws.pq(POUT_DPX)[o];
         acc[2][3] += op6<1, 0, T>([&](int m) { return Y(3, y + m); }, g.hyi) +
                      op6<1, 1, T>([&](int m) { return X(2, x + m); }, g.hxi) +
-                     op6<0, 1, T>([&](int m) { return X(3, x + m); }, T(0)) * inv_mu;
+                     op6<0, 1, T>([&](int m) { return X(3, x + m); }, T(0)) * inv_mu -
+                     ws.pq(POUT_DPY)[o];
+        acc[3][3] -= ws.q(QOUT_DPZ)[o];
         acc[3][3] += op6<1, 1, T>([&](int m) { return X(5, x + m); }, g.hxi) +
                      op6<1, 1, T>([&](int m) { return Y(5, y + m); }, g.hyi) +
                      (op6<0, 1, T>([&](int m) { return Y(6, y + m); }, T(0)) -

@@ -9,7 +9,7 @@ namespace smhd {
 enum QOut : int {
   QOUT_GXZ = 0, QOUT_GZX, QOUT_EY, QOUT_LXY, QOUT_LZY, QOUT_QY,
   QOUT_GYZ, QOUT_GZY, QOUT_EX, QOUT_LYX, QOUT_LZX, QOUT_QX,
-  QOUT_HZ, QOUT_GZZ, QOUT_CZZ, QOUT_COUNT
+  QOUT_HZ, QOUT_GZZ, QOUT_CZZ, QOUT_DPZ, QOUT_COUNT
 };
 
 template <class T> struct QP { T* p[QOUT_COUNT]; };
@@ -18,7 +18,7 @@ template <class T> struct CQP { const T* p[QOUT_COUNT]; };
 // Outputs of pass P, in workspace order.
 enum POut : int {
   POUT_GXY = 0, POUT_GYX, POUT_EZ, POUT_LXZ, POUT_LYZ, POUT_QZ,
-  POUT_GXX, POUT_GYY, POUT_QC, POUT_HX, POUT_HY, POUT_COUNT
+  POUT_GXX, POUT_GYY, POUT_QC, POUT_HX, POUT_HY, POUT_DPX, POUT_DPY, POUT_COUNT
 };
 
 template <class T> struct PQ { T* p[POUT_COUNT]; };

@@ -217,9 +217,10 @@ def test_step_adjoint_f32_close_to_f64():
 #   the float64 gradient by 9e-5; near-ties of the max over three cells that
 #   float32 rounding resolves differently; 8.8e-5 measured for the float32
 #   adjoint), so the float32 adjoint is held to 2e-4 in L2 against the
-#   float64 gradient and to 1e-3 per direction (a direction whose derivative
-#   is small by cancellation shows the same absolute error as a larger
-#   relative one; 9e-4 measured).
+#   float64 gradient, and per direction to 5e-4 of the typical size of a
+#   random directional derivative, |grad L| / sqrt(n) (a direction whose
+#   derivative is small by cancellation would otherwise turn the same
+#   absolute error into a large relative one).
 
 def _energy(f, g, mu):
     """Sum over faces of p_a^2 / (2 adn rho) dV + B_a^2 / (2 mu) dV (float64, CPU)."""
@@ -285,6 +286,8 @@ def test_energy_gradient_128_cubed_40_steps():
     rng = np.random.default_rng(4)
     xnorm = math.sqrt(sum(float((t * t).sum()) for t in u0 + b0))
     worst = {torch.float32: 0.0, torch.float64: 0.0}
+    g64 = grads[torch.float64]
+    typical = math.sqrt(sum(float((t * t).sum()) for t in g64) / (6 * n ** 3))
     for _ in range(ndir):
         v = [torch.from_numpy(rng.standard_normal((n, n, n))) for _ in range(6)]
         vn = math.sqrt(sum(float((t * t).sum()) for t in v))
@@ -295,13 +298,14 @@ def test_energy_gradient_128_cubed_40_steps():
         fd = float((lp - lm) / np.longdouble(2 * eps))
         for dtype, gr in grads.items():
             ad = sum(float((a * b).sum()) for a, b in zip(gr, v))
-            worst[dtype] = max(worst[dtype], abs(ad - fd) / abs(fd))
+            scale = abs(fd) if dtype == torch.float64 else typical
+            worst[dtype] = max(worst[dtype], abs(ad - fd) / scale)
     ctx64.close()
     g32, g64 = grads[torch.float32], grads[torch.float64]
     l2 = math.sqrt(sum(float(((a - b) ** 2).sum()) for a, b in zip(g32, g64))
                    / sum(float((b * b).sum()) for b in g64))
-    print("max relative error over %d directions: float32 %.2e, float64 %.2e; "
+    print("max error over %d directions: float32 (of |grad|/sqrt(n)) %.2e, float64 (relative) %.2e; "
           "float32 vs float64 gradient (L2) %.2e"
           % (ndir, worst[torch.float32], worst[torch.float64], l2))
     assert worst[torch.float64] <= 1e-4, worst
-    assert worst[torch.float32] <= 1e-3 and l2 <= 2e-4, (worst, l2)
+    assert worst[torch.float32] <= 5e-4 and l2 <= 2e-4, (worst, l2)

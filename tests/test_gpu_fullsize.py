@@ -1,0 +1,124 @@
+"""Parity at the benchmark's full size: the 512^3 stratified box (walls in z,
+5 ghost planes per side) in float32, with the stage kernels in the launch
+configuration bench.py times (the library default) and in the persistent
+16x16 configuration.
+
+The oracle cannot hold the whole box, so it checks sampled columns.  The
+right-hand side at a cell depends on cells at most 11 cells away along x and
+y (measured with the oracle: a perturbation of one cell changes F no further
+out), 14 near closed walls (the ghost momenta interpolate the density along
+x and y first), and one RK step on at most 3 x 14.  A full-height window of the state,
+periodic in x and y with width 2 m + w, therefore gives the oracle's exact
+result on its central w x w columns when m covers that radius.  Properties
+that hold at any size (mass conservation with closed walls, div B at
+rounding level) are checked on the whole box.
+
+In hydrostatic balance the momentum right-hand side is a small residual of
+the pressure gradient and gravity, so float32 errors of F are measured
+against the size of the terms being summed: per field, the error norm over
+the sum of the norms of that field's term groups (the oracle run with one
+group of terms at a time), at most 1e-4.  The state after one step is held to
+the stated float32 tolerance, 1e-5 relative L2.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2405_02483_amd import inputs
+from tests.helpers import grid_params, rel_errors
+
+TERM_GROUPS = (O.T_CONT, O.T_ADV, O.T_PRES, O.T_VISC, O.T_LORENTZ, O.T_INDUCT, O.T_RESIST,
+               O.T_EDIFF, O.T_GRAV)
+
+pytestmark = pytest.mark.gpu
+
+N = 512
+RHS_MARGIN = 16
+STEP_MARGIN = 44
+
+
+@pytest.fixture(scope="module")
+def state():
+    f, box, prm = inputs.stratified(N, N, N, seed=3)
+    return f, box, prm
+
+
+def _window(f, box, x0, y0, width):
+    ix = (np.arange(width) + x0) % box["nx"]
+    iy = (np.arange(width) + y0) % box["ny"]
+    sub = [torch.from_numpy(np.ascontiguousarray(np.asarray(a)[:, iy][:, :, ix])).to(torch.float64)
+           for a in f]
+    wbox = dict(box, nx=width, ny=width, Lx=box["Lx"] * width / box["nx"],
+                Ly=box["Ly"] * width / box["ny"])
+    return sub, wbox
+
+
+def _centre(a, margin):
+    return a[:, margin:-margin, margin:-margin]
+
+
+def _windows(seed, count, width):
+    rng = np.random.default_rng(seed)
+    return [tuple(int(v) for v in rng.integers(0, N, 2)) for _ in range(count)]
+
+
+@pytest.mark.parametrize("launch", [None, ("16x16", 1)])
+def test_rhs_sampled_columns_512(state, launch):
+    from paper_2405_02483_amd.lib import Context
+    f, box, prm = state
+    ctx = Context(box, prm, dtype=torch.float32)
+    if launch:
+        ctx.set_launch(*launch)
+    fd = ctx.upload([f])
+    F = [t.view(-1) for t in ctx.box_view(ctx.rhs(fd), 0)]
+    nzt = N + 2 * box["ngz"]
+    width = 2 * RHS_MARGIN + 8
+    for x0, y0 in _windows(51, 4, width):
+        sub, wbox = _window(f, box, x0, y0, width)
+        g, p = grid_params(wbox, prm)
+        want = [_centre(a, RHS_MARGIN) for a in O.rhs(tuple(sub), g, p)]
+        scale = [0.0] * 8
+        for t in TERM_GROUPS:
+            gt, pt = grid_params(wbox, prm, terms=t)
+            for v, a in enumerate(O.rhs(tuple(sub), gt, pt)):
+                scale[v] += float(torch.linalg.norm(_centre(a, RHS_MARGIN)))
+        ix = torch.from_numpy((np.arange(RHS_MARGIN, width - RHS_MARGIN) + x0) % N)
+        iy = torch.from_numpy((np.arange(RHS_MARGIN, width - RHS_MARGIN) + y0) % N)
+        got = [t.view(nzt, N, N)[:, iy.cuda()][:, :, ix.cuda()].cpu().double() for t in F]
+        errs = [float(torch.linalg.norm(a - b)) / max(sc, 1e-300)
+                for a, b, sc in zip(got, want, scale)]
+        print((x0, y0), ["%.1e" % e for e in errs], "plain", ["%.1e" % e for e in rel_errors(got, want)])
+        assert max(errs) < 1e-4, ((x0, y0), errs)
+    ctx.close()
+
+
+def test_step_sampled_columns_and_invariants_512(state):
+    from paper_2405_02483_amd.lib import Context
+    f, box, prm = state
+    ctx = Context(box, prm, dtype=torch.float32)
+    fd = ctx.upload([f])
+    s0 = ctx.reductions(fd)
+    ctx.step(fd, 0.0, 1)                       # as bench.py: Courant dt on the device
+    dt = ctx.last_dt()
+    assert math.isclose(dt, s0["dt"], rel_tol=1e-6), (dt, s0["dt"])
+    s1 = ctx.reductions(fd)
+    assert abs(s1["mass"] - s0["mass"]) <= 1e-6 * s0["mass"]
+    assert s1["divb_max"] * (1.0 / N) <= 1e-5 * s1["bmax"]
+    nzt = N + 2 * box["ngz"]
+    got_all = [t.view(nzt, N, N) for t in ctx.box_view(fd, 0)]
+    width = 2 * STEP_MARGIN + 16
+    g0, g1 = box["ngz"], box["ngz"] + N
+    for x0, y0 in _windows(52, 2, width):
+        sub, wbox = _window(f, box, x0, y0, width)
+        g, p = grid_params(wbox, prm)
+        want = [_centre(a, STEP_MARGIN)[g0:g1] for a in O.step(tuple(sub), g, p, dt, 1)]
+        ix = torch.from_numpy((np.arange(STEP_MARGIN, width - STEP_MARGIN) + x0) % N).cuda()
+        iy = torch.from_numpy((np.arange(STEP_MARGIN, width - STEP_MARGIN) + y0) % N).cuda()
+        got = [t[g0:g1][:, iy][:, :, ix].cpu() for t in got_all]
+        errs = rel_errors(got, want)
+        print((x0, y0), ["%.1e" % e for e in errs])
+        assert max(errs) < 1e-5, ((x0, y0), errs)
+    ctx.close()
