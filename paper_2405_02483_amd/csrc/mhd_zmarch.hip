@@ -79,8 +79,8 @@ __global__ __launch_bounds__(TX * TY) void zA1(const BoxDev* __restrict__ boxes,
   T* __restrict__ uz_out = ws.arr(WS_UZ);
   using PR = Plane<TX, TY, 5>;
   using PP = Plane<TX, TY, 3>;
-  __shared__ T sR[PR::N];
-  __shared__ T sPX[PP::N], sPY[PP::N], sBX[PP::N], sBY[PP::N];
+  __shared__ T sR[PR::NP];
+  __shared__ T sPX[PP::NP], sPY[PP::NP], sBX[PP::NP], sBY[PP::NP];
   __shared__ double sred[TX * TY];
   ZLOOP_BEGIN
   PlaneIdx<TX, TY, 5> i5;
@@ -195,9 +195,9 @@ __global__ __launch_bounds__(TX * TY) void zA2(const BoxDev* __restrict__ boxes,
   using PN = Plane<TX, TY, 2>;
   using PM = Plane<TX, TY, 1>;
   constexpr int NT = TX * TY;
-  __shared__ T sN[PN::N];
-  __shared__ T sMX[3][PM::N];
-  __shared__ T sM[PM::N];
+  __shared__ T sN[PN::NP];
+  __shared__ T sMX[3][PM::NP];
+  __shared__ T sM[PM::NP];
   __shared__ double sred[NT];
   ZLOOP_BEGIN
   PlaneIdx<TX, TY, 2> i2;
@@ -281,8 +281,8 @@ __global__ __launch_bounds__(TX * TY) void zQ(const BoxDev* __restrict__ boxes,
   const T* __restrict__ lntg = ws.arr(WS_LNT);
   const T* __restrict__ Dg = ws.arr(WS_D);
   using P3 = Plane<TX, TY, 3>;
-  __shared__ T sR[P3::N], sL[P3::N];
-  __shared__ T sUZ[3][P3::N], sBZ[3][P3::N], sPZ[3][P3::N];
+  __shared__ T sR[P3::NP], sL[P3::NP];
+  __shared__ T sUZ[3][P3::NP], sBZ[3][P3::NP], sPZ[3][P3::NP];
   ZLOOP_BEGIN
   PlaneIdx<TX, TY, 3> i3;
   i3.init(b, it.x0, it.y0);
@@ -477,8 +477,8 @@ __global__ __launch_bounds__(TX * TY) void zP(const BoxDev* __restrict__ boxes,
   // halo-3 planes: 0 px 1 py 2 e 3 Bx 4 By 5 ln nu | derived: 6 ux 7 uy 8 nu
   // 9 e_m 10 ln e_m 11 xdn(rho) 12 ydn(rho) 13 xdn(ln nu)
   constexpr int NS = 14;
-  __shared__ T sR[P6::N];
-  __shared__ T s3[NS * P3::N];
+  __shared__ T sR[P6::NP];
+  __shared__ T s3[NS * P3::NP];
   ZLOOP_BEGIN
   PlaneIdx<TX, TY, 6> i6;
   PlaneIdx<TX, TY, 3> i3;
@@ -489,7 +489,7 @@ __global__ __launch_bounds__(TX * TY) void zP(const BoxDev* __restrict__ boxes,
              adv = tm & T_ADV, pres = tm & T_PRES, ediff = tm & T_EDIFF;
   const bool need_nu = visc || (res && !(ph.eta_const > T(0)));
   const T inv_mu = ph.inv_mu;
-  auto S = [&](int q, int x, int y) -> T& { return s3[q * P3::N + P3::at(x, y)]; };
+  auto S = [&](int q, int x, int y) -> T& { return s3[q * P3::NP + P3::at(x, y)]; };
   for (int k = it.z0; k < it.z1; ++k) {
     __syncthreads();
     load_plane(sR, f.p[0], b, i6, k);
@@ -506,17 +506,17 @@ __global__ __launch_bounds__(TX * TY) void zP(const BoxDev* __restrict__ boxes,
       const T rxd = op6<0, 0, T>([&](int m) { return sR[P6::at(x + m, y)]; }, T(0));
       const T ryd = op6<0, 0, T>([&](int m) { return sR[P6::at(x, y + m)]; }, T(0));
       const T rc = sR[P6::at(x, y)];
-      s3[6 * P3::N + t] = s3[0 * P3::N + t] / rxd;
-      s3[7 * P3::N + t] = s3[1 * P3::N + t] / ryd;
-      s3[8 * P3::N + t] = exp(s3[5 * P3::N + t]);
-      const T emv = s3[2 * P3::N + t] / rc;
-      s3[9 * P3::N + t] = emv;
-      s3[10 * P3::N + t] = log(emv);
-      s3[11 * P3::N + t] = rxd;
-      s3[12 * P3::N + t] = ryd;
+      s3[6 * P3::NP + t] = s3[0 * P3::NP + t] / rxd;
+      s3[7 * P3::NP + t] = s3[1 * P3::NP + t] / ryd;
+      s3[8 * P3::NP + t] = exp(s3[5 * P3::NP + t]);
+      const T emv = s3[2 * P3::NP + t] / rc;
+      s3[9 * P3::NP + t] = emv;
+      s3[10 * P3::NP + t] = log(emv);
+      s3[11 * P3::NP + t] = rxd;
+      s3[12 * P3::NP + t] = ryd;
       // xdn(ln nu) is only needed on the own columns' y-strip
       if (x >= 0 && x < TX)
-        s3[13 * P3::N + t] = op6<0, 0, T>([&](int m) { return s3[5 * P3::N + t + m]; }, T(0));
+        s3[13 * P3::NP + t] = op6<0, 0, T>([&](int m) { return s3[5 * P3::NP + t + m]; }, T(0));
     }
     __syncthreads();
     if (!own) continue;
@@ -628,9 +628,9 @@ __global__ __launch_bounds__(TX * TY) void zF(const BoxDev* __restrict__ boxes,
   // x strips: 0 px 1 Gxx 2 Gyx 3 Lyz 4 Hx 5 Gzx 6 Lzy 7 Ey 8 Qy
   // y strips: 0 py 1 Gxy 2 Lxz 3 Gyy 4 Hy 5 Gzy 6 Lzx 7 Ex 8 Qx
   // full:     0 Qz 1 Ez
-  __shared__ T sx[9 * PXs::N];
-  __shared__ T sy[9 * PYs::N];
-  __shared__ T s2[2 * P3::N];
+  __shared__ T sx[9 * PXs::NP];
+  __shared__ T sy[9 * PYs::NP];
+  __shared__ T s2[2 * P3::NP];
   ZLOOP_BEGIN
   PlaneIdx<TX, TY, 3, 0> ix;
   PlaneIdx<TX, TY, 0, 3> iy;
@@ -643,9 +643,9 @@ __global__ __launch_bounds__(TX * TY) void zF(const BoxDev* __restrict__ boxes,
   const T inv_mu = ph.inv_mu;
   const double dt = dt_dev ? *dt_dev : dt_host;
   const T bdt = T(beta * dt);
-  auto X = [&](int q, int x) -> T { return sx[q * PXs::N + PXs::at(x, ty)]; };
-  auto Y = [&](int q, int y) -> T { return sy[q * PYs::N + PYs::at(tx, y)]; };
-  auto F2 = [&](int q, int x, int y) -> T { return s2[q * P3::N + P3::at(x, y)]; };
+  auto X = [&](int q, int x) -> T { return sx[q * PXs::NP + PXs::at(x, ty)]; };
+  auto Y = [&](int q, int y) -> T { return sy[q * PYs::NP + PYs::at(tx, y)]; };
+  auto F2 = [&](int q, int x, int y) -> T { return s2[q * P3::NP + P3::at(x, y)]; };
   T acc[7][7];
 #pragma unroll
   for (int a = 0; a < 7; ++a)
@@ -688,14 +688,14 @@ __global__ __launch_bounds__(TX * TY) void zF(const BoxDev* __restrict__ boxes,
                           ws.pq(POUT_HY), ws.q(QOUT_GZY), ws.q(QOUT_LZX), ws.q(QOUT_EX)};
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-          load_plane(sx + q * PXs::N, xs[q], b, ix, k);
-          load_plane(sy + q * PYs::N, ys[q], b, iy, k);
+          load_plane(sx + q * PXs::NP, xs[q], b, ix, k);
+          load_plane(sy + q * PYs::NP, ys[q], b, iy, k);
         }
         load_plane(s2, ws.pq(POUT_QZ), b, i3, k);
-        load_plane(s2 + P3::N, ws.pq(POUT_EZ), b, i3, k);
+        load_plane(s2 + P3::NP, ws.pq(POUT_EZ), b, i3, k);
       }
-      load_plane(sx + 8 * PXs::N, ws.q(QOUT_QY), b, ix, k);
-      load_plane(sy + 8 * PYs::N, ws.q(QOUT_QX), b, iy, k);
+      load_plane(sx + 8 * PXs::NP, ws.q(QOUT_QY), b, ix, k);
+      load_plane(sy + 8 * PYs::NP, ws.q(QOUT_QX), b, iy, k);
       __syncthreads();
       const int x = tx, y = ty;
       if (inch) {

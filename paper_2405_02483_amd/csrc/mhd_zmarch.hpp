@@ -130,6 +130,9 @@ template <int TX, int TY, int HX, int HY = HX> struct Plane {
   static constexpr int W = TX + 2 * HX;
   static constexpr int HT = TY + 2 * HY;
   static constexpr int N = W * HT;
+  // buffer size: N rounded up to whole passes of the workgroup, so that the
+  // cooperative loads need no bounds test (see load_plane)
+  static constexpr int NP = (N + TX * TY - 1) / (TX * TY) * (TX * TY);
   static __device__ __forceinline__ int at(int x, int y) { return (y + HY) * W + (x + HX); }
 };
 
@@ -151,18 +154,19 @@ template <int TX, int TY, int HX, int HY = HX> struct PlaneIdx {
   }
 };
 
-// Cooperative load of plane k of a field into a tile plane buffer.
+// Cooperative load of plane k of a field into a tile plane buffer of
+// Plane::NP elements.  Slots past N load element 0 of the plane (offset 0)
+// into the padding: no bounds test, so no branch separates a load from its
+// store, and the loads of several planes can all be in flight at once.
 template <int TX, int TY, int HX, int HY, class T>
 __device__ __forceinline__ void load_plane(T* __restrict__ dst, const T* __restrict__ src,
                                            const BoxDev& b, const PlaneIdx<TX, TY, HX, HY>& ix,
                                            int k) {
   using PX = PlaneIdx<TX, TY, HX, HY>;
+  static_assert(PX::NPER * PX::NT == PX::PL::NP, "plane padding");
   const T* __restrict__ s = src + b.off + (long long)k * b.nx * b.ny;
 #pragma unroll
-  for (int i = 0; i < PX::NPER; ++i) {
-    const int t = (int)threadIdx.x + i * PX::NT;
-    if (t < PX::PL::N) dst[t] = s[ix.off[i]];
-  }
+  for (int i = 0; i < PX::NPER; ++i) dst[(int)threadIdx.x + i * PX::NT] = s[ix.off[i]];
 }
 
 // Items are assigned so that each XCD (blockIdx % 8) works on a contiguous
