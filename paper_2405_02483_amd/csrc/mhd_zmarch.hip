@@ -657,21 +657,40 @@ __global__ __launch_bounds__(TX * TY) void zF(const BoxDev* __restrict__ boxes,
 #pragma unroll
   for (int a = 0; a < 7; ++a) prev[a] = T(0);
 
-  auto finalize = [&](int v, int k, T Fv) {
-    // wall masking (Section 10) and the RK stage update of field v at plane k
-    if (wall) {
-      const bool cen = k >= b.g0 && k < b.g1;
-      const bool keep = v == 3 ? (k > b.g0 && k < b.g1) : (v == 7 ? (k >= b.g0 && k <= b.g1) : cen);
-      if (!keep) Fv = T(0);
-    }
+  // wall masking (Section 10): F vanishes in ghost planes, and for pz also
+  // on the two wall faces; Bz evolves on the wall faces
+  auto masked = [&](int v, int k, T Fv) -> T {
+    if (!wall) return Fv;
+    const bool cen = k >= b.g0 && k < b.g1;
+    const bool keep = v == 3 ? (k > b.g0 && k < b.g1) : (v == 7 ? (k >= b.g0 && k <= b.g1) : cen);
+    return keep ? Fv : T(0);
+  };
+  // RK stage update of one field at plane k, given its dU and f there
+  auto update = [&](int v, long long o, T Fv, T uin, T fin) {
+    const T U = (du_mode & DU_READ) ? alpha * uin + Fv : Fv;
+    if (du_mode & DU_WRITE) du.p[v][o] = U;
+    f_out.p[v][o] = fin + bdt * U;
+  };
+  // the seven z-accumulated fields at plane k: every load first, so they
+  // share one round trip to memory
+  auto finalize7 = [&](int k) {
     const long long o = col(k);
+    T Fv[7];
+#pragma unroll
+    for (int a = 0; a < 7; ++a) Fv[a] = masked(a, k, acc[a][0]);
     if (f_out.p[0] == nullptr) {
-      du.p[v][o] = Fv;
+#pragma unroll
+      for (int a = 0; a < 7; ++a) du.p[a][o] = Fv[a];
       return;
     }
-    const T U = (du_mode & DU_READ) ? alpha * du.p[v][o] + Fv : Fv;
-    if (du_mode & DU_WRITE) du.p[v][o] = U;
-    f_out.p[v][o] = f.p[v][o] + bdt * U;
+    T uin[7], fin[7];
+#pragma unroll
+    for (int a = 0; a < 7; ++a) {
+      uin[a] = (du_mode & DU_READ) ? du.p[a][o] : T(0);
+      fin[a] = f.p[a][o];
+    }
+#pragma unroll
+    for (int a = 0; a < 7; ++a) update(a, o, Fv[a], uin[a], fin[a]);
   };
 
   for (int r = it.z0 - 3; r <= it.z1 + 2; ++r) {
@@ -696,6 +715,12 @@ __global__ __launch_bounds__(TX * TY) void zF(const BoxDev* __restrict__ boxes,
       }
       load_plane(sx + 8 * PXs::NP, ws.q(QOUT_QY), b, ix, k);
       load_plane(sy + 8 * PYs::NP, ws.q(QOUT_QX), b, iy, k);
+      // Bz's dU and f at this plane, fetched with the planes
+      T bz_u = T(0), bz_f = T(0);
+      if (inch && own && f_out.p[0] != nullptr) {
+        if (du_mode & DU_READ) bz_u = du.p[7][o];
+        bz_f = f.p[7][o];
+      }
       __syncthreads();
       const int x = tx, y = ty;
       if (inch) {
@@ -726,7 +751,11 @@ __global__ __launch_bounds__(TX * TY) void zF(const BoxDev* __restrict__ boxes,
         // Bz has no z divergence: complete at once
         const T fbz = -(op6<1, 1, T>([&](int m) { return X(7, x + m); }, g.hxi) -
                         op6<1, 1, T>([&](int m) { return Y(7, y + m); }, g.hyi));
-        if (own) finalize(7, r, fbz);
+        if (own) {
+          const T F7 = masked(7, r, fbz);
+          if (f_out.p[0] == nullptr) du.p[7][o] = F7;
+          else update(7, o, F7, bz_u, bz_f);
+        }
       }
       const T xqy = op6<0, 1, T>([&](int m) { return X(8, x + m); }, T(0));
       const T yqx = op6<0, 1, T>([&](int m) { return Y(8, y + m); }, T(0));
@@ -763,10 +792,7 @@ __global__ __launch_bounds__(TX * TY) void zF(const BoxDev* __restrict__ boxes,
       for (int a = 0; a < 7; ++a) prev[a] = T(0);
     }
     // ---- plane kb = r-3 is complete
-    if (own && valid(kb) && kb >= it.z0 && kb < it.z1) {
-#pragma unroll
-      for (int a = 0; a < 7; ++a) finalize(a, kb, acc[a][0]);
-    }
+    if (own && valid(kb) && kb >= it.z0 && kb < it.z1) finalize7(kb);
 #pragma unroll
     for (int a = 0; a < 7; ++a) {
 #pragma unroll

@@ -79,7 +79,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 
 
 def lib_path():
-    return os.path.join(_HERE, "libstaggermhd.so")
+    """The library to load: $STAGGER_MHD_LIB if set (another build of the same
+    ABI), else the in-tree build."""
+    return os.environ.get("STAGGER_MHD_LIB") or os.path.join(_HERE, "libstaggermhd.so")
 
 
 _LIB = None
