@@ -81,10 +81,13 @@ def run_gpu(size, dtype, steps, warmup, workload="stratified", tile=None):
     log("generating the %d^3 %s state" % (size, workload))
     f_np, box, prm = make_state(workload, size)
     ctx = Context(box, prm, dtype=dtype)
-    if tile is not None:
-        ctx.set_tile(tile)
     f = ctx.upload([f_np])
     del f_np
+    tune = None
+    if tile is None:
+        tune = ctx.autotune(f, reps=2)          # tile shape and launch mode
+    else:
+        ctx.set_launch(tile, 0)
     work = (ctx.empty(), ctx.empty(), ctx.empty())
     torch.cuda.synchronize()
     ncell = size ** 3
@@ -106,6 +109,7 @@ def run_gpu(size, dtype, steps, warmup, workload="stratified", tile=None):
     t1 = time.perf_counter()
     prof = ctx.profile_read()
     ctx.profile(False)
+    launch = ctx.get_launch()
     dt_last = ctx.last_dt()
     s_end = ctx.reductions(f)
     ctx.close()
@@ -114,6 +118,10 @@ def run_gpu(size, dtype, steps, warmup, workload="stratified", tile=None):
     ms = (t1 - t0) * 1e3 / steps
     stage_ms = sum(prof[p][0] for p in STAGE_PASSES) / (3 * steps)
     return dict(ms_per_step=ms, value=ncell * steps / (t1 - t0), stage_ms=stage_ms,
+                launch={"tile": launch[0], "persistent": launch[1]},
+                autotune_ms_per_rhs=None if tune is None else {
+                    "%s/%s" % (k[0], "persistent" if k[1] else "grid"): round(v, 4)
+                    for k, v in tune.items()},
                 passes={k: (v[0] / max(v[1], 1), v[1]) for k, v in prof.items() if v[1]},
                 dt_last=dt_last, mass=s_end["mass"], ncell=ncell)
 
@@ -223,7 +231,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-size", type=int, default=128)
     ap.add_argument("--workload", default="stratified", choices=("stratified", "turbulent"))
-    ap.add_argument("--tile", default=None, help="stage kernel tile shape, e.g. 32x8")
+    ap.add_argument("--tile", default=None,
+                    help="stage kernel tile shape, e.g. 32x8 (default: autotuned)")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint and ensemble legs")
     a = ap.parse_args()
     if a.gpus != 1:
@@ -270,10 +279,12 @@ def main():
                      "algorithmic_bytes_per_stage": stage_bytes,
                      "stage_ms": r32["stage_ms"],
                      "passes_ms": {k: round(v[0], 4) for k, v in r32["passes"].items()}},
+        "launch": r32["launch"],
+        "autotune_ms_per_rhs": r32["autotune_ms_per_rhs"],
     }
     if r64 is not None:
         out["fp64"] = {"value": r64["value"], "ms_per_step": r64["ms_per_step"],
-                       "stage_ms": r64["stage_ms"],
+                       "stage_ms": r64["stage_ms"], "launch": r64["launch"],
                        "frac": (2 * stage_bytes / (r64["stage_ms"] * 1e-3) / 1e9) / HBM_PEAK_GBS,
                        "passes_ms": {k: round(v[0], 4) for k, v in r64["passes"].items()}}
         out["fp32_over_fp64"] = r32["value"] / r64["value"]
