@@ -79,8 +79,12 @@ __global__ __launch_bounds__(TX * TY) void zA1(const BoxDev* __restrict__ boxes,
   T* __restrict__ uz_out = ws.arr(WS_UZ);
   using PR = Plane<TX, TY, 5>;
   using PP = Plane<TX, TY, 3>;
+  constexpr int NT = TX * TY;
   __shared__ T sR[PR::NP];
   __shared__ T sPX[PP::NP], sPY[PP::NP], sBX[PP::NP], sBY[PP::NP];
+  // face velocities of the plane, computed once per face: u_x at x-offsets
+  // -2..3 of the own rows, u_y at y-offsets -2..3 of the own columns
+  __shared__ T sUX[PP::NP], sUY[PP::NP];
   __shared__ double sred[TX * TY];
   ZLOOP_BEGIN
   PlaneIdx<TX, TY, 5> i5;
@@ -107,18 +111,21 @@ __global__ __launch_bounds__(TX * TY) void zA1(const BoxDev* __restrict__ boxes,
       pz = f.p[3][o];
       e = f.p[4][o];
       bz = f.p[7][o];
-      T u6[6], v6[6];
-#pragma unroll
-      for (int m = -2; m <= 3; ++m) {
-        const T rx = op6<0, 0, T>([&](int a) { return sR[PR::at(tx + m + a, ty)]; }, T(0));
-        const T ry = op6<0, 0, T>([&](int a) { return sR[PR::at(tx, ty + m + a)]; }, T(0));
-        u6[m + 2] = sPX[PP::at(tx + m, ty)] / rx;
-        v6[m + 2] = sPY[PP::at(tx, ty + m)] / ry;
+      // u_x = p_x / xdn(rho) on x-faces -2..3 of the own rows and u_y on
+      // y-faces -2..3 of the own columns, one face per thread and pass
+      for (int t = threadIdx.x; t < PP::N; t += NT) {
+        const int yy = t / PP::W, xx = t - yy * PP::W;
+        const int x = xx - 3, y = yy - 3;
+        if (y >= 0 && y < TY && x >= -2)
+          sUX[t] = sPX[t] / op6<0, 0, T>([&](int a) { return sR[PR::at(x + a, y)]; }, T(0));
+        if (x >= 0 && x < TX && y >= -2)
+          sUY[t] = sPY[t] / op6<0, 0, T>([&](int a) { return sR[PR::at(x, y + a)]; }, T(0));
       }
-      ubx = op6<0, 1, T>([&](int m) { return u6[m + 2]; }, T(0));
-      uby = op6<0, 1, T>([&](int m) { return v6[m + 2]; }, T(0));
-      dxy = op6<1, 1, T>([&](int m) { return u6[m + 2]; }, g.hxi) +
-            op6<1, 1, T>([&](int m) { return v6[m + 2]; }, g.hyi);
+      __syncthreads();
+      ubx = op6<0, 1, T>([&](int m) { return sUX[PP::at(tx + m, ty)]; }, T(0));
+      uby = op6<0, 1, T>([&](int m) { return sUY[PP::at(tx, ty + m)]; }, T(0));
+      dxy = op6<1, 1, T>([&](int m) { return sUX[PP::at(tx + m, ty)]; }, g.hxi) +
+            op6<1, 1, T>([&](int m) { return sUY[PP::at(tx, ty + m)]; }, g.hyi);
       bbx = op6<0, 1, T>([&](int m) { return sBX[PP::at(tx + m, ty)]; }, T(0));
       bby = op6<0, 1, T>([&](int m) { return sBY[PP::at(tx, ty + m)]; }, T(0));
     }
