@@ -164,13 +164,18 @@ static ZLaunch make_zlaunch(const mhd_ctx* c) {
 }
 
 // Work items of the z-march kernels: tiles of TX x TY columns, z split into
-// chunks of about 128 planes (each chunk recomputes a few planes of lead-in).
+// chunks of about kZChunk planes (each chunk recomputes a few planes of
+// lead-in).
+#ifndef MHD_ZCHUNK
+#define MHD_ZCHUNK 128
+#endif
+static constexpr int kZChunk = MHD_ZCHUNK;
 static void build_items(const mhd_ctx* c, int tile, std::vector<ZItem>& items) {
   const int TX = ztile_x(tile), TY = ztile_y(tile);
   items.clear();
   for (int b = 0; b < (int)c->h_boxes.size(); ++b) {
     const BoxDev& d = c->h_boxes[b];
-    const int nch = std::max(1, (d.nzt + 64) / 128);
+    const int nch = std::max(1, (d.nzt + kZChunk / 2) / kZChunk);
     for (int ch = 0; ch < nch; ++ch) {
       const int z0 = (int)((long long)d.nzt * ch / nch), z1 = (int)((long long)d.nzt * (ch + 1) / nch);
       for (int ty = 0; ty < d.ny; ty += TY)

@@ -63,4 +63,10 @@ def test_null_arguments():
     null8 = (ctypes.c_void_p * 8)()
     assert L.mhd_rhs(None, null8, null8) == lib.MHD_EINVAL
     assert L.mhd_field_elems(None) == -1
+    assert L.mhd_step(None, null8, null8, null8, null8, 1e-3, 1) == lib.MHD_EINVAL
+    assert L.mhd_step_adjoint(None, null8, 1e-3, null8, null8) == lib.MHD_EINVAL
+    assert L.mhd_set_launch(None, 0, 0) == lib.MHD_EINVAL
+    t, m = ctypes.c_int32(), ctypes.c_int32()
+    assert L.mhd_get_launch(None, ctypes.byref(t), ctypes.byref(m)) == lib.MHD_EINVAL
+    assert L.mhd_autotune(None, null8, null8, 1, None) == lib.MHD_EINVAL
     L.mhd_destroy(None)
