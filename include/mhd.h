@@ -131,7 +131,8 @@ typedef struct mhd_ctx mhd_ctx;
 
 /* Create a context for the boxes and parameters in *p, bound to hip_stream
  * (a hipStream_t; NULL = the null stream) on the current device.  Checks
- * every box (n >= 6; walls need ngz >= 5 and ngz == 0 otherwise) and
+ * every box (n >= 6; walls need ngz >= 5 and ngz == 0 otherwise; fewer
+ * than 2^31 cells per box, ghost planes included) and
  * parameter (gamma > 1, mu > 0, viscosity and diffusion coefficients >= 0)
  * and allocates the workspace.  On success *out owns it.                   */
 int mhd_init(const mhd_params* p, void* hip_stream, mhd_ctx** out);

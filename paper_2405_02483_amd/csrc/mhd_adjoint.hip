@@ -367,13 +367,22 @@ VPlan plan_program(const VProgram& P) {
 // Kernels: one thread per cell of the packed boxes (block table as for the
 // other whole-box passes).
 
-#define VM_PROLOGUE                                     \
-  CellIdx ci;                                           \
-  BoxDev bx_;                                           \
-  if (!cell_of(boxes, tab, ci, bx_)) return;            \
-  const Geo<T> g(bx_);                                  \
-  const int i = ci.i, j = ci.j, k = ci.k;               \
-  const long long o = g.at(i, j, k);
+// Pointwise operations need only the element index o; the neighbour
+// operations (stencils, max and mean over three cells) also the cell's
+// coordinates, found with 32-bit arithmetic (boxes hold < 2^31 cells).
+#define VM_PROLOGUE                                                  \
+  const Blk tb_ = tab[blockIdx.x];                                   \
+  if ((int)threadIdx.x >= tb_.n) return;                             \
+  const BoxDev& bx_ = boxes[tb_.box];                                \
+  const unsigned q_ = (unsigned)tb_.start + threadIdx.x;             \
+  const long long o = bx_.off + q_;                                  \
+  auto coords = [&](int& i, int& j, int& k) {                        \
+    const unsigned nx_ = (unsigned)bx_.nx, ny_ = (unsigned)bx_.ny;   \
+    const unsigned qx_ = q_ / nx_, qy_ = qx_ / ny_;                   \
+    i = (int)(q_ - qx_ * nx_);                                       \
+    j = (int)(qx_ - qy_ * ny_);                                      \
+    k = (int)qy_;                                                    \
+  };
 
 namespace {
 
@@ -425,7 +434,13 @@ __global__ __launch_bounds__(kBlock) void k_vm_fwd(const BoxDev* boxes, const Bl
   const T* c = I.c >= 0 ? base + I.c * stride : nullptr;
   T r;
   switch (I.op) {
-    case V_STEN: r = sten(a, g, I.ax, I.fam, I.form, i, j, k); break;
+    case V_STEN: {
+      int i, j, k;
+      coords(i, j, k);
+      const Geo<T> g(bx_);
+      r = sten(a, g, I.ax, I.fam, I.form, i, j, k);
+      break;
+    }
     case V_ADD: r = a[o] + b[o]; break;
     case V_SUB: r = a[o] - b[o]; break;
     case V_MUL: r = a[o] * b[o]; break;
@@ -443,14 +458,21 @@ __global__ __launch_bounds__(kBlock) void k_vm_fwd(const BoxDev* boxes, const Bl
       break;
     }
     case V_MAX3: {
+      int i, j, k;
+      coords(i, j, k);
+      const Geo<T> g(bx_);
       const T lo = along(a, g, I.ax, i, j, k, -1), mid = a[o], hi = along(a, g, I.ax, i, j, k, 1);
       const int s = first_max(lo, mid, hi);
       r = s == 0 ? lo : (s == 1 ? mid : hi);
       break;
     }
-    case V_MEAN3:
+    case V_MEAN3: {
+      int i, j, k;
+      coords(i, j, k);
+      const Geo<T> g(bx_);
       r = (along(a, g, I.ax, i, j, k, -1) + a[o] + along(a, g, I.ax, i, j, k, 1)) / T(3);
       break;
+    }
     case V_FILL:
       r = I.geo == G_HINV ? T(I.k / bx_.hmin) : T(I.k * geo_of(bx_, I.geo));
       break;
@@ -483,6 +505,9 @@ __global__ __launch_bounds__(kBlock) void k_vm_bwd(const BoxDev* boxes, const Bl
   switch (I.op) {
     case V_STEN: {
       // interpolation: S^T = the opposite stagger; derivative: minus it
+      int i, j, k;
+      coords(i, j, k);
+      const Geo<T> g(bx_);
       const T t = sten(yb, g, I.ax, I.fam, 1 - I.form, i, j, k);
       put(ca, 1, I.fam ? -t : t);
       break;
@@ -519,6 +544,9 @@ __global__ __launch_bounds__(kBlock) void k_vm_bwd(const BoxDev* boxes, const Bl
     }
     case V_MAX3: {
       // cell (i) is the hi neighbour of i-1, the middle of i, the lo of i+1
+      int i, j, k;
+      coords(i, j, k);
+      const Geo<T> g(bx_);
       auto v = [&](int m) { return along(a, g, I.ax, i, j, k, m); };
       auto w = [&](int m) { return along(yb, g, I.ax, i, j, k, m); };
       const T vm2 = v(-2), vm1 = v(-1), v0 = a[o], vp1 = v(1), vp2 = v(2);
@@ -529,9 +557,13 @@ __global__ __launch_bounds__(kBlock) void k_vm_bwd(const BoxDev* boxes, const Bl
       put(ca, 1, sum);
       break;
     }
-    case V_MEAN3:
+    case V_MEAN3: {
+      int i, j, k;
+      coords(i, j, k);
+      const Geo<T> g(bx_);
       put(ca, 1, (along(yb, g, I.ax, i, j, k, -1) + yb[o] + along(yb, g, I.ax, i, j, k, 1)) / T(3));
       break;
+    }
     default: break;
   }
 }
@@ -540,7 +572,7 @@ template <class T>
 __global__ __launch_bounds__(kBlock) void k_axpby8(const BoxDev* boxes, const Blk* tab, P8<T> y,
                                                    CP8<T> x, T a, T b) {
   VM_PROLOGUE
-  (void)g;
+  (void)coords;
   for (int v = 0; v < 8; ++v) {
     const T xv = x.p[0] ? x.p[v][o] : T(0);
     y.p[v][o] = (a == T(0) ? T(0) : a * y.p[v][o]) + b * xv;

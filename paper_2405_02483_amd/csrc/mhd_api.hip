@@ -352,6 +352,10 @@ int mhd_init(const mhd_params* p, void* hip_stream, mhd_ctx** out) {
       return fail(nullptr, MHD_EINVAL, where + "unknown bc_z");
     }
     if (!(x.Lx > 0) || !(x.Ly > 0) || !(x.Lz > 0)) { delete c; return fail(nullptr, MHD_EINVAL, where + "box sizes must be > 0"); }
+    if ((long long)x.nx * x.ny * (x.nz + 2LL * x.ngz) >= (1LL << 31)) {
+      delete c;
+      return fail(nullptr, MHD_EINVAL, where + "more than 2^31 - 1 cells (ghost planes included)");
+    }
     c->boxes.push_back(x);
     BoxDev d;
     d.nx = x.nx;

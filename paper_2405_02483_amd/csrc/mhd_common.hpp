@@ -211,12 +211,15 @@ __device__ __forceinline__ bool cell_of(const BoxDev* boxes, const Blk* tab, Cel
   const Blk t = tab[blockIdx.x];
   if ((int)threadIdx.x >= t.n) return false;
   b = boxes[t.box];
-  long long q = t.start + threadIdx.x;
+  // boxes hold fewer than 2^31 cells (checked by mhd_init): 32-bit division
+  unsigned q = (unsigned)t.start + threadIdx.x;
+  const unsigned nx = (unsigned)b.nx, ny = (unsigned)b.ny;
   c.box = t.box;
-  c.i = (int)(q % b.nx);
-  q /= b.nx;
-  c.j = (int)(q % b.ny);
-  c.k = (int)(q / b.ny);
+  const unsigned qx = q / nx;
+  c.i = (int)(q - qx * nx);
+  const unsigned qy = qx / ny;
+  c.j = (int)(qx - qy * ny);
+  c.k = (int)qy;
   return true;
 }
 

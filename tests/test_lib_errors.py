@@ -43,6 +43,7 @@ def _params(**over):
     (dict(boxes=[dict(nx=8, ny=8, nz=6, ngz=7, bc_z=1)]), lib.MHD_EINVAL),
     (dict(boxes=[dict(nx=8, ny=8, nz=8, bc_z=3)]), lib.MHD_EINVAL),
     (dict(boxes=[dict(nx=8, ny=8, nz=8, L=0.0)]), lib.MHD_EINVAL),
+    (dict(boxes=[dict(nx=1300, ny=1300, nz=1300)]), lib.MHD_EINVAL),   # >= 2^31 cells
 ])
 def test_init_rejects_bad_arguments(over, code):
     L = lib.load()
