@@ -60,6 +60,27 @@ def _centre(a, margin):
     return a[:, margin:-margin, margin:-margin]
 
 
+def _term_scale(sub, wbox, prm, crop):
+    """Per field, the sum of the norms of what its right-hand side adds up:
+    each term group (the oracle with one group on), and for rho the three
+    derivatives of -div p separately (they cancel for a solenoidal p)."""
+    scale = [0.0] * 8
+    for t in TERM_GROUPS:
+        gt, pt = grid_params(wbox, prm, terms=t)
+        for v, a in enumerate(O.rhs(tuple(sub), gt, pt)):
+            if v != 0:
+                scale[v] += float(torch.linalg.norm(crop(a)))
+    g, _ = grid_params(wbox, prm)
+    Op = g.ops()
+    for q in (Op.ddxup(sub[1]), Op.ddyup(sub[2]), Op.ddzup(sub[3])):
+        scale[0] += float(torch.linalg.norm(crop(q)))
+    return scale
+
+
+def _scaled_errors(got, want, scale):
+    return [float(torch.linalg.norm(a - b)) / max(sc, 1e-300) for a, b, sc in zip(got, want, scale)]
+
+
 def _windows(seed, count, width):
     rng = np.random.default_rng(seed)
     return [tuple(int(v) for v in rng.integers(0, N, 2)) for _ in range(count)]
@@ -80,16 +101,11 @@ def test_rhs_sampled_columns_512(state, launch):
         sub, wbox = _window(f, box, x0, y0, width)
         g, p = grid_params(wbox, prm)
         want = [_centre(a, RHS_MARGIN) for a in O.rhs(tuple(sub), g, p)]
-        scale = [0.0] * 8
-        for t in TERM_GROUPS:
-            gt, pt = grid_params(wbox, prm, terms=t)
-            for v, a in enumerate(O.rhs(tuple(sub), gt, pt)):
-                scale[v] += float(torch.linalg.norm(_centre(a, RHS_MARGIN)))
+        scale = _term_scale(sub, wbox, prm, lambda a: _centre(a, RHS_MARGIN))
         ix = torch.from_numpy((np.arange(RHS_MARGIN, width - RHS_MARGIN) + x0) % N)
         iy = torch.from_numpy((np.arange(RHS_MARGIN, width - RHS_MARGIN) + y0) % N)
         got = [t.view(nzt, N, N)[:, iy.cuda()][:, :, ix.cuda()].cpu().double() for t in F]
-        errs = [float(torch.linalg.norm(a - b)) / max(sc, 1e-300)
-                for a, b, sc in zip(got, want, scale)]
+        errs = _scaled_errors(got, want, scale)
         print((x0, y0), ["%.1e" % e for e in errs], "plain", ["%.1e" % e for e in rel_errors(got, want)])
         assert max(errs) < 1e-4, ((x0, y0), errs)
     ctx.close()
@@ -121,4 +137,71 @@ def test_step_sampled_columns_and_invariants_512(state):
         errs = rel_errors(got, want)
         print((x0, y0), ["%.1e" % e for e in errs])
         assert max(errs) < 1e-5, ((x0, y0), errs)
+    ctx.close()
+
+
+# ---------------------------------------------------------------------------
+# The 256^3 periodic turbulent box (seed 2) in float32 and float64: one
+# right-hand side and one RK step, checked on cubic windows (periodic in all
+# three axes, so the window is cut along z too).  The momenta of this state
+# are solenoidal, so -div p is a residual of derivatives about 10^4 times
+# larger; right-hand sides are measured against the size of what is summed
+# (as for the stratified box), the stepped state by plain relative L2.
+
+M2 = 256
+
+
+@pytest.fixture(scope="module")
+def turb256():
+    return inputs.turbulent(n=M2, seed=2)
+
+
+def _cube(f, box, c, width):
+    idx = [(np.arange(width) + c[a]) % M2 for a in range(3)]
+    sub = [torch.from_numpy(np.ascontiguousarray(np.asarray(a)[idx[2]][:, idx[1]][:, :, idx[0]]))
+           .to(torch.float64) for a in f]
+    h = box["Lx"] / box["nx"]
+    wbox = dict(box, nx=width, ny=width, nz=width, Lx=h * width, Ly=h * width, Lz=h * width)
+    return sub, wbox, idx
+
+
+def _gather(t, idx, margin, width):
+    sel = [torch.from_numpy(i[margin:width - margin]).cuda() for i in idx]
+    return t.view(M2, M2, M2)[sel[2]][:, sel[1]][:, :, sel[0]].cpu().double()
+
+
+def _core(a, m):
+    return a[m:-m, m:-m, m:-m]
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_turbulent_256_rhs_and_step_sampled(turb256, dtype):
+    from paper_2405_02483_amd.lib import Context
+    f, box, prm = turb256
+    ctx = Context(box, prm, dtype=dtype)
+    fd = ctx.upload([f])
+    F = ctx.rhs(fd)
+    tol_rhs, tol_step = (1e-4, 1e-5) if dtype == torch.float32 else (1e-12, 1e-12)
+    rng = np.random.default_rng(53)
+    width = 2 * RHS_MARGIN + 8
+    for _ in range(3):
+        c = [int(v) for v in rng.integers(0, M2, 3)]
+        sub, wbox, idx = _cube(f, box, c, width)
+        g, p = grid_params(wbox, prm)
+        want = [_core(a, RHS_MARGIN) for a in O.rhs(tuple(sub), g, p)]
+        got = [_gather(t, idx, RHS_MARGIN, width) for t in F]
+        errs = _scaled_errors(got, want, _term_scale(sub, wbox, prm, lambda a: _core(a, RHS_MARGIN)))
+        print("rhs", dtype, c, ["%.1e" % e for e in errs])
+        assert max(errs) < tol_rhs, (c, errs)
+    ctx.step(fd, 0.0, 1)                       # Courant dt on the device
+    dt = ctx.last_dt()
+    width = 2 * 36 + 12                        # one step reaches 3 x 11 cells
+    c = [int(v) for v in rng.integers(0, M2, 3)]
+    sub, wbox, idx = _cube(f, box, c, width)
+    g, p = grid_params(wbox, prm)
+    want = [_core(a, 36) for a in O.step(tuple(sub), g, p, dt, 1)]
+    got = [_gather(t, idx, 36, width) for t in fd]
+    errs = rel_errors(got, want)
+    print("step", dtype, c, ["%.1e" % e for e in errs])
+    assert max(errs) < tol_step, (c, errs)
     ctx.close()
