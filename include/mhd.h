@@ -178,6 +178,13 @@ int mhd_step(mhd_ctx* ctx, void* const f[8], void* const tmp1[8],
 int mhd_step_adjoint(mhd_ctx* ctx, void* const f_n[8], double dt,
                      void* const gbar_in[8], void* const gbar_out[8]);
 
+/* Discrete adjoint of mhd_rhs: fbar = (dF/df)^T wbar at the state f (the
+ * same non-smooth conventions as mhd_step_adjoint).  Periodic boxes only
+ * (MHD_EUNSUPPORTED with walls).  f and wbar are not modified; fbar must
+ * not overlap them.  Allocates the adjoint workspace on first use.        */
+int mhd_rhs_adjoint(mhd_ctx* ctx, void* const f[8], void* const wbar[8],
+                    void* const fbar[8]);
+
 /* Float64 totals, diagnostics and the Courant time step (eq. courantcond)
  * of state f over the interior of all boxes; writes *out (host memory) and
  * waits for the stream.  dfdt may be NULL; if given (the time derivatives of

@@ -604,6 +604,51 @@ static int do_adjoint(mhd_ctx* c, void* const fn[8], double dt, void* const gin[
   return check_launch(c, "mhd_step_adjoint launch");
 }
 
+// (dF/df)^T wbar at the state f (periodic boxes): the program's forward run
+// at f, its reverse sweep seeded with wbar.
+template <class T>
+static int do_rhs_adjoint(mhd_ctx* c, void* const f[8], void* const wbar[8],
+                          void* const fbar[8]) {
+  if (!c->prog) {
+    try {
+      c->prog = new VPlan(plan_program(build_rhs_program(c->p)));
+    } catch (...) {
+      return fail(c, MHD_ENOMEM, "adjoint program");
+    }
+  }
+  const VPlan& P = *c->prog;
+  const long long n = c->nelem;
+  const size_t need = ((size_t)P.nval + P.ncot + 25) * (size_t)n * c->esize;
+  if (c->adj_bytes < need) {
+    (void)hipFree(c->adj);
+    c->adj = nullptr;
+    c->adj_bytes = 0;
+    if (hipMalloc(&c->adj, need) != hipSuccess) return fail(c, MHD_ENOMEM, "adjoint workspace");
+    c->adj_bytes = need;
+  }
+  T* base = static_cast<T*>(c->adj);
+  T* cbase = base + (long long)P.nval * n;
+  const size_t bytes = (size_t)n * c->esize;
+  const Launch L = make_launch(c);
+  L.at(PASS_ADJOINT);
+  VLaunch V{c->d_boxes, c->d_tab, c->nblk, c->stream};
+  hipError_t e = hipSuccess;
+  for (int v = 0; v < 8 && e == hipSuccess; ++v)
+    e = hipMemcpyAsync(base + (long long)v * n, f[v], bytes, hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess) vm_forward<T>(V, P, base, n);
+  for (int v = 0; v < 8 && e == hipSuccess; ++v)
+    e = hipMemcpyAsync(cbase + (long long)P.cout[v] * n, wbar[v], bytes, hipMemcpyDeviceToDevice,
+                       c->stream);
+  if (e == hipSuccess) vm_backward<T>(V, P, base, cbase, n);
+  for (int v = 0; v < 8 && e == hipSuccess; ++v)
+    e = P.cin[v] >= 0 ? hipMemcpyAsync(fbar[v], cbase + (long long)P.cin[v] * n, bytes,
+                                       hipMemcpyDeviceToDevice, c->stream)
+                      : hipMemsetAsync(fbar[v], 0, bytes, c->stream);
+  L.at(PASS_END);
+  if (e != hipSuccess) return fail(c, MHD_EHIP, hipGetErrorString(e));
+  return check_launch(c, "mhd_rhs_adjoint launch");
+}
+
 template <class T>
 static int do_reduce(mhd_ctx* c, void* const f[8], void* const dfdt[8], mhd_stats* out) {
   const Launch L = make_launch(c);
@@ -722,6 +767,20 @@ int mhd_step_adjoint(mhd_ctx* c, void* const f_n[8], double dt, void* const gin[
       if (gin[a] == gout[b] || f_n[a] == gout[b]) return fail(c, MHD_EINVAL, "gbar_out overlaps an input");
   return c->p.dtype == MHD_F32 ? do_adjoint<float>(c, f_n, dt, gin, gout)
                                : do_adjoint<double>(c, f_n, dt, gin, gout);
+}
+
+int mhd_rhs_adjoint(mhd_ctx* c, void* const f[8], void* const wbar[8], void* const fbar[8]) {
+  if (!c) return fail(nullptr, MHD_EINVAL, "ctx is NULL");
+  int rc;
+  if ((rc = check8(c, f, "f")) || (rc = check8(c, wbar, "wbar")) || (rc = check8(c, fbar, "fbar")))
+    return rc;
+  for (const auto& b : c->boxes)
+    if (b.bc_z != MHD_BC_PERIODIC) return fail(c, MHD_EUNSUPPORTED, "adjoint supports periodic boxes only");
+  for (int a = 0; a < 8; ++a)
+    for (int b = 0; b < 8; ++b)
+      if (fbar[b] == f[a] || fbar[b] == wbar[a]) return fail(c, MHD_EINVAL, "fbar overlaps an input");
+  return c->p.dtype == MHD_F32 ? do_rhs_adjoint<float>(c, f, wbar, fbar)
+                               : do_rhs_adjoint<double>(c, f, wbar, fbar);
 }
 
 int mhd_profile(mhd_ctx* c, int32_t enable) {

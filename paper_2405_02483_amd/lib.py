@@ -20,7 +20,7 @@ __all__ = [
     "mhd_init", "mhd_destroy", "mhd_last_error", "mhd_field_elems",
     "mhd_box_offset", "mhd_rhs", "mhd_step", "mhd_step_adjoint",
     "mhd_reductions", "mhd_profile", "mhd_profile_read", "mhd_last_dt", "mhd_set_tile",
-    "mhd_set_launch", "mhd_get_launch", "mhd_autotune",
+    "mhd_set_launch", "mhd_get_launch", "mhd_autotune", "mhd_rhs_adjoint",
     "PASS_NAMES", "TILES", "Context",
 ]
 
@@ -121,6 +121,8 @@ def load():
     L.mhd_last_dt.restype = ctypes.c_int
     L.mhd_set_tile.argtypes = [vp, i32]
     L.mhd_set_tile.restype = ctypes.c_int
+    L.mhd_rhs_adjoint.argtypes = [vp, _P8, _P8, _P8]
+    L.mhd_rhs_adjoint.restype = ctypes.c_int
     L.mhd_set_launch.argtypes = [vp, i32, i32]
     L.mhd_set_launch.restype = ctypes.c_int
     L.mhd_get_launch.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
@@ -222,6 +224,11 @@ def mhd_last_dt(ctx):
 
 def mhd_set_tile(ctx, tile):
     _check(load().mhd_set_tile(ctx, int(tile)), ctx)
+
+
+def mhd_rhs_adjoint(ctx, f, wbar, fbar, *, dtype, n):
+    _check(load().mhd_rhs_adjoint(ctx, _ptrs(f, n, dtype, "f"), _ptrs(wbar, n, dtype, "wbar"),
+                                  _ptrs(fbar, n, dtype, "fbar")), ctx)
 
 
 def mhd_set_launch(ctx, tile, persistent):
@@ -346,6 +353,11 @@ class Context:
         gbar_out = gbar_out if gbar_out is not None else self.empty()
         mhd_step_adjoint(self.ctx, f_n, dt, gbar_in, gbar_out, dtype=self.dtype, n=self.n)
         return gbar_out
+
+    def rhs_adjoint(self, f, wbar, fbar=None):
+        fbar = fbar if fbar is not None else self.empty()
+        mhd_rhs_adjoint(self.ctx, f, wbar, fbar, dtype=self.dtype, n=self.n)
+        return fbar
 
     def last_dt(self):
         return mhd_last_dt(self.ctx)

@@ -69,6 +69,46 @@ def test_step_adjoint_matches_oracle_f64(case):
     assert max(errs) < TOL_ADJ64, errs
 
 
+@pytest.mark.parametrize("case", ["ragged", "min6"])
+def test_rhs_adjoint_matches_oracle_f64(case):
+    if case == "ragged":
+        f, box, prm = _ragged()
+    else:
+        f, box, prm = inputs.turbulent(n=6, seed=4, kmax=2.0)
+    g, p = grid_params(box, prm)
+    w = _randn_like(f, 13)
+    ctx = _ctx(box, prm, torch.float64)
+    out = ctx.rhs_adjoint(ctx.upload([f]), ctx.upload([w]))
+    want = O.rhs_vjp(to_cpu64(f), g, p, to_cpu64(w))
+    errs = rel_errors(ctx.box_view(out, 0), want)
+    print(case, ["%.2e" % e for e in errs])
+    assert max(errs) < TOL_ADJ64, errs
+    ctx.close()
+
+
+def test_rhs_adjoint_is_the_transpose_of_finite_differences_f32():
+    """<w, J v> (central differences of mhd_rhs in float64) against
+    <J^T w, v> from the float32 and float64 adjoints."""
+    f, box, prm = _ragged()
+    w = _randn_like(f, 14)
+    v = _randn_like(f, 15)
+    c64 = _ctx(box, prm, torch.float64)
+    x = c64.upload([f])
+    vd = c64.upload([v])
+    wd = c64.upload([w])
+    eps = 1e-7 * math.sqrt(_dot(x, x) / _dot(vd, vd))
+    xp = [a + eps * b for a, b in zip(x, vd)]
+    xm = [a - eps * b for a, b in zip(x, vd)]
+    fd = (_dot(wd, c64.rhs(xp)) - _dot(wd, c64.rhs(xm))) / (2 * eps)
+    for dtype, tol in ((torch.float64, 1e-6), (torch.float32, 1e-4)):
+        ctx = c64 if dtype == torch.float64 else _ctx(box, prm, dtype)
+        ad = _dot(ctx.rhs_adjoint(ctx.upload([f]), ctx.upload([w])), ctx.upload([v]))
+        assert abs(ad - fd) <= tol * abs(fd), (dtype, ad, fd)
+        if ctx is not c64:
+            ctx.close()
+    c64.close()
+
+
 TERM_SETS = {
     "cont": O.T_CONT, "adv": O.T_ADV, "pres": O.T_PRES, "visc": O.T_VISC,
     "lorentz": O.T_LORENTZ, "induct": O.T_INDUCT, "resist": O.T_RESIST,
