@@ -203,7 +203,7 @@ def run_ensemble(nbox=96, nsteps=20, ncheck=4):
                                     for k, v in tune.items()}}
 
 
-def cpu_baseline(n=192, nsteps=2):
+def cpu_baseline(n=192, nsteps=1):
     """The float64 CPU oracle on a bounded sample of the same workload."""
     import torch
     import oracle as O
