@@ -278,7 +278,7 @@ VProgram build_rhs_program(const mhd_params& p) {
 // Storage plan.
 VPlan plan_program(const VProgram& P) {
   const int n = (int)P.code.size(), S = P.nslots;
-  // values some transpose reads: never recycled
+  // values some transpose reads: stored, never recycled
   std::vector<char> keep(S, 0);
   for (int s = 0; s < 8; ++s) keep[s] = 1;
   for (const VInstr& I : P.code) {
@@ -291,23 +291,55 @@ VPlan plan_program(const VProgram& P) {
       default: break;
     }
   }
-  std::vector<int> last(S, -1);
-  for (int q = 0; q < n; ++q)
+  std::vector<int> last(S, -1), prod(S, -1);
+  for (int q = 0; q < n; ++q) {
+    prod[P.code[q].out] = q;
     for (int x : {P.code[q].a, P.code[q].b, P.code[q].c})
       if (x >= 0) last[x] = q;
+  }
+  // groups: a neighbour operation opens one; pointwise operations join
   VPlan R;
+  std::vector<int> gid(n), gend;
+  for (int q = 0; q < n; ++q) {
+    const int op = P.code[q].op;
+    const bool nb = op == V_STEN || op == V_MAX3 || op == V_MEAN3;
+    if (q == 0 || nb || q - R.groups.back().first == kGroupMax) {
+      if (!R.groups.empty()) gend.push_back(q);
+      R.groups.push_back({q, 0});
+    }
+    R.groups.back().count++;
+    gid[q] = (int)R.groups.size() - 1;
+  }
+  gend.push_back(n);
+  // a result is stored if a transpose or a later group reads it
+  std::vector<char> store(S, 0);
+  for (int s = 0; s < 8; ++s) store[s] = 1;
+  for (int q = 0; q < n; ++q) {
+    const int o = P.code[q].out;
+    store[o] = keep[o] || (last[o] >= gend[gid[q]]);
+  }
+  // value slots for the stored results; a slot is free again at the end of
+  // the group of its last reader (a group's first operation may read it at
+  // neighbouring cells while other cells of the group already write)
   std::vector<int> vphys(S, -1), freev;
+  std::vector<std::vector<int>> release(R.groups.size());
   for (int x = 0; x < 8; ++x) vphys[x] = x;
   R.nval = 8;
   R.steps.resize(n);
+  R.fused.resize(n);
   for (int q = 0; q < n; ++q) {
     const VInstr& I = P.code[q];
-    int ph;
-    if (!freev.empty()) {
-      ph = freev.back();
-      freev.pop_back();
-    } else {
-      ph = R.nval++;
+    if (q == R.groups[gid[q]].first && gid[q] > 0) {
+      for (int ph : release[gid[q] - 1]) freev.push_back(ph);
+    }
+    int ph = -1;
+    if (store[I.out]) {
+      if (!freev.empty()) {
+        ph = freev.back();
+        freev.pop_back();
+      } else {
+        ph = R.nval++;
+      }
     }
     vphys[I.out] = ph;
     VInstr F = I;
@@ -316,16 +348,23 @@ VPlan plan_program(const VProgram& P) {
     F.b = I.b >= 0 ? vphys[I.b] : -1;
     F.c = I.c >= 0 ? vphys[I.c] : -1;
     R.steps[q].f = F;
+    VFused& G = R.fused[q];
+    G.f = F;
+    const int g0 = R.groups[gid[q]].first;
+    auto local = [&](int x) { return (x >= 0 && prod[x] >= g0 && prod[x] < q) ? prod[x] - g0 : -1; };
+    G.la = local(I.a);
+    G.lb = local(I.b);
+    G.lc = local(I.c);
+    G.pad = 0;
     int done[3] = {-1, -1, -1}, nd = 0;
     for (int x : {I.a, I.b, I.c}) {
-      if (x < 8 || keep[x] || last[x] != q) continue;
+      if (x < 8 || keep[x] || last[x] != q || vphys[x] < 0) continue;
       bool dup = false;
       for (int m = 0; m < nd; ++m) dup |= done[m] == x;
       if (dup) continue;
       done[nd++] = x;
-      freev.push_back(vphys[x]);
+      release[gid[q]].push_back(vphys[x]);
     }
-    if (!keep[I.out] && last[I.out] < 0) freev.push_back(ph);
   }
   // cotangents, allocated in the reverse sweep
   std::vector<int> cphys(S, -1), freec;
@@ -337,10 +376,7 @@ VPlan plan_program(const VProgram& P) {
     }
     return R.ncot++;
   };
-  for (int v = 0; v < 8; ++v) {
-    R.vout[v] = vphys[P.out[v]];
-    R.cout[v] = cphys[P.out[v]] = alloc();
-  }
+  for (int v = 0; v < 8; ++v) R.cout[v] = cphys[P.out[v]] = alloc();
   for (int q = n - 1; q >= 0; --q) {
     const VInstr& I = P.code[q];
     VStep& st = R.steps[q];
@@ -425,60 +461,80 @@ template <class T> __device__ __forceinline__ int first_max(T lo, T mid, T hi) {
 
 }  // namespace
 
+// One group of the forward run: the first operation may read neighbouring
+// cells from memory; the rest are pointwise, with operands from the group's
+// register file (LDS, one column per thread) or from memory.
 template <class T>
-__global__ __launch_bounds__(kBlock) void k_vm_fwd(const BoxDev* boxes, const Blk* tab, VInstr I,
-                                                   T* base, long long stride) {
+__global__ __launch_bounds__(kBlock) void k_vm_group(const BoxDev* boxes, const Blk* tab,
+                                                     const VFused* __restrict__ code, int first,
+                                                     int count, T* base, long long stride) {
+  __shared__ T regs[kGroupMax * kBlock];
   VM_PROLOGUE
-  const T* a = I.a >= 0 ? base + I.a * stride : nullptr;
-  const T* b = I.b >= 0 ? base + I.b * stride : nullptr;
-  const T* c = I.c >= 0 ? base + I.c * stride : nullptr;
-  T r;
-  switch (I.op) {
-    case V_STEN: {
-      int i, j, k;
-      coords(i, j, k);
-      const Geo<T> g(bx_);
-      r = sten(a, g, I.ax, I.fam, I.form, i, j, k);
-      break;
+  auto R = [&](int r) -> T& { return regs[r * kBlock + threadIdx.x]; };
+  for (int jj = 0; jj < count; ++jj) {
+    const VFused G = code[first + jj];
+    const VInstr& I = G.f;
+    auto opnd = [&](int slot, int loc) -> T { return loc >= 0 ? R(loc) : base[slot * stride + o]; };
+    T r;
+    switch (I.op) {
+      case V_STEN: {
+        int i, j, k;
+        coords(i, j, k);
+        const Geo<T> g(bx_);
+        r = sten(base + I.a * stride, g, I.ax, I.fam, I.form, i, j, k);
+        break;
+      }
+      case V_MAX3: {
+        int i, j, k;
+        coords(i, j, k);
+        const Geo<T> g(bx_);
+        const T* a = base + I.a * stride;
+        const T lo = along(a, g, I.ax, i, j, k, -1), mid = a[o], hi = along(a, g, I.ax, i, j, k, 1);
+        const int s = first_max(lo, mid, hi);
+        r = s == 0 ? lo : (s == 1 ? mid : hi);
+        break;
+      }
+      case V_MEAN3: {
+        int i, j, k;
+        coords(i, j, k);
+        const Geo<T> g(bx_);
+        const T* a = base + I.a * stride;
+        r = (along(a, g, I.ax, i, j, k, -1) + a[o] + along(a, g, I.ax, i, j, k, 1)) / T(3);
+        break;
+      }
+      case V_ADD: r = opnd(I.a, G.la) + opnd(I.b, G.lb); break;
+      case V_SUB: r = opnd(I.a, G.la) - opnd(I.b, G.lb); break;
+      case V_MUL: r = opnd(I.a, G.la) * opnd(I.b, G.lb); break;
+      case V_DIV: r = opnd(I.a, G.la) / opnd(I.b, G.lb); break;
+      case V_SCALE: r = T(I.k * geo_of(bx_, I.geo)) * opnd(I.a, G.la); break;
+      case V_DIVC: r = opnd(I.a, G.la) / T(I.k); break;
+      case V_SQRT: r = sqrt(opnd(I.a, G.la)); break;
+      case V_LOG: r = log(opnd(I.a, G.la)); break;
+      case V_EXP: r = exp(opnd(I.a, G.la)); break;
+      case V_RELU: {
+        const T x = opnd(I.a, G.la);
+        r = x > T(0) ? x : T(0);
+        break;
+      }
+      case V_FLOOR: {
+        const T x = opnd(I.a, G.la);
+        r = x > T(I.k) ? x : T(I.k);
+        break;
+      }
+      case V_NORM3: {
+        const T x = opnd(I.a, G.la), y = opnd(I.b, G.lb), z = opnd(I.c, G.lc);
+        const T s = x * x + y * y + z * z;
+        r = s > T(0) ? sqrt(s) : T(0);
+        break;
+      }
+      case V_FILL:
+        r = I.geo == G_HINV ? T(I.k / bx_.hmin) : T(I.k * geo_of(bx_, I.geo));
+        break;
+      default: r = T(0); break;
     }
-    case V_ADD: r = a[o] + b[o]; break;
-    case V_SUB: r = a[o] - b[o]; break;
-    case V_MUL: r = a[o] * b[o]; break;
-    case V_DIV: r = a[o] / b[o]; break;
-    case V_SCALE: r = T(I.k * geo_of(bx_, I.geo)) * a[o]; break;
-    case V_DIVC: r = a[o] / T(I.k); break;
-    case V_SQRT: r = sqrt(a[o]); break;
-    case V_LOG: r = log(a[o]); break;
-    case V_EXP: r = exp(a[o]); break;
-    case V_RELU: r = a[o] > T(0) ? a[o] : T(0); break;
-    case V_FLOOR: r = a[o] > T(I.k) ? a[o] : T(I.k); break;
-    case V_NORM3: {
-      const T s = a[o] * a[o] + b[o] * b[o] + c[o] * c[o];
-      r = s > T(0) ? sqrt(s) : T(0);
-      break;
-    }
-    case V_MAX3: {
-      int i, j, k;
-      coords(i, j, k);
-      const Geo<T> g(bx_);
-      const T lo = along(a, g, I.ax, i, j, k, -1), mid = a[o], hi = along(a, g, I.ax, i, j, k, 1);
-      const int s = first_max(lo, mid, hi);
-      r = s == 0 ? lo : (s == 1 ? mid : hi);
-      break;
-    }
-    case V_MEAN3: {
-      int i, j, k;
-      coords(i, j, k);
-      const Geo<T> g(bx_);
-      r = (along(a, g, I.ax, i, j, k, -1) + a[o] + along(a, g, I.ax, i, j, k, 1)) / T(3);
-      break;
-    }
-    case V_FILL:
-      r = I.geo == G_HINV ? T(I.k / bx_.hmin) : T(I.k * geo_of(bx_, I.geo));
-      break;
-    default: r = T(0); break;
+    R(jj) = r;
+    if (I.out >= 0) base[I.out * stride + o] = r;
   }
-  base[I.out * stride + o] = r;
 }
 
 // Transposes.  Each thread owns the cotangents of its own cell, so the
@@ -579,10 +635,11 @@ __global__ __launch_bounds__(kBlock) void k_axpby8(const BoxDev* boxes, const Bl
   }
 }
 
-template <class T> void vm_forward(const VLaunch& L, const VPlan& P, T* base, long long stride) {
-  for (const VStep& S : P.steps)
-    hipLaunchKernelGGL(k_vm_fwd<T>, dim3(L.nblk), dim3(kBlock), 0, L.stream, L.boxes, L.tab, S.f, base,
-                       stride);
+template <class T>
+void vm_forward(const VLaunch& L, const VPlan& P, const VFused* d_fused, T* base, long long stride) {
+  for (const VGroup& G : P.groups)
+    hipLaunchKernelGGL(k_vm_group<T>, dim3(L.nblk), dim3(kBlock), 0, L.stream, L.boxes, L.tab, d_fused,
+                       G.first, G.count, base, stride);
 }
 
 template <class T>
@@ -599,8 +656,8 @@ template <class T> void vm_axpby8(const VLaunch& L, P8<T> y, CP8<T> x, double a,
                      T(b));
 }
 
-template void vm_forward<float>(const VLaunch&, const VPlan&, float*, long long);
-template void vm_forward<double>(const VLaunch&, const VPlan&, double*, long long);
+template void vm_forward<float>(const VLaunch&, const VPlan&, const VFused*, float*, long long);
+template void vm_forward<double>(const VLaunch&, const VPlan&, const VFused*, double*, long long);
 template void vm_backward<float>(const VLaunch&, const VPlan&, const float*, float*, long long);
 template void vm_backward<double>(const VLaunch&, const VPlan&, const double*, double*, long long);
 template void vm_axpby8<float>(const VLaunch&, P8<float>, CP8<float>, double, double);

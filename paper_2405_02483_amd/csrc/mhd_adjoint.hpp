@@ -68,11 +68,27 @@ struct VStep {
   int over;                  // bit 0/1/2: the contribution to ca/cb/cc overwrites
 };
 
+// The forward run in groups, one launch each: a group starts with any
+// operation (the only one that may read neighbouring cells) and continues
+// with pointwise operations, up to kGroupMax.  Results made inside a group
+// pass through a per-thread register file in LDS and are stored to their
+// value slot only when a later group or a transpose reads them.
+constexpr int kGroupMax = 16;
+
+struct VFused {
+  VInstr f;                  // value slots (f.out: -1 if the result is not stored)
+  int la, lb, lc;            // register of each operand made in this group (-1: memory)
+  int pad;
+};
+
+struct VGroup { int first, count; };
+
 struct VPlan {
-  std::vector<VStep> steps;
+  std::vector<VStep> steps;  // per operation: value slots of what the transposes read
+  std::vector<VFused> fused; // the same operations for the grouped forward run
+  std::vector<VGroup> groups;
   int nval = 0;              // value slots (0..7: the state)
   int ncot = 0;              // cotangent slots
-  int vout[8];               // value slot of each output (unused by the sweeps)
   int cout[8];               // cotangent slot seeded with each output's cotangent
   int cin[8];                // cotangent slot of each input (-1: the input is unused)
 };
@@ -86,11 +102,13 @@ struct VLaunch {
   hipStream_t stream;
 };
 
-// Forward: value slots base + s * stride (slots 0..7 filled by the caller).
+// Forward: value slots base + s * stride (slots 0..7 filled by the caller);
+// d_fused is plan.fused in device memory.
 // Backward: cotangent slots cbase + s * stride, with the outputs' slots
 // (plan.cout) seeded by the caller; afterwards slot plan.cin[v] holds
 // (dF/df_v)^T of the seed.
-template <class T> void vm_forward(const VLaunch& L, const VPlan& plan, T* base, long long stride);
+template <class T>
+void vm_forward(const VLaunch& L, const VPlan& plan, const VFused* d_fused, T* base, long long stride);
 template <class T>
 void vm_backward(const VLaunch& L, const VPlan& plan, const T* base, T* cbase, long long stride);
 

@@ -40,6 +40,7 @@ struct mhd_ctx {
   void* adj = nullptr;             // adjoint workspace (allocated on first use)
   size_t adj_bytes = 0;
   VPlan* prog = nullptr;           // the right-hand side as a program (adjoint)
+  VFused* d_fused = nullptr;       // prog->fused in device memory
   // z-march stage kernels: work items, tile shape, Courant partials, dt
   ZItem* d_items = nullptr;
   int nitems = 0;
@@ -303,6 +304,7 @@ void mhd_destroy(mhd_ctx* c) {
   (void)hipFree(c->d_part);
   (void)hipFree(c->adj);
   delete c->prog;
+  (void)hipFree(c->d_fused);
   (void)hipFree(c->d_items);
   (void)hipFree(c->d_cpart);
   (void)hipFree(c->d_dt);
@@ -517,6 +519,28 @@ static int do_step(mhd_ctx* c, void* const f[8], void* const t1[8], void* const 
   return check_launch(c, "mhd_step launch");
 }
 
+// The right-hand side as a planned program (built once per context).
+static int ensure_program(mhd_ctx* c) {
+  if (c->prog) return MHD_OK;
+  VPlan* P = nullptr;
+  try {
+    P = new VPlan(plan_program(build_rhs_program(c->p)));
+  } catch (...) {
+    return fail(c, MHD_ENOMEM, "adjoint program");
+  }
+  const size_t bytes = sizeof(VFused) * P->fused.size();
+  hipError_t e = hipMalloc(&c->d_fused, bytes);
+  if (e == hipSuccess) e = hipMemcpy(c->d_fused, P->fused.data(), bytes, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(c->d_fused);
+    c->d_fused = nullptr;
+    delete P;
+    return fail(c, MHD_ENOMEM, "adjoint program upload");
+  }
+  c->prog = P;
+  return MHD_OK;
+}
+
 // Adjoint of one RK step (dt fixed).  With f_s the stage inputs, U_s the
 // 2N-storage derivative and F_s = F(f_s):
 //   U_s = alpha_s U_{s-1} + F_s,  f_{s+1} = f_s + beta_s dt U_s,
@@ -528,13 +552,7 @@ static int do_step(mhd_ctx* c, void* const f[8], void* const t1[8], void* const 
 template <class T>
 static int do_adjoint(mhd_ctx* c, void* const fn[8], double dt, void* const gin[8],
                       void* const gout[8]) {
-  if (!c->prog) {
-    try {
-      c->prog = new VPlan(plan_program(build_rhs_program(c->p)));
-    } catch (...) {
-      return fail(c, MHD_ENOMEM, "adjoint program");
-    }
-  }
+  if (int rc = ensure_program(c)) return rc;
   const VPlan& P = *c->prog;
   const long long n = c->nelem;
   const size_t narr = (size_t)P.nval + P.ncot + 25;
@@ -585,7 +603,7 @@ static int do_adjoint(mhd_ctx* c, void* const fn[8], double dt, void* const gin[
     for (int v = 0; v < 8 && e == hipSuccess; ++v)
       e = hipMemcpyAsync(base + (long long)v * n, fs.p[v], bytes, hipMemcpyDeviceToDevice, c->stream);
     if (e != hipSuccess) break;
-    vm_forward<T>(V, P, base, n);
+    vm_forward<T>(V, P, c->d_fused, base, n);
     for (int v = 0; v < 8 && e == hipSuccess; ++v)
       e = hipMemcpyAsync(cbase + (long long)P.cout[v] * n, Ub.p[v], bytes, hipMemcpyDeviceToDevice,
                          c->stream);
@@ -609,13 +627,7 @@ static int do_adjoint(mhd_ctx* c, void* const fn[8], double dt, void* const gin[
 template <class T>
 static int do_rhs_adjoint(mhd_ctx* c, void* const f[8], void* const wbar[8],
                           void* const fbar[8]) {
-  if (!c->prog) {
-    try {
-      c->prog = new VPlan(plan_program(build_rhs_program(c->p)));
-    } catch (...) {
-      return fail(c, MHD_ENOMEM, "adjoint program");
-    }
-  }
+  if (int rc = ensure_program(c)) return rc;
   const VPlan& P = *c->prog;
   const long long n = c->nelem;
   const size_t need = ((size_t)P.nval + P.ncot + 25) * (size_t)n * c->esize;
@@ -635,7 +647,7 @@ static int do_rhs_adjoint(mhd_ctx* c, void* const f[8], void* const wbar[8],
   hipError_t e = hipSuccess;
   for (int v = 0; v < 8 && e == hipSuccess; ++v)
     e = hipMemcpyAsync(base + (long long)v * n, f[v], bytes, hipMemcpyDeviceToDevice, c->stream);
-  if (e == hipSuccess) vm_forward<T>(V, P, base, n);
+  if (e == hipSuccess) vm_forward<T>(V, P, c->d_fused, base, n);
   for (int v = 0; v < 8 && e == hipSuccess; ++v)
     e = hipMemcpyAsync(cbase + (long long)P.cout[v] * n, wbar[v], bytes, hipMemcpyDeviceToDevice,
                        c->stream);
