@@ -126,18 +126,21 @@ def run_gpu(size, dtype, steps, warmup, workload="stratified", tile=None):
                 dt_last=dt_last, mass=s_end["mass"], ncell=ncell)
 
 
-def run_adjoint(n=128, nsteps=40, ncheck=4, dtype_name="f32"):
+def run_adjoint(n=128, nsteps=40, ncheck=None, dtype_name="f32"):
     """Gradient of a linear functional of the state after nsteps RK steps on
-    the n^3 turbulent box (seed 4): forward time vs checkpointed backward."""
+    the n^3 turbulent box (seed 4): forward time vs checkpointed backward.
+    ncheck None: as many checkpoints as half the free device memory holds."""
     import torch
     from paper_2405_02483_amd import inputs
     from paper_2405_02483_amd.lib import Context
-    from paper_2405_02483_amd.rollout import reversal_cost, rollout
+    from paper_2405_02483_amd.rollout import checkpoint_budget, reversal_cost, rollout
     dtype = torch.float32 if dtype_name == "f32" else torch.float64
     f, box, prm = inputs.turbulent(n=n, seed=4)
     ctx = Context(box, prm, dtype=dtype)
     x0 = ctx.upload([f])
     dt = ctx.reductions(x0)["dt"]
+    if ncheck is None:
+        ncheck = checkpoint_budget(ctx, nsteps)
     w = [torch.ones_like(t) for t in x0]
     x = [t.clone().requires_grad_(True) for t in x0]
     torch.cuda.synchronize()
@@ -157,7 +160,7 @@ def run_adjoint(n=128, nsteps=40, ncheck=4, dtype_name="f32"):
             "recomputed_steps": reversal_cost(nsteps, ncheck)}
 
 
-def run_ensemble(nbox=96, nsteps=20, ncheck=4):
+def run_ensemble(nbox=96, nsteps=20, ncheck=None):
     """The 96-box ensemble (24 each of 48^3, 64^3, 80^3, 96^3, turbulent
     init, seeds 5000+b), float32, launch autotuned, nsteps steps forward, then
     the checkpointed adjoint of the same rollout."""
@@ -183,6 +186,9 @@ def run_ensemble(nbox=96, nsteps=20, ncheck=4):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     del xf, work
+    if ncheck is None:
+        from paper_2405_02483_amd.rollout import checkpoint_budget
+        ncheck = checkpoint_budget(ctx, nsteps)
     x = [t.clone().requires_grad_(True) for t in x0]
     y = rollout(ctx, x, dt, nsteps, ncheck=ncheck)
     torch.cuda.synchronize()
@@ -194,7 +200,8 @@ def run_ensemble(nbox=96, nsteps=20, ncheck=4):
     tile, mode = ctx.get_launch()
     ctx.close()
     torch.cuda.empty_cache()
-    return {"workload": "%d boxes (48/64/80/96)^3 turbulent, float32, %d RK steps" % (nbox, nsteps),
+    return {"workload": "%d boxes (48/64/80/96)^3 turbulent, float32, %d RK steps, %d checkpoints"
+                        % (nbox, nsteps, ncheck),
             "cells": ncell, "value": ncell * nsteps / (t1 - t0), "unit": "cell-updates/s",
             "forward_ms": (t1 - t0) * 1e3, "rollout_forward_ms": (t2 - t1) * 1e3,
             "backward_ms": (t3 - t2) * 1e3, "adjoint_over_forward": (t3 - t2) / (t1 - t0),

@@ -366,8 +366,21 @@ VPlan plan_program(const VProgram& P) {
       release[gid[q]].push_back(vphys[x]);
     }
   }
-  // cotangents, allocated in the reverse sweep
-  std::vector<int> cphys(S, -1), freec;
+  // the reverse sweep in groups (fills carry no transpose and are skipped)
+  std::vector<int> border;
+  for (int q = n - 1; q >= 0; --q) {
+    const int op = P.code[q].op;
+    if (op == V_FILL) continue;
+    const bool nb = op == V_STEN || op == V_MAX3 || op == V_MEAN3;
+    if (R.bgroups.empty() || nb || (int)border.size() - R.bgroups.back().first == kGroupMax)
+      R.bgroups.push_back({(int)border.size(), 0});
+    R.bgroups.back().count++;
+    border.push_back(q);
+  }
+  // cotangents, allocated in the reverse sweep; a slot is free again at the
+  // end of the group of its last use (a group's first transpose may read it
+  // at neighbouring cells while other cells of the group already write)
+  std::vector<int> cphys(S, -1), freec, pend;
   auto alloc = [&]() {
     if (!freec.empty()) {
       const int c = freec.back();
@@ -377,7 +390,14 @@ VPlan plan_program(const VProgram& P) {
     return R.ncot++;
   };
   for (int v = 0; v < 8; ++v) R.cout[v] = cphys[P.out[v]] = alloc();
-  for (int q = n - 1; q >= 0; --q) {
+  size_t bg = 0;
+  for (size_t u = 0; u < border.size(); ++u) {
+    if (bg < R.bgroups.size() && (int)u == R.bgroups[bg].first) {
+      for (int c : pend) freec.push_back(c);
+      pend.clear();
+      ++bg;
+    }
+    const int q = border[u];
     const VInstr& I = P.code[q];
     VStep& st = R.steps[q];
     st.cout = cphys[I.out];
@@ -393,9 +413,10 @@ VPlan plan_program(const VProgram& P) {
       }
       *dst[m] = cphys[src[m]];
     }
-    freec.push_back(st.cout);
+    pend.push_back(st.cout);
   }
   for (int v = 0; v < 8; ++v) R.cin[v] = cphys[v];
+  for (int q : border) R.bsteps.push_back(R.steps[q]);
   return R;
 }
 
@@ -543,9 +564,13 @@ __global__ __launch_bounds__(kBlock) void k_vm_group(const BoxDev* boxes, const 
 // may appear twice, as in a * a: its first contribution overwrites, the
 // second adds).
 template <class T>
-__global__ __launch_bounds__(kBlock) void k_vm_bwd(const BoxDev* boxes, const Blk* tab, VStep S,
-                                                   const T* base, T* cbase, long long stride) {
+__global__ __launch_bounds__(kBlock) void k_vm_bwd(const BoxDev* boxes, const Blk* tab,
+                                                   const VStep* __restrict__ code, int first,
+                                                   int count, const T* base, T* cbase,
+                                                   long long stride) {
   VM_PROLOGUE
+  for (int jj = 0; jj < count; ++jj) {
+  const VStep S = code[first + jj];
   const VInstr& I = S.f;
   const T* a = I.a >= 0 ? base + I.a * stride : nullptr;
   const T* b = I.b >= 0 ? base + I.b * stride : nullptr;
@@ -622,6 +647,7 @@ __global__ __launch_bounds__(kBlock) void k_vm_bwd(const BoxDev* boxes, const Bl
     }
     default: break;
   }
+  }
 }
 
 template <class T>
@@ -643,12 +669,11 @@ void vm_forward(const VLaunch& L, const VPlan& P, const VFused* d_fused, T* base
 }
 
 template <class T>
-void vm_backward(const VLaunch& L, const VPlan& P, const T* base, T* cbase, long long stride) {
-  for (auto it = P.steps.rbegin(); it != P.steps.rend(); ++it) {
-    if (it->f.op == V_FILL) continue;
-    hipLaunchKernelGGL(k_vm_bwd<T>, dim3(L.nblk), dim3(kBlock), 0, L.stream, L.boxes, L.tab, *it, base,
-                       cbase, stride);
-  }
+void vm_backward(const VLaunch& L, const VPlan& P, const VStep* d_bsteps, const T* base, T* cbase,
+                 long long stride) {
+  for (const VGroup& G : P.bgroups)
+    hipLaunchKernelGGL(k_vm_bwd<T>, dim3(L.nblk), dim3(kBlock), 0, L.stream, L.boxes, L.tab, d_bsteps,
+                       G.first, G.count, base, cbase, stride);
 }
 
 template <class T> void vm_axpby8(const VLaunch& L, P8<T> y, CP8<T> x, double a, double b) {
@@ -658,8 +683,10 @@ template <class T> void vm_axpby8(const VLaunch& L, P8<T> y, CP8<T> x, double a,
 
 template void vm_forward<float>(const VLaunch&, const VPlan&, const VFused*, float*, long long);
 template void vm_forward<double>(const VLaunch&, const VPlan&, const VFused*, double*, long long);
-template void vm_backward<float>(const VLaunch&, const VPlan&, const float*, float*, long long);
-template void vm_backward<double>(const VLaunch&, const VPlan&, const double*, double*, long long);
+template void vm_backward<float>(const VLaunch&, const VPlan&, const VStep*, const float*, float*,
+                                 long long);
+template void vm_backward<double>(const VLaunch&, const VPlan&, const VStep*, const double*, double*,
+                                  long long);
 template void vm_axpby8<float>(const VLaunch&, P8<float>, CP8<float>, double, double);
 template void vm_axpby8<double>(const VLaunch&, P8<double>, CP8<double>, double, double);
 

@@ -87,6 +87,12 @@ struct VPlan {
   std::vector<VStep> steps;  // per operation: value slots of what the transposes read
   std::vector<VFused> fused; // the same operations for the grouped forward run
   std::vector<VGroup> groups;
+  // the reverse sweep in groups, one launch each: bsteps holds the steps in
+  // execution order (last operation first); a group starts with any
+  // transpose (the only one that may read neighbouring cells' cotangents)
+  // and continues with pointwise transposes
+  std::vector<VStep> bsteps;
+  std::vector<VGroup> bgroups;
   int nval = 0;              // value slots (0..7: the state)
   int ncot = 0;              // cotangent slots
   int cout[8];               // cotangent slot seeded with each output's cotangent
@@ -106,11 +112,12 @@ struct VLaunch {
 // d_fused is plan.fused in device memory.
 // Backward: cotangent slots cbase + s * stride, with the outputs' slots
 // (plan.cout) seeded by the caller; afterwards slot plan.cin[v] holds
-// (dF/df_v)^T of the seed.
+// (dF/df_v)^T of the seed.  d_bsteps is plan.bsteps in device memory.
 template <class T>
 void vm_forward(const VLaunch& L, const VPlan& plan, const VFused* d_fused, T* base, long long stride);
 template <class T>
-void vm_backward(const VLaunch& L, const VPlan& plan, const T* base, T* cbase, long long stride);
+void vm_backward(const VLaunch& L, const VPlan& plan, const VStep* d_bsteps, const T* base, T* cbase,
+                 long long stride);
 
 // y[v] = a * y[v] + b * x[v] for the 8 fields (x may be null: y = a * y).
 template <class T> void vm_axpby8(const VLaunch& L, P8<T> y, CP8<T> x, double a, double b);

@@ -41,6 +41,7 @@ struct mhd_ctx {
   size_t adj_bytes = 0;
   VPlan* prog = nullptr;           // the right-hand side as a program (adjoint)
   VFused* d_fused = nullptr;       // prog->fused in device memory
+  VStep* d_bsteps = nullptr;       // prog->bsteps in device memory
   // z-march stage kernels: work items, tile shape, Courant partials, dt
   ZItem* d_items = nullptr;
   int nitems = 0;
@@ -305,6 +306,7 @@ void mhd_destroy(mhd_ctx* c) {
   (void)hipFree(c->adj);
   delete c->prog;
   (void)hipFree(c->d_fused);
+  (void)hipFree(c->d_bsteps);
   (void)hipFree(c->d_items);
   (void)hipFree(c->d_cpart);
   (void)hipFree(c->d_dt);
@@ -528,12 +530,16 @@ static int ensure_program(mhd_ctx* c) {
   } catch (...) {
     return fail(c, MHD_ENOMEM, "adjoint program");
   }
-  const size_t bytes = sizeof(VFused) * P->fused.size();
+  const size_t bytes = sizeof(VFused) * P->fused.size(), bbytes = sizeof(VStep) * P->bsteps.size();
   hipError_t e = hipMalloc(&c->d_fused, bytes);
   if (e == hipSuccess) e = hipMemcpy(c->d_fused, P->fused.data(), bytes, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMalloc(&c->d_bsteps, bbytes);
+  if (e == hipSuccess) e = hipMemcpy(c->d_bsteps, P->bsteps.data(), bbytes, hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     (void)hipFree(c->d_fused);
+    (void)hipFree(c->d_bsteps);
     c->d_fused = nullptr;
+    c->d_bsteps = nullptr;
     delete P;
     return fail(c, MHD_ENOMEM, "adjoint program upload");
   }
@@ -608,7 +614,7 @@ static int do_adjoint(mhd_ctx* c, void* const fn[8], double dt, void* const gin[
       e = hipMemcpyAsync(cbase + (long long)P.cout[v] * n, Ub.p[v], bytes, hipMemcpyDeviceToDevice,
                          c->stream);
     if (e != hipSuccess) break;
-    vm_backward<T>(V, P, base, cbase, n);
+    vm_backward<T>(V, P, c->d_bsteps, base, cbase, n);
     CP8<T> cin;
     bool any = false;
     for (int v = 0; v < 8; ++v) {
@@ -651,7 +657,7 @@ static int do_rhs_adjoint(mhd_ctx* c, void* const f[8], void* const wbar[8],
   for (int v = 0; v < 8 && e == hipSuccess; ++v)
     e = hipMemcpyAsync(cbase + (long long)P.cout[v] * n, wbar[v], bytes, hipMemcpyDeviceToDevice,
                        c->stream);
-  if (e == hipSuccess) vm_backward<T>(V, P, base, cbase, n);
+  if (e == hipSuccess) vm_backward<T>(V, P, c->d_bsteps, base, cbase, n);
   for (int v = 0; v < 8 && e == hipSuccess; ++v)
     e = P.cin[v] >= 0 ? hipMemcpyAsync(fbar[v], cbase + (long long)P.cin[v] * n, bytes,
                                        hipMemcpyDeviceToDevice, c->stream)

@@ -13,7 +13,7 @@ import functools
 
 import torch
 
-__all__ = ["MHDRollout", "rollout", "reversal_cost", "reversal_schedule"]
+__all__ = ["MHDRollout", "rollout", "checkpoint_budget", "reversal_cost", "reversal_schedule"]
 
 
 @functools.lru_cache(maxsize=None)
@@ -122,6 +122,18 @@ class MHDRollout(torch.autograd.Function):
         return (None, None, None, None) + tuple(g)
 
 
-def rollout(ctx, x, dt, nsteps, ncheck=4):
-    """Differentiable nsteps-step rollout of the state x (list of 8 tensors)."""
+def checkpoint_budget(ctx, nsteps, fraction=0.5):
+    """Checkpoint slots that fit in `fraction` of the free device memory,
+    at most nsteps - 1 (then no step is recomputed)."""
+    free, _ = torch.cuda.mem_get_info(ctx.device)
+    state = 8 * ctx.n * torch.tensor([], dtype=ctx.dtype).element_size()
+    return max(0, min(nsteps - 1, int(fraction * free // state)))
+
+
+def rollout(ctx, x, dt, nsteps, ncheck=None):
+    """Differentiable nsteps-step rollout of the state x (list of 8 tensors).
+    ncheck: checkpoint slots for the backward pass; None sizes them from the
+    free device memory (checkpoint_budget)."""
+    if ncheck is None:
+        ncheck = checkpoint_budget(ctx, nsteps)
     return list(MHDRollout.apply(ctx, dt, nsteps, ncheck, *x))
