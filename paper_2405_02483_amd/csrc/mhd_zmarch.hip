@@ -16,6 +16,7 @@
 // time step (eq. courantcond), which k_dt folds into a device-resident dt.
 #include <algorithm>
 #include <map>
+#include <utility>
 #include <mutex>
 
 #include "mhd_zmarch.hpp"
@@ -621,7 +622,38 @@ __global__ __launch_bounds__(TX * TY) void zP(const BoxDev* __restrict__ boxes,
 // plane r through LDS strips; z divergences scattered into per-thread
 // accumulators of output planes r-3..r+3 (first differences for
 // derivatives); plane r-3 is then complete.
-template <class T, int TX, int TY, bool PERS>
+//
+// FM selects the fields this launch completes (bit v: field v); the stage
+// runs one launch per mask of kFMasks.  The groups read nearly disjoint
+// inputs, and each launch needs a fraction of the registers and LDS.
+// Masks: the momenta; rho and e; the magnetic field.
+constexpr unsigned kFMasks[] = {0x0Eu, 0x11u, 0xE0u};
+constexpr int kNFMasks = sizeof(kFMasks) / sizeof(kFMasks[0]);
+static_assert(32 + 8 * kNFMasks <= kQueueInts && kQueueInts <= 64, "queue counters per launch");
+constexpr bool masks_partition() {
+  unsigned all = 0;
+  for (unsigned m : kFMasks) {
+    if (all & m) return false;
+    all |= m;
+  }
+  return all == 0xFFu;
+}
+static_assert(masks_partition(), "each field completed by exactly one launch");
+template <unsigned FM> __host__ __device__ constexpr bool hasf(int v) { return (FM >> v) & 1u; }
+// the field each LDS strip serves: x strips, y strips (see zF)
+__host__ __device__ constexpr int kXOwn[9] = {0, 1, 2, 2, 4, 3, 3, 7, 4};
+__host__ __device__ constexpr int kYOwn[9] = {0, 1, 1, 2, 4, 3, 3, 7, 4};
+// LDS position of strip q among the strips a launch loads (own: kXOwn or
+// kYOwn); q = 9 gives their number
+template <unsigned FM>
+__host__ __device__ constexpr int strip_slot(const int (&own)[9], int q) {
+  int n = 0;
+  for (int i = 0; i < q; ++i) n += (FM >> own[i]) & 1u;
+  return n;
+}
+__host__ __device__ constexpr int at_least1(int n) { return n > 0 ? n : 1; }
+
+template <class T, int TX, int TY, bool PERS, unsigned FM>
 __global__ __launch_bounds__(TX * TY) void zF(const BoxDev* __restrict__ boxes,
                                               const ZItem* __restrict__ items, int nitems, const T* __restrict__ ztab,
                                                int* __restrict__ queue,
@@ -635,9 +667,11 @@ __global__ __launch_bounds__(TX * TY) void zF(const BoxDev* __restrict__ boxes,
   // x strips: 0 px 1 Gxx 2 Gyx 3 Lyz 4 Hx 5 Gzx 6 Lzy 7 Ey 8 Qy
   // y strips: 0 py 1 Gxy 2 Lxz 3 Gyy 4 Hy 5 Gzy 6 Lzx 7 Ex 8 Qx
   // full:     0 Qz 1 Ez
-  __shared__ T sx[9 * PXs::NP];
-  __shared__ T sy[9 * PYs::NP];
-  __shared__ T s2[2 * P3::NP];
+  // only the strips of this launch's fields occupy LDS
+  constexpr bool kQz = hasf<FM>(4), kEz = hasf<FM>(5) || hasf<FM>(6);
+  __shared__ T sx[at_least1(strip_slot<FM>(kXOwn, 9)) * PXs::NP];
+  __shared__ T sy[at_least1(strip_slot<FM>(kYOwn, 9)) * PYs::NP];
+  __shared__ T s2[at_least1(int(kQz) + int(kEz)) * P3::NP];
   ZLOOP_BEGIN
   PlaneIdx<TX, TY, 3, 0> ix;
   PlaneIdx<TX, TY, 0, 3> iy;
@@ -650,9 +684,9 @@ __global__ __launch_bounds__(TX * TY) void zF(const BoxDev* __restrict__ boxes,
   const T inv_mu = ph.inv_mu;
   const double dt = dt_dev ? *dt_dev : dt_host;
   const T bdt = T(beta * dt);
-  auto X = [&](int q, int x) -> T { return sx[q * PXs::NP + PXs::at(x, ty)]; };
-  auto Y = [&](int q, int y) -> T { return sy[q * PYs::NP + PYs::at(tx, y)]; };
-  auto F2 = [&](int q, int x, int y) -> T { return s2[q * P3::NP + P3::at(x, y)]; };
+  auto X = [&](int q, int x) -> T { return sx[strip_slot<FM>(kXOwn, q) * PXs::NP + PXs::at(x, ty)]; };
+  auto Y = [&](int q, int y) -> T { return sy[strip_slot<FM>(kYOwn, q) * PYs::NP + PYs::at(tx, y)]; };
+  auto F2 = [&](int q, int x, int y) -> T { return s2[(q && kQz) * P3::NP + P3::at(x, y)]; };
   T acc[7][7];
 #pragma unroll
   for (int a = 0; a < 7; ++a)
@@ -687,17 +721,23 @@ __global__ __launch_bounds__(TX * TY) void zF(const BoxDev* __restrict__ boxes,
     for (int a = 0; a < 7; ++a) Fv[a] = masked(a, k, acc[a][0]);
     if (f_out.p[0] == nullptr) {
 #pragma unroll
-      for (int a = 0; a < 7; ++a) du.p[a][o] = Fv[a];
+      for (int a = 0; a < 7; ++a)
+        if (hasf<FM>(a)) du.p[a][o] = Fv[a];
       return;
     }
     T uin[7], fin[7];
 #pragma unroll
     for (int a = 0; a < 7; ++a) {
-      uin[a] = (du_mode & DU_READ) ? du.p[a][o] : T(0);
-      fin[a] = f.p[a][o];
+      uin[a] = T(0);
+      fin[a] = T(0);
+      if (hasf<FM>(a)) {
+        uin[a] = (du_mode & DU_READ) ? du.p[a][o] : T(0);
+        fin[a] = f.p[a][o];
+      }
     }
 #pragma unroll
-    for (int a = 0; a < 7; ++a) update(a, o, Fv[a], uin[a], fin[a]);
+    for (int a = 0; a < 7; ++a)
+      if (hasf<FM>(a)) update(a, o, Fv[a], uin[a], fin[a]);
   };
 
   for (int r = it.z0 - 3; r <= it.z1 + 2; ++r) {
@@ -714,86 +754,101 @@ __global__ __launch_bounds__(TX * TY) void zF(const BoxDev* __restrict__ boxes,
                           ws.pq(POUT_HY), ws.q(QOUT_GZY), ws.q(QOUT_LZX), ws.q(QOUT_EX)};
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-          load_plane(sx + q * PXs::NP, xs[q], b, ix, k);
-          load_plane(sy + q * PYs::NP, ys[q], b, iy, k);
+          if (hasf<FM>(kXOwn[q])) load_plane(sx + strip_slot<FM>(kXOwn, q) * PXs::NP, xs[q], b, ix, k);
+          if (hasf<FM>(kYOwn[q])) load_plane(sy + strip_slot<FM>(kYOwn, q) * PYs::NP, ys[q], b, iy, k);
         }
-        load_plane(s2, ws.pq(POUT_QZ), b, i3, k);
-        load_plane(s2 + P3::NP, ws.pq(POUT_EZ), b, i3, k);
+        if (kQz) load_plane(s2, ws.pq(POUT_QZ), b, i3, k);
+        if (kEz) load_plane(s2 + kQz * P3::NP, ws.pq(POUT_EZ), b, i3, k);
       }
-      load_plane(sx + 8 * PXs::NP, ws.q(QOUT_QY), b, ix, k);
-      load_plane(sy + 8 * PYs::NP, ws.q(QOUT_QX), b, iy, k);
+      if (hasf<FM>(4)) {
+        load_plane(sx + strip_slot<FM>(kXOwn, 8) * PXs::NP, ws.q(QOUT_QY), b, ix, k);
+        load_plane(sy + strip_slot<FM>(kYOwn, 8) * PYs::NP, ws.q(QOUT_QX), b, iy, k);
+      }
       // Bz's dU and f at this plane, fetched with the planes
       T bz_u = T(0), bz_f = T(0);
-      if (inch && own && f_out.p[0] != nullptr) {
+      if (hasf<FM>(7) && inch && own && f_out.p[0] != nullptr) {
         if (du_mode & DU_READ) bz_u = du.p[7][o];
         bz_f = f.p[7][o];
       }
       __syncthreads();
       const int x = tx, y = ty;
       if (inch) {
-        if (cont)
+        if (hasf<FM>(0) && cont)
           acc[0][3] += -(op6<1, 1, T>([&](int m) { return X(0, x + m); }, g.hxi) +
                          op6<1, 1, T>([&](int m) { return Y(0, y + m); }, g.hyi));
+        if (hasf<FM>(1))
         acc[1][3] += op6<1, 0, T>([&](int m) { return X(1, x + m); }, g.hxi) +
                      op6<1, 1, T>([&](int m) { return Y(1, y + m); }, g.hyi) -
                      op6<0, 1, T>([&](int m) { return Y(2, y + m); }, T(0)) * inv_mu -
                      ws.pq(POUT_DPX)[o];
+        if (hasf<FM>(2))
         acc[2][3] += op6<1, 0, T>([&](int m) { return Y(3, y + m); }, g.hyi) +
                      op6<1, 1, T>([&](int m) { return X(2, x + m); }, g.hxi) +
                      op6<0, 1, T>([&](int m) { return X(3, x + m); }, T(0)) * inv_mu -
                      ws.pq(POUT_DPY)[o];
-        acc[3][3] -= ws.q(QOUT_DPZ)[o];
-        acc[3][3] += op6<1, 1, T>([&](int m) { return X(5, x + m); }, g.hxi) +
-                     op6<1, 1, T>([&](int m) { return Y(5, y + m); }, g.hyi) +
-                     (op6<0, 1, T>([&](int m) { return Y(6, y + m); }, T(0)) -
-                      op6<0, 1, T>([&](int m) { return X(6, x + m); }, T(0))) * inv_mu;
+        if (hasf<FM>(3)) {
+          acc[3][3] -= ws.q(QOUT_DPZ)[o];
+          acc[3][3] += op6<1, 1, T>([&](int m) { return X(5, x + m); }, g.hxi) +
+                       op6<1, 1, T>([&](int m) { return Y(5, y + m); }, g.hyi) +
+                       (op6<0, 1, T>([&](int m) { return Y(6, y + m); }, T(0)) -
+                        op6<0, 1, T>([&](int m) { return X(6, x + m); }, T(0))) * inv_mu;
+        }
+        if (hasf<FM>(4))
         acc[4][3] += ws.pq(POUT_QC)[o] + ws.q(QOUT_CZZ)[o] +
                      op6<1, 1, T>([&](int m) { return X(4, x + m); }, g.hxi) +
                      op6<1, 1, T>([&](int m) { return Y(4, y + m); }, g.hyi) +
                      op6<0, 1, T>([&](int m) {
                        return op6<0, 1, T>([&](int a) { return F2(0, x + a, y + m); }, T(0));
                      }, T(0));
-        acc[5][3] += -op6<1, 1, T>([&](int m) { return F2(1, x, y + m); }, g.hyi);
-        acc[6][3] += op6<1, 1, T>([&](int m) { return F2(1, x + m, y); }, g.hxi);
+        if (hasf<FM>(5)) acc[5][3] += -op6<1, 1, T>([&](int m) { return F2(1, x, y + m); }, g.hyi);
+        if (hasf<FM>(6)) acc[6][3] += op6<1, 1, T>([&](int m) { return F2(1, x + m, y); }, g.hxi);
         // Bz has no z divergence: complete at once
-        const T fbz = -(op6<1, 1, T>([&](int m) { return X(7, x + m); }, g.hxi) -
-                        op6<1, 1, T>([&](int m) { return Y(7, y + m); }, g.hyi));
-        if (own) {
+        if (hasf<FM>(7) && own) {
+          const T fbz = -(op6<1, 1, T>([&](int m) { return X(7, x + m); }, g.hxi) -
+                          op6<1, 1, T>([&](int m) { return Y(7, y + m); }, g.hyi));
           const T F7 = masked(7, r, fbz);
           if (f_out.p[0] == nullptr) du.p[7][o] = F7;
           else update(7, o, F7, bz_u, bz_f);
         }
       }
-      const T xqy = op6<0, 1, T>([&](int m) { return X(8, x + m); }, T(0));
-      const T yqx = op6<0, 1, T>([&](int m) { return Y(8, y + m); }, T(0));
+      T xqy = T(0), yqx = T(0);
+      if (hasf<FM>(4)) {
+        xqy = op6<0, 1, T>([&](int m) { return X(8, x + m); }, T(0));
+        yqx = op6<0, 1, T>([&](int m) { return Y(8, y + m); }, T(0));
+      }
       // ---- z divergences of plane r scattered into output planes r-3..r+3:
       // derivatives through first differences, interpolations directly
       T cur[7];
-      cur[0] = f.p[3][o];
-      cur[1] = ws.q(QOUT_GXZ)[o];
-      cur[2] = ws.q(QOUT_GYZ)[o];
-      cur[3] = ws.q(QOUT_GZZ)[o];
-      cur[4] = ws.q(QOUT_HZ)[o];
-      cur[5] = ws.q(QOUT_EY)[o];
-      cur[6] = ws.q(QOUT_EX)[o];
+      const T* cols[7] = {f.p[3], ws.q(QOUT_GXZ), ws.q(QOUT_GYZ), ws.q(QOUT_GZZ), ws.q(QOUT_HZ),
+                          ws.q(QOUT_EY), ws.q(QOUT_EX)};
+#pragma unroll
+      for (int a = 0; a < 7; ++a) cur[a] = hasf<FM>(a) ? cols[a][o] : T(0);
       T dl[7];
 #pragma unroll
       for (int a = 0; a < 7; ++a) {
         dl[a] = (cur[a] - prev[a]) * g.hzi;
         prev[a] = cur[a];
       }
-      if (cont) zscatter_d<1, 3>(acc[0], kb, -dl[0], wall, N, zt);
-      zscatter_d<1, 3>(acc[1], kb, dl[1], wall, N, zt);
-      zscatter<0, 1, 3>(acc[1], kb, ws.q(QOUT_LXY)[o] * inv_mu, wall, N, zt);
-      zscatter_d<1, 3>(acc[2], kb, dl[2], wall, N, zt);
-      zscatter<0, 1, 3>(acc[2], kb, -ws.q(QOUT_LYX)[o] * inv_mu, wall, N, zt);
-      zscatter_d<0, 3>(acc[3], kb, dl[3], wall, N, zt);
-      if (grav) zscatter<0, 0, 3>(acc[3], kb, -f.p[0][o] * ph.gz, wall, N, zt);
-      zscatter_d<1, 3>(acc[4], kb, dl[4], wall, N, zt);
-      zscatter<0, 1, 3>(acc[4], kb, xqy, wall, N, zt);
-      zscatter<0, 1, 3>(acc[4], kb, yqx, wall, N, zt);
-      zscatter_d<1, 3>(acc[5], kb, dl[5], wall, N, zt);
-      zscatter_d<1, 3>(acc[6], kb, -dl[6], wall, N, zt);
+      if (hasf<FM>(0) && cont) zscatter_d<1, 3>(acc[0], kb, -dl[0], wall, N, zt);
+      if (hasf<FM>(1)) {
+        zscatter_d<1, 3>(acc[1], kb, dl[1], wall, N, zt);
+        zscatter<0, 1, 3>(acc[1], kb, ws.q(QOUT_LXY)[o] * inv_mu, wall, N, zt);
+      }
+      if (hasf<FM>(2)) {
+        zscatter_d<1, 3>(acc[2], kb, dl[2], wall, N, zt);
+        zscatter<0, 1, 3>(acc[2], kb, -ws.q(QOUT_LYX)[o] * inv_mu, wall, N, zt);
+      }
+      if (hasf<FM>(3)) {
+        zscatter_d<0, 3>(acc[3], kb, dl[3], wall, N, zt);
+        if (grav) zscatter<0, 0, 3>(acc[3], kb, -f.p[0][o] * ph.gz, wall, N, zt);
+      }
+      if (hasf<FM>(4)) {
+        zscatter_d<1, 3>(acc[4], kb, dl[4], wall, N, zt);
+        zscatter<0, 1, 3>(acc[4], kb, xqy, wall, N, zt);
+        zscatter<0, 1, 3>(acc[4], kb, yqx, wall, N, zt);
+      }
+      if (hasf<FM>(5)) zscatter_d<1, 3>(acc[5], kb, dl[5], wall, N, zt);
+      if (hasf<FM>(6)) zscatter_d<1, 3>(acc[6], kb, -dl[6], wall, N, zt);
     } else {
 #pragma unroll
       for (int a = 0; a < 7; ++a) prev[a] = T(0);
@@ -838,6 +893,19 @@ __global__ __launch_bounds__(256) void k_dt(const BoxDev* __restrict__ boxes,
 }
 
 // ---------------------------------------------------------------------------
+template <class T, int TX, int TY, bool PERS, unsigned FM, class G>
+static void zF_one(const G& grid, dim3 block, const ZLaunch& L, const ZStageArgs<T>& a, int* q) {
+  hipLaunchKernelGGL((zF<T, TX, TY, PERS, FM>), grid((const void*)zF<T, TX, TY, PERS, FM>), block, 0, L.stream,
+                     L.boxes, L.items, L.nitems, a.ztab, q, a.f, a.w, a.ph, a.du, a.du_mode, a.f_out, a.alpha,
+                     a.beta, a.dt_dev, a.dt_host);
+}
+// one launch per mask, each with its own 8 queue counters
+template <class T, int TX, int TY, bool PERS, class G, size_t... I>
+static void zF_launch(const G& grid, dim3 block, const ZLaunch& L, const ZStageArgs<T>& a, int* q,
+                      std::index_sequence<I...>) {
+  (zF_one<T, TX, TY, PERS, kFMasks[I]>(grid, block, L, a, q ? q + 32 + 8 * int(I) : q), ...);
+}
+
 __global__ void k_qreset(int* q) {
   if ((int)threadIdx.x < kQueueInts) q[threadIdx.x] = 0;
 }
@@ -883,9 +951,7 @@ static void launch_zstage_m(const ZLaunch& L, const ZStageArgs<T>& a) {
   hipLaunchKernelGGL((zP<T, TX, TY, PERS>), grid((const void*)zP<T, TX, TY, PERS>), block, 0, L.stream, L.boxes,
                      L.items, n, a.ztab, q ? q + 24 : q, a.f, a.ph, a.w);
   L.at(PASS_FINAL);
-  hipLaunchKernelGGL((zF<T, TX, TY, PERS>), grid((const void*)zF<T, TX, TY, PERS>), block, 0, L.stream, L.boxes,
-                     L.items, n, a.ztab, q ? q + 32 : q, a.f, a.w, a.ph, a.du, a.du_mode, a.f_out,
-                     a.alpha, a.beta, a.dt_dev, a.dt_host);
+  zF_launch<T, TX, TY, PERS>(grid, block, L, a, q, std::make_index_sequence<kNFMasks>{});
   L.at(PASS_END);
 }
 
