@@ -280,7 +280,12 @@ __global__ __launch_bounds__(TX * TY) void zA2(const BoxDev* __restrict__ boxes,
 //   y-edge (i-1/2, j, k-1/2): Gxz, Gzx, Ey, Lxy, Lzy, Qy
 //   x-edge (i, j-1/2, k-1/2): Gyz, Gzy, Ex, Lyx, Lzx, Qx
 //   Hz (z-face), Gzz, Czz (centre)
-template <class T, int TX, int TY, bool PERS>
+// QM selects the output groups of a launch: QM_EDGES (both edges, which need
+// x/y stencils through LDS) and QM_ZC (z-face and centre, pointwise in x/y).
+// The stage runs one launch of each: apart, each needs far fewer registers
+// (float64: occupancy 1 -> 2 and 3), for four arrays read twice.
+constexpr unsigned QM_EDGES = 1u, QM_ZC = 2u;
+template <class T, int TX, int TY, bool PERS, unsigned QM>
 __global__ __launch_bounds__(TX * TY) void zQ(const BoxDev* __restrict__ boxes,
                                               const ZItem* __restrict__ items, int nitems, const T* __restrict__ ztab,
                                                int* __restrict__ queue,
@@ -289,8 +294,10 @@ __global__ __launch_bounds__(TX * TY) void zQ(const BoxDev* __restrict__ boxes,
   const T* __restrict__ lntg = ws.arr(WS_LNT);
   const T* __restrict__ Dg = ws.arr(WS_D);
   using P3 = Plane<TX, TY, 3>;
-  __shared__ T sR[P3::NP], sL[P3::NP];
-  __shared__ T sUZ[3][P3::NP], sBZ[3][P3::NP], sPZ[3][P3::NP];
+  constexpr bool kE = QM & QM_EDGES, kZ = QM & QM_ZC;
+  constexpr int NPL = kE ? P3::NP : 1;
+  __shared__ T sR[NPL], sL[NPL];
+  __shared__ T sUZ[3][NPL], sBZ[3][NPL], sPZ[3][NPL];
   ZLOOP_BEGIN
   PlaneIdx<TX, TY, 3> i3;
   i3.init(b, it.x0, it.y0);
@@ -309,31 +316,43 @@ __global__ __launch_bounds__(TX * TY) void zQ(const BoxDev* __restrict__ boxes,
     T pzv = T(0), uzv = T(0), ev = T(0), rhov = T(0), nuv = T(0), em = T(0), lem = T(0);
     if (valid(r)) {
       const int k = kk(r), sl = wrapm(r, 3);
-      __syncthreads();
-      load_plane(sR, f.p[0], b, i3, k);
-      load_plane(sL, lntg, b, i3, k);
-      load_plane(sUZ[sl], uzg, b, i3, k);
-      load_plane(sBZ[sl], f.p[7], b, i3, k);
-      load_plane(sPZ[sl], f.p[3], b, i3, k);
-      __syncthreads();
       const long long o = col(r);
-      rx = op6<0, 0, T>([&](int m) { return sR[P3::at(tx + m, ty)]; }, T(0));
-      ry = op6<0, 0, T>([&](int m) { return sR[P3::at(tx, ty + m)]; }, T(0));
-      lx = op6<0, 0, T>([&](int m) { return sL[P3::at(tx + m, ty)]; }, T(0));
-      ly = op6<0, 0, T>([&](int m) { return sL[P3::at(tx, ty + m)]; }, T(0));
-      px = f.p[1][o];
-      py = f.p[2][o];
-      ux = px / rx;
-      uy = py / ry;
-      bxv = f.p[5][o];
-      byv = f.p[6][o];
-      pzv = sPZ[sl][P3::at(tx, ty)];
-      uzv = sUZ[sl][P3::at(tx, ty)];
-      ev = f.p[4][o];
-      rhov = sR[P3::at(tx, ty)];
-      nuv = exp(sL[P3::at(tx, ty)]);
-      em = ev / rhov;
-      lem = log(em);
+      if constexpr (kE) {
+        __syncthreads();
+        load_plane(sR, f.p[0], b, i3, k);
+        load_plane(sL, lntg, b, i3, k);
+        load_plane(sUZ[sl], uzg, b, i3, k);
+        load_plane(sBZ[sl], f.p[7], b, i3, k);
+        load_plane(sPZ[sl], f.p[3], b, i3, k);
+        __syncthreads();
+        rx = op6<0, 0, T>([&](int m) { return sR[P3::at(tx + m, ty)]; }, T(0));
+        ry = op6<0, 0, T>([&](int m) { return sR[P3::at(tx, ty + m)]; }, T(0));
+        lx = op6<0, 0, T>([&](int m) { return sL[P3::at(tx + m, ty)]; }, T(0));
+        ly = op6<0, 0, T>([&](int m) { return sL[P3::at(tx, ty + m)]; }, T(0));
+        px = f.p[1][o];
+        py = f.p[2][o];
+        ux = px / rx;
+        uy = py / ry;
+        bxv = f.p[5][o];
+        byv = f.p[6][o];
+      }
+      if constexpr (kZ) {
+        // own column only: from LDS when the planes are there
+        if constexpr (kE) {
+          pzv = sPZ[sl][P3::at(tx, ty)];
+          uzv = sUZ[sl][P3::at(tx, ty)];
+          rhov = sR[P3::at(tx, ty)];
+          nuv = exp(sL[P3::at(tx, ty)]);
+        } else {
+          pzv = f.p[3][o];
+          uzv = uzg[o];
+          rhov = f.p[0][o];
+          nuv = exp(lntg[o]);
+        }
+        ev = f.p[4][o];
+        em = ev / rhov;
+        lem = log(em);
+      }
     }
     push(wRX, rx); push(wLX, lx); push(wPX, px); push(wUX, ux); push(wBX, bxv);
     push(wRY, ry); push(wLY, ly); push(wPY, py); push(wUY, uy); push(wBY, byv);
@@ -349,7 +368,7 @@ __global__ __launch_bounds__(TX * TY) void zQ(const BoxDev* __restrict__ boxes,
       const T* PZ = sPZ[sq];
       const long long o = col(q);
       // ---- y-edge
-      {
+      if constexpr (kE) {
         const T zRX = zwin<0, 0, 6, 3>(wRX, q, wall, N, T(0), zt);
         const T zPX = zwin<0, 0, 6, 3>(wPX, q, wall, N, T(0), zt);
         const T zUX = zwin<0, 0, 6, 3>(wUX, q, wall, N, T(0), zt);
@@ -389,7 +408,7 @@ __global__ __launch_bounds__(TX * TY) void zQ(const BoxDev* __restrict__ boxes,
         }
       }
       // ---- x-edge
-      {
+      if constexpr (kE) {
         const T zRY = zwin<0, 0, 6, 3>(wRY, q, wall, N, T(0), zt);
         const T zPY = zwin<0, 0, 6, 3>(wPY, q, wall, N, T(0), zt);
         const T zUY = zwin<0, 0, 6, 3>(wUY, q, wall, N, T(0), zt);
@@ -429,7 +448,7 @@ __global__ __launch_bounds__(TX * TY) void zQ(const BoxDev* __restrict__ boxes,
         }
       }
       // ---- z-face energy flux: -zdn(e) u_z + nuE zdn(rho) dz zdn(nu) zdn(e_m) ddzdn(ln e_m)
-      {
+      if constexpr (kZ) {
         T hz = T(0);
         if (adv) hz = -zwin<0, 0, 6, 3>(wE, q, wall, N, T(0), zt) * wUZ[3];
         if (ediff)
@@ -447,7 +466,7 @@ __global__ __launch_bounds__(TX * TY) void zQ(const BoxDev* __restrict__ boxes,
     }
     // centre terms of plane q2 = r - 3 (window slot 2)
     const int q2 = r - 3;
-    if (valid(q2) && q2 >= it.z0 && q2 < it.z1) {
+    if (kZ && valid(q2) && q2 >= it.z0 && q2 < it.z1) {
       const long long o = col(q2);
       const T szz = zwin<1, 1, 6, 2>(wUZ, q2, wall, N, g.hzi, zt);
       T gzz = T(0), czz = T(0);
@@ -629,7 +648,7 @@ __global__ __launch_bounds__(TX * TY) void zP(const BoxDev* __restrict__ boxes,
 // Masks: the momenta; rho and e; the magnetic field.
 constexpr unsigned kFMasks[] = {0x0Eu, 0x11u, 0xE0u};
 constexpr int kNFMasks = sizeof(kFMasks) / sizeof(kFMasks[0]);
-static_assert(32 + 8 * kNFMasks <= kQueueInts && kQueueInts <= 64, "queue counters per launch");
+static_assert(32 + 8 * kNFMasks + 8 <= kQueueInts && kQueueInts <= 64, "queue counters per launch");
 constexpr bool masks_partition() {
   unsigned all = 0;
   for (unsigned m : kFMasks) {
@@ -945,8 +964,10 @@ static void launch_zstage_m(const ZLaunch& L, const ZStageArgs<T>& a) {
                        a.Cdtd, a.nuB, a.eta_const, a.dt_dev);
   }
   L.at(PASS_EDGES);
-  hipLaunchKernelGGL((zQ<T, TX, TY, PERS>), grid((const void*)zQ<T, TX, TY, PERS>), block, 0, L.stream, L.boxes,
-                     L.items, n, a.ztab, q ? q + 16 : q, a.f, a.ph, a.w);
+  hipLaunchKernelGGL((zQ<T, TX, TY, PERS, QM_EDGES>), grid((const void*)zQ<T, TX, TY, PERS, QM_EDGES>), block, 0,
+                     L.stream, L.boxes, L.items, n, a.ztab, q ? q + 16 : q, a.f, a.ph, a.w);
+  hipLaunchKernelGGL((zQ<T, TX, TY, PERS, QM_ZC>), grid((const void*)zQ<T, TX, TY, PERS, QM_ZC>), block, 0,
+                     L.stream, L.boxes, L.items, n, a.ztab, q ? q + 56 : q, a.f, a.ph, a.w);
   L.at(PASS_CF);
   hipLaunchKernelGGL((zP<T, TX, TY, PERS>), grid((const void*)zP<T, TX, TY, PERS>), block, 0, L.stream, L.boxes,
                      L.items, n, a.ztab, q ? q + 24 : q, a.f, a.ph, a.w);

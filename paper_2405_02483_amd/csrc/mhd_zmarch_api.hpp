@@ -47,8 +47,8 @@ template <class T> struct ZWork {
   __host__ __device__ T* pq(int i) const { return arr(WS_P0 + i); }
 };
 
-// Item queues of the persistent mode: 8 counters per launch, at most 7 launches.
-constexpr int kQueueInts = 56;
+// Item queues of the persistent mode: 8 counters per launch, at most 8 launches.
+constexpr int kQueueInts = 64;
 
 struct ZLaunch {
   const BoxDev* boxes;
