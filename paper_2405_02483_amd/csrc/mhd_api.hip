@@ -172,12 +172,26 @@ static ZLaunch make_zlaunch(const mhd_ctx* c) {
 #define MHD_ZCHUNK 128
 #endif
 static constexpr int kZChunk = MHD_ZCHUNK;
+// The z-range of an item: kZChunk planes, halved (down to kZChunkMin) while
+// the items would number fewer than kItemsPerCU per compute unit, so that
+// small boxes still fill the device.  The chunking changes no result: every
+// output plane sums its z contributions in the same order.
+static constexpr int kZChunkMin = 16, kItemsPerCU = 4;
 static void build_items(const mhd_ctx* c, int tile, std::vector<ZItem>& items) {
   const int TX = ztile_x(tile), TY = ztile_y(tile);
+  auto nchunks = [](int nzt, int chunk) { return std::max(1, (nzt + chunk / 2) / chunk); };
+  int chunk = kZChunk;
+  for (;;) {
+    long long n = 0;
+    for (const BoxDev& d : c->h_boxes)
+      n += (long long)nchunks(d.nzt, chunk) * ((d.ny + TY - 1) / TY) * ((d.nx + TX - 1) / TX);
+    if (n >= (long long)kItemsPerCU * c->ncu || chunk / 2 < kZChunkMin) break;
+    chunk /= 2;
+  }
   items.clear();
   for (int b = 0; b < (int)c->h_boxes.size(); ++b) {
     const BoxDev& d = c->h_boxes[b];
-    const int nch = std::max(1, (d.nzt + kZChunk / 2) / kZChunk);
+    const int nch = nchunks(d.nzt, chunk);
     for (int ch = 0; ch < nch; ++ch) {
       const int z0 = (int)((long long)d.nzt * ch / nch), z1 = (int)((long long)d.nzt * (ch + 1) / nch);
       for (int ty = 0; ty < d.ny; ty += TY)

@@ -83,3 +83,26 @@ def test_autotuned_persistent_ensemble_matches_oracle():
         errs = rel_errors(ctx.box_view(fd, b), want)
         assert max(errs) < 1e-5, (b, sizes[b], errs)
     ctx.close()
+
+
+@pytest.mark.parametrize("walls", [False, True])
+def test_z_chunking_changes_no_bits(walls):
+    """Small launches split z into more, shorter chunks (so that the device
+    fills); a box stepped alone (three z-chunks) and the same box inside an
+    ensemble large enough for one chunk per box must agree bit for bit."""
+    from paper_2405_02483_amd.lib import Context
+    if walls:
+        f, box, prm = inputs.stratified(40, 40, 30, seed=7)      # 40 planes with ghosts
+    else:
+        f, box, prm = inputs.turbulent(n=40, seed=11, kmax=3.0)
+    out = []
+    for copies in (1, 110):                  # 10 items per box at 32x8; 1100 >= 4 per CU
+        ctx = Context([box] * copies, prm, dtype=torch.float64)
+        ctx.set_launch("32x8", 0)
+        fd = ctx.upload([f] * copies)
+        ctx.step(fd, 0.0, 2)
+        out.append(([t.clone() for t in ctx.box_view(fd, 0)], ctx.last_dt()))
+        ctx.close()
+    assert out[0][1] == out[1][1]
+    for a, b in zip(out[0][0], out[1][0]):
+        assert torch.equal(a, b)
