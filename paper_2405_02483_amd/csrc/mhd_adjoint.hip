@@ -297,13 +297,16 @@ VPlan plan_program(const VProgram& P) {
     for (int x : {P.code[q].a, P.code[q].b, P.code[q].c})
       if (x >= 0) last[x] = q;
   }
-  // groups: a neighbour operation opens one; pointwise operations join
+  // groups of up to kGroupMax operations; a neighbour operation reads its
+  // operand at neighbouring cells from memory, so it opens a new group only
+  // when that operand is made in the current one
   VPlan R;
   std::vector<int> gid(n), gend;
   for (int q = 0; q < n; ++q) {
-    const int op = P.code[q].op;
-    const bool nb = op == V_STEN || op == V_MAX3 || op == V_MEAN3;
-    if (q == 0 || nb || q - R.groups.back().first == kGroupMax) {
+    const VInstr& I = P.code[q];
+    const bool nb = I.op == V_STEN || I.op == V_MAX3 || I.op == V_MEAN3;
+    const bool dep = nb && !R.groups.empty() && prod[I.a] >= R.groups.back().first;
+    if (q == 0 || dep || q - R.groups.back().first == kGroupMax) {
       if (!R.groups.empty()) gend.push_back(q);
       R.groups.push_back({q, 0});
     }
@@ -366,15 +369,21 @@ VPlan plan_program(const VProgram& P) {
       release[gid[q]].push_back(vphys[x]);
     }
   }
-  // the reverse sweep in groups (fills carry no transpose and are skipped)
-  std::vector<int> border;
+  // the reverse sweep in groups (fills carry no transpose and are skipped);
+  // a neighbour transpose reads its output's cotangent at neighbouring cells,
+  // so it opens a new group only when a transpose of the current group has
+  // added to that cotangent (contrib: position of the last contribution)
+  std::vector<int> border, contrib(S, -1);
   for (int q = n - 1; q >= 0; --q) {
-    const int op = P.code[q].op;
-    if (op == V_FILL) continue;
-    const bool nb = op == V_STEN || op == V_MAX3 || op == V_MEAN3;
-    if (R.bgroups.empty() || nb || (int)border.size() - R.bgroups.back().first == kGroupMax)
+    const VInstr& I = P.code[q];
+    if (I.op == V_FILL) continue;
+    const bool nb = I.op == V_STEN || I.op == V_MAX3 || I.op == V_MEAN3;
+    const bool dep = nb && !R.bgroups.empty() && contrib[I.out] >= R.bgroups.back().first;
+    if (R.bgroups.empty() || dep || (int)border.size() - R.bgroups.back().first == kBGroupMax)
       R.bgroups.push_back({(int)border.size(), 0});
     R.bgroups.back().count++;
+    for (int x : {I.a, I.b, I.c})
+      if (x >= 0) contrib[x] = (int)border.size();
     border.push_back(q);
   }
   // cotangents, allocated in the reverse sweep; a slot is free again at the

@@ -74,6 +74,7 @@ struct VStep {
 // pass through a per-thread register file in LDS and are stored to their
 // value slot only when a later group or a transpose reads them.
 constexpr int kGroupMax = 16;
+constexpr int kBGroupMax = 32;   // transposes per launch of the reverse sweep
 
 struct VFused {
   VInstr f;                  // value slots (f.out: -1 if the result is not stored)
