@@ -12,7 +12,9 @@ Inputs are resident in HBM before timing.
 Prints ONE JSON line:  metric, value (interior cell-updates/s per RK step),
 ms_per_step, the float64 figures of the same workload, the roofline of the
 RK stage (algorithmic bytes per stage / measured stage time, HIP events on
-the library's stream) and the CPU oracle timed on a bounded sample.
+the library's stream; beside the 8 TB/s peak, the bandwidth of a plain 1 GiB
+device copy measured in the same run) and the CPU oracle timed on a bounded
+sample.
 
     python bench.py [--steps K] [--warmup W] [--size N] [--no-fp64]
                     [--no-cpu-baseline]
@@ -124,6 +126,28 @@ def run_gpu(size, dtype, steps, warmup, workload="stratified", tile=None):
                     for k, v in tune.items()},
                 passes={k: (v[0] / max(v[1], 1), v[1]) for k, v in prof.items() if v[1]},
                 dt_last=dt_last, mass=s_end["mass"], ncell=ncell)
+
+
+def stream_copy_gbs(nbytes=1 << 30, reps=10):
+    """Achievable HBM bandwidth on this device: a plain device-to-device copy
+    of nbytes (read once, written once), timed with HIP events on torch's
+    current stream; GB/s counts the bytes read plus the bytes written."""
+    import torch
+    a = torch.ones(nbytes // 4, device="cuda", dtype=torch.float32)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) * 1e-3 / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * nbytes / sec / 1e9
 
 
 def run_adjoint(n=128, nsteps=40, ncheck=None, dtype_name="f32"):
@@ -261,6 +285,8 @@ def main():
     ncell = r32["ncell"]
     stage_bytes = sum(WORDS_PER_STAGE) / 3.0 * 4 * ncell
     achieved = stage_bytes / (r32["stage_ms"] * 1e-3) / 1e9
+    copy_gbs = stream_copy_gbs()
+    log("device copy: %.0f GB/s" % copy_gbs)
     traffic = measured_traffic("f32")
     out = {
         "metric": "MHD cell-updates/s per RK step at 512^3 (FP32; FP64 alongside)",
@@ -286,6 +312,10 @@ def main():
                      "traffic": traffic,
                      "algorithmic_bytes_per_stage": stage_bytes,
                      "stage_ms": r32["stage_ms"],
+                     "stream_copy_GBs": copy_gbs,
+                     "frac_of_copy": achieved / copy_gbs,
+                     "traffic_GBs": (None if traffic is None else
+                                     traffic / (r32["stage_ms"] * 1e-3) / 1e9),
                      "passes_ms": {k: round(v[0], 4) for k, v in r32["passes"].items()}},
         "launch": r32["launch"],
         "autotune_ms_per_rhs": r32["autotune_ms_per_rhs"],
