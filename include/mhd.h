@@ -198,9 +198,10 @@ int mhd_reductions(mhd_ctx* ctx, void* const f[8], void* const dfdt[8],
 int mhd_last_dt(mhd_ctx* ctx, double* dt);
 
 /* Tile shape of the stage kernels: columns per workgroup, 0: 64x4,
- * 1: 32x8, 2: 16x16, 3: 16x8.  Any shape gives the same results (bit for
- * bit); the default is 32x8 (float32) or 16x8 (float64).  Other values:
- * MHD_EINVAL.                                                               */
+ * 1: 32x8, 2: 16x16, 3: 16x8 (256 threads), 4: 64x8 (512 threads, float32
+ * only: MHD_EUNSUPPORTED for float64).  Any shape gives the same results
+ * (bit for bit); the default is 32x8 (float32) or 16x8 (float64).  Other
+ * values: MHD_EINVAL.                                                       */
 int mhd_set_tile(mhd_ctx* ctx, int32_t tile);
 
 /* Tile shape (as mhd_set_tile) and launch mode of the stage kernels.
@@ -217,7 +218,7 @@ int mhd_get_launch(const mhd_ctx* ctx, int32_t* tile, int32_t* persistent);
 /* Autotuner: times reps evaluations of mhd_rhs(f, dfdt) (after one warm-up)
  * in every tile shape and launch mode, keeps the fastest and, if ms is not
  * NULL, writes the milliseconds per evaluation to ms[2 * tile + persistent]
- * (8 entries).  dfdt is overwritten; with walls the ghost planes of f are
+ * (10 entries; 0 for a shape not built for the context's dtype).  dfdt is overwritten; with walls the ghost planes of f are
  * filled.  Waits for the stream.                                            */
 int mhd_autotune(mhd_ctx* ctx, void* const f[8], void* const dfdt[8], int32_t reps,
                  double* ms);

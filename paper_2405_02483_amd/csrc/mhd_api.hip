@@ -857,6 +857,7 @@ int mhd_set_launch(mhd_ctx* c, int32_t tile, int32_t persistent) {
   if (!c) return fail(nullptr, MHD_EINVAL, "ctx is NULL");
   if (tile < 0 || tile >= ZTILE_COUNT) return fail(c, MHD_EINVAL, "unknown tile shape");
   if (persistent != 0 && persistent != 1) return fail(c, MHD_EINVAL, "persistent must be 0 or 1");
+  if (!ztile_ok(tile, c->esize)) return fail(c, MHD_EUNSUPPORTED, "tile shape not built for this dtype");
   int rc = set_tile(c, tile);
   if (rc == MHD_OK) c->persistent = persistent;
   return rc;
@@ -889,6 +890,8 @@ int mhd_autotune(mhd_ctx* c, void* const f[8], void* const dfdt[8], int32_t reps
   int bt = c->tile, bp = c->persistent;
   for (int t = 0; t < ZTILE_COUNT && rc == MHD_OK; ++t)
     for (int m = 0; m < 2 && rc == MHD_OK; ++m) {
+      if (ms) ms[t * 2 + m] = 0.0;
+      if (!ztile_ok(t, c->esize)) continue;
       if ((rc = mhd_set_launch(c, t, m)) != MHD_OK) break;
       rc = mhd_rhs(c, f, dfdt);   // warm-up (and, with walls, the ghost fill)
       (void)hipEventRecord(e0, c->stream);

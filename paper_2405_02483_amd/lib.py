@@ -213,7 +213,7 @@ def mhd_reductions(ctx, f, dfdt=None, *, dtype, n, allow_nonfinite=False):
 
 PASS_NAMES = ("A1", "unused1", "unused2", "A2", "Q", "P", "F", "ghost", "reduce",
               "adjoint")
-TILES = {"64x4": 0, "32x8": 1, "16x16": 2, "16x8": 3}
+TILES = {"64x4": 0, "32x8": 1, "16x16": 2, "16x8": 3, "64x8": 4}
 
 
 def mhd_last_dt(ctx):
@@ -242,7 +242,7 @@ def mhd_get_launch(ctx):
 
 
 def mhd_autotune(ctx, f, dfdt, reps, *, dtype, n):
-    ms = (ctypes.c_double * 8)()
+    ms = (ctypes.c_double * (2 * len(TILES)))()
     _check(load().mhd_autotune(ctx, _ptrs(f, n, dtype, "f"), _ptrs(dfdt, n, dtype, "dfdt"),
                                int(reps), ms), ctx)
     return list(ms)
@@ -378,7 +378,8 @@ class Context:
         dfdt = dfdt if dfdt is not None else self.empty()
         ms = mhd_autotune(self.ctx, f, dfdt, reps, dtype=self.dtype, n=self.n)
         names = {v: k for k, v in TILES.items()}
-        return {(names[q // 2], q % 2): ms[q] for q in range(8)}
+        # shapes not built for this dtype report 0 and are left out
+        return {(names[q // 2], q % 2): ms[q] for q in range(2 * len(TILES)) if ms[q] > 0}
 
     def profile(self, enable=True):
         mhd_profile(self.ctx, enable)

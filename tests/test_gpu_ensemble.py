@@ -19,13 +19,17 @@ def _ensemble(sizes, seed0=5000):
 
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
 def test_persistent_mode_gives_identical_bits(dtype):
-    from paper_2405_02483_amd.lib import Context, TILES
+    from paper_2405_02483_amd.lib import Context, TILES, MhdError, MHD_EUNSUPPORTED
     fields, boxes, prm = _ensemble(inputs.ensemble_sizes(8, (6, 8, 12, 16), seed=5))
     ctx = Context(boxes, prm, dtype=dtype)
     ref = None
     for tile in TILES:
         for persistent in (0, 1):
-            ctx.set_launch(tile, persistent)
+            try:
+                ctx.set_launch(tile, persistent)
+            except MhdError as e:              # a shape not built for this dtype
+                assert e.code == MHD_EUNSUPPORTED and dtype == torch.float64 and tile == "64x8"
+                continue
             assert ctx.get_launch() == (tile, persistent)
             fd = ctx.upload(fields)
             ctx.step(fd, 0.0, 2)            # Courant dt on the device: exercises the partials
@@ -58,7 +62,7 @@ def test_set_launch_rejects_bad_values():
     from paper_2405_02483_amd.lib import Context, MhdError, MHD_EINVAL
     f, box, prm = inputs.turbulent(n=8, seed=3, kmax=2.0)
     ctx = Context(box, prm, dtype=torch.float32)
-    for tile, mode in ((4, 0), (-1, 0), (0, 2)):
+    for tile, mode in ((5, 0), (-1, 0), (0, 2)):
         with pytest.raises(MhdError) as ei:
             ctx.set_launch(tile, mode)
         assert ei.value.code == MHD_EINVAL
@@ -66,13 +70,13 @@ def test_set_launch_rejects_bad_values():
 
 
 def test_autotuned_persistent_ensemble_matches_oracle():
-    from paper_2405_02483_amd.lib import Context
+    from paper_2405_02483_amd.lib import Context, TILES
     sizes = inputs.ensemble_sizes(8, (6, 8, 10, 12), seed=5)
     fields, boxes, prm = _ensemble(sizes)
     ctx = Context(boxes, prm, dtype=torch.float32)
     fd = ctx.upload(fields)
     ms = ctx.autotune(fd, reps=2)
-    assert len(ms) == 8 and all(v > 0 for v in ms.values())
+    assert len(ms) == 2 * len(TILES) and all(v > 0 for v in ms.values())
     assert ms[ctx.get_launch()] == min(ms.values())
     dt = 0.5 * min(O.courant(to_cpu64(f), *grid_params(b, prm))[0] for f, b in zip(fields, boxes))
     fd = ctx.upload(fields)
