@@ -46,7 +46,7 @@ def kernel_source_hash():
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2405_02483_amd", "csrc")
     for name in sorted(os.listdir(d)):
-        if name.endswith((".hip", ".hpp")):
+        if name.endswith((".hip", ".hpp")) or name == "build.py":   # sources and flags
             h.update(open(os.path.join(d, name), "rb").read())
     return h.hexdigest()[:16]
 

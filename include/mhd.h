@@ -198,10 +198,9 @@ int mhd_reductions(mhd_ctx* ctx, void* const f[8], void* const dfdt[8],
 int mhd_last_dt(mhd_ctx* ctx, double* dt);
 
 /* Tile shape of the stage kernels: columns per workgroup, 0: 64x4,
- * 1: 32x8, 2: 16x16, 3: 16x8 (256 threads), 4: 64x8 (512 threads, float32
- * only: MHD_EUNSUPPORTED for float64).  Any shape gives the same results
- * (bit for bit); the default is 32x8 (float32) or 16x8 (float64).  Other
- * values: MHD_EINVAL.                                                       */
+ * 1: 32x8, 2: 16x16, 3: 16x8 (256 threads), 4: 64x8 (512 threads).  Any
+ * shape gives the same results (bit for bit); the default is 32x8
+ * (float32) or 16x8 (float64).  Other values: MHD_EINVAL.                  */
 int mhd_set_tile(mhd_ctx* ctx, int32_t tile);
 
 /* Tile shape (as mhd_set_tile) and launch mode of the stage kernels.

@@ -988,9 +988,7 @@ void launch_zstage(const ZLaunch& L, const ZStageArgs<T>& a) {
     case ZTILE_32x8: launch_zstage_t<T, 32, 8>(L, a); break;
     case ZTILE_16x16: launch_zstage_t<T, 16, 16>(L, a); break;
     case ZTILE_16x8: launch_zstage_t<T, 16, 8>(L, a); break;
-    case ZTILE_64x8:
-      if constexpr (sizeof(T) == 4) launch_zstage_t<T, 64, 8>(L, a);
-      break;
+    case ZTILE_64x8: launch_zstage_t<T, 64, 8>(L, a); break;
     default:
       launch_zstage_t<T, 64, 4>(L, a);
       break;

@@ -27,12 +27,8 @@ template <class T> struct CPQ { const T* p[POUT_COUNT]; };
 // Tile shapes (columns per workgroup, x by y) the stage kernels are built for.
 enum ZTile : int { ZTILE_64x4 = 0, ZTILE_32x8 = 1, ZTILE_16x16 = 2, ZTILE_16x8 = 3, ZTILE_64x8 = 4, ZTILE_COUNT };
 
-// Whether a tile shape is built for an element size: 64x8 only for float32
-// (in float64 its kernels rounded a few viscosity-dependent terms one ulp
-// away from the other shapes, and float64 runs fastest at 16x16 anyway).
-inline bool ztile_ok(int t, size_t esize) {
-  return t >= 0 && t < ZTILE_COUNT && !(t == ZTILE_64x8 && esize != 4);
-}
+// Whether a tile shape is built for an element size (all are).
+inline bool ztile_ok(int t, size_t esize) { (void)esize; return t >= 0 && t < ZTILE_COUNT; }
 
 inline int ztile_x(int t) { return (t == ZTILE_64x4 || t == ZTILE_64x8) ? 64 : (t == ZTILE_32x8 ? 32 : 16); }
 inline int ztile_y(int t) { return t == ZTILE_64x4 ? 4 : (t == ZTILE_16x16 ? 16 : 8); }

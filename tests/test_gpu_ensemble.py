@@ -19,17 +19,13 @@ def _ensemble(sizes, seed0=5000):
 
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
 def test_persistent_mode_gives_identical_bits(dtype):
-    from paper_2405_02483_amd.lib import Context, TILES, MhdError, MHD_EUNSUPPORTED
+    from paper_2405_02483_amd.lib import Context, TILES
     fields, boxes, prm = _ensemble(inputs.ensemble_sizes(8, (6, 8, 12, 16), seed=5))
     ctx = Context(boxes, prm, dtype=dtype)
     ref = None
     for tile in TILES:
         for persistent in (0, 1):
-            try:
-                ctx.set_launch(tile, persistent)
-            except MhdError as e:              # a shape not built for this dtype
-                assert e.code == MHD_EUNSUPPORTED and dtype == torch.float64 and tile == "64x8"
-                continue
+            ctx.set_launch(tile, persistent)
             assert ctx.get_launch() == (tile, persistent)
             fd = ctx.upload(fields)
             ctx.step(fd, 0.0, 2)            # Courant dt on the device: exercises the partials

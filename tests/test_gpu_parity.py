@@ -245,16 +245,12 @@ def test_courant_step_on_device_f64(case):
 
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
 def test_tile_shapes_give_identical_bits(dtype):
-    from paper_2405_02483_amd.lib import TILES, MhdError, MHD_EUNSUPPORTED
+    from paper_2405_02483_amd.lib import TILES
     f, box, prm = _case("turb_ragged")
     ctx = _ctx(box, prm, dtype)
     ref = None
     for name in TILES:
-        try:
-            ctx.set_tile(name)
-        except MhdError as e:                  # a shape not built for this dtype
-            assert e.code == MHD_EUNSUPPORTED and dtype == torch.float64 and name == "64x8"
-            continue
+        ctx.set_tile(name)
         fd = ctx.upload([f])
         ctx.step(fd, 2e-3, 2)
         if ref is None:
