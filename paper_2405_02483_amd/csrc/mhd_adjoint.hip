@@ -452,17 +452,18 @@ VPlan plan_program(const VProgram& P) {
 
 namespace {
 
+// (selects, not a switch: a switch over runtime values becomes a lookup
+// table in scratch memory)
 __device__ __forceinline__ double geo_of(const BoxDev& b, int geo) {
-  switch (geo) {
-    case G_DX: return b.dx;
-    case G_DY: return b.dy;
-    case G_DZ: return b.dz;
-    case G_H: return b.hmin;
-    case G_MXY: return fmax(b.dx, b.dy);
-    case G_MXZ: return fmax(b.dx, b.dz);
-    case G_MYZ: return fmax(b.dy, b.dz);
-    default: return 1.0;
-  }
+  double r = 1.0;
+  r = geo == G_DX ? b.dx : r;
+  r = geo == G_DY ? b.dy : r;
+  r = geo == G_DZ ? b.dz : r;
+  r = geo == G_H ? b.hmin : r;
+  r = geo == G_MXY ? fmax(b.dx, b.dy) : r;
+  r = geo == G_MXZ ? fmax(b.dx, b.dz) : r;
+  r = geo == G_MYZ ? fmax(b.dy, b.dz) : r;
+  return r;
 }
 
 // Value of a at offset m along axis ax from (i, j, k).
@@ -471,11 +472,13 @@ __device__ __forceinline__ T along(const T* a, const Geo<T>& g, int ax, int i, i
   return ax == VX ? a[g.at(i + m, j, k)] : (ax == VY ? a[g.at(i, j + m, k)] : a[g.at(i, j, k + m)]);
 }
 
+// The step's reciprocal comes from the box record in global memory: picking
+// one of a local Geo's fields by a runtime axis would put Geo in scratch.
 template <class T>
-__device__ __forceinline__ T sten(const T* a, const Geo<T>& g, int ax, int fam, int form, int i, int j,
-                                  int k) {
+__device__ __forceinline__ T sten(const T* a, const Geo<T>& g, const BoxDev& bx, int ax, int fam,
+                                  int form, int i, int j, int k) {
   auto at = [&](int m) { return along(a, g, ax, i, j, k, m); };
-  const T hinv = ax == VX ? g.hxi : (ax == VY ? g.hyi : g.hzi);
+  const T hinv = T(1.0 / (ax == VX ? bx.dx : (ax == VY ? bx.dy : bx.dz)));
   if (fam == 0) return form ? op6<0, 1, T>(at, hinv) : op6<0, 0, T>(at, hinv);
   return form ? op6<1, 1, T>(at, hinv) : op6<1, 0, T>(at, hinv);
 }
@@ -511,7 +514,7 @@ __global__ __launch_bounds__(kBlock) void k_vm_group(const BoxDev* boxes, const 
         int i, j, k;
         coords(i, j, k);
         const Geo<T> g(bx_);
-        r = sten(base + I.a * stride, g, I.ax, I.fam, I.form, i, j, k);
+        r = sten(base + I.a * stride, g, bx_, I.ax, I.fam, I.form, i, j, k);
         break;
       }
       case V_MAX3: {
@@ -567,95 +570,208 @@ __global__ __launch_bounds__(kBlock) void k_vm_group(const BoxDev* boxes, const 
   }
 }
 
-// Transposes.  Each thread owns the cotangents of its own cell, so the
+// Transposes.  Each thread owns the cotangents of its own cells, so the
 // gathers of the stencil, max and mean transposes need no atomics; the
 // pointwise rules update the input cotangents one after the other (an input
 // may appear twice, as in a * a: its first contribution overwrites, the
-// second adds).
+// second adds).  A workgroup takes kBwdCells consecutive block-table entries
+// and a thread one cell of each: every transpose first gathers its inputs
+// for all of them, so that many loads are in flight per thread.
+constexpr int kBwdCells = 4;
+
 template <class T>
-__global__ __launch_bounds__(kBlock) void k_vm_bwd(const BoxDev* boxes, const Blk* tab,
+__global__ __launch_bounds__(kBlock) void k_vm_bwd(const BoxDev* boxes, const Blk* tab, int nblk,
                                                    const VStep* __restrict__ code, int first,
                                                    int count, const T* base, T* cbase,
                                                    long long stride) {
-  VM_PROLOGUE
-  for (int jj = 0; jj < count; ++jj) {
-  const VStep S = code[first + jj];
-  const VInstr& I = S.f;
-  const T* a = I.a >= 0 ? base + I.a * stride : nullptr;
-  const T* b = I.b >= 0 ? base + I.b * stride : nullptr;
-  const T* c = I.c >= 0 ? base + I.c * stride : nullptr;
-  T* ca = S.ca >= 0 ? cbase + S.ca * stride : nullptr;
-  T* cb = S.cb >= 0 ? cbase + S.cb * stride : nullptr;
-  T* cc = S.cc >= 0 ? cbase + S.cc * stride : nullptr;
-  const T* yb = cbase + S.cout * stride;
-  auto put = [&](T* dst, int bit, T v) {
-    if (S.over & bit) dst[o] = v;
-    else dst[o] += v;
-  };
-  switch (I.op) {
-    case V_STEN: {
-      // interpolation: S^T = the opposite stagger; derivative: minus it
-      int i, j, k;
-      coords(i, j, k);
-      const Geo<T> g(bx_);
-      const T t = sten(yb, g, I.ax, I.fam, 1 - I.form, i, j, k);
-      put(ca, 1, I.fam ? -t : t);
-      break;
+  constexpr int R = kBwdCells;
+  long long o[R];
+  unsigned q[R];
+  int bi[R];
+  bool ok[R];
+  bool found = false;
+  long long o0 = 0;
+  unsigned q0 = 0;
+  int b0 = 0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int e = (int)blockIdx.x * R + r;
+    ok[r] = false;
+    bi[r] = 0;
+    q[r] = 0;
+    o[r] = 0;
+    if (e < nblk) {
+      const Blk tb = tab[e];
+      ok[r] = (int)threadIdx.x < tb.n;
+      bi[r] = tb.box;
+      q[r] = (unsigned)tb.start + threadIdx.x;
+      o[r] = boxes[tb.box].off + q[r];
+      if (ok[r] && !found) {
+        found = true;
+        o0 = o[r];
+        q0 = q[r];
+        b0 = bi[r];
+      }
     }
-    case V_ADD: put(ca, 1, yb[o]); put(cb, 2, yb[o]); break;
-    case V_SUB: put(ca, 1, yb[o]); put(cb, 2, -yb[o]); break;
-    case V_MUL: {
-      const T y = yb[o], va = a[o], vb = b[o];
-      put(ca, 1, y * vb);
-      put(cb, 2, y * va);
-      break;
-    }
-    case V_DIV: {
-      const T y = yb[o], vb = b[o], q = base[I.out * stride + o];
-      put(ca, 1, y / vb);
-      put(cb, 2, -(y * q / vb));
-      break;
-    }
-    case V_SCALE: put(ca, 1, T(I.k * geo_of(bx_, I.geo)) * yb[o]); break;
-    case V_DIVC: put(ca, 1, yb[o] / T(I.k)); break;
-    case V_SQRT: put(ca, 1, yb[o] / (T(2) * base[I.out * stride + o])); break;
-    case V_LOG: put(ca, 1, yb[o] / a[o]); break;
-    case V_EXP: put(ca, 1, yb[o] * base[I.out * stride + o]); break;
-    case V_RELU: put(ca, 1, a[o] > T(0) ? yb[o] : T(0)); break;
-    case V_FLOOR: put(ca, 1, a[o] > T(I.k) ? yb[o] : T(0)); break;
-    case V_NORM3: {
-      const T nrm = base[I.out * stride + o];
-      const T y = nrm > T(0) ? yb[o] / nrm : T(0);
-      const T va = a[o], vb = b[o], vc = c[o];
-      put(ca, 1, y * va);
-      put(cb, 2, y * vb);
-      put(cc, 4, y * vc);
-      break;
-    }
-    case V_MAX3: {
-      // cell (i) is the hi neighbour of i-1, the middle of i, the lo of i+1
-      int i, j, k;
-      coords(i, j, k);
-      const Geo<T> g(bx_);
-      auto v = [&](int m) { return along(a, g, I.ax, i, j, k, m); };
-      auto w = [&](int m) { return along(yb, g, I.ax, i, j, k, m); };
-      const T vm2 = v(-2), vm1 = v(-1), v0 = a[o], vp1 = v(1), vp2 = v(2);
-      T sum = T(0);
-      if (first_max(vm2, vm1, v0) == 2) sum += w(-1);
-      if (first_max(vm1, v0, vp1) == 1) sum += yb[o];
-      if (first_max(v0, vp1, vp2) == 0) sum += w(1);
-      put(ca, 1, sum);
-      break;
-    }
-    case V_MEAN3: {
-      int i, j, k;
-      coords(i, j, k);
-      const Geo<T> g(bx_);
-      put(ca, 1, (along(yb, g, I.ax, i, j, k, -1) + yb[o] + along(yb, g, I.ax, i, j, k, 1)) / T(3));
-      break;
-    }
-    default: break;
   }
+  if (!found) return;
+  // cells past a table entry's end read a valid cell's data and store nothing
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+    if (!ok[r]) {
+      o[r] = o0;
+      q[r] = q0;
+      bi[r] = b0;
+    }
+  auto coords = [&](int r, int& i, int& j, int& k) {
+    const BoxDev& b = boxes[bi[r]];
+    const unsigned nx_ = (unsigned)b.nx, ny_ = (unsigned)b.ny;
+    const unsigned qx_ = q[r] / nx_, qy_ = qx_ / ny_;
+    i = (int)(q[r] - qx_ * nx_);
+    j = (int)(qx_ - qy_ * ny_);
+    k = (int)qy_;
+  };
+  for (int jj = 0; jj < count; ++jj) {
+    const VStep S = code[first + jj];
+    const VInstr& I = S.f;
+    const T* a = I.a >= 0 ? base + I.a * stride : nullptr;
+    const T* b = I.b >= 0 ? base + I.b * stride : nullptr;
+    const T* c = I.c >= 0 ? base + I.c * stride : nullptr;
+    T* ca = S.ca >= 0 ? cbase + S.ca * stride : nullptr;
+    T* cb = S.cb >= 0 ? cbase + S.cb * stride : nullptr;
+    T* cc = S.cc >= 0 ? cbase + S.cc * stride : nullptr;
+    const T* yb = cbase + S.cout * stride;
+    // the contribution v[r] to dst: overwrite or add, all loads first
+    auto put = [&](T* dst, int bit, const T (&v)[R]) {
+      T cur[R];
+      const bool over = S.over & bit;
+#pragma unroll
+      for (int r = 0; r < R; ++r) cur[r] = over ? T(0) : dst[o[r]];
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+        if (ok[r]) dst[o[r]] = over ? v[r] : cur[r] + v[r];
+    };
+    T y[R], v1[R], v2[R], v3[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) y[r] = yb[o[r]];
+    switch (I.op) {
+      case V_STEN: {
+        // interpolation: S^T = the opposite stagger; derivative: minus it
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          int i, j, k;
+          coords(r, i, j, k);
+          const Geo<T> g(boxes[bi[r]]);
+          const T t = sten(yb, g, boxes[bi[r]], I.ax, I.fam, 1 - I.form, i, j, k);
+          v1[r] = I.fam ? -t : t;
+        }
+        put(ca, 1, v1);
+        break;
+      }
+      case V_ADD:
+      case V_SUB:
+        put(ca, 1, y);
+#pragma unroll
+        for (int r = 0; r < R; ++r) v2[r] = I.op == V_SUB ? -y[r] : y[r];
+        put(cb, 2, v2);
+        break;
+      case V_MUL:
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          v1[r] = y[r] * b[o[r]];
+          v2[r] = y[r] * a[o[r]];
+        }
+        put(ca, 1, v1);
+        put(cb, 2, v2);
+        break;
+      case V_DIV:
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const T vb = b[o[r]], qv = base[I.out * stride + o[r]];
+          v1[r] = y[r] / vb;
+          v2[r] = -(y[r] * qv / vb);
+        }
+        put(ca, 1, v1);
+        put(cb, 2, v2);
+        break;
+      case V_SCALE:
+#pragma unroll
+        for (int r = 0; r < R; ++r) v1[r] = T(I.k * geo_of(boxes[bi[r]], I.geo)) * y[r];
+        put(ca, 1, v1);
+        break;
+      case V_DIVC:
+#pragma unroll
+        for (int r = 0; r < R; ++r) v1[r] = y[r] / T(I.k);
+        put(ca, 1, v1);
+        break;
+      case V_SQRT:
+#pragma unroll
+        for (int r = 0; r < R; ++r) v1[r] = y[r] / (T(2) * base[I.out * stride + o[r]]);
+        put(ca, 1, v1);
+        break;
+      case V_LOG:
+#pragma unroll
+        for (int r = 0; r < R; ++r) v1[r] = y[r] / a[o[r]];
+        put(ca, 1, v1);
+        break;
+      case V_EXP:
+#pragma unroll
+        for (int r = 0; r < R; ++r) v1[r] = y[r] * base[I.out * stride + o[r]];
+        put(ca, 1, v1);
+        break;
+      case V_RELU:
+#pragma unroll
+        for (int r = 0; r < R; ++r) v1[r] = a[o[r]] > T(0) ? y[r] : T(0);
+        put(ca, 1, v1);
+        break;
+      case V_FLOOR:
+#pragma unroll
+        for (int r = 0; r < R; ++r) v1[r] = a[o[r]] > T(I.k) ? y[r] : T(0);
+        put(ca, 1, v1);
+        break;
+      case V_NORM3:
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const T nrm = base[I.out * stride + o[r]];
+          const T w = nrm > T(0) ? y[r] / nrm : T(0);
+          v1[r] = w * a[o[r]];
+          v2[r] = w * b[o[r]];
+          v3[r] = w * c[o[r]];
+        }
+        put(ca, 1, v1);
+        put(cb, 2, v2);
+        put(cc, 4, v3);
+        break;
+      case V_MAX3:
+        // cell (i) is the hi neighbour of i-1, the middle of i, the lo of i+1
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          int i, j, k;
+          coords(r, i, j, k);
+          const Geo<T> g(boxes[bi[r]]);
+          auto v = [&](int m) { return along(a, g, I.ax, i, j, k, m); };
+          auto w = [&](int m) { return along(yb, g, I.ax, i, j, k, m); };
+          const T vm2 = v(-2), vm1 = v(-1), v0 = a[o[r]], vp1 = v(1), vp2 = v(2);
+          T sum = T(0);
+          if (first_max(vm2, vm1, v0) == 2) sum += w(-1);
+          if (first_max(vm1, v0, vp1) == 1) sum += y[r];
+          if (first_max(v0, vp1, vp2) == 0) sum += w(1);
+          v1[r] = sum;
+        }
+        put(ca, 1, v1);
+        break;
+      case V_MEAN3:
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          int i, j, k;
+          coords(r, i, j, k);
+          const Geo<T> g(boxes[bi[r]]);
+          v1[r] = (along(yb, g, I.ax, i, j, k, -1) + y[r] + along(yb, g, I.ax, i, j, k, 1)) / T(3);
+        }
+        put(ca, 1, v1);
+        break;
+      default: break;
+    }
   }
 }
 
@@ -680,9 +796,10 @@ void vm_forward(const VLaunch& L, const VPlan& P, const VFused* d_fused, T* base
 template <class T>
 void vm_backward(const VLaunch& L, const VPlan& P, const VStep* d_bsteps, const T* base, T* cbase,
                  long long stride) {
+  const int grid = (L.nblk + kBwdCells - 1) / kBwdCells;
   for (const VGroup& G : P.bgroups)
-    hipLaunchKernelGGL(k_vm_bwd<T>, dim3(L.nblk), dim3(kBlock), 0, L.stream, L.boxes, L.tab, d_bsteps,
-                       G.first, G.count, base, cbase, stride);
+    hipLaunchKernelGGL(k_vm_bwd<T>, dim3(grid), dim3(kBlock), 0, L.stream, L.boxes, L.tab, L.nblk,
+                       d_bsteps, G.first, G.count, base, cbase, stride);
 }
 
 template <class T> void vm_axpby8(const VLaunch& L, P8<T> y, CP8<T> x, double a, double b) {
