@@ -648,6 +648,8 @@ __global__ __launch_bounds__(TX * TY) void zP(const BoxDev* __restrict__ boxes,
 // Masks: the momenta; rho and e; the magnetic field.
 constexpr unsigned kFMasks[] = {0x0Eu, 0x11u, 0xE0u};
 constexpr int kNFMasks = sizeof(kFMasks) / sizeof(kFMasks[0]);
+// queue counters, 8 per launch: A1, A2, Q edges, P, the F launches, then Q's
+// z-face and centre launch
 static_assert(32 + 8 * kNFMasks + 8 <= kQueueInts && kQueueInts <= 64, "queue counters per launch");
 constexpr bool masks_partition() {
   unsigned all = 0;
@@ -659,7 +661,7 @@ constexpr bool masks_partition() {
 }
 static_assert(masks_partition(), "each field completed by exactly one launch");
 template <unsigned FM> __host__ __device__ constexpr bool hasf(int v) { return (FM >> v) & 1u; }
-// the field each LDS strip serves: x strips, y strips (see zF)
+// the field each LDS strip serves, in zF's strip order: x strips, y strips
 __host__ __device__ constexpr int kXOwn[9] = {0, 1, 2, 2, 4, 3, 3, 7, 4};
 __host__ __device__ constexpr int kYOwn[9] = {0, 1, 1, 2, 4, 3, 3, 7, 4};
 // LDS position of strip q among the strips a launch loads (own: kXOwn or
@@ -967,7 +969,7 @@ static void launch_zstage_m(const ZLaunch& L, const ZStageArgs<T>& a) {
   hipLaunchKernelGGL((zQ<T, TX, TY, PERS, QM_EDGES>), grid((const void*)zQ<T, TX, TY, PERS, QM_EDGES>), block, 0,
                      L.stream, L.boxes, L.items, n, a.ztab, q ? q + 16 : q, a.f, a.ph, a.w);
   hipLaunchKernelGGL((zQ<T, TX, TY, PERS, QM_ZC>), grid((const void*)zQ<T, TX, TY, PERS, QM_ZC>), block, 0,
-                     L.stream, L.boxes, L.items, n, a.ztab, q ? q + 56 : q, a.f, a.ph, a.w);
+                     L.stream, L.boxes, L.items, n, a.ztab, q ? q + 32 + 8 * kNFMasks : q, a.f, a.ph, a.w);
   L.at(PASS_CF);
   hipLaunchKernelGGL((zP<T, TX, TY, PERS>), grid((const void*)zP<T, TX, TY, PERS>), block, 0, L.stream, L.boxes,
                      L.items, n, a.ztab, q ? q + 24 : q, a.f, a.ph, a.w);
