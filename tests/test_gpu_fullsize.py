@@ -205,3 +205,42 @@ def test_turbulent_256_rhs_and_step_sampled(turb256, dtype):
     print("step", dtype, c, ["%.1e" % e for e in errs])
     assert max(errs) < tol_step, (c, errs)
     ctx.close()
+
+
+# ---------------------------------------------------------------------------
+# The 512^3 isothermal atmosphere at rest (no velocity noise, uniform
+# vertical field) in float64: hydrostatic balance holds to truncation, which
+# at this resolution is below rounding, so the state must stay at rest.  The
+# state is horizontally uniform, so every column of the right-hand side must
+# be the same, and a 6 x 6 x 512 oracle box (periodic in x and y) gives that
+# column exactly.
+
+def test_static_atmosphere_512_float64():
+    from paper_2405_02483_amd.lib import Context
+    f, box, prm = inputs.stratified(N, N, N, seed=3, noise=0.0)
+    ctx = Context(box, prm, dtype=torch.float64)
+    fd = ctx.upload([f])
+    nzt = N + 2 * box["ngz"]
+    F = [t.view(nzt, N, N) for t in ctx.box_view(ctx.rhs(fd), 0)]
+    for v, t in enumerate(F):
+        assert torch.equal(t, t[:, :1, :1].expand_as(t)), v      # identical columns
+    # the oracle on a 6 x 6 box of the same columns
+    sub = [torch.from_numpy(np.ascontiguousarray(np.asarray(a)[:, :6, :6])).to(torch.float64) for a in f]
+    wbox = dict(box, nx=6, ny=6, Lx=box["Lx"] * 6 / N, Ly=box["Ly"] * 6 / N)
+    g, p = grid_params(wbox, prm)
+    want = O.rhs(tuple(sub), g, p)
+    # the momentum residual cancels the pressure gradient and gravity (size
+    # g rho, about 4): compare absolutely against that scale
+    scale = float(prm["gz"]) * float(torch.as_tensor(np.asarray(f[0])).max())
+    for v in range(8):
+        err = float((F[v][:, 0, 0].cpu() - want[v][:, 0, 0]).abs().max())
+        assert err <= 1e-12 * scale, (v, err, scale)
+    # ten Courant steps: the gas stays at rest to rounding
+    s0 = ctx.reductions(fd)
+    ctx.step(fd, 0.0, 10)
+    s1 = ctx.reductions(fd)
+    cs = math.sqrt(prm["gamma"])                     # isothermal: P = rho
+    print("max |u| / c_s after 10 steps: %.2e" % (s1["umax"] / cs))
+    assert s1["umax"] / cs <= 1e-10
+    assert abs(s1["mass"] - s0["mass"]) <= 1e-13 * s0["mass"]
+    ctx.close()
