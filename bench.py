@@ -42,17 +42,21 @@ def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash():
-    """Hash of what builds the forward stage kernels (sources and build
-    flags; the adjoint's own sources are left out): the committed traffic
-    counters are used only while it matches."""
+def kernel_source_hash(root=ROOT):
+    """Hash of what builds the forward stage kernels: their sources without
+    `//` comments and blank lines, and the build flags (the adjoint's own
+    sources are left out).  The committed traffic counters are used only
+    while it matches."""
     h = hashlib.sha256()
-    d = os.path.join(ROOT, "paper_2405_02483_amd", "csrc")
+    d = os.path.join(root, "paper_2405_02483_amd", "csrc")
     for name in sorted(os.listdir(d)):
         if name.startswith("mhd_adjoint."):
             continue
         if name.endswith((".hip", ".hpp")) or name == "build.py":
-            h.update(open(os.path.join(d, name), "rb").read())
+            for line in open(os.path.join(d, name), encoding="utf-8"):
+                code = (line.split("#", 1)[0] if name.endswith(".py") else line.split("//", 1)[0]).strip()
+                if code:
+                    h.update(code.encode() + b"\n")
     return h.hexdigest()[:16]
 
 

@@ -229,9 +229,9 @@ enum {
     MHD_PASS_NUS = 1,       /* (unused)                                        */
     MHD_PASS_MAX3 = 2,      /* (unused)                                        */
     MHD_PASS_MEAN3 = 3,     /* A2: max over three cells, three-cell mean, log  */
-    MHD_PASS_EDGES = 4,     /* Q: x/y-edge quantities, Hz, Gzz                 */
+    MHD_PASS_EDGES = 4,     /* Q (two launches): x/y-edge quantities; Hz, Gzz  */
     MHD_PASS_CF = 5,        /* P: z-edge quantities, centre stresses, Hx, Hy   */
-    MHD_PASS_FINAL = 6,     /* F: remaining terms, divergences, RK update      */
+    MHD_PASS_FINAL = 6,     /* F (three launches): divergences, RK update      */
     MHD_PASS_GHOST = 7,     /* closed-wall ghost zones                          */
     MHD_PASS_REDUCE = 8,    /* float64 reductions incl. their viscosity chain   */
     MHD_PASS_ADJOINT = 9,   /* adjoint kernels                                  */

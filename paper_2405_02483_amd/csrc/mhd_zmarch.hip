@@ -1,7 +1,8 @@
 // z-marching kernels of one RK stage (the production forward path).
 //
-// Five passes per stage, each a single launch over all (box, tile, z-range)
-// work items:
+// Five passes per stage, in eight launches over all (box, tile, z-range)
+// work items (Q in two: edges, then z-face and centre terms; F in three, one
+// per field group):
 //   A1  face velocity u_z, div u, and the speed-like viscosity
 //       nu1|u| + nu3(c_s + c_A) + nu2 h max(0, -div u)         (eq. RMnu)
 //   A2  maximum over three cells then three-cell mean, floor, ln  (Section 6.1.1)
