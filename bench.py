@@ -121,6 +121,7 @@ def run_gpu(size, dtype, steps, warmup, workload="stratified", tile=None):
     prof = ctx.profile_read()
     ctx.profile(False)
     launch = ctx.get_launch()
+    ftile = ctx.get_final_tile()
     dt_last = ctx.last_dt()
     s_end = ctx.reductions(f)
     ctx.close()
@@ -129,7 +130,7 @@ def run_gpu(size, dtype, steps, warmup, workload="stratified", tile=None):
     ms = (t1 - t0) * 1e3 / steps
     stage_ms = sum(prof[p][0] for p in STAGE_PASSES) / (3 * steps)
     return dict(ms_per_step=ms, value=ncell * steps / (t1 - t0), stage_ms=stage_ms,
-                launch={"tile": launch[0], "persistent": launch[1]},
+                launch={"tile": launch[0], "persistent": launch[1], "final_pass_tile": ftile},
                 autotune_ms_per_rhs=None if tune is None else {
                     "%s/%s" % (k[0], "persistent" if k[1] else "grid"): round(v, 4)
                     for k, v in tune.items()},
@@ -231,6 +232,7 @@ def run_ensemble(nbox=96, nsteps=20, ncheck=None):
     torch.cuda.synchronize()
     t3 = time.perf_counter()
     tile, mode = ctx.get_launch()
+    ftile = ctx.get_final_tile()
     ctx.close()
     torch.cuda.empty_cache()
     return {"workload": "%d boxes (48/64/80/96)^3 turbulent, float32, %d RK steps, %d checkpoints"
@@ -238,7 +240,7 @@ def run_ensemble(nbox=96, nsteps=20, ncheck=None):
             "cells": ncell, "value": ncell * nsteps / (t1 - t0), "unit": "cell-updates/s",
             "forward_ms": (t1 - t0) * 1e3, "rollout_forward_ms": (t2 - t1) * 1e3,
             "backward_ms": (t3 - t2) * 1e3, "adjoint_over_forward": (t3 - t2) / (t1 - t0),
-            "launch": {"tile": tile, "persistent": mode},
+            "launch": {"tile": tile, "persistent": mode, "final_pass_tile": ftile},
             "autotune_ms_per_rhs": {"%s/%s" % (k[0], "persistent" if k[1] else "grid"): round(v, 4)
                                     for k, v in tune.items()}}
 

@@ -214,11 +214,20 @@ int mhd_set_launch(mhd_ctx* ctx, int32_t tile, int32_t persistent);
 /* Current tile shape and launch mode.                                      */
 int mhd_get_launch(const mhd_ctx* ctx, int32_t* tile, int32_t* persistent);
 
+/* Tile shape of pass F alone (the divergences and the RK stage update), as
+ * mhd_set_tile; mhd_set_tile and mhd_set_launch set it to their own shape.
+ * Results are the same bit for bit.  MHD_EINVAL on other values.            */
+int mhd_set_final_tile(mhd_ctx* ctx, int32_t tile);
+int mhd_get_final_tile(const mhd_ctx* ctx, int32_t* tile);
+
 /* Autotuner: times reps evaluations of mhd_rhs(f, dfdt) (after one warm-up)
  * in every tile shape and launch mode, keeps the fastest and, if ms is not
  * NULL, writes the milliseconds per evaluation to ms[2 * tile + persistent]
- * (10 entries; 0 for a shape not built for the context's dtype).  dfdt is overwritten; with walls the ghost planes of f are
- * filled.  Waits for the stream.                                            */
+ * (10 entries; 0 for a shape not built for the context's dtype).  Then, with
+ * that shape for the other passes, times every shape for pass F alone in
+ * both modes, and keeps the fastest combination if it beats the uniform
+ * launch by more than 2 % (mhd_get_launch, mhd_get_final_tile).  dfdt is overwritten; with walls the ghost
+ * planes of f are filled.  Waits for the stream.                           */
 int mhd_autotune(mhd_ctx* ctx, void* const f[8], void* const dfdt[8], int32_t reps,
                  double* ms);
 

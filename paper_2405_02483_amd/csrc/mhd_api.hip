@@ -45,6 +45,9 @@ struct mhd_ctx {
   // z-march stage kernels: work items, tile shape, Courant partials, dt
   ZItem* d_items = nullptr;
   int nitems = 0;
+  ZItem* d_fitems = nullptr;       // pass F's own work items (tile ftile)
+  int nfitems = 0;
+  int ftile = ZTILE_32x8;
   int tile = ZTILE_32x8;
   CPart* d_cpart = nullptr;
   int* d_queue = nullptr;          // item queues of the persistent launch mode
@@ -156,6 +159,9 @@ static ZLaunch make_zlaunch(const mhd_ctx* c) {
   L.items = c->d_items;
   L.nitems = c->nitems;
   L.tile = c->tile;
+  L.fitems = c->d_fitems;
+  L.nfitems = c->nfitems;
+  L.ftile = c->ftile;
   L.queue = c->d_queue;
   L.persistent = c->persistent;
   L.ncu = c->ncu;
@@ -209,14 +215,15 @@ static void build_items(const mhd_ctx* c, int tile, std::vector<ZItem>& items) {
   }
 }
 
-static int set_tile(mhd_ctx* c, int tile) {
+// Uploads the work items of a tile shape; *d and *n are replaced.
+static int upload_items(mhd_ctx* c, int tile, ZItem** d, int* n, CPart** cpart) {
   std::vector<ZItem> items;
   build_items(c, tile, items);
   ZItem* di = nullptr;
   CPart* dp = nullptr;
   hipError_t e;
   if ((e = hipMalloc(&di, sizeof(ZItem) * items.size())) != hipSuccess ||
-      (e = hipMalloc(&dp, sizeof(CPart) * items.size())) != hipSuccess) {
+      (cpart && (e = hipMalloc(&dp, sizeof(CPart) * items.size())) != hipSuccess)) {
     (void)hipFree(di);
     return fail(c, MHD_ENOMEM, std::string("work item tables: ") + hipGetErrorString(e));
   }
@@ -226,13 +233,29 @@ static int set_tile(mhd_ctx* c, int tile) {
     return hipfail(c, e, "work item upload");
   }
   if (c->stream) (void)hipStreamSynchronize(c->stream);
-  (void)hipFree(c->d_items);
-  (void)hipFree(c->d_cpart);
-  c->d_items = di;
-  c->d_cpart = dp;
-  c->nitems = (int)items.size();
-  c->tile = tile;
+  (void)hipFree(*d);
+  *d = di;
+  *n = (int)items.size();
+  if (cpart) {
+    (void)hipFree(*cpart);
+    *cpart = dp;
+  }
   return MHD_OK;
+}
+
+// Pass F alone (its kernels read no per-item partials).
+static int set_ftile(mhd_ctx* c, int tile) {
+  const int rc = upload_items(c, tile, &c->d_fitems, &c->nfitems, nullptr);
+  if (rc == MHD_OK) c->ftile = tile;
+  return rc;
+}
+
+// Every pass.
+static int set_tile(mhd_ctx* c, int tile) {
+  int rc = upload_items(c, tile, &c->d_items, &c->nitems, &c->d_cpart);
+  if (rc != MHD_OK) return rc;
+  c->tile = tile;
+  return set_ftile(c, tile);
 }
 
 template <class T> static P8<T> p8(void* const f[8]) {
@@ -322,6 +345,7 @@ void mhd_destroy(mhd_ctx* c) {
   (void)hipFree(c->d_fused);
   (void)hipFree(c->d_bsteps);
   (void)hipFree(c->d_items);
+  (void)hipFree(c->d_fitems);
   (void)hipFree(c->d_cpart);
   (void)hipFree(c->d_dt);
   (void)hipFree(c->d_queue);
@@ -870,6 +894,19 @@ int mhd_get_launch(const mhd_ctx* c, int32_t* tile, int32_t* persistent) {
   return MHD_OK;
 }
 
+int mhd_set_final_tile(mhd_ctx* c, int32_t tile) {
+  if (!c) return fail(nullptr, MHD_EINVAL, "ctx is NULL");
+  if (tile < 0 || tile >= ZTILE_COUNT) return fail(c, MHD_EINVAL, "unknown tile shape");
+  if (!ztile_ok(tile, c->esize)) return fail(c, MHD_EUNSUPPORTED, "tile shape not built for this dtype");
+  return set_ftile(c, tile);
+}
+
+int mhd_get_final_tile(const mhd_ctx* c, int32_t* tile) {
+  if (!c || !tile) return MHD_EINVAL;
+  *tile = c->ftile;
+  return MHD_OK;
+}
+
 int mhd_autotune(mhd_ctx* c, void* const f[8], void* const dfdt[8], int32_t reps, double* ms) {
   if (!c) return fail(nullptr, MHD_EINVAL, "ctx is NULL");
   int rc;
@@ -886,6 +923,20 @@ int mhd_autotune(mhd_ctx* c, void* const f[8], void* const dfdt[8], int32_t reps
   }
   const bool prof = c->prof;
   c->prof = false;
+  // milliseconds per mhd_rhs in the current launch configuration
+  auto timed = [&](double& per) {
+    int r0 = mhd_rhs(c, f, dfdt);   // warm-up (and, with walls, the ghost fill)
+    (void)hipEventRecord(e0, c->stream);
+    for (int r = 0; r < reps && r0 == MHD_OK; ++r) r0 = mhd_rhs(c, f, dfdt);
+    (void)hipEventRecord(e1, c->stream);
+    float el = 0.0f;
+    if (r0 == MHD_OK && (hipEventSynchronize(e1) != hipSuccess ||
+                         hipEventElapsedTime(&el, e0, e1) != hipSuccess))
+      r0 = fail(c, MHD_EHIP, "autotune timing");
+    per = (double)el / reps;
+    return r0;
+  };
+  // every pass in one shape and mode
   double best = -1.0;
   int bt = c->tile, bp = c->persistent;
   for (int t = 0; t < ZTILE_COUNT && rc == MHD_OK; ++t)
@@ -893,15 +944,8 @@ int mhd_autotune(mhd_ctx* c, void* const f[8], void* const dfdt[8], int32_t reps
       if (ms) ms[t * 2 + m] = 0.0;
       if (!ztile_ok(t, c->esize)) continue;
       if ((rc = mhd_set_launch(c, t, m)) != MHD_OK) break;
-      rc = mhd_rhs(c, f, dfdt);   // warm-up (and, with walls, the ghost fill)
-      (void)hipEventRecord(e0, c->stream);
-      for (int r = 0; r < reps && rc == MHD_OK; ++r) rc = mhd_rhs(c, f, dfdt);
-      (void)hipEventRecord(e1, c->stream);
-      float el = 0.0f;
-      if (rc == MHD_OK && (hipEventSynchronize(e1) != hipSuccess ||
-                           hipEventElapsedTime(&el, e0, e1) != hipSuccess))
-        rc = fail(c, MHD_EHIP, "autotune timing");
-      const double per = (double)el / reps;
+      double per = 0.0;
+      rc = timed(per);
       if (ms) ms[t * 2 + m] = per;
       if (rc == MHD_OK && (best < 0.0 || per < best)) {
         best = per;
@@ -909,11 +953,34 @@ int mhd_autotune(mhd_ctx* c, void* const f[8], void* const dfdt[8], int32_t reps
         bp = m;
       }
     }
+  // then pass F's own shape, with the others' shape fixed, in both modes:
+  // a change only if it is faster by more than the timing noise (2 %)
+  double tf[2][ZTILE_COUNT];
+  for (int m = 0; m < 2 && rc == MHD_OK; ++m) {
+    if ((rc = mhd_set_launch(c, bt, m)) != MHD_OK) break;
+    for (int t = 0; t < ZTILE_COUNT && rc == MHD_OK; ++t) {
+      tf[m][t] = -1.0;
+      if (!ztile_ok(t, c->esize)) continue;
+      if ((rc = set_ftile(c, t)) != MHD_OK) break;
+      rc = timed(tf[m][t]);
+    }
+  }
+  int bm = bp, bf = bt;
+  if (rc == MHD_OK) {
+    const double base = tf[bp][bt];
+    for (int m = 0; m < 2; ++m)
+      for (int t = 0; t < ZTILE_COUNT; ++t)
+        if (tf[m][t] > 0.0 && tf[m][t] < 0.98 * base && tf[m][t] < tf[bm][bf]) {
+          bm = m;
+          bf = t;
+        }
+    rc = mhd_set_launch(c, bt, bm);
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   c->prof = prof;
   if (rc != MHD_OK) return rc;
-  return mhd_set_launch(c, bt, bp);
+  return set_ftile(c, bf);
 }
 
 }  // extern "C"

@@ -918,7 +918,7 @@ __global__ __launch_bounds__(256) void k_dt(const BoxDev* __restrict__ boxes,
 template <class T, int TX, int TY, bool PERS, unsigned FM, class G>
 static void zF_one(const G& grid, dim3 block, const ZLaunch& L, const ZStageArgs<T>& a, int* q) {
   hipLaunchKernelGGL((zF<T, TX, TY, PERS, FM>), grid((const void*)zF<T, TX, TY, PERS, FM>), block, 0, L.stream,
-                     L.boxes, L.items, L.nitems, a.ztab, q, a.f, a.w, a.ph, a.du, a.du_mode, a.f_out, a.alpha,
+                     L.boxes, L.fitems, L.nfitems, a.ztab, q, a.f, a.w, a.ph, a.du, a.du_mode, a.f_out, a.alpha,
                      a.beta, a.dt_dev, a.dt_host);
 }
 // one launch per mask, each with its own 8 queue counters
@@ -942,6 +942,29 @@ static int resident_groups(const void* kern, int block, int ncu) {
   int nb = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, block, 0) != hipSuccess || nb < 1) nb = 1;
   return cache[kern] = nb * ncu;
+}
+
+// Pass F, in its own tile shape (L.ftile) over its own work items.
+template <class T, int TX, int TY, bool PERS>
+static void launch_final_t(const ZLaunch& L, const ZStageArgs<T>& a, int* q) {
+  const int n = L.nfitems;
+  auto grid = [&](const void* kern) {
+    if (!q) return dim3(8 * ((n + 7) / 8));
+    const int r = std::min(n, resident_groups(kern, TX * TY, L.ncu));
+    return dim3(std::max(8, r - r % 8));
+  };
+  zF_launch<T, TX, TY, PERS>(grid, dim3(TX * TY), L, a, q, std::make_index_sequence<kNFMasks>{});
+}
+
+template <class T, bool PERS>
+static void launch_final(const ZLaunch& L, const ZStageArgs<T>& a, int* q) {
+  switch (L.ftile) {
+    case ZTILE_32x8: launch_final_t<T, 32, 8, PERS>(L, a, q); break;
+    case ZTILE_16x16: launch_final_t<T, 16, 16, PERS>(L, a, q); break;
+    case ZTILE_16x8: launch_final_t<T, 16, 8, PERS>(L, a, q); break;
+    case ZTILE_64x8: launch_final_t<T, 64, 8, PERS>(L, a, q); break;
+    default: launch_final_t<T, 64, 4, PERS>(L, a, q); break;
+  }
 }
 
 template <class T, int TX, int TY, bool PERS>
@@ -975,7 +998,7 @@ static void launch_zstage_m(const ZLaunch& L, const ZStageArgs<T>& a) {
   hipLaunchKernelGGL((zP<T, TX, TY, PERS>), grid((const void*)zP<T, TX, TY, PERS>), block, 0, L.stream, L.boxes,
                      L.items, n, a.ztab, q ? q + 24 : q, a.f, a.ph, a.w);
   L.at(PASS_FINAL);
-  zF_launch<T, TX, TY, PERS>(grid, block, L, a, q, std::make_index_sequence<kNFMasks>{});
+  launch_final<T, PERS>(L, a, q);
   L.at(PASS_END);
 }
 

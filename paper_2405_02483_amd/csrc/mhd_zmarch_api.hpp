@@ -55,6 +55,9 @@ struct ZLaunch {
   const ZItem* items;     // device
   int nitems;
   int tile;               // ZTile of these items
+  const ZItem* fitems;    // device: the work items of pass F, of tile ftile
+  int nfitems;
+  int ftile;
   int* queue;             // device, kQueueInts counters (persistent mode)
   int persistent;         // 0: one workgroup per item; 1: item queues
   int ncu;                // compute units of the device

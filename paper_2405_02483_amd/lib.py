@@ -20,7 +20,8 @@ __all__ = [
     "mhd_init", "mhd_destroy", "mhd_last_error", "mhd_field_elems",
     "mhd_box_offset", "mhd_rhs", "mhd_step", "mhd_step_adjoint",
     "mhd_reductions", "mhd_profile", "mhd_profile_read", "mhd_last_dt", "mhd_set_tile",
-    "mhd_set_launch", "mhd_get_launch", "mhd_autotune", "mhd_rhs_adjoint",
+    "mhd_set_launch", "mhd_get_launch", "mhd_set_final_tile", "mhd_get_final_tile",
+    "mhd_autotune", "mhd_rhs_adjoint",
     "PASS_NAMES", "TILES", "Context",
 ]
 
@@ -127,6 +128,10 @@ def load():
     L.mhd_set_launch.restype = ctypes.c_int
     L.mhd_get_launch.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
     L.mhd_get_launch.restype = ctypes.c_int
+    L.mhd_set_final_tile.argtypes = [vp, i32]
+    L.mhd_set_final_tile.restype = ctypes.c_int
+    L.mhd_get_final_tile.argtypes = [vp, ctypes.POINTER(i32)]
+    L.mhd_get_final_tile.restype = ctypes.c_int
     L.mhd_autotune.argtypes = [vp, _P8, _P8, i32, ctypes.POINTER(ctypes.c_double)]
     L.mhd_autotune.restype = ctypes.c_int
     L.mhd_profile.argtypes = [vp, i32]
@@ -239,6 +244,16 @@ def mhd_get_launch(ctx):
     t, m = ctypes.c_int32(), ctypes.c_int32()
     _check(load().mhd_get_launch(ctx, ctypes.byref(t), ctypes.byref(m)), ctx)
     return t.value, m.value
+
+
+def mhd_set_final_tile(ctx, tile):
+    _check(load().mhd_set_final_tile(ctx, int(tile)), ctx)
+
+
+def mhd_get_final_tile(ctx):
+    t = ctypes.c_int32()
+    _check(load().mhd_get_final_tile(ctx, ctypes.byref(t)), ctx)
+    return t.value
 
 
 def mhd_autotune(ctx, f, dfdt, reps, *, dtype, n):
@@ -371,6 +386,13 @@ class Context:
     def get_launch(self):
         t, m = mhd_get_launch(self.ctx)
         return {v: k for k, v in TILES.items()}[t], m
+
+    def set_final_tile(self, tile):
+        """Tile shape of pass F alone (set_tile / set_launch reset it)."""
+        mhd_set_final_tile(self.ctx, TILES[tile] if isinstance(tile, str) else tile)
+
+    def get_final_tile(self):
+        return {v: k for k, v in TILES.items()}[mhd_get_final_tile(self.ctx)]
 
     def autotune(self, f, reps=3, dfdt=None):
         """Times every tile shape and launch mode on f and keeps the fastest;

@@ -73,7 +73,9 @@ def test_autotuned_persistent_ensemble_matches_oracle():
     fd = ctx.upload(fields)
     ms = ctx.autotune(fd, reps=2)
     assert len(ms) == 2 * len(TILES) and all(v > 0 for v in ms.values())
-    assert ms[ctx.get_launch()] == min(ms.values())
+    # the shape of the fastest uniform launch; the mode and pass F's shape
+    # may then change where that is faster still
+    assert ctx.get_launch()[0] == min(ms, key=ms.get)[0]
     dt = 0.5 * min(O.courant(to_cpu64(f), *grid_params(b, prm))[0] for f, b in zip(fields, boxes))
     fd = ctx.upload(fields)
     ctx.step(fd, dt, 1)
@@ -106,3 +108,33 @@ def test_z_chunking_changes_no_bits(walls):
     assert out[0][1] == out[1][1]
     for a, b in zip(out[0][0], out[1][0]):
         assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_final_pass_tile_gives_identical_bits(dtype):
+    """Pass F in its own tile shape (its own work items and z-chunks) gives
+    the same bits as the uniform launch; set_launch resets it."""
+    from paper_2405_02483_amd.lib import Context, MhdError, MHD_EINVAL
+    fields, boxes, prm = _ensemble(inputs.ensemble_sizes(6, (6, 10, 16), seed=6))
+    ctx = Context(boxes, prm, dtype=dtype)
+    ctx.set_launch("32x8", 0)
+    assert ctx.get_final_tile() == "32x8"
+    fd = ctx.upload(fields)
+    ctx.step(fd, 0.0, 2)
+    ref = ([t.clone() for t in fd], ctx.last_dt())
+    for tile, ftile, persistent in (("16x16", "64x8", 0), ("64x8", "16x8", 1), ("32x8", "64x4", 1)):
+        ctx.set_launch(tile, persistent)
+        ctx.set_final_tile(ftile)
+        assert ctx.get_launch() == (tile, persistent) and ctx.get_final_tile() == ftile
+        fd = ctx.upload(fields)
+        ctx.step(fd, 0.0, 2)
+        assert ctx.last_dt() == ref[1]
+        for a, b in zip(fd, ref[0]):
+            assert torch.equal(a, b), (tile, ftile, persistent)
+    ctx.set_launch("16x8", 0)
+    assert ctx.get_final_tile() == "16x8"
+    for bad in (-1, 5):
+        with pytest.raises(MhdError) as ei:
+            ctx.set_final_tile(bad)
+        assert ei.value.code == MHD_EINVAL
+    ctx.close()

@@ -70,5 +70,7 @@ def test_null_arguments():
     assert L.mhd_set_launch(None, 0, 0) == lib.MHD_EINVAL
     t, m = ctypes.c_int32(), ctypes.c_int32()
     assert L.mhd_get_launch(None, ctypes.byref(t), ctypes.byref(m)) == lib.MHD_EINVAL
+    assert L.mhd_set_final_tile(None, 0) == lib.MHD_EINVAL
+    assert L.mhd_get_final_tile(None, ctypes.byref(t)) == lib.MHD_EINVAL
     assert L.mhd_autotune(None, null8, null8, 1, None) == lib.MHD_EINVAL
     L.mhd_destroy(None)
