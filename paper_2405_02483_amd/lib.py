@@ -395,12 +395,13 @@ class Context:
         return {v: k for k, v in TILES.items()}[mhd_get_final_tile(self.ctx)]
 
     def autotune(self, f, reps=3, dfdt=None):
-        """Times every tile shape and launch mode on f and keeps the fastest;
-        returns {(tile, persistent): ms per right-hand side}."""
+        """Times every tile shape and launch mode on f and keeps the fastest
+        (then, possibly, another shape for pass F alone: get_final_tile);
+        returns {(tile, persistent): ms per right-hand side} of the uniform
+        launches."""
         dfdt = dfdt if dfdt is not None else self.empty()
         ms = mhd_autotune(self.ctx, f, dfdt, reps, dtype=self.dtype, n=self.n)
         names = {v: k for k, v in TILES.items()}
-        # shapes not built for this dtype report 0 and are left out
         return {(names[q // 2], q % 2): ms[q] for q in range(2 * len(TILES)) if ms[q] > 0}
 
     def profile(self, enable=True):
