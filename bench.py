@@ -17,7 +17,8 @@ device copy measured in the same run) and the CPU oracle timed on a bounded
 sample.
 
     python bench.py [--steps K] [--warmup W] [--size N] [--no-fp64]
-                    [--no-cpu-baseline]
+                    [--no-cpu-baseline] [--no-adjoint] [--tile TXxTY]
+    python bench.py --cpu-table     (the CPU oracle alone, 32^3..256^3)
 """
 import argparse
 import hashlib
@@ -264,6 +265,52 @@ def cpu_baseline(n=192, nsteps=1):
                       "float64, %.1f s" % (nsteps, n, el)}
 
 
+def cpu_table(sizes=(32, 64, 128, 256)):
+    """The float64 CPU oracle's RK-step rate on the stratified workload at
+    several sizes, with one thread and with all of torch's threads: the
+    median over a few steps (one step at the largest sizes; the single
+    thread skips 256^3).  Host-side only."""
+    import statistics
+    import torch
+    import oracle as O
+    from paper_2405_02483_amd import inputs
+    nthr = torch.get_num_threads()
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    rows = []
+    for n in sizes:
+        f, box, prm = inputs.stratified(n, n, n, seed=3)
+        ft = tuple(torch.from_numpy(a) for a in f)
+        g = O.Grid(**box)
+        p = O.Params(**{k: v for k, v in prm.items() if k in O.Params.__dataclass_fields__})
+        dt = O.courant(ft, g, p)[0]
+        for threads in (1, nthr):
+            if threads == 1 and n >= 256:
+                continue
+            torch.set_num_threads(threads)
+            steps = 5 if n <= 64 else (3 if n <= 128 else 1)
+            if n <= 64:
+                O.step(ft, g, p, dt, 1)              # warm-up
+            times = []
+            for _ in range(steps):
+                t0 = time.perf_counter()
+                O.step(ft, g, p, dt, 1)
+                times.append(time.perf_counter() - t0)
+            med = statistics.median(times)
+            rows.append({"n": n, "threads": threads, "steps": steps, "median_s_per_step": med,
+                         "cell_updates_per_s": n ** 3 / med})
+            log("cpu oracle %d^3, %d threads: %.3g s per step" % (n, threads, med))
+    torch.set_num_threads(nthr)
+    return {"cpu_oracle_table": rows, "host": {"nproc": os.cpu_count(), "torch_threads": nthr,
+                                               "cpu": model}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -277,7 +324,12 @@ def main():
     ap.add_argument("--tile", default=None,
                     help="stage kernel tile shape, e.g. 32x8 (default: autotuned)")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint and ensemble legs")
+    ap.add_argument("--cpu-table", action="store_true",
+                    help="only time the CPU oracle at 32^3..256^3 (1 and all threads); no GPU")
     a = ap.parse_args()
+    if a.cpu_table:
+        print(json.dumps(cpu_table()), flush=True)
+        return
     if a.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(the hot path shards by z-slabs with halo exchange; see the design notes)",
