@@ -352,7 +352,7 @@ def main():
     log("device copy: %.0f GB/s" % copy_gbs)
     traffic = measured_traffic("f32")
     out = {
-        "metric": "MHD cell-updates/s per RK step at 512^3 (FP32; FP64 alongside)",
+        "metric": "MHD cell-updates/s per RK step at 512^3 FP32 vs FP64; HBM roofline fraction",
         "value": r32["value"],
         "unit": "cell-updates/s",
         "n_gpus": 1,
