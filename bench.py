@@ -314,7 +314,7 @@ def cpu_table(sizes=(32, 64, 128, 256)):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=50)          # the workload's 50 RK steps
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--size", type=int, default=512)
     ap.add_argument("--no-fp64", action="store_true")
