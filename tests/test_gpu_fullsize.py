@@ -1,7 +1,7 @@
 """Parity at the benchmark's full size: the 512^3 stratified box (walls in z,
 5 ghost planes per side) in float32, with the stage kernels in the launch
-configuration bench.py times (the library default) and in the persistent
-16x16 configuration.
+configuration bench.py times (autotuned on the same state), in the library
+default and in the persistent 16x16 configuration.
 
 The oracle cannot hold the whole box, so it checks sampled columns.  The
 right-hand side at a cell depends on cells at most 11 cells away along x and
@@ -86,14 +86,17 @@ def _windows(seed, count, width):
     return [tuple(int(v) for v in rng.integers(0, N, 2)) for _ in range(count)]
 
 
-@pytest.mark.parametrize("launch", [None, ("16x16", 1)])
+@pytest.mark.parametrize("launch", ["autotuned", None, ("16x16", 1)])
 def test_rhs_sampled_columns_512(state, launch):
     from paper_2405_02483_amd.lib import Context
     f, box, prm = state
     ctx = Context(box, prm, dtype=torch.float32)
-    if launch:
-        ctx.set_launch(*launch)
     fd = ctx.upload([f])
+    if launch == "autotuned":
+        ctx.autotune(fd, reps=2)                 # as bench.py
+        print("launch", ctx.get_launch(), "pass F", ctx.get_final_tile())
+    elif launch:
+        ctx.set_launch(*launch)
     F = [t.view(-1) for t in ctx.box_view(ctx.rhs(fd), 0)]
     nzt = N + 2 * box["ngz"]
     width = 2 * RHS_MARGIN + 8
@@ -116,6 +119,7 @@ def test_step_sampled_columns_and_invariants_512(state):
     f, box, prm = state
     ctx = Context(box, prm, dtype=torch.float32)
     fd = ctx.upload([f])
+    ctx.autotune(fd, reps=2)                     # as bench.py (fills the ghosts of fd)
     s0 = ctx.reductions(fd)
     ctx.step(fd, 0.0, 1)                       # as bench.py: Courant dt on the device
     dt = ctx.last_dt()
