@@ -1,0 +1,97 @@
+"""Seeded random sweep of the right-hand side against the float64 oracle:
+ragged box sizes from 6 to 40 cells per axis, periodic and closed-wall boxes,
+both precisions, every tile shape in both launch modes, each with a random
+tile for the final pass.  The fixed cases elsewhere use a handful of sizes;
+this one aims at indexing mistakes that only some (size, tile) pairs expose
+(partial tiles, chunk edges, planes next to a wall).
+
+Error measure: relative L2 per field, as in the other parity tests.  In a
+closed-wall box the atmosphere is hydrostatic, so the z momentum rate is the
+small residual of the pressure gradient and gravity, each several hundred to
+a few thousand times larger; there the error is taken relative to the larger
+of the field's own norm and the norm of the gravity term alone (the scale of
+the cancelling terms, which sets the rounding error of any evaluation).
+"""
+import random
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2405_02483_amd import inputs
+from tests.helpers import grid_params, interior
+
+pytestmark = pytest.mark.gpu
+
+TOL = {torch.float64: 1e-12, torch.float32: 1e-5}
+NCASES = 12
+
+
+def _cases():
+    rng = random.Random(2405)
+    out = []
+    for case in range(NCASES):
+        walls = case % 3 == 2
+        nx, ny = rng.randint(6, 40), rng.randint(6, 40)
+        nz = rng.randint(6, 36) if walls else rng.randint(6, 40)
+        ftiles = [rng.randrange(5) for _ in range(20)]
+        out.append((case, walls, nx, ny, nz, ftiles))
+    return out
+
+
+def _errors(got, want, scale):
+    out = []
+    for g, w, s in zip(got, want, scale):
+        d = float(torch.linalg.norm(g.detach().to("cpu", torch.float64).reshape(w.shape) - w))
+        out.append(d / max(s, 1e-300))
+    return out
+
+
+@pytest.mark.parametrize("case,walls,nx,ny,nz,ftiles", _cases(),
+                         ids=["%s%dx%dx%d" % ("wall" if c[1] else "per", c[2], c[3], c[4])
+                              for c in _cases()])
+def test_rhs_random_sizes_all_tiles(case, walls, nx, ny, nz, ftiles):
+    from paper_2405_02483_amd.lib import Context, TILES
+    if walls:
+        f, box, prm = inputs.stratified(nx, ny, nz, seed=300 + case)
+    else:
+        n = max(nx, ny, nz)
+        f, box, prm = inputs.turbulent(n=n, seed=300 + case, kmax=3.0)
+        f = [np.ascontiguousarray(a[:nz, :ny, :nx]) for a in f]
+        box = dict(box, nx=nx, ny=ny, nz=nz, Lx=nx / n, Ly=ny / n, Lz=nz / n)
+    g, p = grid_params(box, prm)
+    ft = tuple(torch.from_numpy(a.copy()) for a in f)
+    want = O.rhs(ft, g, p)
+    norms = [float(torch.linalg.norm(w)) for w in (interior(want, box) if walls else want)]
+    floor = 1e-3 * max(norms)
+    scale = [max(n, floor) for n in norms]
+    if walls:
+        g2, p2 = grid_params(box, prm, terms=O.T_GRAV)
+        grav = interior(O.rhs(ft, g2, p2), box)
+        scale = [max(s, float(torch.linalg.norm(t))) for s, t in zip(scale, grav)]
+        want = interior(want, box)
+    names = list(TILES)
+    k = 0
+    for dtype in (torch.float64, torch.float32):
+        ctx = Context(box, prm, dtype=dtype)
+        fd = ctx.upload([f])
+        first = None
+        for tile in names:
+            for pers in (0, 1):
+                ftile = names[ftiles[k % len(ftiles)]]
+                k += 1
+                ctx.set_launch(tile, pers)
+                ctx.set_final_tile(ftile)
+                got = ctx.box_view(ctx.rhs(fd), 0)
+                if walls:
+                    got = interior(got, box)
+                errs = _errors(got, want, scale)
+                assert max(errs) < TOL[dtype], (dtype, tile, pers, ftile, errs)
+                # every launch configuration gives the same bits
+                if first is None:
+                    first = [t.clone() for t in got]
+                else:
+                    for a, b in zip(first, got):
+                        assert torch.equal(a, b), (dtype, tile, pers, ftile)
+        ctx.close()
