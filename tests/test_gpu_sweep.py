@@ -95,3 +95,83 @@ def test_rhs_random_sizes_all_tiles(case, walls, nx, ny, nz, ftiles):
                     for a, b in zip(first, got):
                         assert torch.equal(a, b), (dtype, tile, pers, ftile)
         ctx.close()
+
+
+def _ragged_periodic(nx, ny, nz, seed):
+    n = max(nx, ny, nz)
+    f, box, prm = inputs.turbulent(n=n, seed=seed, kmax=3.0)
+    f = [np.ascontiguousarray(a[:nz, :ny, :nx]) for a in f]
+    box = dict(box, nx=nx, ny=ny, nz=nz, Lx=nx / n, Ly=ny / n, Lz=nz / n)
+    return f, box, prm
+
+
+def _rel(got, want):
+    out = []
+    for g, w in zip(got, want):
+        g = g.detach().to("cpu", torch.float64).reshape(w.shape)
+        out.append(float(torch.linalg.norm(g - w)) / max(float(torch.linalg.norm(w)), 1e-300))
+    return out
+
+
+def test_step_random_mixed_ensemble():
+    """One RK step of an ensemble of boxes of random ragged sizes, walled
+    and periodic mixed, in a random launch configuration per precision,
+    box by box against the oracle's step (relative L2 of the state: no
+    cancellation here, so each field's own norm is the scale)."""
+    from paper_2405_02483_amd.lib import Context, TILES
+    rng = random.Random(4831)
+    cases = []
+    for b in range(6):
+        nx, ny = rng.randint(6, 30), rng.randint(6, 30)
+        if b % 2:
+            cases.append(inputs.stratified(nx, ny, rng.randint(6, 30), seed=500 + b))
+        else:
+            cases.append(_ragged_periodic(nx, ny, rng.randint(6, 30), 500 + b))
+    prm = [c for c in cases if c[1].get("wall")][0][2]
+    dt = 0.5 * min(O.courant(tuple(torch.from_numpy(a.copy()) for a in c[0]),
+                             *grid_params(c[1], prm))[0] for c in cases)
+    wants = []
+    for f, box, _ in cases:
+        g, p = grid_params(box, prm)
+        w = O.step(tuple(torch.from_numpy(a.copy()) for a in f), g, p, dt, 1)
+        wants.append(interior(w, box) if box.get("wall") else w)
+    names = list(TILES)
+    for dtype, tol in ((torch.float64, 1e-12), (torch.float32, 1e-5)):
+        ctx = Context([c[1] for c in cases], prm, dtype=dtype)
+        tile, pers, ftile = rng.choice(names), rng.randrange(2), rng.choice(names)
+        ctx.set_launch(tile, pers)
+        ctx.set_final_tile(ftile)
+        fd = ctx.upload([c[0] for c in cases])
+        ctx.step(fd, dt, 1)
+        for b, (f, box, _) in enumerate(cases):
+            got = ctx.box_view(fd, b)
+            if box.get("wall"):
+                got = interior(got, box)
+            errs = _rel(got, wants[b])
+            assert max(errs) < tol, (dtype, b, (box["nx"], box["ny"], box["nz"]), tile, pers, ftile, errs)
+        ctx.close()
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_step_adjoint_random_sizes_f64(seed):
+    """The step adjoint on a periodic box of random ragged size, with a
+    random launch configuration for its stage-state passes, against the
+    oracle's discrete adjoint (1e-10, as for the fixed cases)."""
+    from paper_2405_02483_amd.lib import Context, TILES
+    rng = random.Random(9100 + seed)
+    nx, ny, nz = rng.randint(6, 28), rng.randint(6, 28), rng.randint(6, 28)
+    f, box, prm = _ragged_periodic(nx, ny, nz, 700 + seed)
+    g, p = grid_params(box, prm)
+    ft = tuple(torch.from_numpy(a.copy()) for a in f)
+    dt = 0.5 * O.courant(ft, g, p)[0]
+    nrng = np.random.default_rng(800 + seed)
+    gbar = [nrng.standard_normal(a.shape) for a in f]
+    want = O.step_vjp(ft, g, p, dt, tuple(torch.from_numpy(a) for a in gbar))
+    names = list(TILES)
+    ctx = Context(box, prm, dtype=torch.float64)
+    ctx.set_launch(rng.choice(names), rng.randrange(2))
+    ctx.set_final_tile(rng.choice(names))
+    got = ctx.box_view(ctx.step_adjoint(ctx.upload([f]), dt, ctx.upload([gbar])), 0)
+    errs = _rel(got, want)
+    assert max(errs) < 1e-10, ((nx, ny, nz), errs)
+    ctx.close()
