@@ -55,10 +55,10 @@ def test_persistent_mode_walls_identical_bits():
 
 
 def test_set_launch_rejects_bad_values():
-    from paper_2405_02483_amd.lib import Context, MhdError, MHD_EINVAL
+    from paper_2405_02483_amd.lib import Context, MhdError, MHD_EINVAL, TILES
     f, box, prm = inputs.turbulent(n=8, seed=3, kmax=2.0)
     ctx = Context(box, prm, dtype=torch.float32)
-    for tile, mode in ((5, 0), (-1, 0), (0, 2)):
+    for tile, mode in ((len(TILES), 0), (-1, 0), (0, 2)):
         with pytest.raises(MhdError) as ei:
             ctx.set_launch(tile, mode)
         assert ei.value.code == MHD_EINVAL
@@ -114,7 +114,7 @@ def test_z_chunking_changes_no_bits(walls):
 def test_final_pass_tile_gives_identical_bits(dtype):
     """Pass F in its own tile shape (its own work items and z-chunks) gives
     the same bits as the uniform launch; set_launch resets it."""
-    from paper_2405_02483_amd.lib import Context, MhdError, MHD_EINVAL
+    from paper_2405_02483_amd.lib import Context, MhdError, MHD_EINVAL, TILES
     fields, boxes, prm = _ensemble(inputs.ensemble_sizes(6, (6, 10, 16), seed=6))
     ctx = Context(boxes, prm, dtype=dtype)
     ctx.set_launch("32x8", 0)
@@ -133,7 +133,7 @@ def test_final_pass_tile_gives_identical_bits(dtype):
             assert torch.equal(a, b), (tile, ftile, persistent)
     ctx.set_launch("16x8", 0)
     assert ctx.get_final_tile() == "16x8"
-    for bad in (-1, 5):
+    for bad in (-1, len(TILES)):
         with pytest.raises(MhdError) as ei:
             ctx.set_final_tile(bad)
         assert ei.value.code == MHD_EINVAL

@@ -35,7 +35,8 @@ def _cases():
         walls = case % 3 == 2
         nx, ny = rng.randint(6, 40), rng.randint(6, 40)
         nz = rng.randint(6, 36) if walls else rng.randint(6, 40)
-        ftiles = [rng.randrange(5) for _ in range(20)]
+        frng = random.Random(7000 + case)
+        ftiles = [frng.randrange(64) for _ in range(24)]
         out.append((case, walls, nx, ny, nz, ftiles))
     return out
 
@@ -79,7 +80,7 @@ def test_rhs_random_sizes_all_tiles(case, walls, nx, ny, nz, ftiles):
         first = None
         for tile in names:
             for pers in (0, 1):
-                ftile = names[ftiles[k % len(ftiles)]]
+                ftile = names[ftiles[k % len(ftiles)] % len(names)]
                 k += 1
                 ctx.set_launch(tile, pers)
                 ctx.set_final_tile(ftile)
