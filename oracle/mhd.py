@@ -28,6 +28,10 @@ design notes of the repository):
   give the flux the wrong dimension and is dropped.
 * Resistivity: eta = nuB * (edge viscosity), or a constant.
 * Ideal-gas EOS: P = (gamma - 1) e.
+* eq. NewtonCool: e there is the energy per unit mass, so the source in the
+  equation for the energy per volume is Q = -rho (e_m - e_cool) / t_cool
+  (e_m relaxes to e_cool on the time scale t_cool at fixed density), times
+  one of the density cut-offs of eq. rhocool when one is chosen.
 """
 from dataclasses import dataclass, field, replace
 import math
@@ -38,10 +42,10 @@ from .stagger import Ops, AX_X, AX_Y, AX_Z
 
 __all__ = [
     "T_CONT", "T_ADV", "T_PRES", "T_VISC", "T_LORENTZ", "T_INDUCT",
-    "T_RESIST", "T_EDIFF", "T_GRAV", "T_ALL", "T_HD", "T_IDEAL",
+    "T_RESIST", "T_EDIFF", "T_GRAV", "T_ALL", "T_HD", "T_IDEAL", "T_COOL",
     "ALPHA", "BETA", "Grid", "Params", "ghost_fill", "rhs", "rhs_nofill",
     "step", "rk3", "courant", "stats", "step_vjp", "rhs_vjp", "FIELDS",
-    "interior_slices", "smoothed_viscosity",
+    "interior_slices", "smoothed_viscosity", "newton_cooling",
 ]
 
 FIELDS = ("rho", "px", "py", "pz", "e", "bx", "by", "bz")
@@ -58,6 +62,7 @@ T_RESIST = 1 << 6    # eta J in E and Joule heating
 T_EDIFF = 1 << 7     # energy diffusion (eq. ediffuse)
 T_GRAV = 1 << 8      # constant gravity along -z (Forcing, Table 1)
 T_ALL = (1 << 9) - 1
+T_COOL = 1 << 9      # Newtonian cooling (eq. NewtonCool); not part of T_ALL
 T_HD = T_CONT | T_ADV | T_PRES | T_VISC | T_EDIFF
 T_IDEAL = T_CONT | T_ADV | T_PRES | T_LORENTZ | T_INDUCT
 
@@ -124,6 +129,10 @@ class Params:
     Cdtd: float = 0.7
     Cdtr: float = 0.1
     terms: int = T_ALL
+    e_cool: float = 0.0       # eq. NewtonCool: target energy per unit mass
+    t_cool: float = 1.0       # its time scale
+    rho_cool: float = 1.0     # eq. rhocool: cut-off density
+    cool_cut: int = 0         # 0 none, 1 low-density cut-off, 2 high-density
 
 
 def interior_slices(grid):
@@ -176,6 +185,24 @@ def smoothed_viscosity(f, grid, par, O=None):
     pieces = dict(P=P, ux=ux, uy=uy, uz=uz, ub=(ubx, uby, ubz),
                   bb=(bbx, bby, bbz), D=D, cs=cs, ca=ca, nus=nus)
     return nt, pieces
+
+
+def newton_cooling(rho, e, par):
+    """Newtonian heating/cooling at cell centres (eq. NewtonCool), as a rate
+    of the energy per volume: the energy per unit mass e_m = e / rho relaxes
+    to e_cool on the time scale t_cool, so Q = -rho (e_m - e_cool) / t_cool.
+    Optional density factor (eq. rhocool), with r = rho / rho_cool:
+    r^2 / (1 + r^2) (cooling cut off at low density, cool_cut = 1) or
+    1 / (1 + r^2) (cut off at high density, cool_cut = 2)."""
+    em = e / rho
+    q = -rho * (em - par.e_cool) / par.t_cool
+    if par.cool_cut == 1:
+        r2 = (rho / par.rho_cool) ** 2
+        q = q * (r2 / (1.0 + r2))
+    elif par.cool_cut == 2:
+        r2 = (rho / par.rho_cool) ** 2
+        q = q * (1.0 / (1.0 + r2))
+    return q
 
 
 def rhs_nofill(f, grid, par):
@@ -287,6 +314,8 @@ def rhs_nofill(f, grid, par):
         fy = par.nuE * O.ydn(rho) * (dy * O.ydn(nt)) * O.ydn(em) * O.ddydn(lne)
         fz = par.nuE * O.zdn(rho) * (dz * O.zdn(nt)) * O.zdn(em) * O.ddzdn(lne)
         de = de + O.ddxup(fx) + O.ddyup(fy) + O.ddzup(fz)
+    if T & T_COOL:
+        de = de + newton_cooling(rho, e, par)
 
     # -- induction (eq. indu) ---------------------------------------------------
     dbx = -(O.ddyup(ez) - O.ddzup(ey))
