@@ -74,6 +74,12 @@ enum {
 #define MHD_T_EDIFF    (1u << 7)   /* energy diffusion (eq. ediffuse)          */
 #define MHD_T_GRAV     (1u << 8)   /* constant gravity along -z (Table 1)      */
 #define MHD_T_ALL      ((1u << 9) - 1u)
+/* Newtonian heating/cooling (eq. NewtonCool, eq. rhocool): a source
+ * -rho (e_m - e_cool) / t_cool in the equation for e (e_m = e / rho, the
+ * energy per unit mass), times a density factor chosen by cool_cut.  Not
+ * part of MHD_T_ALL.  The RK3 step is stable for dt < 2.5 t_cool; the
+ * Courant dt does not include this limit.                                  */
+#define MHD_T_COOL     (1u << 9)
 
 /* One box of the mesh (&grid namelist: mx, my, mz, sx, sy, sz). */
 typedef struct {
@@ -101,6 +107,13 @@ typedef struct {
     double Cdt, Cdtd, Cdtr; /* eq. courantcond                                 */
     uint32_t terms;         /* MHD_T_* bit set                                 */
     int32_t reserved;       /* must be 0                                       */
+    /* with MHD_T_COOL (eq. NewtonCool, eq. rhocool); ignored otherwise:     */
+    double e_cool;          /* target energy per unit mass, finite            */
+    double t_cool;          /* time scale, > 0                                 */
+    double rho_cool;        /* cut-off density, > 0 when cool_cut != 0         */
+    int32_t cool_cut;       /* 0: factor 1; 1: r^2/(1+r^2) (weak cooling at low
+                               density); 2: 1/(1+r^2) (at high); r = rho/rho_cool */
+    int32_t reserved2;      /* must be 0                                       */
 } mhd_params;
 
 /* Conserved totals and diagnostics over the interior cells (float64).     */

@@ -264,6 +264,17 @@ VProgram build_rhs_program(const mhd_params& p) {
                          B.ddzdn(lne));
     de = B.add(B.add(B.add(de, B.ddxup(fx)), B.ddyup(fy)), B.ddzup(fz));
   }
+  // Newtonian cooling (eq. NewtonCool, eq. rhocool)
+  if (T & MHD_T_COOL) {
+    int q = B.scale(B.mul(rho, B.sub(em, B.fill(p.e_cool))), -1.0 / p.t_cool);
+    if (p.cool_cut == 1 || p.cool_cut == 2) {
+      const int r = B.scale(rho, 1.0 / p.rho_cool);
+      const int r2 = B.mul(r, r);
+      const int den = B.add(B.fill(1.0), r2);
+      q = B.mul(q, B.div(p.cool_cut == 1 ? r2 : B.fill(1.0), den));
+    }
+    de = B.add(de, q);
+  }
 
   // induction (eq. indu)
   const int dbx = B.neg(B.sub(B.ddyup(ez), B.ddzup(ey)));

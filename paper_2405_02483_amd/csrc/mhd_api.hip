@@ -114,6 +114,11 @@ template <class T> static Phys<T> make_phys(const mhd_params& p) {
   ph.nuE = T(p.nuE);
   ph.nuB = T(p.nuB);
   ph.eta_const = T(p.eta_const);
+  const bool cool = p.terms & MHD_T_COOL;
+  ph.e_cool = cool ? T(p.e_cool) : T(0);
+  ph.inv_tcool = cool ? T(1.0 / p.t_cool) : T(0);
+  ph.inv_rho_cool = cool && p.cool_cut ? T(1.0 / p.rho_cool) : T(0);
+  ph.cool_cut = cool ? p.cool_cut : 0;
   ph.terms = p.terms;
   return ph;
 }
@@ -365,8 +370,15 @@ int mhd_init(const mhd_params* p, void* hip_stream, mhd_ctx** out) {
   for (double v : nn)
     if (!(v >= 0.0) || !std::isfinite(v)) return fail(nullptr, MHD_EINVAL, "viscosity, diffusion and Courant coefficients must be finite and >= 0");
   if (!std::isfinite(p->gz) || !std::isfinite(p->c1)) return fail(nullptr, MHD_EINVAL, "gz and c1 must be finite");
-  if (p->terms & ~MHD_T_ALL) return fail(nullptr, MHD_EINVAL, "unknown term bits");
-  if (p->reserved != 0) return fail(nullptr, MHD_EINVAL, "reserved field must be 0");
+  if (p->terms & ~(MHD_T_ALL | MHD_T_COOL)) return fail(nullptr, MHD_EINVAL, "unknown term bits");
+  if (p->reserved != 0 || p->reserved2 != 0) return fail(nullptr, MHD_EINVAL, "reserved fields must be 0");
+  if (p->terms & MHD_T_COOL) {
+    if (!std::isfinite(p->e_cool) || !(p->t_cool > 0.0) || !std::isfinite(p->t_cool))
+      return fail(nullptr, MHD_EINVAL, "cooling needs a finite e_cool and a finite t_cool > 0");
+    if (p->cool_cut < 0 || p->cool_cut > 2) return fail(nullptr, MHD_EINVAL, "cool_cut must be 0, 1 or 2");
+    if (p->cool_cut != 0 && (!(p->rho_cool > 0.0) || !std::isfinite(p->rho_cool)))
+      return fail(nullptr, MHD_EINVAL, "a cooling cut-off needs a finite rho_cool > 0");
+  }
 
   mhd_ctx* c = new (std::nothrow) mhd_ctx();
   if (!c) return fail(nullptr, MHD_ENOMEM, "host allocation failed");

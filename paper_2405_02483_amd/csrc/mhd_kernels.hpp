@@ -9,6 +9,8 @@ namespace smhd {
 template <class T> struct Phys {
   T gamma, gamma1, mu, inv_mu, gz;
   T nu1, nu2, nu3, nu_const, c1, nuE, nuB, eta_const;
+  T e_cool, inv_tcool, inv_rho_cool;   // Newtonian cooling (with T_COOL)
+  int cool_cut;
   unsigned terms;
 };
 

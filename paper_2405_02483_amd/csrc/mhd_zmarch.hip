@@ -822,6 +822,16 @@ __global__ __launch_bounds__(TX * TY) void zF(const BoxDev* __restrict__ boxes,
                      op6<0, 1, T>([&](int m) {
                        return op6<0, 1, T>([&](int a) { return F2(0, x + a, y + m); }, T(0));
                      }, T(0));
+        // Newtonian cooling (eq. NewtonCool, eq. rhocool) at the cell centre
+        if (hasf<FM>(4) && (tm & T_COOL)) {
+          const T rc = f.p[0][o], ec = f.p[4][o];
+          T q = -rc * (ec / rc - ph.e_cool) * ph.inv_tcool;
+          if (ph.cool_cut) {
+            const T r = rc * ph.inv_rho_cool, r2 = r * r;
+            q = q * ((ph.cool_cut == 1 ? r2 : T(1)) / (T(1) + r2));
+          }
+          acc[4][3] += q;
+        }
         if (hasf<FM>(5)) acc[5][3] += -op6<1, 1, T>([&](int m) { return F2(1, x, y + m); }, g.hyi);
         if (hasf<FM>(6)) acc[6][3] += op6<1, 1, T>([&](int m) { return F2(1, x + m, y); }, g.hxi);
         // Bz has no z divergence: complete at once

@@ -15,7 +15,7 @@ __all__ = [
     "MHD_OK", "MHD_EINVAL", "MHD_ENOMEM", "MHD_EHIP", "MHD_EDTYPE",
     "MHD_ENONFINITE", "MHD_EUNSUPPORTED", "MHD_F32", "MHD_F64",
     "MHD_BC_PERIODIC", "MHD_BC_WALL", "T_CONT", "T_ADV", "T_PRES", "T_VISC",
-    "T_LORENTZ", "T_INDUCT", "T_RESIST", "T_EDIFF", "T_GRAV", "T_ALL",
+    "T_LORENTZ", "T_INDUCT", "T_RESIST", "T_EDIFF", "T_GRAV", "T_ALL", "T_COOL",
     "MhdBox", "MhdParams", "MhdStats", "MhdError", "lib_path", "load",
     "mhd_init", "mhd_destroy", "mhd_last_error", "mhd_field_elems",
     "mhd_box_offset", "mhd_rhs", "mhd_step", "mhd_step_adjoint",
@@ -32,6 +32,7 @@ MHD_BC_PERIODIC, MHD_BC_WALL = 0, 1
 T_CONT, T_ADV, T_PRES, T_VISC, T_LORENTZ, T_INDUCT, T_RESIST, T_EDIFF, T_GRAV = \
     (1 << i for i in range(9))
 T_ALL = (1 << 9) - 1
+T_COOL = 1 << 9      # Newtonian cooling; not part of T_ALL
 
 
 class MhdBox(ctypes.Structure):
@@ -48,7 +49,10 @@ class MhdParams(ctypes.Structure):
                 ("nu_const", ctypes.c_double), ("c1", ctypes.c_double), ("nuE", ctypes.c_double),
                 ("nuB", ctypes.c_double), ("eta_const", ctypes.c_double),
                 ("Cdt", ctypes.c_double), ("Cdtd", ctypes.c_double), ("Cdtr", ctypes.c_double),
-                ("terms", ctypes.c_uint32), ("reserved", ctypes.c_int32)]
+                ("terms", ctypes.c_uint32), ("reserved", ctypes.c_int32),
+                ("e_cool", ctypes.c_double), ("t_cool", ctypes.c_double),
+                ("rho_cool", ctypes.c_double), ("cool_cut", ctypes.c_int32),
+                ("reserved2", ctypes.c_int32)]
 
 
 class MhdStats(ctypes.Structure):
@@ -313,6 +317,11 @@ class Context:
             setattr(p, k, float(defaults[k]))
         p.terms = int(params.get("terms", terms))
         p.reserved = 0
+        p.e_cool = float(params.get("e_cool", 0.0))
+        p.t_cool = float(params.get("t_cool", 1.0))
+        p.rho_cool = float(params.get("rho_cool", 1.0))
+        p.cool_cut = int(params.get("cool_cut", 0))
+        p.reserved2 = 0
         self.params = p
         self.ctx = mhd_init(p, stream)
         self.n = mhd_field_elems(self.ctx)
