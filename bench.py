@@ -13,16 +13,17 @@ Prints ONE JSON line:  metric, value (interior cell-updates/s per RK step),
 ms_per_step, the float64 figures of the same workload, the roofline of the
 RK stage (algorithmic bytes per stage / measured stage time, HIP events on
 the library's stream; beside the 8 TB/s peak, the bandwidth of a plain 1 GiB
-device copy measured in the same run) and the CPU oracle timed on a bounded
-sample.
+device copy measured in the same run), the same float32 workload with
+Newtonian cooling on, and the CPU oracle timed on a bounded sample.
 
     python bench.py [--steps K] [--warmup W] [--size N] [--no-fp64]
-                    [--no-cpu-baseline] [--no-adjoint] [--tile TXxTY]
+                    [--no-cpu-baseline] [--no-adjoint] [--no-cooling] [--tile TXxTY]
     python bench.py --cpu-table     (the CPU oracle alone, 32^3..256^3)
 """
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -37,6 +38,10 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 # writes f.  80 words per full step.
 WORDS_PER_STAGE = (24, 32, 24)
 STAGE_PASSES = ("A1", "A2", "Q", "P", "F")
+# Newtonian cooling for the stratified workload: toward the atmosphere's own
+# energy per unit mass (1 / (gamma - 1)), with the low-density cut-off at the
+# mid-height density exp(-2)
+COOLING = dict(e_cool=1.5, t_cool=0.1, rho_cool=math.exp(-2.0), cool_cut=1)
 
 
 def log(msg):
@@ -86,17 +91,24 @@ def make_state(workload, size):
     raise ValueError(workload)
 
 
-def run_gpu(size, dtype, steps, warmup, workload="stratified", tile=None):
+def run_gpu(size, dtype, steps, warmup, workload="stratified", tile=None, over=None,
+            launch=None):
+    """Times `steps` RK steps.  over: parameters replacing the workload's;
+    launch: a (tile, persistent, final-pass tile) to use instead of tuning."""
     import torch
     from paper_2405_02483_amd.lib import Context
 
     log("generating the %d^3 %s state" % (size, workload))
     f_np, box, prm = make_state(workload, size)
+    prm = dict(prm, **(over or {}))
     ctx = Context(box, prm, dtype=dtype)
     f = ctx.upload([f_np])
     del f_np
     tune = None
-    if tile is None:
+    if launch is not None:
+        ctx.set_launch(launch[0], launch[1])
+        ctx.set_final_tile(launch[2])
+    elif tile is None:
         tune = ctx.autotune(f, reps=2)          # tile shape and launch mode
     else:
         ctx.set_launch(tile, 0)
@@ -324,6 +336,7 @@ def main():
     ap.add_argument("--tile", default=None,
                     help="stage kernel tile shape, e.g. 32x8 (default: autotuned)")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint and ensemble legs")
+    ap.add_argument("--no-cooling", action="store_true", help="skip the Newtonian-cooling leg")
     ap.add_argument("--cpu-table", action="store_true",
                     help="only time the CPU oracle at 32^3..256^3 (1 and all threads); no GPU")
     a = ap.parse_args()
@@ -340,6 +353,15 @@ def main():
 
     r32 = run_gpu(a.size, torch.float32, a.steps, a.warmup, a.workload, a.tile)
     log("f32: %.2f ms/step, %.3e cell-updates/s" % (r32["ms_per_step"], r32["value"]))
+    rcool = None
+    if not a.no_cooling and a.workload == "stratified":
+        # the same workload and launch with Newtonian cooling switched on
+        from paper_2405_02483_amd.lib import T_ALL, T_COOL
+        L = r32["launch"]
+        rcool = run_gpu(a.size, torch.float32, max(2, a.steps // 5), 1, a.workload,
+                        over=dict(COOLING, terms=T_ALL | T_COOL),
+                        launch=(L["tile"], L["persistent"], L["final_pass_tile"]))
+        log("f32 with cooling: %.2f ms/step" % rcool["ms_per_step"])
     r64 = None
     if not a.no_fp64:
         r64 = run_gpu(a.size, torch.float64, max(2, a.steps // 2), 1, a.workload)
@@ -389,6 +411,16 @@ def main():
                        "frac": (2 * stage_bytes / (r64["stage_ms"] * 1e-3) / 1e9) / HBM_PEAK_GBS,
                        "passes_ms": {k: round(v[0], 4) for k, v in r64["passes"].items()}}
         out["fp32_over_fp64"] = r32["value"] / r64["value"]
+    if rcool is not None:
+        out["cooling"] = {
+            "workload": "%s_%d with Newtonian cooling (eq. NewtonCool): e_cool %.1f, "
+                        "t_cool %.1f, low-density cut-off at rho_cool = %.4f (mid-height)"
+                        % (a.workload, a.size, COOLING["e_cool"], COOLING["t_cool"],
+                           COOLING["rho_cool"]),
+            "value": rcool["value"], "unit": "cell-updates/s", "steps": max(2, a.steps // 5),
+            "ms_per_step": rcool["ms_per_step"], "stage_ms": rcool["stage_ms"],
+            "over_plain": rcool["ms_per_step"] / r32["ms_per_step"],
+            "passes_ms": {k: round(v[0], 4) for k, v in rcool["passes"].items()}}
     if not a.no_adjoint:
         log("adjoint leg")
         out["adjoint"] = run_adjoint()
