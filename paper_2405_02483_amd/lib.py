@@ -286,7 +286,9 @@ _PARAM_KEYS = ("gamma", "mu", "gz", "nu1", "nu2", "nu3", "nu_const", "c1", "nuE"
 
 class Context:
     """Owns one mhd_ctx.  ``boxes``: list of dicts with nx, ny, nz, ngz,
-    wall (bool), Lx, Ly, Lz; ``params``: dict of physical parameters."""
+    wall (bool), Lx, Ly, Lz; ``params``: dict of physical parameters (the
+    fields of mhd_params by name, ``terms`` for the term bits, and e_cool,
+    t_cool, rho_cool, cool_cut for Newtonian cooling with T_COOL)."""
 
     def __init__(self, boxes, params, dtype=torch.float32, terms=T_ALL, stream=None,
                  device="cuda"):

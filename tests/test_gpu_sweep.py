@@ -114,12 +114,14 @@ def _rel(got, want):
     return out
 
 
-def test_step_random_mixed_ensemble():
+@pytest.mark.parametrize("cool", [False, True])
+def test_step_random_mixed_ensemble(cool):
     """One RK step of an ensemble of boxes of random ragged sizes, walled
     and periodic mixed, in a random launch configuration per precision,
     box by box against the oracle's step (relative L2 of the state: no
-    cancellation here, so each field's own norm is the scale)."""
-    from paper_2405_02483_amd.lib import Context, TILES
+    cancellation here, so each field's own norm is the scale); then the
+    same with Newtonian cooling and a random cut-off."""
+    from paper_2405_02483_amd.lib import Context, TILES, T_ALL, T_COOL
     rng = random.Random(4831)
     cases = []
     for b in range(6):
@@ -129,6 +131,9 @@ def test_step_random_mixed_ensemble():
         else:
             cases.append(_ragged_periodic(nx, ny, rng.randint(6, 30), 500 + b))
     prm = [c for c in cases if c[1].get("wall")][0][2]
+    if cool:
+        prm = dict(prm, terms=T_ALL | T_COOL, e_cool=1.2, t_cool=0.5, rho_cool=0.7,
+                   cool_cut=random.Random(77).randrange(3))
     dt = 0.5 * min(O.courant(tuple(torch.from_numpy(a.copy()) for a in c[0]),
                              *grid_params(c[1], prm))[0] for c in cases)
     wants = []
