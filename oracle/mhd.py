@@ -32,6 +32,9 @@ design notes of the repository):
   equation for the energy per volume is Q = -rho (e_m - e_cool) / t_cool
   (e_m relaxes to e_cool on the time scale t_cool at fixed density), times
   one of the density cut-offs of eq. rhocool when one is chosen.
+* eq. mom, Coriolis force: -2 rho Omega x u = -2 Omega x p, with each
+  momentum component carried to the face of the component it drives by the
+  staggered interpolations (e.g. p_z at an x-face is xdn(zup(p_z))).
 """
 from dataclasses import dataclass, field, replace
 import math
@@ -42,10 +45,10 @@ from .stagger import Ops, AX_X, AX_Y, AX_Z
 
 __all__ = [
     "T_CONT", "T_ADV", "T_PRES", "T_VISC", "T_LORENTZ", "T_INDUCT",
-    "T_RESIST", "T_EDIFF", "T_GRAV", "T_ALL", "T_HD", "T_IDEAL", "T_COOL",
+    "T_RESIST", "T_EDIFF", "T_GRAV", "T_ALL", "T_HD", "T_IDEAL", "T_COOL", "T_CORI",
     "ALPHA", "BETA", "Grid", "Params", "ghost_fill", "rhs", "rhs_nofill",
     "step", "rk3", "courant", "stats", "step_vjp", "rhs_vjp", "FIELDS",
-    "interior_slices", "smoothed_viscosity", "newton_cooling",
+    "interior_slices", "smoothed_viscosity", "newton_cooling", "coriolis",
 ]
 
 FIELDS = ("rho", "px", "py", "pz", "e", "bx", "by", "bz")
@@ -63,6 +66,7 @@ T_EDIFF = 1 << 7     # energy diffusion (eq. ediffuse)
 T_GRAV = 1 << 8      # constant gravity along -z (Forcing, Table 1)
 T_ALL = (1 << 9) - 1
 T_COOL = 1 << 9      # Newtonian cooling (eq. NewtonCool); not part of T_ALL
+T_CORI = 1 << 10     # Coriolis force (eq. mom); not part of T_ALL
 T_HD = T_CONT | T_ADV | T_PRES | T_VISC | T_EDIFF
 T_IDEAL = T_CONT | T_ADV | T_PRES | T_LORENTZ | T_INDUCT
 
@@ -133,6 +137,7 @@ class Params:
     t_cool: float = 1.0       # its time scale
     rho_cool: float = 1.0     # eq. rhocool: cut-off density
     cool_cut: int = 0         # 0 none, 1 low-density cut-off, 2 high-density
+    omega: tuple = (0.0, 0.0, 0.0)   # rotation vector of the Coriolis force
 
 
 def interior_slices(grid):
@@ -203,6 +208,21 @@ def newton_cooling(rho, e, par):
         r2 = (rho / par.rho_cool) ** 2
         q = q * (1.0 / (1.0 + r2))
     return q
+
+
+def coriolis(px, py, pz, par, O):
+    """Coriolis force on the momenta (eq. mom): -2 rho Omega x u, written
+    -2 Omega x p, each component on its own face.  The other two momentum
+    components reach that face by interpolation: up along their own axis
+    (face to centre), then down along the driven axis (centre to face)."""
+    ox, oy, oz = par.omega
+    pz_x, py_x = O.xdn(O.zup(pz)), O.xdn(O.yup(py))      # at x-faces
+    px_y, pz_y = O.ydn(O.xup(px)), O.ydn(O.zup(pz))      # at y-faces
+    py_z, px_z = O.zdn(O.yup(py)), O.zdn(O.xup(px))      # at z-faces
+    cx = -2.0 * (oy * pz_x - oz * py_x)
+    cy = -2.0 * (oz * px_y - ox * pz_y)
+    cz = -2.0 * (ox * py_z - oy * px_z)
+    return cx, cy, cz
 
 
 def rhs_nofill(f, grid, par):
@@ -291,6 +311,9 @@ def rhs_nofill(f, grid, par):
         dpz = dpz + O.ddzdn(tzz) + O.ddxup(txz) + O.ddyup(tyz)
     if T & T_GRAV:
         dpz = dpz - O.zdn(rho) * par.gz
+    if T & T_CORI:
+        cx, cy, cz = coriolis(px, py, pz, par, O)
+        dpx, dpy, dpz = dpx + cx, dpy + cy, dpz + cz
 
     # -- internal energy (eq. ien, eq. vdiss, eq. ediffuse) --------------------
     de = zero
