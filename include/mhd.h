@@ -80,6 +80,10 @@ enum {
  * part of MHD_T_ALL.  The RK3 step is stable for dt < 2.5 t_cool; the
  * Courant dt does not include this limit.                                  */
 #define MHD_T_COOL     (1u << 9)
+/* Coriolis force -2 rho Omega x u (eq. mom), written -2 Omega x p with each
+ * momentum component interpolated to the face of the one it drives.  Not
+ * part of MHD_T_ALL.                                                        */
+#define MHD_T_CORI     (1u << 10)
 
 /* One box of the mesh (&grid namelist: mx, my, mz, sx, sy, sz). */
 typedef struct {
@@ -114,6 +118,7 @@ typedef struct {
     int32_t cool_cut;       /* 0: factor 1; 1: r^2/(1+r^2) (weak cooling at low
                                density); 2: 1/(1+r^2) (at high); r = rho/rho_cool */
     int32_t reserved2;      /* must be 0                                       */
+    double omega[3];        /* with MHD_T_CORI: rotation vector, finite        */
 } mhd_params;
 
 /* Conserved totals and diagnostics over the interior cells (float64).     */

@@ -233,6 +233,14 @@ VProgram build_rhs_program(const mhd_params& p) {
     dpz = B.add(B.add(B.add(dpz, B.ddzdn(tzz)), B.ddxup(txz)), B.ddyup(tyz));
   }
   if (T & MHD_T_GRAV) dpz = B.sub(dpz, B.scale(B.zdn(rho), p.gz));
+  // Coriolis force (eq. mom): -2 Omega x p, each component on its own face
+  if (T & MHD_T_CORI) {
+    const double wx = 2.0 * p.omega[0], wy = 2.0 * p.omega[1], wz = 2.0 * p.omega[2];
+    auto term = [&](int acc, int v, double w) { return w == 0.0 ? acc : B.add(acc, B.scale(v, w)); };
+    dpx = term(term(dpx, B.xdn(B.zup(pz)), -wy), B.xdn(B.yup(py)), wz);
+    dpy = term(term(dpy, B.ydn(B.xup(px)), -wz), B.ydn(B.zup(pz)), wx);
+    dpz = term(term(dpz, B.zdn(B.yup(py)), -wx), B.zdn(B.xup(px)), wy);
+  }
 
   // internal energy (eqs. ien, vdiss, ediffuse)
   int de = Z;

@@ -119,6 +119,8 @@ template <class T> static Phys<T> make_phys(const mhd_params& p) {
   ph.inv_tcool = cool ? T(1.0 / p.t_cool) : T(0);
   ph.inv_rho_cool = cool && p.cool_cut ? T(1.0 / p.rho_cool) : T(0);
   ph.cool_cut = cool ? p.cool_cut : 0;
+  const bool cori = p.terms & MHD_T_CORI;
+  for (int a = 0; a < 3; ++a) ph.cor2[a] = cori ? T(2.0 * p.omega[a]) : T(0);
   ph.terms = p.terms;
   return ph;
 }
@@ -370,7 +372,10 @@ int mhd_init(const mhd_params* p, void* hip_stream, mhd_ctx** out) {
   for (double v : nn)
     if (!(v >= 0.0) || !std::isfinite(v)) return fail(nullptr, MHD_EINVAL, "viscosity, diffusion and Courant coefficients must be finite and >= 0");
   if (!std::isfinite(p->gz) || !std::isfinite(p->c1)) return fail(nullptr, MHD_EINVAL, "gz and c1 must be finite");
-  if (p->terms & ~(MHD_T_ALL | MHD_T_COOL)) return fail(nullptr, MHD_EINVAL, "unknown term bits");
+  if (p->terms & ~(MHD_T_ALL | MHD_T_COOL | MHD_T_CORI)) return fail(nullptr, MHD_EINVAL, "unknown term bits");
+  if ((p->terms & MHD_T_CORI) &&
+      !(std::isfinite(p->omega[0]) && std::isfinite(p->omega[1]) && std::isfinite(p->omega[2])))
+    return fail(nullptr, MHD_EINVAL, "the rotation vector must be finite");
   if (p->reserved != 0 || p->reserved2 != 0) return fail(nullptr, MHD_EINVAL, "reserved fields must be 0");
   if (p->terms & MHD_T_COOL) {
     if (!std::isfinite(p->e_cool) || !(p->t_cool > 0.0) || !std::isfinite(p->t_cool))

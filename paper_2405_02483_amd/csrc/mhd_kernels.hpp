@@ -11,6 +11,7 @@ template <class T> struct Phys {
   T nu1, nu2, nu3, nu_const, c1, nuE, nuB, eta_const;
   T e_cool, inv_tcool, inv_rho_cool;   // Newtonian cooling (with T_COOL)
   int cool_cut;
+  T cor2[3];                            // 2 Omega (Coriolis force, with T_CORI)
   unsigned terms;
 };
 

@@ -694,6 +694,9 @@ __global__ __launch_bounds__(TX * TY) void zF(const BoxDev* __restrict__ boxes,
   __shared__ T sx[at_least1(strip_slot<FM>(kXOwn, 9)) * PXs::NP];
   __shared__ T sy[at_least1(strip_slot<FM>(kYOwn, 9)) * PYs::NP];
   __shared__ T s2[at_least1(int(kQz) + int(kEz)) * P3::NP];
+  // Coriolis force (bit 8 of FM, momentum launch only): px, py, pz planes
+  constexpr bool kCori = hasf<FM>(8);
+  __shared__ T sc[kCori ? 3 * P3::NP : 1];
   ZLOOP_BEGIN
   PlaneIdx<TX, TY, 3, 0> ix;
   PlaneIdx<TX, TY, 0, 3> iy;
@@ -709,6 +712,7 @@ __global__ __launch_bounds__(TX * TY) void zF(const BoxDev* __restrict__ boxes,
   auto X = [&](int q, int x) -> T { return sx[strip_slot<FM>(kXOwn, q) * PXs::NP + PXs::at(x, ty)]; };
   auto Y = [&](int q, int y) -> T { return sy[strip_slot<FM>(kYOwn, q) * PYs::NP + PYs::at(tx, y)]; };
   auto F2 = [&](int q, int x, int y) -> T { return s2[(q && kQz) * P3::NP + P3::at(x, y)]; };
+  auto C3 = [&](int q, int x, int y) -> T { return sc[q * P3::NP + P3::at(x, y)]; };
   T acc[7][7];
 #pragma unroll
   for (int a = 0; a < 7; ++a)
@@ -786,6 +790,11 @@ __global__ __launch_bounds__(TX * TY) void zF(const BoxDev* __restrict__ boxes,
         load_plane(sx + strip_slot<FM>(kXOwn, 8) * PXs::NP, ws.q(QOUT_QY), b, ix, k);
         load_plane(sy + strip_slot<FM>(kYOwn, 8) * PYs::NP, ws.q(QOUT_QX), b, iy, k);
       }
+      if constexpr (kCori) {
+        load_plane(sc, f.p[1], b, i3, k);
+        load_plane(sc + P3::NP, f.p[2], b, i3, k);
+        load_plane(sc + 2 * P3::NP, f.p[3], b, i3, k);
+      }
       // Bz's dU and f at this plane, fetched with the planes
       T bz_u = T(0), bz_f = T(0);
       if (hasf<FM>(7) && inch && own && f_out.p[0] != nullptr) {
@@ -843,6 +852,24 @@ __global__ __launch_bounds__(TX * TY) void zF(const BoxDev* __restrict__ boxes,
           else update(7, o, F7, bz_u, bz_f);
         }
       }
+      // Coriolis force (eq. mom): -2 Omega x p, each component on its own
+      // face; the parts that end with an interpolation along z are scattered
+      T czx = T(0), czy = T(0), czz = T(0);
+      if constexpr (kCori) {
+        const T wx = ph.cor2[0], wy = ph.cor2[1], wz = ph.cor2[2];
+        if (inch) {
+          acc[1][3] += wz * op6<0, 0, T>([&](int m) {
+                         return op6<0, 1, T>([&](int n) { return C3(1, x + m, y + n); }, T(0));
+                       }, T(0));
+          acc[2][3] -= wz * op6<0, 0, T>([&](int n) {
+                         return op6<0, 1, T>([&](int m) { return C3(0, x + m, y + n); }, T(0));
+                       }, T(0));
+        }
+        czx = -wy * op6<0, 0, T>([&](int m) { return C3(2, x + m, y); }, T(0));
+        czy = wx * op6<0, 0, T>([&](int n) { return C3(2, x, y + n); }, T(0));
+        czz = wy * op6<0, 1, T>([&](int m) { return C3(0, x + m, y); }, T(0)) -
+              wx * op6<0, 1, T>([&](int n) { return C3(1, x, y + n); }, T(0));
+      }
       T xqy = T(0), yqx = T(0);
       if (hasf<FM>(4)) {
         xqy = op6<0, 1, T>([&](int m) { return X(8, x + m); }, T(0));
@@ -865,14 +892,17 @@ __global__ __launch_bounds__(TX * TY) void zF(const BoxDev* __restrict__ boxes,
       if (hasf<FM>(1)) {
         zscatter_d<1, 3>(acc[1], kb, dl[1], wall, N, zt);
         zscatter<0, 1, 3>(acc[1], kb, ws.q(QOUT_LXY)[o] * inv_mu, wall, N, zt);
+        if constexpr (kCori) zscatter<0, 1, 3>(acc[1], kb, czx, wall, N, zt);
       }
       if (hasf<FM>(2)) {
         zscatter_d<1, 3>(acc[2], kb, dl[2], wall, N, zt);
         zscatter<0, 1, 3>(acc[2], kb, -ws.q(QOUT_LYX)[o] * inv_mu, wall, N, zt);
+        if constexpr (kCori) zscatter<0, 1, 3>(acc[2], kb, czy, wall, N, zt);
       }
       if (hasf<FM>(3)) {
         zscatter_d<0, 3>(acc[3], kb, dl[3], wall, N, zt);
         if (grav) zscatter<0, 0, 3>(acc[3], kb, -f.p[0][o] * ph.gz, wall, N, zt);
+        if constexpr (kCori) zscatter<0, 0, 3>(acc[3], kb, czz, wall, N, zt);
       }
       if (hasf<FM>(4)) {
         zscatter_d<1, 3>(acc[4], kb, dl[4], wall, N, zt);
@@ -931,11 +961,16 @@ static void zF_one(const G& grid, dim3 block, const ZLaunch& L, const ZStageArgs
                      L.boxes, L.fitems, L.nfitems, a.ztab, q, a.f, a.w, a.ph, a.du, a.du_mode, a.f_out, a.alpha,
                      a.beta, a.dt_dev, a.dt_host);
 }
+// The momentum launch's mask with the Coriolis bit (8) set; others unchanged.
+template <unsigned FM> constexpr unsigned with_cori() { return (FM & 0x0Eu) ? (FM | 0x100u) : FM; }
 // one launch per mask, each with its own 8 queue counters
 template <class T, int TX, int TY, bool PERS, class G, size_t... I>
 static void zF_launch(const G& grid, dim3 block, const ZLaunch& L, const ZStageArgs<T>& a, int* q,
                       std::index_sequence<I...>) {
-  (zF_one<T, TX, TY, PERS, kFMasks[I]>(grid, block, L, a, q ? q + 32 + 8 * int(I) : q), ...);
+  if (a.ph.terms & T_CORI)
+    (zF_one<T, TX, TY, PERS, with_cori<kFMasks[I]>()>(grid, block, L, a, q ? q + 32 + 8 * int(I) : q), ...);
+  else
+    (zF_one<T, TX, TY, PERS, kFMasks[I]>(grid, block, L, a, q ? q + 32 + 8 * int(I) : q), ...);
 }
 
 __global__ void k_qreset(int* q) {

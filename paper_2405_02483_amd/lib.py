@@ -15,7 +15,7 @@ __all__ = [
     "MHD_OK", "MHD_EINVAL", "MHD_ENOMEM", "MHD_EHIP", "MHD_EDTYPE",
     "MHD_ENONFINITE", "MHD_EUNSUPPORTED", "MHD_F32", "MHD_F64",
     "MHD_BC_PERIODIC", "MHD_BC_WALL", "T_CONT", "T_ADV", "T_PRES", "T_VISC",
-    "T_LORENTZ", "T_INDUCT", "T_RESIST", "T_EDIFF", "T_GRAV", "T_ALL", "T_COOL",
+    "T_LORENTZ", "T_INDUCT", "T_RESIST", "T_EDIFF", "T_GRAV", "T_ALL", "T_COOL", "T_CORI",
     "MhdBox", "MhdParams", "MhdStats", "MhdError", "lib_path", "load",
     "mhd_init", "mhd_destroy", "mhd_last_error", "mhd_field_elems",
     "mhd_box_offset", "mhd_rhs", "mhd_step", "mhd_step_adjoint",
@@ -33,6 +33,7 @@ T_CONT, T_ADV, T_PRES, T_VISC, T_LORENTZ, T_INDUCT, T_RESIST, T_EDIFF, T_GRAV = 
     (1 << i for i in range(9))
 T_ALL = (1 << 9) - 1
 T_COOL = 1 << 9      # Newtonian cooling; not part of T_ALL
+T_CORI = 1 << 10     # Coriolis force; not part of T_ALL
 
 
 class MhdBox(ctypes.Structure):
@@ -52,7 +53,7 @@ class MhdParams(ctypes.Structure):
                 ("terms", ctypes.c_uint32), ("reserved", ctypes.c_int32),
                 ("e_cool", ctypes.c_double), ("t_cool", ctypes.c_double),
                 ("rho_cool", ctypes.c_double), ("cool_cut", ctypes.c_int32),
-                ("reserved2", ctypes.c_int32)]
+                ("reserved2", ctypes.c_int32), ("omega", ctypes.c_double * 3)]
 
 
 class MhdStats(ctypes.Structure):
@@ -288,7 +289,8 @@ class Context:
     """Owns one mhd_ctx.  ``boxes``: list of dicts with nx, ny, nz, ngz,
     wall (bool), Lx, Ly, Lz; ``params``: dict of physical parameters (the
     fields of mhd_params by name, ``terms`` for the term bits, and e_cool,
-    t_cool, rho_cool, cool_cut for Newtonian cooling with T_COOL)."""
+    t_cool, rho_cool, cool_cut for Newtonian cooling with T_COOL, omega
+    (3 values) for the Coriolis force with T_CORI)."""
 
     def __init__(self, boxes, params, dtype=torch.float32, terms=T_ALL, stream=None,
                  device="cuda"):
@@ -324,6 +326,8 @@ class Context:
         p.rho_cool = float(params.get("rho_cool", 1.0))
         p.cool_cut = int(params.get("cool_cut", 0))
         p.reserved2 = 0
+        for a, w in enumerate(params.get("omega", (0.0, 0.0, 0.0))):
+            p.omega[a] = float(w)
         self.params = p
         self.ctx = mhd_init(p, stream)
         self.n = mhd_field_elems(self.ctx)

@@ -22,7 +22,10 @@ def _params(**over):
                 c1=0.0, nuE=1.0, nuB=1.0, eta_const=0.0, Cdt=0.3, Cdtd=0.7, Cdtr=0.1)
     vals.update(over)
     for k, v in vals.items():
-        if k not in ("terms", "reserved"):
+        if k == "omega":
+            for a in range(3):
+                p.omega[a] = v[a]
+        elif k not in ("terms", "reserved"):
             setattr(p, k, v)
     p.terms = vals.get("terms", lib.T_ALL)
     p.reserved = vals.get("reserved", 0)
@@ -36,12 +39,13 @@ def _params(**over):
     (dict(nu1=-0.1), lib.MHD_EINVAL),
     (dict(Cdt=float("nan")), lib.MHD_EINVAL),
     (dict(terms=1 << 12), lib.MHD_EINVAL),
-    (dict(terms=1 << 10), lib.MHD_EINVAL),
     (dict(reserved2=1), lib.MHD_EINVAL),
     (dict(terms=lib.T_ALL | lib.T_COOL, t_cool=0.0), lib.MHD_EINVAL),
     (dict(terms=lib.T_ALL | lib.T_COOL, t_cool=1.0, e_cool=float("nan")), lib.MHD_EINVAL),
     (dict(terms=lib.T_ALL | lib.T_COOL, t_cool=1.0, cool_cut=3), lib.MHD_EINVAL),
     (dict(terms=lib.T_ALL | lib.T_COOL, t_cool=1.0, cool_cut=1, rho_cool=0.0), lib.MHD_EINVAL),
+    (dict(terms=lib.T_ALL | lib.T_CORI, omega=(0.0, float("inf"), 0.0)), lib.MHD_EINVAL),
+    (dict(terms=1 << 11), lib.MHD_EINVAL),
     (dict(nbox=0), lib.MHD_EINVAL),
     (dict(boxes=[dict(nx=5, ny=8, nz=8)]), lib.MHD_EINVAL),
     (dict(boxes=[dict(nx=8, ny=8, nz=8, ngz=5, bc_z=0)]), lib.MHD_EINVAL),
