@@ -14,10 +14,11 @@ ms_per_step, the float64 figures of the same workload, the roofline of the
 RK stage (algorithmic bytes per stage / measured stage time, HIP events on
 the library's stream; beside the 8 TB/s peak, the bandwidth of a plain 1 GiB
 device copy measured in the same run), the same float32 workload with
-Newtonian cooling on, and the CPU oracle timed on a bounded sample.
+Newtonian cooling and with the Coriolis force on, and the CPU oracle timed
+on a bounded sample.
 
     python bench.py [--steps K] [--warmup W] [--size N] [--no-fp64]
-                    [--no-cpu-baseline] [--no-adjoint] [--no-cooling] [--tile TXxTY]
+                    [--no-cpu-baseline] [--no-adjoint] [--no-sources] [--tile TXxTY]
     python bench.py --cpu-table     (the CPU oracle alone, 32^3..256^3)
 """
 import argparse
@@ -42,6 +43,9 @@ STAGE_PASSES = ("A1", "A2", "Q", "P", "F")
 # energy per unit mass (1 / (gamma - 1)), with the low-density cut-off at the
 # mid-height density exp(-2)
 COOLING = dict(e_cool=1.5, t_cool=0.1, rho_cool=math.exp(-2.0), cool_cut=1)
+# Coriolis force: a rotation vector of magnitude 1 tilted 30 degrees from z
+# toward y (a box at 60 degrees latitude)
+CORIOLIS = dict(omega=(0.0, 0.5, math.sqrt(3.0) / 2.0))
 
 
 def log(msg):
@@ -336,7 +340,8 @@ def main():
     ap.add_argument("--tile", default=None,
                     help="stage kernel tile shape, e.g. 32x8 (default: autotuned)")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint and ensemble legs")
-    ap.add_argument("--no-cooling", action="store_true", help="skip the Newtonian-cooling leg")
+    ap.add_argument("--no-sources", action="store_true",
+                    help="skip the legs with Newtonian cooling and with the Coriolis force")
     ap.add_argument("--cpu-table", action="store_true",
                     help="only time the CPU oracle at 32^3..256^3 (1 and all threads); no GPU")
     a = ap.parse_args()
@@ -353,15 +358,16 @@ def main():
 
     r32 = run_gpu(a.size, torch.float32, a.steps, a.warmup, a.workload, a.tile)
     log("f32: %.2f ms/step, %.3e cell-updates/s" % (r32["ms_per_step"], r32["value"]))
-    rcool = None
-    if not a.no_cooling and a.workload == "stratified":
-        # the same workload and launch with Newtonian cooling switched on
-        from paper_2405_02483_amd.lib import T_ALL, T_COOL
+    rsrc = {}
+    if not a.no_sources and a.workload == "stratified":
+        # the same workload and launch with one more source term switched on
+        from paper_2405_02483_amd.lib import T_ALL, T_COOL, T_CORI
         L = r32["launch"]
-        rcool = run_gpu(a.size, torch.float32, max(2, a.steps // 5), 1, a.workload,
-                        over=dict(COOLING, terms=T_ALL | T_COOL),
-                        launch=(L["tile"], L["persistent"], L["final_pass_tile"]))
-        log("f32 with cooling: %.2f ms/step" % rcool["ms_per_step"])
+        for name, bit, over in (("cooling", T_COOL, COOLING), ("coriolis", T_CORI, CORIOLIS)):
+            rsrc[name] = run_gpu(a.size, torch.float32, max(2, a.steps // 5), 1, a.workload,
+                                 over=dict(over, terms=T_ALL | bit),
+                                 launch=(L["tile"], L["persistent"], L["final_pass_tile"]))
+            log("f32 with %s: %.2f ms/step" % (name, rsrc[name]["ms_per_step"]))
     r64 = None
     if not a.no_fp64:
         r64 = run_gpu(a.size, torch.float64, max(2, a.steps // 2), 1, a.workload)
@@ -411,16 +417,18 @@ def main():
                        "frac": (2 * stage_bytes / (r64["stage_ms"] * 1e-3) / 1e9) / HBM_PEAK_GBS,
                        "passes_ms": {k: round(v[0], 4) for k, v in r64["passes"].items()}}
         out["fp32_over_fp64"] = r32["value"] / r64["value"]
-    if rcool is not None:
-        out["cooling"] = {
-            "workload": "%s_%d with Newtonian cooling (eq. NewtonCool): e_cool %.1f, "
-                        "t_cool %.1f, low-density cut-off at rho_cool = %.4f (mid-height)"
-                        % (a.workload, a.size, COOLING["e_cool"], COOLING["t_cool"],
-                           COOLING["rho_cool"]),
-            "value": rcool["value"], "unit": "cell-updates/s", "steps": max(2, a.steps // 5),
-            "ms_per_step": rcool["ms_per_step"], "stage_ms": rcool["stage_ms"],
-            "over_plain": rcool["ms_per_step"] / r32["ms_per_step"],
-            "passes_ms": {k: round(v[0], 4) for k, v in rcool["passes"].items()}}
+    what = {
+        "cooling": "Newtonian cooling (eq. NewtonCool): e_cool %.1f, t_cool %.1f, low-density "
+                   "cut-off at rho_cool = %.4f (mid-height)"
+                   % (COOLING["e_cool"], COOLING["t_cool"], COOLING["rho_cool"]),
+        "coriolis": "the Coriolis force (eq. mom), Omega = (%.3f, %.3f, %.3f)" % CORIOLIS["omega"]}
+    for name, r in rsrc.items():
+        out[name] = {
+            "workload": "%s_%d with %s" % (a.workload, a.size, what[name]),
+            "value": r["value"], "unit": "cell-updates/s", "steps": max(2, a.steps // 5),
+            "ms_per_step": r["ms_per_step"], "stage_ms": r["stage_ms"],
+            "over_plain": r["ms_per_step"] / r32["ms_per_step"],
+            "passes_ms": {k: round(v[0], 4) for k, v in r["passes"].items()}}
     if not a.no_adjoint:
         log("adjoint leg")
         out["adjoint"] = run_adjoint()

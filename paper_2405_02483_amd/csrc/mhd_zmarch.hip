@@ -609,8 +609,21 @@ __global__ __launch_bounds__(TX * TY) void zP(const BoxDev* __restrict__ boxes,
       ws.pq(POUT_GYY)[o] = gyy;
       ws.pq(POUT_QC)[o] = qc;
       // pressure gradients on the x- and y-faces, kept out of the fluxes
-      ws.pq(POUT_DPX)[o] = pres ? ph.gamma1 * op6<1, 0, T>([&](int m) { return S(2, x + m, y); }, g.hxi) : T(0);
-      ws.pq(POUT_DPY)[o] = pres ? ph.gamma1 * op6<1, 0, T>([&](int m) { return S(2, x, y + m); }, g.hyi) : T(0);
+      T dpx = pres ? ph.gamma1 * op6<1, 0, T>([&](int m) { return S(2, x + m, y); }, g.hxi) : T(0);
+      T dpy = pres ? ph.gamma1 * op6<1, 0, T>([&](int m) { return S(2, x, y + m); }, g.hyi) : T(0);
+      if (tm & T_CORI) {
+        // the in-plane parts of the Coriolis force -2 Omega x p (eq. mom),
+        // with the sign of a gradient that pass F subtracts: +2 Omega_z p_y
+        // on x-faces, -2 Omega_z p_x on y-faces
+        dpx -= ph.cor2[2] * op6<0, 0, T>([&](int m) {
+                 return op6<0, 1, T>([&](int n) { return S(1, x + m, y + n); }, T(0));
+               }, T(0));
+        dpy += ph.cor2[2] * op6<0, 0, T>([&](int n) {
+                 return op6<0, 1, T>([&](int m) { return S(0, x + m, y + n); }, T(0));
+               }, T(0));
+      }
+      ws.pq(POUT_DPX)[o] = dpx;
+      ws.pq(POUT_DPY)[o] = dpy;
     }
     // ---- x- and y-faces: energy fluxes
     {
@@ -694,9 +707,12 @@ __global__ __launch_bounds__(TX * TY) void zF(const BoxDev* __restrict__ boxes,
   __shared__ T sx[at_least1(strip_slot<FM>(kXOwn, 9)) * PXs::NP];
   __shared__ T sy[at_least1(strip_slot<FM>(kYOwn, 9)) * PYs::NP];
   __shared__ T s2[at_least1(int(kQz) + int(kEz)) * P3::NP];
-  // Coriolis force (bit 8 of FM, momentum launch only): px, py, pz planes
+  // Coriolis force (bit 8 of FM, momentum launch only; its in-plane parts
+  // come with pass P's face terms): x strips of px and pz, y strips of py
+  // and pz
   constexpr bool kCori = hasf<FM>(8);
-  __shared__ T sc[kCori ? 3 * P3::NP : 1];
+  __shared__ T sxc[kCori ? 2 * PXs::NP : 1];
+  __shared__ T syc[kCori ? 2 * PYs::NP : 1];
   ZLOOP_BEGIN
   PlaneIdx<TX, TY, 3, 0> ix;
   PlaneIdx<TX, TY, 0, 3> iy;
@@ -712,7 +728,8 @@ __global__ __launch_bounds__(TX * TY) void zF(const BoxDev* __restrict__ boxes,
   auto X = [&](int q, int x) -> T { return sx[strip_slot<FM>(kXOwn, q) * PXs::NP + PXs::at(x, ty)]; };
   auto Y = [&](int q, int y) -> T { return sy[strip_slot<FM>(kYOwn, q) * PYs::NP + PYs::at(tx, y)]; };
   auto F2 = [&](int q, int x, int y) -> T { return s2[(q && kQz) * P3::NP + P3::at(x, y)]; };
-  auto C3 = [&](int q, int x, int y) -> T { return sc[q * P3::NP + P3::at(x, y)]; };
+  auto XC = [&](int q, int x) -> T { return sxc[q * PXs::NP + PXs::at(x, ty)]; };
+  auto YC = [&](int q, int y) -> T { return syc[q * PYs::NP + PYs::at(tx, y)]; };
   T acc[7][7];
 #pragma unroll
   for (int a = 0; a < 7; ++a)
@@ -791,9 +808,10 @@ __global__ __launch_bounds__(TX * TY) void zF(const BoxDev* __restrict__ boxes,
         load_plane(sy + strip_slot<FM>(kYOwn, 8) * PYs::NP, ws.q(QOUT_QX), b, iy, k);
       }
       if constexpr (kCori) {
-        load_plane(sc, f.p[1], b, i3, k);
-        load_plane(sc + P3::NP, f.p[2], b, i3, k);
-        load_plane(sc + 2 * P3::NP, f.p[3], b, i3, k);
+        load_plane(sxc, f.p[1], b, ix, k);
+        load_plane(sxc + PXs::NP, f.p[3], b, ix, k);
+        load_plane(syc, f.p[2], b, iy, k);
+        load_plane(syc + PYs::NP, f.p[3], b, iy, k);
       }
       // Bz's dU and f at this plane, fetched with the planes
       T bz_u = T(0), bz_f = T(0);
@@ -853,22 +871,15 @@ __global__ __launch_bounds__(TX * TY) void zF(const BoxDev* __restrict__ boxes,
         }
       }
       // Coriolis force (eq. mom): -2 Omega x p, each component on its own
-      // face; the parts that end with an interpolation along z are scattered
+      // face; the parts that end with an interpolation along z, scattered
+      // below (the in-plane parts arrive with pass P's face terms)
       T czx = T(0), czy = T(0), czz = T(0);
       if constexpr (kCori) {
-        const T wx = ph.cor2[0], wy = ph.cor2[1], wz = ph.cor2[2];
-        if (inch) {
-          acc[1][3] += wz * op6<0, 0, T>([&](int m) {
-                         return op6<0, 1, T>([&](int n) { return C3(1, x + m, y + n); }, T(0));
-                       }, T(0));
-          acc[2][3] -= wz * op6<0, 0, T>([&](int n) {
-                         return op6<0, 1, T>([&](int m) { return C3(0, x + m, y + n); }, T(0));
-                       }, T(0));
-        }
-        czx = -wy * op6<0, 0, T>([&](int m) { return C3(2, x + m, y); }, T(0));
-        czy = wx * op6<0, 0, T>([&](int n) { return C3(2, x, y + n); }, T(0));
-        czz = wy * op6<0, 1, T>([&](int m) { return C3(0, x + m, y); }, T(0)) -
-              wx * op6<0, 1, T>([&](int n) { return C3(1, x, y + n); }, T(0));
+        const T wx = ph.cor2[0], wy = ph.cor2[1];
+        czx = -wy * op6<0, 0, T>([&](int m) { return XC(1, x + m); }, T(0));
+        czy = wx * op6<0, 0, T>([&](int n) { return YC(1, y + n); }, T(0));
+        czz = wy * op6<0, 1, T>([&](int m) { return XC(0, x + m); }, T(0)) -
+              wx * op6<0, 1, T>([&](int n) { return YC(0, y + n); }, T(0));
       }
       T xqy = T(0), yqx = T(0);
       if (hasf<FM>(4)) {
