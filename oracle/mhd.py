@@ -32,6 +32,10 @@ design notes of the repository):
   equation for the energy per volume is Q = -rho (e_m - e_cool) / t_cool
   (e_m relaxes to e_cool on the time scale t_cool at fixed density), times
   one of the density cut-offs of eq. rhocool when one is chosen.
+* eq. ediffav: <e>_horiz is the mean of the energy per unit mass over the
+  x-y plane of each z level (ghost planes included, as filled), and the
+  flux differentiates ln e_m - ln <e_m>_horiz; only the z component
+  changes, since the plane mean does not vary along x or y.
 * eq. mom, Coriolis force: -2 rho Omega x u = -2 Omega x p, with each
   momentum component carried to the face of the component it drives by the
   staggered interpolations (e.g. p_z at an x-face is xdn(zup(p_z))).
@@ -46,9 +50,11 @@ from .stagger import Ops, AX_X, AX_Y, AX_Z
 __all__ = [
     "T_CONT", "T_ADV", "T_PRES", "T_VISC", "T_LORENTZ", "T_INDUCT",
     "T_RESIST", "T_EDIFF", "T_GRAV", "T_ALL", "T_HD", "T_IDEAL", "T_COOL", "T_CORI",
+    "T_EDIFFAV",
     "ALPHA", "BETA", "Grid", "Params", "ghost_fill", "rhs", "rhs_nofill",
     "step", "rk3", "courant", "stats", "step_vjp", "rhs_vjp", "FIELDS",
     "interior_slices", "smoothed_viscosity", "newton_cooling", "coriolis",
+    "horizontal_ln_mean",
 ]
 
 FIELDS = ("rho", "px", "py", "pz", "e", "bx", "by", "bz")
@@ -67,6 +73,7 @@ T_GRAV = 1 << 8      # constant gravity along -z (Forcing, Table 1)
 T_ALL = (1 << 9) - 1
 T_COOL = 1 << 9      # Newtonian cooling (eq. NewtonCool); not part of T_ALL
 T_CORI = 1 << 10     # Coriolis force (eq. mom); not part of T_ALL
+T_EDIFFAV = 1 << 11  # with T_EDIFF: diffuse fluctuations about the plane mean (eq. ediffav)
 T_HD = T_CONT | T_ADV | T_PRES | T_VISC | T_EDIFF
 T_IDEAL = T_CONT | T_ADV | T_PRES | T_LORENTZ | T_INDUCT
 
@@ -210,6 +217,12 @@ def newton_cooling(rho, e, par):
     return q
 
 
+def horizontal_ln_mean(em):
+    """ln <e_m>_horiz of eq. ediffav: the logarithm of the mean of e_m over
+    each z plane, broadcast over the plane."""
+    return torch.log(em.mean(dim=(1, 2), keepdim=True))
+
+
 def coriolis(px, py, pz, par, O):
     """Coriolis force on the momenta (eq. mom): -2 rho Omega x u, written
     -2 Omega x p, each component on its own face.  The other two momentum
@@ -335,7 +348,10 @@ def rhs_nofill(f, grid, par):
         lne = torch.log(em)
         fx = par.nuE * O.xdn(rho) * (dx * O.xdn(nt)) * O.xdn(em) * O.ddxdn(lne)
         fy = par.nuE * O.ydn(rho) * (dy * O.ydn(nt)) * O.ydn(em) * O.ddydn(lne)
-        fz = par.nuE * O.zdn(rho) * (dz * O.zdn(nt)) * O.zdn(em) * O.ddzdn(lne)
+        lnez = lne
+        if T & T_EDIFFAV:
+            lnez = lne - horizontal_ln_mean(em)
+        fz = par.nuE * O.zdn(rho) * (dz * O.zdn(nt)) * O.zdn(em) * O.ddzdn(lnez)
         de = de + O.ddxup(fx) + O.ddyup(fy) + O.ddzup(fz)
     if T & T_COOL:
         de = de + newton_cooling(rho, e, par)
