@@ -84,6 +84,12 @@ enum {
  * momentum component interpolated to the face of the one it drives.  Not
  * part of MHD_T_ALL.                                                        */
 #define MHD_T_CORI     (1u << 10)
+/* With MHD_T_EDIFF: energy diffusion of the fluctuations about the
+ * horizontal mean (eq. ediffav): the z flux differentiates
+ * ln e_m - ln <e_m>, <e_m> the mean of e_m over each z plane of the box
+ * (ghost planes included, as filled).  Not part of MHD_T_ALL; the adjoint
+ * entry points return MHD_EUNSUPPORTED with it.                            */
+#define MHD_T_EDIFFAV  (1u << 11)
 
 /* One box of the mesh (&grid namelist: mx, my, mz, sx, sy, sz). */
 typedef struct {

@@ -55,6 +55,8 @@ struct mhd_ctx {
   int ncu = 1;
   double* d_dt = nullptr;
   void* d_ztab = nullptr;          // z-coefficient tables of wall boxes (ctx dtype)
+  void* d_lnavg = nullptr;         // ln of the plane means of e_m, per plane of every box
+  int nplanes = 0;
   // timing of kernel passes (mhd_profile)
   bool prof = false;
   std::vector<std::pair<int, hipEvent_t>> marks;
@@ -172,6 +174,8 @@ static ZLaunch make_zlaunch(const mhd_ctx* c) {
   L.queue = c->d_queue;
   L.persistent = c->persistent;
   L.ncu = c->ncu;
+  L.nbox = (int)c->h_boxes.size();
+  L.nplanes = c->nplanes;
   L.stream = c->stream;
   L.mark = c->prof ? prof_mark : nullptr;
   L.mark_ctx = const_cast<mhd_ctx*>(c);
@@ -357,6 +361,7 @@ void mhd_destroy(mhd_ctx* c) {
   (void)hipFree(c->d_dt);
   (void)hipFree(c->d_queue);
   (void)hipFree(c->d_ztab);
+  (void)hipFree(c->d_lnavg);
   delete c;
 }
 
@@ -372,7 +377,8 @@ int mhd_init(const mhd_params* p, void* hip_stream, mhd_ctx** out) {
   for (double v : nn)
     if (!(v >= 0.0) || !std::isfinite(v)) return fail(nullptr, MHD_EINVAL, "viscosity, diffusion and Courant coefficients must be finite and >= 0");
   if (!std::isfinite(p->gz) || !std::isfinite(p->c1)) return fail(nullptr, MHD_EINVAL, "gz and c1 must be finite");
-  if (p->terms & ~(MHD_T_ALL | MHD_T_COOL | MHD_T_CORI)) return fail(nullptr, MHD_EINVAL, "unknown term bits");
+  if (p->terms & ~(MHD_T_ALL | MHD_T_COOL | MHD_T_CORI | MHD_T_EDIFFAV))
+    return fail(nullptr, MHD_EINVAL, "unknown term bits");
   if ((p->terms & MHD_T_CORI) &&
       !(std::isfinite(p->omega[0]) && std::isfinite(p->omega[1]) && std::isfinite(p->omega[2])))
     return fail(nullptr, MHD_EINVAL, "the rotation vector must be finite");
@@ -424,7 +430,8 @@ int mhd_init(const mhd_params* p, void* hip_stream, mhd_ctx** out) {
     d.wall = x.bc_z == MHD_BC_WALL;
     d.g0 = x.ngz;
     d.g1 = x.ngz + x.nz;
-    d.pad = 0;
+    d.poff = c->nplanes;
+    c->nplanes += d.nzt;
     d.off = off;
     d.ncell = (long long)d.nx * d.ny * d.nzt;
     d.dx = x.Lx / x.nx;
@@ -488,7 +495,8 @@ int mhd_init(const mhd_params* p, void* hip_stream, mhd_ctx** out) {
     }
   }
   if ((e = hipMalloc(&c->d_dt, sizeof(double))) != hipSuccess ||
-      (e = hipMalloc(&c->d_queue, sizeof(int) * kQueueInts)) != hipSuccess) {
+      (e = hipMalloc(&c->d_queue, sizeof(int) * kQueueInts)) != hipSuccess ||
+      (e = hipMalloc(&c->d_lnavg, c->esize * (size_t)c->nplanes)) != hipSuccess) {
     g_init_err = std::string("device allocation failed: ") + hipGetErrorString(e);
     mhd_destroy(c);
     return MHD_ENOMEM;
@@ -521,6 +529,7 @@ static ZStageArgs<T> zargs(mhd_ctx* c) {
   a.dt_host = 0.0;
   a.cpart = nullptr;
   a.ztab = static_cast<const T*>(c->d_ztab);
+  a.lnavg = static_cast<T*>(c->d_lnavg);
   a.Cdt = c->p.Cdt;
   a.Cdtd = c->p.Cdtd;
   a.nuB = c->p.nuB;
@@ -834,6 +843,7 @@ int mhd_step_adjoint(mhd_ctx* c, void* const f_n[8], double dt, void* const gin[
     return rc;
   for (const auto& b : c->boxes)
     if (b.bc_z != MHD_BC_PERIODIC) return fail(c, MHD_EUNSUPPORTED, "adjoint supports periodic boxes only");
+  if (c->p.terms & MHD_T_EDIFFAV) return fail(c, MHD_EUNSUPPORTED, "adjoint without MHD_T_EDIFFAV only");
   if (!std::isfinite(dt)) return fail(c, MHD_EINVAL, "dt not finite");
   for (int a = 0; a < 8; ++a)
     for (int b = 0; b < 8; ++b)
@@ -849,6 +859,7 @@ int mhd_rhs_adjoint(mhd_ctx* c, void* const f[8], void* const wbar[8], void* con
     return rc;
   for (const auto& b : c->boxes)
     if (b.bc_z != MHD_BC_PERIODIC) return fail(c, MHD_EUNSUPPORTED, "adjoint supports periodic boxes only");
+  if (c->p.terms & MHD_T_EDIFFAV) return fail(c, MHD_EUNSUPPORTED, "adjoint without MHD_T_EDIFFAV only");
   for (int a = 0; a < 8; ++a)
     for (int b = 0; b < 8; ++b)
       if (fbar[b] == f[a] || fbar[b] == wbar[a]) return fail(c, MHD_EINVAL, "fbar overlaps an input");

@@ -19,7 +19,8 @@ namespace smhd {
 enum : unsigned {
   T_CONT = 1u << 0, T_ADV = 1u << 1, T_PRES = 1u << 2, T_VISC = 1u << 3,
   T_LORENTZ = 1u << 4, T_INDUCT = 1u << 5, T_RESIST = 1u << 6,
-  T_EDIFF = 1u << 7, T_GRAV = 1u << 8, T_COOL = 1u << 9, T_CORI = 1u << 10
+  T_EDIFF = 1u << 7, T_GRAV = 1u << 8, T_COOL = 1u << 9, T_CORI = 1u << 10,
+  T_EDIFFAV = 1u << 11
 };
 
 constexpr int kBlock = 256;          // threads per workgroup of the cell kernels
@@ -38,7 +39,8 @@ template <class T> struct Cf {
 // thread of a workgroup through the scalar cache).
 struct BoxDev {
   int nx, ny, nzt, ngz;      // nzt = nz + 2 ngz planes
-  int wall, g0, g1, pad;     // g0 = ngz (first interior plane), g1 = ngz + nz
+  int wall, g0, g1, poff;    // g0 = ngz (first interior plane), g1 = ngz + nz;
+                             // poff: first entry of this box in per-plane tables
   long long off;             // first element in the packed field arrays
   long long ncell;           // nx * ny * nzt
   double dx, dy, dz, hmin, hmax;

@@ -290,7 +290,8 @@ template <class T, int TX, int TY, bool PERS, unsigned QM>
 __global__ __launch_bounds__(TX * TY) void zQ(const BoxDev* __restrict__ boxes,
                                               const ZItem* __restrict__ items, int nitems, const T* __restrict__ ztab,
                                                int* __restrict__ queue,
-                                              CP8<T> f, Phys<T> ph, ZWork<T> ws) {
+                                              CP8<T> f, Phys<T> ph, ZWork<T> ws,
+                                              const T* __restrict__ lnavg) {
   const T* __restrict__ uzg = ws.arr(WS_UZ);
   const T* __restrict__ lntg = ws.arr(WS_LNT);
   const T* __restrict__ Dg = ws.arr(WS_D);
@@ -305,6 +306,7 @@ __global__ __launch_bounds__(TX * TY) void zQ(const BoxDev* __restrict__ boxes,
   const unsigned tm = ph.terms;
   const bool visc = tm & T_VISC, res = tm & T_RESIST, ind = tm & T_INDUCT, lor = tm & T_LORENTZ,
              adv = tm & T_ADV, pres = tm & T_PRES, ediff = tm & T_EDIFF;
+  const bool ediffav = ediff && (tm & T_EDIFFAV);
   const bool need_nu = visc || (res && !(ph.eta_const > T(0)));
   // windows: slot m = plane r-5+m
   T wRX[6] = {}, wLX[6] = {}, wPX[6] = {}, wUX[6] = {}, wBX[6] = {};
@@ -353,6 +355,8 @@ __global__ __launch_bounds__(TX * TY) void zQ(const BoxDev* __restrict__ boxes,
         ev = f.p[4][o];
         em = ev / rhov;
         lem = log(em);
+        // eq. ediffav: the z flux differentiates ln e_m - ln <e_m>
+        if (ediffav) lem -= lnavg[b.poff + k];
       }
     }
     push(wRX, rx); push(wLX, lx); push(wPX, px); push(wUX, ux); push(wBX, bxv);
@@ -938,6 +942,31 @@ __global__ __launch_bounds__(TX * TY) void zF(const BoxDev* __restrict__ boxes,
   ZLOOP_END
 }
 
+// ln <e_m> over each z plane of every box (eq. ediffav), one workgroup per
+// plane: e_m = e / rho summed in float64 in a fixed order (deterministic),
+// then the log of the mean, into out[BoxDev::poff + k].
+template <class T>
+__global__ __launch_bounds__(256) void k_plane_lnmean(const BoxDev* __restrict__ boxes, int nbox,
+                                                      const T* __restrict__ rho,
+                                                      const T* __restrict__ e, T* __restrict__ out) {
+  __shared__ double sh[256];
+  const int P = (int)blockIdx.x;
+  int bi = 0;
+  while (bi + 1 < nbox && boxes[bi + 1].poff <= P) ++bi;
+  const BoxDev b = boxes[bi];
+  const int n = b.nx * b.ny;
+  const long long base = b.off + (long long)(P - b.poff) * n;
+  double s = 0.0;
+  for (int i = (int)threadIdx.x; i < n; i += 256) s += (double)e[base + i] / (double)rho[base + i];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[P] = T(log(sh[0] / (double)n));
+}
+
 // Courant time step of the current state from the per-item maxima of A1 / A2
 // (eq. courantcond, wave and diffusion limits), into dt_dev[0].
 __global__ __launch_bounds__(256) void k_dt(const BoxDev* __restrict__ boxes,
@@ -1045,11 +1074,15 @@ static void launch_zstage_m(const ZLaunch& L, const ZStageArgs<T>& a) {
     hipLaunchKernelGGL(k_dt, dim3(1), dim3(256), 0, L.stream, L.boxes, L.items, n, a.cpart, a.Cdt,
                        a.Cdtd, a.nuB, a.eta_const, a.dt_dev);
   }
+  if ((a.ph.terms & T_EDIFF) && (a.ph.terms & T_EDIFFAV))
+    hipLaunchKernelGGL(k_plane_lnmean<T>, dim3(L.nplanes), dim3(256), 0, L.stream, L.boxes, L.nbox, a.f.p[0],
+                       a.f.p[4], a.lnavg);
   L.at(PASS_EDGES);
   hipLaunchKernelGGL((zQ<T, TX, TY, PERS, QM_EDGES>), grid((const void*)zQ<T, TX, TY, PERS, QM_EDGES>), block, 0,
-                     L.stream, L.boxes, L.items, n, a.ztab, q ? q + 16 : q, a.f, a.ph, a.w);
+                     L.stream, L.boxes, L.items, n, a.ztab, q ? q + 16 : q, a.f, a.ph, a.w, a.lnavg);
   hipLaunchKernelGGL((zQ<T, TX, TY, PERS, QM_ZC>), grid((const void*)zQ<T, TX, TY, PERS, QM_ZC>), block, 0,
-                     L.stream, L.boxes, L.items, n, a.ztab, q ? q + 32 + 8 * kNFMasks : q, a.f, a.ph, a.w);
+                     L.stream, L.boxes, L.items, n, a.ztab, q ? q + 32 + 8 * kNFMasks : q, a.f, a.ph, a.w,
+                     a.lnavg);
   L.at(PASS_CF);
   hipLaunchKernelGGL((zP<T, TX, TY, PERS>), grid((const void*)zP<T, TX, TY, PERS>), block, 0, L.stream, L.boxes,
                      L.items, n, a.ztab, q ? q + 24 : q, a.f, a.ph, a.w);

@@ -61,6 +61,7 @@ struct ZLaunch {
   int* queue;             // device, kQueueInts counters (persistent mode)
   int persistent;         // 0: one workgroup per item; 1: item queues
   int ncu;                // compute units of the device
+  int nbox, nplanes;      // boxes; z planes of all boxes
   hipStream_t stream;
   void (*mark)(void*, int);
   void* mark_ctx;
@@ -82,6 +83,7 @@ template <class T> struct ZStageArgs {
   double dt_host;
   CPart* cpart;           // non-null: also compute the Courant dt into dt_dev
   const T* ztab;          // z-coefficient tables of wall boxes (BoxDev::zoff)
+  T* lnavg;               // per plane of every box (BoxDev::poff): ln <e_m> (T_EDIFFAV)
   double Cdt, Cdtd, nuB, eta_const;
 };
 

@@ -45,7 +45,6 @@ def _params(**over):
     (dict(terms=lib.T_ALL | lib.T_COOL, t_cool=1.0, cool_cut=3), lib.MHD_EINVAL),
     (dict(terms=lib.T_ALL | lib.T_COOL, t_cool=1.0, cool_cut=1, rho_cool=0.0), lib.MHD_EINVAL),
     (dict(terms=lib.T_ALL | lib.T_CORI, omega=(0.0, float("inf"), 0.0)), lib.MHD_EINVAL),
-    (dict(terms=1 << 11), lib.MHD_EINVAL),
     (dict(nbox=0), lib.MHD_EINVAL),
     (dict(boxes=[dict(nx=5, ny=8, nz=8)]), lib.MHD_EINVAL),
     (dict(boxes=[dict(nx=8, ny=8, nz=8, ngz=5, bc_z=0)]), lib.MHD_EINVAL),
