@@ -56,6 +56,7 @@ struct mhd_ctx {
   double* d_dt = nullptr;
   void* d_ztab = nullptr;          // z-coefficient tables of wall boxes (ctx dtype)
   void* d_lnavg = nullptr;         // ln of the plane means of e_m, per plane of every box
+  double* d_lnpart = nullptr;      // their partial sums, kPlaneSlices per plane
   int nplanes = 0;
   // timing of kernel passes (mhd_profile)
   bool prof = false;
@@ -362,6 +363,7 @@ void mhd_destroy(mhd_ctx* c) {
   (void)hipFree(c->d_queue);
   (void)hipFree(c->d_ztab);
   (void)hipFree(c->d_lnavg);
+  (void)hipFree(c->d_lnpart);
   delete c;
 }
 
@@ -496,7 +498,8 @@ int mhd_init(const mhd_params* p, void* hip_stream, mhd_ctx** out) {
   }
   if ((e = hipMalloc(&c->d_dt, sizeof(double))) != hipSuccess ||
       (e = hipMalloc(&c->d_queue, sizeof(int) * kQueueInts)) != hipSuccess ||
-      (e = hipMalloc(&c->d_lnavg, c->esize * (size_t)c->nplanes)) != hipSuccess) {
+      (e = hipMalloc(&c->d_lnavg, c->esize * (size_t)c->nplanes)) != hipSuccess ||
+      (e = hipMalloc(&c->d_lnpart, sizeof(double) * kPlaneSlices * (size_t)c->nplanes)) != hipSuccess) {
     g_init_err = std::string("device allocation failed: ") + hipGetErrorString(e);
     mhd_destroy(c);
     return MHD_ENOMEM;
@@ -530,6 +533,7 @@ static ZStageArgs<T> zargs(mhd_ctx* c) {
   a.cpart = nullptr;
   a.ztab = static_cast<const T*>(c->d_ztab);
   a.lnavg = static_cast<T*>(c->d_lnavg);
+  a.lnpart = c->d_lnpart;
   a.Cdt = c->p.Cdt;
   a.Cdtd = c->p.Cdtd;
   a.nuB = c->p.nuB;

@@ -942,29 +942,46 @@ __global__ __launch_bounds__(TX * TY) void zF(const BoxDev* __restrict__ boxes,
   ZLOOP_END
 }
 
-// ln <e_m> over each z plane of every box (eq. ediffav), one workgroup per
-// plane: e_m = e / rho summed in float64 in a fixed order (deterministic),
-// then the log of the mean, into out[BoxDev::poff + k].
+// ln <e_m> over each z plane of every box (eq. ediffav).  e_m = e / rho is
+// summed in float64 in a fixed order (deterministic): k_plane_sum gives
+// workgroup (P, s) the s-th of kPlaneSlices contiguous slices of plane P
+// (planes of all boxes back to back, BoxDev::poff); k_plane_lnmean adds the
+// slices of each plane in order and writes the log of the mean.
+
 template <class T>
-__global__ __launch_bounds__(256) void k_plane_lnmean(const BoxDev* __restrict__ boxes, int nbox,
-                                                      const T* __restrict__ rho,
-                                                      const T* __restrict__ e, T* __restrict__ out) {
+__global__ __launch_bounds__(256) void k_plane_sum(const BoxDev* __restrict__ boxes, int nbox,
+                                                   const T* __restrict__ rho, const T* __restrict__ e,
+                                                   double* __restrict__ part) {
   __shared__ double sh[256];
-  const int P = (int)blockIdx.x;
+  const int P = (int)blockIdx.x / kPlaneSlices, sl = (int)blockIdx.x % kPlaneSlices;
   int bi = 0;
   while (bi + 1 < nbox && boxes[bi + 1].poff <= P) ++bi;
   const BoxDev b = boxes[bi];
   const int n = b.nx * b.ny;
+  const int i0 = (int)((long long)n * sl / kPlaneSlices), i1 = (int)((long long)n * (sl + 1) / kPlaneSlices);
   const long long base = b.off + (long long)(P - b.poff) * n;
   double s = 0.0;
-  for (int i = (int)threadIdx.x; i < n; i += 256) s += (double)e[base + i] / (double)rho[base + i];
+  for (int i = i0 + (int)threadIdx.x; i < i1; i += 256) s += (double)e[base + i] / (double)rho[base + i];
   sh[threadIdx.x] = s;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
     if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[P] = T(log(sh[0] / (double)n));
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_plane_lnmean(const BoxDev* __restrict__ boxes, int nbox,
+                                                      int nplanes, const double* __restrict__ part,
+                                                      T* __restrict__ out) {
+  const int P = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (P >= nplanes) return;
+  int bi = 0;
+  while (bi + 1 < nbox && boxes[bi + 1].poff <= P) ++bi;
+  double s = 0.0;
+  for (int sl = 0; sl < kPlaneSlices; ++sl) s += part[P * kPlaneSlices + sl];
+  out[P] = T(log(s / ((double)boxes[bi].nx * boxes[bi].ny)));
 }
 
 // Courant time step of the current state from the per-item maxima of A1 / A2
@@ -1074,9 +1091,12 @@ static void launch_zstage_m(const ZLaunch& L, const ZStageArgs<T>& a) {
     hipLaunchKernelGGL(k_dt, dim3(1), dim3(256), 0, L.stream, L.boxes, L.items, n, a.cpart, a.Cdt,
                        a.Cdtd, a.nuB, a.eta_const, a.dt_dev);
   }
-  if ((a.ph.terms & T_EDIFF) && (a.ph.terms & T_EDIFFAV))
-    hipLaunchKernelGGL(k_plane_lnmean<T>, dim3(L.nplanes), dim3(256), 0, L.stream, L.boxes, L.nbox, a.f.p[0],
-                       a.f.p[4], a.lnavg);
+  if ((a.ph.terms & T_EDIFF) && (a.ph.terms & T_EDIFFAV)) {
+    hipLaunchKernelGGL(k_plane_sum<T>, dim3(L.nplanes * kPlaneSlices), dim3(256), 0, L.stream, L.boxes, L.nbox,
+                       a.f.p[0], a.f.p[4], a.lnpart);
+    hipLaunchKernelGGL(k_plane_lnmean<T>, dim3((L.nplanes + 255) / 256), dim3(256), 0, L.stream, L.boxes,
+                       L.nbox, L.nplanes, a.lnpart, a.lnavg);
+  }
   L.at(PASS_EDGES);
   hipLaunchKernelGGL((zQ<T, TX, TY, PERS, QM_EDGES>), grid((const void*)zQ<T, TX, TY, PERS, QM_EDGES>), block, 0,
                      L.stream, L.boxes, L.items, n, a.ztab, q ? q + 16 : q, a.f, a.ph, a.w, a.lnavg);

@@ -47,6 +47,9 @@ template <class T> struct ZWork {
   __host__ __device__ T* pq(int i) const { return arr(WS_P0 + i); }
 };
 
+// Slices of a plane summed by separate workgroups for the plane means.
+constexpr int kPlaneSlices = 8;
+
 // Item queues of the persistent mode: 8 counters per launch, at most 8 launches.
 constexpr int kQueueInts = 64;
 
@@ -84,6 +87,7 @@ template <class T> struct ZStageArgs {
   CPart* cpart;           // non-null: also compute the Courant dt into dt_dev
   const T* ztab;          // z-coefficient tables of wall boxes (BoxDev::zoff)
   T* lnavg;               // per plane of every box (BoxDev::poff): ln <e_m> (T_EDIFFAV)
+  double* lnpart;         // kPlaneSlices partial sums per plane (T_EDIFFAV)
   double Cdt, Cdtd, nuB, eta_const;
 };
 
