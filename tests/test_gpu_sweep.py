@@ -3,7 +3,9 @@ ragged box sizes from 6 to 40 cells per axis, periodic and closed-wall boxes,
 both precisions, every tile shape in both launch modes, each with a random
 tile for the final pass.  The fixed cases elsewhere use a handful of sizes;
 this one aims at indexing mistakes that only some (size, tile) pairs expose
-(partial tiles, chunk edges, planes next to a wall).
+(partial tiles, chunk edges, planes next to a wall).  Each box also switches
+on a random subset of the optional terms (Newtonian cooling, the Coriolis
+force, energy diffusion about the horizontal mean).
 
 Error measure: relative L2 per field, as in the other parity tests.  In a
 closed-wall box the atmosphere is hydrostatic, so the z momentum rate is the
@@ -53,7 +55,7 @@ def _errors(got, want, scale):
                          ids=["%s%dx%dx%d" % ("wall" if c[1] else "per", c[2], c[3], c[4])
                               for c in _cases()])
 def test_rhs_random_sizes_all_tiles(case, walls, nx, ny, nz, ftiles):
-    from paper_2405_02483_amd.lib import Context, TILES
+    from paper_2405_02483_amd.lib import Context, TILES, T_ALL, T_COOL, T_CORI, T_EDIFFAV
     if walls:
         f, box, prm = inputs.stratified(nx, ny, nz, seed=300 + case)
     else:
@@ -61,6 +63,11 @@ def test_rhs_random_sizes_all_tiles(case, walls, nx, ny, nz, ftiles):
         f, box, prm = inputs.turbulent(n=n, seed=300 + case, kmax=3.0)
         f = [np.ascontiguousarray(a[:nz, :ny, :nx]) for a in f]
         box = dict(box, nx=nx, ny=ny, nz=nz, Lx=nx / n, Ly=ny / n, Lz=nz / n)
+    trng = random.Random(9000 + case)
+    extra = sum(bit for bit in (T_COOL, T_CORI, T_EDIFFAV) if trng.random() < 0.5)
+    prm = dict(prm, terms=T_ALL | extra, e_cool=trng.uniform(0.5, 2.0), t_cool=trng.uniform(0.3, 2.0),
+               rho_cool=trng.uniform(0.2, 2.0), cool_cut=trng.randrange(3),
+               omega=tuple(trng.uniform(-1.5, 1.5) for _ in range(3)))
     g, p = grid_params(box, prm)
     ft = tuple(torch.from_numpy(a.copy()) for a in f)
     want = O.rhs(ft, g, p)
