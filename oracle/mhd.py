@@ -36,6 +36,11 @@ design notes of the repository):
   x-y plane of each z level (ghost planes included, as filled), and the
   flux differentiates ln e_m - ln <e_m>_horiz; only the z component
   changes, since the plane mean does not vary along x or y.
+* eq. pressure: P_aver is the mean of P over each z plane (ghost planes
+  included, as filled); every component of grad P in the momentum equation
+  takes the printed form exp(ln P_aver)_f exp(ln(P/P_aver))_f
+  [d ln(P/P_aver) + d ln P_aver]_f with the staggered interpolation and
+  derivative to the face f (the x and y derivatives of P_aver vanish).
 * eq. mom, Coriolis force: -2 rho Omega x u = -2 Omega x p, with each
   momentum component carried to the face of the component it drives by the
   staggered interpolations (e.g. p_z at an x-face is xdn(zup(p_z))).
@@ -50,11 +55,11 @@ from .stagger import Ops, AX_X, AX_Y, AX_Z
 __all__ = [
     "T_CONT", "T_ADV", "T_PRES", "T_VISC", "T_LORENTZ", "T_INDUCT",
     "T_RESIST", "T_EDIFF", "T_GRAV", "T_ALL", "T_HD", "T_IDEAL", "T_COOL", "T_CORI",
-    "T_EDIFFAV",
+    "T_EDIFFAV", "T_LNP",
     "ALPHA", "BETA", "Grid", "Params", "ghost_fill", "rhs", "rhs_nofill",
     "step", "rk3", "courant", "stats", "step_vjp", "rhs_vjp", "FIELDS",
     "interior_slices", "smoothed_viscosity", "newton_cooling", "coriolis",
-    "horizontal_ln_mean",
+    "horizontal_ln_mean", "pressure_gradient_ln",
 ]
 
 FIELDS = ("rho", "px", "py", "pz", "e", "bx", "by", "bz")
@@ -74,6 +79,7 @@ T_ALL = (1 << 9) - 1
 T_COOL = 1 << 9      # Newtonian cooling (eq. NewtonCool); not part of T_ALL
 T_CORI = 1 << 10     # Coriolis force (eq. mom); not part of T_ALL
 T_EDIFFAV = 1 << 11  # with T_EDIFF: diffuse fluctuations about the plane mean (eq. ediffav)
+T_LNP = 1 << 12      # with T_PRES: grad P through ln(P / P_aver) (eq. pressure)
 T_HD = T_CONT | T_ADV | T_PRES | T_VISC | T_EDIFF
 T_IDEAL = T_CONT | T_ADV | T_PRES | T_LORENTZ | T_INDUCT
 
@@ -217,6 +223,18 @@ def newton_cooling(rho, e, par):
     return q
 
 
+def pressure_gradient_ln(P, O):
+    """grad P on the faces through q = ln(P / P_aver) (eq. pressure), P_aver
+    the mean of P over each z plane: for each axis a,
+    exp(adn(ln P_aver)) exp(adn(q)) (ddadn(q) + ddadn(ln P_aver))."""
+    lpa = torch.log(P.mean(dim=(1, 2), keepdim=True)).expand_as(P).contiguous()
+    q = torch.log(P) - lpa
+    out = []
+    for dn, ddn in ((O.xdn, O.ddxdn), (O.ydn, O.ddydn), (O.zdn, O.ddzdn)):
+        out.append(torch.exp(dn(lpa)) * torch.exp(dn(q)) * (ddn(q) + ddn(lpa)))
+    return tuple(out)
+
+
 def horizontal_ln_mean(em):
     """ln <e_m>_horiz of eq. ediffav: the logarithm of the mean of e_m over
     each z plane, broadcast over the plane."""
@@ -311,9 +329,13 @@ def rhs_nofill(f, grid, par):
                      + O.ddxup(O.xdn(pz) * O.zdn(ux))
                      + O.ddyup(O.ydn(pz) * O.zdn(uy)))
     if T & T_PRES:
-        dpx = dpx - O.ddxdn(P)
-        dpy = dpy - O.ddydn(P)
-        dpz = dpz - O.ddzdn(P)
+        if T & T_LNP:
+            gx, gy, gz = pressure_gradient_ln(P, O)
+        else:
+            gx, gy, gz = O.ddxdn(P), O.ddydn(P), O.ddzdn(P)
+        dpx = dpx - gx
+        dpy = dpy - gy
+        dpz = dpz - gz
     if T & T_LORENTZ:
         dpx = dpx + (O.zup(jy * O.xdn(bz)) - O.yup(jz * O.xdn(by))) / mu
         dpy = dpy + (O.xup(jz * O.ydn(bx)) - O.zup(jx * O.ydn(bz))) / mu
