@@ -90,6 +90,12 @@ enum {
  * (ghost planes included, as filled).  Not part of MHD_T_ALL; the adjoint
  * entry points return MHD_EUNSUPPORTED with it.                            */
 #define MHD_T_EDIFFAV  (1u << 11)
+/* With MHD_T_PRES: grad P in the momentum equation through
+ * q = ln(P / P_aver), P_aver the mean of P over each z plane of the box
+ * (eq. pressure): on a face f of axis a, exp(adn(ln P_aver)) exp(adn(q))
+ * (ddadn(q) + ddadn(ln P_aver)).  Exact for an exponential atmosphere.  Not
+ * part of MHD_T_ALL; the adjoint entry points return MHD_EUNSUPPORTED.   */
+#define MHD_T_LNP      (1u << 12)
 
 /* One box of the mesh (&grid namelist: mx, my, mz, sx, sy, sz). */
 typedef struct {

@@ -57,6 +57,7 @@ struct mhd_ctx {
   void* d_ztab = nullptr;          // z-coefficient tables of wall boxes (ctx dtype)
   void* d_lnavg = nullptr;         // ln of the plane means of e_m, per plane of every box
   double* d_lnpart = nullptr;      // their partial sums, kPlaneSlices per plane
+  void* d_lnpav = nullptr;         // ln of the plane means of P, per plane of every box
   int nplanes = 0;
   // timing of kernel passes (mhd_profile)
   bool prof = false;
@@ -160,6 +161,7 @@ template <class T> static ZWork<T> make_zwork(const mhd_ctx* c) {
   ZWork<T> w;
   w.base = static_cast<T*>(c->work);
   w.stride = c->nelem;
+  w.lnpav = static_cast<T*>(c->d_lnpav);
   return w;
 }
 
@@ -364,6 +366,7 @@ void mhd_destroy(mhd_ctx* c) {
   (void)hipFree(c->d_ztab);
   (void)hipFree(c->d_lnavg);
   (void)hipFree(c->d_lnpart);
+  (void)hipFree(c->d_lnpav);
   delete c;
 }
 
@@ -379,7 +382,7 @@ int mhd_init(const mhd_params* p, void* hip_stream, mhd_ctx** out) {
   for (double v : nn)
     if (!(v >= 0.0) || !std::isfinite(v)) return fail(nullptr, MHD_EINVAL, "viscosity, diffusion and Courant coefficients must be finite and >= 0");
   if (!std::isfinite(p->gz) || !std::isfinite(p->c1)) return fail(nullptr, MHD_EINVAL, "gz and c1 must be finite");
-  if (p->terms & ~(MHD_T_ALL | MHD_T_COOL | MHD_T_CORI | MHD_T_EDIFFAV))
+  if (p->terms & ~(MHD_T_ALL | MHD_T_COOL | MHD_T_CORI | MHD_T_EDIFFAV | MHD_T_LNP))
     return fail(nullptr, MHD_EINVAL, "unknown term bits");
   if ((p->terms & MHD_T_CORI) &&
       !(std::isfinite(p->omega[0]) && std::isfinite(p->omega[1]) && std::isfinite(p->omega[2])))
@@ -499,7 +502,8 @@ int mhd_init(const mhd_params* p, void* hip_stream, mhd_ctx** out) {
   if ((e = hipMalloc(&c->d_dt, sizeof(double))) != hipSuccess ||
       (e = hipMalloc(&c->d_queue, sizeof(int) * kQueueInts)) != hipSuccess ||
       (e = hipMalloc(&c->d_lnavg, c->esize * (size_t)c->nplanes)) != hipSuccess ||
-      (e = hipMalloc(&c->d_lnpart, sizeof(double) * kPlaneSlices * (size_t)c->nplanes)) != hipSuccess) {
+      (e = hipMalloc(&c->d_lnpart, sizeof(double) * kPlaneSlices * (size_t)c->nplanes)) != hipSuccess ||
+      (e = hipMalloc(&c->d_lnpav, c->esize * (size_t)c->nplanes)) != hipSuccess) {
     g_init_err = std::string("device allocation failed: ") + hipGetErrorString(e);
     mhd_destroy(c);
     return MHD_ENOMEM;
@@ -847,7 +851,8 @@ int mhd_step_adjoint(mhd_ctx* c, void* const f_n[8], double dt, void* const gin[
     return rc;
   for (const auto& b : c->boxes)
     if (b.bc_z != MHD_BC_PERIODIC) return fail(c, MHD_EUNSUPPORTED, "adjoint supports periodic boxes only");
-  if (c->p.terms & MHD_T_EDIFFAV) return fail(c, MHD_EUNSUPPORTED, "adjoint without MHD_T_EDIFFAV only");
+  if (c->p.terms & (MHD_T_EDIFFAV | MHD_T_LNP))
+    return fail(c, MHD_EUNSUPPORTED, "adjoint without MHD_T_EDIFFAV and MHD_T_LNP only");
   if (!std::isfinite(dt)) return fail(c, MHD_EINVAL, "dt not finite");
   for (int a = 0; a < 8; ++a)
     for (int b = 0; b < 8; ++b)
@@ -863,7 +868,8 @@ int mhd_rhs_adjoint(mhd_ctx* c, void* const f[8], void* const wbar[8], void* con
     return rc;
   for (const auto& b : c->boxes)
     if (b.bc_z != MHD_BC_PERIODIC) return fail(c, MHD_EUNSUPPORTED, "adjoint supports periodic boxes only");
-  if (c->p.terms & MHD_T_EDIFFAV) return fail(c, MHD_EUNSUPPORTED, "adjoint without MHD_T_EDIFFAV only");
+  if (c->p.terms & (MHD_T_EDIFFAV | MHD_T_LNP))
+    return fail(c, MHD_EUNSUPPORTED, "adjoint without MHD_T_EDIFFAV and MHD_T_LNP only");
   for (int a = 0; a < 8; ++a)
     for (int b = 0; b < 8; ++b)
       if (fbar[b] == f[a] || fbar[b] == wbar[a]) return fail(c, MHD_EINVAL, "fbar overlaps an input");

@@ -286,12 +286,15 @@ __global__ __launch_bounds__(TX * TY) void zA2(const BoxDev* __restrict__ boxes,
 // The stage runs one launch of each: apart, each needs far fewer registers
 // (float64: occupancy 1 -> 2 and 3), for four arrays read twice.
 constexpr unsigned QM_EDGES = 1u, QM_ZC = 2u;
+// with QM_ZC: dP/dz through ln(P / P_aver) (eq. pressure)
+constexpr unsigned QM_LNP = 4u;
 template <class T, int TX, int TY, bool PERS, unsigned QM>
 __global__ __launch_bounds__(TX * TY) void zQ(const BoxDev* __restrict__ boxes,
                                               const ZItem* __restrict__ items, int nitems, const T* __restrict__ ztab,
                                                int* __restrict__ queue,
                                               CP8<T> f, Phys<T> ph, ZWork<T> ws,
-                                              const T* __restrict__ lnavg) {
+                                              const T* __restrict__ lnavg,
+                                              const T* __restrict__ lnpav) {
   const T* __restrict__ uzg = ws.arr(WS_UZ);
   const T* __restrict__ lntg = ws.arr(WS_LNT);
   const T* __restrict__ Dg = ws.arr(WS_D);
@@ -312,11 +315,15 @@ __global__ __launch_bounds__(TX * TY) void zQ(const BoxDev* __restrict__ boxes,
   T wRX[6] = {}, wLX[6] = {}, wPX[6] = {}, wUX[6] = {}, wBX[6] = {};
   T wRY[6] = {}, wLY[6] = {}, wPY[6] = {}, wUY[6] = {}, wBY[6] = {};
   T wPZ[6] = {}, wUZ[6] = {}, wE[6] = {}, wRho[6] = {}, wNu[6] = {}, wEm[6] = {}, wLem[6] = {};
+  // eq. pressure (QM_LNP): ln(P / P_aver) and ln P_aver
+  constexpr bool kL = QM & QM_LNP;
+  T wLq[6] = {}, wLpa[6] = {};
   const T inv_mu = ph.inv_mu;
   for (int r = it.z0 - 3; r <= it.z1 + 2; ++r) {
     T rx = T(0), lx = T(0), px = T(0), ux = T(0), bxv = T(0);
     T ry = T(0), ly = T(0), py = T(0), uy = T(0), byv = T(0);
     T pzv = T(0), uzv = T(0), ev = T(0), rhov = T(0), nuv = T(0), em = T(0), lem = T(0);
+    T lq = T(0), lpa = T(0);
     if (valid(r)) {
       const int k = kk(r), sl = wrapm(r, 3);
       const long long o = col(r);
@@ -357,12 +364,20 @@ __global__ __launch_bounds__(TX * TY) void zQ(const BoxDev* __restrict__ boxes,
         lem = log(em);
         // eq. ediffav: the z flux differentiates ln e_m - ln <e_m>
         if (ediffav) lem -= lnavg[b.poff + k];
+        if constexpr (kL) {
+          lpa = lnpav[b.poff + k];
+          lq = log(ph.gamma1 * ev) - lpa;
+        }
       }
     }
     push(wRX, rx); push(wLX, lx); push(wPX, px); push(wUX, ux); push(wBX, bxv);
     push(wRY, ry); push(wLY, ly); push(wPY, py); push(wUY, uy); push(wBY, byv);
     push(wPZ, pzv); push(wUZ, uzv); push(wE, ev); push(wRho, rhov); push(wNu, nuv);
     push(wEm, em); push(wLem, lem);
+    if constexpr (kL) {
+      push(wLq, lq);
+      push(wLpa, lpa);
+    }
 
     // edges and z-face of plane q = r - 2 (window slot 3)
     const int q = r - 2;
@@ -465,7 +480,17 @@ __global__ __launch_bounds__(TX * TY) void zQ(const BoxDev* __restrict__ boxes,
           ws.q(QOUT_HZ)[o] = hz;
           // pressure gradient on its own: folded into the flux, a pressure
           // of order one would swamp the much smaller stresses in float32
-          ws.q(QOUT_DPZ)[o] = pres ? ph.gamma1 * zwin<1, 0, 6, 3>(wE, q, wall, N, g.hzi, zt) : T(0);
+          T dpz = T(0);
+          if (pres) {
+            if constexpr (kL)
+              dpz = exp(zwin<0, 0, 6, 3>(wLpa, q, wall, N, T(0), zt)) *
+                    exp(zwin<0, 0, 6, 3>(wLq, q, wall, N, T(0), zt)) *
+                    (zwin<1, 0, 6, 3>(wLq, q, wall, N, g.hzi, zt) +
+                     zwin<1, 0, 6, 3>(wLpa, q, wall, N, g.hzi, zt));
+            else
+              dpz = ph.gamma1 * zwin<1, 0, 6, 3>(wE, q, wall, N, g.hzi, zt);
+          }
+          ws.q(QOUT_DPZ)[o] = dpz;
         }
       }
     }
@@ -503,6 +528,7 @@ __global__ __launch_bounds__(TX * TY) void zP(const BoxDev* __restrict__ boxes,
                                               CP8<T> f, Phys<T> ph, ZWork<T> ws) {
   const T* __restrict__ lntg = ws.arr(WS_LNT);
   const T* __restrict__ Dg = ws.arr(WS_D);
+  const T* __restrict__ lnpav = ws.lnpav;
   using P6 = Plane<TX, TY, 6>;
   using P3 = Plane<TX, TY, 3>;
   constexpr int NT = TX * TY;
@@ -613,8 +639,21 @@ __global__ __launch_bounds__(TX * TY) void zP(const BoxDev* __restrict__ boxes,
       ws.pq(POUT_GYY)[o] = gyy;
       ws.pq(POUT_QC)[o] = qc;
       // pressure gradients on the x- and y-faces, kept out of the fluxes
-      T dpx = pres ? ph.gamma1 * op6<1, 0, T>([&](int m) { return S(2, x + m, y); }, g.hxi) : T(0);
-      T dpy = pres ? ph.gamma1 * op6<1, 0, T>([&](int m) { return S(2, x, y + m); }, g.hyi) : T(0);
+      T dpx = T(0), dpy = T(0);
+      if (pres && (tm & T_LNP)) {
+        // eq. pressure: exp(ln P_aver) exp(adn(q)) ddadn(q), q = ln(P / P_aver)
+        // (the x and y derivatives of the plane mean vanish)
+        const T lpa = lnpav[b.poff + k];
+        auto lq = [&](int xx, int yy) { return log(ph.gamma1 * S(2, xx, yy)) - lpa; };
+        const T epa = exp(lpa);
+        dpx = epa * exp(op6<0, 0, T>([&](int m) { return lq(x + m, y); }, T(0))) *
+              op6<1, 0, T>([&](int m) { return lq(x + m, y); }, g.hxi);
+        dpy = epa * exp(op6<0, 0, T>([&](int m) { return lq(x, y + m); }, T(0))) *
+              op6<1, 0, T>([&](int m) { return lq(x, y + m); }, g.hyi);
+      } else if (pres) {
+        dpx = ph.gamma1 * op6<1, 0, T>([&](int m) { return S(2, x + m, y); }, g.hxi);
+        dpy = ph.gamma1 * op6<1, 0, T>([&](int m) { return S(2, x, y + m); }, g.hyi);
+      }
       if (tm & T_CORI) {
         // the in-plane parts of the Coriolis force -2 Omega x p (eq. mom),
         // with the sign of a gradient that pass F subtracts: +2 Omega_z p_y
@@ -952,6 +991,7 @@ template <class T>
 __global__ __launch_bounds__(256) void k_plane_sum(const BoxDev* __restrict__ boxes, int nbox,
                                                    const T* __restrict__ rho, const T* __restrict__ e,
                                                    double* __restrict__ part) {
+  // rho == nullptr: sum e itself (for the plane means of P)
   __shared__ double sh[256];
   const int P = (int)blockIdx.x / kPlaneSlices, sl = (int)blockIdx.x % kPlaneSlices;
   int bi = 0;
@@ -961,7 +1001,10 @@ __global__ __launch_bounds__(256) void k_plane_sum(const BoxDev* __restrict__ bo
   const int i0 = (int)((long long)n * sl / kPlaneSlices), i1 = (int)((long long)n * (sl + 1) / kPlaneSlices);
   const long long base = b.off + (long long)(P - b.poff) * n;
   double s = 0.0;
-  for (int i = i0 + (int)threadIdx.x; i < i1; i += 256) s += (double)e[base + i] / (double)rho[base + i];
+  if (rho)
+    for (int i = i0 + (int)threadIdx.x; i < i1; i += 256) s += (double)e[base + i] / (double)rho[base + i];
+  else
+    for (int i = i0 + (int)threadIdx.x; i < i1; i += 256) s += (double)e[base + i];
   sh[threadIdx.x] = s;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
@@ -974,14 +1017,14 @@ __global__ __launch_bounds__(256) void k_plane_sum(const BoxDev* __restrict__ bo
 template <class T>
 __global__ __launch_bounds__(256) void k_plane_lnmean(const BoxDev* __restrict__ boxes, int nbox,
                                                       int nplanes, const double* __restrict__ part,
-                                                      T* __restrict__ out) {
+                                                      double scale, T* __restrict__ out) {
   const int P = (int)(blockIdx.x * blockDim.x + threadIdx.x);
   if (P >= nplanes) return;
   int bi = 0;
   while (bi + 1 < nbox && boxes[bi + 1].poff <= P) ++bi;
   double s = 0.0;
   for (int sl = 0; sl < kPlaneSlices; ++sl) s += part[P * kPlaneSlices + sl];
-  out[P] = T(log(s / ((double)boxes[bi].nx * boxes[bi].ny)));
+  out[P] = T(log(scale * s / ((double)boxes[bi].nx * boxes[bi].ny)));
 }
 
 // Courant time step of the current state from the per-item maxima of A1 / A2
@@ -1095,14 +1138,27 @@ static void launch_zstage_m(const ZLaunch& L, const ZStageArgs<T>& a) {
     hipLaunchKernelGGL(k_plane_sum<T>, dim3(L.nplanes * kPlaneSlices), dim3(256), 0, L.stream, L.boxes, L.nbox,
                        a.f.p[0], a.f.p[4], a.lnpart);
     hipLaunchKernelGGL(k_plane_lnmean<T>, dim3((L.nplanes + 255) / 256), dim3(256), 0, L.stream, L.boxes,
-                       L.nbox, L.nplanes, a.lnpart, a.lnavg);
+                       L.nbox, L.nplanes, a.lnpart, 1.0, a.lnavg);
+  }
+  const bool lnp = (a.ph.terms & T_PRES) && (a.ph.terms & T_LNP);
+  if (lnp) {   // ln P_aver, P = (gamma - 1) e
+    hipLaunchKernelGGL(k_plane_sum<T>, dim3(L.nplanes * kPlaneSlices), dim3(256), 0, L.stream, L.boxes, L.nbox,
+                       (const T*)nullptr, a.f.p[4], a.lnpart);
+    hipLaunchKernelGGL(k_plane_lnmean<T>, dim3((L.nplanes + 255) / 256), dim3(256), 0, L.stream, L.boxes,
+                       L.nbox, L.nplanes, a.lnpart, (double)a.ph.gamma1, a.w.lnpav);
   }
   L.at(PASS_EDGES);
   hipLaunchKernelGGL((zQ<T, TX, TY, PERS, QM_EDGES>), grid((const void*)zQ<T, TX, TY, PERS, QM_EDGES>), block, 0,
-                     L.stream, L.boxes, L.items, n, a.ztab, q ? q + 16 : q, a.f, a.ph, a.w, a.lnavg);
-  hipLaunchKernelGGL((zQ<T, TX, TY, PERS, QM_ZC>), grid((const void*)zQ<T, TX, TY, PERS, QM_ZC>), block, 0,
-                     L.stream, L.boxes, L.items, n, a.ztab, q ? q + 32 + 8 * kNFMasks : q, a.f, a.ph, a.w,
-                     a.lnavg);
+                     L.stream, L.boxes, L.items, n, a.ztab, q ? q + 16 : q, a.f, a.ph, a.w, a.lnavg,
+                     a.w.lnpav);
+  if (lnp)
+    hipLaunchKernelGGL((zQ<T, TX, TY, PERS, QM_ZC | QM_LNP>), grid((const void*)zQ<T, TX, TY, PERS, QM_ZC | QM_LNP>),
+                       block, 0, L.stream, L.boxes, L.items, n, a.ztab, q ? q + 32 + 8 * kNFMasks : q, a.f, a.ph,
+                       a.w, a.lnavg, a.w.lnpav);
+  else
+    hipLaunchKernelGGL((zQ<T, TX, TY, PERS, QM_ZC>), grid((const void*)zQ<T, TX, TY, PERS, QM_ZC>), block, 0,
+                       L.stream, L.boxes, L.items, n, a.ztab, q ? q + 32 + 8 * kNFMasks : q, a.f, a.ph, a.w,
+                       a.lnavg, a.w.lnpav);
   L.at(PASS_CF);
   hipLaunchKernelGGL((zP<T, TX, TY, PERS>), grid((const void*)zP<T, TX, TY, PERS>), block, 0, L.stream, L.boxes,
                      L.items, n, a.ztab, q ? q + 24 : q, a.f, a.ph, a.w);

@@ -42,6 +42,7 @@ enum WsArr : int { WS_NUS = 0, WS_D, WS_UZ, WS_LNT, WS_Q0, WS_P0 = WS_Q0 + QOUT_
 template <class T> struct ZWork {
   T* base;
   long long stride;
+  T* lnpav;               // ln P_aver per plane of every box (BoxDev::poff; eq. pressure)
   __host__ __device__ T* arr(int a) const { return base + (long long)a * stride; }
   __host__ __device__ T* q(int i) const { return arr(WS_Q0 + i); }
   __host__ __device__ T* pq(int i) const { return arr(WS_P0 + i); }

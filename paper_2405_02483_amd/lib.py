@@ -16,7 +16,7 @@ __all__ = [
     "MHD_ENONFINITE", "MHD_EUNSUPPORTED", "MHD_F32", "MHD_F64",
     "MHD_BC_PERIODIC", "MHD_BC_WALL", "T_CONT", "T_ADV", "T_PRES", "T_VISC",
     "T_LORENTZ", "T_INDUCT", "T_RESIST", "T_EDIFF", "T_GRAV", "T_ALL", "T_COOL", "T_CORI",
-    "T_EDIFFAV",
+    "T_EDIFFAV", "T_LNP",
     "MhdBox", "MhdParams", "MhdStats", "MhdError", "lib_path", "load",
     "mhd_init", "mhd_destroy", "mhd_last_error", "mhd_field_elems",
     "mhd_box_offset", "mhd_rhs", "mhd_step", "mhd_step_adjoint",
@@ -36,6 +36,7 @@ T_ALL = (1 << 9) - 1
 T_COOL = 1 << 9      # Newtonian cooling; not part of T_ALL
 T_CORI = 1 << 10     # Coriolis force; not part of T_ALL
 T_EDIFFAV = 1 << 11  # with T_EDIFF: diffusion about the horizontal mean; not part of T_ALL
+T_LNP = 1 << 12      # with T_PRES: grad P through ln(P / P_aver); not part of T_ALL
 
 
 class MhdBox(ctypes.Structure):
