@@ -5,7 +5,8 @@ tile for the final pass.  The fixed cases elsewhere use a handful of sizes;
 this one aims at indexing mistakes that only some (size, tile) pairs expose
 (partial tiles, chunk edges, planes next to a wall).  Each box also switches
 on a random subset of the optional terms (Newtonian cooling, the Coriolis
-force, energy diffusion about the horizontal mean).
+force, energy diffusion about the horizontal mean, the ln(P/P_aver) pressure
+gradient).
 
 Error measure: relative L2 per field, as in the other parity tests.  In a
 closed-wall box the atmosphere is hydrostatic, so the z momentum rate is the
@@ -55,7 +56,7 @@ def _errors(got, want, scale):
                          ids=["%s%dx%dx%d" % ("wall" if c[1] else "per", c[2], c[3], c[4])
                               for c in _cases()])
 def test_rhs_random_sizes_all_tiles(case, walls, nx, ny, nz, ftiles):
-    from paper_2405_02483_amd.lib import Context, TILES, T_ALL, T_COOL, T_CORI, T_EDIFFAV
+    from paper_2405_02483_amd.lib import Context, TILES, T_ALL, T_COOL, T_CORI, T_EDIFFAV, T_LNP
     if walls:
         f, box, prm = inputs.stratified(nx, ny, nz, seed=300 + case)
     else:
@@ -64,7 +65,7 @@ def test_rhs_random_sizes_all_tiles(case, walls, nx, ny, nz, ftiles):
         f = [np.ascontiguousarray(a[:nz, :ny, :nx]) for a in f]
         box = dict(box, nx=nx, ny=ny, nz=nz, Lx=nx / n, Ly=ny / n, Lz=nz / n)
     trng = random.Random(9000 + case)
-    extra = sum(bit for bit in (T_COOL, T_CORI, T_EDIFFAV) if trng.random() < 0.5)
+    extra = sum(bit for bit in (T_COOL, T_CORI, T_EDIFFAV, T_LNP) if trng.random() < 0.5)
     prm = dict(prm, terms=T_ALL | extra, e_cool=trng.uniform(0.5, 2.0), t_cool=trng.uniform(0.3, 2.0),
                rho_cool=trng.uniform(0.2, 2.0), cool_cut=trng.randrange(3),
                omega=tuple(trng.uniform(-1.5, 1.5) for _ in range(3)))
