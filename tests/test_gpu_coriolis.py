@@ -1,8 +1,8 @@
 """The Coriolis force (eq. mom) in the library, through the C ABI: the
 right-hand side, the RK step and the step adjoint against the float64
 oracle (periodic and closed-wall boxes, every tile shape for the RHS, with
-and without Newtonian cooling), and the rotation of a uniform state on the
-GPU without the oracle."""
+and without Newtonian cooling), a checkpointed rollout's gradient with both
+terms, and the rotation of a uniform state on the GPU without the oracle."""
 import numpy as np
 import pytest
 import torch
@@ -135,5 +135,27 @@ def test_step_adjoint_with_coriolis_f64(cool):
     got = ctx.box_view(ctx.step_adjoint(ctx.upload([f]), dt, ctx.upload([gbar])), 0)
     want = O.step_vjp(ft, g, p, dt, to_cpu64(gbar))
     errs = rel_errors(got, want)
+    assert max(errs) < 1e-10, errs
+    ctx.close()
+
+
+def test_rollout_with_coriolis_and_cooling_f64():
+    """A 3-step checkpointed rollout with both optional terms that have an
+    adjoint: its gradient against the oracle's discrete adjoint."""
+    from paper_2405_02483_amd.rollout import rollout
+    f, box, prm = _case("turb_ragged")
+    over = _over(cool=True)
+    g, p = grid_params(box, prm, **over)
+    ft = to_cpu64(f)
+    dt = 0.5 * O.courant(ft, g, p)[0]
+    rng = np.random.default_rng(51)
+    w = [rng.standard_normal(a.shape) for a in f]
+    ctx = _ctx(box, prm, torch.float64, **over)
+    x = [t.requires_grad_(True) for t in ctx.upload([f])]
+    y = rollout(ctx, x, dt, 3, ncheck=1)
+    wd = ctx.upload([w])
+    grads = torch.autograd.grad(sum((a * b).sum() for a, b in zip(y, wd)), x)
+    want = O.step_vjp(ft, g, p, dt, to_cpu64(w), nsteps=3)
+    errs = rel_errors(ctx.box_view([t.detach() for t in grads], 0), want)
     assert max(errs) < 1e-10, errs
     ctx.close()
