@@ -351,8 +351,8 @@ def main():
         print(json.dumps(cpu_table()), flush=True)
         return
     if a.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the hot path shards by z-slabs with halo exchange; see the design notes)",
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
+              "(the hot path would shard by z-slabs or blocks with halo exchange)",
               file=sys.stderr)
         sys.exit(2)
     import torch

@@ -51,7 +51,7 @@ enum {
     MHD_EHIP = -3,          /* a HIP runtime call failed                      */
     MHD_EDTYPE = -4,        /* unknown dtype                                  */
     MHD_ENONFINITE = -5,    /* non-finite or non-positive state detected      */
-    MHD_EUNSUPPORTED = -6   /* valid request this build does not implement    */
+    MHD_EUNSUPPORTED = -6   /* valid request the library does not implement   */
 };
 
 enum { MHD_F32 = 0, MHD_F64 = 1 };

@@ -9,8 +9,8 @@ State: a tuple of 8 float64 tensors ``[nzt, ny, nx]`` in the order
 unit volume (rho times the energy per unit mass of eq. ien) and ``p`` the
 momentum density.  ``nzt = nz + 2*ngz``; ``ngz = 0`` for a periodic z axis.
 
-Readings of the paper taken here (each is listed with its reason in the
-design notes of the repository):
+Readings of the paper taken here, where it is silent, ambiguous or
+garbled:
 
 * eq. mom, eq. itv: the viscous stress enters the momentum equation with the
   dissipative sign (+div tau with tau = +rho nu S), so that the viscous
