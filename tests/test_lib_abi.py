@@ -61,3 +61,12 @@ def test_struct_layouts_match_header(tmp_path):
     subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
     assert got == [c[2] for c in checks]
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    """No fallback: without the built library every call path raises."""
+    from paper_2405_02483_amd import lib
+    monkeypatch.setattr(lib, "_LIB", None)
+    monkeypatch.setenv("STAGGER_MHD_LIB", str(tmp_path / "absent.so"))
+    with pytest.raises(RuntimeError, match="not built"):
+        lib.load()
