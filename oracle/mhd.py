@@ -41,6 +41,12 @@ garbled:
   takes the printed form exp(ln P_aver)_f exp(ln(P/P_aver))_f
   [d ln(P/P_aver) + d ln P_aver]_f with the staggered interpolation and
   derivative to the face f (the x and y derivatives of P_aver vanish).
+* div B diffusion (the C_divb term of the induction equation): the printed
+  term adds a scalar to a vector rate; it is read as the gradient of div B,
+  C_divb min(dx, dy, dz)^2 / dt grad(div B), with div B at cell centres from
+  the up derivatives and its gradient on the faces from the down
+  derivatives.  It needs the step's dt, so only the RK step (or a right-hand
+  side given dt) includes it.
 * eq. mom, Coriolis force: -2 rho Omega x u = -2 Omega x p, with each
   momentum component carried to the face of the component it drives by the
   staggered interpolations (e.g. p_z at an x-face is xdn(zup(p_z))).
@@ -55,7 +61,7 @@ from .stagger import Ops, AX_X, AX_Y, AX_Z
 __all__ = [
     "T_CONT", "T_ADV", "T_PRES", "T_VISC", "T_LORENTZ", "T_INDUCT",
     "T_RESIST", "T_EDIFF", "T_GRAV", "T_ALL", "T_HD", "T_IDEAL", "T_COOL", "T_CORI",
-    "T_EDIFFAV", "T_LNP",
+    "T_EDIFFAV", "T_LNP", "T_DIVB",
     "ALPHA", "BETA", "Grid", "Params", "ghost_fill", "rhs", "rhs_nofill",
     "step", "rk3", "courant", "stats", "step_vjp", "rhs_vjp", "FIELDS",
     "interior_slices", "smoothed_viscosity", "newton_cooling", "coriolis",
@@ -80,6 +86,7 @@ T_COOL = 1 << 9      # Newtonian cooling (eq. NewtonCool); not part of T_ALL
 T_CORI = 1 << 10     # Coriolis force (eq. mom); not part of T_ALL
 T_EDIFFAV = 1 << 11  # with T_EDIFF: diffuse fluctuations about the plane mean (eq. ediffav)
 T_LNP = 1 << 12      # with T_PRES: grad P through ln(P / P_aver) (eq. pressure)
+T_DIVB = 1 << 13     # div B diffusion C_divb h^2 / dt grad(div B); needs the step's dt
 T_HD = T_CONT | T_ADV | T_PRES | T_VISC | T_EDIFF
 T_IDEAL = T_CONT | T_ADV | T_PRES | T_LORENTZ | T_INDUCT
 
@@ -151,6 +158,7 @@ class Params:
     rho_cool: float = 1.0     # eq. rhocool: cut-off density
     cool_cut: int = 0         # 0 none, 1 low-density cut-off, 2 high-density
     omega: tuple = (0.0, 0.0, 0.0)   # rotation vector of the Coriolis force
+    c_divb: float = 0.0       # coefficient of the div B diffusion (< 0.11)
 
 
 def interior_slices(grid):
@@ -256,7 +264,7 @@ def coriolis(px, py, pz, par, O):
     return cx, cy, cz
 
 
-def rhs_nofill(f, grid, par):
+def rhs_nofill(f, grid, par, dt=None):
     """Time derivatives of the 8 variables (eqs. mass, mom, ien, indu, ohm,
     itv, vdiss, RMnu, nuij, ediffuse), evaluated on every plane of the array
     and then zeroed where Section 10 requires (ghost planes, wall faces)."""
@@ -382,6 +390,13 @@ def rhs_nofill(f, grid, par):
     dbx = -(O.ddyup(ez) - O.ddzup(ey))
     dby = -(O.ddzup(ex) - O.ddxup(ez))
     dbz = -(O.ddxup(ey) - O.ddyup(ex))
+    if (T & T_DIVB) and dt:
+        # div B diffusion: C_divb h_min^2 / dt grad(div B)
+        divb = O.ddxup(bx) + O.ddyup(by) + O.ddzup(bz)
+        kd = par.c_divb * grid.hmin ** 2 / dt
+        dbx = dbx + kd * O.ddxdn(divb)
+        dby = dby + kd * O.ddydn(divb)
+        dbz = dbz + kd * O.ddzdn(divb)
 
     out = [drho, dpx, dpy, dpz, de, dbx, dby, dbz]
     if grid.wall:
@@ -471,9 +486,9 @@ def ghost_fill(f, grid):
             e_n, torch.stack(bx_p), torch.stack(by_p), torch.stack(bz_p))
 
 
-def rhs(f, grid, par):
+def rhs(f, grid, par, dt=None):
     """F(f): ghost zones filled first (wall grids), then rhs_nofill."""
-    return rhs_nofill(ghost_fill(f, grid), grid, par)
+    return rhs_nofill(ghost_fill(f, grid), grid, par, dt)
 
 
 def rk3(f, rhs_fn, dt, nsteps=1, fill_fn=None):
@@ -497,7 +512,7 @@ def rk3(f, rhs_fn, dt, nsteps=1, fill_fn=None):
 def step(f, grid, par, dt, nsteps=1):
     """nsteps RK3 steps of the MHD system; ghost zones are refilled before
     every evaluation of F and after the last stage."""
-    return rk3(f, lambda s: rhs_nofill(s, grid, par), dt, nsteps,
+    return rk3(f, lambda s: rhs_nofill(s, grid, par, dt), dt, nsteps,
                fill_fn=lambda s: ghost_fill(s, grid))
 
 
