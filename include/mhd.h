@@ -96,6 +96,12 @@ enum {
  * (ddadn(q) + ddadn(ln P_aver)).  Exact for an exponential atmosphere.  Not
  * part of MHD_T_ALL; the adjoint entry points return MHD_EUNSUPPORTED.   */
 #define MHD_T_LNP      (1u << 12)
+/* div B diffusion: c_divb min(dx, dy, dz)^2 / dt grad(div B) added to the
+ * rate of B, div B at cell centres from the up derivatives, its gradient on
+ * the faces from the down derivatives.  It needs the step's dt, so
+ * mhd_step includes it and mhd_rhs (no dt) leaves it out.  Not part of
+ * MHD_T_ALL; the adjoint entry points return MHD_EUNSUPPORTED.             */
+#define MHD_T_DIVB     (1u << 13)
 
 /* One box of the mesh (&grid namelist: mx, my, mz, sx, sy, sz). */
 typedef struct {
@@ -131,6 +137,7 @@ typedef struct {
                                density); 2: 1/(1+r^2) (at high); r = rho/rho_cool */
     int32_t reserved2;      /* must be 0                                       */
     double omega[3];        /* with MHD_T_CORI: rotation vector, finite        */
+    double c_divb;          /* with MHD_T_DIVB: >= 0 (stable below about 0.11) */
 } mhd_params;
 
 /* Conserved totals and diagnostics over the interior cells (float64).     */

@@ -92,7 +92,7 @@ static int prof_fold(mhd_ctx* c) {
 }
 
 static std::string g_init_err;
-static constexpr int kWorkArrays = WS_COUNT;   // 33 arrays
+static constexpr int kWorkArrays = WS_COUNT;   // 34 arrays
 
 static int fail(mhd_ctx* c, int code, const std::string& msg) {
   if (c) c->err = msg; else g_init_err = msg;
@@ -125,6 +125,7 @@ template <class T> static Phys<T> make_phys(const mhd_params& p) {
   ph.cool_cut = cool ? p.cool_cut : 0;
   const bool cori = p.terms & MHD_T_CORI;
   for (int a = 0; a < 3; ++a) ph.cor2[a] = cori ? T(2.0 * p.omega[a]) : T(0);
+  ph.c_divb = (p.terms & MHD_T_DIVB) ? T(p.c_divb) : T(0);
   ph.terms = p.terms;
   return ph;
 }
@@ -382,8 +383,10 @@ int mhd_init(const mhd_params* p, void* hip_stream, mhd_ctx** out) {
   for (double v : nn)
     if (!(v >= 0.0) || !std::isfinite(v)) return fail(nullptr, MHD_EINVAL, "viscosity, diffusion and Courant coefficients must be finite and >= 0");
   if (!std::isfinite(p->gz) || !std::isfinite(p->c1)) return fail(nullptr, MHD_EINVAL, "gz and c1 must be finite");
-  if (p->terms & ~(MHD_T_ALL | MHD_T_COOL | MHD_T_CORI | MHD_T_EDIFFAV | MHD_T_LNP))
+  if (p->terms & ~(MHD_T_ALL | MHD_T_COOL | MHD_T_CORI | MHD_T_EDIFFAV | MHD_T_LNP | MHD_T_DIVB))
     return fail(nullptr, MHD_EINVAL, "unknown term bits");
+  if ((p->terms & MHD_T_DIVB) && !(p->c_divb >= 0.0 && std::isfinite(p->c_divb)))
+    return fail(nullptr, MHD_EINVAL, "c_divb must be finite and >= 0");
   if ((p->terms & MHD_T_CORI) &&
       !(std::isfinite(p->omega[0]) && std::isfinite(p->omega[1]) && std::isfinite(p->omega[2])))
     return fail(nullptr, MHD_EINVAL, "the rotation vector must be finite");
@@ -851,8 +854,8 @@ int mhd_step_adjoint(mhd_ctx* c, void* const f_n[8], double dt, void* const gin[
     return rc;
   for (const auto& b : c->boxes)
     if (b.bc_z != MHD_BC_PERIODIC) return fail(c, MHD_EUNSUPPORTED, "adjoint supports periodic boxes only");
-  if (c->p.terms & (MHD_T_EDIFFAV | MHD_T_LNP))
-    return fail(c, MHD_EUNSUPPORTED, "adjoint without MHD_T_EDIFFAV and MHD_T_LNP only");
+  if (c->p.terms & (MHD_T_EDIFFAV | MHD_T_LNP | MHD_T_DIVB))
+    return fail(c, MHD_EUNSUPPORTED, "adjoint without MHD_T_EDIFFAV, MHD_T_LNP and MHD_T_DIVB only");
   if (!std::isfinite(dt)) return fail(c, MHD_EINVAL, "dt not finite");
   for (int a = 0; a < 8; ++a)
     for (int b = 0; b < 8; ++b)
@@ -868,8 +871,8 @@ int mhd_rhs_adjoint(mhd_ctx* c, void* const f[8], void* const wbar[8], void* con
     return rc;
   for (const auto& b : c->boxes)
     if (b.bc_z != MHD_BC_PERIODIC) return fail(c, MHD_EUNSUPPORTED, "adjoint supports periodic boxes only");
-  if (c->p.terms & (MHD_T_EDIFFAV | MHD_T_LNP))
-    return fail(c, MHD_EUNSUPPORTED, "adjoint without MHD_T_EDIFFAV and MHD_T_LNP only");
+  if (c->p.terms & (MHD_T_EDIFFAV | MHD_T_LNP | MHD_T_DIVB))
+    return fail(c, MHD_EUNSUPPORTED, "adjoint without MHD_T_EDIFFAV, MHD_T_LNP and MHD_T_DIVB only");
   for (int a = 0; a < 8; ++a)
     for (int b = 0; b < 8; ++b)
       if (fbar[b] == f[a] || fbar[b] == wbar[a]) return fail(c, MHD_EINVAL, "fbar overlaps an input");

@@ -12,6 +12,7 @@ template <class T> struct Phys {
   T e_cool, inv_tcool, inv_rho_cool;   // Newtonian cooling (with T_COOL)
   int cool_cut;
   T cor2[3];                            // 2 Omega (Coriolis force, with T_CORI)
+  T c_divb;                             // div B diffusion coefficient (with T_DIVB)
   unsigned terms;
 };
 

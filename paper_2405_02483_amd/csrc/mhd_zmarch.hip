@@ -78,6 +78,8 @@ __global__ __launch_bounds__(TX * TY) void zA1(const BoxDev* __restrict__ boxes,
                                                CPart* __restrict__ cpart) {
   T* __restrict__ nus_out = ws.arr(WS_NUS);
   T* __restrict__ D_out = ws.arr(WS_D);
+  T* __restrict__ divb_out = ws.arr(WS_DIVB);
+  const bool divb = ph.terms & T_DIVB;
   T* __restrict__ uz_out = ws.arr(WS_UZ);
   using PR = Plane<TX, TY, 5>;
   using PP = Plane<TX, TY, 3>;
@@ -94,11 +96,11 @@ __global__ __launch_bounds__(TX * TY) void zA1(const BoxDev* __restrict__ boxes,
   i5.init(b, it.x0, it.y0);
   i3.init(b, it.x0, it.y0);
   T wR[6] = {}, wUZ[6] = {}, wBZ[8] = {}, fPZ[3] = {}, fE[6] = {};
-  T fUBX[6] = {}, fUBY[6] = {}, fBBX[6] = {}, fBBY[6] = {}, fDXY[6] = {};
+  T fUBX[6] = {}, fUBY[6] = {}, fBBX[6] = {}, fBBY[6] = {}, fDXY[6] = {}, fDXB[6] = {};
   double cmax = 0.0;
   for (int r = it.z0 - 5; r <= it.z1 + 4; ++r) {
     T rr = T(0), pz = T(0), e = T(0), bz = T(0);
-    T ubx = T(0), uby = T(0), bbx = T(0), bby = T(0), dxy = T(0);
+    T ubx = T(0), uby = T(0), bbx = T(0), bby = T(0), dxy = T(0), dxb = T(0);
     if (valid(r)) {
       const int k = kk(r);
       __syncthreads();
@@ -130,6 +132,10 @@ __global__ __launch_bounds__(TX * TY) void zA1(const BoxDev* __restrict__ boxes,
             op6<1, 1, T>([&](int m) { return sUY[PP::at(tx, ty + m)]; }, g.hyi);
       bbx = op6<0, 1, T>([&](int m) { return sBX[PP::at(tx + m, ty)]; }, T(0));
       bby = op6<0, 1, T>([&](int m) { return sBY[PP::at(tx, ty + m)]; }, T(0));
+      // x and y parts of div B at the centre (the div B diffusion)
+      if (divb)
+        dxb = op6<1, 1, T>([&](int m) { return sBX[PP::at(tx + m, ty)]; }, g.hxi) +
+              op6<1, 1, T>([&](int m) { return sBY[PP::at(tx, ty + m)]; }, g.hyi);
     }
     push(wR, rr);
     push(fPZ, pz);
@@ -140,6 +146,7 @@ __global__ __launch_bounds__(TX * TY) void zA1(const BoxDev* __restrict__ boxes,
     push(fBBX, bbx);
     push(fBBY, bby);
     push(fDXY, dxy);
+    push(fDXB, dxb);
     // u_z on the face of plane q1 = r - 2 (wR slot 3 holds plane q1)
     const int q1 = r - 2;
     T uzq = T(0);
@@ -172,6 +179,7 @@ __global__ __launch_bounds__(TX * TY) void zA1(const BoxDev* __restrict__ boxes,
         const long long o = col(q);
         nus_out[o] = nus;
         D_out[o] = D;
+        if (divb) divb_out[o] = fDXB[0] + zwin<1, 1, 8, 2>(wBZ, q, wall, N, g.hzi, zt);
         if (cpart && interior(q)) {
           const double ux_ = fUBX[0], uy_ = fUBY[0], uz_ = ubz;
           const double bx_ = fBBX[0], by_ = fBBY[0], bz_ = bbz, bbd = bb;
@@ -754,6 +762,9 @@ __global__ __launch_bounds__(TX * TY) void zF(const BoxDev* __restrict__ boxes,
   // come with pass P's face terms): x strips of px and pz, y strips of py
   // and pz
   constexpr bool kCori = hasf<FM>(8);
+  // div B diffusion (B launch): x and y strips of div B
+  constexpr bool kDB = hasf<FM>(5);
+  __shared__ T sdb[kDB ? PXs::NP + PYs::NP : 1];
   __shared__ T sxc[kCori ? 2 * PXs::NP : 1];
   __shared__ T syc[kCori ? 2 * PYs::NP : 1];
   ZLOOP_BEGIN
@@ -768,6 +779,8 @@ __global__ __launch_bounds__(TX * TY) void zF(const BoxDev* __restrict__ boxes,
   const T inv_mu = ph.inv_mu;
   const double dt = dt_dev ? *dt_dev : dt_host;
   const T bdt = T(beta * dt);
+  // div B diffusion C_divb h^2 / dt grad(div B); absent without a time step
+  const T kd = (kDB && dt > 0.0) ? T(double(ph.c_divb) * double(g.h) * double(g.h) / dt) : T(0);
   auto X = [&](int q, int x) -> T { return sx[strip_slot<FM>(kXOwn, q) * PXs::NP + PXs::at(x, ty)]; };
   auto Y = [&](int q, int y) -> T { return sy[strip_slot<FM>(kYOwn, q) * PYs::NP + PYs::at(tx, y)]; };
   auto F2 = [&](int q, int x, int y) -> T { return s2[(q && kQz) * P3::NP + P3::at(x, y)]; };
@@ -850,6 +863,10 @@ __global__ __launch_bounds__(TX * TY) void zF(const BoxDev* __restrict__ boxes,
         load_plane(sx + strip_slot<FM>(kXOwn, 8) * PXs::NP, ws.q(QOUT_QY), b, ix, k);
         load_plane(sy + strip_slot<FM>(kYOwn, 8) * PYs::NP, ws.q(QOUT_QX), b, iy, k);
       }
+      if (kDB && kd != T(0)) {
+        load_plane(sdb, ws.arr(WS_DIVB), b, ix, k);
+        load_plane(sdb + PXs::NP, ws.arr(WS_DIVB), b, iy, k);
+      }
       if constexpr (kCori) {
         load_plane(sxc, f.p[1], b, ix, k);
         load_plane(sxc + PXs::NP, f.p[3], b, ix, k);
@@ -904,10 +921,22 @@ __global__ __launch_bounds__(TX * TY) void zF(const BoxDev* __restrict__ boxes,
         }
         if (hasf<FM>(5)) acc[5][3] += -op6<1, 1, T>([&](int m) { return F2(1, x, y + m); }, g.hyi);
         if (hasf<FM>(6)) acc[6][3] += op6<1, 1, T>([&](int m) { return F2(1, x + m, y); }, g.hxi);
+        if (kDB && kd != T(0)) {
+          acc[5][3] += kd * op6<1, 0, T>([&](int m) { return sdb[PXs::at(x + m, ty)]; }, g.hxi);
+          acc[6][3] += kd * op6<1, 0, T>([&](int m) { return sdb[PXs::NP + PYs::at(tx, y + m)]; }, g.hyi);
+        }
         // Bz has no z divergence: complete at once
         if (hasf<FM>(7) && own) {
-          const T fbz = -(op6<1, 1, T>([&](int m) { return X(7, x + m); }, g.hxi) -
-                          op6<1, 1, T>([&](int m) { return Y(7, y + m); }, g.hyi));
+          T fbz = -(op6<1, 1, T>([&](int m) { return X(7, x + m); }, g.hxi) -
+                    op6<1, 1, T>([&](int m) { return Y(7, y + m); }, g.hyi));
+          if (kd != T(0)) {
+            // z part of grad(div B) on this z-face, from the own column
+            const T* __restrict__ dbg = ws.arr(WS_DIVB);
+            T w[6];
+#pragma unroll
+            for (int m = 0; m < 6; ++m) w[m] = valid(r - 3 + m) ? dbg[col(r - 3 + m)] : T(0);
+            fbz += kd * zwin<1, 0, 6, 3>(w, r, wall, N, g.hzi, zt);
+          }
           const T F7 = masked(7, r, fbz);
           if (f_out.p[0] == nullptr) du.p[7][o] = F7;
           else update(7, o, F7, bz_u, bz_f);

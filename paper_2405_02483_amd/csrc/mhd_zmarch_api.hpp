@@ -37,7 +37,7 @@ inline int ztile_y(int t) { return t == ZTILE_64x4 ? 4 : (t == ZTILE_16x16 ? 16 
 // kernel needs one base pointer for all of them (array pointers held in
 // scalar registers would otherwise spill).
 enum WsArr : int { WS_NUS = 0, WS_D, WS_UZ, WS_LNT, WS_Q0, WS_P0 = WS_Q0 + QOUT_COUNT,
-                   WS_COUNT = WS_P0 + POUT_COUNT };
+                   WS_DIVB = WS_P0 + POUT_COUNT, WS_COUNT };
 
 template <class T> struct ZWork {
   T* base;

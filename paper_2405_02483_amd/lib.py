@@ -16,7 +16,7 @@ __all__ = [
     "MHD_ENONFINITE", "MHD_EUNSUPPORTED", "MHD_F32", "MHD_F64",
     "MHD_BC_PERIODIC", "MHD_BC_WALL", "T_CONT", "T_ADV", "T_PRES", "T_VISC",
     "T_LORENTZ", "T_INDUCT", "T_RESIST", "T_EDIFF", "T_GRAV", "T_ALL", "T_COOL", "T_CORI",
-    "T_EDIFFAV", "T_LNP",
+    "T_EDIFFAV", "T_LNP", "T_DIVB",
     "MhdBox", "MhdParams", "MhdStats", "MhdError", "lib_path", "load",
     "mhd_init", "mhd_destroy", "mhd_last_error", "mhd_field_elems",
     "mhd_box_offset", "mhd_rhs", "mhd_step", "mhd_step_adjoint",
@@ -37,6 +37,7 @@ T_COOL = 1 << 9      # Newtonian cooling; not part of T_ALL
 T_CORI = 1 << 10     # Coriolis force; not part of T_ALL
 T_EDIFFAV = 1 << 11  # with T_EDIFF: diffusion about the horizontal mean; not part of T_ALL
 T_LNP = 1 << 12      # with T_PRES: grad P through ln(P / P_aver); not part of T_ALL
+T_DIVB = 1 << 13     # div B diffusion (needs the step's dt); not part of T_ALL
 
 
 class MhdBox(ctypes.Structure):
@@ -56,7 +57,8 @@ class MhdParams(ctypes.Structure):
                 ("terms", ctypes.c_uint32), ("reserved", ctypes.c_int32),
                 ("e_cool", ctypes.c_double), ("t_cool", ctypes.c_double),
                 ("rho_cool", ctypes.c_double), ("cool_cut", ctypes.c_int32),
-                ("reserved2", ctypes.c_int32), ("omega", ctypes.c_double * 3)]
+                ("reserved2", ctypes.c_int32), ("omega", ctypes.c_double * 3),
+                ("c_divb", ctypes.c_double)]
 
 
 class MhdStats(ctypes.Structure):
@@ -293,7 +295,8 @@ class Context:
     wall (bool), Lx, Ly, Lz; ``params``: dict of physical parameters (the
     fields of mhd_params by name, ``terms`` for the term bits, and e_cool,
     t_cool, rho_cool, cool_cut for Newtonian cooling with T_COOL, omega
-    (3 values) for the Coriolis force with T_CORI)."""
+    (3 values) for the Coriolis force with T_CORI, c_divb for the div B
+    diffusion with T_DIVB)."""
 
     def __init__(self, boxes, params, dtype=torch.float32, terms=T_ALL, stream=None,
                  device="cuda"):
@@ -331,6 +334,7 @@ class Context:
         p.reserved2 = 0
         for a, w in enumerate(params.get("omega", (0.0, 0.0, 0.0))):
             p.omega[a] = float(w)
+        p.c_divb = float(params.get("c_divb", 0.0))
         self.params = p
         self.ctx = mhd_init(p, stream)
         self.n = mhd_field_elems(self.ctx)

@@ -38,7 +38,8 @@ def _params(**over):
     (dict(mu=0.0), lib.MHD_EINVAL),
     (dict(nu1=-0.1), lib.MHD_EINVAL),
     (dict(Cdt=float("nan")), lib.MHD_EINVAL),
-    (dict(terms=1 << 13), lib.MHD_EINVAL),
+    (dict(terms=1 << 14), lib.MHD_EINVAL),
+    (dict(terms=lib.T_ALL | lib.T_DIVB, c_divb=-0.1), lib.MHD_EINVAL),
     (dict(reserved2=1), lib.MHD_EINVAL),
     (dict(terms=lib.T_ALL | lib.T_COOL, t_cool=0.0), lib.MHD_EINVAL),
     (dict(terms=lib.T_ALL | lib.T_COOL, t_cool=1.0, e_cool=float("nan")), lib.MHD_EINVAL),
