@@ -14,9 +14,9 @@ ms_per_step, the float64 figures of the same workload, the roofline of the
 RK stage (algorithmic bytes per stage / measured stage time, HIP events on
 the library's stream; beside the 8 TB/s peak, the bandwidth of a plain 1 GiB
 device copy measured in the same run), the same float32 workload with
-Newtonian cooling, with the Coriolis force, with energy diffusion about the
-horizontal mean and with the ln(P/P_aver) pressure gradient on, and the CPU
-oracle timed on a bounded sample.
+each optional term on (Newtonian cooling, the Coriolis force, energy
+diffusion about the horizontal mean, the ln(P/P_aver) pressure gradient, div
+B diffusion), and the CPU oracle timed on a bounded sample.
 
     python bench.py [--steps K] [--warmup W] [--size N] [--no-fp64]
                     [--no-cpu-baseline] [--no-adjoint] [--no-sources] [--tile TXxTY]
@@ -343,7 +343,8 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint and ensemble legs")
     ap.add_argument("--no-sources", action="store_true",
                     help="skip the legs with the optional terms (cooling, Coriolis, energy "
-                         "diffusion about the plane mean, ln(P/P_aver) pressure gradient)")
+                         "diffusion about the plane mean, ln(P/P_aver) pressure gradient, "
+                         "div B diffusion)")
     ap.add_argument("--cpu-table", action="store_true",
                     help="only time the CPU oracle at 32^3..256^3 (1 and all threads); no GPU")
     a = ap.parse_args()
@@ -363,10 +364,11 @@ def main():
     rsrc = {}
     if not a.no_sources and a.workload == "stratified":
         # the same workload and launch with one more source term switched on
-        from paper_2405_02483_amd.lib import T_ALL, T_COOL, T_CORI, T_EDIFFAV, T_LNP
+        from paper_2405_02483_amd.lib import T_ALL, T_COOL, T_CORI, T_EDIFFAV, T_LNP, T_DIVB
         L = r32["launch"]
         for name, bit, over in (("cooling", T_COOL, COOLING), ("coriolis", T_CORI, CORIOLIS),
-                                ("ediffav", T_EDIFFAV, {}), ("lnp", T_LNP, {})):
+                                ("ediffav", T_EDIFFAV, {}), ("lnp", T_LNP, {}),
+                                ("divb", T_DIVB, dict(c_divb=0.05))):
             rsrc[name] = run_gpu(a.size, torch.float32, max(2, a.steps // 5), 1, a.workload,
                                  over=dict(over, terms=T_ALL | bit),
                                  launch=(L["tile"], L["persistent"], L["final_pass_tile"]))
@@ -426,7 +428,8 @@ def main():
                    % (COOLING["e_cool"], COOLING["t_cool"], COOLING["rho_cool"]),
         "coriolis": "the Coriolis force (eq. mom), Omega = (%.3f, %.3f, %.3f)" % CORIOLIS["omega"],
         "ediffav": "energy diffusion about the horizontal mean (eq. ediffav)",
-        "lnp": "the pressure gradient through ln(P/P_aver) (eq. pressure)"}
+        "lnp": "the pressure gradient through ln(P/P_aver) (eq. pressure)",
+        "divb": "div B diffusion, c_divb 0.05"}
     for name, r in rsrc.items():
         out[name] = {
             "workload": "%s_%d with %s" % (a.workload, a.size, what[name]),
