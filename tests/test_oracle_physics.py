@@ -473,3 +473,30 @@ def test_adjoint_matches_central_differences(kind):
         fd = _dot(gbar, [(a - b) / (2 * eps) for a, b in zip(fp, fm)])
         ad = _dot(adj, v)
         assert abs(fd - ad) < 1e-6 * abs(fd), (fd, ad)
+
+
+@pytest.mark.parametrize("extra", ["cool_cori", "divb", "ediffav_lnp"])
+def test_adjoint_with_optional_terms_matches_central_differences(extra):
+    """The same check with the optional terms on, so the reference adjoint
+    the library's is compared with is itself checked for them."""
+    from dataclasses import replace
+    f, g, p = turb(8, seed=22)
+    if extra == "cool_cori":
+        p = replace(p, terms=O.T_ALL | O.T_COOL | O.T_CORI, e_cool=0.8, t_cool=0.5,
+                    rho_cool=1.2, cool_cut=1, omega=(0.4, -0.7, 1.1))
+    elif extra == "divb":
+        p = replace(p, terms=O.T_ALL | O.T_DIVB, c_divb=0.05)
+    else:
+        p = replace(p, terms=O.T_ALL | O.T_EDIFFAV | O.T_LNP)
+    dt = 0.5 * O.courant(f, g, p)[0]
+    gen = torch.Generator().manual_seed(6)
+    gbar = tuple(torch.randn(a.shape, generator=gen, dtype=D) for a in f)
+    adj = O.step_vjp(f, g, p, dt, gbar, nsteps=1)
+    for _ in range(2):
+        v = tuple(torch.randn(a.shape, generator=gen, dtype=D) * a.abs().mean() for a in f)
+        eps = 1e-7
+        fp = O.step(tuple(a + eps * b for a, b in zip(f, v)), g, p, dt, 1)
+        fm = O.step(tuple(a - eps * b for a, b in zip(f, v)), g, p, dt, 1)
+        fd = _dot(gbar, [(a - b) / (2 * eps) for a, b in zip(fp, fm)])
+        ad = _dot(adj, v)
+        assert abs(fd - ad) < 1e-6 * abs(fd), (extra, fd, ad)
