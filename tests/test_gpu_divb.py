@@ -144,3 +144,19 @@ def test_adjoint_refuses_divb():
         ctx.step_adjoint(fd, 1e-3, ctx.zeros())
     assert ei.value.code == MHD_EUNSUPPORTED
     ctx.close()
+
+
+def test_step_with_device_courant_dt_f64():
+    """dt = 0: the library takes the Courant dt on the device, and the div B
+    coefficient uses that dt (read back with last_dt for the oracle)."""
+    f, box, prm = _strat(12, 10, 24, 3)
+    over = _over()
+    ctx = _ctx(box, prm, torch.float64, **over)
+    fd = ctx.upload([f])
+    ctx.step(fd, 0.0, 1)
+    dt = ctx.last_dt()
+    g, p = grid_params(box, prm, **over)
+    want = O.step(to_cpu64(f), g, p, dt, 1)
+    errs = rel_errors(interior(ctx.box_view(fd, 0), box), interior(want, box))
+    assert max(errs) < TOL64, errs
+    ctx.close()
