@@ -23,6 +23,9 @@ garbled:
   compression); the viscosity is spread by a maximum over three cells and
   smoothed by a three-cell mean along x, then y, then z.
 * eq. nuij: off-diagonal (edge) viscosities average ln(nu) and exponentiate.
+* Constant viscosity (Section 6.1, nu_ij = const): every component nu_ij is
+  nu_const on any cell shape; the smoothed speed-like viscosity is then
+  nu_const / h_min, which sets the diffusive Courant limit.
 * eq. ediffuse: the diffusive energy flux is nuE * rho * nu_ii * e_m *
   d(ln e_m)/dx_i with nu_ii = dx_i <nu>; the paper's extra factor dx_i would
   give the flux the wrong dimension and is dropped.
@@ -65,7 +68,8 @@ __all__ = [
     "ALPHA", "BETA", "Grid", "Params", "ghost_fill", "rhs", "rhs_nofill",
     "step", "rk3", "courant", "stats", "step_vjp", "rhs_vjp", "FIELDS",
     "interior_slices", "smoothed_viscosity", "newton_cooling", "coriolis",
-    "horizontal_ln_mean", "pressure_gradient_ln",
+    "horizontal_ln_mean", "pressure_gradient_ln", "viscosity_lengths",
+    "edge_viscosity",
 ]
 
 FIELDS = ("rho", "px", "py", "pz", "e", "bx", "by", "bz")
@@ -144,7 +148,7 @@ class Params:
     nu1: float = 0.02         # c_v   (eq. RMnu)
     nu2: float = 1.0          # c_sh
     nu3: float = 0.02         # c_w
-    nu_const: float = 0.0     # >0: constant viscosity nu_ii = nu_const
+    nu_const: float = 0.0     # >0: constant viscosity nu_ij = nu_const
     c1: float = 0.0           # eq. itv
     nuE: float = 1.0          # eq. ediffuse
     nuB: float = 1.0          # eta = nuB * edge viscosity
@@ -213,6 +217,33 @@ def smoothed_viscosity(f, grid, par, O=None):
     return nt, pieces
 
 
+def viscosity_lengths(grid, par):
+    """Length factors of eq. nuij: ((lx, ly, lz), (lxy, lxz, lyz)) with
+    nu_ii = l_i <nu> and nu_ij = l_ij <nu>.  Richtmyer-Morton viscosity:
+    l_i = dx_i and l_ij = max(dx_i, dx_j).  Constant viscosity (Section 6.1:
+    nu_ij = const for every component): <nu> = nu_const / h_min everywhere and
+    every factor is h_min, so each nu_ij is nu_const on any cell shape."""
+    if par.nu_const > 0:
+        h = grid.hmin
+        return (h, h, h), (h, h, h)
+    dx, dy, dz = grid.dx, grid.dy, grid.dz
+    return (dx, dy, dz), (max(dx, dy), max(dx, dz), max(dy, dz))
+
+
+def edge_viscosity(nt, grid, par, O=None):
+    """Off-diagonal viscosities of eq. nuij on the cell edges (nxy on z-edges,
+    nxz on y-edges, nyz on x-edges): the length factor times the exponential
+    of the two-axis interpolation of ln <nu> (the paper averages ln nu for
+    the off-diagonal components)."""
+    O = O or grid.ops()
+    _, (lxy, lxz, lyz) = viscosity_lengths(grid, par)
+    lnt = torch.log(nt)
+    nxy = lxy * torch.exp(O.ydn(O.xdn(lnt)))
+    nxz = lxz * torch.exp(O.zdn(O.xdn(lnt)))
+    nyz = lyz * torch.exp(O.zdn(O.ydn(lnt)))
+    return nxy, nxz, nyz
+
+
 def newton_cooling(rho, e, par):
     """Newtonian heating/cooling at cell centres (eq. NewtonCool), as a rate
     of the energy per volume: the energy per unit mass e_m = e / rho relaxes
@@ -271,7 +302,6 @@ def rhs_nofill(f, grid, par, dt=None):
     O = grid.ops()
     T = par.terms
     rho, px, py, pz, e, bx, by, bz = f
-    dx, dy, dz = grid.dx, grid.dy, grid.dz
     mu = par.mu
     zero = torch.zeros_like(rho)
 
@@ -279,12 +309,10 @@ def rhs_nofill(f, grid, par, dt=None):
     nt, pc = smoothed_viscosity(f, grid, par, O)
     P, ux, uy, uz, D = pc["P"], pc["ux"], pc["uy"], pc["uz"], pc["D"]
     em = e / rho                          # energy per unit mass
-    lnt = torch.log(nt)
+    (lx, ly, lz), _ = viscosity_lengths(grid, par)
 
     # -- viscosities and densities on edges (eq. nuij) -----------------------
-    nxy = max(dx, dy) * torch.exp(O.ydn(O.xdn(lnt)))    # z-edge
-    nxz = max(dx, dz) * torch.exp(O.zdn(O.xdn(lnt)))    # y-edge
-    nyz = max(dy, dz) * torch.exp(O.zdn(O.ydn(lnt)))    # x-edge
+    nxy, nxz, nyz = edge_viscosity(nt, grid, par, O)    # z-, y-, x-edges
     rxy = O.ydn(O.xdn(rho))
     rxz = O.zdn(O.xdn(rho))
     ryz = O.zdn(O.ydn(rho))
@@ -294,9 +322,9 @@ def rhs_nofill(f, grid, par, dt=None):
     sxy = 0.5 * (O.ddydn(ux) + O.ddxdn(uy))
     sxz = 0.5 * (O.ddzdn(ux) + O.ddxdn(uz))
     syz = 0.5 * (O.ddzdn(uy) + O.ddydn(uz))
-    txx = rho * (dx * nt) * (sxx + par.c1 * D)
-    tyy = rho * (dy * nt) * (syy + par.c1 * D)
-    tzz = rho * (dz * nt) * (szz + par.c1 * D)
+    txx = rho * (lx * nt) * (sxx + par.c1 * D)
+    tyy = rho * (ly * nt) * (syy + par.c1 * D)
+    tzz = rho * (lz * nt) * (szz + par.c1 * D)
     txy = rxy * nxy * sxy
     txz = rxz * nxz * sxz
     tyz = ryz * nyz * syz
@@ -376,12 +404,12 @@ def rhs_nofill(f, grid, par, dt=None):
         de = de + qj
     if T & T_EDIFF:
         lne = torch.log(em)
-        fx = par.nuE * O.xdn(rho) * (dx * O.xdn(nt)) * O.xdn(em) * O.ddxdn(lne)
-        fy = par.nuE * O.ydn(rho) * (dy * O.ydn(nt)) * O.ydn(em) * O.ddydn(lne)
+        fx = par.nuE * O.xdn(rho) * (lx * O.xdn(nt)) * O.xdn(em) * O.ddxdn(lne)
+        fy = par.nuE * O.ydn(rho) * (ly * O.ydn(nt)) * O.ydn(em) * O.ddydn(lne)
         lnez = lne
         if T & T_EDIFFAV:
             lnez = lne - horizontal_ln_mean(em)
-        fz = par.nuE * O.zdn(rho) * (dz * O.zdn(nt)) * O.zdn(em) * O.ddzdn(lnez)
+        fz = par.nuE * O.zdn(rho) * (lz * O.zdn(nt)) * O.zdn(em) * O.ddzdn(lnez)
         de = de + O.ddxup(fx) + O.ddyup(fy) + O.ddzup(fz)
     if T & T_COOL:
         de = de + newton_cooling(rho, e, par)

@@ -176,7 +176,7 @@ def test_energy_diffusion_rate():
 
 
 def test_advection_is_non_dissipative():
-    """Continuity alone with uniform velocity u0 (Section 11.1): a density
+    """Continuity alone with uniform velocity u0 (Section 12.1): a density
     mode moves with the purely imaginary symbol -i u0 K I (no damping,
     dispersive): drho/dt = -u0 eps K I cos(k x_c)."""
     n, m = 32, 7
