@@ -121,7 +121,8 @@ typedef struct {
     double mu;              /* permeability; J = curl B / mu (eq. mom)         */
     double gz;              /* gravity along -z (with MHD_T_GRAV)              */
     double nu1, nu2, nu3;   /* eq. RMnu: c_v, c_sh, c_w                        */
-    double nu_const;        /* > 0: constant viscosity nu_ii = nu_const        */
+    double nu_const;        /* > 0: constant viscosity, nu_ij = nu_const for
+                               every component on any cell shape (Section 6.1) */
     double c1;              /* eq. itv                                         */
     double nuE;             /* eq. ediffuse: c_E                               */
     double nuB;             /* magnetic diffusivity = nuB * edge viscosity     */
@@ -137,7 +138,9 @@ typedef struct {
                                density); 2: 1/(1+r^2) (at high); r = rho/rho_cool */
     int32_t reserved2;      /* must be 0                                       */
     double omega[3];        /* with MHD_T_CORI: rotation vector, finite        */
-    double c_divb;          /* with MHD_T_DIVB: >= 0 (stable below about 0.11) */
+    double c_divb;          /* with MHD_T_DIVB: >= 0 and at most the RK3 limit
+                               2.5127 / (K^2 h_min^2 sum_a 1/h_a^2), K = 2.48333
+                               (0.1358 on cubic cells); MHD_EINVAL above it    */
 } mhd_params;
 
 /* Conserved totals and diagnostics over the interior cells (float64).     */
@@ -210,8 +213,10 @@ int mhd_step(mhd_ctx* ctx, void* const f[8], void* const tmp1[8],
  * Non-smooth points use: max over three cells routes to the first maximal
  * cell (order i-1, i, i+1; passes along x, then y, then z); max(0, x), |v|
  * and the viscosity floor have zero derivative on their flat side.
- * Periodic boxes only (MHD_EUNSUPPORTED with walls).  f_n is not modified;
- * gbar_in and gbar_out must not overlap.                                   */
+ * Periodic boxes only (MHD_EUNSUPPORTED with walls).  dt must be finite and
+ * > 0 (MHD_EINVAL otherwise: the Courant step of mhd_step's dt == 0 is not
+ * differentiated).  f_n is not modified; gbar_in and gbar_out must not
+ * overlap.                                                                 */
 int mhd_step_adjoint(mhd_ctx* ctx, void* const f_n[8], double dt,
                      void* const gbar_in[8], void* const gbar_out[8]);
 

@@ -160,18 +160,18 @@ VProgram build_rhs_program(const mhd_params& p) {
   const int lnt = B.flog(nt);
 
   // edge viscosities and densities (eq. nuij)
-  const int nxy = B.scale(B.fexp(B.ydn(B.xdn(lnt))), 1.0, G_MXY);
-  const int nxz = B.scale(B.fexp(B.zdn(B.xdn(lnt))), 1.0, G_MXZ);
-  const int nyz = B.scale(B.fexp(B.zdn(B.ydn(lnt))), 1.0, G_MYZ);
+  const int nxy = B.scale(B.fexp(B.ydn(B.xdn(lnt))), 1.0, G_LXY);
+  const int nxz = B.scale(B.fexp(B.zdn(B.xdn(lnt))), 1.0, G_LXZ);
+  const int nyz = B.scale(B.fexp(B.zdn(B.ydn(lnt))), 1.0, G_LYZ);
   const int rxy = B.ydn(B.xdn(rho)), rxz = B.zdn(B.xdn(rho)), ryz = B.zdn(B.ydn(rho));
 
   // strain and stress (eq. itv)
   const int sxy = B.scale(B.add(B.ddydn(ux), B.ddxdn(uy)), 0.5);
   const int sxz = B.scale(B.add(B.ddzdn(ux), B.ddxdn(uz)), 0.5);
   const int syz = B.scale(B.add(B.ddzdn(uy), B.ddydn(uz)), 0.5);
-  const int txx = B.mul(B.mul(rho, B.scale(nt, 1.0, G_DX)), B.add(sxx, B.scale(D, p.c1)));
-  const int tyy = B.mul(B.mul(rho, B.scale(nt, 1.0, G_DY)), B.add(syy, B.scale(D, p.c1)));
-  const int tzz = B.mul(B.mul(rho, B.scale(nt, 1.0, G_DZ)), B.add(szz, B.scale(D, p.c1)));
+  const int txx = B.mul(B.mul(rho, B.scale(nt, 1.0, G_LX)), B.add(sxx, B.scale(D, p.c1)));
+  const int tyy = B.mul(B.mul(rho, B.scale(nt, 1.0, G_LY)), B.add(syy, B.scale(D, p.c1)));
+  const int tzz = B.mul(B.mul(rho, B.scale(nt, 1.0, G_LZ)), B.add(szz, B.scale(D, p.c1)));
   const int txy = B.mul(B.mul(rxy, nxy), sxy);
   const int txz = B.mul(B.mul(rxz, nxz), sxz);
   const int tyz = B.mul(B.mul(ryz, nyz), syz);
@@ -264,11 +264,11 @@ VProgram build_rhs_program(const mhd_params& p) {
   }
   if (T & MHD_T_EDIFF) {
     const int lne = B.flog(em);
-    const int fx = B.mul(B.mul(B.mul(B.scale(B.xdn(rho), p.nuE), B.scale(B.xdn(nt), 1.0, G_DX)), B.xdn(em)),
+    const int fx = B.mul(B.mul(B.mul(B.scale(B.xdn(rho), p.nuE), B.scale(B.xdn(nt), 1.0, G_LX)), B.xdn(em)),
                          B.ddxdn(lne));
-    const int fy = B.mul(B.mul(B.mul(B.scale(B.ydn(rho), p.nuE), B.scale(B.ydn(nt), 1.0, G_DY)), B.ydn(em)),
+    const int fy = B.mul(B.mul(B.mul(B.scale(B.ydn(rho), p.nuE), B.scale(B.ydn(nt), 1.0, G_LY)), B.ydn(em)),
                          B.ddydn(lne));
-    const int fz = B.mul(B.mul(B.mul(B.scale(B.zdn(rho), p.nuE), B.scale(B.zdn(nt), 1.0, G_DZ)), B.zdn(em)),
+    const int fz = B.mul(B.mul(B.mul(B.scale(B.zdn(rho), p.nuE), B.scale(B.zdn(nt), 1.0, G_LZ)), B.zdn(em)),
                          B.ddzdn(lne));
     de = B.add(B.add(B.add(de, B.ddxup(fx)), B.ddyup(fy)), B.ddzup(fz));
   }
@@ -475,13 +475,13 @@ namespace {
 // table in scratch memory)
 __device__ __forceinline__ double geo_of(const BoxDev& b, int geo) {
   double r = 1.0;
-  r = geo == G_DX ? b.dx : r;
-  r = geo == G_DY ? b.dy : r;
-  r = geo == G_DZ ? b.dz : r;
+  r = geo == G_LX ? b.lv[0] : r;
+  r = geo == G_LY ? b.lv[1] : r;
+  r = geo == G_LZ ? b.lv[2] : r;
   r = geo == G_H ? b.hmin : r;
-  r = geo == G_MXY ? fmax(b.dx, b.dy) : r;
-  r = geo == G_MXZ ? fmax(b.dx, b.dz) : r;
-  r = geo == G_MYZ ? fmax(b.dy, b.dz) : r;
+  r = geo == G_LXY ? b.le[0] : r;
+  r = geo == G_LXZ ? b.le[1] : r;
+  r = geo == G_LYZ ? b.le[2] : r;
   return r;
 }
 

@@ -36,8 +36,10 @@ enum VOp : int {
   V_COUNT
 };
 
-// Per-box geometric factors multiplying the constant k of V_SCALE / V_FILL.
-enum VGeo : int { G_ONE = 0, G_DX, G_DY, G_DZ, G_H, G_HINV, G_MXY, G_MXZ, G_MYZ };
+// Per-box geometric factors multiplying the constant k of V_SCALE / V_FILL:
+// the viscosity length factors of eq. nuij (BoxDev::lv, le), the smallest
+// spacing and its reciprocal.
+enum VGeo : int { G_ONE = 0, G_LX, G_LY, G_LZ, G_H, G_HINV, G_LXY, G_LXZ, G_LYZ };
 
 // Axes of V_STEN / V_MAX3 / V_MEAN3.
 enum VAxis : int { VX = 0, VY = 1, VZ = 2 };

@@ -36,7 +36,8 @@ struct mhd_ctx {
   std::vector<BoxDev> h_boxes;
   // workspace
   void* work = nullptr;            // kWorkArrays * nelem elements
-  RedPartial* d_part = nullptr;    // nblk + 1 records (last = total)
+  RedItem* d_red = nullptr;        // per-item partials of mhd_reductions (nitems)
+  RedTotal* d_tot = nullptr;       // their fold
   void* adj = nullptr;             // adjoint workspace (allocated on first use)
   size_t adj_bytes = 0;
   VPlan* prog = nullptr;           // the right-hand side as a program (adjoint)
@@ -92,6 +93,44 @@ static int prof_fold(mhd_ctx* c) {
 }
 
 static std::string g_init_err;
+
+static const double kAlpha[3] = {0.0, -0.641874, -1.31021};   // eq. tconst
+static const double kBeta[3] = {0.46173, 0.924087, 0.390614};
+
+// Left end s of the real interval [-s, 0] on which one step of the
+// low-storage RK3 scheme (eqs. ddt, tupdate, tconst, coefficients as printed)
+// does not amplify y' = lambda y, z = lambda dt: |R(z)| <= 1 (about 2.5127).
+static double rk3_real_limit() {
+  auto amp = [](double z) {
+    double f = 1.0, U = 0.0;
+    for (int s = 0; s < 3; ++s) {
+      U = kAlpha[s] * U + z * f;
+      f += kBeta[s] * U;
+    }
+    return std::fabs(f);
+  };
+  double s = 0.0;
+  while (amp(-(s + 1e-3)) <= 1.0) s += 1e-3;
+  double lo = s, hi = s + 1e-3;
+  for (int it = 0; it < 60; ++it) {
+    const double m = 0.5 * (lo + hi);
+    (amp(-m) <= 1.0 ? lo : hi) = m;
+  }
+  return lo;
+}
+
+// Largest stable c_divb of a box: the div B diffusion c h_min^2 / dt
+// grad(div B) has eigenvalues -c h_min^2 / dt sum_a K_a^2 on longitudinal
+// modes, K_a the symbol of the staggered derivative, largest at the
+// two-cell wave: K_a h_a = 2 (75/64 + 25/384 + 3/640).  Stability of the RK3
+// step needs c h_min^2 K^2 sum_a 1/h_a^2 <= rk3_real_limit(); on cubic cells
+// c <= 0.1358.
+static double divb_limit(double dx, double dy, double dz) {
+  const double kh = 2.0 * (75.0 / 64.0 + 25.0 / 384.0 + 3.0 / 640.0);
+  const double h = std::min(dx, std::min(dy, dz));
+  const double s = h * h * (1.0 / (dx * dx) + 1.0 / (dy * dy) + 1.0 / (dz * dz));
+  return rk3_real_limit() / (kh * kh * s);
+}
 static constexpr int kWorkArrays = WS_COUNT;   // 34 arrays
 
 static int fail(mhd_ctx* c, int code, const std::string& msg) {
@@ -128,21 +167,6 @@ template <class T> static Phys<T> make_phys(const mhd_params& p) {
   ph.c_divb = (p.terms & MHD_T_DIVB) ? T(p.c_divb) : T(0);
   ph.terms = p.terms;
   return ph;
-}
-
-template <class T> static Work<T> make_work(const mhd_ctx* c) {
-  T* base = static_cast<T*>(c->work);
-  const long long n = c->nelem;
-  auto a = [&](int q) { return base + (long long)q * n; };
-  Work<T> w;
-  w.ux = a(0);
-  w.uy = a(1);
-  w.uz = a(2);
-  w.nus = a(3);
-  w.nmax = a(4);
-  w.nt = a(5);
-  w.lnt = a(6);
-  return w;
 }
 
 static Launch make_launch(const mhd_ctx* c) {
@@ -230,21 +254,27 @@ static void build_items(const mhd_ctx* c, int tile, std::vector<ZItem>& items) {
   }
 }
 
-// Uploads the work items of a tile shape; *d and *n are replaced.
+// Uploads the work items of a tile shape; *d and *n are replaced.  With
+// cpart (the items of every pass but F), also the per-item Courant and
+// reduction partials.
 static int upload_items(mhd_ctx* c, int tile, ZItem** d, int* n, CPart** cpart) {
   std::vector<ZItem> items;
   build_items(c, tile, items);
   ZItem* di = nullptr;
   CPart* dp = nullptr;
+  RedItem* dr = nullptr;
   hipError_t e;
   if ((e = hipMalloc(&di, sizeof(ZItem) * items.size())) != hipSuccess ||
-      (cpart && (e = hipMalloc(&dp, sizeof(CPart) * items.size())) != hipSuccess)) {
+      (cpart && (e = hipMalloc(&dp, sizeof(CPart) * items.size())) != hipSuccess) ||
+      (cpart && (e = hipMalloc(&dr, sizeof(RedItem) * items.size())) != hipSuccess)) {
     (void)hipFree(di);
+    (void)hipFree(dp);
     return fail(c, MHD_ENOMEM, std::string("work item tables: ") + hipGetErrorString(e));
   }
   if ((e = hipMemcpy(di, items.data(), sizeof(ZItem) * items.size(), hipMemcpyHostToDevice)) != hipSuccess) {
     (void)hipFree(di);
     (void)hipFree(dp);
+    (void)hipFree(dr);
     return hipfail(c, e, "work item upload");
   }
   if (c->stream) (void)hipStreamSynchronize(c->stream);
@@ -254,6 +284,8 @@ static int upload_items(mhd_ctx* c, int tile, ZItem** d, int* n, CPart** cpart) 
   if (cpart) {
     (void)hipFree(*cpart);
     *cpart = dp;
+    (void)hipFree(c->d_red);
+    c->d_red = dr;
   }
   return MHD_OK;
 }
@@ -354,7 +386,8 @@ void mhd_destroy(mhd_ctx* c) {
   (void)hipFree(c->d_tab);
   (void)hipFree(c->d_gtab);
   (void)hipFree(c->work);
-  (void)hipFree(c->d_part);
+  (void)hipFree(c->d_red);
+  (void)hipFree(c->d_tot);
   (void)hipFree(c->adj);
   delete c->prog;
   (void)hipFree(c->d_fused);
@@ -425,6 +458,11 @@ int mhd_init(const mhd_params* p, void* hip_stream, mhd_ctx** out) {
       return fail(nullptr, MHD_EINVAL, where + "unknown bc_z");
     }
     if (!(x.Lx > 0) || !(x.Ly > 0) || !(x.Lz > 0)) { delete c; return fail(nullptr, MHD_EINVAL, where + "box sizes must be > 0"); }
+    if ((p->terms & MHD_T_DIVB) && p->c_divb > divb_limit(x.Lx / x.nx, x.Ly / x.ny, x.Lz / x.nz)) {
+      delete c;
+      return fail(nullptr, MHD_EINVAL, where + "c_divb above the RK3 stability limit " +
+                                           std::to_string(divb_limit(x.Lx / x.nx, x.Ly / x.ny, x.Lz / x.nz)));
+    }
     if ((long long)x.nx * x.ny * (x.nz + 2LL * x.ngz) >= (1LL << 31)) {
       delete c;
       return fail(nullptr, MHD_EINVAL, where + "more than 2^31 - 1 cells (ghost planes included)");
@@ -447,6 +485,16 @@ int mhd_init(const mhd_params* p, void* hip_stream, mhd_ctx** out) {
     d.dz = x.Lz / x.nz;
     d.hmin = std::min(d.dx, std::min(d.dy, d.dz));
     d.hmax = std::max(d.dx, std::max(d.dy, d.dz));
+    if (p->nu_const > 0.0) {
+      for (int a = 0; a < 3; ++a) d.lv[a] = d.le[a] = d.hmin;
+    } else {
+      d.lv[0] = d.dx;
+      d.lv[1] = d.dy;
+      d.lv[2] = d.dz;
+      d.le[0] = std::max(d.dx, d.dy);
+      d.le[1] = std::max(d.dx, d.dz);
+      d.le[2] = std::max(d.dy, d.dz);
+    }
     d.zoff = -1;
     c->h_boxes.push_back(d);
     c->offsets.push_back(off);
@@ -473,7 +521,7 @@ int mhd_init(const mhd_params* p, void* hip_stream, mhd_ctx** out) {
   if ((e = hipMalloc(&c->d_boxes, sizeof(BoxDev) * c->h_boxes.size())) != hipSuccess ||
       (e = hipMalloc(&c->d_tab, sizeof(Blk) * tab.size())) != hipSuccess ||
       (c->ngblk && (e = hipMalloc(&c->d_gtab, sizeof(Blk) * gtab.size())) != hipSuccess) ||
-      (e = hipMalloc(&c->d_part, sizeof(RedPartial) * (c->nblk + 1))) != hipSuccess ||
+      (e = hipMalloc(&c->d_tot, sizeof(RedTotal))) != hipSuccess ||
       (e = hipMalloc(&c->work, (size_t)kWorkArrays * c->nelem * c->esize)) != hipSuccess) {
     g_init_err = std::string("device allocation failed: ") + hipGetErrorString(e);
     mhd_destroy(c);
@@ -558,9 +606,6 @@ static int do_rhs(mhd_ctx* c, void* const f[8], void* const dfdt[8]) {
   launch_zstage<T>(make_zlaunch(c), a);
   return check_launch(c, "mhd_rhs launch");
 }
-
-static const double kAlpha[3] = {0.0, -0.641874, -1.31021};   // eq. tconst
-static const double kBeta[3] = {0.46173, 0.924087, 0.390614};
 
 // dt > 0: fixed step.  dt == 0: the Courant step of each step's initial
 // state, computed on the device during the first stage (never leaves it).
@@ -745,22 +790,19 @@ static int do_rhs_adjoint(mhd_ctx* c, void* const f[8], void* const wbar[8],
 template <class T>
 static int do_reduce(mhd_ctx* c, void* const f[8], void* const dfdt[8], mhd_stats* out) {
   const Launch L = make_launch(c);
-  const Work<T> w = make_work<T>(c);
-  const Phys<T> ph = make_phys<T>(c->p);
   launch_ghost<T>(L, p8<T>(f));
-  L.at(PASS_REDUCE);
-  launch_nu<T>(L, cp8<T>(f), w, ph);
-  launch_reduce<T>(L, cp8<T>(f), cp8<T>(dfdt), w, ph, c->d_part, c->d_part + c->nblk);
-  L.at(PASS_END);
+  const ZLaunch Z = make_zlaunch(c);
+  Z.at(PASS_REDUCE);
+  launch_zreduce<T>(Z, cp8<T>(f), cp8<T>(dfdt), make_zwork<T>(c), make_phys<T>(c->p),
+                    static_cast<const T*>(c->d_ztab), c->d_red, c->d_tot, c->p.Cdt, c->p.Cdtd, c->p.Cdtr,
+                    c->p.nuB, c->p.eta_const);
+  Z.at(PASS_END);
   int rc = check_launch(c, "mhd_reductions launch");
   if (rc) return rc;
-  RedPartial tot;
-  hipError_t e = hipMemcpyAsync(&tot, c->d_part + c->nblk, sizeof(RedPartial),
-                                hipMemcpyDeviceToHost, c->stream);
+  RedTotal tot;
+  hipError_t e = hipMemcpyAsync(&tot, c->d_tot, sizeof(RedTotal), hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) return hipfail(c, e, "mhd_reductions readback");
-  // the kernel already weights the totals by each box's cell volume
-  const BoxDev& b0 = c->h_boxes[0];
   memset(out, 0, sizeof(*out));
   out->mass = tot.sum[0];
   out->mom[0] = tot.sum[1];
@@ -775,20 +817,18 @@ static int do_reduce(mhd_ctx* c, void* const f[8], void* const dfdt[8], mhd_stat
   out->divb_rms = std::sqrt(tot.sum[7] / (double)ninter);
   out->bmax = tot.mx[1];
   out->umax = tot.mx[2];
-  out->cmax = tot.mx[3];
-  out->numax = tot.mx[4];
-  out->ratemax = tot.mx[5];
-  double hmin = b0.hmin;
-  for (const auto& b : c->h_boxes) hmin = std::min(hmin, b.hmin);
+  out->cmax = tot.cmax;
+  out->numax = tot.dmax;
+  out->ratemax = dfdt ? tot.rmax : 0.0;
   const double inf = std::numeric_limits<double>::infinity();
-  out->dt_wave = tot.mx[3] > 0 ? c->p.Cdt * hmin / tot.mx[3] : inf;
-  out->dt_diff = tot.mx[4] > 0 ? c->p.Cdtd * hmin / tot.mx[4] : inf;
-  out->dt_rate = (dfdt && tot.mx[5] > 0) ? c->p.Cdtr / tot.mx[5] : inf;
-  long long arg = tot.arg[0];
+  out->dt_wave = tot.dtw;
+  out->dt_diff = tot.dtd;
+  out->dt_rate = dfdt ? tot.dtr : inf;
+  long long arg = tot.warg;
   out->dt = out->dt_wave;
   out->dt_limit = 0;
-  if (out->dt_diff < out->dt) { out->dt = out->dt_diff; out->dt_limit = 1; arg = tot.arg[1]; }
-  if (out->dt_rate < out->dt) { out->dt = out->dt_rate; out->dt_limit = 2; arg = tot.arg[2]; }
+  if (out->dt_diff < out->dt) { out->dt = out->dt_diff; out->dt_limit = 1; arg = tot.darg; }
+  if (out->dt_rate < out->dt) { out->dt = out->dt_rate; out->dt_limit = 2; arg = tot.rarg; }
   int box = 0;
   for (int b = 0; b < (int)c->offsets.size(); ++b)
     if (arg >= c->offsets[b]) box = b;
@@ -856,7 +896,7 @@ int mhd_step_adjoint(mhd_ctx* c, void* const f_n[8], double dt, void* const gin[
     if (b.bc_z != MHD_BC_PERIODIC) return fail(c, MHD_EUNSUPPORTED, "adjoint supports periodic boxes only");
   if (c->p.terms & (MHD_T_EDIFFAV | MHD_T_LNP | MHD_T_DIVB))
     return fail(c, MHD_EUNSUPPORTED, "adjoint without MHD_T_EDIFFAV, MHD_T_LNP and MHD_T_DIVB only");
-  if (!std::isfinite(dt)) return fail(c, MHD_EINVAL, "dt not finite");
+  if (!std::isfinite(dt) || !(dt > 0.0)) return fail(c, MHD_EINVAL, "dt must be finite and > 0");
   for (int a = 0; a < 8; ++a)
     for (int b = 0; b < 8; ++b)
       if (gin[a] == gout[b] || f_n[a] == gout[b]) return fail(c, MHD_EINVAL, "gbar_out overlaps an input");

@@ -45,6 +45,11 @@ struct BoxDev {
   long long ncell;           // nx * ny * nzt
   double dx, dy, dz, hmin, hmax;
   long long zoff;            // wall boxes: first entry of the z-coefficient table
+  // length factors of the viscosity (eq. nuij): nu_aa = lv[a] <nu>, edge
+  // nu_ab = le[ab] <nu> (xy, xz, yz).  Richtmyer-Morton: dx_a and
+  // max(dx_a, dx_b); constant viscosity: h_min for all, so that every
+  // component is nu_const whatever the cell shape (Section 6.1).
+  double lv[3], le[3];
 };
 
 // z-stencil coefficient tables of wall-bounded boxes: for operator type
@@ -107,11 +112,14 @@ template <class T> struct Geo {
   int nx, ny, nzt, wall, g0, g1;
   long long off, sxy;
   T dx, dy, dz, h, hmax, hxi, hyi, hzi;
+  T lx, ly, lz, lxy, lxz, lyz;   // viscosity length factors (BoxDev::lv, le)
   __device__ explicit Geo(const BoxDev& b)
       : nx(b.nx), ny(b.ny), nzt(b.nzt), wall(b.wall), g0(b.g0), g1(b.g1),
         off(b.off), sxy((long long)b.nx * b.ny),
         dx(T(b.dx)), dy(T(b.dy)), dz(T(b.dz)), h(T(b.hmin)), hmax(T(b.hmax)),
-        hxi(T(1.0 / b.dx)), hyi(T(1.0 / b.dy)), hzi(T(1.0 / b.dz)) {}
+        hxi(T(1.0 / b.dx)), hyi(T(1.0 / b.dy)), hzi(T(1.0 / b.dz)),
+        lx(T(b.lv[0])), ly(T(b.lv[1])), lz(T(b.lv[2])),
+        lxy(T(b.le[0])), lxz(T(b.le[1])), lyz(T(b.le[2])) {}
   __device__ long long at(int i, int j, int k) const {
     i = i < 0 ? i + nx : (i >= nx ? i - nx : i);
     j = j < 0 ? j + ny : (j >= ny ? j - ny : j);

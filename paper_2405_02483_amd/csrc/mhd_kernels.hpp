@@ -16,12 +16,6 @@ template <class T> struct Phys {
   unsigned terms;
 };
 
-// Intermediate arrays of the viscosity chain (context-owned workspace).
-template <class T> struct Work {
-  T *ux, *uy, *uz;        // face velocities
-  T *nus, *nmax, *nt, *lnt;
-};
-
 // Kernel passes, as reported by the timing hook (order = mhd.h MHD_PASS_*).
 enum Pass : int {
   PASS_PRIM = 0, PASS_NUS, PASS_MAX3, PASS_MEAN3, PASS_EDGES, PASS_CF, PASS_FINAL,
@@ -43,21 +37,6 @@ struct Launch {
   void at(int pass) const { if (mark) mark(mark_ctx, pass); }
 };
 
-// Per-block partial results of the float64 reductions.
-constexpr int kNSum = 8;   // mass, px, py, pz, ekin, emag(B^2), eint, divb^2
-constexpr int kNMax = 7;   // |divb|, bmax, umax, cmax, numax, ratemax, (spare)
-constexpr int kNArg = 3;   // argmax of cmax, numax, ratemax (packed index)
-struct RedPartial {
-  double sum[kNSum];
-  double mx[kNMax];
-  long long arg[kNArg];
-  long long nonfinite, nonpositive;
-};
-
-template <class T> void launch_nu(const Launch& L, CP8<T> f, const Work<T>& w, const Phys<T>& ph);
 template <class T> void launch_ghost(const Launch& L, P8<T> f);
-template <class T>
-void launch_reduce(const Launch& L, CP8<T> f, CP8<T> dfdt, const Work<T>& w, const Phys<T>& ph,
-                   RedPartial* partial, RedPartial* total);
 
 }  // namespace smhd

@@ -70,16 +70,26 @@ __device__ __forceinline__ double block_max(double v, double* sh) {
 // Front plane r: x/y stencils of plane r go through LDS, their results wait
 // in short per-thread queues; u_z (plane r-2) and the z stencils (plane r-5)
 // come from register windows.
-template <class T, int TX, int TY, bool PERS>
+//
+// RED (the reduction instantiation of mhd_reductions): also accumulates, in
+// float64 over the item's interior cells, the totals of the state, div B and
+// the maxima, the wave speed c_s + c_A + |u_perp| and the rate
+// max(|d ln rho/dt|, |d ln e_m/dt|) with the cells that set them, into
+// red[item].
+template <class T, int TX, int TY, bool PERS, bool RED = false>
 __global__ __launch_bounds__(TX * TY) void zA1(const BoxDev* __restrict__ boxes,
                                                const ZItem* __restrict__ items, int nitems, const T* __restrict__ ztab,
                                                int* __restrict__ queue,
                                                CP8<T> f, Phys<T> ph, ZWork<T> ws,
-                                               CPart* __restrict__ cpart) {
+                                               CPart* __restrict__ cpart,
+                                               CP8<T> dfdt = CP8<T>{}, RedItem* __restrict__ red = nullptr) {
   T* __restrict__ nus_out = ws.arr(WS_NUS);
   T* __restrict__ D_out = ws.arr(WS_D);
   T* __restrict__ divb_out = ws.arr(WS_DIVB);
   const bool divb = ph.terms & T_DIVB;
+  constexpr int NW = TX * TY / 64;
+  __shared__ double sredw[RED ? NW * 15 : 1];
+  __shared__ long long sredl[RED ? NW * 4 : 1];
   T* __restrict__ uz_out = ws.arr(WS_UZ);
   using PR = Plane<TX, TY, 5>;
   using PP = Plane<TX, TY, 3>;
@@ -98,6 +108,10 @@ __global__ __launch_bounds__(TX * TY) void zA1(const BoxDev* __restrict__ boxes,
   T wR[6] = {}, wUZ[6] = {}, wBZ[8] = {}, fPZ[3] = {}, fE[6] = {};
   T fUBX[6] = {}, fUBY[6] = {}, fBBX[6] = {}, fBBY[6] = {}, fDXY[6] = {}, fDXB[6] = {};
   double cmax = 0.0;
+  // reduction accumulators (RED): sums, maxima, (max, cell) pairs, counts
+  double rs[8] = {}, rdiv = 0.0, rbm = 0.0, rum = 0.0, rc = 0.0, rrate = 0.0;
+  long long rca = 0x7fffffffffffffffLL, rra = 0x7fffffffffffffffLL, rnf = 0, rnp = 0;
+  auto packed = [&](int k_) { return b.off + ((long long)k_ * b.ny + gy) * b.nx + gx; };
   for (int r = it.z0 - 5; r <= it.z1 + 4; ++r) {
     T rr = T(0), pz = T(0), e = T(0), bz = T(0);
     T ubx = T(0), uby = T(0), bbx = T(0), bby = T(0), dxy = T(0), dxb = T(0);
@@ -133,9 +147,37 @@ __global__ __launch_bounds__(TX * TY) void zA1(const BoxDev* __restrict__ boxes,
       bbx = op6<0, 1, T>([&](int m) { return sBX[PP::at(tx + m, ty)]; }, T(0));
       bby = op6<0, 1, T>([&](int m) { return sBY[PP::at(tx, ty + m)]; }, T(0));
       // x and y parts of div B at the centre (the div B diffusion)
-      if (divb)
+      if (divb || RED)
         dxb = op6<1, 1, T>([&](int m) { return sBX[PP::at(tx + m, ty)]; }, g.hxi) +
               op6<1, 1, T>([&](int m) { return sBY[PP::at(tx, ty + m)]; }, g.hyi);
+      // totals over the own cell of an interior plane (faces at the lower side)
+      if (RED && own && r >= it.z0 && r < it.z1 && interior(r)) {
+        const double rd = rr, pxd = sPX[PP::at(tx, ty)], pyd = sPY[PP::at(tx, ty)], pzd = pz;
+        const double ed = e, bxd = sBX[PP::at(tx, ty)], byd = sBY[PP::at(tx, ty)], bzd = bz;
+        const double uxd = sUX[PP::at(tx, ty)], uyd = sUY[PP::at(tx, ty)];
+        const double v8[8] = {rd, pxd, pyd, pzd, ed, bxd, byd, bzd};
+        for (int v = 0; v < 8; ++v) rnf += isfinite(v8[v]) ? 0 : 1;
+        if (!(rd > 0.0) || !(ed > 0.0)) ++rnp;
+        rs[0] += rd;
+        rs[1] += pxd;
+        rs[2] += pyd;
+        rs[3] += pzd;
+        rs[4] += 0.5 * (pxd * uxd + pyd * uyd);
+        rs[5] += bxd * bxd + byd * byd + bzd * bzd;
+        rs[6] += ed;
+        rbm = fmax(rbm, fmax(fabs(bxd), fmax(fabs(byd), fabs(bzd))));
+        rum = fmax(rum, fmax(fabs(uxd), fabs(uyd)));
+        if (dfdt.p[0]) {
+          const long long o = col(r);
+          const double dr = (double)dfdt.p[0][o] / rd;
+          const double dem = (double)dfdt.p[4][o] / ed - dr;
+          const double rate = fmax(fabs(dr), fabs(dem));
+          if (rate > rrate) {
+            rrate = rate;
+            rra = packed(r);
+          }
+        }
+      }
     }
     push(wR, rr);
     push(fPZ, pz);
@@ -154,6 +196,10 @@ __global__ __launch_bounds__(TX * TY) void zA1(const BoxDev* __restrict__ boxes,
       const T zr = zwin<0, 0, 6, 3>(wR, q1, wall, N, T(0), zt);
       uzq = fPZ[0] / zr;
       if (own && q1 >= it.z0 && q1 < it.z1) uz_out[col(q1)] = uzq;
+      if (RED && own && q1 >= it.z0 && q1 < it.z1 && interior(q1)) {
+        rs[4] += 0.5 * (double)fPZ[0] * (double)uzq;
+        rum = fmax(rum, fabs((double)uzq));
+      }
     }
     push(wUZ, uzq);                       // wUZ slot m = plane r-7+m
     // centre quantities of plane q = r - 5
@@ -180,13 +226,23 @@ __global__ __launch_bounds__(TX * TY) void zA1(const BoxDev* __restrict__ boxes,
         nus_out[o] = nus;
         D_out[o] = D;
         if (divb) divb_out[o] = fDXB[0] + zwin<1, 1, 8, 2>(wBZ, q, wall, N, g.hzi, zt);
-        if (cpart && interior(q)) {
+        if ((cpart || RED) && interior(q)) {
           const double ux_ = fUBX[0], uy_ = fUBY[0], uz_ = ubz;
           const double bx_ = fBBX[0], by_ = fBBY[0], bz_ = bbz, bbd = bb;
           const double udotb = bbd > 0.0 ? (ux_ * bx_ + uy_ * by_ + uz_ * bz_) / bbd : 0.0;
           const double uu = ux_ * ux_ + uy_ * uy_ + uz_ * uz_;
           const double up = sqrt(fmax(uu - udotb * udotb, 0.0));
-          cmax = fmax(cmax, (double)cs + (double)ca + up);
+          const double c_ = (double)cs + (double)ca + up;
+          cmax = fmax(cmax, c_);
+          if (RED) {
+            if (c_ > rc) {
+              rc = c_;
+              rca = packed(q);
+            }
+            const double db = (double)fDXB[0] + (double)zwin<1, 1, 8, 2>(wBZ, q, wall, N, g.hzi, zt);
+            rs[7] += db * db;
+            rdiv = fmax(rdiv, fabs(db));
+          }
         }
       }
     }
@@ -195,6 +251,53 @@ __global__ __launch_bounds__(TX * TY) void zA1(const BoxDev* __restrict__ boxes,
     const double m = block_max<TX * TY>(cmax, sred);
     if (threadIdx.x == 0) cpart[item_].cmax = m;
   }
+  if constexpr (RED) {
+    // wavefront reductions, then the waves in order in thread 0
+    const int w = (int)threadIdx.x / 64, lane = (int)threadIdx.x % 64;
+    double* sw = sredw + w * 15;
+    long long* sl = sredl + w * 4;
+    for (int q = 0; q < 8; ++q) rs[q] = wave_sum(rs[q]);
+    rdiv = wave_max(rdiv);
+    rbm = wave_max(rbm);
+    rum = wave_max(rum);
+    wave_maxarg(rc, rca);
+    wave_maxarg(rrate, rra);
+    const long long nf = wave_isum(rnf), np = wave_isum(rnp);
+    __syncthreads();
+    if (lane == 0) {
+      for (int q = 0; q < 8; ++q) sw[q] = rs[q];
+      sw[8] = rdiv;
+      sw[9] = rbm;
+      sw[10] = rum;
+      sw[11] = rc;
+      sw[12] = rrate;
+      sl[0] = rca;
+      sl[1] = rra;
+      sl[2] = nf;
+      sl[3] = np;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      RedItem R = {};
+      R.carg = R.rarg = 0x7fffffffffffffffLL;
+      for (int v = 0; v < NW; ++v) {
+        const double* s = sredw + v * 15;
+        const long long* l = sredl + v * 4;
+        for (int q = 0; q < 8; ++q) R.sum[q] += s[q];
+        R.mx[0] = fmax(R.mx[0], s[8]);
+        R.mx[1] = fmax(R.mx[1], s[9]);
+        R.mx[2] = fmax(R.mx[2], s[10]);
+        if (s[11] > R.cmax || (s[11] == R.cmax && l[0] < R.carg)) { R.cmax = s[11]; R.carg = l[0]; }
+        if (s[12] > R.rmax || (s[12] == R.rmax && l[1] < R.rarg)) { R.rmax = s[12]; R.rarg = l[1]; }
+        R.nonfinite += l[2];
+        R.nonpositive += l[3];
+      }
+      const double dV = b.dx * b.dy * b.dz;   // totals are volume integrals
+      for (int q = 0; q < 7; ++q) R.sum[q] *= dV;
+      R.darg = 0x7fffffffffffffffLL;   // the diffusion speed: A2, which runs next
+      red[item_] = R;
+    }
+  }
   ZLOOP_END
 }
 
@@ -202,11 +305,17 @@ __global__ __launch_bounds__(TX * TY) void zA1(const BoxDev* __restrict__ boxes,
 // A2: m = max over the 3x3x3 neighbourhood (x, y through LDS; z over a ring
 // of three x/y-maximum planes), then three-cell means along x, y (LDS) and
 // z (register window), floor 1e-30, and ln.
-template <class T, int TX, int TY, bool PERS>
+//
+// RED (the reduction instantiation of mhd_reductions): also the diffusion
+// speed max(<nu>, eta_speed h_max / h_min) of eq. courantcond, eta_speed =
+// nuB <nu> or eta_const / h_min, and its first maximal cell, into red[item].
+template <class T, int TX, int TY, bool PERS, bool RED = false>
 __global__ __launch_bounds__(TX * TY) void zA2(const BoxDev* __restrict__ boxes,
                                                const ZItem* __restrict__ items, int nitems, const T* __restrict__ ztab,
                                                int* __restrict__ queue,
-                                               ZWork<T> ws, CPart* __restrict__ cpart) {
+                                               ZWork<T> ws, CPart* __restrict__ cpart,
+                                               double nuB = 0.0, double eta_const = 0.0,
+                                               RedItem* __restrict__ red = nullptr) {
   const T* __restrict__ nus = ws.arr(WS_NUS);
   T* __restrict__ lnt_out = ws.arr(WS_LNT);
   using PN = Plane<TX, TY, 2>;
@@ -221,6 +330,8 @@ __global__ __launch_bounds__(TX * TY) void zA2(const BoxDev* __restrict__ boxes,
   i2.init(b, it.x0, it.y0);
   T wS[3] = {};
   double numax = 0.0;
+  double rd = 0.0;
+  long long rda = 0x7fffffffffffffffLL;
   for (int r = it.z0 - 2; r <= it.z1 + 1; ++r) {
     if (valid(r)) {
       __syncthreads();
@@ -272,12 +383,41 @@ __global__ __launch_bounds__(TX * TY) void zA2(const BoxDev* __restrict__ boxes,
       if (own) {
         lnt_out[col(q)] = log(v);
         if (cpart && interior(q)) numax = fmax(numax, (double)v);
+        if (RED && interior(q)) {
+          const double nu = v;
+          const double es = eta_const > 0.0 ? eta_const / b.hmin : nuB * nu;
+          const double d = fmax(nu, es * (b.hmax / b.hmin));
+          if (d > rd) {
+            rd = d;
+            rda = b.off + ((long long)q * b.ny + gy) * b.nx + gx;
+          }
+        }
       }
     }
   }
   if (cpart) {
     const double m = block_max<NT>(numax, sred);
     if (threadIdx.x == 0) cpart[item_].numax = m;
+  }
+  if constexpr (RED) {
+    wave_maxarg(rd, rda);
+    __syncthreads();
+    if (threadIdx.x % 64 == 0) {
+      sred[threadIdx.x / 64] = rd;
+      reinterpret_cast<long long*>(sred)[NT / 64 + threadIdx.x / 64] = rda;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double d = 0.0;
+      long long a = 0x7fffffffffffffffLL;
+      for (int v = 0; v < NT / 64; ++v) {
+        const double dv = sred[v];
+        const long long av = reinterpret_cast<long long*>(sred)[NT / 64 + v];
+        if (dv > d || (dv == d && av < a)) { d = dv; a = av; }
+      }
+      red[item_].dmax = d;
+      red[item_].darg = a;
+    }
   }
   ZLOOP_END
 }
@@ -409,7 +549,7 @@ __global__ __launch_bounds__(TX * TY) void zQ(const BoxDev* __restrict__ boxes,
         const T dxBZ = op6<1, 0, T>([&](int m) { return BZ[P3::at(tx + m, ty)]; }, g.hxi);
         const T xPZ = op6<0, 0, T>([&](int m) { return PZ[P3::at(tx + m, ty)]; }, T(0));
         T nxz = T(0), txz = T(0), sxz = T(0);
-        if (need_nu) nxz = fmax(g.dx, g.dz) * exp(zwin<0, 0, 6, 3>(wLX, q, wall, N, T(0), zt));
+        if (need_nu) nxz = g.lxz * exp(zwin<0, 0, 6, 3>(wLX, q, wall, N, T(0), zt));
         if (visc) {
           sxz = T(0.5) * (dzUX + dxUZ);
           txz = zRX * nxz * sxz;
@@ -449,7 +589,7 @@ __global__ __launch_bounds__(TX * TY) void zQ(const BoxDev* __restrict__ boxes,
         const T dyBZ = op6<1, 0, T>([&](int m) { return BZ[P3::at(tx, ty + m)]; }, g.hyi);
         const T yPZ = op6<0, 0, T>([&](int m) { return PZ[P3::at(tx, ty + m)]; }, T(0));
         T nyz = T(0), tyz = T(0), syz = T(0);
-        if (need_nu) nyz = fmax(g.dy, g.dz) * exp(zwin<0, 0, 6, 3>(wLY, q, wall, N, T(0), zt));
+        if (need_nu) nyz = g.lyz * exp(zwin<0, 0, 6, 3>(wLY, q, wall, N, T(0), zt));
         if (visc) {
           syz = T(0.5) * (dzUY + dyUZ);
           tyz = zRY * nyz * syz;
@@ -481,7 +621,7 @@ __global__ __launch_bounds__(TX * TY) void zQ(const BoxDev* __restrict__ boxes,
         if (adv) hz = -zwin<0, 0, 6, 3>(wE, q, wall, N, T(0), zt) * wUZ[3];
         if (ediff)
           hz = hz + ph.nuE * zwin<0, 0, 6, 3>(wRho, q, wall, N, T(0), zt) *
-                        (g.dz * zwin<0, 0, 6, 3>(wNu, q, wall, N, T(0), zt)) *
+                        (g.lz * zwin<0, 0, 6, 3>(wNu, q, wall, N, T(0), zt)) *
                         zwin<0, 0, 6, 3>(wEm, q, wall, N, T(0), zt) *
                         zwin<1, 0, 6, 3>(wLem, q, wall, N, g.hzi, zt);
         if (own) {
@@ -509,7 +649,7 @@ __global__ __launch_bounds__(TX * TY) void zQ(const BoxDev* __restrict__ boxes,
       const T szz = zwin<1, 1, 6, 2>(wUZ, q2, wall, N, g.hzi, zt);
       T gzz = T(0), czz = T(0);
       if (visc) {
-        const T tzz = wRho[2] * (g.dz * wNu[2]) * (szz + ph.c1 * Dg[o]);
+        const T tzz = wRho[2] * (g.lz * wNu[2]) * (szz + ph.c1 * Dg[o]);
         gzz = tzz;
         czz = tzz * szz;
       }
@@ -591,7 +731,7 @@ __global__ __launch_bounds__(TX * TY) void zP(const BoxDev* __restrict__ boxes,
     // ---- z-edge (x-1/2, y-1/2)
     T nxy = T(0), txy = T(0), sxy = T(0);
     if (need_nu)
-      nxy = fmax(g.dx, g.dy) * exp(op6<0, 0, T>([&](int m) { return S(13, x, y + m); }, T(0)));
+      nxy = g.lxy * exp(op6<0, 0, T>([&](int m) { return S(13, x, y + m); }, T(0)));
     if (visc) {
       const T rxy = op6<0, 0, T>([&](int m) { return S(11, x, y + m); }, T(0));
       sxy = T(0.5) * (op6<1, 0, T>([&](int m) { return S(6, x, y + m); }, g.hyi) +
@@ -630,8 +770,8 @@ __global__ __launch_bounds__(TX * TY) void zP(const BoxDev* __restrict__ boxes,
       T gxx = T(0), gyy = T(0), qc = T(0);
       if (visc) {
         const T rn = sR[P6::at(x, y)] * S(8, x, y);
-        const T txx = rn * g.dx * (sxx + ph.c1 * Dc);
-        const T tyy = rn * g.dy * (syy + ph.c1 * Dc);
+        const T txx = rn * g.lx * (sxx + ph.c1 * Dc);
+        const T tyy = rn * g.ly * (syy + ph.c1 * Dc);
         gxx = txx;
         gyy = tyy;
         qc = txx * sxx + tyy * syy;
@@ -685,11 +825,11 @@ __global__ __launch_bounds__(TX * TY) void zP(const BoxDev* __restrict__ boxes,
       }
       if (ediff) {
         hx = hx + ph.nuE * S(11, x, y) *
-                      (g.dx * op6<0, 0, T>([&](int m) { return S(8, x + m, y); }, T(0))) *
+                      (g.lx * op6<0, 0, T>([&](int m) { return S(8, x + m, y); }, T(0))) *
                       op6<0, 0, T>([&](int m) { return S(9, x + m, y); }, T(0)) *
                       op6<1, 0, T>([&](int m) { return S(10, x + m, y); }, g.hxi);
         hy = hy + ph.nuE * S(12, x, y) *
-                      (g.dy * op6<0, 0, T>([&](int m) { return S(8, x, y + m); }, T(0))) *
+                      (g.ly * op6<0, 0, T>([&](int m) { return S(8, x, y + m); }, T(0))) *
                       op6<0, 0, T>([&](int m) { return S(9, x, y + m); }, T(0)) *
                       op6<1, 0, T>([&](int m) { return S(10, x, y + m); }, g.hyi);
       }
@@ -1083,6 +1223,145 @@ __global__ __launch_bounds__(256) void k_dt(const BoxDev* __restrict__ boxes,
   if (threadIdx.x == 0) dt_dev[0] = sh[0];
 }
 
+// Totals of the per-item partials of mhd_reductions and the three limits of
+// eq. courantcond: Cdt h_min / cmax and Cdtd h_min / dmax with each item's
+// own box spacing (the smallest over items, with its cell), Cdtr / rmax.
+// Each thread folds items t, t + kRedThreads, ... in order; the threads
+// combine in a fixed tree, so the result is deterministic.
+__device__ __forceinline__ void wave_minarg(double& v, long long& a) {
+  for (int o = 32; o > 0; o >>= 1) {
+    const double v2 = __shfl_xor(v, o, 64);
+    const long long a2 = __shfl_xor(a, o, 64);
+    if (v2 < v || (v2 == v && a2 < a)) {
+      v = v2;
+      a = a2;
+    }
+  }
+}
+
+constexpr int kRedThreads = 256;
+__global__ __launch_bounds__(kRedThreads) void k_red_final(const BoxDev* __restrict__ boxes,
+                                                    const ZItem* __restrict__ items, int nitems,
+                                                    const RedItem* __restrict__ red, double Cdt,
+                                                    double Cdtd, double Cdtr, RedTotal* __restrict__ out) {
+  constexpr long long NOARG = 0x7fffffffffffffffLL;
+  const double inf = __builtin_huge_val();
+  double s[8] = {}, mx[3] = {}, c = 0.0, d = 0.0, r = 0.0, tw = inf, td = inf;
+  long long ca = NOARG, da = NOARG, ra = NOARG, wa = NOARG, dda = NOARG, nf = 0, np = 0;
+  for (int i = threadIdx.x; i < nitems; i += kRedThreads) {
+    const RedItem& R = red[i];
+    const BoxDev& b = boxes[items[i].box];
+    for (int q = 0; q < 8; ++q) s[q] += R.sum[q];
+    for (int q = 0; q < 3; ++q) mx[q] = fmax(mx[q], R.mx[q]);
+    if (R.cmax > c || (R.cmax == c && R.carg < ca)) { c = R.cmax; ca = R.carg; }
+    if (R.dmax > d || (R.dmax == d && R.darg < da)) { d = R.dmax; da = R.darg; }
+    if (R.rmax > r || (R.rmax == r && R.rarg < ra)) { r = R.rmax; ra = R.rarg; }
+    const double w = R.cmax > 0.0 ? Cdt * b.hmin / R.cmax : inf;
+    const double dd = R.dmax > 0.0 ? Cdtd * b.hmin / R.dmax : inf;
+    if (w < tw || (w == tw && R.carg < wa)) { tw = w; wa = R.carg; }
+    if (dd < td || (dd == td && R.darg < dda)) { td = dd; dda = R.darg; }
+    nf += R.nonfinite;
+    np += R.nonpositive;
+  }
+  for (int q = 0; q < 8; ++q) s[q] = wave_sum(s[q]);
+  for (int q = 0; q < 3; ++q) mx[q] = wave_max(mx[q]);
+  wave_maxarg(c, ca);
+  wave_maxarg(d, da);
+  wave_maxarg(r, ra);
+  wave_minarg(tw, wa);
+  wave_minarg(td, dda);
+  nf = wave_isum(nf);
+  np = wave_isum(np);
+  __shared__ double sd[kRedThreads / 64][16];
+  __shared__ long long sl[kRedThreads / 64][7];
+  const int w = (int)threadIdx.x / 64;
+  if (threadIdx.x % 64 == 0) {
+    for (int q = 0; q < 8; ++q) sd[w][q] = s[q];
+    for (int q = 0; q < 3; ++q) sd[w][8 + q] = mx[q];
+    sd[w][11] = c;
+    sd[w][12] = d;
+    sd[w][13] = r;
+    sd[w][14] = tw;
+    sd[w][15] = td;
+    sl[w][0] = ca;
+    sl[w][1] = da;
+    sl[w][2] = ra;
+    sl[w][3] = wa;
+    sl[w][4] = dda;
+    sl[w][5] = nf;
+    sl[w][6] = np;
+  }
+  __syncthreads();
+  // the waves in order: thread q < 8 adds sum q; thread 8 the rest
+  if (threadIdx.x < 8) {
+    double v = 0.0;
+    for (int x = 0; x < kRedThreads / 64; ++x) v += sd[x][threadIdx.x];
+    out->sum[threadIdx.x] = v;
+  } else if (threadIdx.x == 8) {
+    double m0 = 0.0, m1 = 0.0, m2 = 0.0, cm = 0.0, dm = 0.0, rm = 0.0, dw = inf, dd = inf;
+    long long xa = NOARG, ra_ = NOARG, wa_ = NOARG, da_ = NOARG, nf_ = 0, np_ = 0;
+    for (int x = 0; x < kRedThreads / 64; ++x) {
+      m0 = fmax(m0, sd[x][8]);
+      m1 = fmax(m1, sd[x][9]);
+      m2 = fmax(m2, sd[x][10]);
+      if (sd[x][11] > cm || (sd[x][11] == cm && sl[x][0] < xa)) { cm = sd[x][11]; xa = sl[x][0]; }
+      dm = fmax(dm, sd[x][12]);
+      if (sd[x][13] > rm || (sd[x][13] == rm && sl[x][2] < ra_)) { rm = sd[x][13]; ra_ = sl[x][2]; }
+      if (sd[x][14] < dw || (sd[x][14] == dw && sl[x][3] < wa_)) { dw = sd[x][14]; wa_ = sl[x][3]; }
+      if (sd[x][15] < dd || (sd[x][15] == dd && sl[x][4] < da_)) { dd = sd[x][15]; da_ = sl[x][4]; }
+      nf_ += sl[x][5];
+      np_ += sl[x][6];
+    }
+    out->mx[0] = m0;
+    out->mx[1] = m1;
+    out->mx[2] = m2;
+    out->cmax = cm;
+    out->dmax = dm;
+    out->rmax = rm;
+    out->dtw = dw;
+    out->dtd = dd;
+    out->dtr = rm > 0.0 ? Cdtr / rm : inf;
+    out->warg = wa_;
+    out->darg = da_;
+    out->rarg = ra_;
+    out->nonfinite = nf_;
+    out->nonpositive = np_;
+  }
+}
+
+template <class T, int TX, int TY>
+static void launch_zreduce_t(const ZLaunch& L, CP8<T> f, CP8<T> dfdt, const ZWork<T>& w, const Phys<T>& ph,
+                             const T* ztab, RedItem* red, double nuB, double eta_const) {
+  const int n = L.nitems;
+  const dim3 grid(8 * ((n + 7) / 8)), block(TX * TY);
+  hipLaunchKernelGGL((zA1<T, TX, TY, false, true>), grid, block, 0, L.stream, L.boxes, L.items, n, ztab,
+                     (int*)nullptr, f, ph, w, (CPart*)nullptr, dfdt, red);
+  hipLaunchKernelGGL((zA2<T, TX, TY, false, true>), grid, block, 0, L.stream, L.boxes, L.items, n, ztab,
+                     (int*)nullptr, w, (CPart*)nullptr, nuB, eta_const, red);
+}
+
+template <class T>
+void launch_zreduce(const ZLaunch& L, CP8<T> f, CP8<T> dfdt, const ZWork<T>& w, const Phys<T>& ph,
+                    const T* ztab, RedItem* red, RedTotal* tot, double Cdt, double Cdtd, double Cdtr,
+                    double nuB, double eta_const) {
+  switch (L.tile) {
+    case ZTILE_32x8: launch_zreduce_t<T, 32, 8>(L, f, dfdt, w, ph, ztab, red, nuB, eta_const); break;
+    case ZTILE_16x16: launch_zreduce_t<T, 16, 16>(L, f, dfdt, w, ph, ztab, red, nuB, eta_const); break;
+    case ZTILE_16x8: launch_zreduce_t<T, 16, 8>(L, f, dfdt, w, ph, ztab, red, nuB, eta_const); break;
+    case ZTILE_64x8: launch_zreduce_t<T, 64, 8>(L, f, dfdt, w, ph, ztab, red, nuB, eta_const); break;
+    default: launch_zreduce_t<T, 64, 4>(L, f, dfdt, w, ph, ztab, red, nuB, eta_const); break;
+  }
+  hipLaunchKernelGGL(k_red_final, dim3(1), dim3(kRedThreads), 0, L.stream, L.boxes, L.items, L.nitems, red, Cdt, Cdtd,
+                     Cdtr, tot);
+}
+
+template void launch_zreduce<float>(const ZLaunch&, CP8<float>, CP8<float>, const ZWork<float>&,
+                                    const Phys<float>&, const float*, RedItem*, RedTotal*, double, double,
+                                    double, double, double);
+template void launch_zreduce<double>(const ZLaunch&, CP8<double>, CP8<double>, const ZWork<double>&,
+                                     const Phys<double>&, const double*, RedItem*, RedTotal*, double, double,
+                                     double, double, double);
+
 // ---------------------------------------------------------------------------
 template <class T, int TX, int TY, bool PERS, unsigned FM, class G>
 static void zF_one(const G& grid, dim3 block, const ZLaunch& L, const ZStageArgs<T>& a, int* q) {
@@ -1162,6 +1441,7 @@ static void launch_zstage_m(const ZLaunch& L, const ZStageArgs<T>& a) {
     L.at(PASS_REDUCE);
     hipLaunchKernelGGL(k_dt, dim3(1), dim3(256), 0, L.stream, L.boxes, L.items, n, a.cpart, a.Cdt,
                        a.Cdtd, a.nuB, a.eta_const, a.dt_dev);
+    L.at(PASS_MEAN3);   // the plane means below are booked with A2 in every stage
   }
   if ((a.ph.terms & T_EDIFF) && (a.ph.terms & T_EDIFFAV)) {
     hipLaunchKernelGGL(k_plane_sum<T>, dim3(L.nplanes * kPlaneSlices), dim3(256), 0, L.stream, L.boxes, L.nbox,

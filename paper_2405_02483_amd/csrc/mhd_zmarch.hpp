@@ -27,6 +27,55 @@ struct CPart {
   double numax;    // max speed-like viscosity
 };
 
+// Per-item partial results of the float64 reductions (mhd_reductions),
+// written by the reduction instantiations of passes A1 (everything but the
+// diffusion speed) and A2 (the diffusion speed).  Sums are over the item's
+// interior cells; the first seven are weighted by the cell volume.
+struct RedItem {
+  double sum[8];        // mass, px, py, pz, ekin, B^2, e, (div B)^2 (unweighted)
+  double mx[3];         // max |div B|, max |B_a|, max |u_a|
+  double cmax, dmax, rmax;          // wave speed, diffusion speed, rate
+  long long carg, darg, rarg;       // their cells (packed index, first maximal)
+  long long nonfinite, nonpositive;
+};
+
+// Totals of all items and the three Courant limits (eq. courantcond), each
+// from its box's own spacing, with the cell that sets each.
+struct RedTotal {
+  double sum[8];
+  double mx[3];
+  double cmax, dmax, rmax;
+  double dtw, dtd, dtr;
+  long long warg, darg, rarg;
+  long long nonfinite, nonpositive;
+};
+
+// Wavefront reductions (64 lanes): the result is exact in lane 0; every lane
+// combines in a fixed order, so the result does not depend on timing.
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ long long wave_isum(long long v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+// (max, first index): ties go to the smaller index
+__device__ __forceinline__ void wave_maxarg(double& v, long long& a) {
+  for (int o = 32; o > 0; o >>= 1) {
+    const double v2 = __shfl_xor(v, o, 64);
+    const long long a2 = __shfl_xor(a, o, 64);
+    if (v2 > v || (v2 == v && a2 < a)) {
+      v = v2;
+      a = a2;
+    }
+  }
+}
+
 __device__ __forceinline__ int wrapm(int a, int n) {
   const int r = a % n;
   return r < 0 ? r + n : r;

@@ -94,4 +94,12 @@ template <class T> struct ZStageArgs {
 
 template <class T> void launch_zstage(const ZLaunch& L, const ZStageArgs<T>& a);
 
+// mhd_reductions: passes A1 and A2 in their reduction instantiations over
+// the work items of L (grid mode), then the fold of the per-item partials
+// red[L.nitems] into *tot.
+template <class T>
+void launch_zreduce(const ZLaunch& L, CP8<T> f, CP8<T> dfdt, const ZWork<T>& w, const Phys<T>& ph,
+                    const T* ztab, RedItem* red, RedTotal* tot, double Cdt, double Cdtd, double Cdtr,
+                    double nuB, double eta_const);
+
 }  // namespace smhd

@@ -63,6 +63,15 @@ def reversal_schedule(nsteps, ncheck):
     return acts
 
 
+def _check_dt(dt):
+    """The rollout differentiates a fixed step: dt must be a finite positive
+    number.  (The library's dt == 0, a Courant step taken on the device,
+    changes from step to step and is not differentiated.)"""
+    import math
+    if not (isinstance(dt, (int, float)) and math.isfinite(dt) and dt > 0):
+        raise ValueError("rollout needs a fixed time step dt > 0, got %r" % (dt,))
+
+
 class _Stepper:
     """Advances copies of states with the library (fixed dt)."""
 
@@ -83,6 +92,7 @@ class MHDRollout(torch.autograd.Function):
 
     @staticmethod
     def forward(actx, ctx, dt, nsteps, ncheck, *x):
+        _check_dt(dt)
         st = _Stepper(ctx, dt)
         y = st.advance([t.detach() for t in x], nsteps)
         actx.x0 = [t.detach().clone() for t in x]
@@ -134,6 +144,7 @@ def rollout(ctx, x, dt, nsteps, ncheck=None):
     """Differentiable nsteps-step rollout of the state x (list of 8 tensors).
     ncheck: checkpoint slots for the backward pass; None sizes them from the
     free device memory (checkpoint_budget)."""
+    _check_dt(dt)
     if ncheck is None:
         ncheck = checkpoint_budget(ctx, nsteps)
     return list(MHDRollout.apply(ctx, dt, nsteps, ncheck, *x))

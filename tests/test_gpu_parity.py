@@ -42,10 +42,19 @@ def _case(name):
         return f, box, prm
     if name == "strat":
         return inputs.stratified(12, 10, 24, seed=3)
+    if name == "turb_aniso":
+        # dx, dy, dz all different
+        f, box, prm = inputs.turbulent(n=20, seed=6, kmax=3.0)
+        f = [a[:18, :, :16].copy() for a in f]
+        box = dict(box, nx=16, ny=20, nz=18, Lx=1.1, Ly=0.8, Lz=1.35)
+        return f, box, prm
+    if name == "strat_aniso":
+        f, box, prm = inputs.stratified(14, 10, 20, seed=8)
+        return f, dict(box, Lx=box["Lx"] * 1.4, Ly=box["Ly"] * 0.7), prm
     raise KeyError(name)
 
 
-CASES = ["ot32", "turb_ragged", "turb_min", "strat"]
+CASES = ["ot32", "turb_ragged", "turb_min", "strat", "turb_aniso", "strat_aniso"]
 
 
 def _oracle_rhs(f, box, prm, **over):
@@ -145,7 +154,7 @@ def test_rhs_parity_f32(case):
     ctx.close()
 
 
-@pytest.mark.parametrize("case", ["ot32", "strat", "turb_ragged"])
+@pytest.mark.parametrize("case", ["ot32", "strat", "turb_ragged", "turb_aniso", "strat_aniso"])
 def test_reductions_parity(case):
     f, box, prm = _case(case)
     g, p = grid_params(box, prm)
@@ -220,7 +229,7 @@ def test_repeat_calls_are_bitwise_identical():
     ctx.close()
 
 
-@pytest.mark.parametrize("case", ["ot32", "strat", "turb_ragged"])
+@pytest.mark.parametrize("case", ["ot32", "strat", "turb_ragged", "turb_aniso"])
 def test_courant_step_on_device_f64(case):
     """dt == 0: each step takes the Courant step of its initial state,
     computed on the device; state and dt match the oracle."""
@@ -258,4 +267,59 @@ def test_tile_shapes_give_identical_bits(dtype):
         else:
             for a, b in zip(fd, ref):
                 assert torch.equal(a, b), name
+    ctx.close()
+
+
+@pytest.mark.parametrize("const", [False, True])
+def test_anisotropic_viscosity_modes_f64(const):
+    """The viscous terms alone on cells with dx != dy != dz, in the
+    Richtmyer-Morton and the constant-viscosity modes (every nu_ij =
+    nu_const): the library's length factors against the oracle's."""
+    f, box, prm = _case("turb_aniso")
+    over = dict(terms=O.T_VISC | O.T_EDIFF | O.T_RESIST)
+    if const:
+        over["nu_const"] = 0.013
+    ctx = _ctx(box, prm, torch.float64, **over)
+    F = ctx.box_view(ctx.rhs(ctx.upload([f])), 0)
+    errs = rel_errors(F, _oracle_rhs(f, box, prm, **over))
+    assert max(errs) < TOL64, errs
+    ctx.close()
+
+
+def test_reductions_mixed_cell_sizes():
+    """An ensemble of unit boxes of 8, 12 and 16 cells per axis (three cell
+    sizes): the reductions' Courant step, the step the device takes with
+    dt == 0, and the smallest of the oracle's per-box Courant steps agree,
+    and the reductions name the box and cell that set it."""
+    from paper_2405_02483_amd.lib import Context
+    cases = [inputs.turbulent(n=n, seed=6100 + n, kmax=2.0) for n in (12, 8, 16)]
+    # the coarse box moves fastest, so the smallest step need not be on the finest grid
+    cases[1][0][1] *= 3.0
+    prm = cases[0][2]
+    want = []
+    for f, box, _ in cases:
+        g, p = grid_params(box, prm)
+        want.append(O.courant(to_cpu64(f), g, p))
+    b_min = min(range(len(cases)), key=lambda b: want[b][0])
+    ctx = Context([c[1] for c in cases], prm, dtype=torch.float64)
+    fd = ctx.upload([c[0] for c in cases])
+    st = ctx.reductions(fd)
+    assert math.isclose(st["dt"], want[b_min][0], rel_tol=1e-12), (st["dt"], [w[0] for w in want])
+    assert st["dt_box"] == b_min and st["dt_argmax"] == want[b_min][1]
+    assert st["dt_limit"] == want[b_min][2]
+    ctx.step(fd, 0.0, 1)
+    assert math.isclose(ctx.last_dt(), st["dt"], rel_tol=1e-12)
+    ctx.close()
+
+
+def test_step_adjoint_rejects_nonpositive_dt():
+    """The adjoint differentiates a fixed step: dt <= 0 is refused."""
+    from paper_2405_02483_amd.lib import MhdError, MHD_EINVAL
+    f, box, prm = _case("turb_min")
+    ctx = _ctx(box, prm, torch.float64)
+    fd = ctx.upload([f])
+    for dt in (0.0, -1e-3):
+        with pytest.raises(MhdError) as ei:
+            ctx.step_adjoint(fd, dt, fd)
+        assert ei.value.code == MHD_EINVAL
     ctx.close()

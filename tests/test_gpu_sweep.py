@@ -6,7 +6,10 @@ this one aims at indexing mistakes that only some (size, tile) pairs expose
 (partial tiles, chunk edges, planes next to a wall).  Each box also switches
 on a random subset of the optional terms (Newtonian cooling, the Coriolis
 force, energy diffusion about the horizontal mean, the ln(P/P_aver) pressure
-gradient).
+gradient) and, in some boxes, the constant viscosity.  Cells are
+anisotropic: each axis's spacing is scaled by a random factor in [0.6, 1.6],
+so the viscosity length factors dx_a and max(dx_a, dx_b), the Courant limits
+and the div B scale see dx != dy != dz.
 
 Error measure: relative L2 per field, as in the other parity tests.  In a
 closed-wall box the atmosphere is hydrostatic, so the z momentum rate is the
@@ -44,6 +47,13 @@ def _cases():
     return out
 
 
+def _aniso(box, seed):
+    """The box with each side scaled by its own random factor in [0.6, 1.6]."""
+    r = random.Random(seed)
+    return dict(box, Lx=box["Lx"] * r.uniform(0.6, 1.6), Ly=box["Ly"] * r.uniform(0.6, 1.6),
+                Lz=box["Lz"] * r.uniform(0.6, 1.6))
+
+
 def _errors(got, want, scale):
     out = []
     for g, w, s in zip(got, want, scale):
@@ -64,11 +74,14 @@ def test_rhs_random_sizes_all_tiles(case, walls, nx, ny, nz, ftiles):
         f, box, prm = inputs.turbulent(n=n, seed=300 + case, kmax=3.0)
         f = [np.ascontiguousarray(a[:nz, :ny, :nx]) for a in f]
         box = dict(box, nx=nx, ny=ny, nz=nz, Lx=nx / n, Ly=ny / n, Lz=nz / n)
+    box = _aniso(box, 11000 + case)
     trng = random.Random(9000 + case)
     extra = sum(bit for bit in (T_COOL, T_CORI, T_EDIFFAV, T_LNP) if trng.random() < 0.5)
     prm = dict(prm, terms=T_ALL | extra, e_cool=trng.uniform(0.5, 2.0), t_cool=trng.uniform(0.3, 2.0),
                rho_cool=trng.uniform(0.2, 2.0), cool_cut=trng.randrange(3),
                omega=tuple(trng.uniform(-1.5, 1.5) for _ in range(3)))
+    if case % 4 == 1:
+        prm = dict(prm, nu_const=trng.uniform(0.005, 0.02))
     g, p = grid_params(box, prm)
     ft = tuple(torch.from_numpy(a.copy()) for a in f)
     want = O.rhs(ft, g, p)
@@ -106,11 +119,13 @@ def test_rhs_random_sizes_all_tiles(case, walls, nx, ny, nz, ftiles):
         ctx.close()
 
 
-def _ragged_periodic(nx, ny, nz, seed):
+def _ragged_periodic(nx, ny, nz, seed, aniso=False):
     n = max(nx, ny, nz)
     f, box, prm = inputs.turbulent(n=n, seed=seed, kmax=3.0)
     f = [np.ascontiguousarray(a[:nz, :ny, :nx]) for a in f]
     box = dict(box, nx=nx, ny=ny, nz=nz, Lx=nx / n, Ly=ny / n, Lz=nz / n)
+    if aniso:
+        box = _aniso(box, seed)
     return f, box, prm
 
 
@@ -135,9 +150,10 @@ def test_step_random_mixed_ensemble(cool):
     for b in range(6):
         nx, ny = rng.randint(6, 30), rng.randint(6, 30)
         if b % 2:
-            cases.append(inputs.stratified(nx, ny, rng.randint(6, 30), seed=500 + b))
+            f_, box_, prm_ = inputs.stratified(nx, ny, rng.randint(6, 30), seed=500 + b)
+            cases.append((f_, _aniso(box_, 600 + b), prm_))
         else:
-            cases.append(_ragged_periodic(nx, ny, rng.randint(6, 30), 500 + b))
+            cases.append(_ragged_periodic(nx, ny, rng.randint(6, 30), 500 + b, aniso=True))
     prm = [c for c in cases if c[1].get("wall")][0][2]
     if cool:
         prm = dict(prm, terms=T_ALL | T_COOL, e_cool=1.2, t_cool=0.5, rho_cool=0.7,
@@ -170,11 +186,14 @@ def test_step_random_mixed_ensemble(cool):
 def test_step_adjoint_random_sizes_f64(seed):
     """The step adjoint on a periodic box of random ragged size, with a
     random launch configuration for its stage-state passes, against the
-    oracle's discrete adjoint (1e-10, as for the fixed cases)."""
+    oracle's discrete adjoint (1e-10, as for the fixed cases).  Odd seeds
+    use anisotropic cells, and seed 5 the constant viscosity as well."""
     from paper_2405_02483_amd.lib import Context, TILES
     rng = random.Random(9100 + seed)
     nx, ny, nz = rng.randint(6, 28), rng.randint(6, 28), rng.randint(6, 28)
-    f, box, prm = _ragged_periodic(nx, ny, nz, 700 + seed)
+    f, box, prm = _ragged_periodic(nx, ny, nz, 700 + seed, aniso=bool(seed % 2))
+    if seed == 5:
+        prm = dict(prm, nu_const=0.011)
     g, p = grid_params(box, prm)
     ft = tuple(torch.from_numpy(a.copy()) for a in f)
     dt = 0.5 * O.courant(ft, g, p)[0]

@@ -40,6 +40,8 @@ def _params(**over):
     (dict(Cdt=float("nan")), lib.MHD_EINVAL),
     (dict(terms=1 << 14), lib.MHD_EINVAL),
     (dict(terms=lib.T_ALL | lib.T_DIVB, c_divb=-0.1), lib.MHD_EINVAL),
+    # above the RK3 real-axis limit of the div B diffusion on cubic cells
+    (dict(terms=lib.T_ALL | lib.T_DIVB, c_divb=0.1359), lib.MHD_EINVAL),
     (dict(reserved2=1), lib.MHD_EINVAL),
     (dict(terms=lib.T_ALL | lib.T_COOL, t_cool=0.0), lib.MHD_EINVAL),
     (dict(terms=lib.T_ALL | lib.T_COOL, t_cool=1.0, e_cool=float("nan")), lib.MHD_EINVAL),
@@ -84,3 +86,25 @@ def test_null_arguments():
     assert L.mhd_get_final_tile(None, ctypes.byref(t)) == lib.MHD_EINVAL
     assert L.mhd_autotune(None, null8, null8, 1, None) == lib.MHD_EINVAL
     L.mhd_destroy(None)
+
+
+def test_divb_limit_accepts_the_stable_range():
+    """c_divb just below the RK3 limit of the div B diffusion (0.13582 on
+    cubic cells) passes the argument checks: the failure, if any, is not
+    MHD_EINVAL (without a GPU the device allocation fails instead)."""
+    L = lib.load()
+    p, keep = _params(terms=lib.T_ALL | lib.T_DIVB, c_divb=0.1358)
+    ctx = ctypes.c_void_p()
+    rc = L.mhd_init(ctypes.byref(p), None, ctypes.byref(ctx))
+    if rc == lib.MHD_OK:
+        L.mhd_destroy(ctx)
+    assert rc != lib.MHD_EINVAL, L.mhd_last_error(None)
+
+
+def test_rollout_refuses_a_courant_dt():
+    """The rollout differentiates a fixed step: dt == 0 (the library's
+    per-step Courant dt) or dt < 0 raises before any library call."""
+    from paper_2405_02483_amd.rollout import rollout
+    for dt in (0.0, -1e-3, float("nan")):
+        with pytest.raises(ValueError):
+            rollout(None, [], dt, 3, ncheck=1)
