@@ -196,6 +196,22 @@ int64_t mhd_box_offset(const mhd_ctx* ctx, int32_t b);
  * f and dfdt must not overlap.                                             */
 int mhd_rhs(mhd_ctx* ctx, void* const f[8], void* const dfdt[8]);
 
+/* mhd_rhs for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  The
+ * result is that of mhd_rhs, bit for bit (same kernels, same order).  The
+ * call allocates nothing: its per-call scratch (stage workspace, per-plane
+ * tables, queue counters) lives in a static device array of 64 MiB that
+ * each GPU holds from the first mhd_init on it until the process ends; the
+ * context's tables come from mhd_init.  That fits about 490,000 cells of
+ * float32 or 245,000 of float64 (ghost planes included; 34 arrays per cell
+ * plus small per-plane tables).  MHD_EINVAL, with the bytes needed in
+ * mhd_last_error, when the context's boxes need more; MHD_EHIP when the array is
+ * not available on the device.  Every call on one GPU shares the one array
+ * and overwrites its contents: calls that overlap on one GPU (other
+ * streams, other contexts, other threads) race and must be ordered by the
+ * caller.                                                                  */
+int mhd_rhs_noalloc(mhd_ctx* ctx, void* const f[8], void* const dfdt[8]);
+
 /* Advance f by nsteps steps of the low-storage RK3 scheme (eqs. ddt,
  * tupdate, tconst):  per stage i, dU <- alpha_i dU + F(f),
  * f <- f + beta_i dt dU.  dt > 0: that fixed step.  dt == 0: every step

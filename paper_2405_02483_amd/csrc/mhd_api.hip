@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -60,6 +61,7 @@ struct mhd_ctx {
   double* d_lnpart = nullptr;      // their partial sums, kPlaneSlices per plane
   void* d_lnpav = nullptr;         // ln of the plane means of P, per plane of every box
   int nplanes = 0;
+  void* scratch = nullptr;         // this device's address of the static scratch array
   // timing of kernel passes (mhd_profile)
   bool prof = false;
   std::vector<std::pair<int, hipEvent_t>> marks;
@@ -93,6 +95,32 @@ static int prof_fold(mhd_ctx* c) {
 }
 
 static std::string g_init_err;
+
+// The static scratch of mhd_rhs_noalloc (mhd.h): the stage workspace, the
+// per-plane tables and the queue counters of one call, for callers that
+// cannot allocate.  Each device that loads the library holds its own copy
+// until the process ends.  Host code never uses this name as an address:
+// scratch_address() gives each device's copy through hipGetSymbolAddress.
+static constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+// This device's address of `scratch` (the device must be current),
+// resolved once per device.
+static hipError_t scratch_address(int dev, void** out) {
+  static std::mutex mu;
+  static std::vector<void*> addr;
+  std::lock_guard<std::mutex> lock(mu);
+  if (dev < 0) return hipErrorInvalidDevice;
+  if ((int)addr.size() <= dev) addr.resize(dev + 1, nullptr);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[dev] = p;
+  }
+  *out = addr[dev];
+  return hipSuccess;
+}
 
 static const double kAlpha[3] = {0.0, -0.641874, -1.31021};   // eq. tconst
 static const double kBeta[3] = {0.46173, 0.924087, 0.390614};
@@ -182,15 +210,32 @@ static Launch make_launch(const mhd_ctx* c) {
   return L;
 }
 
-template <class T> static ZWork<T> make_zwork(const mhd_ctx* c) {
-  ZWork<T> w;
-  w.base = static_cast<T*>(c->work);
-  w.stride = c->nelem;
-  w.lnpav = static_cast<T*>(c->d_lnpav);
-  return w;
+// Per-call device scratch of the stage kernels: the stage workspace, the
+// per-plane tables and the persistent mode's queue counters.  Normally the
+// context's own allocations; mhd_rhs_noalloc places them in the static
+// array `scratch` instead.
+struct Scratch {
+  void* work;
+  void* lnavg;
+  void* lnpav;
+  double* lnpart;
+  int* queue;
+};
+
+static Scratch own_scratch(const mhd_ctx* c) {
+  return Scratch{c->work, c->d_lnavg, c->d_lnpav, c->d_lnpart, c->d_queue};
 }
 
-static ZLaunch make_zlaunch(const mhd_ctx* c) {
+template <class T> static ZWork<T> make_zwork(const mhd_ctx* c, const Scratch& s) {
+  ZWork<T> w;
+  w.base = static_cast<T*>(s.work);
+  w.stride = c->nelem;
+  w.lnpav = static_cast<T*>(s.lnpav);
+  return w;
+}
+template <class T> static ZWork<T> make_zwork(const mhd_ctx* c) { return make_zwork<T>(c, own_scratch(c)); }
+
+static ZLaunch make_zlaunch(const mhd_ctx* c, const Scratch& s) {
   ZLaunch L;
   L.boxes = c->d_boxes;
   L.items = c->d_items;
@@ -199,7 +244,7 @@ static ZLaunch make_zlaunch(const mhd_ctx* c) {
   L.fitems = c->d_fitems;
   L.nfitems = c->nfitems;
   L.ftile = c->ftile;
-  L.queue = c->d_queue;
+  L.queue = s.queue;
   L.persistent = c->persistent;
   L.ncu = c->ncu;
   L.nbox = (int)c->h_boxes.size();
@@ -209,6 +254,7 @@ static ZLaunch make_zlaunch(const mhd_ctx* c) {
   L.mark_ctx = const_cast<mhd_ctx*>(c);
   return L;
 }
+static ZLaunch make_zlaunch(const mhd_ctx* c) { return make_zlaunch(c, own_scratch(c)); }
 
 // Work items of the z-march kernels: tiles of TX x TY columns, z split into
 // chunks of about kZChunk planes (each chunk recomputes a few planes of
@@ -439,6 +485,9 @@ int mhd_init(const mhd_params* p, void* hip_stream, mhd_ctx** out) {
   c->esize = p->dtype == MHD_F32 ? sizeof(float) : sizeof(double);
   c->stream = static_cast<hipStream_t>(hip_stream);
   (void)hipGetDevice(&c->device);
+  // the static scratch of mhd_rhs_noalloc; without it that call reports the
+  // error and every other call works as usual
+  if (scratch_address(c->device, &c->scratch) != hipSuccess) c->scratch = nullptr;
   if (hipDeviceGetAttribute(&c->ncu, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess ||
       c->ncu < 1)
     c->ncu = 1;
@@ -574,9 +623,9 @@ int mhd_init(const mhd_params* p, void* hip_stream, mhd_ctx** out) {
 
 // ---------------------------------------------------------------------------
 template <class T>
-static ZStageArgs<T> zargs(mhd_ctx* c) {
+static ZStageArgs<T> zargs(mhd_ctx* c, const Scratch& s) {
   ZStageArgs<T> a;
-  a.w = make_zwork<T>(c);
+  a.w = make_zwork<T>(c, s);
   a.ph = make_phys<T>(c->p);
   a.du = p8null<T>();
   a.du_mode = 0;
@@ -587,23 +636,24 @@ static ZStageArgs<T> zargs(mhd_ctx* c) {
   a.dt_host = 0.0;
   a.cpart = nullptr;
   a.ztab = static_cast<const T*>(c->d_ztab);
-  a.lnavg = static_cast<T*>(c->d_lnavg);
-  a.lnpart = c->d_lnpart;
+  a.lnavg = static_cast<T*>(s.lnavg);
+  a.lnpart = s.lnpart;
   a.Cdt = c->p.Cdt;
   a.Cdtd = c->p.Cdtd;
   a.nuB = c->p.nuB;
   a.eta_const = c->p.eta_const;
   return a;
 }
+template <class T> static ZStageArgs<T> zargs(mhd_ctx* c) { return zargs<T>(c, own_scratch(c)); }
 
 template <class T>
-static int do_rhs(mhd_ctx* c, void* const f[8], void* const dfdt[8]) {
+static int do_rhs(mhd_ctx* c, void* const f[8], void* const dfdt[8], const Scratch& s) {
   const Launch L = make_launch(c);
   launch_ghost<T>(L, p8<T>(f));
-  ZStageArgs<T> a = zargs<T>(c);
+  ZStageArgs<T> a = zargs<T>(c, s);
   a.f = cp8<T>(f);
   a.du = p8<T>(dfdt);
-  launch_zstage<T>(make_zlaunch(c), a);
+  launch_zstage<T>(make_zlaunch(c, s), a);
   return check_launch(c, "mhd_rhs launch");
 }
 
@@ -852,7 +902,41 @@ int mhd_rhs(mhd_ctx* c, void* const f[8], void* const dfdt[8]) {
   for (int a = 0; a < 8; ++a)
     for (int b = 0; b < 8; ++b)
       if (f[a] == dfdt[b]) return fail(c, MHD_EINVAL, "f and dfdt overlap");
-  return c->p.dtype == MHD_F32 ? do_rhs<float>(c, f, dfdt) : do_rhs<double>(c, f, dfdt);
+  return c->p.dtype == MHD_F32 ? do_rhs<float>(c, f, dfdt, own_scratch(c))
+                               : do_rhs<double>(c, f, dfdt, own_scratch(c));
+}
+
+// Layout of a context's per-call scratch inside the static array: returns
+// the bytes it needs, and fills *s only when they fit.
+static size_t static_layout(const mhd_ctx* c, Scratch* s) {
+  auto a256 = [](size_t n) { return (n + 255) & ~size_t(255); };
+  const size_t work = a256((size_t)kWorkArrays * c->nelem * c->esize);
+  const size_t tab = a256(c->esize * (size_t)c->nplanes);
+  const size_t part = a256(sizeof(double) * kPlaneSlices * (size_t)c->nplanes);
+  const size_t need = work + 2 * tab + part + a256(sizeof(int) * kQueueInts);
+  if (s && c->scratch && need <= kScratchBytes) {
+    char* b = static_cast<char*>(c->scratch);
+    *s = Scratch{b, b + work, b + work + tab, reinterpret_cast<double*>(b + work + 2 * tab),
+                 reinterpret_cast<int*>(b + work + 2 * tab + part)};
+  }
+  return need;
+}
+
+int mhd_rhs_noalloc(mhd_ctx* c, void* const f[8], void* const dfdt[8]) {
+  if (!c) return fail(nullptr, MHD_EINVAL, "ctx is NULL");
+  int rc;
+  if ((rc = check8(c, f, "f")) || (rc = check8(c, dfdt, "dfdt"))) return rc;
+  for (int a = 0; a < 8; ++a)
+    for (int b = 0; b < 8; ++b)
+      if (f[a] == dfdt[b]) return fail(c, MHD_EINVAL, "f and dfdt overlap");
+  if (!c->scratch) return fail(c, MHD_EHIP, "mhd_rhs_noalloc: the static scratch is not available on this device");
+  Scratch s;
+  const size_t need = static_layout(c, &s);
+  if (need > kScratchBytes)
+    return fail(c, MHD_EINVAL, "mhd_rhs_noalloc: these boxes need " + std::to_string(need) +
+                                   " bytes of scratch, above the static limit of " +
+                                   std::to_string(kScratchBytes) + " bytes (use mhd_rhs)");
+  return c->p.dtype == MHD_F32 ? do_rhs<float>(c, f, dfdt, s) : do_rhs<double>(c, f, dfdt, s);
 }
 
 int mhd_step(mhd_ctx* c, void* const f[8], void* const t1[8], void* const t2[8],

@@ -19,7 +19,7 @@ __all__ = [
     "T_EDIFFAV", "T_LNP", "T_DIVB",
     "MhdBox", "MhdParams", "MhdStats", "MhdError", "lib_path", "load",
     "mhd_init", "mhd_destroy", "mhd_last_error", "mhd_field_elems",
-    "mhd_box_offset", "mhd_rhs", "mhd_step", "mhd_step_adjoint",
+    "mhd_box_offset", "mhd_rhs", "mhd_rhs_noalloc", "mhd_step", "mhd_step_adjoint",
     "mhd_reductions", "mhd_profile", "mhd_profile_read", "mhd_last_dt", "mhd_set_tile",
     "mhd_set_launch", "mhd_get_launch", "mhd_set_final_tile", "mhd_get_final_tile",
     "mhd_autotune", "mhd_rhs_adjoint",
@@ -122,6 +122,8 @@ def load():
     L.mhd_box_offset.restype = i64
     L.mhd_rhs.argtypes = [vp, _P8, _P8]
     L.mhd_rhs.restype = ctypes.c_int
+    L.mhd_rhs_noalloc.argtypes = [vp, _P8, _P8]
+    L.mhd_rhs_noalloc.restype = ctypes.c_int
     L.mhd_step.argtypes = [vp, _P8, _P8, _P8, _P8, ctypes.c_double, i32]
     L.mhd_step.restype = ctypes.c_int
     L.mhd_step_adjoint.argtypes = [vp, _P8, ctypes.c_double, _P8, _P8]
@@ -200,6 +202,10 @@ def _ptrs(ts, n, dtype, name):
 
 def mhd_rhs(ctx, f, dfdt, *, dtype, n):
     _check(load().mhd_rhs(ctx, _ptrs(f, n, dtype, "f"), _ptrs(dfdt, n, dtype, "dfdt")), ctx)
+
+
+def mhd_rhs_noalloc(ctx, f, dfdt, *, dtype, n):
+    _check(load().mhd_rhs_noalloc(ctx, _ptrs(f, n, dtype, "f"), _ptrs(dfdt, n, dtype, "dfdt")), ctx)
 
 
 def mhd_step(ctx, f, tmp1, tmp2, du, dt, nsteps, *, dtype, n):
@@ -379,6 +385,12 @@ class Context:
     def rhs(self, f, dfdt=None):
         dfdt = dfdt if dfdt is not None else self.empty()
         mhd_rhs(self.ctx, f, dfdt, dtype=self.dtype, n=self.n)
+        return dfdt
+
+    def rhs_noalloc(self, f, dfdt):
+        """mhd_rhs_noalloc: dfdt (caller-allocated) = F(f), with the call's
+        scratch in the library's static device array."""
+        mhd_rhs_noalloc(self.ctx, f, dfdt, dtype=self.dtype, n=self.n)
         return dfdt
 
     def step(self, f, dt, nsteps=1, work=None):
