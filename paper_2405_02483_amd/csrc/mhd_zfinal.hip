@@ -1,0 +1,621 @@
+// Pass F of an RK stage: every divergence of the stage's edge, centre and
+// face quantities and of the momenta, gravity, the wall masking and the
+// fused RK stage update (eqs. mass, mom, ien, indu; eqs. ddt, tupdate).
+//
+// x/y divergences of plane r read LDS strips; z divergences are scattered
+// into per-thread accumulators of output planes r-3..r+3 (first differences
+// for derivatives), and plane r-3 is then complete.
+//
+// Two ways to obtain pass P's in-plane quantities (z-edge, centre and x/y
+// face terms; mhd_zstage.hpp):
+//   stored (PIN false): pass P wrote them to the stage workspace and the
+//     launches of F read them back as strips (one launch per field group);
+//   inline (PIN true): one launch for all fields forms them itself, in LDS,
+//     on the strips its divergences need (a halo of 3 around the tile),
+//     from planes of the state and of ln <nu> with a halo of 5 (8 for rho
+//     and ln <nu>); pass P is not launched.  This trades recomputation on
+//     the halo for the 13 workspace arrays pass P would write and F read.
+// Both evaluate the same point functions, so they give the same bits.
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <utility>
+
+#include "mhd_zmarch.hpp"
+#include "mhd_zstage.hpp"
+
+namespace smhd {
+
+// the field each LDS strip serves, in F's strip order: x strips, y strips
+__device__ constexpr int kXOwn[9] = {0, 1, 2, 2, 4, 3, 3, 7, 4};
+__device__ constexpr int kYOwn[9] = {0, 1, 1, 2, 4, 3, 3, 7, 4};
+constexpr int kXOwnH[9] = {0, 1, 2, 2, 4, 3, 3, 7, 4};
+constexpr int kYOwnH[9] = {0, 1, 1, 2, 4, 3, 3, 7, 4};
+// LDS position of strip q among the strips a launch loads (own: kXOwnH or
+// kYOwnH); q = 9 gives their number
+template <unsigned FM>
+__host__ __device__ constexpr int strip_slot(const int (&own)[9], int q) {
+  int n = 0;
+  for (int i = 0; i < q; ++i) n += (FM >> own[i]) & 1u;
+  return n;
+}
+__host__ __device__ constexpr int at_least1(int n) { return n > 0 ? n : 1; }
+
+// LDS layout of the inline mode for a TX x TY tile (element counts).
+template <int TX, int TY> struct PinLayout {
+  using B8 = Plane<TX, TY, 8>;      // rho, ln <nu>
+  using B5 = Plane<TX, TY, 5>;      // the state; derived planes
+  using B3 = Plane<TX, TY, 3>;      // pass P's quantities
+  using PXs = Plane<TX, TY, 3, 0>;  // x strips of pass Q's quantities
+  using PYs = Plane<TX, TY, 0, 3>;  // y strips
+  static constexpr int NIN5 = 7;    // px py e bx by D pz
+  static constexpr int NDER = 9;    // ux uy rxd ryd xl nu em lem lq
+  static constexpr int NPQ = 10;    // Gxx Gyx Lyz Hx | Gxy Lxz Gyy Hy | Qz Ez
+  static constexpr int IN8 = 2 * B8::NP;
+  static constexpr int IN5 = NIN5 * B5::NP;
+  static constexpr int QS = 4 * PXs::NP + 4 * PYs::NP;
+  static constexpr int DER = NDER * B5::N > QS ? NDER * B5::N : QS;   // Q strips alias the derived planes
+  static constexpr int PQ = NPQ * B3::N;
+  static constexpr int DB = PXs::NP + PYs::NP;                          // x/y strips of div B
+  template <class T> static constexpr size_t bytes() { return sizeof(T) * size_t(IN8 + IN5 + DER + PQ + DB); }
+};
+constexpr size_t kLdsMax = 160 * 1024;
+template <class T, int TX, int TY> constexpr bool pin_fits() {
+  return PinLayout<TX, TY>::template bytes<T>() + 1024 <= kLdsMax;
+}
+
+template <class T, int TX, int TY, bool PERS, unsigned FM, bool PIN>
+__global__ __launch_bounds__(TX * TY) void zF(const BoxDev* __restrict__ boxes,
+                                              const ZItem* __restrict__ items, int nitems,
+                                              const T* __restrict__ ztab, int* __restrict__ queue,
+                                              CP8<T> f, ZWork<T> ws, Phys<T> ph, P8<T> du,
+                                              int du_mode, P8<T> f_out, T alpha, double beta,
+                                              const double* __restrict__ dt_dev, double dt_host) {
+  static_assert(!PIN || (FM & 0xFFu) == 0xFFu, "the inline mode completes every field in one launch");
+  constexpr int NT = TX * TY;
+  using PXs = Plane<TX, TY, 3, 0>;   // x-halo strips
+  using PYs = Plane<TX, TY, 0, 3>;   // y-halo strips
+  using P3 = Plane<TX, TY, 3>;
+  using LY = PinLayout<TX, TY>;
+  using B8 = typename LY::B8;
+  using B5 = typename LY::B5;
+  using B3 = typename LY::B3;
+  // x strips: 0 px 1 Gxx 2 Gyx 3 Lyz 4 Hx 5 Gzx 6 Lzy 7 Ey 8 Qy
+  // y strips: 0 py 1 Gxy 2 Lxz 3 Gyy 4 Hy 5 Gzy 6 Lzx 7 Ex 8 Qx
+  // full:     0 Qz 1 Ez
+  constexpr bool kQz = hasf<FM>(4), kEz = hasf<FM>(5) || hasf<FM>(6);
+  // Coriolis force (bit 8 of FM; its in-plane parts come with the face
+  // pressure gradients): x strips of px and pz, y strips of py and pz
+  constexpr bool kCori = hasf<FM>(8);
+  // div B diffusion (with the B_x launch): x and y strips of div B
+  constexpr bool kDB = hasf<FM>(5);
+  // stored mode: only the strips of this launch's fields occupy LDS
+  constexpr int NSX = PIN ? 1 : at_least1(strip_slot<FM>(kXOwnH, 9)) * PXs::NP;
+  constexpr int NSY = PIN ? 1 : at_least1(strip_slot<FM>(kYOwnH, 9)) * PYs::NP;
+  constexpr int NS2 = PIN ? 1 : at_least1(int(kQz) + int(kEz)) * P3::NP;
+  __shared__ T sx[NSX];
+  __shared__ T sy[NSY];
+  __shared__ T s2[NS2];
+  __shared__ T sxc[(kCori && !PIN) ? 2 * PXs::NP : 1];
+  __shared__ T syc[(kCori && !PIN) ? 2 * PYs::NP : 1];
+  __shared__ T sdb[(kDB && !PIN) ? PXs::NP + PYs::NP : 1];
+  // inline mode
+  __shared__ T sIn8[PIN ? LY::IN8 : 1];
+  __shared__ T sIn5[PIN ? LY::IN5 : 1];
+  __shared__ T sDer[PIN ? LY::DER : 1];
+  __shared__ T sPQ[PIN ? LY::PQ : 1];
+  __shared__ T sDB[(kDB && PIN) ? LY::DB : 1];
+  ZLOOP_BEGIN
+  PlaneIdx<TX, TY, 3, 0> ix;
+  PlaneIdx<TX, TY, 0, 3> iy;
+  ix.init(b, it.x0, it.y0);
+  iy.init(b, it.x0, it.y0);
+  const unsigned tm = ph.terms;
+  const bool cont = tm & T_CONT, grav = tm & T_GRAV;
+  const T inv_mu = ph.inv_mu;
+  const double dt = dt_dev ? *dt_dev : dt_host;
+  const T bdt = T(beta * dt);
+  // div B diffusion C_divb h^2 / dt grad(div B); absent without a time step
+  const T kd = (kDB && dt > 0.0) ? T(double(ph.c_divb) * double(g.h) * double(g.h) / dt) : T(0);
+
+  // ---- accessors of the inline mode
+  auto IN8 = [&](int q, int x, int y) -> T { return sIn8[q * B8::NP + B8::at(x, y)]; };   // 0 rho 1 ln nu
+  auto IN5 = [&](int q, int x, int y) -> T { return sIn5[q * B5::NP + B5::at(x, y)]; };   // px py e bx by D pz
+  auto DER = [&](int q, int x, int y) -> T& { return sDer[q * B5::N + B5::at(x, y)]; };   // ux uy rxd ryd xl nu em lem lq
+  auto PQ = [&](int q, int x, int y) -> T& { return sPQ[q * B3::N + B3::at(x, y)]; };
+  auto SA = [&](int q, int x, int y) -> T {
+    switch (q) {
+      case DQ_PX: return IN5(0, x, y);
+      case DQ_PY: return IN5(1, x, y);
+      case DQ_E: return IN5(2, x, y);
+      case DQ_BX: return IN5(3, x, y);
+      case DQ_BY: return IN5(4, x, y);
+      case DQ_LNT: return IN8(1, x, y);
+      case DQ_UX: return DER(0, x, y);
+      case DQ_UY: return DER(1, x, y);
+      case DQ_RXD: return DER(2, x, y);
+      case DQ_RYD: return DER(3, x, y);
+      case DQ_XL: return DER(4, x, y);
+      case DQ_NU: return DER(5, x, y);
+      case DQ_EM: return DER(6, x, y);
+      case DQ_LEM: return DER(7, x, y);
+      case DQ_LQ: return DER(8, x, y);
+      case DQ_RHO: return IN8(0, x, y);
+      default: return IN5(5, x, y);   // DQ_D
+    }
+  };
+  T* const qsx = sDer;                        // Q strips, inline mode (alias the derived planes)
+  T* const qsy = sDer + 4 * PXs::NP;
+
+  // ---- strip accessors of the divergences (both modes)
+  auto X = [&](int q, int x) -> T {
+    if constexpr (PIN) {
+      if (q == 0) return IN5(0, x, ty);
+      if (q <= 4) return PQ(q - 1, x, ty);
+      return qsx[(q - 5) * PXs::NP + PXs::at(x, ty)];
+    } else {
+      return sx[strip_slot<FM>(kXOwnH, q) * PXs::NP + PXs::at(x, ty)];
+    }
+  };
+  auto Y = [&](int q, int y) -> T {
+    if constexpr (PIN) {
+      if (q == 0) return IN5(1, tx, y);
+      if (q <= 4) return PQ(q + 3, tx, y);
+      return qsy[(q - 5) * PYs::NP + PYs::at(tx, y)];
+    } else {
+      return sy[strip_slot<FM>(kYOwnH, q) * PYs::NP + PYs::at(tx, y)];
+    }
+  };
+  auto F2 = [&](int q, int x, int y) -> T {
+    if constexpr (PIN) return PQ(8 + q, x, y);
+    else return s2[(q && kQz) * P3::NP + P3::at(x, y)];
+  };
+  auto XC = [&](int q, int x) -> T {   // 0 px 1 pz
+    if constexpr (PIN) return IN5(q ? 6 : 0, x, ty);
+    else return sxc[q * PXs::NP + PXs::at(x, ty)];
+  };
+  auto YC = [&](int q, int y) -> T {   // 0 py 1 pz
+    if constexpr (PIN) return IN5(q ? 6 : 1, tx, y);
+    else return syc[q * PYs::NP + PYs::at(tx, y)];
+  };
+  T* const dbx = PIN ? sDB : sdb;
+  auto DBX = [&](int x) -> T { return dbx[PXs::at(x, ty)]; };
+  auto DBY = [&](int y) -> T { return dbx[PXs::NP + PYs::at(tx, y)]; };
+
+  T acc[7][7];
+#pragma unroll
+  for (int a = 0; a < 7; ++a)
+#pragma unroll
+    for (int s = 0; s < 7; ++s) acc[a][s] = T(0);
+  // previous-plane values of the z-differentiated quantities (first
+  // differences): 0 pz 1 Gxz 2 Gyz 3 Gzz 4 Hz 5 Ey 6 Ex
+  T prev[7];
+#pragma unroll
+  for (int a = 0; a < 7; ++a) prev[a] = T(0);
+
+  // wall masking (Section 10): F vanishes in ghost planes, and for pz also
+  // on the two wall faces; Bz evolves on the wall faces
+  auto masked = [&](int v, int k, T Fv) -> T {
+    if (!wall) return Fv;
+    const bool cen = k >= b.g0 && k < b.g1;
+    const bool keep = v == 3 ? (k > b.g0 && k < b.g1) : (v == 7 ? (k >= b.g0 && k <= b.g1) : cen);
+    return keep ? Fv : T(0);
+  };
+  // RK stage update of one field at plane k, given its dU and f there
+  auto update = [&](int v, long long o, T Fv, T uin, T fin) {
+    const T U = (du_mode & DU_READ) ? alpha * uin + Fv : Fv;
+    if (du_mode & DU_WRITE) du.p[v][o] = U;
+    f_out.p[v][o] = fin + bdt * U;
+  };
+  // the seven z-accumulated fields at plane k: every load first, so they
+  // share one round trip to memory
+  auto finalize7 = [&](int k) {
+    const long long o = col(k);
+    T Fv[7];
+#pragma unroll
+    for (int a = 0; a < 7; ++a) Fv[a] = masked(a, k, acc[a][0]);
+    if (f_out.p[0] == nullptr) {
+#pragma unroll
+      for (int a = 0; a < 7; ++a)
+        if (hasf<FM>(a)) du.p[a][o] = Fv[a];
+      return;
+    }
+    T uin[7], fin[7];
+#pragma unroll
+    for (int a = 0; a < 7; ++a) {
+      uin[a] = T(0);
+      fin[a] = T(0);
+      if (hasf<FM>(a)) {
+        uin[a] = (du_mode & DU_READ) ? du.p[a][o] : T(0);
+        fin[a] = f.p[a][o];
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < 7; ++a)
+      if (hasf<FM>(a)) update(a, o, Fv[a], uin[a], fin[a]);
+  };
+
+  // inline mode: plane indices of the state's LDS planes
+  PlaneIdx<TX, TY, 8> i8;
+  PlaneIdx<TX, TY, 5> i5;
+  if constexpr (PIN) {
+    i8.init(b, it.x0, it.y0);
+    i5.init(b, it.x0, it.y0);
+  }
+  PlaneIdx<TX, TY, 3> i3;
+  if constexpr (!PIN) i3.init(b, it.x0, it.y0);
+  constexpr int NPX = PXs::NP / NT, NPY = PYs::NP / NT;
+
+  for (int r = it.z0 - 3; r <= it.z1 + 2; ++r) {
+    const int kb = r - 3;
+    const bool inch = r >= it.z0 && r < it.z1;
+    if (valid(r)) {
+      const int k = kk(r);
+      const long long o = col(r);
+      const int x = tx, y = ty;
+      __syncthreads();
+      // ---- loads of plane r
+      // pass Q's strips (inline mode: into registers, stored to LDS once the
+      // derived planes they alias are no longer read)
+      const T* qxs[4] = {ws.q(QOUT_GZX), ws.q(QOUT_LZY), ws.q(QOUT_EY), ws.q(QOUT_QY)};
+      const T* qys[4] = {ws.q(QOUT_GZY), ws.q(QOUT_LZX), ws.q(QOUT_EX), ws.q(QOUT_QX)};
+      T rqx[4][PIN ? NPX : 1], rqy[4][PIN ? NPY : 1];
+      if constexpr (PIN) {
+        const long long pb = b.off + (long long)k * b.nx * b.ny;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if (!inch && q < 3) continue;   // only Qy, Qx outside the own planes
+#pragma unroll
+          for (int i = 0; i < NPX; ++i) rqx[q][i] = qxs[q][pb + ix.off[i]];
+#pragma unroll
+          for (int i = 0; i < NPY; ++i) rqy[q][i] = qys[q][pb + iy.off[i]];
+        }
+        if (inch) {
+          load_plane(sIn8, f.p[0], b, i8, k);
+          load_plane(sIn8 + B8::NP, ws.arr(WS_LNT), b, i8, k);
+          const T* in5[6] = {f.p[1], f.p[2], f.p[4], f.p[5], f.p[6], ws.arr(WS_D)};
+#pragma unroll
+          for (int q = 0; q < 6; ++q) load_plane(sIn5 + q * B5::NP, in5[q], b, i5, k);
+        }
+        if (kCori) {
+          if (!inch) {
+            load_plane(sIn5, f.p[1], b, i5, k);
+            load_plane(sIn5 + B5::NP, f.p[2], b, i5, k);
+          }
+          load_plane(sIn5 + 6 * B5::NP, f.p[3], b, i5, k);
+        }
+        if (kDB && kd != T(0)) {
+          load_plane(sDB, ws.arr(WS_DIVB), b, ix, k);
+          load_plane(sDB + PXs::NP, ws.arr(WS_DIVB), b, iy, k);
+        }
+      } else {
+        if (inch) {
+          const T* xs[8] = {f.p[1], ws.pq(POUT_GXX), ws.pq(POUT_GYX), ws.pq(POUT_LYZ),
+                            ws.pq(POUT_HX), qxs[0], qxs[1], qxs[2]};
+          const T* ys[8] = {f.p[2], ws.pq(POUT_GXY), ws.pq(POUT_LXZ), ws.pq(POUT_GYY),
+                            ws.pq(POUT_HY), qys[0], qys[1], qys[2]};
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            if (hasf<FM>(kXOwnH[q])) load_plane(sx + strip_slot<FM>(kXOwnH, q) * PXs::NP, xs[q], b, ix, k);
+            if (hasf<FM>(kYOwnH[q])) load_plane(sy + strip_slot<FM>(kYOwnH, q) * PYs::NP, ys[q], b, iy, k);
+          }
+          if (kQz) load_plane(s2, ws.pq(POUT_QZ), b, i3, k);
+          if (kEz) load_plane(s2 + kQz * P3::NP, ws.pq(POUT_EZ), b, i3, k);
+        }
+        if (hasf<FM>(4)) {
+          load_plane(sx + strip_slot<FM>(kXOwnH, 8) * PXs::NP, qxs[3], b, ix, k);
+          load_plane(sy + strip_slot<FM>(kYOwnH, 8) * PYs::NP, qys[3], b, iy, k);
+        }
+        if (kDB && kd != T(0)) {
+          load_plane(sdb, ws.arr(WS_DIVB), b, ix, k);
+          load_plane(sdb + PXs::NP, ws.arr(WS_DIVB), b, iy, k);
+        }
+        if constexpr (kCori) {
+          load_plane(sxc, f.p[1], b, ix, k);
+          load_plane(sxc + PXs::NP, f.p[3], b, ix, k);
+          load_plane(syc, f.p[2], b, iy, k);
+          load_plane(syc + PYs::NP, f.p[3], b, iy, k);
+        }
+      }
+      // own-column values of plane r for the z divergences
+      T cur[7];
+      const T* cols[7] = {f.p[3], ws.q(QOUT_GXZ), ws.q(QOUT_GYZ), ws.q(QOUT_GZZ), ws.q(QOUT_HZ),
+                          ws.q(QOUT_EY), ws.q(QOUT_EX)};
+#pragma unroll
+      for (int a = 0; a < 7; ++a) cur[a] = hasf<FM>(a) ? cols[a][o] : T(0);
+      const T lxy = hasf<FM>(1) ? ws.q(QOUT_LXY)[o] : T(0);
+      const T lyx = hasf<FM>(2) ? ws.q(QOUT_LYX)[o] : T(0);
+      const T rho_o = (hasf<FM>(3) && grav) ? f.p[0][o] : T(0);
+      // own-cell terms of the own planes
+      T dpx = T(0), dpy = T(0), qc = T(0), dpz = T(0), czz_ = T(0);
+      if (inch) {
+        if (hasf<FM>(3)) dpz = ws.q(QOUT_DPZ)[o];
+        if (hasf<FM>(4)) czz_ = ws.q(QOUT_CZZ)[o];
+        if constexpr (!PIN) {
+          if (hasf<FM>(1)) dpx = ws.pq(POUT_DPX)[o];
+          if (hasf<FM>(2)) dpy = ws.pq(POUT_DPY)[o];
+          if (hasf<FM>(4)) qc = ws.pq(POUT_QC)[o];
+        }
+      }
+      // Bz's dU and f at this plane, fetched with the planes
+      T bz_u = T(0), bz_f = T(0);
+      if (hasf<FM>(7) && inch && own && f_out.p[0] != nullptr) {
+        if (du_mode & DU_READ) bz_u = du.p[7][o];
+        bz_f = f.p[7][o];
+      }
+      __syncthreads();
+      if constexpr (PIN) {
+        if (inch) {
+          // ---- derived planes over the halo-5 box
+          const T lpa = (tm & T_LNP) ? ws.lnpav[b.poff + k] : T(0);
+          for (int t = threadIdx.x; t < B5::N; t += NT) {
+            const int yy = t / B5::W, xx = t - yy * B5::W;
+            const int xq = xx - 5, yq = yy - 5;
+            const T rxd = op6<0, 0, T>([&](int m) { return IN8(0, xq + m, yq); }, T(0));
+            const T ryd = op6<0, 0, T>([&](int m) { return IN8(0, xq, yq + m); }, T(0));
+            sDer[0 * B5::N + t] = IN5(0, xq, yq) / rxd;
+            sDer[1 * B5::N + t] = IN5(1, xq, yq) / ryd;
+            sDer[2 * B5::N + t] = rxd;
+            sDer[3 * B5::N + t] = ryd;
+            sDer[4 * B5::N + t] = op6<0, 0, T>([&](int m) { return IN8(1, xq + m, yq); }, T(0));
+            sDer[5 * B5::N + t] = exp(IN8(1, xq, yq));
+            const T emv = IN5(2, xq, yq) / IN8(0, xq, yq);
+            sDer[6 * B5::N + t] = emv;
+            sDer[7 * B5::N + t] = log(emv);
+            if (tm & T_LNP) sDer[8 * B5::N + t] = log(ph.gamma1 * IN5(2, xq, yq)) - lpa;
+          }
+          __syncthreads();
+          // ---- pass P's quantities: z-edge and face terms on the box
+          // [-2, TX+3) x [-2, TY+3), centre terms on [-3, TX+2) x [-3, TY+2)
+          constexpr int WE = TX + 5, NE = (TX + 5) * (TY + 5);
+          for (int t = threadIdx.x; t < NE; t += NT) {
+            const int yy = t / WE, xx = t - yy * WE;
+            const int xq = xx - 2, yq = yy - 2;
+            T gxy, gyx, ez, lxz, lyz, qz;
+            zedge_q<T>(SA, xq, yq, g, ph, gxy, gyx, ez, lxz, lyz, qz);
+            PQ(1, xq, yq) = gyx;
+            PQ(2, xq, yq) = lyz;
+            PQ(3, xq, yq) = xface_h<T>(SA, xq, yq, g, ph);
+            PQ(4, xq, yq) = gxy;
+            PQ(5, xq, yq) = lxz;
+            PQ(7, xq, yq) = yface_h<T>(SA, xq, yq, g, ph);
+            PQ(8, xq, yq) = qz;
+            PQ(9, xq, yq) = ez;
+          }
+          constexpr int WC = TX + 5, NC = (TX + 5) * (TY + 5);
+          for (int t = threadIdx.x; t < NC; t += NT) {
+            const int yy = t / WC, xx = t - yy * WC;
+            const int xq = xx - 3, yq = yy - 3;
+            T gxx, gyy, qcx;
+            centre_q<T>(SA, xq, yq, g, ph, gxx, gyy, qcx);
+            PQ(0, xq, yq) = gxx;
+            PQ(6, xq, yq) = gyy;
+          }
+          if (own) {
+            T gxx, gyy;
+            centre_q<T>(SA, x, y, g, ph, gxx, gyy, qc);
+            face_dp<T>(SA, x, y, g, ph, (tm & T_LNP) ? T(exp(lpa)) : T(0), dpx, dpy);
+          }
+        }
+        __syncthreads();
+        // ---- pass Q's strips into LDS (over the derived planes)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if (!inch && q < 3) continue;
+#pragma unroll
+          for (int i = 0; i < NPX; ++i) qsx[q * PXs::NP + (int)threadIdx.x + i * NT] = rqx[q][i];
+#pragma unroll
+          for (int i = 0; i < NPY; ++i) qsy[q * PYs::NP + (int)threadIdx.x + i * NT] = rqy[q][i];
+        }
+        __syncthreads();
+      }
+      if (inch) {
+        if (hasf<FM>(0) && cont)
+          acc[0][3] += -(op6<1, 1, T>([&](int m) { return X(0, x + m); }, g.hxi) +
+                         op6<1, 1, T>([&](int m) { return Y(0, y + m); }, g.hyi));
+        if (hasf<FM>(1))
+          acc[1][3] += op6<1, 0, T>([&](int m) { return X(1, x + m); }, g.hxi) +
+                       op6<1, 1, T>([&](int m) { return Y(1, y + m); }, g.hyi) -
+                       op6<0, 1, T>([&](int m) { return Y(2, y + m); }, T(0)) * inv_mu - dpx;
+        if (hasf<FM>(2))
+          acc[2][3] += op6<1, 0, T>([&](int m) { return Y(3, y + m); }, g.hyi) +
+                       op6<1, 1, T>([&](int m) { return X(2, x + m); }, g.hxi) +
+                       op6<0, 1, T>([&](int m) { return X(3, x + m); }, T(0)) * inv_mu - dpy;
+        if (hasf<FM>(3)) {
+          acc[3][3] -= dpz;
+          acc[3][3] += op6<1, 1, T>([&](int m) { return X(5, x + m); }, g.hxi) +
+                       op6<1, 1, T>([&](int m) { return Y(5, y + m); }, g.hyi) +
+                       (op6<0, 1, T>([&](int m) { return Y(6, y + m); }, T(0)) -
+                        op6<0, 1, T>([&](int m) { return X(6, x + m); }, T(0))) * inv_mu;
+        }
+        if (hasf<FM>(4))
+          acc[4][3] += qc + czz_ +
+                       op6<1, 1, T>([&](int m) { return X(4, x + m); }, g.hxi) +
+                       op6<1, 1, T>([&](int m) { return Y(4, y + m); }, g.hyi) +
+                       op6<0, 1, T>([&](int m) {
+                         return op6<0, 1, T>([&](int a) { return F2(0, x + a, y + m); }, T(0));
+                       }, T(0));
+        // Newtonian cooling (eq. NewtonCool, eq. rhocool) at the cell centre
+        if (hasf<FM>(4) && (tm & T_COOL)) {
+          const T rc = f.p[0][o], ec = f.p[4][o];
+          T q = -rc * (ec / rc - ph.e_cool) * ph.inv_tcool;
+          if (ph.cool_cut) {
+            const T rr = rc * ph.inv_rho_cool, r2 = rr * rr;
+            q = q * ((ph.cool_cut == 1 ? r2 : T(1)) / (T(1) + r2));
+          }
+          acc[4][3] += q;
+        }
+        if (hasf<FM>(5)) acc[5][3] += -op6<1, 1, T>([&](int m) { return F2(1, x, y + m); }, g.hyi);
+        if (hasf<FM>(6)) acc[6][3] += op6<1, 1, T>([&](int m) { return F2(1, x + m, y); }, g.hxi);
+        if (kDB && kd != T(0)) {
+          acc[5][3] += kd * op6<1, 0, T>([&](int m) { return DBX(x + m); }, g.hxi);
+          acc[6][3] += kd * op6<1, 0, T>([&](int m) { return DBY(y + m); }, g.hyi);
+        }
+        // Bz has no z divergence: complete at once
+        if (hasf<FM>(7) && own) {
+          T fbz = -(op6<1, 1, T>([&](int m) { return X(7, x + m); }, g.hxi) -
+                    op6<1, 1, T>([&](int m) { return Y(7, y + m); }, g.hyi));
+          if (kd != T(0)) {
+            // z part of grad(div B) on this z-face, from the own column
+            const T* __restrict__ dbg = ws.arr(WS_DIVB);
+            T w[6];
+#pragma unroll
+            for (int m = 0; m < 6; ++m) w[m] = valid(r - 3 + m) ? dbg[col(r - 3 + m)] : T(0);
+            fbz += kd * zwin<1, 0, 6, 3>(w, r, wall, N, g.hzi, zt);
+          }
+          const T F7 = masked(7, r, fbz);
+          if (f_out.p[0] == nullptr) du.p[7][o] = F7;
+          else update(7, o, F7, bz_u, bz_f);
+        }
+      }
+      // Coriolis force (eq. mom): -2 Omega x p, each component on its own
+      // face; the parts that end with an interpolation along z, scattered
+      // below (the in-plane parts arrive with the face pressure gradients)
+      T czx = T(0), czy = T(0), czz = T(0);
+      if constexpr (kCori) {
+        const T wx = ph.cor2[0], wy = ph.cor2[1];
+        czx = -wy * op6<0, 0, T>([&](int m) { return XC(1, x + m); }, T(0));
+        czy = wx * op6<0, 0, T>([&](int n) { return YC(1, y + n); }, T(0));
+        czz = wy * op6<0, 1, T>([&](int m) { return XC(0, x + m); }, T(0)) -
+              wx * op6<0, 1, T>([&](int n) { return YC(0, y + n); }, T(0));
+      }
+      T xqy = T(0), yqx = T(0);
+      if (hasf<FM>(4)) {
+        xqy = op6<0, 1, T>([&](int m) { return X(8, x + m); }, T(0));
+        yqx = op6<0, 1, T>([&](int m) { return Y(8, y + m); }, T(0));
+      }
+      // ---- z divergences of plane r scattered into output planes r-3..r+3:
+      // derivatives through first differences, interpolations directly
+      T dl[7];
+#pragma unroll
+      for (int a = 0; a < 7; ++a) {
+        dl[a] = (cur[a] - prev[a]) * g.hzi;
+        prev[a] = cur[a];
+      }
+      if (hasf<FM>(0) && cont) zscatter_d<1, 3>(acc[0], kb, -dl[0], wall, N, zt);
+      if (hasf<FM>(1)) {
+        zscatter_d<1, 3>(acc[1], kb, dl[1], wall, N, zt);
+        zscatter<0, 1, 3>(acc[1], kb, lxy * inv_mu, wall, N, zt);
+        if constexpr (kCori) zscatter<0, 1, 3>(acc[1], kb, czx, wall, N, zt);
+      }
+      if (hasf<FM>(2)) {
+        zscatter_d<1, 3>(acc[2], kb, dl[2], wall, N, zt);
+        zscatter<0, 1, 3>(acc[2], kb, -lyx * inv_mu, wall, N, zt);
+        if constexpr (kCori) zscatter<0, 1, 3>(acc[2], kb, czy, wall, N, zt);
+      }
+      if (hasf<FM>(3)) {
+        zscatter_d<0, 3>(acc[3], kb, dl[3], wall, N, zt);
+        if (grav) zscatter<0, 0, 3>(acc[3], kb, -rho_o * ph.gz, wall, N, zt);
+        if constexpr (kCori) zscatter<0, 0, 3>(acc[3], kb, czz, wall, N, zt);
+      }
+      if (hasf<FM>(4)) {
+        zscatter_d<1, 3>(acc[4], kb, dl[4], wall, N, zt);
+        zscatter<0, 1, 3>(acc[4], kb, xqy, wall, N, zt);
+        zscatter<0, 1, 3>(acc[4], kb, yqx, wall, N, zt);
+      }
+      if (hasf<FM>(5)) zscatter_d<1, 3>(acc[5], kb, dl[5], wall, N, zt);
+      if (hasf<FM>(6)) zscatter_d<1, 3>(acc[6], kb, -dl[6], wall, N, zt);
+    } else {
+#pragma unroll
+      for (int a = 0; a < 7; ++a) prev[a] = T(0);
+    }
+    // ---- plane kb = r-3 is complete
+    if (own && valid(kb) && kb >= it.z0 && kb < it.z1) finalize7(kb);
+#pragma unroll
+    for (int a = 0; a < 7; ++a) {
+#pragma unroll
+      for (int s = 0; s < 6; ++s) acc[a][s] = acc[a][s + 1];
+      acc[a][6] = T(0);
+    }
+  }
+  ZLOOP_END
+}
+
+// ---------------------------------------------------------------------------
+// Launchers.
+// Workgroups of a kernel that fit on the device at once (cached per kernel).
+static int resident_groups(const void* kern, int block, int ncu) {
+  static std::mutex mu;
+  static std::map<const void*, int> cache;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = cache.find(kern);
+  if (it != cache.end()) return it->second;
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, block, 0) != hipSuccess || nb < 1) nb = 1;
+  return cache[kern] = nb * ncu;
+}
+
+int zresident_groups(const void* kern, int block, int ncu) { return resident_groups(kern, block, ncu); }
+
+template <class T, int TX, int TY, bool PERS, unsigned FM, bool PIN, class G>
+static void zF_one(const G& grid, dim3 block, const ZLaunch& L, const ZStageArgs<T>& a, int* q) {
+  hipLaunchKernelGGL((zF<T, TX, TY, PERS, FM, PIN>), grid((const void*)zF<T, TX, TY, PERS, FM, PIN>), block, 0,
+                     L.stream, L.boxes, L.fitems, L.nfitems, a.ztab, q, a.f, a.w, a.ph, a.du, a.du_mode, a.f_out,
+                     a.alpha, a.beta, a.dt_dev, a.dt_host);
+}
+// The momentum launch's mask with the Coriolis bit (8) set; others unchanged.
+template <unsigned FM> constexpr unsigned with_cori() { return (FM & 0x0Eu) ? (FM | 0x100u) : FM; }
+// stored mode: one launch per mask, each with its own 8 queue counters
+template <class T, int TX, int TY, bool PERS, class G, size_t... I>
+static void zF_launch(const G& grid, dim3 block, const ZLaunch& L, const ZStageArgs<T>& a, int* q,
+                      std::index_sequence<I...>) {
+  if (a.ph.terms & T_CORI)
+    (zF_one<T, TX, TY, PERS, with_cori<kFMasks[I]>(), false>(grid, block, L, a, q ? q + 32 + 8 * int(I) : q), ...);
+  else
+    (zF_one<T, TX, TY, PERS, kFMasks[I], false>(grid, block, L, a, q ? q + 32 + 8 * int(I) : q), ...);
+}
+
+// Pass F, in its own tile shape (L.ftile) over its own work items.
+template <class T, int TX, int TY, bool PERS>
+static bool launch_final_t(const ZLaunch& L, const ZStageArgs<T>& a, int* q) {
+  const int n = L.nfitems;
+  auto grid = [&](const void* kern) {
+    if (!q) return dim3(8 * ((n + 7) / 8));
+    const int r = std::min(n, resident_groups(kern, TX * TY, L.ncu));
+    return dim3(std::max(8, r - r % 8));
+  };
+  if (!L.fuse) {
+    zF_launch<T, TX, TY, PERS>(grid, dim3(TX * TY), L, a, q, std::make_index_sequence<kNFMasks>{});
+    return true;
+  }
+  if constexpr (pin_fits<T, TX, TY>()) {
+    if (a.ph.terms & T_CORI) zF_one<T, TX, TY, PERS, 0x1FFu, true>(grid, dim3(TX * TY), L, a, q ? q + 32 : q);
+    else zF_one<T, TX, TY, PERS, 0xFFu, true>(grid, dim3(TX * TY), L, a, q ? q + 32 : q);
+    return true;
+  }
+  return false;
+}
+
+template <class T, bool PERS>
+bool launch_final(const ZLaunch& L, const ZStageArgs<T>& a, int* q) {
+  switch (L.ftile) {
+    case ZTILE_32x8: return launch_final_t<T, 32, 8, PERS>(L, a, q);
+    case ZTILE_16x16: return launch_final_t<T, 16, 16, PERS>(L, a, q);
+    case ZTILE_16x8: return launch_final_t<T, 16, 8, PERS>(L, a, q);
+    case ZTILE_64x8: return launch_final_t<T, 64, 8, PERS>(L, a, q);
+    case ZTILE_32x16: return launch_final_t<T, 32, 16, PERS>(L, a, q);
+    default: return launch_final_t<T, 64, 4, PERS>(L, a, q);
+  }
+}
+
+bool final_fuse_ok(int tile, size_t esize) {
+  auto fits = [&](auto tag) -> bool {
+    using T = decltype(tag);
+    switch (tile) {
+      case ZTILE_32x8: return pin_fits<T, 32, 8>();
+      case ZTILE_16x16: return pin_fits<T, 16, 16>();
+      case ZTILE_16x8: return pin_fits<T, 16, 8>();
+      case ZTILE_64x8: return pin_fits<T, 64, 8>();
+      case ZTILE_32x16: return pin_fits<T, 32, 16>();
+      default: return pin_fits<T, 64, 4>();
+    }
+  };
+  return esize == sizeof(float) ? fits(float()) : fits(double());
+}
+
+template bool launch_final<float, false>(const ZLaunch&, const ZStageArgs<float>&, int*);
+template bool launch_final<float, true>(const ZLaunch&, const ZStageArgs<float>&, int*);
+template bool launch_final<double, false>(const ZLaunch&, const ZStageArgs<double>&, int*);
+template bool launch_final<double, true>(const ZLaunch&, const ZStageArgs<double>&, int*);
+
+}  // namespace smhd

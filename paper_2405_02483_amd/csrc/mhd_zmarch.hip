@@ -21,49 +21,9 @@
 #include <mutex>
 
 #include "mhd_zmarch.hpp"
-#include "mhd_zmarch_api.hpp"
+#include "mhd_zstage.hpp"
 
 namespace smhd {
-
-// Item loop of the stage kernels.  Grid mode (PERS false): one item
-// per workgroup, blockIdx mapped XCD-aware.  Persistent mode: a grid of about
-// one resident wave of workgroups; each pulls items from its XCD's queue
-// (queue[x] counts the items of range x taken) and, once that is empty,
-// from the other XCDs' ranges.  Results do not depend on the mode.
-#define ZLOOP_BEGIN                                                            \
-  __shared__ int snext_;                                                       \
-  for (int item_ = zfirst<PERS>(nitems, queue, &snext_); item_ < nitems;      \
-       item_ = znext<PERS>(nitems, queue, &snext_)) {                         \
-  const ZItem it = items[item_];                                               \
-  const BoxDev b = boxes[it.box];                                              \
-  const Geo<T> g(b);                                                           \
-  const int tx = (int)threadIdx.x % TX, ty = (int)threadIdx.x / TX;           \
-  const int gx = wrapm(it.x0 + tx, b.nx), gy = wrapm(it.y0 + ty, b.ny);      \
-  const bool own = (it.x0 + tx < b.nx) && (it.y0 + ty < b.ny);                \
-  const int N = b.nzt;                                                         \
-  const bool wall = b.wall != 0;                                               \
-  const long long colo = b.off + (long long)gy * b.nx + gx;                   \
-  const long long pstride = (long long)b.nx * b.ny;                           \
-  auto valid = [&](int r_) { return !wall || (r_ >= 0 && r_ < N); };          \
-  auto kk = [&](int r_) { return wall ? r_ : wrapm(r_, N); };                 \
-  auto col = [&](int r_) { return colo + (long long)kk(r_) * pstride; };      \
-  auto interior = [&](int r_) { return !wall || (r_ >= b.g0 && r_ < b.g1); };       \
-  const T* __restrict__ zt = wall ? ztab + b.zoff : nullptr;                         \
-  (void)zt;
-
-#define ZLOOP_END }
-
-// Block maximum of a double (all threads call; result valid in thread 0).
-template <int NT>
-__device__ __forceinline__ double block_max(double v, double* sh) {
-  sh[threadIdx.x] = v;
-  __syncthreads();
-  for (int s = NT / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
-    __syncthreads();
-  }
-  return sh[0];
-}
 
 // ---------------------------------------------------------------------------
 // A1: u_z = p_z / zdn(rho); div u; speed-like viscosity nu_s.
@@ -691,10 +651,6 @@ __global__ __launch_bounds__(TX * TY) void zP(const BoxDev* __restrict__ boxes,
   i6.init(b, it.x0, it.y0);
   i3.init(b, it.x0, it.y0);
   const unsigned tm = ph.terms;
-  const bool visc = tm & T_VISC, res = tm & T_RESIST, ind = tm & T_INDUCT, lor = tm & T_LORENTZ,
-             adv = tm & T_ADV, pres = tm & T_PRES, ediff = tm & T_EDIFF;
-  const bool need_nu = visc || (res && !(ph.eta_const > T(0)));
-  const T inv_mu = ph.inv_mu;
   auto S = [&](int q, int x, int y) -> T& { return s3[q * P3::NP + P3::at(x, y)]; };
   for (int k = it.z0; k < it.z1; ++k) {
     __syncthreads();
@@ -728,424 +684,32 @@ __global__ __launch_bounds__(TX * TY) void zP(const BoxDev* __restrict__ boxes,
     if (!own) continue;
     const int x = tx, y = ty;
     const long long o = colo + (long long)k * pstride;
-    // ---- z-edge (x-1/2, y-1/2)
-    T nxy = T(0), txy = T(0), sxy = T(0);
-    if (need_nu)
-      nxy = g.lxy * exp(op6<0, 0, T>([&](int m) { return S(13, x, y + m); }, T(0)));
-    if (visc) {
-      const T rxy = op6<0, 0, T>([&](int m) { return S(11, x, y + m); }, T(0));
-      sxy = T(0.5) * (op6<1, 0, T>([&](int m) { return S(6, x, y + m); }, g.hyi) +
-                      op6<1, 0, T>([&](int m) { return S(7, x + m, y); }, g.hxi));
-      txy = rxy * nxy * sxy;
-    }
-    const T jz = op6<1, 0, T>([&](int m) { return S(4, x + m, y); }, g.hxi) -
-                 op6<1, 0, T>([&](int m) { return S(3, x, y + m); }, g.hyi);
-    const T eta = ph.eta_const > T(0) ? ph.eta_const : ph.nuB * nxy;
-    const T xBY = op6<0, 0, T>([&](int m) { return S(4, x + m, y); }, T(0));
-    const T yBX = op6<0, 0, T>([&](int m) { return S(3, x, y + m); }, T(0));
-    const T yUX = op6<0, 0, T>([&](int m) { return S(6, x, y + m); }, T(0));
-    const T xUY = op6<0, 0, T>([&](int m) { return S(7, x + m, y); }, T(0));
-    T ez = T(0);
-    if (ind) ez = ez - (yUX * xBY - xUY * yBX);
-    if (res) ez = ez + eta * jz;
-    T gxy = txy, gyx = txy;
-    if (adv) {
-      gxy = gxy - op6<0, 0, T>([&](int m) { return S(0, x, y + m); }, T(0)) * xUY;
-      gyx = gyx - op6<0, 0, T>([&](int m) { return S(1, x + m, y); }, T(0)) * yUX;
-    }
-    T qz = visc ? T(2) * txy * sxy : T(0);
-    if (res) qz = qz + eta * jz * jz * inv_mu;
+    const T Dc = Dg[o];
+    const T lpa = (tm & T_LNP) ? lnpav[b.poff + k] : T(0);
+    // derived planes by id (mhd_zstage.hpp); ln(P / P_aver) on the fly
+    auto SA = [&](int q, int xx, int yy) -> T {
+      if (q == DQ_RHO) return sR[P6::at(xx, yy)];
+      if (q == DQ_D) return Dc;    // read at the own point only
+      if (q == DQ_LQ) return log(ph.gamma1 * S(DQ_E, xx, yy)) - lpa;
+      return S(q, xx, yy);
+    };
+    T gxy, gyx, ez, lxz, lyz, qz, gxx, gyy, qc, dpx, dpy;
+    zedge_q<T>(SA, x, y, g, ph, gxy, gyx, ez, lxz, lyz, qz);
+    centre_q<T>(SA, x, y, g, ph, gxx, gyy, qc);
+    face_dp<T>(SA, x, y, g, ph, (tm & T_LNP) ? T(exp(lpa)) : T(0), dpx, dpy);
     ws.pq(POUT_GXY)[o] = gxy;
     ws.pq(POUT_GYX)[o] = gyx;
     ws.pq(POUT_EZ)[o] = ez;
-    ws.pq(POUT_LXZ)[o] = lor ? jz * xBY : T(0);
-    ws.pq(POUT_LYZ)[o] = lor ? jz * yBX : T(0);
+    ws.pq(POUT_LXZ)[o] = lxz;
+    ws.pq(POUT_LYZ)[o] = lyz;
     ws.pq(POUT_QZ)[o] = qz;
-    // ---- centre
-    {
-      const T sxx = op6<1, 1, T>([&](int m) { return S(6, x + m, y); }, g.hxi);
-      const T syy = op6<1, 1, T>([&](int m) { return S(7, x, y + m); }, g.hyi);
-      const T Dc = Dg[o];
-      const T Pc = ph.gamma1 * S(2, x, y);
-      T gxx = T(0), gyy = T(0), qc = T(0);
-      if (visc) {
-        const T rn = sR[P6::at(x, y)] * S(8, x, y);
-        const T txx = rn * g.lx * (sxx + ph.c1 * Dc);
-        const T tyy = rn * g.ly * (syy + ph.c1 * Dc);
-        gxx = txx;
-        gyy = tyy;
-        qc = txx * sxx + tyy * syy;
-      }
-      if (adv) {
-        gxx = gxx - op6<0, 1, T>([&](int m) { return S(0, x + m, y); }, T(0)) *
-                        op6<0, 1, T>([&](int m) { return S(6, x + m, y); }, T(0));
-        gyy = gyy - op6<0, 1, T>([&](int m) { return S(1, x, y + m); }, T(0)) *
-                        op6<0, 1, T>([&](int m) { return S(7, x, y + m); }, T(0));
-      }
-      if (pres) qc = qc - Pc * Dc;
-      ws.pq(POUT_GXX)[o] = gxx;
-      ws.pq(POUT_GYY)[o] = gyy;
-      ws.pq(POUT_QC)[o] = qc;
-      // pressure gradients on the x- and y-faces, kept out of the fluxes
-      T dpx = T(0), dpy = T(0);
-      if (pres && (tm & T_LNP)) {
-        // eq. pressure: exp(ln P_aver) exp(adn(q)) ddadn(q), q = ln(P / P_aver)
-        // (the x and y derivatives of the plane mean vanish)
-        const T lpa = lnpav[b.poff + k];
-        auto lq = [&](int xx, int yy) { return log(ph.gamma1 * S(2, xx, yy)) - lpa; };
-        const T epa = exp(lpa);
-        dpx = epa * exp(op6<0, 0, T>([&](int m) { return lq(x + m, y); }, T(0))) *
-              op6<1, 0, T>([&](int m) { return lq(x + m, y); }, g.hxi);
-        dpy = epa * exp(op6<0, 0, T>([&](int m) { return lq(x, y + m); }, T(0))) *
-              op6<1, 0, T>([&](int m) { return lq(x, y + m); }, g.hyi);
-      } else if (pres) {
-        dpx = ph.gamma1 * op6<1, 0, T>([&](int m) { return S(2, x + m, y); }, g.hxi);
-        dpy = ph.gamma1 * op6<1, 0, T>([&](int m) { return S(2, x, y + m); }, g.hyi);
-      }
-      if (tm & T_CORI) {
-        // the in-plane parts of the Coriolis force -2 Omega x p (eq. mom),
-        // with the sign of a gradient that pass F subtracts: +2 Omega_z p_y
-        // on x-faces, -2 Omega_z p_x on y-faces
-        dpx -= ph.cor2[2] * op6<0, 0, T>([&](int m) {
-                 return op6<0, 1, T>([&](int n) { return S(1, x + m, y + n); }, T(0));
-               }, T(0));
-        dpy += ph.cor2[2] * op6<0, 0, T>([&](int n) {
-                 return op6<0, 1, T>([&](int m) { return S(0, x + m, y + n); }, T(0));
-               }, T(0));
-      }
-      ws.pq(POUT_DPX)[o] = dpx;
-      ws.pq(POUT_DPY)[o] = dpy;
-    }
-    // ---- x- and y-faces: energy fluxes
-    {
-      T hx = T(0), hy = T(0);
-      if (adv) {
-        hx = -op6<0, 0, T>([&](int m) { return S(2, x + m, y); }, T(0)) * S(6, x, y);
-        hy = -op6<0, 0, T>([&](int m) { return S(2, x, y + m); }, T(0)) * S(7, x, y);
-      }
-      if (ediff) {
-        hx = hx + ph.nuE * S(11, x, y) *
-                      (g.lx * op6<0, 0, T>([&](int m) { return S(8, x + m, y); }, T(0))) *
-                      op6<0, 0, T>([&](int m) { return S(9, x + m, y); }, T(0)) *
-                      op6<1, 0, T>([&](int m) { return S(10, x + m, y); }, g.hxi);
-        hy = hy + ph.nuE * S(12, x, y) *
-                      (g.ly * op6<0, 0, T>([&](int m) { return S(8, x, y + m); }, T(0))) *
-                      op6<0, 0, T>([&](int m) { return S(9, x, y + m); }, T(0)) *
-                      op6<1, 0, T>([&](int m) { return S(10, x, y + m); }, g.hyi);
-      }
-      ws.pq(POUT_HX)[o] = hx;
-      ws.pq(POUT_HY)[o] = hy;
-    }
-  }
-  ZLOOP_END
-}
-
-// ---------------------------------------------------------------------------
-// F: all divergences of P's and Q's quantities and of the momenta, the
-// gravity force, wall masking and the RK stage update.  x/y divergences of
-// plane r through LDS strips; z divergences scattered into per-thread
-// accumulators of output planes r-3..r+3 (first differences for
-// derivatives); plane r-3 is then complete.
-//
-// FM selects the fields this launch completes (bit v: field v); the stage
-// runs one launch per mask of kFMasks.  The groups read nearly disjoint
-// inputs, and each launch needs a fraction of the registers and LDS.
-// Masks: the momenta; rho and e; the magnetic field.
-constexpr unsigned kFMasks[] = {0x0Eu, 0x11u, 0xE0u};
-constexpr int kNFMasks = sizeof(kFMasks) / sizeof(kFMasks[0]);
-// queue counters, 8 per launch: A1, A2, Q edges, P, the F launches, then Q's
-// z-face and centre launch
-static_assert(32 + 8 * kNFMasks + 8 <= kQueueInts && kQueueInts <= 64, "queue counters per launch");
-constexpr bool masks_partition() {
-  unsigned all = 0;
-  for (unsigned m : kFMasks) {
-    if (all & m) return false;
-    all |= m;
-  }
-  return all == 0xFFu;
-}
-static_assert(masks_partition(), "each field completed by exactly one launch");
-template <unsigned FM> __host__ __device__ constexpr bool hasf(int v) { return (FM >> v) & 1u; }
-// the field each LDS strip serves, in zF's strip order: x strips, y strips
-__host__ __device__ constexpr int kXOwn[9] = {0, 1, 2, 2, 4, 3, 3, 7, 4};
-__host__ __device__ constexpr int kYOwn[9] = {0, 1, 1, 2, 4, 3, 3, 7, 4};
-// LDS position of strip q among the strips a launch loads (own: kXOwn or
-// kYOwn); q = 9 gives their number
-template <unsigned FM>
-__host__ __device__ constexpr int strip_slot(const int (&own)[9], int q) {
-  int n = 0;
-  for (int i = 0; i < q; ++i) n += (FM >> own[i]) & 1u;
-  return n;
-}
-__host__ __device__ constexpr int at_least1(int n) { return n > 0 ? n : 1; }
-
-template <class T, int TX, int TY, bool PERS, unsigned FM>
-__global__ __launch_bounds__(TX * TY) void zF(const BoxDev* __restrict__ boxes,
-                                              const ZItem* __restrict__ items, int nitems, const T* __restrict__ ztab,
-                                               int* __restrict__ queue,
-                                              CP8<T> f, ZWork<T> ws, Phys<T> ph, P8<T> du,
-                                              int du_mode, P8<T> f_out, T alpha, double beta,
-                                              const double* __restrict__ dt_dev,
-                                              double dt_host) {
-  using PXs = Plane<TX, TY, 3, 0>;   // x-halo strips
-  using PYs = Plane<TX, TY, 0, 3>;   // y-halo strips
-  using P3 = Plane<TX, TY, 3>;
-  // x strips: 0 px 1 Gxx 2 Gyx 3 Lyz 4 Hx 5 Gzx 6 Lzy 7 Ey 8 Qy
-  // y strips: 0 py 1 Gxy 2 Lxz 3 Gyy 4 Hy 5 Gzy 6 Lzx 7 Ex 8 Qx
-  // full:     0 Qz 1 Ez
-  // only the strips of this launch's fields occupy LDS
-  constexpr bool kQz = hasf<FM>(4), kEz = hasf<FM>(5) || hasf<FM>(6);
-  __shared__ T sx[at_least1(strip_slot<FM>(kXOwn, 9)) * PXs::NP];
-  __shared__ T sy[at_least1(strip_slot<FM>(kYOwn, 9)) * PYs::NP];
-  __shared__ T s2[at_least1(int(kQz) + int(kEz)) * P3::NP];
-  // Coriolis force (bit 8 of FM, momentum launch only; its in-plane parts
-  // come with pass P's face terms): x strips of px and pz, y strips of py
-  // and pz
-  constexpr bool kCori = hasf<FM>(8);
-  // div B diffusion (B launch): x and y strips of div B
-  constexpr bool kDB = hasf<FM>(5);
-  __shared__ T sdb[kDB ? PXs::NP + PYs::NP : 1];
-  __shared__ T sxc[kCori ? 2 * PXs::NP : 1];
-  __shared__ T syc[kCori ? 2 * PYs::NP : 1];
-  ZLOOP_BEGIN
-  PlaneIdx<TX, TY, 3, 0> ix;
-  PlaneIdx<TX, TY, 0, 3> iy;
-  PlaneIdx<TX, TY, 3> i3;
-  ix.init(b, it.x0, it.y0);
-  iy.init(b, it.x0, it.y0);
-  i3.init(b, it.x0, it.y0);
-  const unsigned tm = ph.terms;
-  const bool cont = tm & T_CONT, grav = tm & T_GRAV;
-  const T inv_mu = ph.inv_mu;
-  const double dt = dt_dev ? *dt_dev : dt_host;
-  const T bdt = T(beta * dt);
-  // div B diffusion C_divb h^2 / dt grad(div B); absent without a time step
-  const T kd = (kDB && dt > 0.0) ? T(double(ph.c_divb) * double(g.h) * double(g.h) / dt) : T(0);
-  auto X = [&](int q, int x) -> T { return sx[strip_slot<FM>(kXOwn, q) * PXs::NP + PXs::at(x, ty)]; };
-  auto Y = [&](int q, int y) -> T { return sy[strip_slot<FM>(kYOwn, q) * PYs::NP + PYs::at(tx, y)]; };
-  auto F2 = [&](int q, int x, int y) -> T { return s2[(q && kQz) * P3::NP + P3::at(x, y)]; };
-  auto XC = [&](int q, int x) -> T { return sxc[q * PXs::NP + PXs::at(x, ty)]; };
-  auto YC = [&](int q, int y) -> T { return syc[q * PYs::NP + PYs::at(tx, y)]; };
-  T acc[7][7];
-#pragma unroll
-  for (int a = 0; a < 7; ++a)
-#pragma unroll
-    for (int s = 0; s < 7; ++s) acc[a][s] = T(0);
-  // previous-plane values of the z-differentiated quantities (first
-  // differences): 0 pz 1 Gxz 2 Gyz 3 Gzz 4 Hz 5 Ey 6 Ex
-  T prev[7];
-#pragma unroll
-  for (int a = 0; a < 7; ++a) prev[a] = T(0);
-
-  // wall masking (Section 10): F vanishes in ghost planes, and for pz also
-  // on the two wall faces; Bz evolves on the wall faces
-  auto masked = [&](int v, int k, T Fv) -> T {
-    if (!wall) return Fv;
-    const bool cen = k >= b.g0 && k < b.g1;
-    const bool keep = v == 3 ? (k > b.g0 && k < b.g1) : (v == 7 ? (k >= b.g0 && k <= b.g1) : cen);
-    return keep ? Fv : T(0);
-  };
-  // RK stage update of one field at plane k, given its dU and f there
-  auto update = [&](int v, long long o, T Fv, T uin, T fin) {
-    const T U = (du_mode & DU_READ) ? alpha * uin + Fv : Fv;
-    if (du_mode & DU_WRITE) du.p[v][o] = U;
-    f_out.p[v][o] = fin + bdt * U;
-  };
-  // the seven z-accumulated fields at plane k: every load first, so they
-  // share one round trip to memory
-  auto finalize7 = [&](int k) {
-    const long long o = col(k);
-    T Fv[7];
-#pragma unroll
-    for (int a = 0; a < 7; ++a) Fv[a] = masked(a, k, acc[a][0]);
-    if (f_out.p[0] == nullptr) {
-#pragma unroll
-      for (int a = 0; a < 7; ++a)
-        if (hasf<FM>(a)) du.p[a][o] = Fv[a];
-      return;
-    }
-    T uin[7], fin[7];
-#pragma unroll
-    for (int a = 0; a < 7; ++a) {
-      uin[a] = T(0);
-      fin[a] = T(0);
-      if (hasf<FM>(a)) {
-        uin[a] = (du_mode & DU_READ) ? du.p[a][o] : T(0);
-        fin[a] = f.p[a][o];
-      }
-    }
-#pragma unroll
-    for (int a = 0; a < 7; ++a)
-      if (hasf<FM>(a)) update(a, o, Fv[a], uin[a], fin[a]);
-  };
-
-  for (int r = it.z0 - 3; r <= it.z1 + 2; ++r) {
-    const int kb = r - 3;
-    const bool inch = r >= it.z0 && r < it.z1;
-    if (valid(r)) {
-      const int k = kk(r);
-      const long long o = col(r);
-      __syncthreads();
-      if (inch) {
-        const T* xs[8] = {f.p[1], ws.pq(POUT_GXX), ws.pq(POUT_GYX), ws.pq(POUT_LYZ),
-                          ws.pq(POUT_HX), ws.q(QOUT_GZX), ws.q(QOUT_LZY), ws.q(QOUT_EY)};
-        const T* ys[8] = {f.p[2], ws.pq(POUT_GXY), ws.pq(POUT_LXZ), ws.pq(POUT_GYY),
-                          ws.pq(POUT_HY), ws.q(QOUT_GZY), ws.q(QOUT_LZX), ws.q(QOUT_EX)};
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          if (hasf<FM>(kXOwn[q])) load_plane(sx + strip_slot<FM>(kXOwn, q) * PXs::NP, xs[q], b, ix, k);
-          if (hasf<FM>(kYOwn[q])) load_plane(sy + strip_slot<FM>(kYOwn, q) * PYs::NP, ys[q], b, iy, k);
-        }
-        if (kQz) load_plane(s2, ws.pq(POUT_QZ), b, i3, k);
-        if (kEz) load_plane(s2 + kQz * P3::NP, ws.pq(POUT_EZ), b, i3, k);
-      }
-      if (hasf<FM>(4)) {
-        load_plane(sx + strip_slot<FM>(kXOwn, 8) * PXs::NP, ws.q(QOUT_QY), b, ix, k);
-        load_plane(sy + strip_slot<FM>(kYOwn, 8) * PYs::NP, ws.q(QOUT_QX), b, iy, k);
-      }
-      if (kDB && kd != T(0)) {
-        load_plane(sdb, ws.arr(WS_DIVB), b, ix, k);
-        load_plane(sdb + PXs::NP, ws.arr(WS_DIVB), b, iy, k);
-      }
-      if constexpr (kCori) {
-        load_plane(sxc, f.p[1], b, ix, k);
-        load_plane(sxc + PXs::NP, f.p[3], b, ix, k);
-        load_plane(syc, f.p[2], b, iy, k);
-        load_plane(syc + PYs::NP, f.p[3], b, iy, k);
-      }
-      // Bz's dU and f at this plane, fetched with the planes
-      T bz_u = T(0), bz_f = T(0);
-      if (hasf<FM>(7) && inch && own && f_out.p[0] != nullptr) {
-        if (du_mode & DU_READ) bz_u = du.p[7][o];
-        bz_f = f.p[7][o];
-      }
-      __syncthreads();
-      const int x = tx, y = ty;
-      if (inch) {
-        if (hasf<FM>(0) && cont)
-          acc[0][3] += -(op6<1, 1, T>([&](int m) { return X(0, x + m); }, g.hxi) +
-                         op6<1, 1, T>([&](int m) { return Y(0, y + m); }, g.hyi));
-        if (hasf<FM>(1))
-        acc[1][3] += op6<1, 0, T>([&](int m) { return X(1, x + m); }, g.hxi) +
-                     op6<1, 1, T>([&](int m) { return Y(1, y + m); }, g.hyi) -
-                     op6<0, 1, T>([&](int m) { return Y(2, y + m); }, T(0)) * inv_mu -
-                     ws.pq(POUT_DPX)[o];
-        if (hasf<FM>(2))
-        acc[2][3] += op6<1, 0, T>([&](int m) { return Y(3, y + m); }, g.hyi) +
-                     op6<1, 1, T>([&](int m) { return X(2, x + m); }, g.hxi) +
-                     op6<0, 1, T>([&](int m) { return X(3, x + m); }, T(0)) * inv_mu -
-                     ws.pq(POUT_DPY)[o];
-        if (hasf<FM>(3)) {
-          acc[3][3] -= ws.q(QOUT_DPZ)[o];
-          acc[3][3] += op6<1, 1, T>([&](int m) { return X(5, x + m); }, g.hxi) +
-                       op6<1, 1, T>([&](int m) { return Y(5, y + m); }, g.hyi) +
-                       (op6<0, 1, T>([&](int m) { return Y(6, y + m); }, T(0)) -
-                        op6<0, 1, T>([&](int m) { return X(6, x + m); }, T(0))) * inv_mu;
-        }
-        if (hasf<FM>(4))
-        acc[4][3] += ws.pq(POUT_QC)[o] + ws.q(QOUT_CZZ)[o] +
-                     op6<1, 1, T>([&](int m) { return X(4, x + m); }, g.hxi) +
-                     op6<1, 1, T>([&](int m) { return Y(4, y + m); }, g.hyi) +
-                     op6<0, 1, T>([&](int m) {
-                       return op6<0, 1, T>([&](int a) { return F2(0, x + a, y + m); }, T(0));
-                     }, T(0));
-        // Newtonian cooling (eq. NewtonCool, eq. rhocool) at the cell centre
-        if (hasf<FM>(4) && (tm & T_COOL)) {
-          const T rc = f.p[0][o], ec = f.p[4][o];
-          T q = -rc * (ec / rc - ph.e_cool) * ph.inv_tcool;
-          if (ph.cool_cut) {
-            const T r = rc * ph.inv_rho_cool, r2 = r * r;
-            q = q * ((ph.cool_cut == 1 ? r2 : T(1)) / (T(1) + r2));
-          }
-          acc[4][3] += q;
-        }
-        if (hasf<FM>(5)) acc[5][3] += -op6<1, 1, T>([&](int m) { return F2(1, x, y + m); }, g.hyi);
-        if (hasf<FM>(6)) acc[6][3] += op6<1, 1, T>([&](int m) { return F2(1, x + m, y); }, g.hxi);
-        if (kDB && kd != T(0)) {
-          acc[5][3] += kd * op6<1, 0, T>([&](int m) { return sdb[PXs::at(x + m, ty)]; }, g.hxi);
-          acc[6][3] += kd * op6<1, 0, T>([&](int m) { return sdb[PXs::NP + PYs::at(tx, y + m)]; }, g.hyi);
-        }
-        // Bz has no z divergence: complete at once
-        if (hasf<FM>(7) && own) {
-          T fbz = -(op6<1, 1, T>([&](int m) { return X(7, x + m); }, g.hxi) -
-                    op6<1, 1, T>([&](int m) { return Y(7, y + m); }, g.hyi));
-          if (kd != T(0)) {
-            // z part of grad(div B) on this z-face, from the own column
-            const T* __restrict__ dbg = ws.arr(WS_DIVB);
-            T w[6];
-#pragma unroll
-            for (int m = 0; m < 6; ++m) w[m] = valid(r - 3 + m) ? dbg[col(r - 3 + m)] : T(0);
-            fbz += kd * zwin<1, 0, 6, 3>(w, r, wall, N, g.hzi, zt);
-          }
-          const T F7 = masked(7, r, fbz);
-          if (f_out.p[0] == nullptr) du.p[7][o] = F7;
-          else update(7, o, F7, bz_u, bz_f);
-        }
-      }
-      // Coriolis force (eq. mom): -2 Omega x p, each component on its own
-      // face; the parts that end with an interpolation along z, scattered
-      // below (the in-plane parts arrive with pass P's face terms)
-      T czx = T(0), czy = T(0), czz = T(0);
-      if constexpr (kCori) {
-        const T wx = ph.cor2[0], wy = ph.cor2[1];
-        czx = -wy * op6<0, 0, T>([&](int m) { return XC(1, x + m); }, T(0));
-        czy = wx * op6<0, 0, T>([&](int n) { return YC(1, y + n); }, T(0));
-        czz = wy * op6<0, 1, T>([&](int m) { return XC(0, x + m); }, T(0)) -
-              wx * op6<0, 1, T>([&](int n) { return YC(0, y + n); }, T(0));
-      }
-      T xqy = T(0), yqx = T(0);
-      if (hasf<FM>(4)) {
-        xqy = op6<0, 1, T>([&](int m) { return X(8, x + m); }, T(0));
-        yqx = op6<0, 1, T>([&](int m) { return Y(8, y + m); }, T(0));
-      }
-      // ---- z divergences of plane r scattered into output planes r-3..r+3:
-      // derivatives through first differences, interpolations directly
-      T cur[7];
-      const T* cols[7] = {f.p[3], ws.q(QOUT_GXZ), ws.q(QOUT_GYZ), ws.q(QOUT_GZZ), ws.q(QOUT_HZ),
-                          ws.q(QOUT_EY), ws.q(QOUT_EX)};
-#pragma unroll
-      for (int a = 0; a < 7; ++a) cur[a] = hasf<FM>(a) ? cols[a][o] : T(0);
-      T dl[7];
-#pragma unroll
-      for (int a = 0; a < 7; ++a) {
-        dl[a] = (cur[a] - prev[a]) * g.hzi;
-        prev[a] = cur[a];
-      }
-      if (hasf<FM>(0) && cont) zscatter_d<1, 3>(acc[0], kb, -dl[0], wall, N, zt);
-      if (hasf<FM>(1)) {
-        zscatter_d<1, 3>(acc[1], kb, dl[1], wall, N, zt);
-        zscatter<0, 1, 3>(acc[1], kb, ws.q(QOUT_LXY)[o] * inv_mu, wall, N, zt);
-        if constexpr (kCori) zscatter<0, 1, 3>(acc[1], kb, czx, wall, N, zt);
-      }
-      if (hasf<FM>(2)) {
-        zscatter_d<1, 3>(acc[2], kb, dl[2], wall, N, zt);
-        zscatter<0, 1, 3>(acc[2], kb, -ws.q(QOUT_LYX)[o] * inv_mu, wall, N, zt);
-        if constexpr (kCori) zscatter<0, 1, 3>(acc[2], kb, czy, wall, N, zt);
-      }
-      if (hasf<FM>(3)) {
-        zscatter_d<0, 3>(acc[3], kb, dl[3], wall, N, zt);
-        if (grav) zscatter<0, 0, 3>(acc[3], kb, -f.p[0][o] * ph.gz, wall, N, zt);
-        if constexpr (kCori) zscatter<0, 0, 3>(acc[3], kb, czz, wall, N, zt);
-      }
-      if (hasf<FM>(4)) {
-        zscatter_d<1, 3>(acc[4], kb, dl[4], wall, N, zt);
-        zscatter<0, 1, 3>(acc[4], kb, xqy, wall, N, zt);
-        zscatter<0, 1, 3>(acc[4], kb, yqx, wall, N, zt);
-      }
-      if (hasf<FM>(5)) zscatter_d<1, 3>(acc[5], kb, dl[5], wall, N, zt);
-      if (hasf<FM>(6)) zscatter_d<1, 3>(acc[6], kb, -dl[6], wall, N, zt);
-    } else {
-#pragma unroll
-      for (int a = 0; a < 7; ++a) prev[a] = T(0);
-    }
-    // ---- plane kb = r-3 is complete
-    if (own && valid(kb) && kb >= it.z0 && kb < it.z1) finalize7(kb);
-#pragma unroll
-    for (int a = 0; a < 7; ++a) {
-#pragma unroll
-      for (int s = 0; s < 6; ++s) acc[a][s] = acc[a][s + 1];
-      acc[a][6] = T(0);
-    }
+    ws.pq(POUT_GXX)[o] = gxx;
+    ws.pq(POUT_GYY)[o] = gyy;
+    ws.pq(POUT_QC)[o] = qc;
+    ws.pq(POUT_DPX)[o] = dpx;
+    ws.pq(POUT_DPY)[o] = dpy;
+    ws.pq(POUT_HX)[o] = xface_h<T>(SA, x, y, g, ph);
+    ws.pq(POUT_HY)[o] = yface_h<T>(SA, x, y, g, ph);
   }
   ZLOOP_END
 }
@@ -1349,6 +913,7 @@ void launch_zreduce(const ZLaunch& L, CP8<T> f, CP8<T> dfdt, const ZWork<T>& w, 
     case ZTILE_16x16: launch_zreduce_t<T, 16, 16>(L, f, dfdt, w, ph, ztab, red, nuB, eta_const); break;
     case ZTILE_16x8: launch_zreduce_t<T, 16, 8>(L, f, dfdt, w, ph, ztab, red, nuB, eta_const); break;
     case ZTILE_64x8: launch_zreduce_t<T, 64, 8>(L, f, dfdt, w, ph, ztab, red, nuB, eta_const); break;
+    case ZTILE_32x16: launch_zreduce_t<T, 32, 16>(L, f, dfdt, w, ph, ztab, red, nuB, eta_const); break;
     default: launch_zreduce_t<T, 64, 4>(L, f, dfdt, w, ph, ztab, red, nuB, eta_const); break;
   }
   hipLaunchKernelGGL(k_red_final, dim3(1), dim3(kRedThreads), 0, L.stream, L.boxes, L.items, L.nitems, red, Cdt, Cdtd,
@@ -1362,62 +927,8 @@ template void launch_zreduce<double>(const ZLaunch&, CP8<double>, CP8<double>, c
                                      const Phys<double>&, const double*, RedItem*, RedTotal*, double, double,
                                      double, double, double);
 
-// ---------------------------------------------------------------------------
-template <class T, int TX, int TY, bool PERS, unsigned FM, class G>
-static void zF_one(const G& grid, dim3 block, const ZLaunch& L, const ZStageArgs<T>& a, int* q) {
-  hipLaunchKernelGGL((zF<T, TX, TY, PERS, FM>), grid((const void*)zF<T, TX, TY, PERS, FM>), block, 0, L.stream,
-                     L.boxes, L.fitems, L.nfitems, a.ztab, q, a.f, a.w, a.ph, a.du, a.du_mode, a.f_out, a.alpha,
-                     a.beta, a.dt_dev, a.dt_host);
-}
-// The momentum launch's mask with the Coriolis bit (8) set; others unchanged.
-template <unsigned FM> constexpr unsigned with_cori() { return (FM & 0x0Eu) ? (FM | 0x100u) : FM; }
-// one launch per mask, each with its own 8 queue counters
-template <class T, int TX, int TY, bool PERS, class G, size_t... I>
-static void zF_launch(const G& grid, dim3 block, const ZLaunch& L, const ZStageArgs<T>& a, int* q,
-                      std::index_sequence<I...>) {
-  if (a.ph.terms & T_CORI)
-    (zF_one<T, TX, TY, PERS, with_cori<kFMasks[I]>()>(grid, block, L, a, q ? q + 32 + 8 * int(I) : q), ...);
-  else
-    (zF_one<T, TX, TY, PERS, kFMasks[I]>(grid, block, L, a, q ? q + 32 + 8 * int(I) : q), ...);
-}
-
 __global__ void k_qreset(int* q) {
   if ((int)threadIdx.x < kQueueInts) q[threadIdx.x] = 0;
-}
-
-// Workgroups of a kernel that fit on the device at once (cached per kernel).
-static int resident_groups(const void* kern, int block, int ncu) {
-  static std::mutex mu;
-  static std::map<const void*, int> cache;
-  std::lock_guard<std::mutex> lock(mu);
-  auto it = cache.find(kern);
-  if (it != cache.end()) return it->second;
-  int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, block, 0) != hipSuccess || nb < 1) nb = 1;
-  return cache[kern] = nb * ncu;
-}
-
-// Pass F, in its own tile shape (L.ftile) over its own work items.
-template <class T, int TX, int TY, bool PERS>
-static void launch_final_t(const ZLaunch& L, const ZStageArgs<T>& a, int* q) {
-  const int n = L.nfitems;
-  auto grid = [&](const void* kern) {
-    if (!q) return dim3(8 * ((n + 7) / 8));
-    const int r = std::min(n, resident_groups(kern, TX * TY, L.ncu));
-    return dim3(std::max(8, r - r % 8));
-  };
-  zF_launch<T, TX, TY, PERS>(grid, dim3(TX * TY), L, a, q, std::make_index_sequence<kNFMasks>{});
-}
-
-template <class T, bool PERS>
-static void launch_final(const ZLaunch& L, const ZStageArgs<T>& a, int* q) {
-  switch (L.ftile) {
-    case ZTILE_32x8: launch_final_t<T, 32, 8, PERS>(L, a, q); break;
-    case ZTILE_16x16: launch_final_t<T, 16, 16, PERS>(L, a, q); break;
-    case ZTILE_16x8: launch_final_t<T, 16, 8, PERS>(L, a, q); break;
-    case ZTILE_64x8: launch_final_t<T, 64, 8, PERS>(L, a, q); break;
-    default: launch_final_t<T, 64, 4, PERS>(L, a, q); break;
-  }
 }
 
 template <class T, int TX, int TY, bool PERS>
@@ -1427,7 +938,7 @@ static void launch_zstage_m(const ZLaunch& L, const ZStageArgs<T>& a) {
   int* q = PERS ? L.queue : nullptr;
   auto grid = [&](const void* kern) {
     if (!q) return dim3(8 * ((n + 7) / 8));
-    const int r = std::min(n, resident_groups(kern, TX * TY, L.ncu));
+    const int r = std::min(n, zresident_groups(kern, TX * TY, L.ncu));
     return dim3(std::max(8, r - r % 8));
   };
   if (q) hipLaunchKernelGGL(k_qreset, dim3(1), dim3(64), 0, L.stream, q);
@@ -1468,9 +979,11 @@ static void launch_zstage_m(const ZLaunch& L, const ZStageArgs<T>& a) {
     hipLaunchKernelGGL((zQ<T, TX, TY, PERS, QM_ZC>), grid((const void*)zQ<T, TX, TY, PERS, QM_ZC>), block, 0,
                        L.stream, L.boxes, L.items, n, a.ztab, q ? q + 32 + 8 * kNFMasks : q, a.f, a.ph, a.w,
                        a.lnavg, a.w.lnpav);
-  L.at(PASS_CF);
-  hipLaunchKernelGGL((zP<T, TX, TY, PERS>), grid((const void*)zP<T, TX, TY, PERS>), block, 0, L.stream, L.boxes,
-                     L.items, n, a.ztab, q ? q + 24 : q, a.f, a.ph, a.w);
+  if (!L.fuse) {   // inline mode: pass F forms pass P's quantities itself
+    L.at(PASS_CF);
+    hipLaunchKernelGGL((zP<T, TX, TY, PERS>), grid((const void*)zP<T, TX, TY, PERS>), block, 0, L.stream,
+                       L.boxes, L.items, n, a.ztab, q ? q + 24 : q, a.f, a.ph, a.w);
+  }
   L.at(PASS_FINAL);
   launch_final<T, PERS>(L, a, q);
   L.at(PASS_END);
@@ -1489,6 +1002,7 @@ void launch_zstage(const ZLaunch& L, const ZStageArgs<T>& a) {
     case ZTILE_16x16: launch_zstage_t<T, 16, 16>(L, a); break;
     case ZTILE_16x8: launch_zstage_t<T, 16, 8>(L, a); break;
     case ZTILE_64x8: launch_zstage_t<T, 64, 8>(L, a); break;
+    case ZTILE_32x16: launch_zstage_t<T, 32, 16>(L, a); break;
     default:
       launch_zstage_t<T, 64, 4>(L, a);
       break;

@@ -25,13 +25,17 @@ template <class T> struct PQ { T* p[POUT_COUNT]; };
 template <class T> struct CPQ { const T* p[POUT_COUNT]; };
 
 // Tile shapes (columns per workgroup, x by y) the stage kernels are built for.
-enum ZTile : int { ZTILE_64x4 = 0, ZTILE_32x8 = 1, ZTILE_16x16 = 2, ZTILE_16x8 = 3, ZTILE_64x8 = 4, ZTILE_COUNT };
+enum ZTile : int {
+  ZTILE_64x4 = 0, ZTILE_32x8 = 1, ZTILE_16x16 = 2, ZTILE_16x8 = 3, ZTILE_64x8 = 4, ZTILE_32x16 = 5, ZTILE_COUNT
+};
 
 // Whether a tile shape is built for an element size (all are).
 inline bool ztile_ok(int t, size_t esize) { (void)esize; return t >= 0 && t < ZTILE_COUNT; }
 
-inline int ztile_x(int t) { return (t == ZTILE_64x4 || t == ZTILE_64x8) ? 64 : (t == ZTILE_32x8 ? 32 : 16); }
-inline int ztile_y(int t) { return t == ZTILE_64x4 ? 4 : (t == ZTILE_16x16 ? 16 : 8); }
+inline int ztile_x(int t) {
+  return (t == ZTILE_64x4 || t == ZTILE_64x8) ? 64 : ((t == ZTILE_32x8 || t == ZTILE_32x16) ? 32 : 16);
+}
+inline int ztile_y(int t) { return t == ZTILE_64x4 ? 4 : ((t == ZTILE_16x16 || t == ZTILE_32x16) ? 16 : 8); }
 
 // Stage workspace: WS_COUNT arrays of `stride` elements back to back, so a
 // kernel needs one base pointer for all of them (array pointers held in
@@ -64,6 +68,7 @@ struct ZLaunch {
   int ftile;
   int* queue;             // device, kQueueInts counters (persistent mode)
   int persistent;         // 0: one workgroup per item; 1: item queues
+  int fuse;               // 1: pass F forms pass P's quantities itself (no pass P)
   int ncu;                // compute units of the device
   int nbox, nplanes;      // boxes; z planes of all boxes
   hipStream_t stream;
@@ -93,6 +98,14 @@ template <class T> struct ZStageArgs {
 };
 
 template <class T> void launch_zstage(const ZLaunch& L, const ZStageArgs<T>& a);
+
+// Pass F (mhd_zfinal.hip) in its tile shape L.ftile and mode L.fuse; false
+// if that shape has no inline variant for T (its LDS would not fit).
+template <class T, bool PERS> bool launch_final(const ZLaunch& L, const ZStageArgs<T>& a, int* q);
+// Whether pass F of tile shape `tile` has an inline variant for element size esize.
+bool final_fuse_ok(int tile, size_t esize);
+// Workgroups of a kernel that fit on the device at once (cached per kernel).
+int zresident_groups(const void* kern, int block, int ncu);
 
 // mhd_reductions: passes A1 and A2 in their reduction instantiations over
 // the work items of L (grid mode), then the fold of the per-item partials
