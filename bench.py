@@ -97,7 +97,7 @@ def make_state(workload, size):
 
 
 def run_gpu(size, dtype, steps, warmup, workload="stratified", tile=None, over=None,
-            launch=None, fuse=None):
+            launch=None):
     """Times `steps` RK steps.  over: parameters replacing the workload's;
     launch: a (tile, persistent, final-pass tile) to use instead of tuning."""
     import torch
@@ -117,8 +117,6 @@ def run_gpu(size, dtype, steps, warmup, workload="stratified", tile=None, over=N
         tune = ctx.autotune(f, reps=2)          # tile shape and launch mode
     else:
         ctx.set_launch(tile, 0)
-    if fuse is not None:
-        ctx.set_fusion(fuse)                    # pass F forms pass P's quantities (1) or not
     work = (ctx.empty(), ctx.empty(), ctx.empty())
     torch.cuda.synchronize()
     ncell = size ** 3
@@ -142,7 +140,6 @@ def run_gpu(size, dtype, steps, warmup, workload="stratified", tile=None, over=N
     ctx.profile(False)
     launch = ctx.get_launch()
     ftile = ctx.get_final_tile()
-    fusion = ctx.get_fusion()
     dt_last = ctx.last_dt()
     s_end = ctx.reductions(f)
     ctx.close()
@@ -151,8 +148,7 @@ def run_gpu(size, dtype, steps, warmup, workload="stratified", tile=None, over=N
     ms = (t1 - t0) * 1e3 / steps
     stage_ms = sum(prof[p][0] for p in STAGE_PASSES) / (3 * steps)
     return dict(ms_per_step=ms, value=ncell * steps / (t1 - t0), stage_ms=stage_ms,
-                launch={"tile": launch[0], "persistent": launch[1], "final_pass_tile": ftile,
-                        "final_pass_inline": fusion},
+                launch={"tile": launch[0], "persistent": launch[1], "final_pass_tile": ftile},
                 autotune_ms_per_rhs=None if tune is None else {
                     "%s/%s" % (k[0], "persistent" if k[1] else "grid"): round(v, 4)
                     for k, v in tune.items()},
@@ -344,9 +340,6 @@ def main():
     ap.add_argument("--workload", default="stratified", choices=("stratified", "turbulent"))
     ap.add_argument("--tile", default=None,
                     help="stage kernel tile shape, e.g. 32x8 (default: autotuned)")
-    ap.add_argument("--fuse", type=int, default=None, choices=(0, 1),
-                    help="pass F forms pass P's quantities itself (1) or reads them (0); "
-                         "default: as tuned")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint and ensemble legs")
     ap.add_argument("--no-sources", action="store_true",
                     help="skip the legs with the optional terms (cooling, Coriolis, energy "
@@ -366,7 +359,7 @@ def main():
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
 
-    r32 = run_gpu(a.size, torch.float32, a.steps, a.warmup, a.workload, a.tile, fuse=a.fuse)
+    r32 = run_gpu(a.size, torch.float32, a.steps, a.warmup, a.workload, a.tile)
     log("f32: %.2f ms/step, %.3e cell-updates/s" % (r32["ms_per_step"], r32["value"]))
     rsrc = {}
     if not a.no_sources and a.workload == "stratified":

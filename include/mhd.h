@@ -259,7 +259,7 @@ int mhd_last_dt(mhd_ctx* ctx, double* dt);
  * 1: 32x8, 2: 16x16, 3: 16x8 (256 threads), 4: 64x8, 5: 32x16 (512
  * threads).  Any shape gives the same results (bit for bit); the default is
  * 32x8 (float32) or 16x8 (float64).  Other values: MHD_EINVAL.  Also sets
- * pass F to this shape in the stored mode (mhd_set_fusion).               */
+ * pass F to this shape (mhd_set_final_tile).                               */
 int mhd_set_tile(mhd_ctx* ctx, int32_t tile);
 
 /* Tile shape (as mhd_set_tile) and launch mode of the stage kernels.
@@ -275,33 +275,18 @@ int mhd_get_launch(const mhd_ctx* ctx, int32_t* tile, int32_t* persistent);
 
 /* Tile shape of pass F alone (the divergences and the RK stage update), as
  * mhd_set_tile; mhd_set_tile and mhd_set_launch set it to their own shape.
- * Results are the same bit for bit.  MHD_EINVAL on other values;
- * MHD_EUNSUPPORTED if the inline mode is on and not built for the shape.    */
+ * Results are the same bit for bit.  MHD_EINVAL on other values.            */
 int mhd_set_final_tile(mhd_ctx* ctx, int32_t tile);
 int mhd_get_final_tile(const mhd_ctx* ctx, int32_t* tile);
 
-/* Where pass F gets pass P's in-plane quantities (z-edge stress, E_z,
- * Lorentz products, centre stresses, x/y energy fluxes and pressure
- * gradients: eqs. itv, nuij, ohm, vdiss, ien, ediffuse).  fuse = 0
- * (stored, the default): pass P writes them to the stage workspace and the
- * launches of pass F (one per field group) read them back with halos.
- * fuse = 1 (inline): pass P is not launched; one launch of pass F forms
- * them in LDS on the halo strips its divergences need, trading
- * recomputation for memory traffic.  Both modes give the same bits.
- * MHD_EUNSUPPORTED when pass F's tile shape has no inline variant for the
- * dtype (its LDS would not fit: float32 has it for every shape, float64 for
- * the 256-thread shapes); mhd_set_tile and mhd_set_launch reset it to 0.   */
-int mhd_set_fusion(mhd_ctx* ctx, int32_t fuse);
-int mhd_get_fusion(const mhd_ctx* ctx, int32_t* fuse);
 
 /* Autotuner: times reps evaluations of mhd_rhs(f, dfdt) (after one warm-up)
  * in every tile shape and launch mode, keeps the fastest and, if ms is not
  * NULL, writes the milliseconds per evaluation to ms[2 * tile + persistent]
  * (12 entries; 0 for a shape not built for the context's dtype).  Then, with
  * that shape for the other passes, times every shape for pass F alone in
- * both launch modes and both fusion modes (mhd_set_fusion), and keeps the
- * fastest combination if it beats the uniform launch by more than 2 %
- * (mhd_get_launch, mhd_get_final_tile, mhd_get_fusion).  dfdt is overwritten; with walls the ghost
+ * both modes, and keeps the fastest combination if it beats the uniform
+ * launch by more than 2 % (mhd_get_launch, mhd_get_final_tile).  dfdt is overwritten; with walls the ghost
  * planes of f are filled.  Waits for the stream.                           */
 int mhd_autotune(mhd_ctx* ctx, void* const f[8], void* const dfdt[8], int32_t reps,
                  double* ms);

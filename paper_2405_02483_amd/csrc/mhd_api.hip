@@ -54,7 +54,6 @@ struct mhd_ctx {
   CPart* d_cpart = nullptr;
   int* d_queue = nullptr;          // item queues of the persistent launch mode
   int persistent = 0;
-  int fuse = 0;                    // pass F forms pass P's quantities itself (mhd_set_fusion)
   int ncu = 1;
   double* d_dt = nullptr;
   void* d_ztab = nullptr;          // z-coefficient tables of wall boxes (ctx dtype)
@@ -247,7 +246,6 @@ static ZLaunch make_zlaunch(const mhd_ctx* c, const Scratch& s) {
   L.ftile = c->ftile;
   L.queue = s.queue;
   L.persistent = c->persistent;
-  L.fuse = c->fuse;
   L.ncu = c->ncu;
   L.nbox = (int)c->h_boxes.size();
   L.nplanes = c->nplanes;
@@ -350,7 +348,6 @@ static int set_tile(mhd_ctx* c, int tile) {
   int rc = upload_items(c, tile, &c->d_items, &c->nitems, &c->d_cpart);
   if (rc != MHD_OK) return rc;
   c->tile = tile;
-  c->fuse = 0;
   return set_ftile(c, tile);
 }
 
@@ -1066,24 +1063,7 @@ int mhd_set_final_tile(mhd_ctx* c, int32_t tile) {
   if (!c) return fail(nullptr, MHD_EINVAL, "ctx is NULL");
   if (tile < 0 || tile >= ZTILE_COUNT) return fail(c, MHD_EINVAL, "unknown tile shape");
   if (!ztile_ok(tile, c->esize)) return fail(c, MHD_EUNSUPPORTED, "tile shape not built for this dtype");
-  if (c->fuse && !final_fuse_ok(tile, c->esize))
-    return fail(c, MHD_EUNSUPPORTED, "the inline mode of pass F is not built for this tile shape and dtype");
   return set_ftile(c, tile);
-}
-
-int mhd_set_fusion(mhd_ctx* c, int32_t fuse) {
-  if (!c) return fail(nullptr, MHD_EINVAL, "ctx is NULL");
-  if (fuse != 0 && fuse != 1) return fail(c, MHD_EINVAL, "fuse must be 0 or 1");
-  if (fuse && !final_fuse_ok(c->ftile, c->esize))
-    return fail(c, MHD_EUNSUPPORTED, "the inline mode of pass F is not built for this tile shape and dtype");
-  c->fuse = fuse;
-  return MHD_OK;
-}
-
-int mhd_get_fusion(const mhd_ctx* c, int32_t* fuse) {
-  if (!c || !fuse) return MHD_EINVAL;
-  *fuse = c->fuse;
-  return MHD_OK;
 }
 
 int mhd_get_final_tile(const mhd_ctx* c, int32_t* tile) {
@@ -1138,42 +1118,34 @@ int mhd_autotune(mhd_ctx* c, void* const f[8], void* const dfdt[8], int32_t reps
         bp = m;
       }
     }
-  // then pass F's own shape and mode (stored, or inline where built), with
-  // the others' shape fixed, in both launch modes: a change only if it is
-  // faster by more than the timing noise (2 %)
-  double tf[2][2][ZTILE_COUNT];
+  // then pass F's own shape, with the others' shape fixed, in both modes:
+  // a change only if it is faster by more than the timing noise (2 %)
+  double tf[2][ZTILE_COUNT];
   for (int m = 0; m < 2 && rc == MHD_OK; ++m) {
     if ((rc = mhd_set_launch(c, bt, m)) != MHD_OK) break;
-    for (int u = 0; u < 2 && rc == MHD_OK; ++u)
-      for (int t = 0; t < ZTILE_COUNT && rc == MHD_OK; ++t) {
-        tf[u][m][t] = -1.0;
-        if (!ztile_ok(t, c->esize) || (u && !final_fuse_ok(t, c->esize))) continue;
-        c->fuse = 0;
-        if ((rc = set_ftile(c, t)) != MHD_OK) break;
-        c->fuse = u;
-        rc = timed(tf[u][m][t]);
-      }
+    for (int t = 0; t < ZTILE_COUNT && rc == MHD_OK; ++t) {
+      tf[m][t] = -1.0;
+      if (!ztile_ok(t, c->esize)) continue;
+      if ((rc = set_ftile(c, t)) != MHD_OK) break;
+      rc = timed(tf[m][t]);
+    }
   }
-  int bm = bp, bf = bt, bu = 0;
+  int bm = bp, bf = bt;
   if (rc == MHD_OK) {
-    const double base = tf[0][bp][bt];
-    for (int u = 0; u < 2; ++u)
-      for (int m = 0; m < 2; ++m)
-        for (int t = 0; t < ZTILE_COUNT; ++t)
-          if (tf[u][m][t] > 0.0 && tf[u][m][t] < 0.98 * base && tf[u][m][t] < tf[bu][bm][bf]) {
-            bu = u;
-            bm = m;
-            bf = t;
-          }
+    const double base = tf[bp][bt];
+    for (int m = 0; m < 2; ++m)
+      for (int t = 0; t < ZTILE_COUNT; ++t)
+        if (tf[m][t] > 0.0 && tf[m][t] < 0.98 * base && tf[m][t] < tf[bm][bf]) {
+          bm = m;
+          bf = t;
+        }
     rc = mhd_set_launch(c, bt, bm);
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   c->prof = prof;
   if (rc != MHD_OK) return rc;
-  if ((rc = set_ftile(c, bf)) != MHD_OK) return rc;
-  c->fuse = bu;
-  return MHD_OK;
+  return set_ftile(c, bf);
 }
 
 }  // extern "C"

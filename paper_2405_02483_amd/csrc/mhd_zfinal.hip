@@ -6,16 +6,9 @@
 // into per-thread accumulators of output planes r-3..r+3 (first differences
 // for derivatives), and plane r-3 is then complete.
 //
-// Two ways to obtain pass P's in-plane quantities (z-edge, centre and x/y
-// face terms; mhd_zstage.hpp):
-//   stored (PIN false): pass P wrote them to the stage workspace and the
-//     launches of F read them back as strips (one launch per field group);
-//   inline (PIN true): one launch for all fields forms them itself, in LDS,
-//     on the strips its divergences need (a halo of 3 around the tile),
-//     from planes of the state and of ln <nu> with a halo of 5 (8 for rho
-//     and ln <nu>); pass P is not launched.  This trades recomputation on
-//     the halo for the 13 workspace arrays pass P would write and F read.
-// Both evaluate the same point functions, so they give the same bits.
+// Pass P's in-plane quantities (z-edge, centre and x/y face terms;
+// mhd_zstage.hpp) come from the stage workspace as strips; each launch
+// completes one field group (kFMasks) and loads only that group's strips.
 #include <algorithm>
 #include <map>
 #include <mutex>
@@ -27,12 +20,10 @@
 namespace smhd {
 
 // the field each LDS strip serves, in F's strip order: x strips, y strips
-__device__ constexpr int kXOwn[9] = {0, 1, 2, 2, 4, 3, 3, 7, 4};
-__device__ constexpr int kYOwn[9] = {0, 1, 1, 2, 4, 3, 3, 7, 4};
-constexpr int kXOwnH[9] = {0, 1, 2, 2, 4, 3, 3, 7, 4};
-constexpr int kYOwnH[9] = {0, 1, 1, 2, 4, 3, 3, 7, 4};
-// LDS position of strip q among the strips a launch loads (own: kXOwnH or
-// kYOwnH); q = 9 gives their number
+constexpr int kXOwn[9] = {0, 1, 2, 2, 4, 3, 3, 7, 4};
+constexpr int kYOwn[9] = {0, 1, 1, 2, 4, 3, 3, 7, 4};
+// LDS position of strip q among the strips a launch loads (own: kXOwn or
+// kYOwn); q = 9 gives their number
 template <unsigned FM>
 __host__ __device__ constexpr int strip_slot(const int (&own)[9], int q) {
   int n = 0;
@@ -41,45 +32,16 @@ __host__ __device__ constexpr int strip_slot(const int (&own)[9], int q) {
 }
 __host__ __device__ constexpr int at_least1(int n) { return n > 0 ? n : 1; }
 
-// LDS layout of the inline mode for a TX x TY tile (element counts).
-template <int TX, int TY> struct PinLayout {
-  using B8 = Plane<TX, TY, 8>;      // rho, ln <nu>
-  using B5 = Plane<TX, TY, 5>;      // the state; derived planes
-  using B3 = Plane<TX, TY, 3>;      // pass P's quantities
-  using PXs = Plane<TX, TY, 3, 0>;  // x strips of pass Q's quantities
-  using PYs = Plane<TX, TY, 0, 3>;  // y strips
-  static constexpr int NIN5 = 7;    // px py e bx by D pz
-  static constexpr int NDER = 9;    // ux uy rxd ryd xl nu em lem lq
-  static constexpr int NPQ = 10;    // Gxx Gyx Lyz Hx | Gxy Lxz Gyy Hy | Qz Ez
-  static constexpr int IN8 = 2 * B8::NP;
-  static constexpr int IN5 = NIN5 * B5::NP;
-  static constexpr int QS = 4 * PXs::NP + 4 * PYs::NP;
-  static constexpr int DER = NDER * B5::N > QS ? NDER * B5::N : QS;   // Q strips alias the derived planes
-  static constexpr int PQ = NPQ * B3::N;
-  static constexpr int DB = PXs::NP + PYs::NP;                          // x/y strips of div B
-  template <class T> static constexpr size_t bytes() { return sizeof(T) * size_t(IN8 + IN5 + DER + PQ + DB); }
-};
-constexpr size_t kLdsMax = 160 * 1024;
-template <class T, int TX, int TY> constexpr bool pin_fits() {
-  return PinLayout<TX, TY>::template bytes<T>() + 1024 <= kLdsMax;
-}
-
-template <class T, int TX, int TY, bool PERS, unsigned FM, bool PIN>
+template <class T, int TX, int TY, bool PERS, unsigned FM>
 __global__ __launch_bounds__(TX * TY) void zF(const BoxDev* __restrict__ boxes,
                                               const ZItem* __restrict__ items, int nitems,
                                               const T* __restrict__ ztab, int* __restrict__ queue,
                                               CP8<T> f, ZWork<T> ws, Phys<T> ph, P8<T> du,
                                               int du_mode, P8<T> f_out, T alpha, double beta,
                                               const double* __restrict__ dt_dev, double dt_host) {
-  static_assert(!PIN || (FM & 0xFFu) == 0xFFu, "the inline mode completes every field in one launch");
-  constexpr int NT = TX * TY;
   using PXs = Plane<TX, TY, 3, 0>;   // x-halo strips
   using PYs = Plane<TX, TY, 0, 3>;   // y-halo strips
   using P3 = Plane<TX, TY, 3>;
-  using LY = PinLayout<TX, TY>;
-  using B8 = typename LY::B8;
-  using B5 = typename LY::B5;
-  using B3 = typename LY::B3;
   // x strips: 0 px 1 Gxx 2 Gyx 3 Lyz 4 Hx 5 Gzx 6 Lzy 7 Ey 8 Qy
   // y strips: 0 py 1 Gxy 2 Lxz 3 Gyy 4 Hy 5 Gzy 6 Lzx 7 Ex 8 Qx
   // full:     0 Qz 1 Ez
@@ -89,22 +51,13 @@ __global__ __launch_bounds__(TX * TY) void zF(const BoxDev* __restrict__ boxes,
   constexpr bool kCori = hasf<FM>(8);
   // div B diffusion (with the B_x launch): x and y strips of div B
   constexpr bool kDB = hasf<FM>(5);
-  // stored mode: only the strips of this launch's fields occupy LDS
-  constexpr int NSX = PIN ? 1 : at_least1(strip_slot<FM>(kXOwnH, 9)) * PXs::NP;
-  constexpr int NSY = PIN ? 1 : at_least1(strip_slot<FM>(kYOwnH, 9)) * PYs::NP;
-  constexpr int NS2 = PIN ? 1 : at_least1(int(kQz) + int(kEz)) * P3::NP;
-  __shared__ T sx[NSX];
-  __shared__ T sy[NSY];
-  __shared__ T s2[NS2];
-  __shared__ T sxc[(kCori && !PIN) ? 2 * PXs::NP : 1];
-  __shared__ T syc[(kCori && !PIN) ? 2 * PYs::NP : 1];
-  __shared__ T sdb[(kDB && !PIN) ? PXs::NP + PYs::NP : 1];
-  // inline mode
-  __shared__ T sIn8[PIN ? LY::IN8 : 1];
-  __shared__ T sIn5[PIN ? LY::IN5 : 1];
-  __shared__ T sDer[PIN ? LY::DER : 1];
-  __shared__ T sPQ[PIN ? LY::PQ : 1];
-  __shared__ T sDB[(kDB && PIN) ? LY::DB : 1];
+  // only the strips of this launch's fields occupy LDS
+  __shared__ T sx[at_least1(strip_slot<FM>(kXOwn, 9)) * PXs::NP];
+  __shared__ T sy[at_least1(strip_slot<FM>(kYOwn, 9)) * PYs::NP];
+  __shared__ T s2[at_least1(int(kQz) + int(kEz)) * P3::NP];
+  __shared__ T sxc[kCori ? 2 * PXs::NP : 1];
+  __shared__ T syc[kCori ? 2 * PYs::NP : 1];
+  __shared__ T sdb[kDB ? PXs::NP + PYs::NP : 1];
   ZLOOP_BEGIN
   PlaneIdx<TX, TY, 3, 0> ix;
   PlaneIdx<TX, TY, 0, 3> iy;
@@ -118,69 +71,13 @@ __global__ __launch_bounds__(TX * TY) void zF(const BoxDev* __restrict__ boxes,
   // div B diffusion C_divb h^2 / dt grad(div B); absent without a time step
   const T kd = (kDB && dt > 0.0) ? T(double(ph.c_divb) * double(g.h) * double(g.h) / dt) : T(0);
 
-  // ---- accessors of the inline mode
-  auto IN8 = [&](int q, int x, int y) -> T { return sIn8[q * B8::NP + B8::at(x, y)]; };   // 0 rho 1 ln nu
-  auto IN5 = [&](int q, int x, int y) -> T { return sIn5[q * B5::NP + B5::at(x, y)]; };   // px py e bx by D pz
-  auto DER = [&](int q, int x, int y) -> T& { return sDer[q * B5::N + B5::at(x, y)]; };   // ux uy rxd ryd xl nu em lem lq
-  auto PQ = [&](int q, int x, int y) -> T& { return sPQ[q * B3::N + B3::at(x, y)]; };
-  auto SA = [&](int q, int x, int y) -> T {
-    switch (q) {
-      case DQ_PX: return IN5(0, x, y);
-      case DQ_PY: return IN5(1, x, y);
-      case DQ_E: return IN5(2, x, y);
-      case DQ_BX: return IN5(3, x, y);
-      case DQ_BY: return IN5(4, x, y);
-      case DQ_LNT: return IN8(1, x, y);
-      case DQ_UX: return DER(0, x, y);
-      case DQ_UY: return DER(1, x, y);
-      case DQ_RXD: return DER(2, x, y);
-      case DQ_RYD: return DER(3, x, y);
-      case DQ_XL: return DER(4, x, y);
-      case DQ_NU: return DER(5, x, y);
-      case DQ_EM: return DER(6, x, y);
-      case DQ_LEM: return DER(7, x, y);
-      case DQ_LQ: return DER(8, x, y);
-      case DQ_RHO: return IN8(0, x, y);
-      default: return IN5(5, x, y);   // DQ_D
-    }
-  };
-  T* const qsx = sDer;                        // Q strips, inline mode (alias the derived planes)
-  T* const qsy = sDer + 4 * PXs::NP;
-
-  // ---- strip accessors of the divergences (both modes)
-  auto X = [&](int q, int x) -> T {
-    if constexpr (PIN) {
-      if (q == 0) return IN5(0, x, ty);
-      if (q <= 4) return PQ(q - 1, x, ty);
-      return qsx[(q - 5) * PXs::NP + PXs::at(x, ty)];
-    } else {
-      return sx[strip_slot<FM>(kXOwnH, q) * PXs::NP + PXs::at(x, ty)];
-    }
-  };
-  auto Y = [&](int q, int y) -> T {
-    if constexpr (PIN) {
-      if (q == 0) return IN5(1, tx, y);
-      if (q <= 4) return PQ(q + 3, tx, y);
-      return qsy[(q - 5) * PYs::NP + PYs::at(tx, y)];
-    } else {
-      return sy[strip_slot<FM>(kYOwnH, q) * PYs::NP + PYs::at(tx, y)];
-    }
-  };
-  auto F2 = [&](int q, int x, int y) -> T {
-    if constexpr (PIN) return PQ(8 + q, x, y);
-    else return s2[(q && kQz) * P3::NP + P3::at(x, y)];
-  };
-  auto XC = [&](int q, int x) -> T {   // 0 px 1 pz
-    if constexpr (PIN) return IN5(q ? 6 : 0, x, ty);
-    else return sxc[q * PXs::NP + PXs::at(x, ty)];
-  };
-  auto YC = [&](int q, int y) -> T {   // 0 py 1 pz
-    if constexpr (PIN) return IN5(q ? 6 : 1, tx, y);
-    else return syc[q * PYs::NP + PYs::at(tx, y)];
-  };
-  T* const dbx = PIN ? sDB : sdb;
-  auto DBX = [&](int x) -> T { return dbx[PXs::at(x, ty)]; };
-  auto DBY = [&](int y) -> T { return dbx[PXs::NP + PYs::at(tx, y)]; };
+  auto X = [&](int q, int x) -> T { return sx[strip_slot<FM>(kXOwn, q) * PXs::NP + PXs::at(x, ty)]; };
+  auto Y = [&](int q, int y) -> T { return sy[strip_slot<FM>(kYOwn, q) * PYs::NP + PYs::at(tx, y)]; };
+  auto F2 = [&](int q, int x, int y) -> T { return s2[(q && kQz) * P3::NP + P3::at(x, y)]; };
+  auto XC = [&](int q, int x) -> T { return sxc[q * PXs::NP + PXs::at(x, ty)]; };   // 0 px 1 pz
+  auto YC = [&](int q, int y) -> T { return syc[q * PYs::NP + PYs::at(tx, y)]; };   // 0 py 1 pz
+  auto DBX = [&](int x) -> T { return sdb[PXs::at(x, ty)]; };
+  auto DBY = [&](int y) -> T { return sdb[PXs::NP + PYs::at(tx, y)]; };
 
   T acc[7][7];
 #pragma unroll
@@ -235,16 +132,8 @@ __global__ __launch_bounds__(TX * TY) void zF(const BoxDev* __restrict__ boxes,
       if (hasf<FM>(a)) update(a, o, Fv[a], uin[a], fin[a]);
   };
 
-  // inline mode: plane indices of the state's LDS planes
-  PlaneIdx<TX, TY, 8> i8;
-  PlaneIdx<TX, TY, 5> i5;
-  if constexpr (PIN) {
-    i8.init(b, it.x0, it.y0);
-    i5.init(b, it.x0, it.y0);
-  }
   PlaneIdx<TX, TY, 3> i3;
-  if constexpr (!PIN) i3.init(b, it.x0, it.y0);
-  constexpr int NPX = PXs::NP / NT, NPY = PYs::NP / NT;
+  i3.init(b, it.x0, it.y0);
 
   for (int r = it.z0 - 3; r <= it.z1 + 2; ++r) {
     const int kb = r - 3;
@@ -255,67 +144,34 @@ __global__ __launch_bounds__(TX * TY) void zF(const BoxDev* __restrict__ boxes,
       const int x = tx, y = ty;
       __syncthreads();
       // ---- loads of plane r
-      // pass Q's strips (inline mode: into registers, stored to LDS once the
-      // derived planes they alias are no longer read)
       const T* qxs[4] = {ws.q(QOUT_GZX), ws.q(QOUT_LZY), ws.q(QOUT_EY), ws.q(QOUT_QY)};
       const T* qys[4] = {ws.q(QOUT_GZY), ws.q(QOUT_LZX), ws.q(QOUT_EX), ws.q(QOUT_QX)};
-      T rqx[4][PIN ? NPX : 1], rqy[4][PIN ? NPY : 1];
-      if constexpr (PIN) {
-        const long long pb = b.off + (long long)k * b.nx * b.ny;
+      if (inch) {
+        const T* xs[8] = {f.p[1], ws.pq(POUT_GXX), ws.pq(POUT_GYX), ws.pq(POUT_LYZ),
+                          ws.pq(POUT_HX), qxs[0], qxs[1], qxs[2]};
+        const T* ys[8] = {f.p[2], ws.pq(POUT_GXY), ws.pq(POUT_LXZ), ws.pq(POUT_GYY),
+                          ws.pq(POUT_HY), qys[0], qys[1], qys[2]};
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          if (!inch && q < 3) continue;   // only Qy, Qx outside the own planes
-#pragma unroll
-          for (int i = 0; i < NPX; ++i) rqx[q][i] = qxs[q][pb + ix.off[i]];
-#pragma unroll
-          for (int i = 0; i < NPY; ++i) rqy[q][i] = qys[q][pb + iy.off[i]];
+        for (int q = 0; q < 8; ++q) {
+          if (hasf<FM>(kXOwn[q])) load_plane(sx + strip_slot<FM>(kXOwn, q) * PXs::NP, xs[q], b, ix, k);
+          if (hasf<FM>(kYOwn[q])) load_plane(sy + strip_slot<FM>(kYOwn, q) * PYs::NP, ys[q], b, iy, k);
         }
-        if (inch) {
-          load_plane(sIn8, f.p[0], b, i8, k);
-          load_plane(sIn8 + B8::NP, ws.arr(WS_LNT), b, i8, k);
-          const T* in5[6] = {f.p[1], f.p[2], f.p[4], f.p[5], f.p[6], ws.arr(WS_D)};
-#pragma unroll
-          for (int q = 0; q < 6; ++q) load_plane(sIn5 + q * B5::NP, in5[q], b, i5, k);
-        }
-        if (kCori) {
-          if (!inch) {
-            load_plane(sIn5, f.p[1], b, i5, k);
-            load_plane(sIn5 + B5::NP, f.p[2], b, i5, k);
-          }
-          load_plane(sIn5 + 6 * B5::NP, f.p[3], b, i5, k);
-        }
-        if (kDB && kd != T(0)) {
-          load_plane(sDB, ws.arr(WS_DIVB), b, ix, k);
-          load_plane(sDB + PXs::NP, ws.arr(WS_DIVB), b, iy, k);
-        }
-      } else {
-        if (inch) {
-          const T* xs[8] = {f.p[1], ws.pq(POUT_GXX), ws.pq(POUT_GYX), ws.pq(POUT_LYZ),
-                            ws.pq(POUT_HX), qxs[0], qxs[1], qxs[2]};
-          const T* ys[8] = {f.p[2], ws.pq(POUT_GXY), ws.pq(POUT_LXZ), ws.pq(POUT_GYY),
-                            ws.pq(POUT_HY), qys[0], qys[1], qys[2]};
-#pragma unroll
-          for (int q = 0; q < 8; ++q) {
-            if (hasf<FM>(kXOwnH[q])) load_plane(sx + strip_slot<FM>(kXOwnH, q) * PXs::NP, xs[q], b, ix, k);
-            if (hasf<FM>(kYOwnH[q])) load_plane(sy + strip_slot<FM>(kYOwnH, q) * PYs::NP, ys[q], b, iy, k);
-          }
-          if (kQz) load_plane(s2, ws.pq(POUT_QZ), b, i3, k);
-          if (kEz) load_plane(s2 + kQz * P3::NP, ws.pq(POUT_EZ), b, i3, k);
-        }
-        if (hasf<FM>(4)) {
-          load_plane(sx + strip_slot<FM>(kXOwnH, 8) * PXs::NP, qxs[3], b, ix, k);
-          load_plane(sy + strip_slot<FM>(kYOwnH, 8) * PYs::NP, qys[3], b, iy, k);
-        }
-        if (kDB && kd != T(0)) {
-          load_plane(sdb, ws.arr(WS_DIVB), b, ix, k);
-          load_plane(sdb + PXs::NP, ws.arr(WS_DIVB), b, iy, k);
-        }
-        if constexpr (kCori) {
-          load_plane(sxc, f.p[1], b, ix, k);
-          load_plane(sxc + PXs::NP, f.p[3], b, ix, k);
-          load_plane(syc, f.p[2], b, iy, k);
-          load_plane(syc + PYs::NP, f.p[3], b, iy, k);
-        }
+        if (kQz) load_plane(s2, ws.pq(POUT_QZ), b, i3, k);
+        if (kEz) load_plane(s2 + kQz * P3::NP, ws.pq(POUT_EZ), b, i3, k);
+      }
+      if (hasf<FM>(4)) {
+        load_plane(sx + strip_slot<FM>(kXOwn, 8) * PXs::NP, qxs[3], b, ix, k);
+        load_plane(sy + strip_slot<FM>(kYOwn, 8) * PYs::NP, qys[3], b, iy, k);
+      }
+      if (kDB && kd != T(0)) {
+        load_plane(sdb, ws.arr(WS_DIVB), b, ix, k);
+        load_plane(sdb + PXs::NP, ws.arr(WS_DIVB), b, iy, k);
+      }
+      if constexpr (kCori) {
+        load_plane(sxc, f.p[1], b, ix, k);
+        load_plane(sxc + PXs::NP, f.p[3], b, ix, k);
+        load_plane(syc, f.p[2], b, iy, k);
+        load_plane(syc + PYs::NP, f.p[3], b, iy, k);
       }
       // own-column values of plane r for the z divergences
       T cur[7];
@@ -331,11 +187,9 @@ __global__ __launch_bounds__(TX * TY) void zF(const BoxDev* __restrict__ boxes,
       if (inch) {
         if (hasf<FM>(3)) dpz = ws.q(QOUT_DPZ)[o];
         if (hasf<FM>(4)) czz_ = ws.q(QOUT_CZZ)[o];
-        if constexpr (!PIN) {
-          if (hasf<FM>(1)) dpx = ws.pq(POUT_DPX)[o];
-          if (hasf<FM>(2)) dpy = ws.pq(POUT_DPY)[o];
-          if (hasf<FM>(4)) qc = ws.pq(POUT_QC)[o];
-        }
+        if (hasf<FM>(1)) dpx = ws.pq(POUT_DPX)[o];
+        if (hasf<FM>(2)) dpy = ws.pq(POUT_DPY)[o];
+        if (hasf<FM>(4)) qc = ws.pq(POUT_QC)[o];
       }
       // Bz's dU and f at this plane, fetched with the planes
       T bz_u = T(0), bz_f = T(0);
@@ -344,71 +198,6 @@ __global__ __launch_bounds__(TX * TY) void zF(const BoxDev* __restrict__ boxes,
         bz_f = f.p[7][o];
       }
       __syncthreads();
-      if constexpr (PIN) {
-        if (inch) {
-          // ---- derived planes over the halo-5 box
-          const T lpa = (tm & T_LNP) ? ws.lnpav[b.poff + k] : T(0);
-          for (int t = threadIdx.x; t < B5::N; t += NT) {
-            const int yy = t / B5::W, xx = t - yy * B5::W;
-            const int xq = xx - 5, yq = yy - 5;
-            const T rxd = op6<0, 0, T>([&](int m) { return IN8(0, xq + m, yq); }, T(0));
-            const T ryd = op6<0, 0, T>([&](int m) { return IN8(0, xq, yq + m); }, T(0));
-            sDer[0 * B5::N + t] = IN5(0, xq, yq) / rxd;
-            sDer[1 * B5::N + t] = IN5(1, xq, yq) / ryd;
-            sDer[2 * B5::N + t] = rxd;
-            sDer[3 * B5::N + t] = ryd;
-            sDer[4 * B5::N + t] = op6<0, 0, T>([&](int m) { return IN8(1, xq + m, yq); }, T(0));
-            sDer[5 * B5::N + t] = exp(IN8(1, xq, yq));
-            const T emv = IN5(2, xq, yq) / IN8(0, xq, yq);
-            sDer[6 * B5::N + t] = emv;
-            sDer[7 * B5::N + t] = log(emv);
-            if (tm & T_LNP) sDer[8 * B5::N + t] = log(ph.gamma1 * IN5(2, xq, yq)) - lpa;
-          }
-          __syncthreads();
-          // ---- pass P's quantities: z-edge and face terms on the box
-          // [-2, TX+3) x [-2, TY+3), centre terms on [-3, TX+2) x [-3, TY+2)
-          constexpr int WE = TX + 5, NE = (TX + 5) * (TY + 5);
-          for (int t = threadIdx.x; t < NE; t += NT) {
-            const int yy = t / WE, xx = t - yy * WE;
-            const int xq = xx - 2, yq = yy - 2;
-            T gxy, gyx, ez, lxz, lyz, qz;
-            zedge_q<T>(SA, xq, yq, g, ph, gxy, gyx, ez, lxz, lyz, qz);
-            PQ(1, xq, yq) = gyx;
-            PQ(2, xq, yq) = lyz;
-            PQ(3, xq, yq) = xface_h<T>(SA, xq, yq, g, ph);
-            PQ(4, xq, yq) = gxy;
-            PQ(5, xq, yq) = lxz;
-            PQ(7, xq, yq) = yface_h<T>(SA, xq, yq, g, ph);
-            PQ(8, xq, yq) = qz;
-            PQ(9, xq, yq) = ez;
-          }
-          constexpr int WC = TX + 5, NC = (TX + 5) * (TY + 5);
-          for (int t = threadIdx.x; t < NC; t += NT) {
-            const int yy = t / WC, xx = t - yy * WC;
-            const int xq = xx - 3, yq = yy - 3;
-            T gxx, gyy, qcx;
-            centre_q<T>(SA, xq, yq, g, ph, gxx, gyy, qcx);
-            PQ(0, xq, yq) = gxx;
-            PQ(6, xq, yq) = gyy;
-          }
-          if (own) {
-            T gxx, gyy;
-            centre_q<T>(SA, x, y, g, ph, gxx, gyy, qc);
-            face_dp<T>(SA, x, y, g, ph, (tm & T_LNP) ? T(exp(lpa)) : T(0), dpx, dpy);
-          }
-        }
-        __syncthreads();
-        // ---- pass Q's strips into LDS (over the derived planes)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          if (!inch && q < 3) continue;
-#pragma unroll
-          for (int i = 0; i < NPX; ++i) qsx[q * PXs::NP + (int)threadIdx.x + i * NT] = rqx[q][i];
-#pragma unroll
-          for (int i = 0; i < NPY; ++i) qsy[q * PYs::NP + (int)threadIdx.x + i * NT] = rqy[q][i];
-        }
-        __syncthreads();
-      }
       if (inch) {
         if (hasf<FM>(0) && cont)
           acc[0][3] += -(op6<1, 1, T>([&](int m) { return X(0, x + m); }, g.hxi) +
@@ -547,75 +336,51 @@ static int resident_groups(const void* kern, int block, int ncu) {
 
 int zresident_groups(const void* kern, int block, int ncu) { return resident_groups(kern, block, ncu); }
 
-template <class T, int TX, int TY, bool PERS, unsigned FM, bool PIN, class G>
+template <class T, int TX, int TY, bool PERS, unsigned FM, class G>
 static void zF_one(const G& grid, dim3 block, const ZLaunch& L, const ZStageArgs<T>& a, int* q) {
-  hipLaunchKernelGGL((zF<T, TX, TY, PERS, FM, PIN>), grid((const void*)zF<T, TX, TY, PERS, FM, PIN>), block, 0,
+  hipLaunchKernelGGL((zF<T, TX, TY, PERS, FM>), grid((const void*)zF<T, TX, TY, PERS, FM>), block, 0,
                      L.stream, L.boxes, L.fitems, L.nfitems, a.ztab, q, a.f, a.w, a.ph, a.du, a.du_mode, a.f_out,
                      a.alpha, a.beta, a.dt_dev, a.dt_host);
 }
 // The momentum launch's mask with the Coriolis bit (8) set; others unchanged.
 template <unsigned FM> constexpr unsigned with_cori() { return (FM & 0x0Eu) ? (FM | 0x100u) : FM; }
-// stored mode: one launch per mask, each with its own 8 queue counters
+// one launch per mask, each with its own 8 queue counters
 template <class T, int TX, int TY, bool PERS, class G, size_t... I>
 static void zF_launch(const G& grid, dim3 block, const ZLaunch& L, const ZStageArgs<T>& a, int* q,
                       std::index_sequence<I...>) {
   if (a.ph.terms & T_CORI)
-    (zF_one<T, TX, TY, PERS, with_cori<kFMasks[I]>(), false>(grid, block, L, a, q ? q + 32 + 8 * int(I) : q), ...);
+    (zF_one<T, TX, TY, PERS, with_cori<kFMasks[I]>()>(grid, block, L, a, q ? q + 32 + 8 * int(I) : q), ...);
   else
-    (zF_one<T, TX, TY, PERS, kFMasks[I], false>(grid, block, L, a, q ? q + 32 + 8 * int(I) : q), ...);
+    (zF_one<T, TX, TY, PERS, kFMasks[I]>(grid, block, L, a, q ? q + 32 + 8 * int(I) : q), ...);
 }
 
 // Pass F, in its own tile shape (L.ftile) over its own work items.
 template <class T, int TX, int TY, bool PERS>
-static bool launch_final_t(const ZLaunch& L, const ZStageArgs<T>& a, int* q) {
+static void launch_final_t(const ZLaunch& L, const ZStageArgs<T>& a, int* q) {
   const int n = L.nfitems;
   auto grid = [&](const void* kern) {
     if (!q) return dim3(8 * ((n + 7) / 8));
     const int r = std::min(n, resident_groups(kern, TX * TY, L.ncu));
     return dim3(std::max(8, r - r % 8));
   };
-  if (!L.fuse) {
-    zF_launch<T, TX, TY, PERS>(grid, dim3(TX * TY), L, a, q, std::make_index_sequence<kNFMasks>{});
-    return true;
-  }
-  if constexpr (pin_fits<T, TX, TY>()) {
-    if (a.ph.terms & T_CORI) zF_one<T, TX, TY, PERS, 0x1FFu, true>(grid, dim3(TX * TY), L, a, q ? q + 32 : q);
-    else zF_one<T, TX, TY, PERS, 0xFFu, true>(grid, dim3(TX * TY), L, a, q ? q + 32 : q);
-    return true;
-  }
-  return false;
+  zF_launch<T, TX, TY, PERS>(grid, dim3(TX * TY), L, a, q, std::make_index_sequence<kNFMasks>{});
 }
 
 template <class T, bool PERS>
-bool launch_final(const ZLaunch& L, const ZStageArgs<T>& a, int* q) {
+void launch_final(const ZLaunch& L, const ZStageArgs<T>& a, int* q) {
   switch (L.ftile) {
-    case ZTILE_32x8: return launch_final_t<T, 32, 8, PERS>(L, a, q);
-    case ZTILE_16x16: return launch_final_t<T, 16, 16, PERS>(L, a, q);
-    case ZTILE_16x8: return launch_final_t<T, 16, 8, PERS>(L, a, q);
-    case ZTILE_64x8: return launch_final_t<T, 64, 8, PERS>(L, a, q);
-    case ZTILE_32x16: return launch_final_t<T, 32, 16, PERS>(L, a, q);
-    default: return launch_final_t<T, 64, 4, PERS>(L, a, q);
+    case ZTILE_32x8: launch_final_t<T, 32, 8, PERS>(L, a, q); break;
+    case ZTILE_16x16: launch_final_t<T, 16, 16, PERS>(L, a, q); break;
+    case ZTILE_16x8: launch_final_t<T, 16, 8, PERS>(L, a, q); break;
+    case ZTILE_64x8: launch_final_t<T, 64, 8, PERS>(L, a, q); break;
+    case ZTILE_32x16: launch_final_t<T, 32, 16, PERS>(L, a, q); break;
+    default: launch_final_t<T, 64, 4, PERS>(L, a, q); break;
   }
 }
 
-bool final_fuse_ok(int tile, size_t esize) {
-  auto fits = [&](auto tag) -> bool {
-    using T = decltype(tag);
-    switch (tile) {
-      case ZTILE_32x8: return pin_fits<T, 32, 8>();
-      case ZTILE_16x16: return pin_fits<T, 16, 16>();
-      case ZTILE_16x8: return pin_fits<T, 16, 8>();
-      case ZTILE_64x8: return pin_fits<T, 64, 8>();
-      case ZTILE_32x16: return pin_fits<T, 32, 16>();
-      default: return pin_fits<T, 64, 4>();
-    }
-  };
-  return esize == sizeof(float) ? fits(float()) : fits(double());
-}
-
-template bool launch_final<float, false>(const ZLaunch&, const ZStageArgs<float>&, int*);
-template bool launch_final<float, true>(const ZLaunch&, const ZStageArgs<float>&, int*);
-template bool launch_final<double, false>(const ZLaunch&, const ZStageArgs<double>&, int*);
-template bool launch_final<double, true>(const ZLaunch&, const ZStageArgs<double>&, int*);
+template void launch_final<float, false>(const ZLaunch&, const ZStageArgs<float>&, int*);
+template void launch_final<float, true>(const ZLaunch&, const ZStageArgs<float>&, int*);
+template void launch_final<double, false>(const ZLaunch&, const ZStageArgs<double>&, int*);
+template void launch_final<double, true>(const ZLaunch&, const ZStageArgs<double>&, int*);
 
 }  // namespace smhd

@@ -979,11 +979,9 @@ static void launch_zstage_m(const ZLaunch& L, const ZStageArgs<T>& a) {
     hipLaunchKernelGGL((zQ<T, TX, TY, PERS, QM_ZC>), grid((const void*)zQ<T, TX, TY, PERS, QM_ZC>), block, 0,
                        L.stream, L.boxes, L.items, n, a.ztab, q ? q + 32 + 8 * kNFMasks : q, a.f, a.ph, a.w,
                        a.lnavg, a.w.lnpav);
-  if (!L.fuse) {   // inline mode: pass F forms pass P's quantities itself
-    L.at(PASS_CF);
-    hipLaunchKernelGGL((zP<T, TX, TY, PERS>), grid((const void*)zP<T, TX, TY, PERS>), block, 0, L.stream,
-                       L.boxes, L.items, n, a.ztab, q ? q + 24 : q, a.f, a.ph, a.w);
-  }
+  L.at(PASS_CF);
+  hipLaunchKernelGGL((zP<T, TX, TY, PERS>), grid((const void*)zP<T, TX, TY, PERS>), block, 0, L.stream, L.boxes,
+                     L.items, n, a.ztab, q ? q + 24 : q, a.f, a.ph, a.w);
   L.at(PASS_FINAL);
   launch_final<T, PERS>(L, a, q);
   L.at(PASS_END);

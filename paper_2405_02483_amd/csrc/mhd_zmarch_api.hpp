@@ -68,7 +68,6 @@ struct ZLaunch {
   int ftile;
   int* queue;             // device, kQueueInts counters (persistent mode)
   int persistent;         // 0: one workgroup per item; 1: item queues
-  int fuse;               // 1: pass F forms pass P's quantities itself (no pass P)
   int ncu;                // compute units of the device
   int nbox, nplanes;      // boxes; z planes of all boxes
   hipStream_t stream;
@@ -99,11 +98,8 @@ template <class T> struct ZStageArgs {
 
 template <class T> void launch_zstage(const ZLaunch& L, const ZStageArgs<T>& a);
 
-// Pass F (mhd_zfinal.hip) in its tile shape L.ftile and mode L.fuse; false
-// if that shape has no inline variant for T (its LDS would not fit).
-template <class T, bool PERS> bool launch_final(const ZLaunch& L, const ZStageArgs<T>& a, int* q);
-// Whether pass F of tile shape `tile` has an inline variant for element size esize.
-bool final_fuse_ok(int tile, size_t esize);
+// Pass F (mhd_zfinal.hip) in its tile shape L.ftile.
+template <class T, bool PERS> void launch_final(const ZLaunch& L, const ZStageArgs<T>& a, int* q);
 // Workgroups of a kernel that fit on the device at once (cached per kernel).
 int zresident_groups(const void* kern, int block, int ncu);
 

@@ -22,7 +22,6 @@ __all__ = [
     "mhd_box_offset", "mhd_rhs", "mhd_rhs_noalloc", "mhd_step", "mhd_step_adjoint",
     "mhd_reductions", "mhd_profile", "mhd_profile_read", "mhd_last_dt", "mhd_set_tile",
     "mhd_set_launch", "mhd_get_launch", "mhd_set_final_tile", "mhd_get_final_tile",
-    "mhd_set_fusion", "mhd_get_fusion",
     "mhd_autotune", "mhd_rhs_adjoint",
     "PASS_NAMES", "TILES", "Context",
 ]
@@ -145,10 +144,6 @@ def load():
     L.mhd_set_final_tile.restype = ctypes.c_int
     L.mhd_get_final_tile.argtypes = [vp, ctypes.POINTER(i32)]
     L.mhd_get_final_tile.restype = ctypes.c_int
-    L.mhd_set_fusion.argtypes = [vp, i32]
-    L.mhd_set_fusion.restype = ctypes.c_int
-    L.mhd_get_fusion.argtypes = [vp, ctypes.POINTER(i32)]
-    L.mhd_get_fusion.restype = ctypes.c_int
     L.mhd_autotune.argtypes = [vp, _P8, _P8, i32, ctypes.POINTER(ctypes.c_double)]
     L.mhd_autotune.restype = ctypes.c_int
     L.mhd_profile.argtypes = [vp, i32]
@@ -275,16 +270,6 @@ def mhd_get_final_tile(ctx):
     t = ctypes.c_int32()
     _check(load().mhd_get_final_tile(ctx, ctypes.byref(t)), ctx)
     return t.value
-
-
-def mhd_set_fusion(ctx, fuse):
-    _check(load().mhd_set_fusion(ctx, int(fuse)), ctx)
-
-
-def mhd_get_fusion(ctx):
-    u = ctypes.c_int32()
-    _check(load().mhd_get_fusion(ctx, ctypes.byref(u)), ctx)
-    return u.value
 
 
 def mhd_autotune(ctx, f, dfdt, reps, *, dtype, n):
@@ -443,13 +428,6 @@ class Context:
     def get_final_tile(self):
         return {v: k for k, v in TILES.items()}[mhd_get_final_tile(self.ctx)]
 
-    def set_fusion(self, fuse):
-        """1: pass F forms pass P's quantities itself (pass P not launched);
-        0: pass P stores them (set_tile / set_launch reset it to 0)."""
-        mhd_set_fusion(self.ctx, fuse)
-
-    def get_fusion(self):
-        return mhd_get_fusion(self.ctx)
 
     def autotune(self, f, reps=3, dfdt=None):
         """Times every tile shape and launch mode on f and keeps the fastest

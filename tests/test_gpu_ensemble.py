@@ -122,23 +122,18 @@ def test_final_pass_tile_gives_identical_bits(dtype):
     fd = ctx.upload(fields)
     ctx.step(fd, 0.0, 2)
     ref = ([t.clone() for t in fd], ctx.last_dt())
-    cfgs = [("16x16", "64x8", 0, 0), ("64x8", "16x8", 1, 0), ("32x8", "64x4", 1, 0),
-            ("64x8", "16x16", 0, 1), ("32x16", "16x8", 1, 1)]
-    if dtype == torch.float32:
-        cfgs += [("16x8", "32x16", 1, 1), ("32x8", "64x8", 0, 1)]
-    for tile, ftile, persistent, fuse in cfgs:
+    for tile, ftile, persistent in (("16x16", "64x8", 0), ("64x8", "16x8", 1), ("32x8", "64x4", 1),
+                                    ("32x16", "16x16", 0), ("16x8", "32x16", 1)):
         ctx.set_launch(tile, persistent)
         ctx.set_final_tile(ftile)
-        ctx.set_fusion(fuse)
         assert ctx.get_launch() == (tile, persistent) and ctx.get_final_tile() == ftile
-        assert ctx.get_fusion() == fuse
         fd = ctx.upload(fields)
         ctx.step(fd, 0.0, 2)
         assert ctx.last_dt() == ref[1]
         for a, b in zip(fd, ref[0]):
-            assert torch.equal(a, b), (tile, ftile, persistent, fuse)
+            assert torch.equal(a, b), (tile, ftile, persistent)
     ctx.set_launch("16x8", 0)
-    assert ctx.get_final_tile() == "16x8" and ctx.get_fusion() == 0
+    assert ctx.get_final_tile() == "16x8"
     for bad in (-1, len(TILES)):
         with pytest.raises(MhdError) as ei:
             ctx.set_final_tile(bad)

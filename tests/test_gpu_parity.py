@@ -254,39 +254,27 @@ def test_courant_step_on_device_f64(case):
 
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
 def test_tile_shapes_give_identical_bits(dtype):
-    """Every tile shape, with pass F in the stored mode and (where built)
-    the inline mode, gives the same bits over two RK steps."""
-    from paper_2405_02483_amd.lib import TILES, MhdError, MHD_EUNSUPPORTED
+    from paper_2405_02483_amd.lib import TILES
     f, box, prm = _case("turb_ragged")
     ctx = _ctx(box, prm, dtype)
     ref = None
-    ninline = 0
     for name in TILES:
-        for fuse in (0, 1):
-            ctx.set_tile(name)
-            if fuse:
-                try:
-                    ctx.set_fusion(1)
-                except MhdError as e:
-                    assert e.code == MHD_EUNSUPPORTED
-                    continue
-                ninline += 1
-            fd = ctx.upload([f])
-            ctx.step(fd, 2e-3, 2)
-            if ref is None:
-                ref = [t.clone() for t in fd]
-            else:
-                for a, b in zip(fd, ref):
-                    assert torch.equal(a, b), (name, fuse)
-    assert ninline >= (len(TILES) if dtype == torch.float32 else 2)
+        ctx.set_tile(name)
+        fd = ctx.upload([f])
+        ctx.step(fd, 2e-3, 2)
+        if ref is None:
+            ref = [t.clone() for t in fd]
+        else:
+            for a, b in zip(fd, ref):
+                assert torch.equal(a, b), name
     ctx.close()
 
 
 @pytest.mark.parametrize("case", ["ot32", "strat", "turb_aniso"])
-def test_inline_pass_f_parity(case):
-    """Pass F forming pass P's quantities itself: two steps against the
-    oracle (float64 1e-12, float32 1e-5) with the optional terms that touch
-    pass F (cooling, Coriolis, the ln(P/P_aver) gradient, div B diffusion)."""
+def test_optional_terms_two_steps(case):
+    """Two steps against the oracle (float64 1e-12, float32 1e-5) with every
+    optional term that passes P and F evaluate (cooling, Coriolis, the
+    ln(P/P_aver) gradient, div B diffusion), in the 16x16 and 32x16 shapes."""
     from paper_2405_02483_amd.lib import T_COOL, T_CORI, T_LNP, T_DIVB
     f, box, prm = _case(case)
     prm = dict(prm, terms=O.T_ALL | T_COOL | T_CORI | T_LNP | T_DIVB, e_cool=1.2, t_cool=0.6,
@@ -300,7 +288,6 @@ def test_inline_pass_f_parity(case):
     for dtype, tol, tile in ((torch.float64, TOL64, "16x16"), (torch.float32, 1e-5, "32x16")):
         ctx = _ctx(box, prm, dtype)
         ctx.set_tile(tile)
-        ctx.set_fusion(1)
         fd = ctx.upload([f])
         ctx.step(fd, dt, 2)
         got = ctx.box_view(fd, 0)

@@ -47,18 +47,6 @@ def _cases():
     return out
 
 
-def _try_fusion(ctx):
-    """Switch pass F to its inline mode; False where the tile shape has no
-    inline variant for the dtype."""
-    from paper_2405_02483_amd.lib import MhdError, MHD_EUNSUPPORTED
-    try:
-        ctx.set_fusion(1)
-    except MhdError as e:
-        assert e.code == MHD_EUNSUPPORTED
-        return False
-    return True
-
-
 def _aniso(box, seed):
     """The box with each side scaled by its own random factor in [0.6, 1.6]."""
     r = random.Random(seed)
@@ -113,24 +101,21 @@ def test_rhs_random_sizes_all_tiles(case, walls, nx, ny, nz, ftiles):
         first = None
         for tile in names:
             for pers in (0, 1):
-                for fuse in (0, 1):
-                    ftile = names[ftiles[k % len(ftiles)] % len(names)]
-                    k += 1
-                    ctx.set_launch(tile, pers)
-                    ctx.set_final_tile(ftile)
-                    if fuse and not _try_fusion(ctx):
-                        continue
-                    got = ctx.box_view(ctx.rhs(fd), 0)
-                    if walls:
-                        got = interior(got, box)
-                    errs = _errors(got, want, scale)
-                    assert max(errs) < TOL[dtype], (dtype, tile, pers, ftile, fuse, errs)
-                    # every launch configuration gives the same bits
-                    if first is None:
-                        first = [t.clone() for t in got]
-                    else:
-                        for a, b in zip(first, got):
-                            assert torch.equal(a, b), (dtype, tile, pers, ftile, fuse)
+                ftile = names[ftiles[k % len(ftiles)] % len(names)]
+                k += 1
+                ctx.set_launch(tile, pers)
+                ctx.set_final_tile(ftile)
+                got = ctx.box_view(ctx.rhs(fd), 0)
+                if walls:
+                    got = interior(got, box)
+                errs = _errors(got, want, scale)
+                assert max(errs) < TOL[dtype], (dtype, tile, pers, ftile, errs)
+                # every launch configuration gives the same bits
+                if first is None:
+                    first = [t.clone() for t in got]
+                else:
+                    for a, b in zip(first, got):
+                        assert torch.equal(a, b), (dtype, tile, pers, ftile)
         ctx.close()
 
 
@@ -186,8 +171,6 @@ def test_step_random_mixed_ensemble(cool):
         tile, pers, ftile = rng.choice(names), rng.randrange(2), rng.choice(names)
         ctx.set_launch(tile, pers)
         ctx.set_final_tile(ftile)
-        if dtype == torch.float32:
-            _try_fusion(ctx)
         fd = ctx.upload([c[0] for c in cases])
         ctx.step(fd, dt, 1)
         for b, (f, box, _) in enumerate(cases):
