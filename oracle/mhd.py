@@ -50,6 +50,18 @@ garbled:
   the up derivatives and its gradient on the faces from the down
   derivatives.  It needs the step's dt, so only the RK step (or a right-hand
   side given dt) includes it.
+* Section 6.1.1, maximum over three or five cells: with T_MAX5 the
+  viscosity is spread by the maximum over five adjacent cells along each
+  axis (the three-cell maximum applied twice), then smoothed by the
+  three-cell mean as before.
+* eq. nusmag, eq. nuij2 (Smagorinsky): nu_S = c_smag [2(sum_i S_ii^2 -
+  (div u)^2/3 + sum_{i!=j} S_ij^2)]^(1/2), a rate, with the off-diagonal
+  S_ij interpolated from its edge to the cell centre before squaring.  It
+  enters the same chain as the Richtmyer-Morton viscosity as the speed
+  h_min nu_S, added before the maximum and the mean (the paper combines the
+  two "in varying proportions"), so that nu_ii = dx_i h_min <nu_S>: eq.
+  nuij2's (dx_i)^2 <nu> on cubic cells.  The depth factor the paper applies
+  "sometimes" in stratified runs is not used.
 * eq. mom, Coriolis force: -2 rho Omega x u = -2 Omega x p, with each
   momentum component carried to the face of the component it drives by the
   staggered interpolations (e.g. p_z at an x-face is xdn(zup(p_z))).
@@ -64,12 +76,12 @@ from .stagger import Ops, AX_X, AX_Y, AX_Z
 __all__ = [
     "T_CONT", "T_ADV", "T_PRES", "T_VISC", "T_LORENTZ", "T_INDUCT",
     "T_RESIST", "T_EDIFF", "T_GRAV", "T_ALL", "T_HD", "T_IDEAL", "T_COOL", "T_CORI",
-    "T_EDIFFAV", "T_LNP", "T_DIVB",
+    "T_EDIFFAV", "T_LNP", "T_DIVB", "T_SMAG", "T_MAX5",
     "ALPHA", "BETA", "Grid", "Params", "ghost_fill", "rhs", "rhs_nofill",
     "step", "rk3", "courant", "stats", "step_vjp", "rhs_vjp", "FIELDS",
     "interior_slices", "smoothed_viscosity", "newton_cooling", "coriolis",
     "horizontal_ln_mean", "pressure_gradient_ln", "viscosity_lengths",
-    "edge_viscosity",
+    "edge_viscosity", "smagorinsky_rate",
 ]
 
 FIELDS = ("rho", "px", "py", "pz", "e", "bx", "by", "bz")
@@ -91,6 +103,8 @@ T_CORI = 1 << 10     # Coriolis force (eq. mom); not part of T_ALL
 T_EDIFFAV = 1 << 11  # with T_EDIFF: diffuse fluctuations about the plane mean (eq. ediffav)
 T_LNP = 1 << 12      # with T_PRES: grad P through ln(P / P_aver) (eq. pressure)
 T_DIVB = 1 << 13     # div B diffusion C_divb h^2 / dt grad(div B); needs the step's dt
+T_SMAG = 1 << 14     # Smagorinsky viscosity added to the speed-like one (eq. nusmag)
+T_MAX5 = 1 << 15     # spread the viscosity by the maximum over five cells (do_max5)
 T_HD = T_CONT | T_ADV | T_PRES | T_VISC | T_EDIFF
 T_IDEAL = T_CONT | T_ADV | T_PRES | T_LORENTZ | T_INDUCT
 
@@ -163,6 +177,7 @@ class Params:
     cool_cut: int = 0         # 0 none, 1 low-density cut-off, 2 high-density
     omega: tuple = (0.0, 0.0, 0.0)   # rotation vector of the Coriolis force
     c_divb: float = 0.0       # coefficient of the div B diffusion (< 0.11)
+    c_smag: float = 0.0       # Smagorinsky constant (eq. nusmag; &pde Csmag)
 
 
 def interior_slices(grid):
@@ -209,12 +224,35 @@ def smoothed_viscosity(f, grid, par, O=None):
         nus = (par.nu1 * _safe_norm3(ubx, uby, ubz)
                + par.nu3 * (cs + ca)
                + par.nu2 * h * _relu(-D))
-    m = O.max3(O.max3(O.max3(nus, AX_X), AX_Y), AX_Z)
+        if par.terms & T_SMAG:
+            nus = nus + par.c_smag * h * smagorinsky_rate(ux, uy, uz, D, O)
+    mx = O.max5 if par.terms & T_MAX5 else O.max3
+    m = mx(mx(mx(nus, AX_X), AX_Y), AX_Z)
     nt = O.mean3(O.mean3(O.mean3(m, AX_X), AX_Y), AX_Z)
     nt = torch.where(nt > NU_FLOOR, nt, torch.full_like(nt, NU_FLOOR))
     pieces = dict(P=P, ux=ux, uy=uy, uz=uz, ub=(ubx, uby, ubz),
                   bb=(bbx, bby, bbz), D=D, cs=cs, ca=ca, nus=nus)
     return nt, pieces
+
+
+def smagorinsky_rate(ux, uy, uz, D, O):
+    """The Smagorinsky viscosity rate of eq. nusmag without its constant,
+    [2(S_xx^2 + S_yy^2 + S_zz^2 - D^2/3 + 2(S_xy^2 + S_xz^2 + S_yz^2))]^(1/2)
+    at cell centres: S_aa = ddaup(u_a); S_ab = (1/2)(ddbdn(u_a) + ddadn(u_b))
+    on its edge, interpolated to the centre (up along a and b)."""
+    sxx, syy, szz = O.ddxup(ux), O.ddyup(uy), O.ddzup(uz)
+    sxy = O.yup(O.xup(0.5 * (O.ddydn(ux) + O.ddxdn(uy))))
+    sxz = O.zup(O.xup(0.5 * (O.ddzdn(ux) + O.ddxdn(uz))))
+    syz = O.zup(O.yup(0.5 * (O.ddzdn(uy) + O.ddydn(uz))))
+    s2 = 2.0 * (sxx * sxx + syy * syy + szz * szz - D * D / 3.0
+                + 2.0 * (sxy * sxy + sxz * sxz + syz * syz))
+    return _safe_sqrt(s2)
+
+
+def _safe_sqrt(s):
+    """sqrt(max(s, 0)) with zero derivative where s <= 0."""
+    pos = s > 0
+    return torch.where(pos, torch.sqrt(torch.where(pos, s, torch.ones_like(s))), torch.zeros_like(s))
 
 
 def viscosity_lengths(grid, par):

@@ -171,6 +171,12 @@ class Ops:
         lo, hi = _shift(f, -1, axis), _shift(f, 1, axis)
         return torch.stack([lo, f, hi]).max(dim=0).values
 
+    def max5(self, f, axis):
+        """Maximum over the five adjacent cells i-2 .. i+2 (over the available
+        ones at the ends of a wall-bounded axis): the three-cell maximum
+        applied twice, which also fixes the adjoint's choice in a tie."""
+        return self.max3(self.max3(f, axis), axis)
+
     def mean3(self, f, axis):
         """Average over the three adjacent cells (over the available ones at
         the ends of a wall-bounded axis)."""
