@@ -102,6 +102,17 @@ enum {
  * mhd_step includes it and mhd_rhs (no dt) leaves it out.  Not part of
  * MHD_T_ALL; the adjoint entry points return MHD_EUNSUPPORTED.             */
 #define MHD_T_DIVB     (1u << 13)
+/* Smagorinsky viscosity (eq. nusmag): the rate nu_S = c_smag [2(sum_i S_ii^2
+ * - (div u)^2/3 + sum_{i!=j} S_ij^2)]^(1/2), off-diagonal strain
+ * interpolated to the cell centre, added to the Richtmyer-Morton viscosity
+ * as the speed h_min nu_S before the maximum and mean, so that
+ * nu_ii = dx_i h_min <nu_S> (eq. nuij2's (dx_i)^2 <nu> on cubic cells).
+ * Ignored with nu_const > 0.  Not part of MHD_T_ALL.                       */
+#define MHD_T_SMAG     (1u << 14)
+/* Spread the viscosity by the maximum over five adjacent cells along each
+ * axis instead of three (Section 6.1.1, &pde do_max5).  Not part of
+ * MHD_T_ALL.                                                               */
+#define MHD_T_MAX5     (1u << 15)
 
 /* One box of the mesh (&grid namelist: mx, my, mz, sx, sy, sz). */
 typedef struct {
@@ -141,6 +152,8 @@ typedef struct {
     double c_divb;          /* with MHD_T_DIVB: >= 0 and at most the RK3 limit
                                2.5127 / (K^2 h_min^2 sum_a 1/h_a^2), K = 2.48333
                                (0.1358 on cubic cells); MHD_EINVAL above it    */
+    double c_smag;          /* with MHD_T_SMAG: the Smagorinsky constant, finite
+                               and >= 0 (&pde Csmag, typically 0.1 - 0.15)     */
 } mhd_params;
 
 /* Conserved totals and diagnostics over the interior cells (float64).     */

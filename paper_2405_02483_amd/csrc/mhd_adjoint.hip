@@ -152,8 +152,21 @@ VProgram build_rhs_program(const mhd_params& p) {
     const int ca = B.div(bb, B.fsqrt(B.scale(rho, p.mu)));
     nus = B.add(B.add(B.scale(ub, p.nu1), B.scale(B.add(cs, ca), p.nu3)),
                 B.scale(B.relu(B.neg(D)), p.nu2, G_H));
+    // Smagorinsky viscosity (eq. nusmag): the strain of eq. itv, its edge
+    // components interpolated to the centre
+    if (T & MHD_T_SMAG) {
+      const int cxy = B.yup(B.xup(B.scale(B.add(B.ddydn(ux), B.ddxdn(uy)), 0.5)));
+      const int cxz = B.zup(B.xup(B.scale(B.add(B.ddzdn(ux), B.ddxdn(uz)), 0.5)));
+      const int cyz = B.zup(B.yup(B.scale(B.add(B.ddzdn(uy), B.ddydn(uz)), 0.5)));
+      const int dia = B.add(B.add(B.mul(sxx, sxx), B.mul(syy, syy)), B.mul(szz, szz));
+      const int off = B.add(B.add(B.mul(cxy, cxy), B.mul(cxz, cxz)), B.mul(cyz, cyz));
+      const int s2 = B.scale(B.add(B.sub(dia, B.scale(B.mul(D, D), 1.0 / 3.0)), B.scale(off, 2.0)), 2.0);
+      nus = B.add(nus, B.scale(B.fsqrt(B.relu(s2)), p.c_smag, G_H));
+    }
   }
-  int m = B.max3(B.max3(B.max3(nus, VX), VY), VZ);
+  // maximum over three (or, with MHD_T_MAX5, five) cells along each axis
+  auto mx = [&](int a, int ax) { return T & MHD_T_MAX5 ? B.max3(B.max3(a, ax), ax) : B.max3(a, ax); };
+  int m = mx(mx(mx(nus, VX), VY), VZ);
   int nt = B.mean3(B.mean3(B.mean3(m, VX), VY), VZ);
   nt = B.floor_at(nt, 1e-30);
   const int em = B.div(e, rho);
@@ -725,7 +738,10 @@ __global__ __launch_bounds__(kBlock) void k_vm_bwd(const BoxDev* boxes, const Bl
         break;
       case V_SQRT:
 #pragma unroll
-        for (int r = 0; r < R; ++r) v1[r] = y[r] / (T(2) * base[I.out * stride + o[r]]);
+        for (int r = 0; r < R; ++r) {
+          const T s = base[I.out * stride + o[r]];
+          v1[r] = s > T(0) ? y[r] / (T(2) * s) : T(0);
+        }
         put(ca, 1, v1);
         break;
       case V_LOG:

@@ -24,7 +24,7 @@ enum VOp : int {
   V_DIV,        // out = a / b
   V_SCALE,      // out = (k * geo) * a
   V_DIVC,       // out = a / k
-  V_SQRT,       // out = sqrt(a)
+  V_SQRT,       // out = sqrt(a)              (derivative 0 where out = 0)
   V_LOG,        // out = ln(a)
   V_EXP,        // out = exp(a)
   V_RELU,       // out = max(0, a)            (derivative 0 at a <= 0)

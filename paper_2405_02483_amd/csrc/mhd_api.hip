@@ -193,6 +193,7 @@ template <class T> static Phys<T> make_phys(const mhd_params& p) {
   const bool cori = p.terms & MHD_T_CORI;
   for (int a = 0; a < 3; ++a) ph.cor2[a] = cori ? T(2.0 * p.omega[a]) : T(0);
   ph.c_divb = (p.terms & MHD_T_DIVB) ? T(p.c_divb) : T(0);
+  ph.c_smag = (p.terms & MHD_T_SMAG) ? T(p.c_smag) : T(0);
   ph.terms = p.terms;
   return ph;
 }
@@ -462,10 +463,13 @@ int mhd_init(const mhd_params* p, void* hip_stream, mhd_ctx** out) {
   for (double v : nn)
     if (!(v >= 0.0) || !std::isfinite(v)) return fail(nullptr, MHD_EINVAL, "viscosity, diffusion and Courant coefficients must be finite and >= 0");
   if (!std::isfinite(p->gz) || !std::isfinite(p->c1)) return fail(nullptr, MHD_EINVAL, "gz and c1 must be finite");
-  if (p->terms & ~(MHD_T_ALL | MHD_T_COOL | MHD_T_CORI | MHD_T_EDIFFAV | MHD_T_LNP | MHD_T_DIVB))
+  if (p->terms & ~(MHD_T_ALL | MHD_T_COOL | MHD_T_CORI | MHD_T_EDIFFAV | MHD_T_LNP | MHD_T_DIVB |
+                   MHD_T_SMAG | MHD_T_MAX5))
     return fail(nullptr, MHD_EINVAL, "unknown term bits");
   if ((p->terms & MHD_T_DIVB) && !(p->c_divb >= 0.0 && std::isfinite(p->c_divb)))
     return fail(nullptr, MHD_EINVAL, "c_divb must be finite and >= 0");
+  if ((p->terms & MHD_T_SMAG) && !(p->c_smag >= 0.0 && std::isfinite(p->c_smag)))
+    return fail(nullptr, MHD_EINVAL, "c_smag must be finite and >= 0");
   if ((p->terms & MHD_T_CORI) &&
       !(std::isfinite(p->omega[0]) && std::isfinite(p->omega[1]) && std::isfinite(p->omega[2])))
     return fail(nullptr, MHD_EINVAL, "the rotation vector must be finite");

@@ -20,7 +20,8 @@ enum : unsigned {
   T_CONT = 1u << 0, T_ADV = 1u << 1, T_PRES = 1u << 2, T_VISC = 1u << 3,
   T_LORENTZ = 1u << 4, T_INDUCT = 1u << 5, T_RESIST = 1u << 6,
   T_EDIFF = 1u << 7, T_GRAV = 1u << 8, T_COOL = 1u << 9, T_CORI = 1u << 10,
-  T_EDIFFAV = 1u << 11, T_LNP = 1u << 12, T_DIVB = 1u << 13
+  T_EDIFFAV = 1u << 11, T_LNP = 1u << 12, T_DIVB = 1u << 13, T_SMAG = 1u << 14,
+  T_MAX5 = 1u << 15
 };
 
 constexpr int kBlock = 256;          // threads per workgroup of the cell kernels

@@ -13,6 +13,7 @@ template <class T> struct Phys {
   int cool_cut;
   T cor2[3];                            // 2 Omega (Coriolis force, with T_CORI)
   T c_divb;                             // div B diffusion coefficient (with T_DIVB)
+  T c_smag;                             // Smagorinsky constant (with T_SMAG)
   unsigned terms;
 };
 

@@ -36,7 +36,10 @@ namespace smhd {
 // the maxima, the wave speed c_s + c_A + |u_perp| and the rate
 // max(|d ln rho/dt|, |d ln e_m/dt|) with the cells that set them, into
 // red[item].
-template <class T, int TX, int TY, bool PERS, bool RED = false>
+// SMAG (with T_SMAG): also writes what pass S needs for the Smagorinsky
+// viscosity into the workspace of pass Q (free until then): the centred
+// velocities aup(u_a) and the diagonal strain ddaup(u_a).
+template <class T, int TX, int TY, bool PERS, bool RED = false, bool SMAG = false>
 __global__ __launch_bounds__(TX * TY) void zA1(const BoxDev* __restrict__ boxes,
                                                const ZItem* __restrict__ items, int nitems, const T* __restrict__ ztab,
                                                int* __restrict__ queue,
@@ -106,6 +109,11 @@ __global__ __launch_bounds__(TX * TY) void zA1(const BoxDev* __restrict__ boxes,
             op6<1, 1, T>([&](int m) { return sUY[PP::at(tx, ty + m)]; }, g.hyi);
       bbx = op6<0, 1, T>([&](int m) { return sBX[PP::at(tx + m, ty)]; }, T(0));
       bby = op6<0, 1, T>([&](int m) { return sBY[PP::at(tx, ty + m)]; }, T(0));
+      if (SMAG && own && r >= it.z0 && r < it.z1) {
+        const long long o = col(r);
+        ws.q(3)[o] = op6<1, 1, T>([&](int m) { return sUX[PP::at(tx + m, ty)]; }, g.hxi);
+        ws.q(4)[o] = op6<1, 1, T>([&](int m) { return sUY[PP::at(tx, ty + m)]; }, g.hyi);
+      }
       // x and y parts of div B at the centre (the div B diffusion)
       if (divb || RED)
         dxb = op6<1, 1, T>([&](int m) { return sBX[PP::at(tx + m, ty)]; }, g.hxi) +
@@ -185,6 +193,12 @@ __global__ __launch_bounds__(TX * TY) void zA1(const BoxDev* __restrict__ boxes,
         const long long o = col(q);
         nus_out[o] = nus;
         D_out[o] = D;
+        if (SMAG) {
+          ws.q(0)[o] = fUBX[0];
+          ws.q(1)[o] = fUBY[0];
+          ws.q(2)[o] = ubz;
+          ws.q(5)[o] = dzz;
+        }
         if (divb) divb_out[o] = fDXB[0] + zwin<1, 1, 8, 2>(wBZ, q, wall, N, g.hzi, zt);
         if ((cpart || RED) && interior(q)) {
           const double ux_ = fUBX[0], uy_ = fUBY[0], uz_ = ubz;
@@ -262,65 +276,166 @@ __global__ __launch_bounds__(TX * TY) void zA1(const BoxDev* __restrict__ boxes,
 }
 
 // ---------------------------------------------------------------------------
-// A2: m = max over the 3x3x3 neighbourhood (x, y through LDS; z over a ring
-// of three x/y-maximum planes), then three-cell means along x, y (LDS) and
-// z (register window), floor 1e-30, and ln.
+// S (with T_SMAG): the Smagorinsky rate of eq. nusmag at cell centres,
+// [2(S_xx^2 + S_yy^2 + S_zz^2 - (div u)^2/3 + 2(S_xy^2 + S_xz^2 + S_yz^2))]^(1/2),
+// added to pass A1's speed-like viscosity as h_min c_smag times it.  The
+// off-diagonal strain interpolated from its edge to the centre equals, the
+// operators along different axes commuting, S_ab = (D_b ub_a + D_a ub_b) / 2
+// with ub_a = aup(u_a) the centred velocities of pass A1 and D_a =
+// aup(ddadn(.)): the x and y composites from LDS strips of the front plane
+// (queued for the lag of the z ones), the z composites from register
+// windows, ddzdn on the z-faces (lag 2), then zup at the centre (lag 5).
+// The Smagorinsky term is part of the speed-like viscosity only; the
+// constant-viscosity mode has none.
+template <class T> static inline bool smag_on(const Phys<T>& ph) {
+  return (ph.terms & T_SMAG) && !(ph.nu_const > T(0));
+}
+
+template <class T, int TX, int TY, bool PERS>
+__global__ __launch_bounds__(TX * TY) void zS(const BoxDev* __restrict__ boxes,
+                                              const ZItem* __restrict__ items, int nitems,
+                                              const T* __restrict__ ztab, int* __restrict__ queue,
+                                              Phys<T> ph, ZWork<T> ws) {
+  const T* __restrict__ ubx = ws.q(0);
+  const T* __restrict__ uby = ws.q(1);
+  const T* __restrict__ ubz = ws.q(2);
+  const T* __restrict__ sxx = ws.q(3);
+  const T* __restrict__ syy = ws.q(4);
+  const T* __restrict__ szz = ws.q(5);
+  const T* __restrict__ Dg = ws.arr(WS_D);
+  T* __restrict__ nus = ws.arr(WS_NUS);
+  using PX5 = Plane<TX, TY, 5, 0>;
+  using PY5 = Plane<TX, TY, 0, 5>;
+  __shared__ T sUYx[PX5::NP], sUZx[PX5::NP], sUXy[PY5::NP], sUZy[PY5::NP];
+  ZLOOP_BEGIN
+  PlaneIdx<TX, TY, 5, 0> ix;
+  PlaneIdx<TX, TY, 0, 5> iy;
+  ix.init(b, it.x0, it.y0);
+  iy.init(b, it.x0, it.y0);
+  // windows of ub_x, ub_y (slot m = plane r-5+m), of their ddzdn on the
+  // z-faces (slot m = face r-7+m), and queues of the x/y composites (slot
+  // m = plane r-5+m)
+  T wX[6] = {}, wY[6] = {}, wDX[6] = {}, wDY[6] = {};
+  T qA[6] = {}, qB[6] = {}, qCX[6] = {}, qCY[6] = {};
+  auto comp = [&](const T* s, int step, int base, T hinv) {   // aup(ddadn) over 11 samples
+    return op6<0, 1, T>([&](int m) {
+      return op6<1, 0, T>([&](int n) { return s[base + (m + n) * step]; }, hinv);
+    }, T(0));
+  };
+  for (int r = it.z0 - 5; r <= it.z1 + 4; ++r) {
+    T ux_ = T(0), uy_ = T(0), a = T(0), c = T(0), cx = T(0), cy = T(0);
+    if (valid(r)) {
+      const int k = kk(r);
+      __syncthreads();
+      load_plane(sUYx, uby, b, ix, k);
+      load_plane(sUZx, ubz, b, ix, k);
+      load_plane(sUXy, ubx, b, iy, k);
+      load_plane(sUZy, ubz, b, iy, k);
+      __syncthreads();
+      ux_ = sUXy[PY5::at(tx, ty)];
+      uy_ = sUYx[PX5::at(tx, ty)];
+      a = comp(sUXy, PY5::W, PY5::at(tx, ty), g.hyi);     // D_y ub_x
+      c = comp(sUYx, 1, PX5::at(tx, ty), g.hxi);          // D_x ub_y
+      cx = comp(sUZx, 1, PX5::at(tx, ty), g.hxi);         // D_x ub_z
+      cy = comp(sUZy, PY5::W, PY5::at(tx, ty), g.hyi);    // D_y ub_z
+    }
+    push(wX, ux_);
+    push(wY, uy_);
+    push(qA, a);
+    push(qB, c);
+    push(qCX, cx);
+    push(qCY, cy);
+    const int q1 = r - 2;
+    T dx_ = T(0), dy_ = T(0);
+    if (valid(q1)) {
+      dx_ = zwin<1, 0, 6, 3>(wX, q1, wall, N, g.hzi, zt);
+      dy_ = zwin<1, 0, 6, 3>(wY, q1, wall, N, g.hzi, zt);
+    }
+    push(wDX, dx_);
+    push(wDY, dy_);
+    const int q = r - 5;
+    if (own && valid(q) && q >= it.z0 && q < it.z1) {
+      const long long o = col(q);
+      const T sxy = T(0.5) * (qA[0] + qB[0]);
+      const T sxz = T(0.5) * (zwin<0, 1, 6, 2>(wDX, q, wall, N, T(0), zt) + qCX[0]);
+      const T syz = T(0.5) * (zwin<0, 1, 6, 2>(wDY, q, wall, N, T(0), zt) + qCY[0]);
+      const T s11 = sxx[o], s22 = syy[o], s33 = szz[o], D = Dg[o];
+      const T s2 = T(2) * (s11 * s11 + s22 * s22 + s33 * s33 - D * D / T(3) +
+                           T(2) * (sxy * sxy + sxz * sxz + syz * syz));
+      nus[o] += ph.c_smag * g.h * (s2 > T(0) ? sqrt(s2) : T(0));
+    }
+  }
+  ZLOOP_END
+}
+
+// ---------------------------------------------------------------------------
+// A2: m = max over the MW x MW x MW neighbourhood (MW = 3, or 5 with T_MAX5;
+// x, y through LDS, z over a ring of MW x/y-maximum planes), then
+// three-cell means along x, y (LDS) and z (register window), floor 1e-30,
+// and ln.
 //
 // RED (the reduction instantiation of mhd_reductions): also the diffusion
 // speed max(<nu>, eta_speed h_max / h_min) of eq. courantcond, eta_speed =
 // nuB <nu> or eta_const / h_min, and its first maximal cell, into red[item].
-template <class T, int TX, int TY, bool PERS, bool RED = false>
+template <class T, int TX, int TY, bool PERS, bool RED = false, int MW = 3>
 __global__ __launch_bounds__(TX * TY) void zA2(const BoxDev* __restrict__ boxes,
                                                const ZItem* __restrict__ items, int nitems, const T* __restrict__ ztab,
                                                int* __restrict__ queue,
                                                ZWork<T> ws, CPart* __restrict__ cpart,
                                                double nuB = 0.0, double eta_const = 0.0,
                                                RedItem* __restrict__ red = nullptr) {
+  static_assert(MW == 3 || MW == 5, "maximum over three or five cells");
+  constexpr int MH = MW / 2;
   const T* __restrict__ nus = ws.arr(WS_NUS);
   T* __restrict__ lnt_out = ws.arr(WS_LNT);
-  using PN = Plane<TX, TY, 2>;
+  using PN = Plane<TX, TY, MH + 1>;
   using PM = Plane<TX, TY, 1>;
   constexpr int NT = TX * TY;
   __shared__ T sN[PN::NP];
-  __shared__ T sMX[3][PM::NP];
+  __shared__ T sMX[MW][PM::NP];
   __shared__ T sM[PM::NP];
   __shared__ double sred[NT];
   ZLOOP_BEGIN
-  PlaneIdx<TX, TY, 2> i2;
+  PlaneIdx<TX, TY, MH + 1> i2;
   i2.init(b, it.x0, it.y0);
   T wS[3] = {};
   double numax = 0.0;
   double rd = 0.0;
   long long rda = 0x7fffffffffffffffLL;
-  for (int r = it.z0 - 2; r <= it.z1 + 1; ++r) {
+  for (int r = it.z0 - MH - 1; r <= it.z1 + MH; ++r) {
     if (valid(r)) {
       __syncthreads();
       load_plane(sN, nus, b, i2, kk(r));
       __syncthreads();
-      T* dst = sMX[wrapm(r, 3)];
+      T* dst = sMX[wrapm(r, MW)];
       for (int t = threadIdx.x; t < PM::N; t += NT) {
         const int yy = t / PM::W, xx = t - yy * PM::W;
         const int x = xx - 1, y = yy - 1;
         T m = sN[PN::at(x, y)];
 #pragma unroll
-        for (int dy = -1; dy <= 1; ++dy)
+        for (int dy = -MH; dy <= MH; ++dy)
 #pragma unroll
-          for (int dx = -1; dx <= 1; ++dx) m = fmax(m, sN[PN::at(x + dx, y + dy)]);
+          for (int dx = -MH; dx <= MH; ++dx) m = fmax(m, sN[PN::at(x + dx, y + dy)]);
         dst[t] = m;
       }
     }
-    const int q1 = r - 1;
+    const int q1 = r - MH;
     T sxy = T(0);
     if (valid(q1)) {
       __syncthreads();
-      const bool lo = valid(q1 - 1), hi = valid(q1 + 1);
-      const T* a = sMX[wrapm(q1, 3)];
-      const T* am = sMX[wrapm(q1 - 1, 3)];
-      const T* ap = sMX[wrapm(q1 + 1, 3)];
+      // maximum over the planes q1 - MH .. q1 + MH that exist
+      bool use[MW];
+      const T* pl[MW];
+#pragma unroll
+      for (int d = 0; d < MW; ++d) {
+        use[d] = valid(q1 + d - MH);
+        pl[d] = sMX[wrapm(q1 + d - MH, MW)];
+      }
       for (int t = threadIdx.x; t < PM::N; t += NT) {
-        T m = a[t];
-        if (lo) m = fmax(m, am[t]);
-        if (hi) m = fmax(m, ap[t]);
+        T m = pl[MH][t];
+#pragma unroll
+        for (int d = 0; d < MW; ++d)
+          if (d != MH && use[d]) m = fmax(m, pl[d][t]);
         sM[t] = m;
       }
       __syncthreads();
@@ -331,8 +446,8 @@ __global__ __launch_bounds__(TX * TY) void zA2(const BoxDev* __restrict__ boxes,
                       sM[PM::at(tx + 1, ty + dy)]) / T(3);
       sxy = (sx[0] + sx[1] + sx[2]) / T(3);
     }
-    push(wS, sxy);                        // wS slot m = plane r-3+m
-    const int q = r - 2;
+    push(wS, sxy);                        // wS slot m = plane r-MH-2+m
+    const int q = r - MH - 1;
     if (valid(q) && q >= it.z0 && q < it.z1) {
       T s = wS[1];
       int cnt = 1;
@@ -898,10 +1013,21 @@ static void launch_zreduce_t(const ZLaunch& L, CP8<T> f, CP8<T> dfdt, const ZWor
                              const T* ztab, RedItem* red, double nuB, double eta_const) {
   const int n = L.nitems;
   const dim3 grid(8 * ((n + 7) / 8)), block(TX * TY);
-  hipLaunchKernelGGL((zA1<T, TX, TY, false, true>), grid, block, 0, L.stream, L.boxes, L.items, n, ztab,
-                     (int*)nullptr, f, ph, w, (CPart*)nullptr, dfdt, red);
-  hipLaunchKernelGGL((zA2<T, TX, TY, false, true>), grid, block, 0, L.stream, L.boxes, L.items, n, ztab,
-                     (int*)nullptr, w, (CPart*)nullptr, nuB, eta_const, red);
+  if (smag_on(ph)) {
+    hipLaunchKernelGGL((zA1<T, TX, TY, false, true, true>), grid, block, 0, L.stream, L.boxes, L.items, n, ztab,
+                       (int*)nullptr, f, ph, w, (CPart*)nullptr, dfdt, red);
+    hipLaunchKernelGGL((zS<T, TX, TY, false>), grid, block, 0, L.stream, L.boxes, L.items, n, ztab,
+                       (int*)nullptr, ph, w);
+  } else {
+    hipLaunchKernelGGL((zA1<T, TX, TY, false, true>), grid, block, 0, L.stream, L.boxes, L.items, n, ztab,
+                       (int*)nullptr, f, ph, w, (CPart*)nullptr, dfdt, red);
+  }
+  if (ph.terms & T_MAX5)
+    hipLaunchKernelGGL((zA2<T, TX, TY, false, true, 5>), grid, block, 0, L.stream, L.boxes, L.items, n, ztab,
+                       (int*)nullptr, w, (CPart*)nullptr, nuB, eta_const, red);
+  else
+    hipLaunchKernelGGL((zA2<T, TX, TY, false, true>), grid, block, 0, L.stream, L.boxes, L.items, n, ztab,
+                       (int*)nullptr, w, (CPart*)nullptr, nuB, eta_const, red);
 }
 
 template <class T>
@@ -927,7 +1053,7 @@ template void launch_zreduce<double>(const ZLaunch&, CP8<double>, CP8<double>, c
                                      const Phys<double>&, const double*, RedItem*, RedTotal*, double, double,
                                      double, double, double);
 
-__global__ void k_qreset(int* q) {
+__global__ __launch_bounds__(128) void k_qreset(int* q) {
   if ((int)threadIdx.x < kQueueInts) q[threadIdx.x] = 0;
 }
 
@@ -941,13 +1067,24 @@ static void launch_zstage_m(const ZLaunch& L, const ZStageArgs<T>& a) {
     const int r = std::min(n, zresident_groups(kern, TX * TY, L.ncu));
     return dim3(std::max(8, r - r % 8));
   };
-  if (q) hipLaunchKernelGGL(k_qreset, dim3(1), dim3(64), 0, L.stream, q);
+  if (q) hipLaunchKernelGGL(k_qreset, dim3(1), dim3(128), 0, L.stream, q);
   L.at(PASS_PRIM);
-  hipLaunchKernelGGL((zA1<T, TX, TY, PERS>), grid((const void*)zA1<T, TX, TY, PERS>), block, 0, L.stream, L.boxes,
-                     L.items, n, a.ztab, q, a.f, a.ph, a.w, a.cpart);
+  if (smag_on(a.ph)) {
+    hipLaunchKernelGGL((zA1<T, TX, TY, PERS, false, true>), grid((const void*)zA1<T, TX, TY, PERS, false, true>),
+                       block, 0, L.stream, L.boxes, L.items, n, a.ztab, q, a.f, a.ph, a.w, a.cpart);
+    hipLaunchKernelGGL((zS<T, TX, TY, PERS>), grid((const void*)zS<T, TX, TY, PERS>), block, 0, L.stream,
+                       L.boxes, L.items, n, a.ztab, q ? q + 64 : q, a.ph, a.w);
+  } else {
+    hipLaunchKernelGGL((zA1<T, TX, TY, PERS>), grid((const void*)zA1<T, TX, TY, PERS>), block, 0, L.stream,
+                       L.boxes, L.items, n, a.ztab, q, a.f, a.ph, a.w, a.cpart);
+  }
   L.at(PASS_MEAN3);
-  hipLaunchKernelGGL((zA2<T, TX, TY, PERS>), grid((const void*)zA2<T, TX, TY, PERS>), block, 0, L.stream, L.boxes,
-                     L.items, n, a.ztab, q ? q + 8 : q, a.w, a.cpart);
+  if (a.ph.terms & T_MAX5)
+    hipLaunchKernelGGL((zA2<T, TX, TY, PERS, false, 5>), grid((const void*)zA2<T, TX, TY, PERS, false, 5>), block,
+                       0, L.stream, L.boxes, L.items, n, a.ztab, q ? q + 8 : q, a.w, a.cpart);
+  else
+    hipLaunchKernelGGL((zA2<T, TX, TY, PERS>), grid((const void*)zA2<T, TX, TY, PERS>), block, 0, L.stream,
+                       L.boxes, L.items, n, a.ztab, q ? q + 8 : q, a.w, a.cpart);
   if (a.cpart) {
     L.at(PASS_REDUCE);
     hipLaunchKernelGGL(k_dt, dim3(1), dim3(256), 0, L.stream, L.boxes, L.items, n, a.cpart, a.Cdt,

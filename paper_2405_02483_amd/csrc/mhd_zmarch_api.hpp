@@ -55,8 +55,8 @@ template <class T> struct ZWork {
 // Slices of a plane summed by separate workgroups for the plane means.
 constexpr int kPlaneSlices = 8;
 
-// Item queues of the persistent mode: 8 counters per launch, at most 8 launches.
-constexpr int kQueueInts = 64;
+// Item queues of the persistent mode: 8 counters per launch, at most 9 launches.
+constexpr int kQueueInts = 72;
 
 struct ZLaunch {
   const BoxDev* boxes;
