@@ -62,6 +62,15 @@ garbled:
   two "in varying proportions"), so that nu_ii = dx_i h_min <nu_S>: eq.
   nuij2's (dx_i)^2 <nu> on cubic cells.  The depth factor the paper applies
   "sometimes" in stratified runs is not used.
+* eq. quench: the printed second line sets T to q_i times a bracket; read
+  as the stress being multiplied by the bracket min(max(q_{i-1}, q_i,
+  q_{i+1}), q_lim), which reduces smooth stress and raises a two-zone
+  wiggle, as the text says.  In three dimensions Delta^2 T is the sum over
+  the axes of the absolute second differences (absolute, so that q >= 0)
+  and the maximum runs over the 3x3x3 neighbourhood, as for the viscosity.
+  All six components are quenched, each at its own position, and the
+  quenched stress enters both the momentum equation and the viscous
+  heating (which keeps the total energy budget).
 * eq. mom, Coriolis force: -2 rho Omega x u = -2 Omega x p, with each
   momentum component carried to the face of the component it drives by the
   staggered interpolations (e.g. p_z at an x-face is xdn(zup(p_z))).
@@ -76,12 +85,12 @@ from .stagger import Ops, AX_X, AX_Y, AX_Z
 __all__ = [
     "T_CONT", "T_ADV", "T_PRES", "T_VISC", "T_LORENTZ", "T_INDUCT",
     "T_RESIST", "T_EDIFF", "T_GRAV", "T_ALL", "T_HD", "T_IDEAL", "T_COOL", "T_CORI",
-    "T_EDIFFAV", "T_LNP", "T_DIVB", "T_SMAG", "T_MAX5",
+    "T_EDIFFAV", "T_LNP", "T_DIVB", "T_SMAG", "T_MAX5", "T_QUENCH",
     "ALPHA", "BETA", "Grid", "Params", "ghost_fill", "rhs", "rhs_nofill",
     "step", "rk3", "courant", "stats", "step_vjp", "rhs_vjp", "FIELDS",
     "interior_slices", "smoothed_viscosity", "newton_cooling", "coriolis",
     "horizontal_ln_mean", "pressure_gradient_ln", "viscosity_lengths",
-    "edge_viscosity", "smagorinsky_rate",
+    "edge_viscosity", "smagorinsky_rate", "quench_factor",
 ]
 
 FIELDS = ("rho", "px", "py", "pz", "e", "bx", "by", "bz")
@@ -105,6 +114,7 @@ T_LNP = 1 << 12      # with T_PRES: grad P through ln(P / P_aver) (eq. pressure)
 T_DIVB = 1 << 13     # div B diffusion C_divb h^2 / dt grad(div B); needs the step's dt
 T_SMAG = 1 << 14     # Smagorinsky viscosity added to the speed-like one (eq. nusmag)
 T_MAX5 = 1 << 15     # spread the viscosity by the maximum over five cells (do_max5)
+T_QUENCH = 1 << 16   # quench each viscous stress component (eq. quench)
 T_HD = T_CONT | T_ADV | T_PRES | T_VISC | T_EDIFF
 T_IDEAL = T_CONT | T_ADV | T_PRES | T_LORENTZ | T_INDUCT
 
@@ -178,6 +188,8 @@ class Params:
     omega: tuple = (0.0, 0.0, 0.0)   # rotation vector of the Coriolis force
     c_divb: float = 0.0       # coefficient of the div B diffusion (< 0.11)
     c_smag: float = 0.0       # Smagorinsky constant (eq. nusmag; &pde Csmag)
+    q_max: float = 8.0        # eq. quench, &quench qmax
+    q_lim: float = 2.0        # eq. quench, &quench qlim
 
 
 def interior_slices(grid):
@@ -253,6 +265,21 @@ def _safe_sqrt(s):
     """sqrt(max(s, 0)) with zero derivative where s <= 0."""
     pos = s > 0
     return torch.where(pos, torch.sqrt(torch.where(pos, s, torch.ones_like(s))), torch.zeros_like(s))
+
+
+def quench_factor(t, O, par):
+    """The factor that multiplies a viscous stress component t (Section 6.2,
+    eq. quench): q = D2 / (|t| + D2 / q_max), with D2 the sum over the three
+    axes of the absolute second differences of t (zero at the end planes of
+    a wall-bounded axis) and q = 0 where t and D2 both vanish; the factor is
+    min(max of q over the 3x3x3 neighbourhood, q_lim).  Smooth stress
+    (D2 << |t|) is reduced, a two-zone wiggle raised up to q_lim."""
+    d2 = O.d2abs(t, AX_X) + O.d2abs(t, AX_Y) + O.d2abs(t, AX_Z)
+    den = t.abs() + d2 / par.q_max
+    pos = den > 0
+    q = torch.where(pos, d2 / torch.where(pos, den, torch.ones_like(den)), torch.zeros_like(den))
+    m = O.max3(O.max3(O.max3(q, AX_X), AX_Y), AX_Z)
+    return torch.where(m < par.q_lim, m, torch.full_like(m, par.q_lim))
 
 
 def viscosity_lengths(grid, par):
@@ -366,6 +393,9 @@ def rhs_nofill(f, grid, par, dt=None):
     txy = rxy * nxy * sxy
     txz = rxz * nxz * sxz
     tyz = ryz * nyz * syz
+    if T & T_QUENCH:
+        txx, tyy, tzz, txy, txz, tyz = (t * quench_factor(t, O, par)
+                                        for t in (txx, tyy, tzz, txy, txz, tyz))
 
     # -- current and electric field (eq. ohm, J = curl B) ---------------------
     jx = O.ddydn(bz) - O.ddzdn(by)

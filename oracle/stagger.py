@@ -177,6 +177,16 @@ class Ops:
         applied twice, which also fixes the adjoint's choice in a tie."""
         return self.max3(self.max3(f, axis), axis)
 
+    def d2abs(self, f, axis):
+        """Absolute second difference |f[i+1] - 2 f[i] + f[i-1]| along the
+        axis; zero on the end planes of a wall-bounded axis, where one of the
+        two neighbours does not exist."""
+        if axis == AX_Z and self.wall_z:
+            d = torch.zeros_like(f)
+            d[1:-1] = (f[2:] - 2.0 * f[1:-1] + f[:-2]).abs()
+            return d
+        return (_shift(f, 1, axis) - 2.0 * f + _shift(f, -1, axis)).abs()
+
     def mean3(self, f, axis):
         """Average over the three adjacent cells (over the available ones at
         the ends of a wall-bounded axis)."""
