@@ -113,6 +113,14 @@ enum {
  * axis instead of three (Section 6.1.1, &pde do_max5).  Not part of
  * MHD_T_ALL.                                                               */
 #define MHD_T_MAX5     (1u << 15)
+/* Quenching of the viscous stress (Section 6.2, eq. quench): each of the six
+ * components tau is multiplied by min(max of q over the 3x3x3 neighbourhood,
+ * q_lim), q = D2 / (|tau| + D2 / q_max), with D2 the sum over the three axes
+ * of the absolute second differences of tau (none across the ends of a
+ * wall-bounded axis; q = 0 where tau and D2 vanish).  The quenched stress
+ * drives the momentum and the viscous heating.  Needs MHD_T_VISC to have
+ * an effect.  Not part of MHD_T_ALL.                                        */
+#define MHD_T_QUENCH   (1u << 16)
 
 /* One box of the mesh (&grid namelist: mx, my, mz, sx, sy, sz). */
 typedef struct {
@@ -154,6 +162,8 @@ typedef struct {
                                (0.1358 on cubic cells); MHD_EINVAL above it    */
     double c_smag;          /* with MHD_T_SMAG: the Smagorinsky constant, finite
                                and >= 0 (&pde Csmag, typically 0.1 - 0.15)     */
+    double q_max, q_lim;    /* with MHD_T_QUENCH: eq. quench, both finite and
+                               > 0 (&quench qmax = 8, qlim = 2)                */
 } mhd_params;
 
 /* Conserved totals and diagnostics over the interior cells (float64).     */

@@ -87,6 +87,10 @@ struct Builder {
   int max3(int a, int ax) { return emit(V_MAX3, a, ZERO, ZERO, 0.0, G_ONE, ax, 0, 0); }
   int mean3(int a, int ax) { return emit(V_MEAN3, a, ZERO, ZERO, 0.0, G_ONE, ax, 0, 0); }
   int fill(double k, int geo = G_ONE) { return emit(V_FILL, ZERO, ZERO, ZERO, k, geo, 0, 0, 0); }
+  int fabs_(int a) { return un(V_ABS, a); }
+  int d2(int a, int ax) { return emit(V_D2, a, ZERO, ZERO, 0.0, G_ONE, ax, 0, 0); }
+  int sdiv(int a, int b) { return emit(V_SDIV, a, b, ZERO, 0.0, G_ONE, 0, 0, 0); }
+  int cap(int a, double k) { return un(V_CAP, a, k); }
 };
 
 // Drops instructions whose results never reach an output, renumbers slots
@@ -182,12 +186,27 @@ VProgram build_rhs_program(const mhd_params& p) {
   const int sxy = B.scale(B.add(B.ddydn(ux), B.ddxdn(uy)), 0.5);
   const int sxz = B.scale(B.add(B.ddzdn(ux), B.ddxdn(uz)), 0.5);
   const int syz = B.scale(B.add(B.ddzdn(uy), B.ddydn(uz)), 0.5);
-  const int txx = B.mul(B.mul(rho, B.scale(nt, 1.0, G_LX)), B.add(sxx, B.scale(D, p.c1)));
-  const int tyy = B.mul(B.mul(rho, B.scale(nt, 1.0, G_LY)), B.add(syy, B.scale(D, p.c1)));
-  const int tzz = B.mul(B.mul(rho, B.scale(nt, 1.0, G_LZ)), B.add(szz, B.scale(D, p.c1)));
-  const int txy = B.mul(B.mul(rxy, nxy), sxy);
-  const int txz = B.mul(B.mul(rxz, nxz), sxz);
-  const int tyz = B.mul(B.mul(ryz, nyz), syz);
+  int txx = B.mul(B.mul(rho, B.scale(nt, 1.0, G_LX)), B.add(sxx, B.scale(D, p.c1)));
+  int tyy = B.mul(B.mul(rho, B.scale(nt, 1.0, G_LY)), B.add(syy, B.scale(D, p.c1)));
+  int tzz = B.mul(B.mul(rho, B.scale(nt, 1.0, G_LZ)), B.add(szz, B.scale(D, p.c1)));
+  int txy = B.mul(B.mul(rxy, nxy), sxy);
+  int txz = B.mul(B.mul(rxz, nxz), sxz);
+  int tyz = B.mul(B.mul(ryz, nyz), syz);
+  // quenching (Section 6.2, eq. quench): each component times
+  // min(max over 3x3x3 of D2 / (|tau| + D2 / q_max), q_lim)
+  if ((T & MHD_T_QUENCH) && (T & MHD_T_VISC)) {
+    auto quench = [&](int t) {
+      const int s = B.add(B.add(B.fabs_(B.d2(t, VX)), B.fabs_(B.d2(t, VY))), B.fabs_(B.d2(t, VZ)));
+      const int q = B.sdiv(s, B.add(B.fabs_(t), B.divc(s, p.q_max)));
+      return B.mul(t, B.cap(B.max3(B.max3(B.max3(q, VX), VY), VZ), p.q_lim));
+    };
+    txx = quench(txx);
+    tyy = quench(tyy);
+    tzz = quench(tzz);
+    txy = quench(txy);
+    txz = quench(txz);
+    tyz = quench(tyz);
+  }
 
   // current and electric field (eq. ohm)
   const int jx = B.sub(B.ddydn(bz), B.ddzdn(by));
@@ -318,7 +337,8 @@ VPlan plan_program(const VProgram& P) {
       case V_MUL: keep[I.a] = keep[I.b] = 1; break;
       case V_DIV: keep[I.b] = keep[I.out] = 1; break;
       case V_SQRT: case V_EXP: keep[I.out] = 1; break;
-      case V_LOG: case V_RELU: case V_FLOOR: case V_MAX3: keep[I.a] = 1; break;
+      case V_LOG: case V_RELU: case V_FLOOR: case V_MAX3: case V_ABS: case V_CAP: keep[I.a] = 1; break;
+      case V_SDIV: keep[I.b] = keep[I.out] = 1; break;
       case V_NORM3: keep[I.a] = keep[I.b] = keep[I.c] = keep[I.out] = 1; break;
       default: break;
     }
@@ -336,7 +356,7 @@ VPlan plan_program(const VProgram& P) {
   std::vector<int> gid(n), gend;
   for (int q = 0; q < n; ++q) {
     const VInstr& I = P.code[q];
-    const bool nb = I.op == V_STEN || I.op == V_MAX3 || I.op == V_MEAN3;
+    const bool nb = I.op == V_STEN || I.op == V_MAX3 || I.op == V_MEAN3 || I.op == V_D2;
     const bool dep = nb && !R.groups.empty() && prod[I.a] >= R.groups.back().first;
     if (q == 0 || dep || q - R.groups.back().first == kGroupMax) {
       if (!R.groups.empty()) gend.push_back(q);
@@ -409,7 +429,7 @@ VPlan plan_program(const VProgram& P) {
   for (int q = n - 1; q >= 0; --q) {
     const VInstr& I = P.code[q];
     if (I.op == V_FILL) continue;
-    const bool nb = I.op == V_STEN || I.op == V_MAX3 || I.op == V_MEAN3;
+    const bool nb = I.op == V_STEN || I.op == V_MAX3 || I.op == V_MEAN3 || I.op == V_D2;
     const bool dep = nb && !R.bgroups.empty() && contrib[I.out] >= R.bgroups.back().first;
     if (R.bgroups.empty() || dep || (int)border.size() - R.bgroups.back().first == kBGroupMax)
       R.bgroups.push_back({(int)border.size(), 0});
@@ -567,6 +587,14 @@ __global__ __launch_bounds__(kBlock) void k_vm_group(const BoxDev* boxes, const 
         r = (along(a, g, I.ax, i, j, k, -1) + a[o] + along(a, g, I.ax, i, j, k, 1)) / T(3);
         break;
       }
+      case V_D2: {
+        int i, j, k;
+        coords(i, j, k);
+        const Geo<T> g(bx_);
+        const T* a = base + I.a * stride;
+        r = along(a, g, I.ax, i, j, k, 1) - T(2) * a[o] + along(a, g, I.ax, i, j, k, -1);
+        break;
+      }
       case V_ADD: r = opnd(I.a, G.la) + opnd(I.b, G.lb); break;
       case V_SUB: r = opnd(I.a, G.la) - opnd(I.b, G.lb); break;
       case V_MUL: r = opnd(I.a, G.la) * opnd(I.b, G.lb); break;
@@ -595,6 +623,17 @@ __global__ __launch_bounds__(kBlock) void k_vm_group(const BoxDev* boxes, const 
       case V_FILL:
         r = I.geo == G_HINV ? T(I.k / bx_.hmin) : T(I.k * geo_of(bx_, I.geo));
         break;
+      case V_ABS: r = fabs(opnd(I.a, G.la)); break;
+      case V_SDIV: {
+        const T x = opnd(I.a, G.la), y = opnd(I.b, G.lb);
+        r = y > T(0) ? x / y : T(0);
+        break;
+      }
+      case V_CAP: {
+        const T x = opnd(I.a, G.la);
+        r = x < T(I.k) ? x : T(I.k);
+        break;
+      }
       default: r = T(0); break;
     }
     R(jj) = r;
@@ -803,6 +842,39 @@ __global__ __launch_bounds__(kBlock) void k_vm_bwd(const BoxDev* boxes, const Bl
           const Geo<T> g(boxes[bi[r]]);
           v1[r] = (along(yb, g, I.ax, i, j, k, -1) + y[r] + along(yb, g, I.ax, i, j, k, 1)) / T(3);
         }
+        put(ca, 1, v1);
+        break;
+      case V_D2:   // symmetric on a periodic axis
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          int i, j, k;
+          coords(r, i, j, k);
+          const Geo<T> g(boxes[bi[r]]);
+          v1[r] = along(yb, g, I.ax, i, j, k, 1) - T(2) * y[r] + along(yb, g, I.ax, i, j, k, -1);
+        }
+        put(ca, 1, v1);
+        break;
+      case V_ABS:
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const T x = a[o[r]];
+          v1[r] = x > T(0) ? y[r] : (x < T(0) ? -y[r] : T(0));
+        }
+        put(ca, 1, v1);
+        break;
+      case V_SDIV:
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const T vb = b[o[r]], qv = base[I.out * stride + o[r]];
+          v1[r] = vb > T(0) ? y[r] / vb : T(0);
+          v2[r] = vb > T(0) ? -(y[r] * qv / vb) : T(0);
+        }
+        put(ca, 1, v1);
+        put(cb, 2, v2);
+        break;
+      case V_CAP:
+#pragma unroll
+        for (int r = 0; r < R; ++r) v1[r] = a[o[r]] < T(I.k) ? y[r] : T(0);
         put(ca, 1, v1);
         break;
       default: break;

@@ -33,6 +33,10 @@ enum VOp : int {
   V_MAX3,       // out = max over cells i-1, i, i+1 along ax (first maximal one)
   V_MEAN3,      // out = (f[i-1] + f[i] + f[i+1]) / 3 along ax
   V_FILL,       // out = k * geo (or k / h with G_HINV)
+  V_ABS,        // out = |a|                  (derivative 0 at a = 0)
+  V_D2,         // out = a[i+1] - 2 a[i] + a[i-1] along ax (periodic)
+  V_SDIV,       // out = b > 0 ? a / b : 0
+  V_CAP,        // out = a < k ? a : k        (derivative 0 at a >= k)
   V_COUNT
 };
 
@@ -41,7 +45,7 @@ enum VOp : int {
 // spacing and its reciprocal.
 enum VGeo : int { G_ONE = 0, G_LX, G_LY, G_LZ, G_H, G_HINV, G_LXY, G_LXZ, G_LYZ };
 
-// Axes of V_STEN / V_MAX3 / V_MEAN3.
+// Axes of V_STEN / V_MAX3 / V_MEAN3 / V_D2.
 enum VAxis : int { VX = 0, VY = 1, VZ = 2 };
 
 struct VInstr {

@@ -36,7 +36,7 @@ struct mhd_ctx {
   int ngblk = 0;
   std::vector<BoxDev> h_boxes;
   // workspace
-  void* work = nullptr;            // kWorkArrays * nelem elements
+  void* work = nullptr;            // work_arrays(p) * nelem elements
   RedItem* d_red = nullptr;        // per-item partials of mhd_reductions (nitems)
   RedTotal* d_tot = nullptr;       // their fold
   void* adj = nullptr;             // adjoint workspace (allocated on first use)
@@ -159,7 +159,10 @@ static double divb_limit(double dx, double dy, double dz) {
   const double s = h * h * (1.0 / (dx * dx) + 1.0 / (dy * dy) + 1.0 / (dz * dz));
   return rk3_real_limit() / (kh * kh * s);
 }
-static constexpr int kWorkArrays = WS_COUNT;   // 34 arrays
+// Stage workspace arrays: 34, and 6 more for the quenched stress.
+static int work_arrays(const mhd_params& p) {
+  return (p.terms & MHD_T_QUENCH) ? WS_COUNT_QUENCH : WS_COUNT;
+}
 
 static int fail(mhd_ctx* c, int code, const std::string& msg) {
   if (c) c->err = msg; else g_init_err = msg;
@@ -194,6 +197,9 @@ template <class T> static Phys<T> make_phys(const mhd_params& p) {
   for (int a = 0; a < 3; ++a) ph.cor2[a] = cori ? T(2.0 * p.omega[a]) : T(0);
   ph.c_divb = (p.terms & MHD_T_DIVB) ? T(p.c_divb) : T(0);
   ph.c_smag = (p.terms & MHD_T_SMAG) ? T(p.c_smag) : T(0);
+  const bool quench = p.terms & MHD_T_QUENCH;
+  ph.q_max = quench ? T(p.q_max) : T(1);
+  ph.q_lim = quench ? T(p.q_lim) : T(0);
   ph.terms = p.terms;
   return ph;
 }
@@ -464,12 +470,15 @@ int mhd_init(const mhd_params* p, void* hip_stream, mhd_ctx** out) {
     if (!(v >= 0.0) || !std::isfinite(v)) return fail(nullptr, MHD_EINVAL, "viscosity, diffusion and Courant coefficients must be finite and >= 0");
   if (!std::isfinite(p->gz) || !std::isfinite(p->c1)) return fail(nullptr, MHD_EINVAL, "gz and c1 must be finite");
   if (p->terms & ~(MHD_T_ALL | MHD_T_COOL | MHD_T_CORI | MHD_T_EDIFFAV | MHD_T_LNP | MHD_T_DIVB |
-                   MHD_T_SMAG | MHD_T_MAX5))
+                   MHD_T_SMAG | MHD_T_MAX5 | MHD_T_QUENCH))
     return fail(nullptr, MHD_EINVAL, "unknown term bits");
   if ((p->terms & MHD_T_DIVB) && !(p->c_divb >= 0.0 && std::isfinite(p->c_divb)))
     return fail(nullptr, MHD_EINVAL, "c_divb must be finite and >= 0");
   if ((p->terms & MHD_T_SMAG) && !(p->c_smag >= 0.0 && std::isfinite(p->c_smag)))
     return fail(nullptr, MHD_EINVAL, "c_smag must be finite and >= 0");
+  if ((p->terms & MHD_T_QUENCH) && !(p->q_max > 0.0 && std::isfinite(p->q_max) && p->q_lim > 0.0 &&
+                                     std::isfinite(p->q_lim)))
+    return fail(nullptr, MHD_EINVAL, "q_max and q_lim must be finite and > 0");
   if ((p->terms & MHD_T_CORI) &&
       !(std::isfinite(p->omega[0]) && std::isfinite(p->omega[1]) && std::isfinite(p->omega[2])))
     return fail(nullptr, MHD_EINVAL, "the rotation vector must be finite");
@@ -575,7 +584,7 @@ int mhd_init(const mhd_params* p, void* hip_stream, mhd_ctx** out) {
       (e = hipMalloc(&c->d_tab, sizeof(Blk) * tab.size())) != hipSuccess ||
       (c->ngblk && (e = hipMalloc(&c->d_gtab, sizeof(Blk) * gtab.size())) != hipSuccess) ||
       (e = hipMalloc(&c->d_tot, sizeof(RedTotal))) != hipSuccess ||
-      (e = hipMalloc(&c->work, (size_t)kWorkArrays * c->nelem * c->esize)) != hipSuccess) {
+      (e = hipMalloc(&c->work, (size_t)work_arrays(c->p) * c->nelem * c->esize)) != hipSuccess) {
     g_init_err = std::string("device allocation failed: ") + hipGetErrorString(e);
     mhd_destroy(c);
     return MHD_ENOMEM;
@@ -914,7 +923,7 @@ int mhd_rhs(mhd_ctx* c, void* const f[8], void* const dfdt[8]) {
 // the bytes it needs, and fills *s only when they fit.
 static size_t static_layout(const mhd_ctx* c, Scratch* s) {
   auto a256 = [](size_t n) { return (n + 255) & ~size_t(255); };
-  const size_t work = a256((size_t)kWorkArrays * c->nelem * c->esize);
+  const size_t work = a256((size_t)work_arrays(c->p) * c->nelem * c->esize);
   const size_t tab = a256(c->esize * (size_t)c->nplanes);
   const size_t part = a256(sizeof(double) * kPlaneSlices * (size_t)c->nplanes);
   const size_t need = work + 2 * tab + part + a256(sizeof(int) * kQueueInts);

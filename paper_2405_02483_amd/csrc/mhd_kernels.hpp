@@ -14,6 +14,7 @@ template <class T> struct Phys {
   T cor2[3];                            // 2 Omega (Coriolis force, with T_CORI)
   T c_divb;                             // div B diffusion coefficient (with T_DIVB)
   T c_smag;                             // Smagorinsky constant (with T_SMAG)
+  T q_max, q_lim;                       // quenching (with T_QUENCH)
   unsigned terms;
 };
 

@@ -511,6 +511,9 @@ __global__ __launch_bounds__(TX * TY) void zA2(const BoxDev* __restrict__ boxes,
 constexpr unsigned QM_EDGES = 1u, QM_ZC = 2u;
 // with QM_ZC: dP/dz through ln(P / P_aver) (eq. pressure)
 constexpr unsigned QM_LNP = 4u;
+// quenching: only the raw stress components of the selected groups
+// (tau_xz, tau_yz; tau_zz), into the workspace arrays q(TAU_*)
+constexpr unsigned QM_TAU = 8u;
 template <class T, int TX, int TY, bool PERS, unsigned QM>
 __global__ __launch_bounds__(TX * TY) void zQ(const BoxDev* __restrict__ boxes,
                                               const ZItem* __restrict__ items, int nitems, const T* __restrict__ ztab,
@@ -522,10 +525,12 @@ __global__ __launch_bounds__(TX * TY) void zQ(const BoxDev* __restrict__ boxes,
   const T* __restrict__ lntg = ws.arr(WS_LNT);
   const T* __restrict__ Dg = ws.arr(WS_D);
   using P3 = Plane<TX, TY, 3>;
-  constexpr bool kE = QM & QM_EDGES, kZ = QM & QM_ZC;
+  constexpr bool kE = QM & QM_EDGES, kZ = QM & QM_ZC, kT = QM & QM_TAU;
   constexpr int NPL = kE ? P3::NP : 1;
+  constexpr int NPB = kE && !kT ? P3::NP : 1;
   __shared__ T sR[NPL], sL[NPL];
-  __shared__ T sUZ[3][NPL], sBZ[3][NPL], sPZ[3][NPL];
+  __shared__ T sUZ[3][NPL], sBZ[3][NPB], sPZ[3][NPB];
+  const T* __restrict__ tq = ws.tq;
   ZLOOP_BEGIN
   PlaneIdx<TX, TY, 3> i3;
   i3.init(b, it.x0, it.y0);
@@ -555,8 +560,10 @@ __global__ __launch_bounds__(TX * TY) void zQ(const BoxDev* __restrict__ boxes,
         load_plane(sR, f.p[0], b, i3, k);
         load_plane(sL, lntg, b, i3, k);
         load_plane(sUZ[sl], uzg, b, i3, k);
-        load_plane(sBZ[sl], f.p[7], b, i3, k);
-        load_plane(sPZ[sl], f.p[3], b, i3, k);
+        if constexpr (!kT) {
+          load_plane(sBZ[sl], f.p[7], b, i3, k);
+          load_plane(sPZ[sl], f.p[3], b, i3, k);
+        }
         __syncthreads();
         rx = op6<0, 0, T>([&](int m) { return sR[P3::at(tx + m, ty)]; }, T(0));
         ry = op6<0, 0, T>([&](int m) { return sR[P3::at(tx, ty + m)]; }, T(0));
@@ -566,12 +573,14 @@ __global__ __launch_bounds__(TX * TY) void zQ(const BoxDev* __restrict__ boxes,
         py = f.p[2][o];
         ux = px / rx;
         uy = py / ry;
-        bxv = f.p[5][o];
-        byv = f.p[6][o];
+        if constexpr (!kT) {
+          bxv = f.p[5][o];
+          byv = f.p[6][o];
+        }
       }
       if constexpr (kZ) {
         // own column only: from LDS when the planes are there
-        if constexpr (kE) {
+        if constexpr (kE && !kT) {
           pzv = sPZ[sl][P3::at(tx, ty)];
           uzv = sUZ[sl][P3::at(tx, ty)];
           rhov = sR[P3::at(tx, ty)];
@@ -610,8 +619,21 @@ __global__ __launch_bounds__(TX * TY) void zQ(const BoxDev* __restrict__ boxes,
       const T* BZ = sBZ[sq];
       const T* PZ = sPZ[sq];
       const long long o = col(q);
+      // ---- raw stress only (quenching)
+      if constexpr (kE && kT) {
+        const T dxUZ = op6<1, 0, T>([&](int m) { return UZ[P3::at(tx + m, ty)]; }, g.hxi);
+        const T dyUZ = op6<1, 0, T>([&](int m) { return UZ[P3::at(tx, ty + m)]; }, g.hyi);
+        const T sxz = T(0.5) * (zwin<1, 0, 6, 3>(wUX, q, wall, N, g.hzi, zt) + dxUZ);
+        const T syz = T(0.5) * (zwin<1, 0, 6, 3>(wUY, q, wall, N, g.hzi, zt) + dyUZ);
+        if (own) {
+          ws.q(TAU_XZ)[o] = zwin<0, 0, 6, 3>(wRX, q, wall, N, T(0), zt) *
+                            (g.lxz * exp(zwin<0, 0, 6, 3>(wLX, q, wall, N, T(0), zt))) * sxz;
+          ws.q(TAU_YZ)[o] = zwin<0, 0, 6, 3>(wRY, q, wall, N, T(0), zt) *
+                            (g.lyz * exp(zwin<0, 0, 6, 3>(wLY, q, wall, N, T(0), zt))) * syz;
+        }
+      }
       // ---- y-edge
-      if constexpr (kE) {
+      if constexpr (kE && !kT) {
         const T zRX = zwin<0, 0, 6, 3>(wRX, q, wall, N, T(0), zt);
         const T zPX = zwin<0, 0, 6, 3>(wPX, q, wall, N, T(0), zt);
         const T zUX = zwin<0, 0, 6, 3>(wUX, q, wall, N, T(0), zt);
@@ -627,7 +649,7 @@ __global__ __launch_bounds__(TX * TY) void zQ(const BoxDev* __restrict__ boxes,
         if (need_nu) nxz = g.lxz * exp(zwin<0, 0, 6, 3>(wLX, q, wall, N, T(0), zt));
         if (visc) {
           sxz = T(0.5) * (dzUX + dxUZ);
-          txz = zRX * nxz * sxz;
+          txz = tq ? tq[TAU_XZ * ws.stride + o] : zRX * nxz * sxz;
         }
         const T jy = dzBX - dxBZ;
         const T eta = ph.eta_const > T(0) ? ph.eta_const : ph.nuB * nxz;
@@ -651,7 +673,7 @@ __global__ __launch_bounds__(TX * TY) void zQ(const BoxDev* __restrict__ boxes,
         }
       }
       // ---- x-edge
-      if constexpr (kE) {
+      if constexpr (kE && !kT) {
         const T zRY = zwin<0, 0, 6, 3>(wRY, q, wall, N, T(0), zt);
         const T zPY = zwin<0, 0, 6, 3>(wPY, q, wall, N, T(0), zt);
         const T zUY = zwin<0, 0, 6, 3>(wUY, q, wall, N, T(0), zt);
@@ -667,7 +689,7 @@ __global__ __launch_bounds__(TX * TY) void zQ(const BoxDev* __restrict__ boxes,
         if (need_nu) nyz = g.lyz * exp(zwin<0, 0, 6, 3>(wLY, q, wall, N, T(0), zt));
         if (visc) {
           syz = T(0.5) * (dzUY + dyUZ);
-          tyz = zRY * nyz * syz;
+          tyz = tq ? tq[TAU_YZ * ws.stride + o] : zRY * nyz * syz;
         }
         const T jx = dyBZ - dzBY;
         const T eta = ph.eta_const > T(0) ? ph.eta_const : ph.nuB * nyz;
@@ -691,7 +713,7 @@ __global__ __launch_bounds__(TX * TY) void zQ(const BoxDev* __restrict__ boxes,
         }
       }
       // ---- z-face energy flux: -zdn(e) u_z + nuE zdn(rho) dz zdn(nu) zdn(e_m) ddzdn(ln e_m)
-      if constexpr (kZ) {
+      if constexpr (kZ && !kT) {
         T hz = T(0);
         if (adv) hz = -zwin<0, 0, 6, 3>(wE, q, wall, N, T(0), zt) * wUZ[3];
         if (ediff)
@@ -722,9 +744,13 @@ __global__ __launch_bounds__(TX * TY) void zQ(const BoxDev* __restrict__ boxes,
     if (kZ && valid(q2) && q2 >= it.z0 && q2 < it.z1) {
       const long long o = col(q2);
       const T szz = zwin<1, 1, 6, 2>(wUZ, q2, wall, N, g.hzi, zt);
+      if constexpr (kT) {
+        if (own) ws.q(TAU_ZZ)[o] = wRho[2] * (g.lz * wNu[2]) * (szz + ph.c1 * Dg[o]);
+        continue;
+      }
       T gzz = T(0), czz = T(0);
       if (visc) {
-        const T tzz = wRho[2] * (g.lz * wNu[2]) * (szz + ph.c1 * Dg[o]);
+        const T tzz = tq ? tq[TAU_ZZ * ws.stride + o] : wRho[2] * (g.lz * wNu[2]) * (szz + ph.c1 * Dg[o]);
         gzz = tzz;
         czz = tzz * szz;
       }
@@ -744,7 +770,9 @@ __global__ __launch_bounds__(TX * TY) void zQ(const BoxDev* __restrict__ boxes,
 // Lyz, Qz (as in Q), the centre terms Gxx = tau_xx - xup(p_x) xup(u_x) - P,
 // Gyy, Qc = tau_xx S_xx + tau_yy S_yy - P div u, and the x/y-face energy
 // fluxes Hx, Hy (eq. ien, eq. ediffuse).
-template <class T, int TX, int TY, bool PERS>
+// TAU (quenching): only the raw stress components tau_xy, tau_xx, tau_yy,
+// into the workspace arrays q(TAU_*).
+template <class T, int TX, int TY, bool PERS, bool TAU = false>
 __global__ __launch_bounds__(TX * TY) void zP(const BoxDev* __restrict__ boxes,
                                               const ZItem* __restrict__ items, int nitems, const T* __restrict__ ztab,
                                                int* __restrict__ queue,
@@ -808,9 +836,18 @@ __global__ __launch_bounds__(TX * TY) void zP(const BoxDev* __restrict__ boxes,
       if (q == DQ_LQ) return log(ph.gamma1 * S(DQ_E, xx, yy)) - lpa;
       return S(q, xx, yy);
     };
+    if constexpr (TAU) {
+      T sxx, syy, txx, tyy;
+      centre_tau<T>(SA, x, y, g, ph, sxx, syy, txx, tyy);
+      ws.q(TAU_XY)[o] = zedge_tau<T>(SA, x, y, g);
+      ws.q(TAU_XX)[o] = txx;
+      ws.q(TAU_YY)[o] = tyy;
+      continue;
+    }
     T gxy, gyx, ez, lxz, lyz, qz, gxx, gyy, qc, dpx, dpy;
-    zedge_q<T>(SA, x, y, g, ph, gxy, gyx, ez, lxz, lyz, qz);
-    centre_q<T>(SA, x, y, g, ph, gxx, gyy, qc);
+    const T* tq = ws.tq;
+    zedge_q<T>(SA, x, y, g, ph, gxy, gyx, ez, lxz, lyz, qz, tq ? tq + TAU_XY * ws.stride + o : nullptr);
+    centre_q<T>(SA, x, y, g, ph, gxx, gyy, qc, tq ? tq + TAU_XX * ws.stride + o : nullptr, ws.stride);
     face_dp<T>(SA, x, y, g, ph, (tm & T_LNP) ? T(exp(lpa)) : T(0), dpx, dpy);
     ws.pq(POUT_GXY)[o] = gxy;
     ws.pq(POUT_GYX)[o] = gyx;
@@ -825,6 +862,72 @@ __global__ __launch_bounds__(TX * TY) void zP(const BoxDev* __restrict__ boxes,
     ws.pq(POUT_DPY)[o] = dpy;
     ws.pq(POUT_HX)[o] = xface_h<T>(SA, x, y, g, ph);
     ws.pq(POUT_HY)[o] = yface_h<T>(SA, x, y, g, ph);
+  }
+  ZLOOP_END
+}
+
+// ---------------------------------------------------------------------------
+// Quenching of the viscous stress (Section 6.2, eq. quench): component
+// blockIdx.y of the raw stress (workspace array q(c)) into the quenched one
+// (array WS_TQ0 + c): tau min(max of q over the 3x3x3 neighbourhood, q_lim),
+// q = D2 / (|tau| + D2 / q_max), D2 the sum over the axes of the absolute
+// second differences (none across the ends of a wall-bounded z axis), q = 0
+// where tau and D2 vanish.  The raw planes r-2, r-1, r sit in an LDS ring
+// (halo 2); q of plane r-1 on the tile and a one-cell rim goes to LDS, its
+// in-plane maximum over 3x3 cells into a z window (q >= 0, so a plane that
+// does not exist counts as 0), and plane r-2 is finished.
+template <class T, int TX, int TY>
+__global__ __launch_bounds__(TX * TY) void zQn(const BoxDev* __restrict__ boxes,
+                                               const ZItem* __restrict__ items, int nitems,
+                                               const T* __restrict__ ztab, Phys<T> ph, ZWork<T> ws) {
+  constexpr bool PERS = false;
+  int* queue = nullptr;
+  using P2 = Plane<TX, TY, 2>;
+  using P1 = Plane<TX, TY, 1>;
+  constexpr int NT = TX * TY;
+  __shared__ T sT[3][P2::NP];
+  __shared__ T sQ[P1::NP];
+  const int c = (int)blockIdx.y;
+  const T* __restrict__ tin = ws.q(c);
+  T* __restrict__ tout = ws.arr(WS_TQ0 + c);
+  ZLOOP_BEGIN
+  PlaneIdx<TX, TY, 2> i2;
+  i2.init(b, it.x0, it.y0);
+  T wM[3] = {};   // slot m: in-plane maximum of q on plane r-3+m
+  for (int r = it.z0 - 2; r <= it.z1 + 1; ++r) {
+    __syncthreads();
+    if (valid(r)) load_plane(sT[wrapm(r, 3)], tin, b, i2, kk(r));
+    __syncthreads();
+    const int p = r - 1;
+    T m = T(0);
+    if (r >= it.z0 && valid(p)) {
+      const T* A = sT[wrapm(p, 3)];
+      const T* Am = sT[wrapm(p - 1, 3)];
+      const T* Ap = sT[wrapm(p + 1, 3)];
+      const bool zok = valid(p - 1) && valid(p + 1);
+      for (int t = threadIdx.x; t < P1::N; t += NT) {
+        const int yy = t / P1::W, xx = t - yy * P1::W;
+        const int x = xx - 1, y = yy - 1;
+        const T v = A[P2::at(x, y)];
+        T d2 = fabs(A[P2::at(x + 1, y)] - T(2) * v + A[P2::at(x - 1, y)]) +
+               fabs(A[P2::at(x, y + 1)] - T(2) * v + A[P2::at(x, y - 1)]);
+        if (zok) d2 = d2 + fabs(Ap[P2::at(x, y)] - T(2) * v + Am[P2::at(x, y)]);
+        const T den = fabs(v) + d2 / ph.q_max;
+        sQ[t] = den > T(0) ? d2 / den : T(0);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx) m = fmax(m, sQ[P1::at(tx + dx, ty + dy)]);
+    }
+    push(wM, m);
+    const int oz = r - 2;
+    if (own && oz >= it.z0 && oz < it.z1 && valid(oz)) {
+      const T mz = fmax(fmax(wM[0], wM[1]), wM[2]);
+      const T fac = mz < ph.q_lim ? mz : ph.q_lim;
+      tout[col(oz)] = sT[wrapm(oz, 3)][P2::at(tx, ty)] * fac;
+    }
   }
   ZLOOP_END
 }
@@ -1105,20 +1208,35 @@ static void launch_zstage_m(const ZLaunch& L, const ZStageArgs<T>& a) {
                        L.nbox, L.nplanes, a.lnpart, (double)a.ph.gamma1, a.w.lnpav);
   }
   L.at(PASS_EDGES);
+  // quenching: the raw stress (stress-only launches of Q and P), then its
+  // quenched version, which Q and P below take in place of their own
+  ZWork<T> wq = a.w;
+  if ((a.ph.terms & T_QUENCH) && (a.ph.terms & T_VISC)) {
+    const dim3 gq(8 * ((n + 7) / 8));
+    hipLaunchKernelGGL((zQ<T, TX, TY, false, QM_EDGES | QM_TAU>), gq, block, 0, L.stream, L.boxes, L.items, n,
+                       a.ztab, (int*)nullptr, a.f, a.ph, a.w, a.lnavg, a.w.lnpav);
+    hipLaunchKernelGGL((zQ<T, TX, TY, false, QM_ZC | QM_TAU>), gq, block, 0, L.stream, L.boxes, L.items, n,
+                       a.ztab, (int*)nullptr, a.f, a.ph, a.w, a.lnavg, a.w.lnpav);
+    hipLaunchKernelGGL((zP<T, TX, TY, false, true>), gq, block, 0, L.stream, L.boxes, L.items, n, a.ztab,
+                       (int*)nullptr, a.f, a.ph, a.w);
+    hipLaunchKernelGGL((zQn<T, TX, TY>), dim3(gq.x, TAU_COUNT), block, 0, L.stream, L.boxes, L.items, n, a.ztab,
+                       a.ph, a.w);
+    wq.tq = a.w.arr(WS_TQ0);
+  }
   hipLaunchKernelGGL((zQ<T, TX, TY, PERS, QM_EDGES>), grid((const void*)zQ<T, TX, TY, PERS, QM_EDGES>), block, 0,
-                     L.stream, L.boxes, L.items, n, a.ztab, q ? q + 16 : q, a.f, a.ph, a.w, a.lnavg,
+                     L.stream, L.boxes, L.items, n, a.ztab, q ? q + 16 : q, a.f, a.ph, wq, a.lnavg,
                      a.w.lnpav);
   if (lnp)
     hipLaunchKernelGGL((zQ<T, TX, TY, PERS, QM_ZC | QM_LNP>), grid((const void*)zQ<T, TX, TY, PERS, QM_ZC | QM_LNP>),
                        block, 0, L.stream, L.boxes, L.items, n, a.ztab, q ? q + 32 + 8 * kNFMasks : q, a.f, a.ph,
-                       a.w, a.lnavg, a.w.lnpav);
+                       wq, a.lnavg, a.w.lnpav);
   else
     hipLaunchKernelGGL((zQ<T, TX, TY, PERS, QM_ZC>), grid((const void*)zQ<T, TX, TY, PERS, QM_ZC>), block, 0,
-                       L.stream, L.boxes, L.items, n, a.ztab, q ? q + 32 + 8 * kNFMasks : q, a.f, a.ph, a.w,
+                       L.stream, L.boxes, L.items, n, a.ztab, q ? q + 32 + 8 * kNFMasks : q, a.f, a.ph, wq,
                        a.lnavg, a.w.lnpav);
   L.at(PASS_CF);
   hipLaunchKernelGGL((zP<T, TX, TY, PERS>), grid((const void*)zP<T, TX, TY, PERS>), block, 0, L.stream, L.boxes,
-                     L.items, n, a.ztab, q ? q + 24 : q, a.f, a.ph, a.w);
+                     L.items, n, a.ztab, q ? q + 24 : q, a.f, a.ph, wq);
   L.at(PASS_FINAL);
   launch_final<T, PERS>(L, a, q);
   L.at(PASS_END);

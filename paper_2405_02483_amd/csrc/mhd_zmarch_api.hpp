@@ -40,13 +40,26 @@ inline int ztile_y(int t) { return t == ZTILE_64x4 ? 4 : ((t == ZTILE_16x16 || t
 // Stage workspace: WS_COUNT arrays of `stride` elements back to back, so a
 // kernel needs one base pointer for all of them (array pointers held in
 // scalar registers would otherwise spill).
+// With T_QUENCH six more follow: the quenched stress components, in the
+// order of TauC.
 enum WsArr : int { WS_NUS = 0, WS_D, WS_UZ, WS_LNT, WS_Q0, WS_P0 = WS_Q0 + QOUT_COUNT,
-                   WS_DIVB = WS_P0 + POUT_COUNT, WS_COUNT };
+                   WS_DIVB = WS_P0 + POUT_COUNT, WS_COUNT, WS_TQ0 = WS_COUNT,
+                   WS_COUNT_QUENCH = WS_TQ0 + 6 };
+
+// Viscous stress components (eq. itv) and where they live: tau_xz on the
+// y-edge, tau_yz on the x-edge, tau_zz, tau_xx, tau_yy at the centre, tau_xy
+// on the z-edge.  Under quenching the passes' stress-only launches write
+// the raw components to workspace arrays q(TauC) (pass Q's outputs, not
+// yet written then), and the quench pass the quenched ones to WS_TQ0 + TauC.
+enum TauC : int { TAU_XZ = 0, TAU_YZ, TAU_ZZ, TAU_XY, TAU_XX, TAU_YY, TAU_COUNT };
 
 template <class T> struct ZWork {
   T* base;
   long long stride;
   T* lnpav;               // ln P_aver per plane of every box (BoxDev::poff; eq. pressure)
+  // quenched stress (component c at tq + c * stride), or null: the passes
+  // then form the stress themselves
+  const T* tq = nullptr;
   __host__ __device__ T* arr(int a) const { return base + (long long)a * stride; }
   __host__ __device__ T* q(int i) const { return arr(WS_Q0 + i); }
   __host__ __device__ T* pq(int i) const { return arr(WS_P0 + i); }

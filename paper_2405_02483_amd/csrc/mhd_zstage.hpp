@@ -75,25 +75,44 @@ enum DQ : int {
   DQ_COUNT
 };
 
-// z-directed edge (x - 1/2, y - 1/2): edge viscosity (eq. nuij), strain and
-// stress (eq. itv), E_z (eq. ohm), the momentum fluxes G_xy = tau_xy -
-// ydn(p_x) xdn(u_y) and G_yx = tau_xy - xdn(p_y) ydn(u_x), the Lorentz
-// products L_xz = J_z xdn(B_y), L_yz = J_z ydn(B_x), and the heating
-// 2 tau_xy S_xy + eta J_z^2 / mu (eq. vdiss, Joule).
+// z-directed edge (x - 1/2, y - 1/2): the edge viscosity (eq. nuij), the
+// density ydn(xdn(rho)) and the strain S_xy (eq. itv).
+template <class T, class A>
+__device__ __forceinline__ T zedge_nu(const A& S, int x, int y, const Geo<T>& g) {
+  return g.lxy * exp(op6<0, 0, T>([&](int m) { return S(DQ_XL, x, y + m); }, T(0)));
+}
+template <class T, class A> __device__ __forceinline__ T zedge_rho(const A& S, int x, int y) {
+  return op6<0, 0, T>([&](int m) { return S(DQ_RXD, x, y + m); }, T(0));
+}
+template <class T, class A>
+__device__ __forceinline__ T zedge_strain(const A& S, int x, int y, const Geo<T>& g) {
+  return T(0.5) * (op6<1, 0, T>([&](int m) { return S(DQ_UX, x, y + m); }, g.hyi) +
+                   op6<1, 0, T>([&](int m) { return S(DQ_UY, x + m, y); }, g.hxi));
+}
+// the viscous stress tau_xy = rho nu_xy S_xy on the z-edge
+template <class T, class A>
+__device__ __forceinline__ T zedge_tau(const A& S, int x, int y, const Geo<T>& g) {
+  return zedge_rho<T>(S, x, y) * zedge_nu<T>(S, x, y, g) * zedge_strain<T>(S, x, y, g);
+}
+
+// z-directed edge: strain and stress (eq. itv; tq: the quenched stress, or
+// null), E_z (eq. ohm), the momentum fluxes G_xy = tau_xy - ydn(p_x)
+// xdn(u_y) and G_yx = tau_xy - xdn(p_y) ydn(u_x), the Lorentz products L_xz =
+// J_z xdn(B_y), L_yz = J_z ydn(B_x), and the heating 2 tau_xy S_xy +
+// eta J_z^2 / mu (eq. vdiss, Joule).
 template <class T, class A>
 __device__ __forceinline__ void zedge_q(const A& S, int x, int y, const Geo<T>& g, const Phys<T>& ph,
-                                        T& gxy, T& gyx, T& ez, T& lxz, T& lyz, T& qz) {
+                                        T& gxy, T& gyx, T& ez, T& lxz, T& lyz, T& qz,
+                                        const T* tq = nullptr) {
   const unsigned tm = ph.terms;
   const bool visc = tm & T_VISC, res = tm & T_RESIST, ind = tm & T_INDUCT, lor = tm & T_LORENTZ,
              adv = tm & T_ADV;
   const bool need_nu = visc || (res && !(ph.eta_const > T(0)));
   T nxy = T(0), txy = T(0), sxy = T(0);
-  if (need_nu) nxy = g.lxy * exp(op6<0, 0, T>([&](int m) { return S(DQ_XL, x, y + m); }, T(0)));
+  if (need_nu) nxy = zedge_nu<T>(S, x, y, g);
   if (visc) {
-    const T rxy = op6<0, 0, T>([&](int m) { return S(DQ_RXD, x, y + m); }, T(0));
-    sxy = T(0.5) * (op6<1, 0, T>([&](int m) { return S(DQ_UX, x, y + m); }, g.hyi) +
-                    op6<1, 0, T>([&](int m) { return S(DQ_UY, x + m, y); }, g.hxi));
-    txy = rxy * nxy * sxy;
+    sxy = zedge_strain<T>(S, x, y, g);
+    txy = tq ? *tq : zedge_rho<T>(S, x, y) * nxy * sxy;
   }
   const T jz = op6<1, 0, T>([&](int m) { return S(DQ_BY, x + m, y); }, g.hxi) -
                op6<1, 0, T>([&](int m) { return S(DQ_BX, x, y + m); }, g.hyi);
@@ -120,23 +139,38 @@ __device__ __forceinline__ void zedge_q(const A& S, int x, int y, const Geo<T>& 
   qz = q;
 }
 
-// Cell centre (x, y): G_xx = tau_xx - xup(p_x) xup(u_x), G_yy likewise
-// (eq. itv, eq. mom), and Q_c = tau_xx S_xx + tau_yy S_yy - P div u (eq.
-// vdiss, eq. ien).
+// Cell centre (x, y): the strain S_xx, S_yy and the viscous stress tau_xx =
+// rho nu_xx (S_xx + c1 div u), tau_yy (eq. itv, eq. nuij).
+template <class T, class A>
+__device__ __forceinline__ void centre_tau(const A& S, int x, int y, const Geo<T>& g, const Phys<T>& ph,
+                                           T& sxx, T& syy, T& txx, T& tyy) {
+  sxx = op6<1, 1, T>([&](int m) { return S(DQ_UX, x + m, y); }, g.hxi);
+  syy = op6<1, 1, T>([&](int m) { return S(DQ_UY, x, y + m); }, g.hyi);
+  const T Dc = S(DQ_D, x, y);
+  const T rn = S(DQ_RHO, x, y) * S(DQ_NU, x, y);
+  txx = rn * g.lx * (sxx + ph.c1 * Dc);
+  tyy = rn * g.ly * (syy + ph.c1 * Dc);
+}
+
+// Cell centre: G_xx = tau_xx - xup(p_x) xup(u_x), G_yy likewise (eq. itv,
+// eq. mom), and Q_c = tau_xx S_xx + tau_yy S_yy - P div u (eq. vdiss, eq.
+// ien); tq: the quenched tau_xx and tau_yy (tq[0], tq[stride]), or null.
 template <class T, class A>
 __device__ __forceinline__ void centre_q(const A& S, int x, int y, const Geo<T>& g, const Phys<T>& ph,
-                                         T& gxx, T& gyy, T& qc) {
+                                         T& gxx, T& gyy, T& qc, const T* tq = nullptr,
+                                         long long stride = 0) {
   const unsigned tm = ph.terms;
   const bool visc = tm & T_VISC, adv = tm & T_ADV, pres = tm & T_PRES;
-  const T sxx = op6<1, 1, T>([&](int m) { return S(DQ_UX, x + m, y); }, g.hxi);
-  const T syy = op6<1, 1, T>([&](int m) { return S(DQ_UY, x, y + m); }, g.hyi);
+  T sxx, syy, txx, tyy;
+  centre_tau<T>(S, x, y, g, ph, sxx, syy, txx, tyy);
   const T Dc = S(DQ_D, x, y);
   const T Pc = ph.gamma1 * S(DQ_E, x, y);
   T a = T(0), c = T(0), q = T(0);
   if (visc) {
-    const T rn = S(DQ_RHO, x, y) * S(DQ_NU, x, y);
-    const T txx = rn * g.lx * (sxx + ph.c1 * Dc);
-    const T tyy = rn * g.ly * (syy + ph.c1 * Dc);
+    if (tq) {
+      txx = tq[0];
+      tyy = tq[stride];
+    }
     a = txx;
     c = tyy;
     q = txx * sxx + tyy * syy;

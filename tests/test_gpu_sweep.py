@@ -6,8 +6,8 @@ this one aims at indexing mistakes that only some (size, tile) pairs expose
 (partial tiles, chunk edges, planes next to a wall).  Each box also switches
 on a random subset of the optional terms (Newtonian cooling, the Coriolis
 force, energy diffusion about the horizontal mean, the ln(P/P_aver) pressure
-gradient, the Smagorinsky viscosity, the five-cell maximum) and, in some
-boxes, the constant viscosity.  Cells are
+gradient, the Smagorinsky viscosity, the five-cell maximum, the quenching
+of the viscous stress) and, in some boxes, the constant viscosity.  Cells are
 anisotropic: each axis's spacing is scaled by a random factor in [0.6, 1.6],
 so the viscosity length factors dx_a and max(dx_a, dx_b), the Courant limits
 and the div B scale see dx != dy != dz.
@@ -81,7 +81,7 @@ def test_rhs_random_sizes_all_tiles(case, walls, nx, ny, nz, ftiles):
     prm = dict(prm, terms=T_ALL | extra, e_cool=trng.uniform(0.5, 2.0), t_cool=trng.uniform(0.3, 2.0),
                rho_cool=trng.uniform(0.2, 2.0), cool_cut=trng.randrange(3),
                omega=tuple(trng.uniform(-1.5, 1.5) for _ in range(3)))
-    extra2 = sum(bit for bit in (O.T_SMAG, O.T_MAX5) if trng.random() < 0.5)
+    extra2 = sum(bit for bit in (O.T_SMAG, O.T_MAX5, O.T_QUENCH) if trng.random() < 0.5)
     prm = dict(prm, terms=prm["terms"] | extra2, c_smag=trng.uniform(0.05, 0.3))
     if case % 4 == 1:
         prm = dict(prm, nu_const=trng.uniform(0.005, 0.02))

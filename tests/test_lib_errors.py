@@ -41,6 +41,8 @@ def _params(**over):
     (dict(terms=1 << 16), lib.MHD_EINVAL),
     (dict(terms=lib.T_ALL | lib.T_SMAG, c_smag=-0.1), lib.MHD_EINVAL),
     (dict(terms=lib.T_ALL | lib.T_SMAG, c_smag=float("nan")), lib.MHD_EINVAL),
+    (dict(terms=lib.T_ALL | lib.T_QUENCH, q_max=0.0, q_lim=2.0), lib.MHD_EINVAL),
+    (dict(terms=lib.T_ALL | lib.T_QUENCH, q_max=8.0, q_lim=float("inf")), lib.MHD_EINVAL),
     (dict(terms=lib.T_ALL | lib.T_DIVB, c_divb=-0.1), lib.MHD_EINVAL),
     # above the RK3 real-axis limit of the div B diffusion on cubic cells
     (dict(terms=lib.T_ALL | lib.T_DIVB, c_divb=0.1359), lib.MHD_EINVAL),
