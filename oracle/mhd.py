@@ -71,6 +71,14 @@ garbled:
   All six components are quenched, each at its own position, and the
   quenched stress enters both the momentum equation and the viscous
   heating (which keeps the total energy budget).
+* Section 3 after eq. itv, the switch to second-order derivatives: read as
+  the strain of the viscous stress (and the div u of its c1 term) taken
+  with the second-order staggered derivative (the first pair of eq. deriv
+  with weight 1) wherever a cell touching the component's position is
+  rough: some axis's absolute second difference of ln rho or ln e_m
+  (energy per unit mass, the paper's e) exceeds d2_lim (&pde d2lnr_lim =
+  0.3).  The viscous heating uses the same strain.  The indicator is a
+  mask: it carries no derivative.
 * eq. mom, Coriolis force: -2 rho Omega x u = -2 Omega x p, with each
   momentum component carried to the face of the component it drives by the
   staggered interpolations (e.g. p_z at an x-face is xdn(zup(p_z))).
@@ -85,12 +93,12 @@ from .stagger import Ops, AX_X, AX_Y, AX_Z
 __all__ = [
     "T_CONT", "T_ADV", "T_PRES", "T_VISC", "T_LORENTZ", "T_INDUCT",
     "T_RESIST", "T_EDIFF", "T_GRAV", "T_ALL", "T_HD", "T_IDEAL", "T_COOL", "T_CORI",
-    "T_EDIFFAV", "T_LNP", "T_DIVB", "T_SMAG", "T_MAX5", "T_QUENCH",
+    "T_EDIFFAV", "T_LNP", "T_DIVB", "T_SMAG", "T_MAX5", "T_QUENCH", "T_ORDER2",
     "ALPHA", "BETA", "Grid", "Params", "ghost_fill", "rhs", "rhs_nofill",
     "step", "rk3", "courant", "stats", "step_vjp", "rhs_vjp", "FIELDS",
     "interior_slices", "smoothed_viscosity", "newton_cooling", "coriolis",
     "horizontal_ln_mean", "pressure_gradient_ln", "viscosity_lengths",
-    "edge_viscosity", "smagorinsky_rate", "quench_factor",
+    "edge_viscosity", "smagorinsky_rate", "quench_factor", "rough_cells", "strain",
 ]
 
 FIELDS = ("rho", "px", "py", "pz", "e", "bx", "by", "bz")
@@ -115,6 +123,7 @@ T_DIVB = 1 << 13     # div B diffusion C_divb h^2 / dt grad(div B); needs the st
 T_SMAG = 1 << 14     # Smagorinsky viscosity added to the speed-like one (eq. nusmag)
 T_MAX5 = 1 << 15     # spread the viscosity by the maximum over five cells (do_max5)
 T_QUENCH = 1 << 16   # quench each viscous stress component (eq. quench)
+T_ORDER2 = 1 << 17   # second-order strain where ln rho or ln e_m is rough (after eq. itv)
 T_HD = T_CONT | T_ADV | T_PRES | T_VISC | T_EDIFF
 T_IDEAL = T_CONT | T_ADV | T_PRES | T_LORENTZ | T_INDUCT
 
@@ -190,6 +199,7 @@ class Params:
     c_smag: float = 0.0       # Smagorinsky constant (eq. nusmag; &pde Csmag)
     q_max: float = 8.0        # eq. quench, &quench qmax
     q_lim: float = 2.0        # eq. quench, &quench qlim
+    d2_lim: float = 0.3       # second-order strain above this |D2 ln rho|, |D2 ln e_m| (&pde d2lnr_lim)
 
 
 def interior_slices(grid):
@@ -265,6 +275,47 @@ def _safe_sqrt(s):
     """sqrt(max(s, 0)) with zero derivative where s <= 0."""
     pos = s > 0
     return torch.where(pos, torch.sqrt(torch.where(pos, s, torch.ones_like(s))), torch.zeros_like(s))
+
+
+def rough_cells(rho, e, O, lim):
+    """Cells where the sixth-order strain gives way to the second-order one
+    (Section 3, after eq. itv): some axis's absolute second difference of
+    ln rho or of ln e_m (e_m = e / rho, the energy per unit mass) exceeds
+    lim (none across the ends of a wall-bounded axis)."""
+    lr, le = torch.log(rho), torch.log(e / rho)
+    m = None
+    for a in (AX_X, AX_Y, AX_Z):
+        for f in (lr, le):
+            d = O.d2abs(f, a)
+            m = d if m is None else torch.maximum(m, d)
+    return m > lim
+
+
+def strain(ux, uy, uz, O, rough=None):
+    """The strain of eq. itv, (sxx, syy, szz, sxy, sxz, syz, D): diagonal and
+    div u at cell centres, S_xy on the z-edge, S_xz on the y-edge, S_yz on
+    the x-edge, from the sixth-order derivatives, or where `rough` (a mask
+    of cells) is given, from the second-order ones wherever one of the
+    cells touching the component's position is rough."""
+    def d(f, ax, form, order):
+        return O.stencil(f, ax, "d", form, order)
+    out = []
+    for order in ((6, 2) if rough is not None else (6,)):
+        sxx, syy, szz = d(ux, AX_X, "up", order), d(uy, AX_Y, "up", order), d(uz, AX_Z, "up", order)
+        out.append((sxx, syy, szz,
+                    0.5 * (d(ux, AX_Y, "dn", order) + d(uy, AX_X, "dn", order)),
+                    0.5 * (d(ux, AX_Z, "dn", order) + d(uz, AX_X, "dn", order)),
+                    0.5 * (d(uy, AX_Z, "dn", order) + d(uz, AX_Y, "dn", order)),
+                    sxx + syy + szz))
+    if rough is None:
+        return out[0]
+    s6, s2 = out
+    c = rough
+    ze = O.any_dn(O.any_dn(c, AX_X), AX_Y)    # z-edge (i-1/2, j-1/2, k)
+    ye = O.any_dn(O.any_dn(c, AX_X), AX_Z)    # y-edge (i-1/2, j, k-1/2)
+    xe = O.any_dn(O.any_dn(c, AX_Y), AX_Z)    # x-edge (i, j-1/2, k-1/2)
+    masks = (c, c, c, ze, ye, xe, c)
+    return tuple(torch.where(mk, b, a) for mk, a, b in zip(masks, s6, s2))
 
 
 def quench_factor(t, O, par):
@@ -383,13 +434,13 @@ def rhs_nofill(f, grid, par, dt=None):
     ryz = O.zdn(O.ydn(rho))
 
     # -- strain and viscous stress (eq. itv) ---------------------------------
-    sxx, syy, szz = O.ddxup(ux), O.ddyup(uy), O.ddzup(uz)
-    sxy = 0.5 * (O.ddydn(ux) + O.ddxdn(uy))
-    sxz = 0.5 * (O.ddzdn(ux) + O.ddxdn(uz))
-    syz = 0.5 * (O.ddzdn(uy) + O.ddydn(uz))
-    txx = rho * (lx * nt) * (sxx + par.c1 * D)
-    tyy = rho * (ly * nt) * (syy + par.c1 * D)
-    tzz = rho * (lz * nt) * (szz + par.c1 * D)
+    rough = rough_cells(rho, e, O, par.d2_lim) if T & T_ORDER2 else None
+    sxx, syy, szz, sxy, sxz, syz, Dt = strain(ux, uy, uz, O, rough)
+    if rough is None:
+        Dt = D
+    txx = rho * (lx * nt) * (sxx + par.c1 * Dt)
+    tyy = rho * (ly * nt) * (syy + par.c1 * Dt)
+    tzz = rho * (lz * nt) * (szz + par.c1 * Dt)
     txy = rxy * nxy * sxy
     txz = rxz * nxz * sxz
     tyz = ryz * nyz * syz

@@ -106,18 +106,20 @@ class Ops:
         self.wall_z = wall_z
 
     # -- generic -----------------------------------------------------------
-    def stencil(self, f, axis, fam, form):
-        """fam: 'i' (interpolation) or 'd' (derivative); form: 'dn' or 'up'."""
+    def stencil(self, f, axis, fam, form, order=6):
+        """fam: 'i' (interpolation) or 'd' (derivative); form: 'dn' or 'up';
+        order: 6, or 2 for the second-order stencil (the strain where the
+        state is rough, the switch after eq. itv)."""
         h = self.h[axis]
         if axis == AX_Z and self.wall_z:
-            return self._wall_stencil(f, fam, form, h)
+            return self._wall_stencil(f, fam, form, h, order)
         off = 0 if form == "dn" else 1      # c = i + off
 
         def get(p):
             return _shift(f, off + p - 1, axis), _shift(f, off - p, axis)
-        return _pair_formula(get, fam, 6, h)
+        return _pair_formula(get, fam, order, h)
 
-    def _wall_stencil(self, f, fam, form, h):
+    def _wall_stencil(self, f, fam, form, h, top=6):
         n = f.shape[0]
         off = 0 if form == "dn" else 1
         planes = [None] * n
@@ -125,6 +127,8 @@ class Ops:
             c = k + off
             order = None
             for o in (6, 4, 2):
+                if o > top:
+                    continue
                 q = o // 2
                 if c - q >= 0 and c + q - 1 <= n - 1:
                     order = o
@@ -176,6 +180,15 @@ class Ops:
         ones at the ends of a wall-bounded axis): the three-cell maximum
         applied twice, which also fixes the adjoint's choice in a tie."""
         return self.max3(self.max3(f, axis), axis)
+
+    def any_dn(self, m, axis):
+        """m[i] or m[i-1] along the axis for a boolean mask (just m[0] at the
+        lower end of a wall-bounded axis)."""
+        if axis == AX_Z and self.wall_z:
+            out = m.clone()
+            out[1:] = m[1:] | m[:-1]
+            return out
+        return m | _shift(m, -1, axis)
 
     def d2abs(self, f, axis):
         """Absolute second difference |f[i+1] - 2 f[i] + f[i-1]| along the

@@ -475,7 +475,7 @@ def test_adjoint_matches_central_differences(kind):
         assert abs(fd - ad) < 1e-6 * abs(fd), (fd, ad)
 
 
-@pytest.mark.parametrize("extra", ["cool_cori", "divb", "ediffav_lnp", "smag_max5", "quench"])
+@pytest.mark.parametrize("extra", ["cool_cori", "divb", "ediffav_lnp", "smag_max5", "quench", "order2"])
 def test_adjoint_with_optional_terms_matches_central_differences(extra):
     """The same check with the optional terms on, so the reference adjoint
     the library's is compared with is itself checked for them."""
@@ -490,6 +490,8 @@ def test_adjoint_with_optional_terms_matches_central_differences(extra):
         p = replace(p, terms=O.T_ALL | O.T_SMAG | O.T_MAX5, c_smag=0.15)
     elif extra == "quench":
         p = replace(p, terms=O.T_ALL | O.T_QUENCH)
+    elif extra == "order2":   # about a third of the cells rough
+        p = replace(p, terms=O.T_ALL | O.T_ORDER2, d2_lim=0.025, c1=-1.0 / 3.0)
     else:
         p = replace(p, terms=O.T_ALL | O.T_EDIFFAV | O.T_LNP)
     dt = 0.5 * O.courant(f, g, p)[0]
