@@ -121,6 +121,15 @@ enum {
  * drives the momentum and the viscous heating.  Needs MHD_T_VISC to have
  * an effect.  Not part of MHD_T_ALL.                                        */
 #define MHD_T_QUENCH   (1u << 16)
+/* Second-order strain where the state is rough (Section 3, after eq. itv):
+ * a cell is rough where some axis's absolute second difference of ln rho
+ * or of ln e_m (e_m = e / rho) exceeds d2_lim (none across the ends of a
+ * wall-bounded axis); a strain component of the viscous stress (and the
+ * div u of its c1 term) takes the second-order staggered derivatives
+ * wherever a cell touching its position is rough.  The viscous heating
+ * uses the same strain.  Needs MHD_T_VISC to have an effect.  Not part of
+ * MHD_T_ALL.                                                               */
+#define MHD_T_ORDER2   (1u << 17)
 
 /* One box of the mesh (&grid namelist: mx, my, mz, sx, sy, sz). */
 typedef struct {
@@ -164,6 +173,8 @@ typedef struct {
                                and >= 0 (&pde Csmag, typically 0.1 - 0.15)     */
     double q_max, q_lim;    /* with MHD_T_QUENCH: eq. quench, both finite and
                                > 0 (&quench qmax = 8, qlim = 2)                */
+    double d2_lim;          /* with MHD_T_ORDER2: the roughness limit, finite
+                               (&pde d2lnr_lim = 0.3)                          */
 } mhd_params;
 
 /* Conserved totals and diagnostics over the interior cells (float64).     */

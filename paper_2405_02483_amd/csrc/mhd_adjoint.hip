@@ -91,6 +91,13 @@ struct Builder {
   int d2(int a, int ax) { return emit(V_D2, a, ZERO, ZERO, 0.0, G_ONE, ax, 0, 0); }
   int sdiv(int a, int b) { return emit(V_SDIV, a, b, ZERO, 0.0, G_ONE, 0, 0, 0); }
   int cap(int a, double k) { return un(V_CAP, a, k); }
+  // second-order staggered derivative (form 0 dn, 1 up)
+  int dd2(int a, int ax, int form) { return emit(V_STEN, a, ZERO, ZERO, 0.0, G_ONE, ax, 2, form); }
+  // 1 where a cell touching position `kind` is rough, else 0 (no derivative)
+  int rough(int lnr, int lne, double lim, int kind) {
+    return emit(V_ROUGH, lnr, lne, ZERO, lim, G_ONE, kind, 0, 0);
+  }
+  int sel(int a, int b, int m) { return emit(V_SEL, a, b, m, 0.0, G_ONE, 0, 0, 0); }
 };
 
 // Drops instructions whose results never reach an output, renumbers slots
@@ -183,15 +190,31 @@ VProgram build_rhs_program(const mhd_params& p) {
   const int rxy = B.ydn(B.xdn(rho)), rxz = B.zdn(B.xdn(rho)), ryz = B.zdn(B.ydn(rho));
 
   // strain and stress (eq. itv)
-  const int sxy = B.scale(B.add(B.ddydn(ux), B.ddxdn(uy)), 0.5);
-  const int sxz = B.scale(B.add(B.ddzdn(ux), B.ddxdn(uz)), 0.5);
-  const int syz = B.scale(B.add(B.ddzdn(uy), B.ddydn(uz)), 0.5);
-  int txx = B.mul(B.mul(rho, B.scale(nt, 1.0, G_LX)), B.add(sxx, B.scale(D, p.c1)));
-  int tyy = B.mul(B.mul(rho, B.scale(nt, 1.0, G_LY)), B.add(syy, B.scale(D, p.c1)));
-  int tzz = B.mul(B.mul(rho, B.scale(nt, 1.0, G_LZ)), B.add(szz, B.scale(D, p.c1)));
-  int txy = B.mul(B.mul(rxy, nxy), sxy);
-  int txz = B.mul(B.mul(rxz, nxz), sxz);
-  int tyz = B.mul(B.mul(ryz, nyz), syz);
+  int vxx = sxx, vyy = syy, vzz = szz, Dt = D;
+  int vxy = B.scale(B.add(B.ddydn(ux), B.ddxdn(uy)), 0.5);
+  int vxz = B.scale(B.add(B.ddzdn(ux), B.ddxdn(uz)), 0.5);
+  int vyz = B.scale(B.add(B.ddzdn(uy), B.ddydn(uz)), 0.5);
+  // second-order switch (Section 3 after eq. itv): where a touching cell is
+  // rough, the stress's strain and div u from second-order derivatives
+  if ((T & MHD_T_ORDER2) && (T & MHD_T_VISC)) {
+    const int lnr = B.flog(rho), lne = B.flog(em);
+    const int mc = B.rough(lnr, lne, p.d2_lim, 0), mxe = B.rough(lnr, lne, p.d2_lim, 1);
+    const int mye = B.rough(lnr, lne, p.d2_lim, 2), mze = B.rough(lnr, lne, p.d2_lim, 3);
+    const int s2xx = B.dd2(ux, VX, 1), s2yy = B.dd2(uy, VY, 1), s2zz = B.dd2(uz, VZ, 1);
+    Dt = B.sel(D, B.add(B.add(s2xx, s2yy), s2zz), mc);
+    vxx = B.sel(vxx, s2xx, mc);
+    vyy = B.sel(vyy, s2yy, mc);
+    vzz = B.sel(vzz, s2zz, mc);
+    vxy = B.sel(vxy, B.scale(B.add(B.dd2(ux, VY, 0), B.dd2(uy, VX, 0)), 0.5), mze);
+    vxz = B.sel(vxz, B.scale(B.add(B.dd2(ux, VZ, 0), B.dd2(uz, VX, 0)), 0.5), mye);
+    vyz = B.sel(vyz, B.scale(B.add(B.dd2(uy, VZ, 0), B.dd2(uz, VY, 0)), 0.5), mxe);
+  }
+  int txx = B.mul(B.mul(rho, B.scale(nt, 1.0, G_LX)), B.add(vxx, B.scale(Dt, p.c1)));
+  int tyy = B.mul(B.mul(rho, B.scale(nt, 1.0, G_LY)), B.add(vyy, B.scale(Dt, p.c1)));
+  int tzz = B.mul(B.mul(rho, B.scale(nt, 1.0, G_LZ)), B.add(vzz, B.scale(Dt, p.c1)));
+  int txy = B.mul(B.mul(rxy, nxy), vxy);
+  int txz = B.mul(B.mul(rxz, nxz), vxz);
+  int tyz = B.mul(B.mul(ryz, nyz), vyz);
   // quenching (Section 6.2, eq. quench): each component times
   // min(max over 3x3x3 of D2 / (|tau| + D2 / q_max), q_lim)
   if ((T & MHD_T_QUENCH) && (T & MHD_T_VISC)) {
@@ -281,9 +304,9 @@ VProgram build_rhs_program(const mhd_params& p) {
                          B.ddzup(B.mul(B.zdn(e), uz))));
   if (T & MHD_T_PRES) de = B.sub(de, B.mul(P, D));
   if (T & MHD_T_VISC) {
-    int qv = B.add(B.add(B.mul(txx, sxx), B.mul(tyy, syy)), B.mul(tzz, szz));
-    qv = B.add(qv, B.scale(B.add(B.add(B.yup(B.xup(B.mul(txy, sxy))), B.zup(B.xup(B.mul(txz, sxz)))),
-                                 B.zup(B.yup(B.mul(tyz, syz)))),
+    int qv = B.add(B.add(B.mul(txx, vxx), B.mul(tyy, vyy)), B.mul(tzz, vzz));
+    qv = B.add(qv, B.scale(B.add(B.add(B.yup(B.xup(B.mul(txy, vxy))), B.zup(B.xup(B.mul(txz, vxz)))),
+                                 B.zup(B.yup(B.mul(tyz, vyz)))),
                            2.0));
     de = B.add(de, qv);
   }
@@ -339,6 +362,7 @@ VPlan plan_program(const VProgram& P) {
       case V_SQRT: case V_EXP: keep[I.out] = 1; break;
       case V_LOG: case V_RELU: case V_FLOOR: case V_MAX3: case V_ABS: case V_CAP: keep[I.a] = 1; break;
       case V_SDIV: keep[I.b] = keep[I.out] = 1; break;
+      case V_SEL: keep[I.c] = 1; break;
       case V_NORM3: keep[I.a] = keep[I.b] = keep[I.c] = keep[I.out] = 1; break;
       default: break;
     }
@@ -356,8 +380,10 @@ VPlan plan_program(const VProgram& P) {
   std::vector<int> gid(n), gend;
   for (int q = 0; q < n; ++q) {
     const VInstr& I = P.code[q];
-    const bool nb = I.op == V_STEN || I.op == V_MAX3 || I.op == V_MEAN3 || I.op == V_D2;
-    const bool dep = nb && !R.groups.empty() && prod[I.a] >= R.groups.back().first;
+    const bool nb = I.op == V_STEN || I.op == V_MAX3 || I.op == V_MEAN3 || I.op == V_D2 || I.op == V_ROUGH;
+    const bool dep = nb && !R.groups.empty() &&
+                     (prod[I.a] >= R.groups.back().first ||
+                      (I.op == V_ROUGH && prod[I.b] >= R.groups.back().first));
     if (q == 0 || dep || q - R.groups.back().first == kGroupMax) {
       if (!R.groups.empty()) gend.push_back(q);
       R.groups.push_back({q, 0});
@@ -531,8 +557,38 @@ __device__ __forceinline__ T sten(const T* a, const Geo<T>& g, const BoxDev& bx,
                                   int form, int i, int j, int k) {
   auto at = [&](int m) { return along(a, g, ax, i, j, k, m); };
   const T hinv = T(1.0 / (ax == VX ? bx.dx : (ax == VY ? bx.dy : bx.dz)));
+  if (fam == 2) return form ? (at(1) - at(0)) * hinv : (at(0) - at(-1)) * hinv;
   if (fam == 0) return form ? op6<0, 1, T>(at, hinv) : op6<0, 0, T>(at, hinv);
   return form ? op6<1, 1, T>(at, hinv) : op6<1, 0, T>(at, hinv);
+}
+
+// Second-order switch: whether cell (i, j, k) is rough (some axis's absolute
+// second difference of ln rho or ln e_m above lim), and whether a cell
+// touching position `kind` (0 centre, 1 x-edge, 2 y-edge, 3 z-edge of the
+// index) is.  Periodic boxes only (the adjoint's domain).
+template <class T>
+__device__ __forceinline__ bool rough_cell(const T* lr, const T* le, const Geo<T>& g, int i, int j, int k,
+                                           T lim) {
+  T m = T(0);
+  for (int v = 0; v < 2; ++v) {
+    const T* a = v ? le : lr;
+    const T c = a[g.at(i, j, k)];
+    m = fmax(m, fabs(a[g.at(i + 1, j, k)] - T(2) * c + a[g.at(i - 1, j, k)]));
+    m = fmax(m, fabs(a[g.at(i, j + 1, k)] - T(2) * c + a[g.at(i, j - 1, k)]));
+    m = fmax(m, fabs(a[g.at(i, j, k + 1)] - T(2) * c + a[g.at(i, j, k - 1)]));
+  }
+  return m > lim;
+}
+template <class T>
+__device__ __forceinline__ bool rough_at(const T* lr, const T* le, const Geo<T>& g, int i, int j, int k,
+                                         T lim, int kind) {
+  const int di = (kind == 2 || kind == 3) ? 1 : 0, dj = (kind == 1 || kind == 3) ? 1 : 0,
+            dk = (kind == 1 || kind == 2) ? 1 : 0;
+  bool r = false;
+  for (int a = 0; a <= dk; ++a)
+    for (int b = 0; b <= dj; ++b)
+      for (int c = 0; c <= di; ++c) r = r || rough_cell(lr, le, g, i - c, j - b, k - a, lim);
+  return r;
 }
 
 // Which of (lo, mid, hi) is the first maximal one: 0, 1 or 2.
@@ -624,6 +680,14 @@ __global__ __launch_bounds__(kBlock) void k_vm_group(const BoxDev* boxes, const 
         r = I.geo == G_HINV ? T(I.k / bx_.hmin) : T(I.k * geo_of(bx_, I.geo));
         break;
       case V_ABS: r = fabs(opnd(I.a, G.la)); break;
+      case V_ROUGH: {
+        int i, j, k;
+        coords(i, j, k);
+        const Geo<T> g(bx_);
+        r = rough_at(base + I.a * stride, base + I.b * stride, g, i, j, k, T(I.k), I.ax) ? T(1) : T(0);
+        break;
+      }
+      case V_SEL: r = opnd(I.c, G.lc) > T(0.5) ? opnd(I.b, G.lb) : opnd(I.a, G.la); break;
       case V_SDIV: {
         const T x = opnd(I.a, G.la), y = opnd(I.b, G.lb);
         r = y > T(0) ? x / y : T(0);
@@ -876,6 +940,24 @@ __global__ __launch_bounds__(kBlock) void k_vm_bwd(const BoxDev* boxes, const Bl
 #pragma unroll
         for (int r = 0; r < R; ++r) v1[r] = a[o[r]] < T(I.k) ? y[r] : T(0);
         put(ca, 1, v1);
+        break;
+      case V_ROUGH:   // a mask: no derivative
+#pragma unroll
+        for (int r = 0; r < R; ++r) v1[r] = T(0);
+        put(ca, 1, v1);
+        put(cb, 2, v1);
+        break;
+      case V_SEL:
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const bool m = c[o[r]] > T(0.5);
+          v1[r] = m ? T(0) : y[r];
+          v2[r] = m ? y[r] : T(0);
+          v3[r] = T(0);
+        }
+        put(ca, 1, v1);
+        put(cb, 2, v2);
+        put(cc, 4, v3);
         break;
       default: break;
     }

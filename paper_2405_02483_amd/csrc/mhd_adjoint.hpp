@@ -17,7 +17,8 @@
 namespace smhd {
 
 enum VOp : int {
-  V_STEN = 0,   // out = S(a): axis ax, family fam (0 interp, 1 deriv), form (0 dn, 1 up)
+  V_STEN = 0,   // out = S(a): axis ax, family fam (0 interp, 1 deriv, 2 second-order
+                //   deriv), form (0 dn, 1 up)
   V_ADD,        // out = a + b
   V_SUB,        // out = a - b
   V_MUL,        // out = a * b
@@ -37,6 +38,10 @@ enum VOp : int {
   V_D2,         // out = a[i+1] - 2 a[i] + a[i-1] along ax (periodic)
   V_SDIV,       // out = b > 0 ? a / b : 0
   V_CAP,        // out = a < k ? a : k        (derivative 0 at a >= k)
+  V_ROUGH,      // out = 1 if a cell touching position ax (0 centre, 1 x-, 2 y-,
+                //   3 z-edge) has a second difference of a (ln rho) or b (ln e_m)
+                //   above k, else 0 (a mask: no derivative)
+  V_SEL,        // out = c > 1/2 ? b : a
   V_COUNT
 };
 

@@ -159,8 +159,10 @@ static double divb_limit(double dx, double dy, double dz) {
   const double s = h * h * (1.0 / (dx * dx) + 1.0 / (dy * dy) + 1.0 / (dz * dz));
   return rk3_real_limit() / (kh * kh * s);
 }
-// Stage workspace arrays: 34, and 6 more for the quenched stress.
+// Stage workspace arrays: 34, 6 more for the quenched stress, and 2 more
+// for the second-order switch.
 static int work_arrays(const mhd_params& p) {
+  if (p.terms & MHD_T_ORDER2) return WS_COUNT_ALL;
   return (p.terms & MHD_T_QUENCH) ? WS_COUNT_QUENCH : WS_COUNT;
 }
 
@@ -200,6 +202,7 @@ template <class T> static Phys<T> make_phys(const mhd_params& p) {
   const bool quench = p.terms & MHD_T_QUENCH;
   ph.q_max = quench ? T(p.q_max) : T(1);
   ph.q_lim = quench ? T(p.q_lim) : T(0);
+  ph.d2_lim = (p.terms & MHD_T_ORDER2) ? T(p.d2_lim) : T(0);
   ph.terms = p.terms;
   return ph;
 }
@@ -470,7 +473,7 @@ int mhd_init(const mhd_params* p, void* hip_stream, mhd_ctx** out) {
     if (!(v >= 0.0) || !std::isfinite(v)) return fail(nullptr, MHD_EINVAL, "viscosity, diffusion and Courant coefficients must be finite and >= 0");
   if (!std::isfinite(p->gz) || !std::isfinite(p->c1)) return fail(nullptr, MHD_EINVAL, "gz and c1 must be finite");
   if (p->terms & ~(MHD_T_ALL | MHD_T_COOL | MHD_T_CORI | MHD_T_EDIFFAV | MHD_T_LNP | MHD_T_DIVB |
-                   MHD_T_SMAG | MHD_T_MAX5 | MHD_T_QUENCH))
+                   MHD_T_SMAG | MHD_T_MAX5 | MHD_T_QUENCH | MHD_T_ORDER2))
     return fail(nullptr, MHD_EINVAL, "unknown term bits");
   if ((p->terms & MHD_T_DIVB) && !(p->c_divb >= 0.0 && std::isfinite(p->c_divb)))
     return fail(nullptr, MHD_EINVAL, "c_divb must be finite and >= 0");
@@ -479,6 +482,8 @@ int mhd_init(const mhd_params* p, void* hip_stream, mhd_ctx** out) {
   if ((p->terms & MHD_T_QUENCH) && !(p->q_max > 0.0 && std::isfinite(p->q_max) && p->q_lim > 0.0 &&
                                      std::isfinite(p->q_lim)))
     return fail(nullptr, MHD_EINVAL, "q_max and q_lim must be finite and > 0");
+  if ((p->terms & MHD_T_ORDER2) && !std::isfinite(p->d2_lim))
+    return fail(nullptr, MHD_EINVAL, "d2_lim must be finite");
   if ((p->terms & MHD_T_CORI) &&
       !(std::isfinite(p->omega[0]) && std::isfinite(p->omega[1]) && std::isfinite(p->omega[2])))
     return fail(nullptr, MHD_EINVAL, "the rotation vector must be finite");

@@ -21,7 +21,7 @@ enum : unsigned {
   T_LORENTZ = 1u << 4, T_INDUCT = 1u << 5, T_RESIST = 1u << 6,
   T_EDIFF = 1u << 7, T_GRAV = 1u << 8, T_COOL = 1u << 9, T_CORI = 1u << 10,
   T_EDIFFAV = 1u << 11, T_LNP = 1u << 12, T_DIVB = 1u << 13, T_SMAG = 1u << 14,
-  T_MAX5 = 1u << 15, T_QUENCH = 1u << 16
+  T_MAX5 = 1u << 15, T_QUENCH = 1u << 16, T_ORDER2 = 1u << 17
 };
 
 constexpr int kBlock = 256;          // threads per workgroup of the cell kernels

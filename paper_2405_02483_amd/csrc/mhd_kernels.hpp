@@ -15,6 +15,7 @@ template <class T> struct Phys {
   T c_divb;                             // div B diffusion coefficient (with T_DIVB)
   T c_smag;                             // Smagorinsky constant (with T_SMAG)
   T q_max, q_lim;                       // quenching (with T_QUENCH)
+  T d2_lim;                             // roughness limit (with T_ORDER2)
   unsigned terms;
 };
 

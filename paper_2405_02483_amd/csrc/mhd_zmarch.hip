@@ -619,12 +619,26 @@ __global__ __launch_bounds__(TX * TY) void zQ(const BoxDev* __restrict__ boxes,
       const T* BZ = sBZ[sq];
       const T* PZ = sPZ[sq];
       const long long o = col(q);
+      // second-order switch: the strain of the x- and y-edges (the end face
+      // of a wall axis copies its neighbour's z derivative)
+      const unsigned fl = (kE && ws.rgh) ? (unsigned)ws.rgh[o] : 0u;
+      auto dz2 = [&](const T (&w)[6]) {
+        return (wall && q == 0) ? (w[4] - w[3]) * g.hzi : (w[3] - w[2]) * g.hzi;
+      };
+      auto s_xz = [&](T dzUX, T dxUZ) {
+        if (fl & RG_YE) return T(0.5) * (dz2(wUX) + (UZ[P3::at(tx, ty)] - UZ[P3::at(tx - 1, ty)]) * g.hxi);
+        return T(0.5) * (dzUX + dxUZ);
+      };
+      auto s_yz = [&](T dzUY, T dyUZ) {
+        if (fl & RG_XE) return T(0.5) * (dz2(wUY) + (UZ[P3::at(tx, ty)] - UZ[P3::at(tx, ty - 1)]) * g.hyi);
+        return T(0.5) * (dzUY + dyUZ);
+      };
       // ---- raw stress only (quenching)
       if constexpr (kE && kT) {
         const T dxUZ = op6<1, 0, T>([&](int m) { return UZ[P3::at(tx + m, ty)]; }, g.hxi);
         const T dyUZ = op6<1, 0, T>([&](int m) { return UZ[P3::at(tx, ty + m)]; }, g.hyi);
-        const T sxz = T(0.5) * (zwin<1, 0, 6, 3>(wUX, q, wall, N, g.hzi, zt) + dxUZ);
-        const T syz = T(0.5) * (zwin<1, 0, 6, 3>(wUY, q, wall, N, g.hzi, zt) + dyUZ);
+        const T sxz = s_xz(zwin<1, 0, 6, 3>(wUX, q, wall, N, g.hzi, zt), dxUZ);
+        const T syz = s_yz(zwin<1, 0, 6, 3>(wUY, q, wall, N, g.hzi, zt), dyUZ);
         if (own) {
           ws.q(TAU_XZ)[o] = zwin<0, 0, 6, 3>(wRX, q, wall, N, T(0), zt) *
                             (g.lxz * exp(zwin<0, 0, 6, 3>(wLX, q, wall, N, T(0), zt))) * sxz;
@@ -648,7 +662,7 @@ __global__ __launch_bounds__(TX * TY) void zQ(const BoxDev* __restrict__ boxes,
         T nxz = T(0), txz = T(0), sxz = T(0);
         if (need_nu) nxz = g.lxz * exp(zwin<0, 0, 6, 3>(wLX, q, wall, N, T(0), zt));
         if (visc) {
-          sxz = T(0.5) * (dzUX + dxUZ);
+          sxz = s_xz(dzUX, dxUZ);
           txz = tq ? tq[TAU_XZ * ws.stride + o] : zRX * nxz * sxz;
         }
         const T jy = dzBX - dxBZ;
@@ -688,7 +702,7 @@ __global__ __launch_bounds__(TX * TY) void zQ(const BoxDev* __restrict__ boxes,
         T nyz = T(0), tyz = T(0), syz = T(0);
         if (need_nu) nyz = g.lyz * exp(zwin<0, 0, 6, 3>(wLY, q, wall, N, T(0), zt));
         if (visc) {
-          syz = T(0.5) * (dzUY + dyUZ);
+          syz = s_yz(dzUY, dyUZ);
           tyz = tq ? tq[TAU_YZ * ws.stride + o] : zRY * nyz * syz;
         }
         const T jx = dyBZ - dzBY;
@@ -743,14 +757,18 @@ __global__ __launch_bounds__(TX * TY) void zQ(const BoxDev* __restrict__ boxes,
     const int q2 = r - 3;
     if (kZ && valid(q2) && q2 >= it.z0 && q2 < it.z1) {
       const long long o = col(q2);
-      const T szz = zwin<1, 1, 6, 2>(wUZ, q2, wall, N, g.hzi, zt);
+      // second-order switch at the centre: S_zz and the stress's div u
+      const bool o2 = ws.rgh && ((unsigned)ws.rgh[o] & RG_C);
+      const T szz = !o2 ? zwin<1, 1, 6, 2>(wUZ, q2, wall, N, g.hzi, zt)
+                        : ((wall && q2 == N - 1) ? (wUZ[2] - wUZ[1]) * g.hzi : (wUZ[3] - wUZ[2]) * g.hzi);
+      const T Dt = o2 ? ws.arr(WS_D2)[o] : Dg[o];
       if constexpr (kT) {
-        if (own) ws.q(TAU_ZZ)[o] = wRho[2] * (g.lz * wNu[2]) * (szz + ph.c1 * Dg[o]);
+        if (own) ws.q(TAU_ZZ)[o] = wRho[2] * (g.lz * wNu[2]) * (szz + ph.c1 * Dt);
         continue;
       }
       T gzz = T(0), czz = T(0);
       if (visc) {
-        const T tzz = tq ? tq[TAU_ZZ * ws.stride + o] : wRho[2] * (g.lz * wNu[2]) * (szz + ph.c1 * Dg[o]);
+        const T tzz = tq ? tq[TAU_ZZ * ws.stride + o] : wRho[2] * (g.lz * wNu[2]) * (szz + ph.c1 * Dt);
         gzz = tzz;
         czz = tzz * szz;
       }
@@ -779,6 +797,7 @@ __global__ __launch_bounds__(TX * TY) void zP(const BoxDev* __restrict__ boxes,
                                               CP8<T> f, Phys<T> ph, ZWork<T> ws) {
   const T* __restrict__ lntg = ws.arr(WS_LNT);
   const T* __restrict__ Dg = ws.arr(WS_D);
+  const T* __restrict__ uzg = ws.arr(WS_UZ);
   const T* __restrict__ lnpav = ws.lnpav;
   using P6 = Plane<TX, TY, 6>;
   using P3 = Plane<TX, TY, 3>;
@@ -836,18 +855,32 @@ __global__ __launch_bounds__(TX * TY) void zP(const BoxDev* __restrict__ boxes,
       if (q == DQ_LQ) return log(ph.gamma1 * S(DQ_E, xx, yy)) - lpa;
       return S(q, xx, yy);
     };
+    // second-order switch: this cell's flags and its second-order div u
+    // (also for pass Q's tau_zz; the end plane of a wall axis copies its
+    // neighbour's z derivative)
+    unsigned fl = 0;
+    T D2 = T(0);
+    if (ws.rgh) {
+      fl = (unsigned)ws.rgh[o];
+      const int kp = (wall && k == N - 1) ? k - 1 : k;
+      D2 = (S(DQ_UX, x + 1, y) - S(DQ_UX, x, y)) * g.hxi + (S(DQ_UY, x, y + 1) - S(DQ_UY, x, y)) * g.hyi +
+           (uzg[col(kp + 1)] - uzg[col(kp)]) * g.hzi;
+      ws.arr(WS_D2)[o] = D2;
+    }
     if constexpr (TAU) {
       T sxx, syy, txx, tyy;
-      centre_tau<T>(SA, x, y, g, ph, sxx, syy, txx, tyy);
-      ws.q(TAU_XY)[o] = zedge_tau<T>(SA, x, y, g);
+      centre_tau<T>(SA, x, y, g, ph, sxx, syy, txx, tyy, fl & RG_C, D2);
+      ws.q(TAU_XY)[o] = zedge_tau<T>(SA, x, y, g, fl & RG_ZE);
       ws.q(TAU_XX)[o] = txx;
       ws.q(TAU_YY)[o] = tyy;
       continue;
     }
     T gxy, gyx, ez, lxz, lyz, qz, gxx, gyy, qc, dpx, dpy;
     const T* tq = ws.tq;
-    zedge_q<T>(SA, x, y, g, ph, gxy, gyx, ez, lxz, lyz, qz, tq ? tq + TAU_XY * ws.stride + o : nullptr);
-    centre_q<T>(SA, x, y, g, ph, gxx, gyy, qc, tq ? tq + TAU_XX * ws.stride + o : nullptr, ws.stride);
+    zedge_q<T>(SA, x, y, g, ph, gxy, gyx, ez, lxz, lyz, qz, tq ? tq + TAU_XY * ws.stride + o : nullptr,
+               fl & RG_ZE);
+    centre_q<T>(SA, x, y, g, ph, gxx, gyy, qc, tq ? tq + TAU_XX * ws.stride + o : nullptr, ws.stride,
+                fl & RG_C, D2);
     face_dp<T>(SA, x, y, g, ph, (tm & T_LNP) ? T(exp(lpa)) : T(0), dpx, dpy);
     ws.pq(POUT_GXY)[o] = gxy;
     ws.pq(POUT_GYX)[o] = gyx;
@@ -862,6 +895,86 @@ __global__ __launch_bounds__(TX * TY) void zP(const BoxDev* __restrict__ boxes,
     ws.pq(POUT_DPY)[o] = dpy;
     ws.pq(POUT_HX)[o] = xface_h<T>(SA, x, y, g, ph);
     ws.pq(POUT_HY)[o] = yface_h<T>(SA, x, y, g, ph);
+  }
+  ZLOOP_END
+}
+
+// ---------------------------------------------------------------------------
+// Second-order switch (Section 3 after eq. itv): the flags (RG_*) of every
+// cell into workspace array WS_RGH.  A cell is rough where some axis's
+// absolute second difference of ln rho or ln e_m exceeds d2_lim (none across
+// the ends of a wall-bounded axis).  ln rho and ln e_m of planes r-2, r-1, r
+// sit in an LDS ring (halo 2); the roughness of plane r-1 on the tile and a
+// one-cell rim goes to an LDS ring of two planes (an absent plane is
+// smooth); the flags of plane r-1 collect the cells touching each position.
+template <class T, int TX, int TY, bool PERS>
+__global__ __launch_bounds__(TX * TY) void zRough(const BoxDev* __restrict__ boxes,
+                                                  const ZItem* __restrict__ items, int nitems,
+                                                  const T* __restrict__ ztab, int* __restrict__ queue,
+                                                  CP8<T> f, Phys<T> ph, ZWork<T> ws) {
+  using P2 = Plane<TX, TY, 2>;
+  using P1 = Plane<TX, TY, 1>;
+  using I2 = PlaneIdx<TX, TY, 2>;
+  constexpr int NT = TX * TY;
+  __shared__ T sLR[3][P2::NP], sLE[3][P2::NP];
+  __shared__ unsigned char sG[2][P1::NP];
+  T* __restrict__ out = ws.arr(WS_RGH);
+  ZLOOP_BEGIN
+  I2 i2;
+  i2.init(b, it.x0, it.y0);
+  for (int r = it.z0 - 2; r <= it.z1; ++r) {
+    __syncthreads();
+    if (valid(r)) {
+      const int sl = wrapm(r, 3);
+      const T* __restrict__ pr = f.p[0] + b.off + (long long)kk(r) * pstride;
+      const T* __restrict__ pe = f.p[4] + b.off + (long long)kk(r) * pstride;
+#pragma unroll
+      for (int i = 0; i < I2::NPER; ++i) {
+        const int t = (int)threadIdx.x + i * NT;
+        const T rv = pr[i2.off[i]], ev = pe[i2.off[i]];
+        sLR[sl][t] = log(rv);
+        sLE[sl][t] = log(ev / rv);
+      }
+    }
+    __syncthreads();
+    const int p = r - 1;
+    if (r < it.z0) continue;
+    unsigned char* G = sG[wrapm(p, 2)];
+    if (valid(p)) {
+      const int s0 = wrapm(p, 3), sm = wrapm(p - 1, 3), sp = wrapm(p + 1, 3);
+      const bool zok = valid(p - 1) && valid(p + 1);
+      for (int t = threadIdx.x; t < P1::N; t += NT) {
+        const int yy = t / P1::W, xx = t - yy * P1::W;
+        const int x = xx - 1, y = yy - 1;
+        T m = T(0);
+        for (int v = 0; v < 2; ++v) {
+          const T* A = v ? sLE[s0] : sLR[s0];
+          const T c = A[P2::at(x, y)];
+          m = fmax(m, fabs(A[P2::at(x + 1, y)] - T(2) * c + A[P2::at(x - 1, y)]));
+          m = fmax(m, fabs(A[P2::at(x, y + 1)] - T(2) * c + A[P2::at(x, y - 1)]));
+          if (zok) {
+            const T* Am = v ? sLE[sm] : sLR[sm];
+            const T* Ap = v ? sLE[sp] : sLR[sp];
+            m = fmax(m, fabs(Ap[P2::at(x, y)] - T(2) * c + Am[P2::at(x, y)]));
+          }
+        }
+        G[t] = m > ph.d2_lim ? 1 : 0;
+      }
+    } else {
+      for (int t = threadIdx.x; t < P1::NP; t += NT) G[t] = 0;
+    }
+    __syncthreads();
+    if (own && p >= it.z0 && p < it.z1 && valid(p)) {
+      const unsigned char* G1 = sG[wrapm(p - 1, 2)];
+      auto g0 = [&](int dx, int dy) { return G[P1::at(tx + dx, ty + dy)] != 0; };
+      auto g1 = [&](int dx, int dy) { return G1[P1::at(tx + dx, ty + dy)] != 0; };
+      unsigned fl = 0;
+      if (g0(0, 0)) fl |= RG_C;
+      if (g0(0, 0) || g0(0, -1) || g1(0, 0) || g1(0, -1)) fl |= RG_XE;
+      if (g0(0, 0) || g0(-1, 0) || g1(0, 0) || g1(-1, 0)) fl |= RG_YE;
+      if (g0(0, 0) || g0(-1, 0) || g0(0, -1) || g0(-1, -1)) fl |= RG_ZE;
+      out[col(p)] = T(fl);
+    }
   }
   ZLOOP_END
 }
@@ -1208,21 +1321,37 @@ static void launch_zstage_m(const ZLaunch& L, const ZStageArgs<T>& a) {
                        L.nbox, L.nplanes, a.lnpart, (double)a.ph.gamma1, a.w.lnpav);
   }
   L.at(PASS_EDGES);
-  // quenching: the raw stress (stress-only launches of Q and P), then its
-  // quenched version, which Q and P below take in place of their own
+  // the optional passes run in grid mode (their own launches, no queue)
+  const dim3 gq(8 * ((n + 7) / 8));
+  // second-order switch: the flags of every cell; pass P then writes the
+  // second-order div u that pass Q's tau_zz takes, so P goes first
   ZWork<T> wq = a.w;
-  if ((a.ph.terms & T_QUENCH) && (a.ph.terms & T_VISC)) {
-    const dim3 gq(8 * ((n + 7) / 8));
-    hipLaunchKernelGGL((zQ<T, TX, TY, false, QM_EDGES | QM_TAU>), gq, block, 0, L.stream, L.boxes, L.items, n,
-                       a.ztab, (int*)nullptr, a.f, a.ph, a.w, a.lnavg, a.w.lnpav);
-    hipLaunchKernelGGL((zQ<T, TX, TY, false, QM_ZC | QM_TAU>), gq, block, 0, L.stream, L.boxes, L.items, n,
-                       a.ztab, (int*)nullptr, a.f, a.ph, a.w, a.lnavg, a.w.lnpav);
-    hipLaunchKernelGGL((zP<T, TX, TY, false, true>), gq, block, 0, L.stream, L.boxes, L.items, n, a.ztab,
+  const bool o2 = (a.ph.terms & T_ORDER2) && (a.ph.terms & T_VISC);
+  if (o2) {
+    hipLaunchKernelGGL((zRough<T, TX, TY, false>), gq, block, 0, L.stream, L.boxes, L.items, n, a.ztab,
                        (int*)nullptr, a.f, a.ph, a.w);
+    wq.rgh = a.w.arr(WS_RGH);
+  }
+  // quenching: the raw stress (stress-only launches of P and Q), then its
+  // quenched version, which P and Q below take in place of their own
+  if ((a.ph.terms & T_QUENCH) && (a.ph.terms & T_VISC)) {
+    hipLaunchKernelGGL((zP<T, TX, TY, false, true>), gq, block, 0, L.stream, L.boxes, L.items, n, a.ztab,
+                       (int*)nullptr, a.f, a.ph, wq);
+    hipLaunchKernelGGL((zQ<T, TX, TY, false, QM_EDGES | QM_TAU>), gq, block, 0, L.stream, L.boxes, L.items, n,
+                       a.ztab, (int*)nullptr, a.f, a.ph, wq, a.lnavg, a.w.lnpav);
+    hipLaunchKernelGGL((zQ<T, TX, TY, false, QM_ZC | QM_TAU>), gq, block, 0, L.stream, L.boxes, L.items, n,
+                       a.ztab, (int*)nullptr, a.f, a.ph, wq, a.lnavg, a.w.lnpav);
     hipLaunchKernelGGL((zQn<T, TX, TY>), dim3(gq.x, TAU_COUNT), block, 0, L.stream, L.boxes, L.items, n, a.ztab,
                        a.ph, a.w);
     wq.tq = a.w.arr(WS_TQ0);
   }
+  auto launch_p = [&]() {
+    L.at(PASS_CF);
+    hipLaunchKernelGGL((zP<T, TX, TY, PERS>), grid((const void*)zP<T, TX, TY, PERS>), block, 0, L.stream,
+                       L.boxes, L.items, n, a.ztab, q ? q + 24 : q, a.f, a.ph, wq);
+  };
+  if (o2) launch_p();
+  L.at(PASS_EDGES);
   hipLaunchKernelGGL((zQ<T, TX, TY, PERS, QM_EDGES>), grid((const void*)zQ<T, TX, TY, PERS, QM_EDGES>), block, 0,
                      L.stream, L.boxes, L.items, n, a.ztab, q ? q + 16 : q, a.f, a.ph, wq, a.lnavg,
                      a.w.lnpav);
@@ -1234,9 +1363,7 @@ static void launch_zstage_m(const ZLaunch& L, const ZStageArgs<T>& a) {
     hipLaunchKernelGGL((zQ<T, TX, TY, PERS, QM_ZC>), grid((const void*)zQ<T, TX, TY, PERS, QM_ZC>), block, 0,
                        L.stream, L.boxes, L.items, n, a.ztab, q ? q + 32 + 8 * kNFMasks : q, a.f, a.ph, wq,
                        a.lnavg, a.w.lnpav);
-  L.at(PASS_CF);
-  hipLaunchKernelGGL((zP<T, TX, TY, PERS>), grid((const void*)zP<T, TX, TY, PERS>), block, 0, L.stream, L.boxes,
-                     L.items, n, a.ztab, q ? q + 24 : q, a.f, a.ph, wq);
+  if (!o2) launch_p();
   L.at(PASS_FINAL);
   launch_final<T, PERS>(L, a, q);
   L.at(PASS_END);

@@ -41,10 +41,12 @@ inline int ztile_y(int t) { return t == ZTILE_64x4 ? 4 : ((t == ZTILE_16x16 || t
 // kernel needs one base pointer for all of them (array pointers held in
 // scalar registers would otherwise spill).
 // With T_QUENCH six more follow: the quenched stress components, in the
-// order of TauC.
+// order of TauC; with T_ORDER2 also those and two more: the per-cell flags
+// of the second-order switch (RG_*) and the second-order div u.
 enum WsArr : int { WS_NUS = 0, WS_D, WS_UZ, WS_LNT, WS_Q0, WS_P0 = WS_Q0 + QOUT_COUNT,
                    WS_DIVB = WS_P0 + POUT_COUNT, WS_COUNT, WS_TQ0 = WS_COUNT,
-                   WS_COUNT_QUENCH = WS_TQ0 + 6 };
+                   WS_COUNT_QUENCH = WS_TQ0 + 6, WS_RGH = WS_COUNT_QUENCH, WS_D2,
+                   WS_COUNT_ALL };
 
 // Viscous stress components (eq. itv) and where they live: tau_xz on the
 // y-edge, tau_yz on the x-edge, tau_zz, tau_xx, tau_yy at the centre, tau_xy
@@ -60,6 +62,8 @@ template <class T> struct ZWork {
   // quenched stress (component c at tq + c * stride), or null: the passes
   // then form the stress themselves
   const T* tq = nullptr;
+  // the second-order switch's flags, or null: sixth-order strain everywhere
+  const T* rgh = nullptr;
   __host__ __device__ T* arr(int a) const { return base + (long long)a * stride; }
   __host__ __device__ T* q(int i) const { return arr(WS_Q0 + i); }
   __host__ __device__ T* pq(int i) const { return arr(WS_P0 + i); }

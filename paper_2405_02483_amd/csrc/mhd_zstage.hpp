@@ -84,26 +84,35 @@ __device__ __forceinline__ T zedge_nu(const A& S, int x, int y, const Geo<T>& g)
 template <class T, class A> __device__ __forceinline__ T zedge_rho(const A& S, int x, int y) {
   return op6<0, 0, T>([&](int m) { return S(DQ_RXD, x, y + m); }, T(0));
 }
+// o2: from the second-order derivatives (the switch after eq. itv)
 template <class T, class A>
-__device__ __forceinline__ T zedge_strain(const A& S, int x, int y, const Geo<T>& g) {
+__device__ __forceinline__ T zedge_strain(const A& S, int x, int y, const Geo<T>& g, bool o2 = false) {
+  if (o2)
+    return T(0.5) * ((S(DQ_UX, x, y) - S(DQ_UX, x, y - 1)) * g.hyi +
+                     (S(DQ_UY, x, y) - S(DQ_UY, x - 1, y)) * g.hxi);
   return T(0.5) * (op6<1, 0, T>([&](int m) { return S(DQ_UX, x, y + m); }, g.hyi) +
                    op6<1, 0, T>([&](int m) { return S(DQ_UY, x + m, y); }, g.hxi));
 }
 // the viscous stress tau_xy = rho nu_xy S_xy on the z-edge
 template <class T, class A>
-__device__ __forceinline__ T zedge_tau(const A& S, int x, int y, const Geo<T>& g) {
-  return zedge_rho<T>(S, x, y) * zedge_nu<T>(S, x, y, g) * zedge_strain<T>(S, x, y, g);
+__device__ __forceinline__ T zedge_tau(const A& S, int x, int y, const Geo<T>& g, bool o2 = false) {
+  return zedge_rho<T>(S, x, y) * zedge_nu<T>(S, x, y, g) * zedge_strain<T>(S, x, y, g, o2);
 }
 
+// Second-order switch (Section 3 after eq. itv): per-cell flags of the
+// positions whose strain takes the second-order derivatives (bit 0 the
+// centre, 1 the x-edge, 2 the y-edge, 3 the z-edge of the cell's index).
+enum : unsigned { RG_C = 1u, RG_XE = 2u, RG_YE = 4u, RG_ZE = 8u };
+
 // z-directed edge: strain and stress (eq. itv; tq: the quenched stress, or
-// null), E_z (eq. ohm), the momentum fluxes G_xy = tau_xy - ydn(p_x)
+// null; o2: second-order strain), E_z (eq. ohm), the momentum fluxes G_xy = tau_xy - ydn(p_x)
 // xdn(u_y) and G_yx = tau_xy - xdn(p_y) ydn(u_x), the Lorentz products L_xz =
 // J_z xdn(B_y), L_yz = J_z ydn(B_x), and the heating 2 tau_xy S_xy +
 // eta J_z^2 / mu (eq. vdiss, Joule).
 template <class T, class A>
 __device__ __forceinline__ void zedge_q(const A& S, int x, int y, const Geo<T>& g, const Phys<T>& ph,
                                         T& gxy, T& gyx, T& ez, T& lxz, T& lyz, T& qz,
-                                        const T* tq = nullptr) {
+                                        const T* tq = nullptr, bool o2 = false) {
   const unsigned tm = ph.terms;
   const bool visc = tm & T_VISC, res = tm & T_RESIST, ind = tm & T_INDUCT, lor = tm & T_LORENTZ,
              adv = tm & T_ADV;
@@ -111,7 +120,7 @@ __device__ __forceinline__ void zedge_q(const A& S, int x, int y, const Geo<T>& 
   T nxy = T(0), txy = T(0), sxy = T(0);
   if (need_nu) nxy = zedge_nu<T>(S, x, y, g);
   if (visc) {
-    sxy = zedge_strain<T>(S, x, y, g);
+    sxy = zedge_strain<T>(S, x, y, g, o2);
     txy = tq ? *tq : zedge_rho<T>(S, x, y) * nxy * sxy;
   }
   const T jz = op6<1, 0, T>([&](int m) { return S(DQ_BY, x + m, y); }, g.hxi) -
@@ -140,13 +149,20 @@ __device__ __forceinline__ void zedge_q(const A& S, int x, int y, const Geo<T>& 
 }
 
 // Cell centre (x, y): the strain S_xx, S_yy and the viscous stress tau_xx =
-// rho nu_xx (S_xx + c1 div u), tau_yy (eq. itv, eq. nuij).
+// rho nu_xx (S_xx + c1 div u), tau_yy (eq. itv, eq. nuij); with o2 from the
+// second-order derivatives and D2, the second-order div u.
 template <class T, class A>
 __device__ __forceinline__ void centre_tau(const A& S, int x, int y, const Geo<T>& g, const Phys<T>& ph,
-                                           T& sxx, T& syy, T& txx, T& tyy) {
-  sxx = op6<1, 1, T>([&](int m) { return S(DQ_UX, x + m, y); }, g.hxi);
-  syy = op6<1, 1, T>([&](int m) { return S(DQ_UY, x, y + m); }, g.hyi);
-  const T Dc = S(DQ_D, x, y);
+                                           T& sxx, T& syy, T& txx, T& tyy, bool o2 = false,
+                                           T D2 = T(0)) {
+  if (o2) {
+    sxx = (S(DQ_UX, x + 1, y) - S(DQ_UX, x, y)) * g.hxi;
+    syy = (S(DQ_UY, x, y + 1) - S(DQ_UY, x, y)) * g.hyi;
+  } else {
+    sxx = op6<1, 1, T>([&](int m) { return S(DQ_UX, x + m, y); }, g.hxi);
+    syy = op6<1, 1, T>([&](int m) { return S(DQ_UY, x, y + m); }, g.hyi);
+  }
+  const T Dc = o2 ? D2 : S(DQ_D, x, y);
   const T rn = S(DQ_RHO, x, y) * S(DQ_NU, x, y);
   txx = rn * g.lx * (sxx + ph.c1 * Dc);
   tyy = rn * g.ly * (syy + ph.c1 * Dc);
@@ -158,11 +174,11 @@ __device__ __forceinline__ void centre_tau(const A& S, int x, int y, const Geo<T
 template <class T, class A>
 __device__ __forceinline__ void centre_q(const A& S, int x, int y, const Geo<T>& g, const Phys<T>& ph,
                                          T& gxx, T& gyy, T& qc, const T* tq = nullptr,
-                                         long long stride = 0) {
+                                         long long stride = 0, bool o2 = false, T D2 = T(0)) {
   const unsigned tm = ph.terms;
   const bool visc = tm & T_VISC, adv = tm & T_ADV, pres = tm & T_PRES;
   T sxx, syy, txx, tyy;
-  centre_tau<T>(S, x, y, g, ph, sxx, syy, txx, tyy);
+  centre_tau<T>(S, x, y, g, ph, sxx, syy, txx, tyy, o2, D2);
   const T Dc = S(DQ_D, x, y);
   const T Pc = ph.gamma1 * S(DQ_E, x, y);
   T a = T(0), c = T(0), q = T(0);

@@ -16,7 +16,7 @@ __all__ = [
     "MHD_ENONFINITE", "MHD_EUNSUPPORTED", "MHD_F32", "MHD_F64",
     "MHD_BC_PERIODIC", "MHD_BC_WALL", "T_CONT", "T_ADV", "T_PRES", "T_VISC",
     "T_LORENTZ", "T_INDUCT", "T_RESIST", "T_EDIFF", "T_GRAV", "T_ALL", "T_COOL", "T_CORI",
-    "T_EDIFFAV", "T_LNP", "T_DIVB", "T_SMAG", "T_MAX5", "T_QUENCH",
+    "T_EDIFFAV", "T_LNP", "T_DIVB", "T_SMAG", "T_MAX5", "T_QUENCH", "T_ORDER2",
     "MhdBox", "MhdParams", "MhdStats", "MhdError", "lib_path", "load",
     "mhd_init", "mhd_destroy", "mhd_last_error", "mhd_field_elems",
     "mhd_box_offset", "mhd_rhs", "mhd_rhs_noalloc", "mhd_step", "mhd_step_adjoint",
@@ -41,6 +41,7 @@ T_DIVB = 1 << 13     # div B diffusion (needs the step's dt); not part of T_ALL
 T_SMAG = 1 << 14     # Smagorinsky viscosity added to the speed-like one; not part of T_ALL
 T_MAX5 = 1 << 15     # viscosity spread by the maximum over five cells; not part of T_ALL
 T_QUENCH = 1 << 16   # quenching of the viscous stress (eq. quench); not part of T_ALL
+T_ORDER2 = 1 << 17   # second-order strain where the state is rough; not part of T_ALL
 
 
 class MhdBox(ctypes.Structure):
@@ -62,7 +63,8 @@ class MhdParams(ctypes.Structure):
                 ("rho_cool", ctypes.c_double), ("cool_cut", ctypes.c_int32),
                 ("reserved2", ctypes.c_int32), ("omega", ctypes.c_double * 3),
                 ("c_divb", ctypes.c_double), ("c_smag", ctypes.c_double),
-                ("q_max", ctypes.c_double), ("q_lim", ctypes.c_double)]
+                ("q_max", ctypes.c_double), ("q_lim", ctypes.c_double),
+                ("d2_lim", ctypes.c_double)]
 
 
 class MhdStats(ctypes.Structure):
@@ -307,7 +309,8 @@ class Context:
     t_cool, rho_cool, cool_cut for Newtonian cooling with T_COOL, omega
     (3 values) for the Coriolis force with T_CORI, c_divb for the div B
     diffusion with T_DIVB, c_smag for the Smagorinsky viscosity with
-    T_SMAG, q_max and q_lim for the quenching with T_QUENCH)."""
+    T_SMAG, q_max and q_lim for the quenching with T_QUENCH, d2_lim for the
+    second-order switch with T_ORDER2)."""
 
     def __init__(self, boxes, params, dtype=torch.float32, terms=T_ALL, stream=None,
                  device="cuda"):
@@ -349,6 +352,7 @@ class Context:
         p.c_smag = float(params.get("c_smag", 0.0))
         p.q_max = float(params.get("q_max", 8.0))
         p.q_lim = float(params.get("q_lim", 2.0))
+        p.d2_lim = float(params.get("d2_lim", 0.3))
         self.params = p
         self.ctx = mhd_init(p, stream)
         self.n = mhd_field_elems(self.ctx)

@@ -38,11 +38,12 @@ def _params(**over):
     (dict(mu=0.0), lib.MHD_EINVAL),
     (dict(nu1=-0.1), lib.MHD_EINVAL),
     (dict(Cdt=float("nan")), lib.MHD_EINVAL),
-    (dict(terms=1 << 16), lib.MHD_EINVAL),
+    (dict(terms=1 << 18), lib.MHD_EINVAL),
     (dict(terms=lib.T_ALL | lib.T_SMAG, c_smag=-0.1), lib.MHD_EINVAL),
     (dict(terms=lib.T_ALL | lib.T_SMAG, c_smag=float("nan")), lib.MHD_EINVAL),
     (dict(terms=lib.T_ALL | lib.T_QUENCH, q_max=0.0, q_lim=2.0), lib.MHD_EINVAL),
     (dict(terms=lib.T_ALL | lib.T_QUENCH, q_max=8.0, q_lim=float("inf")), lib.MHD_EINVAL),
+    (dict(terms=lib.T_ALL | lib.T_ORDER2, d2_lim=float("nan")), lib.MHD_EINVAL),
     (dict(terms=lib.T_ALL | lib.T_DIVB, c_divb=-0.1), lib.MHD_EINVAL),
     # above the RK3 real-axis limit of the div B diffusion on cubic cells
     (dict(terms=lib.T_ALL | lib.T_DIVB, c_divb=0.1359), lib.MHD_EINVAL),
