@@ -13,13 +13,19 @@ Prints ONE JSON line:  metric, value (interior cell-updates/s per RK step),
 ms_per_step, the float64 figures of the same workload, the roofline of the
 RK stage (algorithmic bytes per stage / measured stage time, HIP events on
 the library's stream; beside the 8 TB/s peak, the bandwidth of a plain 1 GiB
-device copy measured in the same run), the same float32 workload with
-each optional term on (Newtonian cooling, the Coriolis force, energy
-diffusion about the horizontal mean, the ln(P/P_aver) pressure gradient, div
-B diffusion), and the CPU oracle timed on a bounded sample.
+device copy measured in the same run, the HBM bytes the counters measured
+and the vector-issue ceiling of the counted VALU instructions), the same
+float32 workload with each optional term on (Newtonian cooling, the Coriolis
+force, energy diffusion about the horizontal mean, the ln(P/P_aver) pressure
+gradient, div B diffusion, the Smagorinsky viscosity with the five-cell
+maximum, quenching, the second-order switch), the adjoint and ensemble legs,
+and the CPU oracle timed on a bounded sample: one RK step of a full-height
+column window of the same state, whose central columns the float32 step of
+the whole box is compared with, field by field.
 
     python bench.py [--steps K] [--warmup W] [--size N] [--no-fp64]
                     [--no-cpu-baseline] [--no-adjoint] [--no-sources] [--tile TXxTY]
+    python bench.py --adjoint-only  (the adjoint leg alone, for profiling)
     python bench.py --cpu-table     (the CPU oracle alone, 32^3..256^3)
 """
 import argparse
@@ -34,6 +40,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+# Vector issue rate: 256 CUs x 4 SIMDs, a wave64 VALU instruction every 4
+# cycles per SIMD (16 lanes; no packed math) at 2.4 GHz = 3.93e13
+# lane-instructions/s (the 78.6 TFLOP/s of unpacked float32 FMAs).
+VALU_LANE_RATE = 256 * 4 * 16 * 2.4e9
+# The float32 step's check against the oracle: one full-height window of
+# the state, periodic in x and y, WIN_MARGIN columns each side of a central
+# WIN_CORE x WIN_CORE block (one RK step reaches at most 3 x 14 cells).
+WIN_MARGIN, WIN_CORE = 44, 16
 # Algorithmic HBM words per interior cell per RK stage (8 fields, 2N storage,
 # stage input and output in different buffers): stage 1 reads f, writes dU
 # and f; stage 2 reads f and dU, writes dU and f; stage 3 reads f and dU,
@@ -71,10 +85,10 @@ def kernel_source_hash(root=ROOT):
     return h.hexdigest()[:16]
 
 
-def measured_traffic(dtype_name):
-    """HBM bytes per RK stage from the committed rocprofv3 counter summary,
-    if it was taken from the current kernel sources; else None."""
-    path = os.path.join(ROOT, "profiles", "traffic_rk_stage_stratified512.json")
+def _profile_record(name):
+    """A committed rocprofv3 counter summary (profiles/<name>.json), if it
+    was taken from the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", name + ".json")
     if not os.path.exists(path):
         return None
     try:
@@ -83,7 +97,21 @@ def measured_traffic(dtype_name):
         return None
     if rec.get("source_hash") != kernel_source_hash():
         return None
-    v = rec.get(dtype_name, {}).get("bytes_per_stage")
+    return rec
+
+
+def measured_traffic(dtype_name):
+    """HBM bytes per RK stage from the committed counter summary, or None."""
+    rec = _profile_record("traffic_rk_stage_stratified512")
+    v = (rec or {}).get(dtype_name, {}).get("bytes_per_stage")
+    return float(v) if v else None
+
+
+def measured_valu(dtype_name):
+    """VALU lane-instructions per cell and stage from the committed counter
+    summary, or None."""
+    rec = _profile_record("instructions_rk_stage_stratified512")
+    v = (rec or {}).get(dtype_name, {}).get("valu_per_cell_stage")
     return float(v) if v else None
 
 
@@ -96,10 +124,25 @@ def make_state(workload, size):
     raise ValueError(workload)
 
 
+def _window(f_np, box, x0, y0, width):
+    """A full-height column window of the state, periodic in x and y."""
+    import numpy as np
+    ix = (np.arange(width) + x0) % box["nx"]
+    iy = (np.arange(width) + y0) % box["ny"]
+    sub = [np.ascontiguousarray(np.asarray(a)[:, iy][:, :, ix]) for a in f_np]
+    wbox = dict(box, nx=width, ny=width, Lx=box["Lx"] * width / box["nx"],
+                Ly=box["Ly"] * width / box["ny"])
+    return sub, wbox
+
+
 def run_gpu(size, dtype, steps, warmup, workload="stratified", tile=None, over=None,
-            launch=None):
+            launch=None, window=None):
     """Times `steps` RK steps.  over: parameters replacing the workload's;
-    launch: a (tile, persistent, final-pass tile) to use instead of tuning."""
+    launch: a (tile, persistent, final-pass tile) to use instead of tuning;
+    window: (x0, y0) of a column window: after the timing, one step of the
+    initial state with its Courant dt, whose central columns are returned
+    (with the window of the initial state and the dt) for the oracle."""
+    import numpy as np
     import torch
     from paper_2405_02483_amd.lib import Context
 
@@ -108,6 +151,10 @@ def run_gpu(size, dtype, steps, warmup, workload="stratified", tile=None, over=N
     prm = dict(prm, **(over or {}))
     ctx = Context(box, prm, dtype=dtype)
     f = ctx.upload([f_np])
+    win = None
+    if window is not None:
+        win = _window(f_np, box, window[0], window[1], 2 * WIN_MARGIN + WIN_CORE)
+        f0 = [t.clone() for t in f]
     del f_np
     tune = None
     if launch is not None:
@@ -138,6 +185,18 @@ def run_gpu(size, dtype, steps, warmup, workload="stratified", tile=None, over=N
     t1 = time.perf_counter()
     prof = ctx.profile_read()
     ctx.profile(False)
+    gpu_win = None
+    if win is not None:
+        # one step of the initial state in the launch just timed
+        ctx.step(f0, 0.0, 1, work=work)
+        nzt = box["nz"] + 2 * box.get("ngz", 0)
+        core = np.arange(WIN_MARGIN, WIN_MARGIN + WIN_CORE)
+        ix = torch.from_numpy((core + window[0]) % box["nx"]).to(f0[0].device)
+        iy = torch.from_numpy((core + window[1]) % box["ny"]).to(f0[0].device)
+        gpu_win = dict(sub=win[0], box=win[1], prm=prm, dt=ctx.last_dt(), window=window,
+                       got=[t.view(nzt, box["ny"], box["nx"])[:, iy][:, :, ix].double().cpu().numpy()
+                            for t in ctx.box_view(f0, 0)])
+        del f0
     launch = ctx.get_launch()
     ftile = ctx.get_final_tile()
     dt_last = ctx.last_dt()
@@ -153,7 +212,7 @@ def run_gpu(size, dtype, steps, warmup, workload="stratified", tile=None, over=N
                     "%s/%s" % (k[0], "persistent" if k[1] else "grid"): round(v, 4)
                     for k, v in tune.items()},
                 passes={k: (v[0] / max(v[1], 1), v[1]) for k, v in prof.items() if v[1]},
-                dt_last=dt_last, mass=s_end["mass"], ncell=ncell)
+                dt_last=dt_last, mass=s_end["mass"], ncell=ncell, window=gpu_win)
 
 
 def stream_copy_gbs(nbytes=1 << 30, reps=10):
@@ -263,23 +322,50 @@ def run_ensemble(nbox=96, nsteps=20, ncheck=None):
                                     for k, v in tune.items()}}
 
 
-def cpu_baseline(n=192, nsteps=1):
-    """The float64 CPU oracle on a bounded sample of the same workload."""
+def cpu_baseline(win):
+    """The float64 CPU oracle on a bounded sample of the same workload: one
+    RK step of a full-height column window (periodic in x and y) of the
+    benchmark's state, with the dt the library's float32 step took.  The
+    window's central columns are exact (they lie beyond the step's reach of
+    the window's edges), so they also give the float32 step's error against
+    the oracle, field by field (relative L2 over the interior planes)."""
+    import numpy as np
     import torch
     import oracle as O
-    from paper_2405_02483_amd import inputs
-    f, box, prm = inputs.stratified(n, n, n, seed=3)
-    ft = tuple(torch.from_numpy(a) for a in f)
+    sub, box, prm, dt = win["sub"], win["box"], win["prm"], win["dt"]
+    ft = tuple(torch.from_numpy(np.asarray(a, dtype=np.float64)) for a in sub)
     g = O.Grid(**box)
     p = O.Params(**{k: v for k, v in prm.items() if k in O.Params.__dataclass_fields__})
-    dt = O.courant(ft, g, p)[0]
     t0 = time.perf_counter()
-    O.step(ft, g, p, dt, nsteps)
+    out = O.step(ft, g, p, dt, 1)
     el = time.perf_counter() - t0
-    return {"value": n ** 3 * nsteps / el, "unit": "cell-updates/s",
+    # the same from the float32-rounded state the library starts from: what
+    # the float32 arithmetic adds to the rounding of the stored inputs
+    ft32 = tuple(torch.from_numpy(np.asarray(a, dtype=np.float32).astype(np.float64)) for a in sub)
+    out32 = O.step(ft32, g, p, dt, 1)
+    g0, g1 = box.get("ngz", 0), box.get("ngz", 0) + box["nz"]
+    c = slice(WIN_MARGIN, WIN_MARGIN + WIN_CORE)
+
+    def rel(ref):
+        errs = {}
+        for name, a, b in zip(O.FIELDS, ref, win["got"]):
+            want = a[g0:g1, c, c].numpy()
+            errs[name] = float(np.linalg.norm(b[g0:g1] - want) / max(np.linalg.norm(want), 1e-300))
+        return errs
+    errs, errs32 = rel(out), rel(out32)
+    ncell = box["nx"] * box["ny"] * box["nz"]
+    return {"value": ncell / el, "unit": "cell-updates/s",
             "cores": torch.get_num_threads(), "kind": "oracle",
-            "sample": "%d RK3 steps of the stratified workload at %d^3 (+2x5 ghost planes), "
-                      "float64, %.1f s" % (nsteps, n, el)}
+            "sample": "one RK3 step (float64) of a %dx%d full-height column window (%d interior "
+                      "+ 2x%d ghost planes) at (x, y) = %s of the workload's state, %.1f s"
+                      % (box["nx"], box["ny"], box["nz"], box.get("ngz", 0), win["window"], el),
+            "fp32_vs_oracle": {
+                "what": "the library's float32 step of the whole box against the oracle's step "
+                        "of the window, on the window's central %dx%d columns, interior planes: "
+                        "relative L2 per field (bound 1e-5)" % (WIN_CORE, WIN_CORE),
+                "rel_l2": errs, "max": max(errs.values()),
+                "rel_l2_from_fp32_rounded_state": errs32,
+                "max_from_fp32_rounded_state": max(errs32.values())}}
 
 
 def cpu_table(sizes=(32, 64, 128, 256)):
@@ -336,7 +422,8 @@ def main():
     ap.add_argument("--size", type=int, default=512)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-size", type=int, default=192)
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="only the adjoint leg (128^3, 40 steps), e.g. under a profiler")
     ap.add_argument("--workload", default="stratified", choices=("stratified", "turbulent"))
     ap.add_argument("--tile", default=None,
                     help="stage kernel tile shape, e.g. 32x8 (default: autotuned)")
@@ -344,7 +431,8 @@ def main():
     ap.add_argument("--no-sources", action="store_true",
                     help="skip the legs with the optional terms (cooling, Coriolis, energy "
                          "diffusion about the plane mean, ln(P/P_aver) pressure gradient, "
-                         "div B diffusion)")
+                         "div B diffusion, Smagorinsky with the five-cell maximum, quenching, "
+                         "the second-order switch)")
     ap.add_argument("--cpu-table", action="store_true",
                     help="only time the CPU oracle at 32^3..256^3 (1 and all threads); no GPU")
     a = ap.parse_args()
@@ -358,17 +446,27 @@ def main():
         sys.exit(2)
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if a.adjoint_only:
+        print(json.dumps({"adjoint": run_adjoint()}), flush=True)
+        return
 
-    r32 = run_gpu(a.size, torch.float32, a.steps, a.warmup, a.workload, a.tile)
+    window = None
+    if not a.no_cpu_baseline and a.workload == "stratified" and a.size >= 2 * WIN_MARGIN + WIN_CORE:
+        window = (137 % a.size, 301 % a.size)
+    r32 = run_gpu(a.size, torch.float32, a.steps, a.warmup, a.workload, a.tile, window=window)
     log("f32: %.2f ms/step, %.3e cell-updates/s" % (r32["ms_per_step"], r32["value"]))
     rsrc = {}
     if not a.no_sources and a.workload == "stratified":
         # the same workload and launch with one more source term switched on
-        from paper_2405_02483_amd.lib import T_ALL, T_COOL, T_CORI, T_EDIFFAV, T_LNP, T_DIVB
+        from paper_2405_02483_amd.lib import (T_ALL, T_COOL, T_CORI, T_EDIFFAV, T_LNP, T_DIVB,
+                                              T_SMAG, T_MAX5, T_QUENCH, T_ORDER2)
         L = r32["launch"]
         for name, bit, over in (("cooling", T_COOL, COOLING), ("coriolis", T_CORI, CORIOLIS),
                                 ("ediffav", T_EDIFFAV, {}), ("lnp", T_LNP, {}),
-                                ("divb", T_DIVB, dict(c_divb=0.05))):
+                                ("divb", T_DIVB, dict(c_divb=0.05)),
+                                ("smagorinsky_max5", T_SMAG | T_MAX5, dict(c_smag=0.15)),
+                                ("quench", T_QUENCH, dict(q_max=8.0, q_lim=2.0)),
+                                ("order2", T_ORDER2, dict(d2_lim=0.3))):
             rsrc[name] = run_gpu(a.size, torch.float32, max(2, a.steps // 5), 1, a.workload,
                                  over=dict(over, terms=T_ALL | bit),
                                  launch=(L["tile"], L["persistent"], L["final_pass_tile"]))
@@ -384,6 +482,7 @@ def main():
     copy_gbs = stream_copy_gbs()
     log("device copy: %.0f GB/s" % copy_gbs)
     traffic = measured_traffic("f32")
+    valu = measured_valu("f32")
     out = {
         "metric": "MHD cell-updates/s per RK step at 512^3 FP32 vs FP64; HBM roofline fraction",
         "value": r32["value"],
@@ -412,7 +511,14 @@ def main():
                      "frac_of_copy": achieved / copy_gbs,
                      "traffic_GBs": (None if traffic is None else
                                      traffic / (r32["stage_ms"] * 1e-3) / 1e9),
-                     "passes_ms": {k: round(v[0], 4) for k, v in r32["passes"].items()}},
+                     "passes_ms": {k: round(v[0], 4) for k, v in r32["passes"].items()},
+                     # the vector-issue ceiling of the same stage: counted VALU
+                     # lane-instructions over the chip's issue rate
+                     "valu": None if valu is None else {
+                         "per_cell_stage": valu,
+                         "issue_ms_per_stage": valu * ncell / VALU_LANE_RATE * 1e3,
+                         "issue_frac_of_stage": valu * ncell / VALU_LANE_RATE * 1e3 / r32["stage_ms"],
+                         "peak_lane_instr_per_s": VALU_LANE_RATE}},
         "launch": r32["launch"],
         "autotune_ms_per_rhs": r32["autotune_ms_per_rhs"],
     }
@@ -429,7 +535,11 @@ def main():
         "coriolis": "the Coriolis force (eq. mom), Omega = (%.3f, %.3f, %.3f)" % CORIOLIS["omega"],
         "ediffav": "energy diffusion about the horizontal mean (eq. ediffav)",
         "lnp": "the pressure gradient through ln(P/P_aver) (eq. pressure)",
-        "divb": "div B diffusion, c_divb 0.05"}
+        "divb": "div B diffusion, c_divb 0.05",
+        "smagorinsky_max5": "the Smagorinsky viscosity (eq. nusmag, c_smag 0.15) and the maximum "
+                            "over five cells (Section 6.1.1)",
+        "quench": "quenching of the viscous stress (eq. quench, q_max 8, q_lim 2)",
+        "order2": "the second-order switch of the strain (after eq. itv, d2_lim 0.3)"}
     for name, r in rsrc.items():
         out[name] = {
             "workload": "%s_%d with %s" % (a.workload, a.size, what[name]),
@@ -442,9 +552,9 @@ def main():
         out["adjoint"] = run_adjoint()
         log("ensemble leg")
         out["ensemble"] = run_ensemble()
-    if not a.no_cpu_baseline:
+    if not a.no_cpu_baseline and r32["window"] is not None:
         log("timing the CPU oracle sample")
-        out["cpu_baseline"] = cpu_baseline(a.cpu_size)
+        out["cpu_baseline"] = cpu_baseline(r32["window"])
     print(json.dumps(out), flush=True)
 
 

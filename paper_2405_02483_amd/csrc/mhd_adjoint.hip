@@ -384,7 +384,10 @@ VPlan plan_program(const VProgram& P) {
     const bool dep = nb && !R.groups.empty() &&
                      (prod[I.a] >= R.groups.back().first ||
                       (I.op == V_ROUGH && prod[I.b] >= R.groups.back().first));
-    if (q == 0 || dep || q - R.groups.back().first == kGroupMax) {
+    // the mask runs in a launch of its own (k_vm_rough): its eight-cell
+    // gathers would size the registers of every group's launch
+    const bool alone = I.op == V_ROUGH || (q > 0 && P.code[q - 1].op == V_ROUGH);
+    if (q == 0 || dep || alone || q - R.groups.back().first == kGroupMax) {
       if (!R.groups.empty()) gend.push_back(q);
       R.groups.push_back({q, 0});
     }
@@ -680,13 +683,6 @@ __global__ __launch_bounds__(kBlock) void k_vm_group(const BoxDev* boxes, const 
         r = I.geo == G_HINV ? T(I.k / bx_.hmin) : T(I.k * geo_of(bx_, I.geo));
         break;
       case V_ABS: r = fabs(opnd(I.a, G.la)); break;
-      case V_ROUGH: {
-        int i, j, k;
-        coords(i, j, k);
-        const Geo<T> g(bx_);
-        r = rough_at(base + I.a * stride, base + I.b * stride, g, i, j, k, T(I.k), I.ax) ? T(1) : T(0);
-        break;
-      }
       case V_SEL: r = opnd(I.c, G.lc) > T(0.5) ? opnd(I.b, G.lb) : opnd(I.a, G.la); break;
       case V_SDIV: {
         const T x = opnd(I.a, G.la), y = opnd(I.b, G.lb);
@@ -975,11 +971,31 @@ __global__ __launch_bounds__(kBlock) void k_axpby8(const BoxDev* boxes, const Bl
   }
 }
 
+// The second-order switch's mask (V_ROUGH), alone in its group: both
+// operands and the result in memory.
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_vm_rough(const BoxDev* boxes, const Blk* tab,
+                                                     const VFused* __restrict__ code, int at, T* base,
+                                                     long long stride) {
+  VM_PROLOGUE
+  const VInstr I = code[at].f;
+  int i, j, k;
+  coords(i, j, k);
+  const Geo<T> g(bx_);
+  base[I.out * stride + o] =
+      rough_at(base + I.a * stride, base + I.b * stride, g, i, j, k, T(I.k), I.ax) ? T(1) : T(0);
+}
+
 template <class T>
 void vm_forward(const VLaunch& L, const VPlan& P, const VFused* d_fused, T* base, long long stride) {
-  for (const VGroup& G : P.groups)
-    hipLaunchKernelGGL(k_vm_group<T>, dim3(L.nblk), dim3(kBlock), 0, L.stream, L.boxes, L.tab, d_fused,
-                       G.first, G.count, base, stride);
+  for (const VGroup& G : P.groups) {
+    if (P.fused[G.first].f.op == V_ROUGH)
+      hipLaunchKernelGGL(k_vm_rough<T>, dim3(L.nblk), dim3(kBlock), 0, L.stream, L.boxes, L.tab, d_fused,
+                         G.first, base, stride);
+    else
+      hipLaunchKernelGGL(k_vm_group<T>, dim3(L.nblk), dim3(kBlock), 0, L.stream, L.boxes, L.tab, d_fused,
+                         G.first, G.count, base, stride);
+  }
 }
 
 template <class T>

@@ -1350,8 +1350,10 @@ static void launch_zstage_m(const ZLaunch& L, const ZStageArgs<T>& a) {
     hipLaunchKernelGGL((zP<T, TX, TY, PERS>), grid((const void*)zP<T, TX, TY, PERS>), block, 0, L.stream,
                        L.boxes, L.items, n, a.ztab, q ? q + 24 : q, a.f, a.ph, wq);
   };
-  if (o2) launch_p();
-  L.at(PASS_EDGES);
+  if (o2) {
+    launch_p();
+    L.at(PASS_EDGES);
+  }
   hipLaunchKernelGGL((zQ<T, TX, TY, PERS, QM_EDGES>), grid((const void*)zQ<T, TX, TY, PERS, QM_EDGES>), block, 0,
                      L.stream, L.boxes, L.items, n, a.ztab, q ? q + 16 : q, a.f, a.ph, wq, a.lnavg,
                      a.w.lnpav);
