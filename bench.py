@@ -423,7 +423,9 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--adjoint-only", action="store_true",
-                    help="only the adjoint leg (128^3, 40 steps), e.g. under a profiler")
+                    help="only the adjoint leg, e.g. under a profiler")
+    ap.add_argument("--adjoint-size", type=int, default=128)
+    ap.add_argument("--adjoint-steps", type=int, default=40)
     ap.add_argument("--workload", default="stratified", choices=("stratified", "turbulent"))
     ap.add_argument("--tile", default=None,
                     help="stage kernel tile shape, e.g. 32x8 (default: autotuned)")
@@ -447,7 +449,7 @@ def main():
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if a.adjoint_only:
-        print(json.dumps({"adjoint": run_adjoint()}), flush=True)
+        print(json.dumps({"adjoint": run_adjoint(a.adjoint_size, a.adjoint_steps)}), flush=True)
         return
 
     window = None
@@ -549,7 +551,7 @@ def main():
             "passes_ms": {k: round(v[0], 4) for k, v in r["passes"].items()}}
     if not a.no_adjoint:
         log("adjoint leg")
-        out["adjoint"] = run_adjoint()
+        out["adjoint"] = run_adjoint(a.adjoint_size, a.adjoint_steps)
         log("ensemble leg")
         out["ensemble"] = run_ensemble()
     if not a.no_cpu_baseline and r32["window"] is not None:
