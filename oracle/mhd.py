@@ -88,7 +88,7 @@ import math
 
 import torch
 
-from .stagger import Ops, AX_X, AX_Y, AX_Z
+from .stagger import Ops, AX_X, AX_Y, AX_Z, DERIV6
 
 __all__ = [
     "T_CONT", "T_ADV", "T_PRES", "T_VISC", "T_LORENTZ", "T_INDUCT",
@@ -99,6 +99,7 @@ __all__ = [
     "interior_slices", "smoothed_viscosity", "newton_cooling", "coriolis",
     "horizontal_ln_mean", "pressure_gradient_ln", "viscosity_lengths",
     "edge_viscosity", "smagorinsky_rate", "quench_factor", "rough_cells", "strain",
+    "derivative_symbol", "divb_clean",
 ]
 
 FIELDS = ("rho", "px", "py", "pz", "e", "bx", "by", "bz")
@@ -707,6 +708,42 @@ def courant(f, grid, par, dfdt=None):
         if rmax > 0:
             cand.append((par.Cdtr / rmax, int(torch.argmax(rate)), 2))
     return min(cand, key=lambda c: c[0])
+
+
+def derivative_symbol(n, h):
+    """K(theta_m) for the n Fourier modes m = 0..n-1 of a periodic axis of
+    spacing h: the sixth-order staggered derivative (eq. deriv) multiplies
+    the mode exp(i theta j), theta = 2 pi m / n, by i K with a half-cell
+    shift, K = (2/h) sum_p d_p sin((2p - 1) theta / 2)."""
+    th = 2.0 * math.pi * torch.arange(n, dtype=torch.float64) / n
+    K = torch.zeros(n, dtype=torch.float64)
+    for p, w in enumerate(DERIV6, start=1):
+        K = K + w * torch.sin((2 * p - 1) * th / 2.0)
+    return 2.0 * K / h
+
+
+def divb_clean(f, grid):
+    """div B cleaning (Section 3, eq. clean1, eq. clean2) of a periodic box:
+    the potential phi with ddxup(ddxdn(phi)) + ddyup(ddydn(phi)) +
+    ddzup(ddzdn(phi)) = div B, div B = ddxup(B_x) + ddyup(B_y) + ddzup(B_z)
+    at the centres, solved in Fourier space, where the operator is
+    multiplication by -(K_x^2 + K_y^2 + K_z^2) (zero only for the mean mode,
+    whose phi is 0); then B_a - ddadn(phi) on the faces.  The cleaned B has
+    zero discrete divergence; the other fields are returned unchanged."""
+    if grid.wall:
+        raise ValueError("div B cleaning in Fourier space needs a periodic box")
+    O = grid.ops()
+    rho, px, py, pz, e, bx, by, bz = f
+    div = O.ddxup(bx) + O.ddyup(by) + O.ddzup(bz)
+    nz, ny, nx = div.shape
+    kx = derivative_symbol(nx, grid.dx) ** 2
+    ky = derivative_symbol(ny, grid.dy) ** 2
+    kz = derivative_symbol(nz, grid.dz) ** 2
+    lap = -(kz.view(-1, 1, 1) + ky.view(1, -1, 1) + kx.view(1, 1, -1))
+    dh = torch.fft.fftn(div)
+    ph = torch.where(lap < 0, dh / torch.where(lap < 0, lap, torch.ones_like(lap)), torch.zeros_like(dh))
+    phi = torch.fft.ifftn(ph).real
+    return (rho, px, py, pz, e, bx - O.ddxdn(phi), by - O.ddydn(phi), bz - O.ddzdn(phi))
 
 
 def stats(f, grid, par):
