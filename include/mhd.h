@@ -286,6 +286,20 @@ int mhd_rhs_adjoint(mhd_ctx* ctx, void* const f[8], void* const wbar[8],
 int mhd_reductions(mhd_ctx* ctx, void* const f[8], void* const dfdt[8],
                    mhd_stats* out);
 
+/* div B cleaning in Fourier space (Section 3, eq. clean1, eq. clean2):
+ * projects the magnetic field f[5..7] of every box in place onto its
+ * discretely solenoidal part.  The potential phi solves ddxup(ddxdn(phi))
+ * + ddyup(ddydn(phi)) + ddzup(ddzdn(phi)) = div B (div B from the up
+ * derivatives at the centres), whose Fourier symbol is -(K_x^2 + K_y^2 +
+ * K_z^2) with K the sixth-order derivative symbol (the mean mode's phi is
+ * 0); then B_a -= ddadn(phi).  Afterwards the discrete div B is zero to
+ * rounding; a discrete curl is unchanged; the other fields are untouched.
+ * Needs periodic boxes (MHD_EUNSUPPORTED with walls).  The first call
+ * makes rocFFT plans per box shape and allocates scratch for the largest
+ * box (about 3 of its fields), kept until mhd_destroy (MHD_ENOMEM,
+ * MHD_EHIP on failure).  Returns without waiting.                          */
+int mhd_divb_clean(mhd_ctx* ctx, void* const f[8]);
+
 /* The dt of the last step taken with dt == 0 (waits for the stream).      */
 int mhd_last_dt(mhd_ctx* ctx, double* dt);
 

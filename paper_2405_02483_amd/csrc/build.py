@@ -60,7 +60,10 @@ def build(verbose=False):
             if l.strip():
                 print(os.path.basename(s), l)
     tmp = LIB + ".tmp"
-    cmd = [_hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs
+    # rocFFT (div B cleaning) from the ROCm installation
+    rocm_lib = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "lib")
+    cmd = ([_hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs +
+           ["-L" + rocm_lib, "-Wl,-rpath," + rocm_lib, "-lrocfft"])
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stdout + r.stderr)

@@ -14,6 +14,7 @@
 
 #include "../../include/mhd.h"
 #include "mhd_adjoint.hpp"
+#include "mhd_clean.hpp"
 #include "mhd_kernels.hpp"
 #include "mhd_zmarch_api.hpp"
 
@@ -62,6 +63,7 @@ struct mhd_ctx {
   void* d_lnpav = nullptr;         // ln of the plane means of P, per plane of every box
   int nplanes = 0;
   void* scratch = nullptr;         // this device's address of the static scratch array
+  CleanState* clean = nullptr;     // div B cleaning: rocFFT plans and scratch (first use)
   // timing of kernel passes (mhd_profile)
   bool prof = false;
   std::vector<std::pair<int, hipEvent_t>> marks;
@@ -457,6 +459,7 @@ void mhd_destroy(mhd_ctx* c) {
   (void)hipFree(c->d_lnavg);
   (void)hipFree(c->d_lnpart);
   (void)hipFree(c->d_lnpav);
+  clean_free(c->clean);
   delete c;
 }
 
@@ -985,6 +988,21 @@ int mhd_reductions(mhd_ctx* c, void* const f[8], void* const dfdt[8], mhd_stats*
   if (dfdt && (rc = check8(c, dfdt, "dfdt"))) return rc;
   return c->p.dtype == MHD_F32 ? do_reduce<float>(c, f, dfdt, out)
                                : do_reduce<double>(c, f, dfdt, out);
+}
+
+int mhd_divb_clean(mhd_ctx* c, void* const f[8]) {
+  if (!c) return fail(nullptr, MHD_EINVAL, "ctx is NULL");
+  int rc;
+  if ((rc = check8(c, f, "f"))) return rc;
+  for (const auto& b : c->boxes)
+    if (b.bc_z != MHD_BC_PERIODIC)
+      return fail(c, MHD_EUNSUPPORTED, "div B cleaning in Fourier space needs periodic boxes");
+  std::string err;
+  const int r = c->p.dtype == MHD_F32 ? clean_boxes<float>(&c->clean, c->h_boxes, p8<float>(f), c->stream, err)
+                                      : clean_boxes<double>(&c->clean, c->h_boxes, p8<double>(f), c->stream, err);
+  if (r == 2) return fail(c, MHD_ENOMEM, "mhd_divb_clean: " + err);
+  if (r) return fail(c, MHD_EHIP, "mhd_divb_clean: " + err);
+  return check_launch(c, "mhd_divb_clean launch");
 }
 
 int mhd_step_adjoint(mhd_ctx* c, void* const f_n[8], double dt, void* const gin[8],

@@ -19,7 +19,7 @@ __all__ = [
     "T_EDIFFAV", "T_LNP", "T_DIVB", "T_SMAG", "T_MAX5", "T_QUENCH", "T_ORDER2",
     "MhdBox", "MhdParams", "MhdStats", "MhdError", "lib_path", "load",
     "mhd_init", "mhd_destroy", "mhd_last_error", "mhd_field_elems",
-    "mhd_box_offset", "mhd_rhs", "mhd_rhs_noalloc", "mhd_step", "mhd_step_adjoint",
+    "mhd_box_offset", "mhd_rhs", "mhd_rhs_noalloc", "mhd_step", "mhd_step_adjoint", "mhd_divb_clean",
     "mhd_reductions", "mhd_profile", "mhd_profile_read", "mhd_last_dt", "mhd_set_tile",
     "mhd_set_launch", "mhd_get_launch", "mhd_set_final_tile", "mhd_get_final_tile",
     "mhd_autotune", "mhd_rhs_adjoint",
@@ -136,6 +136,8 @@ def load():
     L.mhd_step_adjoint.restype = ctypes.c_int
     L.mhd_reductions.argtypes = [vp, _P8, ctypes.c_void_p, ctypes.POINTER(MhdStats)]
     L.mhd_reductions.restype = ctypes.c_int
+    L.mhd_divb_clean.argtypes = [vp, _P8]
+    L.mhd_divb_clean.restype = ctypes.c_int
     L.mhd_last_dt.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
     L.mhd_last_dt.restype = ctypes.c_int
     L.mhd_set_tile.argtypes = [vp, i32]
@@ -212,6 +214,10 @@ def mhd_rhs(ctx, f, dfdt, *, dtype, n):
 
 def mhd_rhs_noalloc(ctx, f, dfdt, *, dtype, n):
     _check(load().mhd_rhs_noalloc(ctx, _ptrs(f, n, dtype, "f"), _ptrs(dfdt, n, dtype, "dfdt")), ctx)
+
+
+def mhd_divb_clean(ctx, f, *, dtype, n):
+    _check(load().mhd_divb_clean(ctx, _ptrs(f, n, dtype, "f")), ctx)
 
 
 def mhd_step(ctx, f, tmp1, tmp2, du, dt, nsteps, *, dtype, n):
@@ -404,6 +410,12 @@ class Context:
         scratch in the library's static device array."""
         mhd_rhs_noalloc(self.ctx, f, dfdt, dtype=self.dtype, n=self.n)
         return dfdt
+
+    def divb_clean(self, f):
+        """mhd_divb_clean: B of every (periodic) box projected in place onto
+        its discretely solenoidal part (eq. clean1, eq. clean2)."""
+        mhd_divb_clean(self.ctx, f, dtype=self.dtype, n=self.n)
+        return f
 
     def step(self, f, dt, nsteps=1, work=None):
         work = work or (self.empty(), self.empty(), self.empty())
