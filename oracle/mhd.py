@@ -99,7 +99,7 @@ __all__ = [
     "interior_slices", "smoothed_viscosity", "newton_cooling", "coriolis",
     "horizontal_ln_mean", "pressure_gradient_ln", "viscosity_lengths",
     "edge_viscosity", "smagorinsky_rate", "quench_factor", "rough_cells", "strain",
-    "derivative_symbol", "divb_clean",
+    "derivative_symbol", "divb_clean", "zgrid_intervals", "z_face_length",
 ]
 
 FIELDS = ("rho", "px", "py", "pz", "e", "bx", "by", "bz")
@@ -135,6 +135,39 @@ BETA = (0.46173, 0.924087, 0.390614)
 NU_FLOOR = 1e-30
 
 
+def zgrid_intervals(zc):
+    """Grid intervals dz/dxi of a stretched z axis (Section 4.2: the
+    Jacobian is the inverse of the grid interval, from a spline fit, at the
+    centre of each derivative).  zc: the heights of the n cell centres
+    (xi = 0..n-1, strictly increasing).  The not-a-knot cubic spline through
+    (k, zc[k]) has second derivatives M solving, with unit spacing,
+    M[k-1] + 4 M[k] + M[k+1] = 6 (zc[k+1] - 2 zc[k] + zc[k-1]) for interior k
+    and M[0] - 2 M[1] + M[2] = 0, M[n-3] - 2 M[n-2] + M[n-1] = 0 (a
+    continuous third derivative at the second and the second-last knots).
+    Returns (dzc, dzf): its derivative at the centres xi = k and at the
+    faces xi = k - 1/2 (face 0 from the first interval's cubic)."""
+    z = torch.as_tensor(zc, dtype=torch.float64)
+    n = z.shape[0]
+    if n < 4:
+        raise ValueError("a stretched axis needs at least 4 planes")
+    A = torch.zeros(n, n, dtype=torch.float64)
+    r = torch.zeros(n, dtype=torch.float64)
+    A[0, 0], A[0, 1], A[0, 2] = 1.0, -2.0, 1.0
+    A[n - 1, n - 3], A[n - 1, n - 2], A[n - 1, n - 1] = 1.0, -2.0, 1.0
+    for k in range(1, n - 1):
+        A[k, k - 1], A[k, k], A[k, k + 1] = 1.0, 4.0, 1.0
+        r[k] = 6.0 * (z[k + 1] - 2.0 * z[k] + z[k - 1])
+    M = torch.linalg.solve(A, r)
+    # on [k, k+1]: S(xi) = M_k (k+1-xi)^3/6 + M_{k+1} (xi-k)^3/6
+    #                    + (z_k - M_k/6)(k+1-xi) + (z_{k+1} - M_{k+1}/6)(xi-k)
+    def slope(k, t):      # S'(k + t) on the interval [k, k+1]
+        return (-M[k] * (1.0 - t) ** 2 / 2.0 + M[k + 1] * t ** 2 / 2.0
+                + (z[k + 1] - M[k + 1] / 6.0) - (z[k] - M[k] / 6.0))
+    dzc = torch.stack([slope(k, 0.0) if k < n - 1 else slope(n - 2, 1.0) for k in range(n)])
+    dzf = torch.stack([slope(k - 1, 0.5) if k > 0 else slope(0, -0.5) for k in range(n)])
+    return dzc, dzf
+
+
 @dataclass(frozen=True)
 class Grid:
     nx: int
@@ -145,10 +178,26 @@ class Grid:
     Lx: float = 1.0
     Ly: float = 1.0
     Lz: float = 1.0
+    # stretched z (walls only): the heights of the nz + 2 ngz cell centres;
+    # None: uniform, dz = Lz / nz
+    zc: tuple = None
 
     @property
     def nzt(self):
         return self.nz + 2 * self.ngz
+
+    @property
+    def stretched(self):
+        return self.zc is not None
+
+    def zintervals(self):
+        """(dzc, dzf) per plane (tensors of nzt), stretched or uniform."""
+        if self.zc is None:
+            d = torch.full((self.nzt,), self.dz, dtype=torch.float64)
+            return d, d
+        if not self.wall or len(self.zc) != self.nzt:
+            raise ValueError("a stretched z axis needs walls and nz + 2 ngz heights")
+        return zgrid_intervals(self.zc)
 
     @property
     def dx(self):
@@ -164,13 +213,20 @@ class Grid:
 
     @property
     def hmin(self):
+        if self.zc is not None:
+            return min(self.dx, self.dy, float(self.zintervals()[0].min()))
         return min(self.dx, self.dy, self.dz)
 
     @property
     def hmax(self):
+        if self.zc is not None:
+            return max(self.dx, self.dy, float(self.zintervals()[0].max()))
         return max(self.dx, self.dy, self.dz)
 
     def ops(self):
+        if self.zc is not None:
+            dzc, dzf = self.zintervals()
+            return Ops(self.dx, self.dy, self.dz, wall_z=self.wall, jz=(1.0 / dzc, 1.0 / dzf))
         return Ops(self.dx, self.dy, self.dz, wall_z=self.wall)
 
 
@@ -234,6 +290,9 @@ def smoothed_viscosity(f, grid, par, O=None):
     O = O or grid.ops()
     rho, px, py, pz, e, bx, by, bz = f
     h = grid.hmin
+    if grid.stretched and not par.nu_const > 0:
+        # the local smallest spacing of each plane's cells
+        h = torch.clamp(grid.zintervals()[0], max=min(grid.dx, grid.dy)).view(-1, 1, 1)
     P = (par.gamma - 1.0) * e
     ux, uy, uz = px / O.xdn(rho), py / O.ydn(rho), pz / O.zdn(rho)
     ubx, uby, ubz = O.xup(ux), O.yup(uy), O.zup(uz)
@@ -242,7 +301,7 @@ def smoothed_viscosity(f, grid, par, O=None):
     cs = torch.sqrt(par.gamma * P / rho)
     ca = _safe_norm3(bbx, bby, bbz) / torch.sqrt(par.mu * rho)
     if par.nu_const > 0:
-        nus = torch.full_like(rho, par.nu_const / h)
+        nus = torch.full_like(rho, par.nu_const / grid.hmin)
     else:
         nus = (par.nu1 * _safe_norm3(ubx, uby, ubz)
                + par.nu3 * (cs + ca)
@@ -339,12 +398,29 @@ def viscosity_lengths(grid, par):
     nu_ii = l_i <nu> and nu_ij = l_ij <nu>.  Richtmyer-Morton viscosity:
     l_i = dx_i and l_ij = max(dx_i, dx_j).  Constant viscosity (Section 6.1:
     nu_ij = const for every component): <nu> = nu_const / h_min everywhere and
-    every factor is h_min, so each nu_ij is nu_const on any cell shape."""
+    every factor is h_min, so each nu_ij is nu_const on any cell shape.
+    On a stretched z axis the z spacing is the plane's own (tensors over
+    the planes): its centre interval for lz, its face interval for lxz and
+    lyz (the y- and x-edges sit at the faces' heights)."""
     if par.nu_const > 0:
         h = grid.hmin
         return (h, h, h), (h, h, h)
-    dx, dy, dz = grid.dx, grid.dy, grid.dz
+    dx, dy = grid.dx, grid.dy
+    if grid.stretched:
+        dzc, dzf = (d.view(-1, 1, 1) for d in grid.zintervals())
+        return (dx, dy, dzc), (max(dx, dy), torch.clamp(dzf, min=dx), torch.clamp(dzf, min=dy))
+    dz = grid.dz
     return (dx, dy, dz), (max(dx, dy), max(dx, dz), max(dy, dz))
+
+
+def z_face_length(grid, par):
+    """The z length factor of the energy-diffusion flux on the z-faces
+    (eq. ediffuse): the face interval on a stretched axis."""
+    if par.nu_const > 0:
+        return grid.hmin
+    if grid.stretched:
+        return grid.zintervals()[1].view(-1, 1, 1)
+    return grid.dz
 
 
 def edge_viscosity(nt, grid, par, O=None):
@@ -529,7 +605,7 @@ def rhs_nofill(f, grid, par, dt=None):
         lnez = lne
         if T & T_EDIFFAV:
             lnez = lne - horizontal_ln_mean(em)
-        fz = par.nuE * O.zdn(rho) * (lz * O.zdn(nt)) * O.zdn(em) * O.ddzdn(lnez)
+        fz = par.nuE * O.zdn(rho) * (z_face_length(grid, par) * O.zdn(nt)) * O.zdn(em) * O.ddzdn(lnez)
         de = de + O.ddxup(fx) + O.ddyup(fy) + O.ddzup(fz)
     if T & T_COOL:
         de = de + newton_cooling(rho, e, par)
@@ -753,17 +829,18 @@ def stats(f, grid, par):
     counts of non-finite values and of cells with rho <= 0 or e <= 0."""
     O = grid.ops()
     rho, px, py, pz, e, bx, by, bz = f
-    dV = grid.dx * grid.dy * grid.dz
+    # cell volumes (a plane's centre interval on a stretched z axis)
+    dV = (grid.dx * grid.dy * grid.zintervals()[0]).view(-1, 1, 1)
     sc, _ = interior_slices(grid)
     out = {}
-    out["mass"] = rho[sc].sum().item() * dV
-    out["mom"] = [q[sc].sum().item() * dV for q in (px, py, pz)]
+    out["mass"] = (rho * dV)[sc].sum().item()
+    out["mom"] = [(q * dV)[sc].sum().item() for q in (px, py, pz)]
     ekin = 0.0
     for q, r in ((px, O.xdn(rho)), (py, O.ydn(rho)), (pz, O.zdn(rho))):
-        ekin += (0.5 * q * q / r)[sc].sum().item()
-    out["ekin"] = ekin * dV
-    out["emag"] = sum((q * q)[sc].sum().item() for q in (bx, by, bz)) * dV / (2 * par.mu)
-    out["eint"] = e[sc].sum().item() * dV
+        ekin += (0.5 * q * q / r * dV)[sc].sum().item()
+    out["ekin"] = ekin
+    out["emag"] = sum((q * q * dV)[sc].sum().item() for q in (bx, by, bz)) / (2 * par.mu)
+    out["eint"] = (e * dV)[sc].sum().item()
     divb = (O.ddxup(bx) + O.ddyup(by) + O.ddzup(bz))[sc]
     out["divb_max"] = divb.abs().max().item()
     out["divb_rms"] = math.sqrt((divb * divb).mean().item())

@@ -99,11 +99,16 @@ class Ops:
     end treatment described in the module docstring; x and y are always
     periodic (Section 10).
     ``h``: grid spacings (dx, dy, dz).
+    ``jz``: a stretched z axis (walls only): (Jc, Jf), the Jacobians of each
+    plane's centre and face (Section 4.2: derivatives in index space times
+    the Jacobian at the derivative's centre); an up derivative's output sits
+    at a centre, a down derivative's on a face.
     """
 
-    def __init__(self, dx, dy, dz, wall_z=False):
+    def __init__(self, dx, dy, dz, wall_z=False, jz=None):
         self.h = {AX_X: dx, AX_Y: dy, AX_Z: dz}
         self.wall_z = wall_z
+        self.jz = jz
 
     # -- generic -----------------------------------------------------------
     def stencil(self, f, axis, fam, form, order=6):
@@ -112,14 +117,17 @@ class Ops:
         state is rough, the switch after eq. itv)."""
         h = self.h[axis]
         if axis == AX_Z and self.wall_z:
-            return self._wall_stencil(f, fam, form, h, order)
+            jac = None
+            if self.jz is not None and fam == "d":
+                jac = self.jz[0] if form == "up" else self.jz[1]
+            return self._wall_stencil(f, fam, form, h, order, jac)
         off = 0 if form == "dn" else 1      # c = i + off
 
         def get(p):
             return _shift(f, off + p - 1, axis), _shift(f, off - p, axis)
         return _pair_formula(get, fam, order, h)
 
-    def _wall_stencil(self, f, fam, form, h, top=6):
+    def _wall_stencil(self, f, fam, form, h, top=6, jac=None):
         n = f.shape[0]
         off = 0 if form == "dn" else 1
         planes = [None] * n
@@ -138,7 +146,10 @@ class Ops:
 
             def get(p, c=c):
                 return f[c + p - 1], f[c - p]
-            planes[k] = _pair_formula(get, fam, order, h)
+            if jac is None:
+                planes[k] = _pair_formula(get, fam, order, h)
+            else:     # index space, times this output's Jacobian
+                planes[k] = _pair_formula(get, fam, order, 1.0) * jac[k]
         # the one end value no centred stencil reaches copies its neighbour
         if planes[0] is None:
             planes[0] = planes[1]
