@@ -138,6 +138,19 @@ typedef struct {
     int32_t bc_z;           /* MHD_BC_PERIODIC or MHD_BC_WALL                  */
     int32_t reserved;       /* must be 0                                       */
     double Lx, Ly, Lz;      /* box size; dx = Lx/nx, dy = Ly/ny, dz = Lz/nz    */
+    /* Stretched z (Section 4.2; walls only), or NULL for uniform dz: host
+     * array of the nz + 2 ngz cell-centre heights (ghost planes included),
+     * finite and strictly increasing, copied by mhd_init (Lz is then
+     * unused).  The grid interval dz/dxi is the derivative of the
+     * not-a-knot cubic spline through (k, zc[k]), at the centres and the
+     * faces; every z derivative is the index-space stencil times the
+     * inverse interval at its output; nu_zz's length is the centre interval,
+     * the x-/y-edge lengths max(dx or dy, face interval), the energy
+     * diffusion's z length the face interval, the shock and Smagorinsky h
+     * the cell's smallest spacing, cell volumes dx dy dz_c; the Courant,
+     * div B diffusion and constant-viscosity h is the box's smallest
+     * spacing.  MHD_EINVAL for a periodic box or a non-increasing zc.      */
+    const double* zc;
 } mhd_box;
 
 /* Physical and numerical parameters (&pde, &run, &force namelists).         */

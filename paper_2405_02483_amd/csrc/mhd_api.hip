@@ -64,6 +64,10 @@ struct mhd_ctx {
   int nplanes = 0;
   void* scratch = nullptr;         // this device's address of the static scratch array
   CleanState* clean = nullptr;     // div B cleaning: rocFFT plans and scratch (first use)
+  // stretched z axes: per box the grid intervals at the centres and faces
+  // (empty for a uniform box)
+  std::vector<std::vector<double>> dzc, dzf;
+  int stretched = 0;
   // timing of kernel passes (mhd_profile)
   bool prof = false;
   std::vector<std::pair<int, hipEvent_t>> marks;
@@ -168,6 +172,51 @@ static int work_arrays(const mhd_params& p) {
   return (p.terms & MHD_T_QUENCH) ? WS_COUNT_QUENCH : WS_COUNT;
 }
 
+// Grid intervals dz/dxi of a stretched z axis (Section 4.2: the Jacobian is
+// the inverse of the spline-fitted grid interval at the derivative's
+// centre): the not-a-knot cubic spline through (k, z[k]), k = 0..n-1, has
+// second derivatives M with M[k-1] + 4 M[k] + M[k+1] = 6 (z[k+1] - 2 z[k] +
+// z[k-1]) inside and M[0] - 2 M[1] + M[2] = 0, M[n-3] - 2 M[n-2] + M[n-1] =
+// 0.  Subtracting the end rows from their neighbours gives M[1] and M[n-2]
+// directly; rows 2..n-3 are tridiagonal in M[2..n-3].  Returns its
+// derivative at the centres k (dzc) and the faces k - 1/2 (dzf; face 0 from
+// the first interval's cubic).
+static void zintervals(const std::vector<double>& z, std::vector<double>& dzc, std::vector<double>& dzf) {
+  const int n = (int)z.size();
+  std::vector<double> r(n, 0.0), M(n, 0.0);
+  for (int k = 1; k < n - 1; ++k) r[k] = 6.0 * (z[k + 1] - 2.0 * z[k] + z[k - 1]);
+  M[1] = r[1] / 6.0;
+  M[n - 2] = r[n - 2] / 6.0;
+  if (n > 4) {
+    // Thomas algorithm on rows k = 2..n-3: M[k-1] + 4 M[k] + M[k+1] = r[k]
+    const int a = 2, e = n - 3, m = e - a + 1;
+    std::vector<double> cp(m), dp(m);
+    for (int i = 0; i < m; ++i) {
+      const int k = a + i;
+      double rhs = r[k];
+      if (k - 1 == 1) rhs -= M[1];
+      if (k + 1 == n - 2) rhs -= M[n - 2];
+      const double lo = i > 0 ? 1.0 : 0.0, up = i < m - 1 ? 1.0 : 0.0;
+      const double den = 4.0 - lo * (i > 0 ? cp[i - 1] : 0.0);
+      cp[i] = up / den;
+      dp[i] = (rhs - lo * (i > 0 ? dp[i - 1] : 0.0)) / den;
+    }
+    for (int i = m - 1; i >= 0; --i) M[a + i] = dp[i] - (i < m - 1 ? cp[i] * M[a + i + 1] : 0.0);
+  }
+  M[0] = 2.0 * M[1] - M[2];
+  M[n - 1] = 2.0 * M[n - 2] - M[n - 3];
+  auto slope = [&](int k, double t) {   // S'(k + t) on [k, k+1]
+    return -M[k] * (1.0 - t) * (1.0 - t) / 2.0 + M[k + 1] * t * t / 2.0 + (z[k + 1] - M[k + 1] / 6.0) -
+           (z[k] - M[k] / 6.0);
+  };
+  dzc.resize(n);
+  dzf.resize(n);
+  for (int k = 0; k < n; ++k) {
+    dzc[k] = k < n - 1 ? slope(k, 0.0) : slope(n - 2, 1.0);
+    dzf[k] = k > 0 ? slope(k - 1, 0.5) : slope(0, -0.5);
+  }
+}
+
 static int fail(mhd_ctx* c, int code, const std::string& msg) {
   if (c) c->err = msg; else g_init_err = msg;
   return code;
@@ -261,6 +310,7 @@ static ZLaunch make_zlaunch(const mhd_ctx* c, const Scratch& s) {
   L.ncu = c->ncu;
   L.nbox = (int)c->h_boxes.size();
   L.nplanes = c->nplanes;
+  L.stretched = c->stretched;
   L.stream = c->stream;
   L.mark = c->prof ? prof_mark : nullptr;
   L.mark_ctx = const_cast<mhd_ctx*>(c);
@@ -528,16 +578,41 @@ int mhd_init(const mhd_params* p, void* hip_stream, mhd_ctx** out) {
       return fail(nullptr, MHD_EINVAL, where + "unknown bc_z");
     }
     if (!(x.Lx > 0) || !(x.Ly > 0) || !(x.Lz > 0)) { delete c; return fail(nullptr, MHD_EINVAL, where + "box sizes must be > 0"); }
-    if ((p->terms & MHD_T_DIVB) && p->c_divb > divb_limit(x.Lx / x.nx, x.Ly / x.ny, x.Lz / x.nz)) {
+    // a stretched z axis: the heights, copied, and their spline intervals
+    std::vector<double> dzc, dzf;
+    double dzmin = x.Lz / x.nz, dzmax = dzmin;
+    if (x.zc) {
+      if (x.bc_z != MHD_BC_WALL) { delete c; return fail(nullptr, MHD_EINVAL, where + "a stretched z axis needs walls"); }
+      const int nzt = x.nz + 2 * x.ngz;
+      std::vector<double> z(x.zc, x.zc + nzt);
+      for (int k = 0; k < nzt; ++k)
+        if (!std::isfinite(z[k]) || (k > 0 && !(z[k] > z[k - 1]))) {
+          delete c;
+          return fail(nullptr, MHD_EINVAL, where + "zc must be finite and strictly increasing");
+        }
+      zintervals(z, dzc, dzf);
+      for (int k = 0; k < nzt; ++k)
+        if (!(dzc[k] > 0.0) || !(dzf[k] > 0.0)) {
+          delete c;
+          return fail(nullptr, MHD_EINVAL, where + "the spline of zc is not increasing everywhere");
+        }
+      dzmin = *std::min_element(dzc.begin(), dzc.end());
+      dzmax = *std::max_element(dzc.begin(), dzc.end());
+      c->stretched = 1;
+    }
+    c->dzc.push_back(dzc);
+    c->dzf.push_back(dzf);
+    if ((p->terms & MHD_T_DIVB) && p->c_divb > divb_limit(x.Lx / x.nx, x.Ly / x.ny, dzmin)) {
       delete c;
       return fail(nullptr, MHD_EINVAL, where + "c_divb above the RK3 stability limit " +
-                                           std::to_string(divb_limit(x.Lx / x.nx, x.Ly / x.ny, x.Lz / x.nz)));
+                                           std::to_string(divb_limit(x.Lx / x.nx, x.Ly / x.ny, dzmin)));
     }
     if ((long long)x.nx * x.ny * (x.nz + 2LL * x.ngz) >= (1LL << 31)) {
       delete c;
       return fail(nullptr, MHD_EINVAL, where + "more than 2^31 - 1 cells (ghost planes included)");
     }
     c->boxes.push_back(x);
+    c->boxes.back().zc = nullptr;    // the caller's array is not kept
     BoxDev d;
     d.nx = x.nx;
     d.ny = x.ny;
@@ -553,8 +628,10 @@ int mhd_init(const mhd_params* p, void* hip_stream, mhd_ctx** out) {
     d.dx = x.Lx / x.nx;
     d.dy = x.Ly / x.ny;
     d.dz = x.Lz / x.nz;
-    d.hmin = std::min(d.dx, std::min(d.dy, d.dz));
-    d.hmax = std::max(d.dx, std::max(d.dy, d.dz));
+    d.hmin = std::min(d.dx, std::min(d.dy, dzmin));
+    d.hmax = std::max(d.dx, std::max(d.dy, dzmax));
+    d.stretched = x.zc ? 1 : 0;
+    d.joff = -1;
     if (p->nu_const > 0.0) {
       for (int a = 0; a < 3; ++a) d.lv[a] = d.le[a] = d.hmin;
     } else {
@@ -582,6 +659,34 @@ int mhd_init(const mhd_params* p, void* hip_stream, mhd_ctx** out) {
           const int p = k + dd;
           ztab.push_back(p >= 0 && p < d.nzt ? zwall_coef(t, k, p, d.nzt) : 0.0);
         }
+  }
+  // per-plane z tables of every box (ZJ_*): constants on a uniform axis
+  for (size_t bi = 0; bi < c->h_boxes.size(); ++bi) {
+    BoxDev& d = c->h_boxes[bi];
+    d.joff = (long long)ztab.size();
+    const bool cst = p->nu_const > 0.0;
+    for (int k = 0; k < d.nzt; ++k) {
+      double jc = 1.0 / d.dz, jf = 1.0 / d.dz, dc = d.dz, df = d.dz;
+      if (d.stretched) {
+        // the wall end copy: the up output at the top plane and the down
+        // output at the bottom plane take their neighbour's stencil
+        const int kc = k == d.nzt - 1 ? k - 1 : k, kf = k == 0 ? 1 : k;
+        jc = 1.0 / c->dzc[bi][kc];
+        jf = 1.0 / c->dzf[bi][kf];
+        dc = c->dzc[bi][k];
+        df = c->dzf[bi][k];
+      }
+      double e[ZJ_COUNT];
+      e[ZJ_C] = jc;
+      e[ZJ_F] = jf;
+      e[ZJ_LZZ] = cst ? d.hmin : (d.stretched ? dc : d.lv[2]);
+      e[ZJ_LXZ] = cst ? d.hmin : (d.stretched ? std::max(d.dx, df) : d.le[1]);
+      e[ZJ_LYZ] = cst ? d.hmin : (d.stretched ? std::max(d.dy, df) : d.le[2]);
+      e[ZJ_LZF] = cst ? d.hmin : (d.stretched ? df : d.lv[2]);
+      e[ZJ_H] = cst ? d.hmin : (d.stretched ? std::min(std::min(d.dx, d.dy), dc) : d.hmin);
+      e[ZJ_DZC] = dc;
+      for (int q = 0; q < ZJ_COUNT; ++q) ztab.push_back(e[q]);
+    }
   }
   std::vector<Blk> tab, gtab;
   build_tables(c, tab, gtab);

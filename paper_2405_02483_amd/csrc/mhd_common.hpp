@@ -51,7 +51,21 @@ struct BoxDev {
   // max(dx_a, dx_b); constant viscosity: h_min for all, so that every
   // component is nu_const whatever the cell shape (Section 6.1).
   double lv[3], le[3];
+  // per-plane z table (ZJ_COUNT entries per plane) in the z-coefficient
+  // array, for every box; stretched: a stretched z axis
+  long long joff;
+  int stretched;
 };
+
+// Per-plane z quantities (Section 4.2: derivatives in index space times the
+// Jacobian at the output; uniform boxes hold constants): ZJ_C, ZJ_F the
+// Jacobians of up derivatives (outputs at centres) and down derivatives
+// (outputs on faces), with the wall end copy built in (the end output no
+// stencil reaches takes its neighbour's); ZJ_LZZ nu_zz's length (centre);
+// ZJ_LXZ, ZJ_LYZ the y- and x-edge lengths (face heights); ZJ_LZF the
+// energy diffusion's z length (faces); ZJ_H the shock and Smagorinsky h;
+// ZJ_DZC the centre interval (cell volumes).
+enum ZJ : int { ZJ_C = 0, ZJ_F, ZJ_LZZ, ZJ_LXZ, ZJ_LYZ, ZJ_LZF, ZJ_H, ZJ_DZC, ZJ_COUNT };
 
 // z-stencil coefficient tables of wall-bounded boxes: for operator type
 // ZT_*, output plane k and offset d = p - k in [-3, 3], the coefficient of

@@ -51,6 +51,9 @@ __global__ __launch_bounds__(TX * TY) void zF(const BoxDev* __restrict__ boxes,
   constexpr bool kCori = hasf<FM>(8);
   // div B diffusion (with the B_x launch): x and y strips of div B
   constexpr bool kDB = hasf<FM>(5);
+  // a stretched z axis (bit 9): z derivatives scattered with each output
+  // plane's Jacobian
+  constexpr bool kStr = hasf<FM>(9);
   // only the strips of this launch's fields occupy LDS
   __shared__ T sx[at_least1(strip_slot<FM>(kXOwn, 9)) * PXs::NP];
   __shared__ T sy[at_least1(strip_slot<FM>(kYOwn, 9)) * PYs::NP];
@@ -250,7 +253,7 @@ __global__ __launch_bounds__(TX * TY) void zF(const BoxDev* __restrict__ boxes,
             T w[6];
 #pragma unroll
             for (int m = 0; m < 6; ++m) w[m] = valid(r - 3 + m) ? dbg[col(r - 3 + m)] : T(0);
-            fbz += kd * zwin<1, 0, 6, 3>(w, r, wall, N, g.hzi, zt);
+            fbz += kd * zwin<1, 0, 6, 3>(w, r, wall, N, zj(r, ZJ_F), zt);
           }
           const T F7 = masked(7, r, fbz);
           if (f_out.p[0] == nullptr) du.p[7][o] = F7;
@@ -278,32 +281,46 @@ __global__ __launch_bounds__(TX * TY) void zF(const BoxDev* __restrict__ boxes,
       T dl[7];
 #pragma unroll
       for (int a = 0; a < 7; ++a) {
-        dl[a] = (cur[a] - prev[a]) * g.hzi;
+        dl[a] = kStr ? cur[a] - prev[a] : (cur[a] - prev[a]) * g.hzi;
         prev[a] = cur[a];
       }
-      if (hasf<FM>(0) && cont) zscatter_d<1, 3>(acc[0], kb, -dl[0], wall, N, zt);
+      // Jacobians of the output planes kb..kb+6 (up: centres, dn: faces)
+      T jsc[7], jsf[7];
+      if constexpr (kStr) {
+#pragma unroll
+        for (int s = 0; s < 7; ++s) {
+          jsc[s] = valid(kb + s) ? zj(kb + s, ZJ_C) : T(0);
+          jsf[s] = valid(kb + s) ? zj(kb + s, ZJ_F) : T(0);
+        }
+      }
+      auto scat_up = [&](T (&ac)[7], T dv) {
+        if constexpr (kStr) zscatter_dj<1, 3>(ac, kb, dv, jsc, wall, N, zt);
+        else zscatter_d<1, 3>(ac, kb, dv, wall, N, zt);
+      };
+      if (hasf<FM>(0) && cont) scat_up(acc[0], -dl[0]);
       if (hasf<FM>(1)) {
-        zscatter_d<1, 3>(acc[1], kb, dl[1], wall, N, zt);
+        scat_up(acc[1], dl[1]);
         zscatter<0, 1, 3>(acc[1], kb, lxy * inv_mu, wall, N, zt);
         if constexpr (kCori) zscatter<0, 1, 3>(acc[1], kb, czx, wall, N, zt);
       }
       if (hasf<FM>(2)) {
-        zscatter_d<1, 3>(acc[2], kb, dl[2], wall, N, zt);
+        scat_up(acc[2], dl[2]);
         zscatter<0, 1, 3>(acc[2], kb, -lyx * inv_mu, wall, N, zt);
         if constexpr (kCori) zscatter<0, 1, 3>(acc[2], kb, czy, wall, N, zt);
       }
       if (hasf<FM>(3)) {
-        zscatter_d<0, 3>(acc[3], kb, dl[3], wall, N, zt);
+        if constexpr (kStr) zscatter_dj<0, 3>(acc[3], kb, dl[3], jsf, wall, N, zt);
+        else zscatter_d<0, 3>(acc[3], kb, dl[3], wall, N, zt);
         if (grav) zscatter<0, 0, 3>(acc[3], kb, -rho_o * ph.gz, wall, N, zt);
         if constexpr (kCori) zscatter<0, 0, 3>(acc[3], kb, czz, wall, N, zt);
       }
       if (hasf<FM>(4)) {
-        zscatter_d<1, 3>(acc[4], kb, dl[4], wall, N, zt);
+        scat_up(acc[4], dl[4]);
         zscatter<0, 1, 3>(acc[4], kb, xqy, wall, N, zt);
         zscatter<0, 1, 3>(acc[4], kb, yqx, wall, N, zt);
       }
-      if (hasf<FM>(5)) zscatter_d<1, 3>(acc[5], kb, dl[5], wall, N, zt);
-      if (hasf<FM>(6)) zscatter_d<1, 3>(acc[6], kb, -dl[6], wall, N, zt);
+      if (hasf<FM>(5)) scat_up(acc[5], dl[5]);
+      if (hasf<FM>(6)) scat_up(acc[6], -dl[6]);
     } else {
 #pragma unroll
       for (int a = 0; a < 7; ++a) prev[a] = T(0);
@@ -344,10 +361,20 @@ static void zF_one(const G& grid, dim3 block, const ZLaunch& L, const ZStageArgs
 }
 // The momentum launch's mask with the Coriolis bit (8) set; others unchanged.
 template <unsigned FM> constexpr unsigned with_cori() { return (FM & 0x0Eu) ? (FM | 0x100u) : FM; }
-// one launch per mask, each with its own 8 queue counters
+// one launch per mask, each with its own 8 queue counters; a stretched z
+// axis takes the instantiations with bit 9 (grid mode only)
 template <class T, int TX, int TY, bool PERS, class G, size_t... I>
 static void zF_launch(const G& grid, dim3 block, const ZLaunch& L, const ZStageArgs<T>& a, int* q,
                       std::index_sequence<I...>) {
+  if constexpr (!PERS) {
+    if (L.stretched) {
+      if (a.ph.terms & T_CORI)
+        (zF_one<T, TX, TY, false, with_cori<kFMasks[I]>() | 0x200u>(grid, block, L, a, nullptr), ...);
+      else
+        (zF_one<T, TX, TY, false, kFMasks[I] | 0x200u>(grid, block, L, a, nullptr), ...);
+      return;
+    }
+  }
   if (a.ph.terms & T_CORI)
     (zF_one<T, TX, TY, PERS, with_cori<kFMasks[I]>()>(grid, block, L, a, q ? q + 32 + 8 * int(I) : q), ...);
   else
@@ -368,6 +395,12 @@ static void launch_final_t(const ZLaunch& L, const ZStageArgs<T>& a, int* q) {
 
 template <class T, bool PERS>
 void launch_final(const ZLaunch& L, const ZStageArgs<T>& a, int* q) {
+  if constexpr (PERS) {
+    if (L.stretched) {   // the stretched instantiations run in grid mode
+      launch_final<T, false>(L, a, nullptr);
+      return;
+    }
+  }
   switch (L.ftile) {
     case ZTILE_32x8: launch_final_t<T, 32, 8, PERS>(L, a, q); break;
     case ZTILE_16x16: launch_final_t<T, 16, 16, PERS>(L, a, q); break;

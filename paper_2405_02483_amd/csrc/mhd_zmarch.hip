@@ -126,13 +126,15 @@ __global__ __launch_bounds__(TX * TY) void zA1(const BoxDev* __restrict__ boxes,
         const double v8[8] = {rd, pxd, pyd, pzd, ed, bxd, byd, bzd};
         for (int v = 0; v < 8; ++v) rnf += isfinite(v8[v]) ? 0 : 1;
         if (!(rd > 0.0) || !(ed > 0.0)) ++rnp;
-        rs[0] += rd;
-        rs[1] += pxd;
-        rs[2] += pyd;
-        rs[3] += pzd;
-        rs[4] += 0.5 * (pxd * uxd + pyd * uyd);
-        rs[5] += bxd * bxd + byd * byd + bzd * bzd;
-        rs[6] += ed;
+        // the cell's volume relative to dx dy dz (a stretched z axis)
+        const double wz = b.stretched ? double(zj(r, ZJ_DZC)) / b.dz : 1.0;
+        rs[0] += rd * wz;
+        rs[1] += pxd * wz;
+        rs[2] += pyd * wz;
+        rs[3] += pzd * wz;
+        rs[4] += 0.5 * (pxd * uxd + pyd * uyd) * wz;
+        rs[5] += (bxd * bxd + byd * byd + bzd * bzd) * wz;
+        rs[6] += ed * wz;
         rbm = fmax(rbm, fmax(fabs(bxd), fmax(fabs(byd), fabs(bzd))));
         rum = fmax(rum, fmax(fabs(uxd), fabs(uyd)));
         if (dfdt.p[0]) {
@@ -165,7 +167,7 @@ __global__ __launch_bounds__(TX * TY) void zA1(const BoxDev* __restrict__ boxes,
       uzq = fPZ[0] / zr;
       if (own && q1 >= it.z0 && q1 < it.z1) uz_out[col(q1)] = uzq;
       if (RED && own && q1 >= it.z0 && q1 < it.z1 && interior(q1)) {
-        rs[4] += 0.5 * (double)fPZ[0] * (double)uzq;
+        rs[4] += 0.5 * (double)fPZ[0] * (double)uzq * (b.stretched ? double(zj(q1, ZJ_DZC)) / b.dz : 1.0);
         rum = fmax(rum, fabs((double)uzq));
       }
     }
@@ -174,7 +176,7 @@ __global__ __launch_bounds__(TX * TY) void zA1(const BoxDev* __restrict__ boxes,
     const int q = r - 5;
     if (valid(q) && q >= it.z0 && q < it.z1) {
       const T ubz = zwin<0, 1, 6, 2>(wUZ, q, wall, N, T(0), zt);
-      const T dzz = zwin<1, 1, 6, 2>(wUZ, q, wall, N, g.hzi, zt);
+      const T dzz = zwin<1, 1, 6, 2>(wUZ, q, wall, N, zj(q, ZJ_C), zt);
       const T bbz = zwin<0, 1, 8, 2>(wBZ, q, wall, N, T(0), zt);
       const T rq = wR[0], eq = fE[0];
       const T D = fDXY[0] + dzz;
@@ -187,7 +189,7 @@ __global__ __launch_bounds__(TX * TY) void zA1(const BoxDev* __restrict__ boxes,
         nus = ph.nu_const / g.h;
       } else {
         const T relu = -D > T(0) ? -D : T(0);
-        nus = ph.nu1 * norm3(fUBX[0], fUBY[0], ubz) + ph.nu3 * (cs + ca) + ph.nu2 * g.h * relu;
+        nus = ph.nu1 * norm3(fUBX[0], fUBY[0], ubz) + ph.nu3 * (cs + ca) + ph.nu2 * zj(q, ZJ_H) * relu;
       }
       if (own) {
         const long long o = col(q);
@@ -199,7 +201,7 @@ __global__ __launch_bounds__(TX * TY) void zA1(const BoxDev* __restrict__ boxes,
           ws.q(2)[o] = ubz;
           ws.q(5)[o] = dzz;
         }
-        if (divb) divb_out[o] = fDXB[0] + zwin<1, 1, 8, 2>(wBZ, q, wall, N, g.hzi, zt);
+        if (divb) divb_out[o] = fDXB[0] + zwin<1, 1, 8, 2>(wBZ, q, wall, N, zj(q, ZJ_C), zt);
         if ((cpart || RED) && interior(q)) {
           const double ux_ = fUBX[0], uy_ = fUBY[0], uz_ = ubz;
           const double bx_ = fBBX[0], by_ = fBBY[0], bz_ = bbz, bbd = bb;
@@ -213,7 +215,7 @@ __global__ __launch_bounds__(TX * TY) void zA1(const BoxDev* __restrict__ boxes,
               rc = c_;
               rca = packed(q);
             }
-            const double db = (double)fDXB[0] + (double)zwin<1, 1, 8, 2>(wBZ, q, wall, N, g.hzi, zt);
+            const double db = (double)fDXB[0] + (double)zwin<1, 1, 8, 2>(wBZ, q, wall, N, zj(q, ZJ_C), zt);
             rs[7] += db * db;
             rdiv = fmax(rdiv, fabs(db));
           }
@@ -348,8 +350,8 @@ __global__ __launch_bounds__(TX * TY) void zS(const BoxDev* __restrict__ boxes,
     const int q1 = r - 2;
     T dx_ = T(0), dy_ = T(0);
     if (valid(q1)) {
-      dx_ = zwin<1, 0, 6, 3>(wX, q1, wall, N, g.hzi, zt);
-      dy_ = zwin<1, 0, 6, 3>(wY, q1, wall, N, g.hzi, zt);
+      dx_ = zwin<1, 0, 6, 3>(wX, q1, wall, N, zj(q1, ZJ_F), zt);
+      dy_ = zwin<1, 0, 6, 3>(wY, q1, wall, N, zj(q1, ZJ_F), zt);
     }
     push(wDX, dx_);
     push(wDY, dy_);
@@ -362,7 +364,7 @@ __global__ __launch_bounds__(TX * TY) void zS(const BoxDev* __restrict__ boxes,
       const T s11 = sxx[o], s22 = syy[o], s33 = szz[o], D = Dg[o];
       const T s2 = T(2) * (s11 * s11 + s22 * s22 + s33 * s33 - D * D / T(3) +
                            T(2) * (sxy * sxy + sxz * sxz + syz * syz));
-      nus[o] += ph.c_smag * g.h * (s2 > T(0) ? sqrt(s2) : T(0));
+      nus[o] += ph.c_smag * zj(q, ZJ_H) * (s2 > T(0) ? sqrt(s2) : T(0));
     }
   }
   ZLOOP_END
@@ -623,7 +625,7 @@ __global__ __launch_bounds__(TX * TY) void zQ(const BoxDev* __restrict__ boxes,
       // of a wall axis copies its neighbour's z derivative)
       const unsigned fl = (kE && ws.rgh) ? (unsigned)ws.rgh[o] : 0u;
       auto dz2 = [&](const T (&w)[6]) {
-        return (wall && q == 0) ? (w[4] - w[3]) * g.hzi : (w[3] - w[2]) * g.hzi;
+        return (wall && q == 0) ? (w[4] - w[3]) * zj(q, ZJ_F) : (w[3] - w[2]) * zj(q, ZJ_F);
       };
       auto s_xz = [&](T dzUX, T dxUZ) {
         if (fl & RG_YE) return T(0.5) * (dz2(wUX) + (UZ[P3::at(tx, ty)] - UZ[P3::at(tx - 1, ty)]) * g.hxi);
@@ -637,13 +639,13 @@ __global__ __launch_bounds__(TX * TY) void zQ(const BoxDev* __restrict__ boxes,
       if constexpr (kE && kT) {
         const T dxUZ = op6<1, 0, T>([&](int m) { return UZ[P3::at(tx + m, ty)]; }, g.hxi);
         const T dyUZ = op6<1, 0, T>([&](int m) { return UZ[P3::at(tx, ty + m)]; }, g.hyi);
-        const T sxz = s_xz(zwin<1, 0, 6, 3>(wUX, q, wall, N, g.hzi, zt), dxUZ);
-        const T syz = s_yz(zwin<1, 0, 6, 3>(wUY, q, wall, N, g.hzi, zt), dyUZ);
+        const T sxz = s_xz(zwin<1, 0, 6, 3>(wUX, q, wall, N, zj(q, ZJ_F), zt), dxUZ);
+        const T syz = s_yz(zwin<1, 0, 6, 3>(wUY, q, wall, N, zj(q, ZJ_F), zt), dyUZ);
         if (own) {
           ws.q(TAU_XZ)[o] = zwin<0, 0, 6, 3>(wRX, q, wall, N, T(0), zt) *
-                            (g.lxz * exp(zwin<0, 0, 6, 3>(wLX, q, wall, N, T(0), zt))) * sxz;
+                            (zj(q, ZJ_LXZ) * exp(zwin<0, 0, 6, 3>(wLX, q, wall, N, T(0), zt))) * sxz;
           ws.q(TAU_YZ)[o] = zwin<0, 0, 6, 3>(wRY, q, wall, N, T(0), zt) *
-                            (g.lyz * exp(zwin<0, 0, 6, 3>(wLY, q, wall, N, T(0), zt))) * syz;
+                            (zj(q, ZJ_LYZ) * exp(zwin<0, 0, 6, 3>(wLY, q, wall, N, T(0), zt))) * syz;
         }
       }
       // ---- y-edge
@@ -651,16 +653,16 @@ __global__ __launch_bounds__(TX * TY) void zQ(const BoxDev* __restrict__ boxes,
         const T zRX = zwin<0, 0, 6, 3>(wRX, q, wall, N, T(0), zt);
         const T zPX = zwin<0, 0, 6, 3>(wPX, q, wall, N, T(0), zt);
         const T zUX = zwin<0, 0, 6, 3>(wUX, q, wall, N, T(0), zt);
-        const T dzUX = zwin<1, 0, 6, 3>(wUX, q, wall, N, g.hzi, zt);
+        const T dzUX = zwin<1, 0, 6, 3>(wUX, q, wall, N, zj(q, ZJ_F), zt);
         const T zBX = zwin<0, 0, 6, 3>(wBX, q, wall, N, T(0), zt);
-        const T dzBX = zwin<1, 0, 6, 3>(wBX, q, wall, N, g.hzi, zt);
+        const T dzBX = zwin<1, 0, 6, 3>(wBX, q, wall, N, zj(q, ZJ_F), zt);
         const T xUZ = op6<0, 0, T>([&](int m) { return UZ[P3::at(tx + m, ty)]; }, T(0));
         const T dxUZ = op6<1, 0, T>([&](int m) { return UZ[P3::at(tx + m, ty)]; }, g.hxi);
         const T xBZ = op6<0, 0, T>([&](int m) { return BZ[P3::at(tx + m, ty)]; }, T(0));
         const T dxBZ = op6<1, 0, T>([&](int m) { return BZ[P3::at(tx + m, ty)]; }, g.hxi);
         const T xPZ = op6<0, 0, T>([&](int m) { return PZ[P3::at(tx + m, ty)]; }, T(0));
         T nxz = T(0), txz = T(0), sxz = T(0);
-        if (need_nu) nxz = g.lxz * exp(zwin<0, 0, 6, 3>(wLX, q, wall, N, T(0), zt));
+        if (need_nu) nxz = zj(q, ZJ_LXZ) * exp(zwin<0, 0, 6, 3>(wLX, q, wall, N, T(0), zt));
         if (visc) {
           sxz = s_xz(dzUX, dxUZ);
           txz = tq ? tq[TAU_XZ * ws.stride + o] : zRX * nxz * sxz;
@@ -691,16 +693,16 @@ __global__ __launch_bounds__(TX * TY) void zQ(const BoxDev* __restrict__ boxes,
         const T zRY = zwin<0, 0, 6, 3>(wRY, q, wall, N, T(0), zt);
         const T zPY = zwin<0, 0, 6, 3>(wPY, q, wall, N, T(0), zt);
         const T zUY = zwin<0, 0, 6, 3>(wUY, q, wall, N, T(0), zt);
-        const T dzUY = zwin<1, 0, 6, 3>(wUY, q, wall, N, g.hzi, zt);
+        const T dzUY = zwin<1, 0, 6, 3>(wUY, q, wall, N, zj(q, ZJ_F), zt);
         const T zBY = zwin<0, 0, 6, 3>(wBY, q, wall, N, T(0), zt);
-        const T dzBY = zwin<1, 0, 6, 3>(wBY, q, wall, N, g.hzi, zt);
+        const T dzBY = zwin<1, 0, 6, 3>(wBY, q, wall, N, zj(q, ZJ_F), zt);
         const T yUZ = op6<0, 0, T>([&](int m) { return UZ[P3::at(tx, ty + m)]; }, T(0));
         const T dyUZ = op6<1, 0, T>([&](int m) { return UZ[P3::at(tx, ty + m)]; }, g.hyi);
         const T yBZ = op6<0, 0, T>([&](int m) { return BZ[P3::at(tx, ty + m)]; }, T(0));
         const T dyBZ = op6<1, 0, T>([&](int m) { return BZ[P3::at(tx, ty + m)]; }, g.hyi);
         const T yPZ = op6<0, 0, T>([&](int m) { return PZ[P3::at(tx, ty + m)]; }, T(0));
         T nyz = T(0), tyz = T(0), syz = T(0);
-        if (need_nu) nyz = g.lyz * exp(zwin<0, 0, 6, 3>(wLY, q, wall, N, T(0), zt));
+        if (need_nu) nyz = zj(q, ZJ_LYZ) * exp(zwin<0, 0, 6, 3>(wLY, q, wall, N, T(0), zt));
         if (visc) {
           syz = s_yz(dzUY, dyUZ);
           tyz = tq ? tq[TAU_YZ * ws.stride + o] : zRY * nyz * syz;
@@ -732,9 +734,9 @@ __global__ __launch_bounds__(TX * TY) void zQ(const BoxDev* __restrict__ boxes,
         if (adv) hz = -zwin<0, 0, 6, 3>(wE, q, wall, N, T(0), zt) * wUZ[3];
         if (ediff)
           hz = hz + ph.nuE * zwin<0, 0, 6, 3>(wRho, q, wall, N, T(0), zt) *
-                        (g.lz * zwin<0, 0, 6, 3>(wNu, q, wall, N, T(0), zt)) *
+                        (zj(q, ZJ_LZF) * zwin<0, 0, 6, 3>(wNu, q, wall, N, T(0), zt)) *
                         zwin<0, 0, 6, 3>(wEm, q, wall, N, T(0), zt) *
-                        zwin<1, 0, 6, 3>(wLem, q, wall, N, g.hzi, zt);
+                        zwin<1, 0, 6, 3>(wLem, q, wall, N, zj(q, ZJ_F), zt);
         if (own) {
           ws.q(QOUT_HZ)[o] = hz;
           // pressure gradient on its own: folded into the flux, a pressure
@@ -744,10 +746,10 @@ __global__ __launch_bounds__(TX * TY) void zQ(const BoxDev* __restrict__ boxes,
             if constexpr (kL)
               dpz = exp(zwin<0, 0, 6, 3>(wLpa, q, wall, N, T(0), zt)) *
                     exp(zwin<0, 0, 6, 3>(wLq, q, wall, N, T(0), zt)) *
-                    (zwin<1, 0, 6, 3>(wLq, q, wall, N, g.hzi, zt) +
-                     zwin<1, 0, 6, 3>(wLpa, q, wall, N, g.hzi, zt));
+                    (zwin<1, 0, 6, 3>(wLq, q, wall, N, zj(q, ZJ_F), zt) +
+                     zwin<1, 0, 6, 3>(wLpa, q, wall, N, zj(q, ZJ_F), zt));
             else
-              dpz = ph.gamma1 * zwin<1, 0, 6, 3>(wE, q, wall, N, g.hzi, zt);
+              dpz = ph.gamma1 * zwin<1, 0, 6, 3>(wE, q, wall, N, zj(q, ZJ_F), zt);
           }
           ws.q(QOUT_DPZ)[o] = dpz;
         }
@@ -759,16 +761,17 @@ __global__ __launch_bounds__(TX * TY) void zQ(const BoxDev* __restrict__ boxes,
       const long long o = col(q2);
       // second-order switch at the centre: S_zz and the stress's div u
       const bool o2 = ws.rgh && ((unsigned)ws.rgh[o] & RG_C);
-      const T szz = !o2 ? zwin<1, 1, 6, 2>(wUZ, q2, wall, N, g.hzi, zt)
-                        : ((wall && q2 == N - 1) ? (wUZ[2] - wUZ[1]) * g.hzi : (wUZ[3] - wUZ[2]) * g.hzi);
+      const T jq2 = zj(q2, ZJ_C);
+      const T szz = !o2 ? zwin<1, 1, 6, 2>(wUZ, q2, wall, N, jq2, zt)
+                        : ((wall && q2 == N - 1) ? (wUZ[2] - wUZ[1]) * jq2 : (wUZ[3] - wUZ[2]) * jq2);
       const T Dt = o2 ? ws.arr(WS_D2)[o] : Dg[o];
       if constexpr (kT) {
-        if (own) ws.q(TAU_ZZ)[o] = wRho[2] * (g.lz * wNu[2]) * (szz + ph.c1 * Dt);
+        if (own) ws.q(TAU_ZZ)[o] = wRho[2] * (zj(q2, ZJ_LZZ) * wNu[2]) * (szz + ph.c1 * Dt);
         continue;
       }
       T gzz = T(0), czz = T(0);
       if (visc) {
-        const T tzz = tq ? tq[TAU_ZZ * ws.stride + o] : wRho[2] * (g.lz * wNu[2]) * (szz + ph.c1 * Dt);
+        const T tzz = tq ? tq[TAU_ZZ * ws.stride + o] : wRho[2] * (zj(q2, ZJ_LZZ) * wNu[2]) * (szz + ph.c1 * Dt);
         gzz = tzz;
         czz = tzz * szz;
       }
@@ -864,7 +867,7 @@ __global__ __launch_bounds__(TX * TY) void zP(const BoxDev* __restrict__ boxes,
       fl = (unsigned)ws.rgh[o];
       const int kp = (wall && k == N - 1) ? k - 1 : k;
       D2 = (S(DQ_UX, x + 1, y) - S(DQ_UX, x, y)) * g.hxi + (S(DQ_UY, x, y + 1) - S(DQ_UY, x, y)) * g.hyi +
-           (uzg[col(kp + 1)] - uzg[col(kp)]) * g.hzi;
+           (uzg[col(kp + 1)] - uzg[col(kp)]) * zj(k, ZJ_C);
       ws.arr(WS_D2)[o] = D2;
     }
     if constexpr (TAU) {

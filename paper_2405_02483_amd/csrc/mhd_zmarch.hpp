@@ -172,6 +172,25 @@ __device__ __forceinline__ void zscatter_d(T (&acc)[7], int kbase, T dv, bool wa
   }
 }
 
+// The same on a stretched z axis: dv without the 1/h, each output plane's
+// share times that plane's Jacobian js[s] (derivatives in index space times
+// the Jacobian at the output).
+template <int FORM, int PK, class T>
+__device__ __forceinline__ void zscatter_dj(T (&acc)[7], int kbase, T dv, const T (&js)[7], bool wall, int N,
+                                            const T* __restrict__ zt) {
+  if (!wall || (kbase >= 3 && kbase + 6 <= N - 4)) {
+#pragma unroll
+    for (int s = 0; s < 7; ++s) acc[s] += zdcoef6<FORM, T>(PK - s) * dv * js[s];
+    return;
+  }
+  constexpr int type = FORM ? ZT_DDUP : ZT_DDDN;
+#pragma unroll
+  for (int s = 0; s < 7; ++s) {
+    const int k = kbase + s;
+    if (k >= 0 && k < N) acc[s] += zt[((long long)type * N + k) * 7 + PK - s + 3] * dv * js[s];
+  }
+}
+
 // Tile plane in LDS: (TX + 2HX) x (TY + 2HY) values of one plane, element
 // (x, y) of the tile (x in -HX .. TX+HX-1, y in -HY .. TY+HY-1) at
 // (y + HY) * W + (x + HX).

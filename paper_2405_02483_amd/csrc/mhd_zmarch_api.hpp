@@ -87,6 +87,7 @@ struct ZLaunch {
   int persistent;         // 0: one workgroup per item; 1: item queues
   int ncu;                // compute units of the device
   int nbox, nplanes;      // boxes; z planes of all boxes
+  int stretched;          // some box has a stretched z axis (pass F's STR instantiation)
   hipStream_t stream;
   void (*mark)(void*, int);
   void* mark_ctx;

@@ -34,7 +34,10 @@ namespace smhd {
   auto col = [&](int r_) { return colo + (long long)kk(r_) * pstride; };      \
   auto interior = [&](int r_) { return !wall || (r_ >= b.g0 && r_ < b.g1); };       \
   const T* __restrict__ zt = wall ? ztab + b.zoff : nullptr;                         \
-  (void)zt;
+  (void)zt;                                                                          \
+  const T* __restrict__ zj_ = ztab + b.joff;                                         \
+  auto zj = [&](int r_, int e_) { return zj_[(long long)kk(r_) * ZJ_COUNT + e_]; };  \
+  (void)zj;
 
 #define ZLOOP_END }
 

@@ -47,7 +47,8 @@ T_ORDER2 = 1 << 17   # second-order strain where the state is rough; not part of
 class MhdBox(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
                 ("ngz", ctypes.c_int32), ("bc_z", ctypes.c_int32), ("reserved", ctypes.c_int32),
-                ("Lx", ctypes.c_double), ("Ly", ctypes.c_double), ("Lz", ctypes.c_double)]
+                ("Lx", ctypes.c_double), ("Ly", ctypes.c_double), ("Lz", ctypes.c_double),
+                ("zc", ctypes.POINTER(ctypes.c_double))]
 
 
 class MhdParams(ctypes.Structure):
@@ -310,7 +311,8 @@ _PARAM_KEYS = ("gamma", "mu", "gz", "nu1", "nu2", "nu3", "nu_const", "c1", "nuE"
 
 class Context:
     """Owns one mhd_ctx.  ``boxes``: list of dicts with nx, ny, nz, ngz,
-    wall (bool), Lx, Ly, Lz; ``params``: dict of physical parameters (the
+    wall (bool), Lx, Ly, Lz and, for a stretched z, zc (the nz + 2 ngz
+    cell-centre heights); ``params``: dict of physical parameters (the
     fields of mhd_params by name, ``terms`` for the term bits, and e_cool,
     t_cool, rho_cool, cool_cut for Newtonian cooling with T_COOL, omega
     (3 values) for the Coriolis force with T_CORI, c_divb for the div B
@@ -326,12 +328,18 @@ class Context:
         self.device = torch.device(device)
         self.boxes = [dict(b) for b in boxes]
         arr = (MhdBox * len(boxes))()
+        self._zc_c = []
         for a, b in zip(arr, boxes):
             a.nx, a.ny, a.nz = b["nx"], b["ny"], b["nz"]
             a.ngz = b.get("ngz", 0)
             a.bc_z = MHD_BC_WALL if b.get("wall", False) else MHD_BC_PERIODIC
             a.reserved = 0
             a.Lx, a.Ly, a.Lz = b.get("Lx", 1.0), b.get("Ly", 1.0), b.get("Lz", 1.0)
+            zc = b.get("zc")
+            if zc is not None:      # stretched z: the cell-centre heights
+                zarr = (ctypes.c_double * len(zc))(*[float(v) for v in zc])
+                self._zc_c.append(zarr)
+                a.zc = ctypes.cast(zarr, ctypes.POINTER(ctypes.c_double))
         self._boxes_c = arr
         p = MhdParams()
         p.dtype = MHD_F32 if dtype == torch.float32 else MHD_F64

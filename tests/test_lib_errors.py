@@ -10,10 +10,15 @@ from paper_2405_02483_amd import lib
 def _params(**over):
     boxes = over.pop("boxes", [dict(nx=8, ny=8, nz=8, ngz=0, bc_z=0)])
     arr = (lib.MhdBox * len(boxes))()
+    keep = [arr]
     for a, b in zip(arr, boxes):
         a.nx, a.ny, a.nz = b["nx"], b["ny"], b["nz"]
         a.ngz, a.bc_z, a.reserved = b.get("ngz", 0), b.get("bc_z", 0), b.get("reserved", 0)
         a.Lx = a.Ly = a.Lz = b.get("L", 1.0)
+        if "zc" in b:
+            zarr = (ctypes.c_double * len(b["zc"]))(*b["zc"])
+            keep.append(zarr)
+            a.zc = ctypes.cast(zarr, ctypes.POINTER(ctypes.c_double))
     p = lib.MhdParams()
     p.dtype = over.pop("dtype", lib.MHD_F64)
     p.nbox = over.pop("nbox", len(boxes))
@@ -29,7 +34,7 @@ def _params(**over):
             setattr(p, k, v)
     p.terms = vals.get("terms", lib.T_ALL)
     p.reserved = vals.get("reserved", 0)
-    return p, arr
+    return p, keep
 
 
 @pytest.mark.parametrize("over,code", [
@@ -60,6 +65,12 @@ def _params(**over):
     (dict(boxes=[dict(nx=8, ny=8, nz=6, ngz=7, bc_z=1)]), lib.MHD_EINVAL),
     (dict(boxes=[dict(nx=8, ny=8, nz=8, bc_z=3)]), lib.MHD_EINVAL),
     (dict(boxes=[dict(nx=8, ny=8, nz=8, L=0.0)]), lib.MHD_EINVAL),
+    # a stretched z axis needs walls and increasing heights
+    (dict(boxes=[dict(nx=8, ny=8, nz=8, zc=[0.1 * k for k in range(8)])]), lib.MHD_EINVAL),
+    (dict(boxes=[dict(nx=8, ny=8, nz=8, ngz=5, bc_z=1, zc=[0.1 * k * (-1) ** k for k in range(18)])]),
+     lib.MHD_EINVAL),
+    (dict(boxes=[dict(nx=8, ny=8, nz=8, ngz=5, bc_z=1, zc=[0.1 * k for k in range(17)] + [float("nan")])]),
+     lib.MHD_EINVAL),
     (dict(boxes=[dict(nx=1300, ny=1300, nz=1300)]), lib.MHD_EINVAL),   # >= 2^31 cells
 ])
 def test_init_rejects_bad_arguments(over, code):
