@@ -139,3 +139,33 @@ def test_final_pass_tile_gives_identical_bits(dtype):
             ctx.set_final_tile(bad)
         assert ei.value.code == MHD_EINVAL
     ctx.close()
+
+
+def test_benchmark_ensemble_boxes_match_oracle():
+    """The bench's 96-box float32 ensemble (24 each of 48^3, 64^3, 80^3,
+    96^3, turbulent, seeds 5000 + b) in its autotuned launch: one RK step
+    with the Courant dt taken on the device, then the first 48^3 and the
+    first 96^3 box against the oracle's step of that box alone (<= 1e-5
+    relative L2 per field)."""
+    import math
+    from paper_2405_02483_amd.lib import Context
+    cases, prm = inputs.ensemble()
+    sizes = [c[1]["nx"] for c in cases]
+    ctx = Context([c[1] for c in cases], prm, dtype=torch.float32)
+    fd = ctx.upload([c[0] for c in cases])
+    ctx.autotune(fd, reps=2)
+    print("launch", ctx.get_launch(), "pass F", ctx.get_final_tile())
+    fd = ctx.upload([c[0] for c in cases])
+    ctx.step(fd, 0.0, 1)
+    dt = ctx.last_dt()
+    want_dt = min(O.courant(to_cpu64(f), *grid_params(b, prm))[0] for f, b in cases)
+    assert math.isclose(dt, want_dt, rel_tol=1e-6), (dt, want_dt)
+    for n in (48, 96):
+        b = sizes.index(n)
+        f, box = cases[b]
+        g, p = grid_params(box, prm)
+        want = O.step(to_cpu64(f), g, p, dt, 1)
+        errs = rel_errors(ctx.box_view(fd, b), want)
+        print(n, b, ["%.1e" % e for e in errs])
+        assert max(errs) < 1e-5, (n, b, errs)
+    ctx.close()
