@@ -87,20 +87,19 @@ enum {
 /* With MHD_T_EDIFF: energy diffusion of the fluctuations about the
  * horizontal mean (eq. ediffav): the z flux differentiates
  * ln e_m - ln <e_m>, <e_m> the mean of e_m over each z plane of the box
- * (ghost planes included, as filled).  Not part of MHD_T_ALL; the adjoint
- * entry points return MHD_EUNSUPPORTED with it.                            */
+ * (ghost planes included, as filled).  Not part of MHD_T_ALL.              */
 #define MHD_T_EDIFFAV  (1u << 11)
 /* With MHD_T_PRES: grad P in the momentum equation through
  * q = ln(P / P_aver), P_aver the mean of P over each z plane of the box
  * (eq. pressure): on a face f of axis a, exp(adn(ln P_aver)) exp(adn(q))
  * (ddadn(q) + ddadn(ln P_aver)).  Exact for an exponential atmosphere.  Not
- * part of MHD_T_ALL; the adjoint entry points return MHD_EUNSUPPORTED.   */
+ * part of MHD_T_ALL.                                                       */
 #define MHD_T_LNP      (1u << 12)
 /* div B diffusion: c_divb min(dx, dy, dz)^2 / dt grad(div B) added to the
  * rate of B, div B at cell centres from the up derivatives, its gradient on
  * the faces from the down derivatives.  It needs the step's dt, so
- * mhd_step includes it and mhd_rhs (no dt) leaves it out.  Not part of
- * MHD_T_ALL; the adjoint entry points return MHD_EUNSUPPORTED.             */
+ * mhd_step and mhd_step_adjoint include it, mhd_rhs and mhd_rhs_adjoint
+ * (no dt) leave it out.  Not part of MHD_T_ALL.                            */
 #define MHD_T_DIVB     (1u << 13)
 /* Smagorinsky viscosity (eq. nusmag): the rate nu_S = c_smag [2(sum_i S_ii^2
  * - (div u)^2/3 + sum_{i!=j} S_ij^2)]^(1/2), off-diagonal strain
@@ -275,7 +274,9 @@ int mhd_step(mhd_ctx* ctx, void* const f[8], void* const tmp1[8],
  * gbar_out = (d f_{n+1} / d f_n)^T gbar_in, evaluated at the state f_n.
  * Non-smooth points use: max over three cells routes to the first maximal
  * cell (order i-1, i, i+1; passes along x, then y, then z); max(0, x), |v|
- * and the viscosity floor have zero derivative on their flat side.
+ * and the viscosity floor have zero derivative on their flat side.  Every
+ * term bit is differentiated, the plane means of MHD_T_EDIFFAV and
+ * MHD_T_LNP included (each mean depends on every cell of its plane).
  * Periodic boxes only (MHD_EUNSUPPORTED with walls).  dt must be finite and
  * > 0 (MHD_EINVAL otherwise: the Courant step of mhd_step's dt == 0 is not
  * differentiated).  f_n is not modified; gbar_in and gbar_out must not

@@ -98,6 +98,7 @@ struct Builder {
     return emit(V_ROUGH, lnr, lne, ZERO, lim, G_ONE, kind, 0, 0);
   }
   int sel(int a, int b, int m) { return emit(V_SEL, a, b, m, 0.0, G_ONE, 0, 0, 0); }
+  int pmean(int a) { return emit(V_PMEAN, a, ZERO, ZERO, 0.0, G_ONE, 0, 0, 0); }
 };
 
 // Drops instructions whose results never reach an output, renumbers slots
@@ -142,7 +143,7 @@ VProgram finish(Builder& B, int out[8]) {
 
 }  // namespace
 
-VProgram build_rhs_program(const mhd_params& p) {
+VProgram build_rhs_program(const mhd_params& p, double dt) {
   Builder B;
   const unsigned T = p.terms;
   const int rho = 0, px = 1, py = 2, pz = 3, e = 4, bx = 5, by = 6, bz = 7;
@@ -273,9 +274,23 @@ VProgram build_rhs_program(const mhd_params& p) {
                            B.ddyup(B.mul(B.ydn(pz), B.zdn(uy)))));
   }
   if (T & MHD_T_PRES) {
-    dpx = B.sub(dpx, B.ddxdn(P));
-    dpy = B.sub(dpy, B.ddydn(P));
-    dpz = B.sub(dpz, B.ddzdn(P));
+    if (T & MHD_T_LNP) {
+      // eq. pressure: exp(adn ln P_aver) exp(adn q) (ddadn q + ddadn ln P_aver),
+      // q = ln(P / P_aver), P_aver the mean of P over each z plane
+      const int lpa = B.flog(B.pmean(P));
+      const int q = B.sub(B.flog(P), lpa);
+      auto g = [&](int ax) {
+        return B.mul(B.mul(B.fexp(B.st(lpa, ax, 0, 0)), B.fexp(B.st(q, ax, 0, 0))),
+                     B.add(B.st(q, ax, 1, 0), B.st(lpa, ax, 1, 0)));
+      };
+      dpx = B.sub(dpx, g(VX));
+      dpy = B.sub(dpy, g(VY));
+      dpz = B.sub(dpz, g(VZ));
+    } else {
+      dpx = B.sub(dpx, B.ddxdn(P));
+      dpy = B.sub(dpy, B.ddydn(P));
+      dpz = B.sub(dpz, B.ddzdn(P));
+    }
   }
   if (T & MHD_T_LORENTZ) {
     dpx = B.add(dpx, B.divc(B.sub(B.zup(B.mul(jy, B.xdn(bz))), B.yup(B.mul(jz, B.xdn(by)))), p.mu));
@@ -323,8 +338,10 @@ VProgram build_rhs_program(const mhd_params& p) {
                          B.ddxdn(lne));
     const int fy = B.mul(B.mul(B.mul(B.scale(B.ydn(rho), p.nuE), B.scale(B.ydn(nt), 1.0, G_LY)), B.ydn(em)),
                          B.ddydn(lne));
+    // eq. ediffav: the z flux differentiates ln e_m - ln <e_m>_horiz
+    const int lnez = (T & MHD_T_EDIFFAV) ? B.sub(lne, B.flog(B.pmean(em))) : lne;
     const int fz = B.mul(B.mul(B.mul(B.scale(B.zdn(rho), p.nuE), B.scale(B.zdn(nt), 1.0, G_LZ)), B.zdn(em)),
-                         B.ddzdn(lne));
+                         B.ddzdn(lnez));
     de = B.add(B.add(B.add(de, B.ddxup(fx)), B.ddyup(fy)), B.ddzup(fz));
   }
   // Newtonian cooling (eq. NewtonCool, eq. rhocool)
@@ -340,9 +357,17 @@ VProgram build_rhs_program(const mhd_params& p) {
   }
 
   // induction (eq. indu)
-  const int dbx = B.neg(B.sub(B.ddyup(ez), B.ddzup(ey)));
-  const int dby = B.neg(B.sub(B.ddzup(ex), B.ddxup(ez)));
-  const int dbz = B.neg(B.sub(B.ddxup(ey), B.ddyup(ex)));
+  int dbx = B.neg(B.sub(B.ddyup(ez), B.ddzup(ey)));
+  int dby = B.neg(B.sub(B.ddzup(ex), B.ddxup(ez)));
+  int dbz = B.neg(B.sub(B.ddxup(ey), B.ddyup(ex)));
+  // div B diffusion c_divb h_min^2 / dt grad(div B), with the step's dt
+  if ((T & MHD_T_DIVB) && dt > 0.0) {
+    const int divb = B.add(B.add(B.ddxup(bx), B.ddyup(by)), B.ddzup(bz));
+    auto kd = [&](int a) { return B.scale(B.scale(a, p.c_divb / dt, G_H), 1.0, G_H); };
+    dbx = B.add(dbx, kd(B.ddxdn(divb)));
+    dby = B.add(dby, kd(B.ddydn(divb)));
+    dbz = B.add(dbz, kd(B.ddzdn(divb)));
+  }
 
   int out[8] = {drho, dpx, dpy, dpz, de, dbx, dby, dbz};
   return finish(B, out);
@@ -380,13 +405,15 @@ VPlan plan_program(const VProgram& P) {
   std::vector<int> gid(n), gend;
   for (int q = 0; q < n; ++q) {
     const VInstr& I = P.code[q];
-    const bool nb = I.op == V_STEN || I.op == V_MAX3 || I.op == V_MEAN3 || I.op == V_D2 || I.op == V_ROUGH;
+    const bool nb = I.op == V_STEN || I.op == V_MAX3 || I.op == V_MEAN3 || I.op == V_D2 || I.op == V_ROUGH ||
+                    I.op == V_PMEAN;
     const bool dep = nb && !R.groups.empty() &&
                      (prod[I.a] >= R.groups.back().first ||
                       (I.op == V_ROUGH && prod[I.b] >= R.groups.back().first));
     // the mask runs in a launch of its own (k_vm_rough): its eight-cell
     // gathers would size the registers of every group's launch
-    const bool alone = I.op == V_ROUGH || (q > 0 && P.code[q - 1].op == V_ROUGH);
+    const bool alone = I.op == V_ROUGH || I.op == V_PMEAN ||
+                       (q > 0 && (P.code[q - 1].op == V_ROUGH || P.code[q - 1].op == V_PMEAN));
     if (q == 0 || dep || alone || q - R.groups.back().first == kGroupMax) {
       if (!R.groups.empty()) gend.push_back(q);
       R.groups.push_back({q, 0});
@@ -460,7 +487,10 @@ VPlan plan_program(const VProgram& P) {
     if (I.op == V_FILL) continue;
     const bool nb = I.op == V_STEN || I.op == V_MAX3 || I.op == V_MEAN3 || I.op == V_D2;
     const bool dep = nb && !R.bgroups.empty() && contrib[I.out] >= R.bgroups.back().first;
-    if (R.bgroups.empty() || dep || (int)border.size() - R.bgroups.back().first == kBGroupMax)
+    // a plane mean's transpose runs in launches of its own (a plane sum of
+    // the cotangent, then its broadcast)
+    const bool alone = I.op == V_PMEAN || (!border.empty() && P.code[border.back()].op == V_PMEAN);
+    if (R.bgroups.empty() || dep || alone || (int)border.size() - R.bgroups.back().first == kBGroupMax)
       R.bgroups.push_back({(int)border.size(), 0});
     R.bgroups.back().count++;
     for (int x : {I.a, I.b, I.c})
@@ -986,12 +1016,57 @@ __global__ __launch_bounds__(kBlock) void k_vm_rough(const BoxDev* boxes, const 
       rough_at(base + I.a * stride, base + I.b * stride, g, i, j, k, T(I.k), I.ax) ? T(1) : T(0);
 }
 
+// V_PMEAN: the mean of src over each z plane of every box, in float64 and a
+// fixed order (one workgroup per plane), then its broadcast over the plane
+// into dst (overwriting, or added with over = 0).
+constexpr int kPlaneBlock = 256;
+template <class T>
+__global__ __launch_bounds__(kPlaneBlock) void k_vm_psum(const BoxDev* __restrict__ boxes, int nbox,
+                                                        const T* __restrict__ src, double* __restrict__ pm) {
+  __shared__ double sh[kPlaneBlock];
+  const int P = (int)blockIdx.x;
+  int bi = 0;
+  while (bi + 1 < nbox && boxes[bi + 1].poff <= P) ++bi;
+  const BoxDev& b = boxes[bi];
+  const int n = b.nx * b.ny;
+  const T* __restrict__ s = src + b.off + (long long)(P - b.poff) * n;
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += kPlaneBlock) acc += (double)s[i];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = kPlaneBlock / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) pm[P] = sh[0] / (double)n;
+}
+
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_vm_pbcast(const BoxDev* boxes, const Blk* tab,
+                                                      const double* __restrict__ pm, T* dst, int over) {
+  VM_PROLOGUE
+  int i, j, k;
+  coords(i, j, k);
+  const T v = T(pm[bx_.poff + k]);
+  dst[o] = over ? v : dst[o] + v;
+}
+
+template <class T>
+static void vm_pmean(const VLaunch& L, const T* src, T* dst, int over) {
+  hipLaunchKernelGGL(k_vm_psum<T>, dim3(L.nplanes), dim3(kPlaneBlock), 0, L.stream, L.boxes, L.nbox, src, L.pm);
+  hipLaunchKernelGGL(k_vm_pbcast<T>, dim3(L.nblk), dim3(kBlock), 0, L.stream, L.boxes, L.tab,
+                     (const double*)L.pm, dst, over);
+}
+
 template <class T>
 void vm_forward(const VLaunch& L, const VPlan& P, const VFused* d_fused, T* base, long long stride) {
   for (const VGroup& G : P.groups) {
-    if (P.fused[G.first].f.op == V_ROUGH)
+    const VInstr& I = P.fused[G.first].f;
+    if (I.op == V_ROUGH)
       hipLaunchKernelGGL(k_vm_rough<T>, dim3(L.nblk), dim3(kBlock), 0, L.stream, L.boxes, L.tab, d_fused,
                          G.first, base, stride);
+    else if (I.op == V_PMEAN)
+      vm_pmean<T>(L, base + I.a * stride, base + I.out * stride, 1);
     else
       hipLaunchKernelGGL(k_vm_group<T>, dim3(L.nblk), dim3(kBlock), 0, L.stream, L.boxes, L.tab, d_fused,
                          G.first, G.count, base, stride);
@@ -1002,9 +1077,15 @@ template <class T>
 void vm_backward(const VLaunch& L, const VPlan& P, const VStep* d_bsteps, const T* base, T* cbase,
                  long long stride) {
   const int grid = (L.nblk + kBwdCells - 1) / kBwdCells;
-  for (const VGroup& G : P.bgroups)
+  for (const VGroup& G : P.bgroups) {
+    const VStep& S = P.bsteps[G.first];
+    if (S.f.op == V_PMEAN) {
+      vm_pmean<T>(L, (const T*)(cbase + S.cout * stride), cbase + S.ca * stride, S.over & 1);
+      continue;
+    }
     hipLaunchKernelGGL(k_vm_bwd<T>, dim3(grid), dim3(kBlock), 0, L.stream, L.boxes, L.tab, L.nblk,
                        d_bsteps, G.first, G.count, base, cbase, stride);
+  }
 }
 
 template <class T> void vm_axpby8(const VLaunch& L, P8<T> y, CP8<T> x, double a, double b) {

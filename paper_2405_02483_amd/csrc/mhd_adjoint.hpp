@@ -42,6 +42,8 @@ enum VOp : int {
                 //   3 z-edge) has a second difference of a (ln rho) or b (ln e_m)
                 //   above k, else 0 (a mask: no derivative)
   V_SEL,        // out = c > 1/2 ? b : a
+  V_PMEAN,      // out = the mean of a over its z plane (of its box), at every
+                //   cell of the plane (symmetric: its own transpose)
   V_COUNT
 };
 
@@ -67,7 +69,8 @@ struct VProgram {
   int out[8];
 };
 
-VProgram build_rhs_program(const mhd_params& p);
+// dt: the step's (the div B diffusion's coefficient); 0 leaves that term out
+VProgram build_rhs_program(const mhd_params& p, double dt = 0.0);
 
 // A program with storage assigned.  Forward values that no transpose reads
 // share slots once their last reader has run; cotangents are allocated over
@@ -118,6 +121,8 @@ struct VLaunch {
   const Blk* tab;
   int nblk;
   hipStream_t stream;
+  int nbox, nplanes;      // boxes; z planes of all boxes (BoxDev::poff)
+  double* pm;             // nplanes values: plane means (V_PMEAN)
 };
 
 // Forward: value slots base + s * stride (slots 0..7 filled by the caller);

@@ -43,6 +43,8 @@ struct mhd_ctx {
   void* adj = nullptr;             // adjoint workspace (allocated on first use)
   size_t adj_bytes = 0;
   VPlan* prog = nullptr;           // the right-hand side as a program (adjoint)
+  double prog_dt = 0.0;            // the dt it was built for (div B diffusion; 0: without)
+  double* d_pm = nullptr;          // plane means of the program (V_PMEAN), per plane
   VFused* d_fused = nullptr;       // prog->fused in device memory
   VStep* d_bsteps = nullptr;       // prog->bsteps in device memory
   // z-march stage kernels: work items, tile shape, Courant partials, dt
@@ -498,6 +500,7 @@ void mhd_destroy(mhd_ctx* c) {
   (void)hipFree(c->d_tot);
   (void)hipFree(c->adj);
   delete c->prog;
+  (void)hipFree(c->d_pm);
   (void)hipFree(c->d_fused);
   (void)hipFree(c->d_bsteps);
   (void)hipFree(c->d_items);
@@ -817,12 +820,24 @@ static int do_step(mhd_ctx* c, void* const f[8], void* const t1[8], void* const 
   return check_launch(c, "mhd_step launch");
 }
 
-// The right-hand side as a planned program (built once per context).
-static int ensure_program(mhd_ctx* c) {
-  if (c->prog) return MHD_OK;
+// The right-hand side as a planned program, built once per context, and
+// again when the div B diffusion's dt changes (dt 0: without that term).
+static int ensure_program(mhd_ctx* c, double dt) {
+  if (!(c->p.terms & MHD_T_DIVB)) dt = 0.0;
+  if (c->prog && c->prog_dt == dt) return MHD_OK;
+  if (c->prog) {
+    delete c->prog;
+    c->prog = nullptr;
+    (void)hipFree(c->d_fused);
+    (void)hipFree(c->d_bsteps);
+    c->d_fused = nullptr;
+    c->d_bsteps = nullptr;
+  }
+  if (!c->d_pm && hipMalloc(&c->d_pm, sizeof(double) * std::max(1, c->nplanes)) != hipSuccess)
+    return fail(c, MHD_ENOMEM, "adjoint plane means");
   VPlan* P = nullptr;
   try {
-    P = new VPlan(plan_program(build_rhs_program(c->p)));
+    P = new VPlan(plan_program(build_rhs_program(c->p, dt)));
   } catch (...) {
     return fail(c, MHD_ENOMEM, "adjoint program");
   }
@@ -840,6 +855,7 @@ static int ensure_program(mhd_ctx* c) {
     return fail(c, MHD_ENOMEM, "adjoint program upload");
   }
   c->prog = P;
+  c->prog_dt = dt;
   return MHD_OK;
 }
 
@@ -854,7 +870,7 @@ static int ensure_program(mhd_ctx* c) {
 template <class T>
 static int do_adjoint(mhd_ctx* c, void* const fn[8], double dt, void* const gin[8],
                       void* const gout[8]) {
-  if (int rc = ensure_program(c)) return rc;
+  if (int rc = ensure_program(c, dt)) return rc;
   const VPlan& P = *c->prog;
   const long long n = c->nelem;
   const size_t narr = (size_t)P.nval + P.ncot + 25;
@@ -894,7 +910,7 @@ static int do_adjoint(mhd_ctx* c, void* const fn[8], double dt, void* const gin[
     launch_zstage<T>(Z, a);
   }
   L.at(PASS_ADJOINT);
-  VLaunch V{c->d_boxes, c->d_tab, c->nblk, c->stream};
+  VLaunch V{c->d_boxes, c->d_tab, c->nblk, c->stream, (int)c->h_boxes.size(), c->nplanes, c->d_pm};
   hipError_t e = hipMemsetAsync(zeros, 0, bytes, c->stream);
   for (int v = 0; v < 8 && e == hipSuccess; ++v)
     e = hipMemcpyAsync(G.p[v], gin[v], bytes, hipMemcpyDeviceToDevice, c->stream);
@@ -929,7 +945,7 @@ static int do_adjoint(mhd_ctx* c, void* const fn[8], double dt, void* const gin[
 template <class T>
 static int do_rhs_adjoint(mhd_ctx* c, void* const f[8], void* const wbar[8],
                           void* const fbar[8]) {
-  if (int rc = ensure_program(c)) return rc;
+  if (int rc = ensure_program(c, 0.0)) return rc;
   const VPlan& P = *c->prog;
   const long long n = c->nelem;
   const size_t need = ((size_t)P.nval + P.ncot + 25) * (size_t)n * c->esize;
@@ -945,7 +961,7 @@ static int do_rhs_adjoint(mhd_ctx* c, void* const f[8], void* const wbar[8],
   const size_t bytes = (size_t)n * c->esize;
   const Launch L = make_launch(c);
   L.at(PASS_ADJOINT);
-  VLaunch V{c->d_boxes, c->d_tab, c->nblk, c->stream};
+  VLaunch V{c->d_boxes, c->d_tab, c->nblk, c->stream, (int)c->h_boxes.size(), c->nplanes, c->d_pm};
   hipError_t e = hipSuccess;
   for (int v = 0; v < 8 && e == hipSuccess; ++v)
     e = hipMemcpyAsync(base + (long long)v * n, f[v], bytes, hipMemcpyDeviceToDevice, c->stream);
@@ -1119,8 +1135,6 @@ int mhd_step_adjoint(mhd_ctx* c, void* const f_n[8], double dt, void* const gin[
     return rc;
   for (const auto& b : c->boxes)
     if (b.bc_z != MHD_BC_PERIODIC) return fail(c, MHD_EUNSUPPORTED, "adjoint supports periodic boxes only");
-  if (c->p.terms & (MHD_T_EDIFFAV | MHD_T_LNP | MHD_T_DIVB))
-    return fail(c, MHD_EUNSUPPORTED, "adjoint without MHD_T_EDIFFAV, MHD_T_LNP and MHD_T_DIVB only");
   if (!std::isfinite(dt) || !(dt > 0.0)) return fail(c, MHD_EINVAL, "dt must be finite and > 0");
   for (int a = 0; a < 8; ++a)
     for (int b = 0; b < 8; ++b)
@@ -1136,8 +1150,6 @@ int mhd_rhs_adjoint(mhd_ctx* c, void* const f[8], void* const wbar[8], void* con
     return rc;
   for (const auto& b : c->boxes)
     if (b.bc_z != MHD_BC_PERIODIC) return fail(c, MHD_EUNSUPPORTED, "adjoint supports periodic boxes only");
-  if (c->p.terms & (MHD_T_EDIFFAV | MHD_T_LNP | MHD_T_DIVB))
-    return fail(c, MHD_EUNSUPPORTED, "adjoint without MHD_T_EDIFFAV, MHD_T_LNP and MHD_T_DIVB only");
   for (int a = 0; a < 8; ++a)
     for (int b = 0; b < 8; ++b)
       if (fbar[b] == f[a] || fbar[b] == wbar[a]) return fail(c, MHD_EINVAL, "fbar overlaps an input");

@@ -349,3 +349,89 @@ def test_energy_gradient_128_cubed_40_steps():
           % (ndir, worst[torch.float32], worst[torch.float64], l2))
     assert worst[torch.float64] <= 1e-4, worst
     assert worst[torch.float32] <= 5e-4 and l2 <= 2e-4, (worst, l2)
+
+
+def _plane_terms(name):
+    """Term sets with the plane means (eq. ediffav, eq. pressure) and the
+    div B diffusion; c_divb below the RK3 limit of the cells used here."""
+    extra = {"ediffav": O.T_EDIFFAV, "lnp": O.T_LNP, "divb": O.T_DIVB,
+             "all3": O.T_EDIFFAV | O.T_LNP | O.T_DIVB}[name]
+    return dict(terms=O.T_ALL | extra, c_divb=0.08)
+
+
+@pytest.mark.parametrize("name", ["ediffav", "lnp", "divb", "all3"])
+def test_step_adjoint_plane_means_and_divb_f64(name):
+    """Each plane mean depends on every cell of its plane: the transpose
+    sums the cotangent over the plane and spreads it back."""
+    f, box, prm = _ragged()
+    errs = _adjoint_vs_oracle(f, box, prm, seed=31, **_plane_terms(name))
+    print(name, ["%.2e" % e for e in errs])
+    assert max(errs) < TOL_ADJ64, errs
+
+
+@pytest.mark.parametrize("name", ["ediffav", "lnp", "all3"])
+def test_rhs_adjoint_plane_means_f64(name):
+    """The bare right-hand side has no dt, so its adjoint leaves the div B
+    diffusion out, as the oracle's right-hand side without dt does."""
+    f, box, prm = _ragged()
+    over = _plane_terms(name)
+    g, p = grid_params(box, prm, **over)
+    w = _randn_like(f, 33)
+    ctx = _ctx(box, prm, torch.float64, **over)
+    out = ctx.rhs_adjoint(ctx.upload([f]), ctx.upload([w]))
+    want = O.rhs_vjp(to_cpu64(f), g, p, to_cpu64(w))
+    errs = rel_errors(ctx.box_view(out, 0), want)
+    ctx.close()
+    print(name, ["%.2e" % e for e in errs])
+    assert max(errs) < TOL_ADJ64, errs
+
+
+def test_adjoint_program_follows_dt_f64():
+    """The div B term's coefficient is c_divb h^2 / dt: one context, steps
+    at two dt and the bare right-hand side in between, each against the
+    oracle."""
+    f, box, prm = _ragged()
+    over = _plane_terms("all3")
+    g, p = grid_params(box, prm, **over)
+    ft = to_cpu64(f)
+    dt0 = 0.5 * O.courant(ft, g, p)[0]
+    gbar = _randn_like(f, 35)
+    ctx = _ctx(box, prm, torch.float64, **over)
+    fd, gd = ctx.upload([f]), ctx.upload([gbar])
+    for dt in (dt0, 0.4 * dt0, None, dt0):
+        if dt is None:
+            got = ctx.rhs_adjoint(fd, gd)
+            want = O.rhs_vjp(ft, g, p, to_cpu64(gbar))
+        else:
+            got = ctx.step_adjoint(fd, dt, gd)
+            want = O.step_vjp(ft, g, p, dt, to_cpu64(gbar))
+        errs = rel_errors(ctx.box_view(got, 0), want)
+        assert max(errs) < TOL_ADJ64, (dt, errs)
+    ctx.close()
+
+
+def test_ensemble_adjoint_plane_tables_f64():
+    """Three periodic boxes of different shapes in one context: each box's
+    planes have their own means, forward and transposed."""
+    shapes = ((12, 10, 14), (8, 14, 9), (10, 9, 16))
+    cases = []
+    for b, (nx, ny, nz) in enumerate(shapes):
+        f, box, prm = inputs.turbulent(n=16, seed=40 + b)
+        f = [a[:nz, :ny, :nx].copy() for a in f]
+        cases.append((f, dict(box, nx=nx, ny=ny, nz=nz, Lx=nx / 16, Ly=ny / 16, Lz=nz / 16), prm))
+    prm = cases[0][2]
+    over = _plane_terms("all3")
+    dts = []
+    for f, box, _ in cases:
+        g, p = grid_params(box, prm, **over)
+        dts.append(O.courant(to_cpu64(f), g, p)[0])
+    dt = 0.5 * min(dts)
+    gbars = [_randn_like(c[0], 50 + b) for b, c in enumerate(cases)]
+    ctx = _ctx([c[1] for c in cases], prm, torch.float64, **over)
+    out = ctx.step_adjoint(ctx.upload([c[0] for c in cases]), dt, ctx.upload(gbars))
+    for b, (f, box, _) in enumerate(cases):
+        g, p = grid_params(box, prm, **over)
+        want = O.step_vjp(to_cpu64(f), g, p, dt, to_cpu64(gbars[b]))
+        errs = rel_errors(ctx.box_view(out, b), want)
+        assert max(errs) < TOL_ADJ64, (b, errs)
+    ctx.close()

@@ -1,7 +1,8 @@
 """div B diffusion (c_divb h^2 / dt grad(div B)) in the library, through the
 C ABI: RK steps against the float64 oracle (periodic and closed-wall boxes,
-a mixed persistent ensemble), its absence from a bare right-hand side, the
-per-step decay of an x mode on the GPU alone, and the adjoint's refusal."""
+a mixed persistent ensemble), its absence from a bare right-hand side and
+the per-step decay of an x mode on the GPU alone.  The adjoint with this term
+is tested with the other adjoint tests."""
 import math
 
 import numpy as np
@@ -133,17 +134,6 @@ def test_x_mode_decays_by_the_rk3_polynomial_f64():
     z = -CDIVB * h * h * K * K
     R = 1 + z + z * z / 2 + z ** 3 / 6
     assert np.max(np.abs(got - R * bx)) < 2e-6 * A
-
-
-def test_adjoint_refuses_divb():
-    from paper_2405_02483_amd.lib import MhdError, MHD_EUNSUPPORTED
-    f, box, prm = _ragged()
-    ctx = _ctx(box, prm, torch.float64, **_over())
-    fd = ctx.upload([f])
-    with pytest.raises(MhdError) as ei:
-        ctx.step_adjoint(fd, 1e-3, ctx.zeros())
-    assert ei.value.code == MHD_EUNSUPPORTED
-    ctx.close()
 
 
 def test_step_with_device_courant_dt_f64():

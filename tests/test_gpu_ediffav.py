@@ -1,8 +1,8 @@
 """Energy diffusion about the horizontal mean (eq. ediffav) in the library,
 through the C ABI: the right-hand side and the RK step against the float64
 oracle, in closed-wall and periodic boxes and in an ensemble (per-box plane
-tables), a plane-constant state that must not diffuse, and the adjoint's
-refusal."""
+tables) and a plane-constant state that must not diffuse.  The adjoint
+with this term is tested with the other adjoint tests."""
 import math
 
 import numpy as np
@@ -132,17 +132,3 @@ def test_plane_constant_energy_does_not_diffuse_f64():
         ctx.close()
     assert float(rates["plain"].abs().max()) > 1e-3
     assert float(rates["av"].abs().max()) < 1e-12 * float(rates["plain"].abs().max())
-
-
-def test_adjoint_refuses_ediffav():
-    from paper_2405_02483_amd.lib import MhdError, MHD_EUNSUPPORTED
-    f, box, prm = _ragged()
-    ctx = _ctx(box, prm, torch.float64, **_over())
-    fd = ctx.upload([f])
-    with pytest.raises(MhdError) as ei:
-        ctx.step_adjoint(fd, 1e-3, ctx.zeros())
-    assert ei.value.code == MHD_EUNSUPPORTED
-    with pytest.raises(MhdError) as ei:
-        ctx.rhs_adjoint(fd, ctx.zeros())
-    assert ei.value.code == MHD_EUNSUPPORTED
-    ctx.close()

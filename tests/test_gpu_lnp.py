@@ -1,8 +1,8 @@
 """Pressure gradient through ln(P / P_aver) (eq. pressure) in the library,
 through the C ABI: the right-hand side and the RK step against the float64
 oracle (closed-wall and periodic boxes, an ensemble with per-box plane
-tables), the exact gradient of an exponential atmosphere on the GPU alone,
-and the adjoint's refusal."""
+tables) and the exact gradient of an exponential atmosphere on the GPU
+alone.  The adjoint with this term is tested with the other adjoint tests."""
 import math
 
 import numpy as np
@@ -124,14 +124,3 @@ def test_exponential_atmosphere_gradient_is_exact_f64():
     plain = np.max(np.abs(rates["plain"][inner] - w[inner])) / np.max(np.abs(w[inner]))
     assert err < 1e-13, err
     assert plain > 100 * max(err, 1e-16), (plain, err)
-
-
-def test_adjoint_refuses_lnp():
-    from paper_2405_02483_amd.lib import MhdError, MHD_EUNSUPPORTED
-    f, box, prm = _ragged()
-    ctx = _ctx(box, prm, torch.float64, **_over())
-    fd = ctx.upload([f])
-    with pytest.raises(MhdError) as ei:
-        ctx.step_adjoint(fd, 1e-3, ctx.zeros())
-    assert ei.value.code == MHD_EUNSUPPORTED
-    ctx.close()
