@@ -61,6 +61,10 @@ COOLING = dict(e_cool=1.5, t_cool=0.1, rho_cool=math.exp(-2.0), cool_cut=1)
 # Coriolis force: a rotation vector of magnitude 1 tilted 30 degrees from z
 # toward y (a box at 60 degrees latitude)
 CORIOLIS = dict(omega=(0.0, 0.5, math.sqrt(3.0) / 2.0))
+# Stretched z axis for the stratified workload: the cubic height map's
+# coefficients (a, b); the spacing falls from 1.35 of the mean at the bottom
+# to about 0.85 near the top
+STRETCH = (0.35, -0.2)
 
 
 def log(msg):
@@ -115,10 +119,10 @@ def measured_valu(dtype_name):
     return float(v) if v else None
 
 
-def make_state(workload, size):
+def make_state(workload, size, **kw):
     from paper_2405_02483_amd import inputs
     if workload == "stratified":
-        return inputs.stratified(size, size, size, seed=3)
+        return inputs.stratified(size, size, size, seed=3, **kw)
     if workload == "turbulent":
         return inputs.turbulent(n=size, seed=2)
     raise ValueError(workload)
@@ -136,7 +140,7 @@ def _window(f_np, box, x0, y0, width):
 
 
 def run_gpu(size, dtype, steps, warmup, workload="stratified", tile=None, over=None,
-            launch=None, window=None):
+            launch=None, window=None, state_kw=None):
     """Times `steps` RK steps.  over: parameters replacing the workload's;
     launch: a (tile, persistent, final-pass tile) to use instead of tuning;
     window: (x0, y0) of a column window: after the timing, one step of the
@@ -147,7 +151,7 @@ def run_gpu(size, dtype, steps, warmup, workload="stratified", tile=None, over=N
     from paper_2405_02483_amd.lib import Context
 
     log("generating the %d^3 %s state" % (size, workload))
-    f_np, box, prm = make_state(workload, size)
+    f_np, box, prm = make_state(workload, size, **(state_kw or {}))
     prm = dict(prm, **(over or {}))
     ctx = Context(box, prm, dtype=dtype)
     f = ctx.upload([f_np])
@@ -469,7 +473,7 @@ def main():
                     help="skip the legs with the optional terms (cooling, Coriolis, energy "
                          "diffusion about the plane mean, ln(P/P_aver) pressure gradient, "
                          "div B diffusion, Smagorinsky with the five-cell maximum, quenching, "
-                         "the second-order switch)")
+                         "the second-order switch, a stretched z axis) and div B cleaning")
     ap.add_argument("--cpu-table", action="store_true",
                     help="only time the CPU oracle at 32^3..256^3 (1 and all threads); no GPU")
     a = ap.parse_args()
@@ -498,15 +502,17 @@ def main():
         from paper_2405_02483_amd.lib import (T_ALL, T_COOL, T_CORI, T_EDIFFAV, T_LNP, T_DIVB,
                                               T_SMAG, T_MAX5, T_QUENCH, T_ORDER2)
         L = r32["launch"]
-        for name, bit, over in (("cooling", T_COOL, COOLING), ("coriolis", T_CORI, CORIOLIS),
-                                ("ediffav", T_EDIFFAV, {}), ("lnp", T_LNP, {}),
-                                ("divb", T_DIVB, dict(c_divb=0.05)),
-                                ("smagorinsky_max5", T_SMAG | T_MAX5, dict(c_smag=0.15)),
-                                ("quench", T_QUENCH, dict(q_max=8.0, q_lim=2.0)),
-                                ("order2", T_ORDER2, dict(d2_lim=0.3))):
+        for name, bit, over, skw in (("cooling", T_COOL, COOLING, None), ("coriolis", T_CORI, CORIOLIS, None),
+                                     ("ediffav", T_EDIFFAV, {}, None), ("lnp", T_LNP, {}, None),
+                                     ("divb", T_DIVB, dict(c_divb=0.05), None),
+                                     ("smagorinsky_max5", T_SMAG | T_MAX5, dict(c_smag=0.15), None),
+                                     ("quench", T_QUENCH, dict(q_max=8.0, q_lim=2.0), None),
+                                     ("order2", T_ORDER2, dict(d2_lim=0.3), None),
+                                     ("stretched", 0, {}, dict(stretch=STRETCH))):
             rsrc[name] = run_gpu(a.size, torch.float32, max(2, a.steps // 5), 1, a.workload,
                                  over=dict(over, terms=T_ALL | bit),
-                                 launch=(L["tile"], L["persistent"], L["final_pass_tile"]))
+                                 launch=(L["tile"], L["persistent"], L["final_pass_tile"]),
+                                 state_kw=skw)
             log("f32 with %s: %.2f ms/step" % (name, rsrc[name]["ms_per_step"]))
     r64 = None
     if not a.no_fp64:
@@ -576,7 +582,10 @@ def main():
         "smagorinsky_max5": "the Smagorinsky viscosity (eq. nusmag, c_smag 0.15) and the maximum "
                             "over five cells (Section 6.1.1)",
         "quench": "quenching of the viscous stress (eq. quench, q_max 8, q_lim 2)",
-        "order2": "the second-order switch of the strain (after eq. itv, d2_lim 0.3)"}
+        "order2": "the second-order switch of the strain (after eq. itv, d2_lim 0.3)",
+        "stretched": "a stretched z axis (Section 4.2), heights L s(u), s(u) = u + %.2f u(1-u) %+.2f u^2(1-u): "
+                     "dz from %.2f to %.2f of the mean" % (STRETCH[0], STRETCH[1], 1 + STRETCH[0],
+                                                           1 - STRETCH[0] - STRETCH[1])}
     for name, r in rsrc.items():
         out[name] = {
             "workload": "%s_%d with %s" % (a.workload, a.size, what[name]),

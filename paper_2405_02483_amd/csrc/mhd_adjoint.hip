@@ -583,32 +583,86 @@ __device__ __forceinline__ T along(const T* a, const Geo<T>& g, int ax, int i, i
   return ax == VX ? a[g.at(i + m, j, k)] : (ax == VY ? a[g.at(i, j + m, k)] : a[g.at(i, j, k + m)]);
 }
 
+// Planes of a wall-bounded z axis within this distance of an end take the
+// wall forms of the z operators (the tables); the others (and their
+// transposes) the periodic pair forms, whose samples then all lie inside.
+constexpr int kWallReach = 6;
+
+__device__ __forceinline__ bool wall_z(const BoxDev& b, int ax) { return ax == VZ && b.wall; }
+__device__ __forceinline__ bool near_end(const BoxDev& b, int k) {
+  return k < kWallReach || k >= b.nzt - kWallReach;
+}
+
+// Coefficient of input plane p in output plane k of a z operator on a
+// wall-bounded axis, before the 1/h of a derivative: fam 0, 1 from the box's
+// table (reduced orders at the ends, the end output no stencil reaches
+// copying its neighbour's); fam 2 the second-order pair, whose end output
+// copies its neighbour's in the same way.
+template <class T>
+__device__ __forceinline__ T zw_coef(const T* zt, const BoxDev& b, int fam, int form, int k, int p) {
+  const int N = b.nzt;
+  if (fam == 2) {
+    const int c = form ? (k + 1 < N ? k + 1 : N - 1) : (k > 0 ? k : 1);
+    return p == c ? T(1) : (p == c - 1 ? T(-1) : T(0));
+  }
+  const int d = p - k;
+  if (d < -3 || d > 3) return T(0);
+  const int type = fam == 0 ? (form ? ZT_IUP : ZT_IDN) : (form ? ZT_DUP : ZT_DDN);
+  return zt[b.zoff + ((long long)type * N + k) * 7 + d + 3];
+}
+
 // The step's reciprocal comes from the box record in global memory: picking
 // one of a local Geo's fields by a runtime axis would put Geo in scratch.
 template <class T>
-__device__ __forceinline__ T sten(const T* a, const Geo<T>& g, const BoxDev& bx, int ax, int fam,
-                                  int form, int i, int j, int k) {
+__device__ __forceinline__ T sten(const T* a, const Geo<T>& g, const BoxDev& bx, const T* zt, int ax,
+                                  int fam, int form, int i, int j, int k) {
   auto at = [&](int m) { return along(a, g, ax, i, j, k, m); };
   const T hinv = T(1.0 / (ax == VX ? bx.dx : (ax == VY ? bx.dy : bx.dz)));
+  if (wall_z(bx, ax) && near_end(bx, k)) {
+    T acc = T(0);
+    const int p0 = k - 3 > 0 ? k - 3 : 0, p1 = k + 3 < bx.nzt - 1 ? k + 3 : bx.nzt - 1;
+    for (int p = p0; p <= p1; ++p) acc += zw_coef(zt, bx, fam, form, k, p) * a[g.at(i, j, p)];
+    return fam ? acc * hinv : acc;
+  }
   if (fam == 2) return form ? (at(1) - at(0)) * hinv : (at(0) - at(-1)) * hinv;
   if (fam == 0) return form ? op6<0, 1, T>(at, hinv) : op6<0, 0, T>(at, hinv);
   return form ? op6<1, 1, T>(at, hinv) : op6<1, 0, T>(at, hinv);
 }
 
+// Transpose of sten at input cell (i, j, k), applied to the cotangent yb of
+// its outputs: the opposite stagger (minus it for a derivative), or near
+// the ends of a wall axis the gather over the table's columns.
+template <class T>
+__device__ __forceinline__ T sten_t(const T* yb, const Geo<T>& g, const BoxDev& bx, const T* zt, int ax,
+                                    int fam, int form, int i, int j, int k) {
+  if (wall_z(bx, ax) && near_end(bx, k)) {
+    const T hinv = T(1.0 / bx.dz);
+    T acc = T(0);
+    const int k0 = k - 3 > 0 ? k - 3 : 0, k1 = k + 3 < bx.nzt - 1 ? k + 3 : bx.nzt - 1;
+    for (int q = k0; q <= k1; ++q) acc += zw_coef(zt, bx, fam, form, q, k) * yb[g.at(i, j, q)];
+    return fam ? acc * hinv : acc;
+  }
+  const T t = sten(yb, g, bx, zt, ax, fam, 1 - form, i, j, k);
+  return fam ? -t : t;
+}
+
 // Second-order switch: whether cell (i, j, k) is rough (some axis's absolute
 // second difference of ln rho or ln e_m above lim), and whether a cell
 // touching position `kind` (0 centre, 1 x-edge, 2 y-edge, 3 z-edge of the
-// index) is.  Periodic boxes only (the adjoint's domain).
+// index) is.  On a wall-bounded z axis there is no z second difference on
+// the end planes, and a position on the lower end plane touches no cell
+// below it.
 template <class T>
 __device__ __forceinline__ bool rough_cell(const T* lr, const T* le, const Geo<T>& g, int i, int j, int k,
                                            T lim) {
   T m = T(0);
+  const bool zd = !g.wall || (k > 0 && k < g.nzt - 1);
   for (int v = 0; v < 2; ++v) {
     const T* a = v ? le : lr;
     const T c = a[g.at(i, j, k)];
     m = fmax(m, fabs(a[g.at(i + 1, j, k)] - T(2) * c + a[g.at(i - 1, j, k)]));
     m = fmax(m, fabs(a[g.at(i, j + 1, k)] - T(2) * c + a[g.at(i, j - 1, k)]));
-    m = fmax(m, fabs(a[g.at(i, j, k + 1)] - T(2) * c + a[g.at(i, j, k - 1)]));
+    if (zd) m = fmax(m, fabs(a[g.at(i, j, k + 1)] - T(2) * c + a[g.at(i, j, k - 1)]));
   }
   return m > lim;
 }
@@ -618,10 +672,20 @@ __device__ __forceinline__ bool rough_at(const T* lr, const T* le, const Geo<T>&
   const int di = (kind == 2 || kind == 3) ? 1 : 0, dj = (kind == 1 || kind == 3) ? 1 : 0,
             dk = (kind == 1 || kind == 2) ? 1 : 0;
   bool r = false;
-  for (int a = 0; a <= dk; ++a)
+  for (int a = 0; a <= dk; ++a) {
+    if (g.wall && k - a < 0) continue;
     for (int b = 0; b <= dj; ++b)
       for (int c = 0; c <= di; ++c) r = r || rough_cell(lr, le, g, i - c, j - b, k - a, lim);
+  }
   return r;
+}
+
+// Value of a at offset m along z from (i, j, k) on a wall-bounded axis, or
+// -inf past an end (never chosen by a maximum).
+template <class T>
+__device__ __forceinline__ T zval_or_ninf(const T* a, const Geo<T>& g, int i, int j, int k, int m) {
+  const int q = k + m;
+  return (q >= 0 && q < g.nzt) ? a[g.at(i, j, q)] : T(-INFINITY);
 }
 
 // Which of (lo, mid, hi) is the first maximal one: 0, 1 or 2.
@@ -641,7 +705,8 @@ template <class T> __device__ __forceinline__ int first_max(T lo, T mid, T hi) {
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_vm_group(const BoxDev* boxes, const Blk* tab,
                                                      const VFused* __restrict__ code, int first,
-                                                     int count, T* base, long long stride) {
+                                                     int count, T* base, long long stride,
+                                                     const T* __restrict__ zt) {
   __shared__ T regs[kGroupMax * kBlock];
   VM_PROLOGUE
   auto R = [&](int r) -> T& { return regs[r * kBlock + threadIdx.x]; };
@@ -655,15 +720,19 @@ __global__ __launch_bounds__(kBlock) void k_vm_group(const BoxDev* boxes, const 
         int i, j, k;
         coords(i, j, k);
         const Geo<T> g(bx_);
-        r = sten(base + I.a * stride, g, bx_, I.ax, I.fam, I.form, i, j, k);
+        r = sten(base + I.a * stride, g, bx_, zt, I.ax, I.fam, I.form, i, j, k);
         break;
       }
       case V_MAX3: {
+        // over the available cells at the ends of a wall axis
         int i, j, k;
         coords(i, j, k);
         const Geo<T> g(bx_);
         const T* a = base + I.a * stride;
-        const T lo = along(a, g, I.ax, i, j, k, -1), mid = a[o], hi = along(a, g, I.ax, i, j, k, 1);
+        const bool wz = wall_z(bx_, I.ax);
+        const T lo = wz ? zval_or_ninf(a, g, i, j, k, -1) : along(a, g, I.ax, i, j, k, -1);
+        const T hi = wz ? zval_or_ninf(a, g, i, j, k, 1) : along(a, g, I.ax, i, j, k, 1);
+        const T mid = a[o];
         const int s = first_max(lo, mid, hi);
         r = s == 0 ? lo : (s == 1 ? mid : hi);
         break;
@@ -673,7 +742,15 @@ __global__ __launch_bounds__(kBlock) void k_vm_group(const BoxDev* boxes, const 
         coords(i, j, k);
         const Geo<T> g(bx_);
         const T* a = base + I.a * stride;
-        r = (along(a, g, I.ax, i, j, k, -1) + a[o] + along(a, g, I.ax, i, j, k, 1)) / T(3);
+        if (wall_z(bx_, I.ax)) {
+          // the mean of the available cells, summed in the order k-1, k, k+1
+          const bool lo = k > 0, hi = k < bx_.nzt - 1;
+          T s = lo ? a[g.at(i, j, k - 1)] + a[o] : a[o];
+          if (hi) s = s + a[g.at(i, j, k + 1)];
+          r = s / T(1 + (lo ? 1 : 0) + (hi ? 1 : 0));
+        } else {
+          r = (along(a, g, I.ax, i, j, k, -1) + a[o] + along(a, g, I.ax, i, j, k, 1)) / T(3);
+        }
         break;
       }
       case V_D2: {
@@ -681,7 +758,11 @@ __global__ __launch_bounds__(kBlock) void k_vm_group(const BoxDev* boxes, const 
         coords(i, j, k);
         const Geo<T> g(bx_);
         const T* a = base + I.a * stride;
-        r = along(a, g, I.ax, i, j, k, 1) - T(2) * a[o] + along(a, g, I.ax, i, j, k, -1);
+        // none across the ends of a wall axis
+        if (wall_z(bx_, I.ax) && (k == 0 || k == bx_.nzt - 1))
+          r = T(0);
+        else
+          r = along(a, g, I.ax, i, j, k, 1) - T(2) * a[o] + along(a, g, I.ax, i, j, k, -1);
         break;
       }
       case V_ADD: r = opnd(I.a, G.la) + opnd(I.b, G.lb); break;
@@ -744,7 +825,7 @@ template <class T>
 __global__ __launch_bounds__(kBlock) void k_vm_bwd(const BoxDev* boxes, const Blk* tab, int nblk,
                                                    const VStep* __restrict__ code, int first,
                                                    int count, const T* base, T* cbase,
-                                                   long long stride) {
+                                                   long long stride, const T* __restrict__ zt) {
   constexpr int R = kBwdCells;
   long long o[R];
   unsigned q[R];
@@ -823,8 +904,7 @@ __global__ __launch_bounds__(kBlock) void k_vm_bwd(const BoxDev* boxes, const Bl
           int i, j, k;
           coords(r, i, j, k);
           const Geo<T> g(boxes[bi[r]]);
-          const T t = sten(yb, g, boxes[bi[r]], I.ax, I.fam, 1 - I.form, i, j, k);
-          v1[r] = I.fam ? -t : t;
+          v1[r] = sten_t(yb, g, boxes[bi[r]], zt, I.ax, I.fam, I.form, i, j, k);
         }
         put(ca, 1, v1);
         break;
@@ -913,13 +993,16 @@ __global__ __launch_bounds__(kBlock) void k_vm_bwd(const BoxDev* boxes, const Bl
           int i, j, k;
           coords(r, i, j, k);
           const Geo<T> g(boxes[bi[r]]);
-          auto v = [&](int m) { return along(a, g, I.ax, i, j, k, m); };
+          // on a wall axis: cells past an end are -inf, outputs past an end absent
+          const bool wz = wall_z(boxes[bi[r]], I.ax);
+          auto v = [&](int m) { return wz ? zval_or_ninf(a, g, i, j, k, m) : along(a, g, I.ax, i, j, k, m); };
           auto w = [&](int m) { return along(yb, g, I.ax, i, j, k, m); };
           const T vm2 = v(-2), vm1 = v(-1), v0 = a[o[r]], vp1 = v(1), vp2 = v(2);
+          const bool has_lo = !wz || k > 0, has_hi = !wz || k < g.nzt - 1;
           T sum = T(0);
-          if (first_max(vm2, vm1, v0) == 2) sum += w(-1);
+          if (has_lo && first_max(vm2, vm1, v0) == 2) sum += w(-1);
           if (first_max(vm1, v0, vp1) == 1) sum += y[r];
-          if (first_max(v0, vp1, vp2) == 0) sum += w(1);
+          if (has_hi && first_max(v0, vp1, vp2) == 0) sum += w(1);
           v1[r] = sum;
         }
         put(ca, 1, v1);
@@ -930,7 +1013,17 @@ __global__ __launch_bounds__(kBlock) void k_vm_bwd(const BoxDev* boxes, const Bl
           int i, j, k;
           coords(r, i, j, k);
           const Geo<T> g(boxes[bi[r]]);
-          v1[r] = (along(yb, g, I.ax, i, j, k, -1) + y[r] + along(yb, g, I.ax, i, j, k, 1)) / T(3);
+          if (wall_z(boxes[bi[r]], I.ax)) {
+            // output q averages over 2 cells at an end of the axis, else 3
+            const int N = g.nzt;
+            auto cnt = [&](int q) { return T(q == 0 || q == N - 1 ? 2 : 3); };
+            T s = y[r] / cnt(k);
+            if (k > 0) s += yb[g.at(i, j, k - 1)] / cnt(k - 1);
+            if (k < N - 1) s += yb[g.at(i, j, k + 1)] / cnt(k + 1);
+            v1[r] = s;
+          } else {
+            v1[r] = (along(yb, g, I.ax, i, j, k, -1) + y[r] + along(yb, g, I.ax, i, j, k, 1)) / T(3);
+          }
         }
         put(ca, 1, v1);
         break;
@@ -940,7 +1033,16 @@ __global__ __launch_bounds__(kBlock) void k_vm_bwd(const BoxDev* boxes, const Bl
           int i, j, k;
           coords(r, i, j, k);
           const Geo<T> g(boxes[bi[r]]);
-          v1[r] = along(yb, g, I.ax, i, j, k, 1) - T(2) * y[r] + along(yb, g, I.ax, i, j, k, -1);
+          if (wall_z(boxes[bi[r]], I.ax)) {
+            // outputs 1 .. N-2 only
+            const int N = g.nzt;
+            T s = (k >= 1 && k <= N - 2) ? T(-2) * y[r] : T(0);
+            if (k - 1 >= 1) s += yb[g.at(i, j, k - 1)];
+            if (k + 1 <= N - 2) s += yb[g.at(i, j, k + 1)];
+            v1[r] = s;
+          } else {
+            v1[r] = along(yb, g, I.ax, i, j, k, 1) - T(2) * y[r] + along(yb, g, I.ax, i, j, k, -1);
+          }
         }
         put(ca, 1, v1);
         break;
@@ -1058,6 +1160,174 @@ static void vm_pmean(const VLaunch& L, const T* src, T* dst, int over) {
                      (const double*)L.pm, dst, over);
 }
 
+// ---------------------------------------------------------------------------
+// Transpose of the closed-wall ghost fill (Section 10 "Closed"), linearised
+// at the filled state s.  The fill sets, on ghost plane k at distance d from
+// the wall, from interior planes a0 (next to the wall) and a1:
+//   rho_k = exp(L_r), L_r = (1 + d) ln rho_a0 - d ln rho_a1,
+//   e_k = rho_k exp(L_m), L_m the same of ln(e / rho),
+//   p_x,k = X_k p_x,m / X_m with X = xdn(rho) on planes k and m (the mirror
+//   across the wall; p_y with ydn), B_x,k = -B_x,m, B_y,k = -B_y,m,
+//   p_z and B_z beyond the wall face mirrored (- and +), p_z = 0 on both
+//   wall faces.
+// One thread per ghost cell of one side (lower side 0, upper 1; the sides
+// run apart, since their mirror planes can meet in a shallow box), in three
+// launches: (1) the cotangents of X_k and X_m of each ghost p_x, p_y cell
+// into tmp 0..3 and the mirror contributions to p_x, p_y, B and p_z; (2) the
+// cotangent of the ghost density (through X_k and e_k), of L_r and L_m into
+// tmp 4, 5, and that of the mirror density through X_m; (3) per column the
+// sums over the side's ghost planes into rho and e at a0 and a1, and the
+// ghost cotangents cleared.
+namespace {
+struct GhostCell {
+  int i, j, k, m, d, a0, a1;
+  bool lower;
+};
+__device__ __forceinline__ bool ghost_cell(const BoxDev& b, const Blk& t, int side, GhostCell& c) {
+  long long q = t.start + threadIdx.x;   // over nx * ny * (2 ngz)
+  c.i = (int)(q % b.nx);
+  q /= b.nx;
+  c.j = (int)(q % b.ny);
+  const int s = (int)(q / b.ny);
+  c.lower = s < b.ngz;
+  if (c.lower != (side == 0)) return false;
+  c.k = c.lower ? s : b.g1 + (s - b.ngz);
+  c.d = c.lower ? b.g0 - c.k : c.k - b.g1 + 1;
+  c.m = c.lower ? 2 * b.g0 - 1 - c.k : 2 * b.g1 - 1 - c.k;
+  c.a0 = c.lower ? b.g0 : b.g1 - 1;
+  c.a1 = c.lower ? b.g0 + 1 : b.g1 - 2;
+  return true;
+}
+}  // namespace
+
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_fill_vjp1(const BoxDev* boxes, const Blk* gtab, int side, CP8<T> s,
+                                                      P8<T> g, T* t0, T* t1, T* t2, T* t3) {
+  const Blk t = gtab[blockIdx.x];
+  if ((int)threadIdx.x >= t.n) return;
+  const BoxDev& b = boxes[t.box];
+  GhostCell c;
+  if (!ghost_cell(b, t, side, c)) return;
+  const Geo<T> G(b);
+  const int i = c.i, j = c.j, k = c.k, m = c.m;
+  const long long o = G.at(i, j, k), om = G.at(i, j, m);
+  const T* rho = s.p[0];
+  const T xk = op6<0, 0, T>([&](int l) { return rho[G.at(i + l, j, k)]; }, T(0));
+  const T xm = op6<0, 0, T>([&](int l) { return rho[G.at(i + l, j, m)]; }, T(0));
+  const T yk = op6<0, 0, T>([&](int l) { return rho[G.at(i, j + l, k)]; }, T(0));
+  const T ym = op6<0, 0, T>([&](int l) { return rho[G.at(i, j + l, m)]; }, T(0));
+  const T gpx = g.p[1][o], gpy = g.p[2][o];
+  const T pxm = s.p[1][om], pym = s.p[2][om];
+  t0[o] = gpx * (pxm / xm);
+  t1[o] = gpy * (pym / ym);
+  t2[o] = -(gpx * (xk * pxm / xm) / xm);
+  t3[o] = -(gpy * (yk * pym / ym) / ym);
+  g.p[1][om] += gpx * (xk / xm);
+  g.p[2][om] += gpy * (yk / ym);
+  g.p[5][om] -= g.p[5][o];
+  g.p[6][om] -= g.p[6][o];
+  // z-faces beyond the wall face mirror the faces inside it
+  if (c.lower || k != b.g1) {
+    const long long of = G.at(i, j, c.lower ? 2 * b.g0 - k : 2 * b.g1 - k);
+    g.p[3][of] -= g.p[3][o];
+    g.p[7][of] += g.p[7][o];
+  }
+}
+
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_fill_vjp2(const BoxDev* boxes, const Blk* gtab, int side, CP8<T> s,
+                                                      P8<T> g, const T* t0, const T* t1, const T* t2,
+                                                      const T* t3, T* t4, T* t5) {
+  const Blk t = gtab[blockIdx.x];
+  if ((int)threadIdx.x >= t.n) return;
+  const BoxDev& b = boxes[t.box];
+  GhostCell c;
+  if (!ghost_cell(b, t, side, c)) return;
+  const Geo<T> G(b);
+  const int i = c.i, j = c.j, k = c.k;
+  const long long o = G.at(i, j, k), om = G.at(i, j, c.m);
+  // transposes of xdn, ydn on a periodic axis: xup, yup
+  const T rk = g.p[0][o] + op6<0, 1, T>([&](int l) { return t0[G.at(i + l, j, k)]; }, T(0)) +
+               op6<0, 1, T>([&](int l) { return t1[G.at(i, j + l, k)]; }, T(0));
+  const T rn = s.p[0][o], en = s.p[4][o], ge = g.p[4][o];
+  t4[o] = (rk + ge * (en / rn)) * rn;
+  t5[o] = ge * en;
+  g.p[0][om] += op6<0, 1, T>([&](int l) { return t2[G.at(i + l, j, k)]; }, T(0)) +
+                op6<0, 1, T>([&](int l) { return t3[G.at(i, j + l, k)]; }, T(0));
+}
+
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_fill_vjp3(const BoxDev* boxes, const Blk* gtab, int side, CP8<T> s,
+                                                      P8<T> g, const T* t4, const T* t5) {
+  const Blk t = gtab[blockIdx.x];
+  if ((int)threadIdx.x >= t.n) return;
+  const BoxDev& b = boxes[t.box];
+  GhostCell c;
+  if (!ghost_cell(b, t, side, c)) return;
+  const Geo<T> G(b);
+  const int i = c.i, j = c.j, k = c.k;
+  const long long o = G.at(i, j, k);
+  if (c.d == 1) {
+    // L_r and L_m of every ghost plane of this side, into ln rho, ln e_m at a0, a1
+    T lr0 = T(0), lr1 = T(0), lm0 = T(0), lm1 = T(0);
+    for (int dd = 1; dd <= b.ngz; ++dd) {
+      const long long oq = G.at(i, j, c.lower ? b.g0 - dd : b.g1 - 1 + dd);
+      lr0 += T(1 + dd) * t4[oq];
+      lr1 -= T(dd) * t4[oq];
+      lm0 += T(1 + dd) * t5[oq];
+      lm1 -= T(dd) * t5[oq];
+    }
+    const long long o0 = G.at(i, j, c.a0), o1 = G.at(i, j, c.a1);
+    // ln e_m = ln e - ln rho
+    g.p[0][o0] += (lr0 - lm0) / s.p[0][o0];
+    g.p[4][o0] += lm0 / s.p[4][o0];
+    g.p[0][o1] += (lr1 - lm1) / s.p[0][o1];
+    g.p[4][o1] += lm1 / s.p[4][o1];
+    if (c.lower) g.p[3][G.at(i, j, b.g0)] = T(0);   // p_z on the lower wall face
+  }
+  // the fill overwrites every ghost value except B_z on the upper wall face
+#pragma unroll
+  for (int v = 0; v < 8; ++v)
+    if (!(v == 7 && k == b.g1)) g.p[v][o] = T(0);
+}
+
+// Zero where the right-hand side is zeroed on a wall box: the ghost planes
+// of centred fields, p_z outside the open interior faces, B_z outside the
+// faces from wall to wall.
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_wall_mask8(const BoxDev* boxes, const Blk* tab, P8<T> y) {
+  VM_PROLOGUE
+  if (!bx_.wall) return;
+  int i, j, k;
+  coords(i, j, k);
+  (void)i;
+  (void)j;
+  const bool cen = k >= bx_.g0 && k < bx_.g1;
+#pragma unroll
+  for (int v = 0; v < 8; ++v) {
+    const bool keep = v == 3 ? (k > bx_.g0 && k < bx_.g1) : (v == 7 ? (k >= bx_.g0 && k <= bx_.g1) : cen);
+    if (!keep) y.p[v][o] = T(0);
+  }
+}
+
+template <class T> void vm_fill_vjp(const VLaunch& L, CP8<T> s, P8<T> g, T* tmp, long long stride) {
+  if (L.nghost_blk == 0) return;
+  T* t[6];
+  for (int q = 0; q < 6; ++q) t[q] = tmp + (long long)q * stride;
+  for (int side = 0; side < 2; ++side) {
+    hipLaunchKernelGGL(k_fill_vjp1<T>, dim3(L.nghost_blk), dim3(kBlock), 0, L.stream, L.boxes, L.gtab, side, s,
+                       g, t[0], t[1], t[2], t[3]);
+    hipLaunchKernelGGL(k_fill_vjp2<T>, dim3(L.nghost_blk), dim3(kBlock), 0, L.stream, L.boxes, L.gtab, side, s,
+                       g, (const T*)t[0], (const T*)t[1], (const T*)t[2], (const T*)t[3], t[4], t[5]);
+    hipLaunchKernelGGL(k_fill_vjp3<T>, dim3(L.nghost_blk), dim3(kBlock), 0, L.stream, L.boxes, L.gtab, side, s,
+                       g, (const T*)t[4], (const T*)t[5]);
+  }
+}
+
+template <class T> void vm_wall_mask(const VLaunch& L, P8<T> g) {
+  hipLaunchKernelGGL(k_wall_mask8<T>, dim3(L.nblk), dim3(kBlock), 0, L.stream, L.boxes, L.tab, g);
+}
+
 template <class T>
 void vm_forward(const VLaunch& L, const VPlan& P, const VFused* d_fused, T* base, long long stride) {
   for (const VGroup& G : P.groups) {
@@ -1069,7 +1339,7 @@ void vm_forward(const VLaunch& L, const VPlan& P, const VFused* d_fused, T* base
       vm_pmean<T>(L, base + I.a * stride, base + I.out * stride, 1);
     else
       hipLaunchKernelGGL(k_vm_group<T>, dim3(L.nblk), dim3(kBlock), 0, L.stream, L.boxes, L.tab, d_fused,
-                         G.first, G.count, base, stride);
+                         G.first, G.count, base, stride, (const T*)L.ztab);
   }
 }
 
@@ -1084,7 +1354,7 @@ void vm_backward(const VLaunch& L, const VPlan& P, const VStep* d_bsteps, const 
       continue;
     }
     hipLaunchKernelGGL(k_vm_bwd<T>, dim3(grid), dim3(kBlock), 0, L.stream, L.boxes, L.tab, L.nblk,
-                       d_bsteps, G.first, G.count, base, cbase, stride);
+                       d_bsteps, G.first, G.count, base, cbase, stride, (const T*)L.ztab);
   }
 }
 
@@ -1101,5 +1371,9 @@ template void vm_backward<double>(const VLaunch&, const VPlan&, const VStep*, co
                                   long long);
 template void vm_axpby8<float>(const VLaunch&, P8<float>, CP8<float>, double, double);
 template void vm_axpby8<double>(const VLaunch&, P8<double>, CP8<double>, double, double);
+template void vm_fill_vjp<float>(const VLaunch&, CP8<float>, P8<float>, float*, long long);
+template void vm_fill_vjp<double>(const VLaunch&, CP8<double>, P8<double>, double*, long long);
+template void vm_wall_mask<float>(const VLaunch&, P8<float>);
+template void vm_wall_mask<double>(const VLaunch&, P8<double>);
 
 }  // namespace smhd

@@ -123,6 +123,9 @@ struct VLaunch {
   hipStream_t stream;
   int nbox, nplanes;      // boxes; z planes of all boxes (BoxDev::poff)
   double* pm;             // nplanes values: plane means (V_PMEAN)
+  const void* ztab;       // z-coefficient tables of wall boxes (BoxDev::zoff), compute type
+  const Blk* gtab;        // blocks over the ghost planes of wall boxes
+  int nghost_blk;
 };
 
 // Forward: value slots base + s * stride (slots 0..7 filled by the caller);
@@ -138,5 +141,15 @@ void vm_backward(const VLaunch& L, const VPlan& plan, const VStep* d_bsteps, con
 
 // y[v] = a * y[v] + b * x[v] for the 8 fields (x may be null: y = a * y).
 template <class T> void vm_axpby8(const VLaunch& L, P8<T> y, CP8<T> x, double a, double b);
+
+// Closed walls (Section 10): the transpose of the ghost fill at the filled
+// state s, in place: g holds the cotangent of the filled state on entry and
+// that of the state before the fill on exit (zero in the ghost planes and on
+// the two wall faces of p_z, which the fill overwrites).  tmp: 6 arrays of
+// the packed field size (only their ghost cells are used).
+template <class T> void vm_fill_vjp(const VLaunch& L, CP8<T> s, P8<T> g, T* tmp, long long stride);
+// Closed walls: zero a cotangent of the right-hand side where the
+// right-hand side itself is zeroed (ghost planes; p_z on the wall faces).
+template <class T> void vm_wall_mask(const VLaunch& L, P8<T> g);
 
 }  // namespace smhd

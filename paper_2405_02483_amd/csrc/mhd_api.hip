@@ -867,23 +867,55 @@ static int ensure_program(mhd_ctx* c, double dt) {
 //   gbar  += (dF/df at f_s)^T Ubar_s.
 // f_1 and f_2 come from the fused stage kernels; F's intermediates at each
 // f_s from the program's forward run, just before its transpose.
+static VLaunch make_vlaunch(mhd_ctx* c) {
+  return VLaunch{c->d_boxes, c->d_tab, c->nblk, c->stream, (int)c->h_boxes.size(), c->nplanes, c->d_pm,
+                 c->d_ztab, c->d_gtab, c->ngblk};
+}
+
+static bool any_wall(const mhd_ctx* c) {
+  for (const auto& b : c->boxes)
+    if (b.bc_z == MHD_BC_WALL) return true;
+  return false;
+}
+
+// The adjoint workspace: the program's value and cotangent slots, then the
+// stage states and dU (25 arrays; 16 more with walls: the filled input and
+// the step's end state).
+template <class T> static T* adjoint_workspace(mhd_ctx* c, const VPlan& P, bool walls, int& rc) {
+  const long long n = c->nelem;
+  const size_t narr = (size_t)P.nval + P.ncot + 25 + (walls ? 16 : 0);
+  const size_t need = narr * (size_t)n * c->esize;
+  rc = MHD_OK;
+  if (c->adj_bytes < need) {
+    (void)hipFree(c->adj);
+    c->adj = nullptr;
+    c->adj_bytes = 0;
+    if (hipMalloc(&c->adj, need) != hipSuccess) {
+      rc = fail(c, MHD_ENOMEM, "adjoint workspace");
+      return nullptr;
+    }
+    c->adj_bytes = need;
+  }
+  return static_cast<T*>(c->adj);
+}
+
+// One RK step's adjoint at fixed dt.  The stage states are recomputed with
+// the stage kernels; then, stage by stage backwards, Ubar = alpha Ubar +
+// beta dt G, the program's forward run at the stage state and its reverse
+// sweep seeded with Ubar give G += (dF/df)^T Ubar.  With walls the states
+// are filled (the step fills before every F and after the last stage),
+// Ubar is masked like F, and G passes through the fill's transpose after
+// each stage (and first through that of the end state's fill).
 template <class T>
 static int do_adjoint(mhd_ctx* c, void* const fn[8], double dt, void* const gin[8],
                       void* const gout[8]) {
   if (int rc = ensure_program(c, dt)) return rc;
   const VPlan& P = *c->prog;
   const long long n = c->nelem;
-  const size_t narr = (size_t)P.nval + P.ncot + 25;
-  const size_t need = narr * (size_t)n * c->esize;
-  if (c->adj_bytes < need) {
-    (void)hipFree(c->adj);
-    c->adj = nullptr;
-    c->adj_bytes = 0;
-    hipError_t e = hipMalloc(&c->adj, need);
-    if (e != hipSuccess) return fail(c, MHD_ENOMEM, "adjoint workspace");
-    c->adj_bytes = need;
-  }
-  T* base = static_cast<T*>(c->adj);
+  const bool walls = any_wall(c);
+  int rc = MHD_OK;
+  T* base = adjoint_workspace<T>(c, P, walls, rc);
+  if (!base) return rc;
   T* cbase = base + (long long)P.nval * n;
   T* rest = cbase + (long long)P.ncot * n;
   auto set8 = [&](int first) {
@@ -892,32 +924,46 @@ static int do_adjoint(mhd_ctx* c, void* const fn[8], double dt, void* const gin[
     return q;
   };
   const P8<T> F1 = set8(0), F2 = set8(8), U = set8(16);
+  const P8<T> S0 = walls ? set8(25) : p8<T>(fn), F3 = set8(walls ? 33 : 0);
   const P8<T> G = p8<T>(gout);
   const size_t bytes = (size_t)n * c->esize;
   T* zeros = rest + 24LL * n;   // the cotangent of an input F does not read
   const Launch L = make_launch(c);
-  // stage states f_1, f_2
+  hipError_t e = hipSuccess;
+  if (walls) {
+    // the step fills its input first; f_n itself is left as it is
+    for (int v = 0; v < 8 && e == hipSuccess; ++v)
+      e = hipMemcpyAsync(S0.p[v], fn[v], bytes, hipMemcpyDeviceToDevice, c->stream);
+    if (e != hipSuccess) return fail(c, MHD_EHIP, hipGetErrorString(e));
+    launch_ghost<T>(L, S0);
+  }
+  // stage states f_1, f_2 (and with walls the end state, for its fill)
   const ZLaunch Z = make_zlaunch(c);
-  for (int s = 0; s < 2; ++s) {
+  for (int s = 0; s < (walls ? 3 : 2); ++s) {
     ZStageArgs<T> a = zargs<T>(c);
-    a.f = s == 0 ? cp8<T>(fn) : cp8<T>(F1);
+    a.f = s == 0 ? cp8<T>(S0) : (s == 1 ? cp8<T>(F1) : cp8<T>(F2));
     a.du = U;
-    a.du_mode = (s == 0 ? 0 : DU_READ) | DU_WRITE;
-    a.f_out = s == 0 ? F1 : F2;
+    a.du_mode = (s == 0 ? 0 : DU_READ) | (s == 2 ? 0 : DU_WRITE);
+    a.f_out = s == 0 ? F1 : (s == 1 ? F2 : F3);
     a.alpha = T(kAlpha[s]);
     a.beta = kBeta[s];
     a.dt_host = dt;
     launch_zstage<T>(Z, a);
+    if (walls) launch_ghost<T>(L, a.f_out);
   }
   L.at(PASS_ADJOINT);
-  VLaunch V{c->d_boxes, c->d_tab, c->nblk, c->stream, (int)c->h_boxes.size(), c->nplanes, c->d_pm};
-  hipError_t e = hipMemsetAsync(zeros, 0, bytes, c->stream);
+  const VLaunch V = make_vlaunch(c);
+  e = hipMemsetAsync(zeros, 0, bytes, c->stream);
   for (int v = 0; v < 8 && e == hipSuccess; ++v)
     e = hipMemcpyAsync(G.p[v], gin[v], bytes, hipMemcpyDeviceToDevice, c->stream);
+  // (value slots are free outside the program's runs: the fill's transpose
+  // keeps its temporaries there)
+  if (walls && e == hipSuccess) vm_fill_vjp<T>(V, cp8<T>(F3), G, base, n);
   const P8<T> Ub = U;   // U is free again: it becomes Ubar
   for (int s = 2; s >= 0 && e == hipSuccess; --s) {
     vm_axpby8<T>(V, Ub, cp8<T>(G), s == 2 ? 0.0 : kAlpha[s + 1], kBeta[s] * dt);
-    const P8<T> fs = s == 0 ? p8<T>(fn) : (s == 1 ? F1 : F2);
+    if (walls) vm_wall_mask<T>(V, Ub);
+    const P8<T> fs = s == 0 ? S0 : (s == 1 ? F1 : F2);
     for (int v = 0; v < 8 && e == hipSuccess; ++v)
       e = hipMemcpyAsync(base + (long long)v * n, fs.p[v], bytes, hipMemcpyDeviceToDevice, c->stream);
     if (e != hipSuccess) break;
@@ -934,46 +980,64 @@ static int do_adjoint(mhd_ctx* c, void* const fn[8], double dt, void* const gin[
       any |= P.cin[v] >= 0;
     }
     if (any) vm_axpby8<T>(V, G, cin, 1.0, 1.0);
+    if (walls) vm_fill_vjp<T>(V, cp8<T>(fs), G, base, n);
   }
   L.at(PASS_END);
   if (e != hipSuccess) return fail(c, MHD_EHIP, hipGetErrorString(e));
   return check_launch(c, "mhd_step_adjoint launch");
 }
 
-// (dF/df)^T wbar at the state f (periodic boxes): the program's forward run
-// at f, its reverse sweep seeded with wbar.
+// (dF/df)^T wbar at the state f: the program's forward run at f, its
+// reverse sweep seeded with wbar.  With walls, F is the right-hand side of
+// mhd_rhs, which fills the ghost planes first: the run is at the filled
+// state, the seed is masked like F, and the result passes through the
+// fill's transpose.
 template <class T>
 static int do_rhs_adjoint(mhd_ctx* c, void* const f[8], void* const wbar[8],
                           void* const fbar[8]) {
   if (int rc = ensure_program(c, 0.0)) return rc;
   const VPlan& P = *c->prog;
   const long long n = c->nelem;
-  const size_t need = ((size_t)P.nval + P.ncot + 25) * (size_t)n * c->esize;
-  if (c->adj_bytes < need) {
-    (void)hipFree(c->adj);
-    c->adj = nullptr;
-    c->adj_bytes = 0;
-    if (hipMalloc(&c->adj, need) != hipSuccess) return fail(c, MHD_ENOMEM, "adjoint workspace");
-    c->adj_bytes = need;
-  }
-  T* base = static_cast<T*>(c->adj);
+  const bool walls = any_wall(c);
+  int rc = MHD_OK;
+  T* base = adjoint_workspace<T>(c, P, walls, rc);
+  if (!base) return rc;
   T* cbase = base + (long long)P.nval * n;
+  T* rest = cbase + (long long)P.ncot * n;
   const size_t bytes = (size_t)n * c->esize;
   const Launch L = make_launch(c);
   L.at(PASS_ADJOINT);
-  VLaunch V{c->d_boxes, c->d_tab, c->nblk, c->stream, (int)c->h_boxes.size(), c->nplanes, c->d_pm};
+  const VLaunch V = make_vlaunch(c);
+  P8<T> S, W;
+  for (int v = 0; v < 8; ++v) {
+    S.p[v] = rest + (long long)v * n;          // the filled state (walls)
+    W.p[v] = rest + (long long)(8 + v) * n;    // the masked seed (walls)
+  }
   hipError_t e = hipSuccess;
   for (int v = 0; v < 8 && e == hipSuccess; ++v)
     e = hipMemcpyAsync(base + (long long)v * n, f[v], bytes, hipMemcpyDeviceToDevice, c->stream);
+  if (walls) {
+    for (int v = 0; v < 8 && e == hipSuccess; ++v) {
+      e = hipMemcpyAsync(S.p[v], f[v], bytes, hipMemcpyDeviceToDevice, c->stream);
+      if (e == hipSuccess) e = hipMemcpyAsync(W.p[v], wbar[v], bytes, hipMemcpyDeviceToDevice, c->stream);
+    }
+    if (e == hipSuccess) {
+      launch_ghost<T>(L, S);
+      vm_wall_mask<T>(V, W);
+    }
+    for (int v = 0; v < 8 && e == hipSuccess; ++v)
+      e = hipMemcpyAsync(base + (long long)v * n, S.p[v], bytes, hipMemcpyDeviceToDevice, c->stream);
+  }
   if (e == hipSuccess) vm_forward<T>(V, P, c->d_fused, base, n);
   for (int v = 0; v < 8 && e == hipSuccess; ++v)
-    e = hipMemcpyAsync(cbase + (long long)P.cout[v] * n, wbar[v], bytes, hipMemcpyDeviceToDevice,
-                       c->stream);
+    e = hipMemcpyAsync(cbase + (long long)P.cout[v] * n, walls ? W.p[v] : wbar[v], bytes,
+                       hipMemcpyDeviceToDevice, c->stream);
   if (e == hipSuccess) vm_backward<T>(V, P, c->d_bsteps, base, cbase, n);
   for (int v = 0; v < 8 && e == hipSuccess; ++v)
     e = P.cin[v] >= 0 ? hipMemcpyAsync(fbar[v], cbase + (long long)P.cin[v] * n, bytes,
                                        hipMemcpyDeviceToDevice, c->stream)
                       : hipMemsetAsync(fbar[v], 0, bytes, c->stream);
+  if (walls && e == hipSuccess) vm_fill_vjp<T>(V, cp8<T>(S), p8<T>(fbar), base, n);
   L.at(PASS_END);
   if (e != hipSuccess) return fail(c, MHD_EHIP, hipGetErrorString(e));
   return check_launch(c, "mhd_rhs_adjoint launch");
@@ -1133,8 +1197,7 @@ int mhd_step_adjoint(mhd_ctx* c, void* const f_n[8], double dt, void* const gin[
   if ((rc = check8(c, f_n, "f_n")) || (rc = check8(c, gin, "gbar_in")) ||
       (rc = check8(c, gout, "gbar_out")))
     return rc;
-  for (const auto& b : c->boxes)
-    if (b.bc_z != MHD_BC_PERIODIC) return fail(c, MHD_EUNSUPPORTED, "adjoint supports periodic boxes only");
+  if (c->stretched) return fail(c, MHD_EUNSUPPORTED, "adjoint with a stretched z axis");
   if (!std::isfinite(dt) || !(dt > 0.0)) return fail(c, MHD_EINVAL, "dt must be finite and > 0");
   for (int a = 0; a < 8; ++a)
     for (int b = 0; b < 8; ++b)
@@ -1148,8 +1211,7 @@ int mhd_rhs_adjoint(mhd_ctx* c, void* const f[8], void* const wbar[8], void* con
   int rc;
   if ((rc = check8(c, f, "f")) || (rc = check8(c, wbar, "wbar")) || (rc = check8(c, fbar, "fbar")))
     return rc;
-  for (const auto& b : c->boxes)
-    if (b.bc_z != MHD_BC_PERIODIC) return fail(c, MHD_EUNSUPPORTED, "adjoint supports periodic boxes only");
+  if (c->stretched) return fail(c, MHD_EUNSUPPORTED, "adjoint with a stretched z axis");
   for (int a = 0; a < 8; ++a)
     for (int b = 0; b < 8; ++b)
       if (fbar[b] == f[a] || fbar[b] == wbar[a]) return fail(c, MHD_EINVAL, "fbar overlaps an input");

@@ -154,8 +154,12 @@ def turbulent(n=256, seed=2, gamma=5.0 / 3.0, mach=0.5, beta=1.0, kmax=8.0,
 
 
 def stratified(nx=512, ny=512, nz=512, seed=3, gamma=5.0 / 3.0, ngz=5,
-               scale_heights=4.0, noise=1e-3, beta_mid=100.0):
-    """Isothermal stratified box with closed z walls (unit cube interior)."""
+               scale_heights=4.0, noise=1e-3, beta_mid=100.0, stretch=None):
+    """Isothermal stratified box with closed z walls (unit cube interior).
+    stretch = (a, b): a stretched z axis with heights z = L s(u) at
+    u = (k - ngz + 1/2) / nz for the cell centres (k - ngz at the lower
+    faces), s(u) = u + a u (1 - u) + b u^2 (1 - u), ghost planes included;
+    the box then carries the centre heights as zc."""
     rng = np.random.default_rng(seed)
     L = 1.0
     H = L / scale_heights
@@ -163,8 +167,14 @@ def stratified(nx=512, ny=512, nz=512, seed=3, gamma=5.0 / 3.0, ngz=5,
     dz = L / nz
     nzt = nz + 2 * ngz
     kz = np.arange(nzt, dtype=np.float64) - ngz
-    zc = (kz + 0.5) * dz         # centre heights, z = 0 at the lower wall
-    zf = kz * dz                 # lower z-face heights
+    if stretch is None:
+        zc = (kz + 0.5) * dz     # centre heights, z = 0 at the lower wall
+        zf = kz * dz             # lower z-face heights
+    else:
+        a, b = stretch
+        s = lambda u: u + a * u * (1.0 - u) + b * u * u * (1.0 - u)
+        zc = L * s((kz + 0.5) / nz)
+        zf = L * s(kz / nz)
     rc = np.exp(-zc / H)
     rf = np.exp(-zf / H)
     shape = (nzt, ny, nx)
@@ -181,6 +191,8 @@ def stratified(nx=512, ny=512, nz=512, seed=3, gamma=5.0 / 3.0, ngz=5,
     bx = np.zeros(shape)
     by = np.zeros(shape)
     box = _box(nx, ny, nz, ngz=ngz, wall=True, L=(nx * dz, ny * dz, L))
+    if stretch is not None:
+        box["zc"] = tuple(float(z) for z in zc)
     params = dict(gamma=gamma, mu=1.0, gz=g, nu1=0.02, nu2=1.0, nu3=0.02,
                   nuE=1.0, nuB=1.0, c1=0.0, Cdt=0.3, Cdtd=0.7, Cdtr=0.1)
     return [rho, px, py, pz, e, bx, by, bz], box, params

@@ -148,13 +148,162 @@ def test_step_adjoint_ensemble_f64():
     ctx.close()
 
 
-def test_step_adjoint_rejects_walls():
+def _walled(nx, ny, nz, seed, ngz=5, Lx=None, Ly=None):
+    """A closed-wall isothermal atmosphere (4 scale heights) with seeded
+    density, energy, velocity and field noise, so that every term and every
+    rule of the ghost fill is exercised."""
+    rng = np.random.default_rng(seed)
+    nzt = nz + 2 * ngz
+    H, g, gam = 0.25, 4.0, 5.0 / 3.0
+    zc = (np.arange(nzt) - ngz + 0.5) / nz
+    s = (nzt, ny, nx)
+    rho = np.exp(-zc / H).reshape(-1, 1, 1) * np.exp(0.05 * rng.standard_normal(s))
+    e = rho * g * H / (gam - 1.0) * np.exp(0.05 * rng.standard_normal(s))
+    f = [rho, 0.05 * rng.standard_normal(s) * rho, 0.05 * rng.standard_normal(s) * rho,
+         0.05 * rng.standard_normal(s) * rho, e, 0.1 + 0.02 * rng.standard_normal(s),
+         -0.05 + 0.02 * rng.standard_normal(s), 0.3 + 0.02 * rng.standard_normal(s)]
+    box = dict(nx=nx, ny=ny, nz=nz, ngz=ngz, wall=True, Lx=Lx or nx / nz, Ly=Ly or ny / nz, Lz=1.0)
+    prm = dict(gamma=gam, gz=g, nu1=0.02, nu2=1.0, nu3=0.02, nuE=1.0, nuB=1.0, c1=0.0)
+    return [np.ascontiguousarray(a) for a in f], box, prm
+
+
+WALL_TERMS = {
+    "core": dict(terms=O.T_ALL),
+    # every optional term; the second-order switch with every cell rough
+    # (the float64 mask then cannot differ from the oracle's by rounding)
+    "everything": dict(terms=O.T_ALL | O.T_EDIFFAV | O.T_LNP | O.T_DIVB | O.T_SMAG | O.T_MAX5 | O.T_QUENCH
+                       | O.T_ORDER2 | O.T_COOL | O.T_CORI, c_divb=0.08, c_smag=0.15, e_cool=1.4,
+                       t_cool=0.5, omega=(0.2, 0.4, 0.9), d2_lim=-1.0),
+    "nu_const": dict(terms=O.T_ALL, nu_const=0.011),
+}
+WALL_BOXES = {
+    "deep": (12, 10, 24, 61),
+    # nz < 2 ngz: the mirror planes of the two walls overlap
+    "shallow": (10, 8, 7, 62),
+    "aniso": (14, 9, 16, 63),
+}
+
+
+@pytest.mark.parametrize("terms", sorted(WALL_TERMS))
+@pytest.mark.parametrize("shape", sorted(WALL_BOXES))
+def test_step_adjoint_walls_f64(shape, terms):
+    """Closed z walls (Section 10): the step fills the ghost planes before
+    every evaluation of F and after the last stage, and F is zero in the
+    ghosts and for p_z on the wall faces; the adjoint transposes all of it,
+    and the oracle's autograd differentiates through its own fill."""
+    nx, ny, nz, seed = WALL_BOXES[shape]
+    f, box, prm = _walled(nx, ny, nz, seed, Lx=1.3 * nx / nz if shape == "aniso" else None)
+    errs = _adjoint_vs_oracle(f, box, prm, seed=seed, **WALL_TERMS[terms])
+    print(shape, terms, ["%.2e" % e for e in errs])
+    assert max(errs) < TOL_ADJ64, errs
+
+
+def _rhs_vjp_filled(f, g, p, w):
+    """(dF/df)^T w for F = the oracle's right-hand side with the ghost fill
+    (what mhd_rhs computes from a state)."""
+    x = tuple(t.detach().clone().requires_grad_(True) for t in f)
+    y = O.rhs(x, g, p)
+    gr = torch.autograd.grad(y, x, grad_outputs=tuple(w), allow_unused=True)
+    return [torch.zeros_like(a) if b is None else b for a, b in zip(f, gr)]
+
+
+@pytest.mark.parametrize("terms", ["core", "everything"])
+def test_rhs_adjoint_walls_f64(terms):
+    f, box, prm = _walled(12, 10, 20, 64)
+    over = WALL_TERMS[terms]
+    g, p = grid_params(box, prm, **over)
+    w = _randn_like(f, 65)
+    ctx = _ctx(box, prm, torch.float64, **over)
+    fd, wd = ctx.upload([f]), ctx.upload([w])
+    keep = [t.clone() for t in fd] + [t.clone() for t in wd]
+    out = ctx.rhs_adjoint(fd, wd)
+    # f and wbar are left as they were (the fill works on a copy)
+    for a, b in zip(list(fd) + list(wd), keep):
+        assert torch.equal(a, b)
+    want = _rhs_vjp_filled(to_cpu64(f), g, p, to_cpu64(w))
+    errs = rel_errors(ctx.box_view(out, 0), want)
+    ctx.close()
+    print(terms, ["%.2e" % e for e in errs])
+    assert max(errs) < TOL_ADJ64, errs
+
+
+def test_adjoint_walls_ensemble_and_transpose_f32():
+    """A walled and a periodic box in one context against the oracle
+    (float64), and <w, J v> = <J^T w, v> of one step against central
+    differences of the library's own float64 step, for the float32 adjoint."""
+    f1, b1, prm = _walled(10, 12, 14, 66)
+    f2, b2, _ = inputs.turbulent(n=12, seed=67)
+    b2 = dict(b2, Lx=12 / 14, Ly=12 / 14, Lz=12 / 14)   # the walled box's cell size
+    over = WALL_TERMS["everything"]
+    dts = []
+    for f, box in ((f1, b1), (f2, b2)):
+        g, p = grid_params(box, prm, **over)
+        dts.append(O.courant(to_cpu64(f), g, p)[0])
+    dt = 0.5 * min(dts)
+    gb = [_randn_like(f1, 68), _randn_like(f2, 69)]
+    ctx = _ctx([b1, b2], prm, torch.float64, **over)
+    out = ctx.step_adjoint(ctx.upload([f1, f2]), dt, ctx.upload(gb))
+    for bi, (f, box) in enumerate(((f1, b1), (f2, b2))):
+        g, p = grid_params(box, prm, **over)
+        want = O.step_vjp(to_cpu64(f), g, p, dt, to_cpu64(gb[bi]))
+        errs = rel_errors(ctx.box_view(out, bi), want)
+        assert max(errs) < TOL_ADJ64, (bi, errs)
+    # float64 and float32 adjoints against differences of the float64 step
+    # (walled box, the core terms: no caps or switches near the differences)
+    over = WALL_TERMS["core"]
+    c64 = _ctx(b1, prm, torch.float64, **over)
+    x = c64.upload([f1])
+    w = _randn_like(f1, 70)
+    v = _randn_like(f1, 71)
+    vd, wd = c64.upload([v]), c64.upload([w])
+    eps = 1e-7 * math.sqrt(_dot(x, x) / _dot(vd, vd))
+
+    def stepped(sign):
+        y = [a + sign * eps * b for a, b in zip(x, vd)]
+        c64.step(y, dt, 1)
+        return y
+    fd = (_dot(wd, stepped(1.0)) - _dot(wd, stepped(-1.0))) / (2 * eps)
+    ad64 = _dot(c64.step_adjoint(c64.upload([f1]), dt, wd), vd)
+    assert abs(ad64 - fd) <= 1e-6 * abs(fd), (ad64, fd)
+    c32 = _ctx(b1, prm, torch.float32, **over)
+    ad = _dot(c32.step_adjoint(c32.upload([f1]), dt, c32.upload([w])), c32.upload([v]))
+    assert abs(ad - fd) <= 1e-4 * abs(fd), (ad, fd)
+    for c in (ctx, c64, c32):
+        c.close()
+
+
+@pytest.mark.parametrize("ncheck", [1, 3])
+def test_rollout_walls_matches_oracle_f64(ncheck):
+    """Three checkpointed steps of a walled box with every optional term,
+    against the oracle's adjoint of the three steps."""
+    from paper_2405_02483_amd.rollout import rollout
+    f, box, prm = _walled(10, 9, 12, 72)
+    over = WALL_TERMS["everything"]
+    g, p = grid_params(box, prm, **over)
+    ft = to_cpu64(f)
+    dt = 0.5 * O.courant(ft, g, p)[0]
+    w = _randn_like(f, 73)
+    ctx = _ctx(box, prm, torch.float64, **over)
+    x = [t.requires_grad_(True) for t in ctx.upload([f])]
+    y = rollout(ctx, x, dt, 3, ncheck=ncheck)
+    loss = sum((a * b).sum() for a, b in zip(y, ctx.upload([w])))
+    grads = torch.autograd.grad(loss, x)
+    want = O.step_vjp(ft, g, p, dt, to_cpu64(w), nsteps=3)
+    errs = rel_errors(ctx.box_view([t.detach() for t in grads], 0), want)
+    ctx.close()
+    assert max(errs) < TOL_ADJ64, errs
+
+
+def test_adjoint_rejects_a_stretched_axis():
     from paper_2405_02483_amd.lib import MhdError, MHD_EUNSUPPORTED
-    f, box, prm = inputs.stratified(12, 10, 24, seed=3)
+    f, box, prm = inputs.stratified(12, 10, 24, seed=3, stretch=(0.3, -0.1))
     ctx = _ctx(box, prm, torch.float64)
     fd = ctx.upload([f])
     with pytest.raises(MhdError) as ei:
         ctx.step_adjoint(fd, 1e-3, ctx.zeros())
+    assert ei.value.code == MHD_EUNSUPPORTED
+    with pytest.raises(MhdError) as ei:
+        ctx.rhs_adjoint(fd, ctx.zeros())
     assert ei.value.code == MHD_EUNSUPPORTED
     ctx.close()
 
