@@ -463,6 +463,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="only the adjoint leg, e.g. under a profiler")
+    ap.add_argument("--clean-only", action="store_true",
+                    help="only the div B cleaning leg, e.g. under a profiler")
     ap.add_argument("--adjoint-size", type=int, default=128)
     ap.add_argument("--adjoint-steps", type=int, default=40)
     ap.add_argument("--workload", default="stratified", choices=("stratified", "turbulent"))
@@ -489,6 +491,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if a.adjoint_only:
         print(json.dumps({"adjoint": run_adjoint(a.adjoint_size, a.adjoint_steps)}), flush=True)
+        return
+    if a.clean_only:
+        print(json.dumps({"divb_clean": run_clean()}), flush=True)
         return
 
     window = None
