@@ -280,8 +280,9 @@ int mhd_step(mhd_ctx* ctx, void* const f[8], void* const tmp1[8],
  * closed walls the step's ghost fills (before every evaluation of F and
  * after the last stage) and the zeroing of F in the ghost planes and on the
  * wall faces are transposed too, so gbar_out is zero in the ghost planes
- * and for p_z on the wall faces (values the step overwrites).  A stretched
- * z axis is not differentiated (MHD_EUNSUPPORTED).  dt must be finite and
+ * and for p_z on the wall faces (values the step overwrites).  On a
+ * stretched z axis the per-plane Jacobians and lengths are constants of
+ * the differentiation, as dx, dy are.  dt must be finite and
  * > 0 (MHD_EINVAL otherwise: the Courant step of mhd_step's dt == 0 is not
  * differentiated).  f_n is not modified; gbar_in and gbar_out must not
  * overlap.                                                                 */
@@ -291,9 +292,8 @@ int mhd_step_adjoint(mhd_ctx* ctx, void* const f_n[8], double dt,
 /* Discrete adjoint of mhd_rhs: fbar = (dF/df)^T wbar at the state f (the
  * same non-smooth conventions as mhd_step_adjoint).  With walls F is what
  * mhd_rhs computes from f, ghost fill included, and fbar is zero where the
- * fill overwrites f.  Not with a stretched z axis (MHD_EUNSUPPORTED).  f
- * and wbar are not modified; fbar must not overlap them.  Allocates the
- * adjoint workspace on first use.                                          */
+ * fill overwrites f.  f and wbar are not modified; fbar must not overlap
+ * them.  Allocates the adjoint workspace on first use.                     */
 int mhd_rhs_adjoint(mhd_ctx* ctx, void* const f[8], void* const wbar[8],
                     void* const fbar[8]);
 

@@ -340,7 +340,7 @@ VProgram build_rhs_program(const mhd_params& p, double dt) {
                          B.ddydn(lne));
     // eq. ediffav: the z flux differentiates ln e_m - ln <e_m>_horiz
     const int lnez = (T & MHD_T_EDIFFAV) ? B.sub(lne, B.flog(B.pmean(em))) : lne;
-    const int fz = B.mul(B.mul(B.mul(B.scale(B.zdn(rho), p.nuE), B.scale(B.zdn(nt), 1.0, G_LZ)), B.zdn(em)),
+    const int fz = B.mul(B.mul(B.mul(B.scale(B.zdn(rho), p.nuE), B.scale(B.zdn(nt), 1.0, G_LZF)), B.zdn(em)),
                          B.ddzdn(lnez));
     de = B.add(B.add(B.add(de, B.ddxup(fx)), B.ddyup(fy)), B.ddzup(fz));
   }
@@ -363,7 +363,7 @@ VProgram build_rhs_program(const mhd_params& p, double dt) {
   // div B diffusion c_divb h_min^2 / dt grad(div B), with the step's dt
   if ((T & MHD_T_DIVB) && dt > 0.0) {
     const int divb = B.add(B.add(B.ddxup(bx), B.ddyup(by)), B.ddzup(bz));
-    auto kd = [&](int a) { return B.scale(B.scale(a, p.c_divb / dt, G_H), 1.0, G_H); };
+    auto kd = [&](int a) { return B.scale(B.scale(a, p.c_divb / dt, G_HMIN), 1.0, G_HMIN); };
     dbx = B.add(dbx, kd(B.ddxdn(divb)));
     dby = B.add(dby, kd(B.ddydn(divb)));
     dbz = B.add(dbz, kd(B.ddzdn(divb)));
@@ -574,6 +574,23 @@ __device__ __forceinline__ double geo_of(const BoxDev& b, int geo) {
   r = geo == G_LXY ? b.le[0] : r;
   r = geo == G_LXZ ? b.le[1] : r;
   r = geo == G_LYZ ? b.le[2] : r;
+  r = geo == G_LZF ? b.lv[2] : r;
+  r = geo == G_HMIN ? b.hmin : r;
+  return r;
+}
+
+// The same at plane k: on a stretched z axis the z-dependent factors come
+// from the plane's entries of the per-plane table.
+template <class T>
+__device__ __forceinline__ double geo_at(const BoxDev& b, int geo, const T* zt, int k) {
+  if (!b.stretched) return geo_of(b, geo);
+  const T* e = zt + b.joff + (long long)k * ZJ_COUNT;
+  double r = geo_of(b, geo);
+  r = geo == G_LZ ? double(e[ZJ_LZZ]) : r;
+  r = geo == G_LXZ ? double(e[ZJ_LXZ]) : r;
+  r = geo == G_LYZ ? double(e[ZJ_LYZ]) : r;
+  r = geo == G_LZF ? double(e[ZJ_LZF]) : r;
+  r = geo == G_H ? double(e[ZJ_H]) : r;
   return r;
 }
 
@@ -589,8 +606,18 @@ __device__ __forceinline__ T along(const T* a, const Geo<T>& g, int ax, int i, i
 constexpr int kWallReach = 6;
 
 __device__ __forceinline__ bool wall_z(const BoxDev& b, int ax) { return ax == VZ && b.wall; }
+// (on a stretched axis every plane takes the table forms: the Jacobian
+// varies from output to output, so the pair forms' transposes do not hold)
 __device__ __forceinline__ bool near_end(const BoxDev& b, int k) {
-  return k < kWallReach || k >= b.nzt - kWallReach;
+  return b.stretched || k < kWallReach || k >= b.nzt - kWallReach;
+}
+
+// The factor of a z derivative at output plane k of a wall-bounded axis:
+// the Jacobian of an up (centre) or down (face) output from the per-plane
+// table, with the end copy built in (1/dz on a uniform axis).
+template <class T>
+__device__ __forceinline__ T zjac(const T* zt, const BoxDev& b, int form, int k) {
+  return zt[b.joff + (long long)k * ZJ_COUNT + (form ? ZJ_C : ZJ_F)];
 }
 
 // Coefficient of input plane p in output plane k of a z operator on a
@@ -622,7 +649,7 @@ __device__ __forceinline__ T sten(const T* a, const Geo<T>& g, const BoxDev& bx,
     T acc = T(0);
     const int p0 = k - 3 > 0 ? k - 3 : 0, p1 = k + 3 < bx.nzt - 1 ? k + 3 : bx.nzt - 1;
     for (int p = p0; p <= p1; ++p) acc += zw_coef(zt, bx, fam, form, k, p) * a[g.at(i, j, p)];
-    return fam ? acc * hinv : acc;
+    return fam ? acc * (bx.stretched ? zjac(zt, bx, form, k) : hinv) : acc;
   }
   if (fam == 2) return form ? (at(1) - at(0)) * hinv : (at(0) - at(-1)) * hinv;
   if (fam == 0) return form ? op6<0, 1, T>(at, hinv) : op6<0, 0, T>(at, hinv);
@@ -639,6 +666,11 @@ __device__ __forceinline__ T sten_t(const T* yb, const Geo<T>& g, const BoxDev& 
     const T hinv = T(1.0 / bx.dz);
     T acc = T(0);
     const int k0 = k - 3 > 0 ? k - 3 : 0, k1 = k + 3 < bx.nzt - 1 ? k + 3 : bx.nzt - 1;
+    if (bx.stretched && fam) {
+      for (int q = k0; q <= k1; ++q)
+        acc += zw_coef(zt, bx, fam, form, q, k) * zjac(zt, bx, form, q) * yb[g.at(i, j, q)];
+      return acc;
+    }
     for (int q = k0; q <= k1; ++q) acc += zw_coef(zt, bx, fam, form, q, k) * yb[g.at(i, j, q)];
     return fam ? acc * hinv : acc;
   }
@@ -769,7 +801,18 @@ __global__ __launch_bounds__(kBlock) void k_vm_group(const BoxDev* boxes, const 
       case V_SUB: r = opnd(I.a, G.la) - opnd(I.b, G.lb); break;
       case V_MUL: r = opnd(I.a, G.la) * opnd(I.b, G.lb); break;
       case V_DIV: r = opnd(I.a, G.la) / opnd(I.b, G.lb); break;
-      case V_SCALE: r = T(I.k * geo_of(bx_, I.geo)) * opnd(I.a, G.la); break;
+      case V_SCALE: {
+        double gv;
+        if (bx_.stretched) {
+          int i, j, k;
+          coords(i, j, k);
+          gv = geo_at(bx_, I.geo, zt, k);
+        } else {
+          gv = geo_of(bx_, I.geo);
+        }
+        r = T(I.k * gv) * opnd(I.a, G.la);
+        break;
+      }
       case V_DIVC: r = opnd(I.a, G.la) / T(I.k); break;
       case V_SQRT: r = sqrt(opnd(I.a, G.la)); break;
       case V_LOG: r = log(opnd(I.a, G.la)); break;
@@ -937,7 +980,18 @@ __global__ __launch_bounds__(kBlock) void k_vm_bwd(const BoxDev* boxes, const Bl
         break;
       case V_SCALE:
 #pragma unroll
-        for (int r = 0; r < R; ++r) v1[r] = T(I.k * geo_of(boxes[bi[r]], I.geo)) * y[r];
+        for (int r = 0; r < R; ++r) {
+          const BoxDev& b = boxes[bi[r]];
+          double gv;
+          if (b.stretched) {
+            int i, j, k;
+            coords(r, i, j, k);
+            gv = geo_at(b, I.geo, zt, k);
+          } else {
+            gv = geo_of(b, I.geo);
+          }
+          v1[r] = T(I.k * gv) * y[r];
+        }
         put(ca, 1, v1);
         break;
       case V_DIVC:

@@ -47,10 +47,12 @@ enum VOp : int {
   V_COUNT
 };
 
-// Per-box geometric factors multiplying the constant k of V_SCALE / V_FILL:
-// the viscosity length factors of eq. nuij (BoxDev::lv, le), the smallest
-// spacing and its reciprocal.
-enum VGeo : int { G_ONE = 0, G_LX, G_LY, G_LZ, G_H, G_HINV, G_LXY, G_LXZ, G_LYZ };
+// Geometric factors multiplying the constant k of V_SCALE / V_FILL: the
+// viscosity length factors of eq. nuij (BoxDev::lv, le), the energy
+// diffusion's z length on the z-faces, the shock and Smagorinsky length,
+// the box's smallest spacing and its reciprocal.  On a stretched z axis
+// the z-dependent ones are the plane's (the per-plane table, ZJ_*).
+enum VGeo : int { G_ONE = 0, G_LX, G_LY, G_LZ, G_H, G_HINV, G_LXY, G_LXZ, G_LYZ, G_LZF, G_HMIN };
 
 // Axes of V_STEN / V_MAX3 / V_MEAN3 / V_D2.
 enum VAxis : int { VX = 0, VY = 1, VZ = 2 };

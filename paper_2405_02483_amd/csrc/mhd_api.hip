@@ -1197,7 +1197,6 @@ int mhd_step_adjoint(mhd_ctx* c, void* const f_n[8], double dt, void* const gin[
   if ((rc = check8(c, f_n, "f_n")) || (rc = check8(c, gin, "gbar_in")) ||
       (rc = check8(c, gout, "gbar_out")))
     return rc;
-  if (c->stretched) return fail(c, MHD_EUNSUPPORTED, "adjoint with a stretched z axis");
   if (!std::isfinite(dt) || !(dt > 0.0)) return fail(c, MHD_EINVAL, "dt must be finite and > 0");
   for (int a = 0; a < 8; ++a)
     for (int b = 0; b < 8; ++b)
@@ -1211,7 +1210,6 @@ int mhd_rhs_adjoint(mhd_ctx* c, void* const f[8], void* const wbar[8], void* con
   int rc;
   if ((rc = check8(c, f, "f")) || (rc = check8(c, wbar, "wbar")) || (rc = check8(c, fbar, "fbar")))
     return rc;
-  if (c->stretched) return fail(c, MHD_EUNSUPPORTED, "adjoint with a stretched z axis");
   for (int a = 0; a < 8; ++a)
     for (int b = 0; b < 8; ++b)
       if (fbar[b] == f[a] || fbar[b] == wbar[a]) return fail(c, MHD_EINVAL, "fbar overlaps an input");
