@@ -73,13 +73,13 @@ def log(msg):
 
 def kernel_source_hash(root=ROOT):
     """Hash of what builds the forward stage kernels: their sources without
-    `//` comments and blank lines, and the build flags (the adjoint's own
-    sources are left out).  The committed traffic counters are used only
-    while it matches."""
+    `//` comments and blank lines, and the build flags (the adjoint's and
+    the div B cleaning's own sources are left out).  The committed traffic
+    counters are used only while it matches."""
     h = hashlib.sha256()
     d = os.path.join(root, "paper_2405_02483_amd", "csrc")
     for name in sorted(os.listdir(d)):
-        if name.startswith("mhd_adjoint."):
+        if name.startswith(("mhd_adjoint.", "mhd_clean.")):
             continue
         if name.endswith((".hip", ".hpp")) or name == "build.py":
             for line in open(os.path.join(d, name), encoding="utf-8"):

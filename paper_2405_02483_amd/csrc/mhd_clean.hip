@@ -21,14 +21,24 @@ namespace {
 
 constexpr int kCleanBlock = 256;
 
+// Cell coordinates of box-local index q in 32-bit arithmetic (boxes hold
+// fewer than 2^31 cells; 64-bit division is emulated and slow).
+__device__ __forceinline__ void clean_coords(unsigned q, unsigned nx, unsigned ny, int& i, int& j, int& k) {
+  const unsigned qx = q / nx, qy = qx / ny;
+  i = (int)(q - qx * nx);
+  j = (int)(qx - qy * ny);
+  k = (int)qy;
+}
+
 // div B at the centres of one box (box-local output index).
 template <class T>
 __global__ __launch_bounds__(kCleanBlock) void k_clean_div(BoxDev b, const T* __restrict__ bx,
                                                            const T* __restrict__ by,
                                                            const T* __restrict__ bz, T* __restrict__ div) {
-  const long long q = (long long)blockIdx.x * kCleanBlock + threadIdx.x;
-  if (q >= b.ncell) return;
-  const int i = (int)(q % b.nx), j = (int)((q / b.nx) % b.ny), k = (int)(q / ((long long)b.nx * b.ny));
+  const unsigned q = blockIdx.x * kCleanBlock + threadIdx.x;
+  if ((long long)q >= b.ncell) return;
+  int i, j, k;
+  clean_coords(q, (unsigned)b.nx, (unsigned)b.ny, i, j, k);
   const Geo<T> g(b);
   div[q] = op6<1, 1, T>([&](int m) { return bx[g.at(i + m, j, k)]; }, g.hxi) +
            op6<1, 1, T>([&](int m) { return by[g.at(i, j + m, k)]; }, g.hyi) +
@@ -43,9 +53,10 @@ __global__ __launch_bounds__(kCleanBlock) void k_clean_solve(C* __restrict__ F, 
                                                              const T* __restrict__ k2y,
                                                              const T* __restrict__ k2z, int nxh, int ny, int nz,
                                                              T scale) {
-  const long long q = (long long)blockIdx.x * kCleanBlock + threadIdx.x;
-  if (q >= (long long)nxh * ny * nz) return;
-  const int i = (int)(q % nxh), j = (int)((q / nxh) % ny), k = (int)(q / ((long long)nxh * ny));
+  const unsigned q = blockIdx.x * kCleanBlock + threadIdx.x;
+  if ((long long)q >= (long long)nxh * ny * nz) return;
+  int i, j, k;
+  clean_coords(q, (unsigned)nxh, (unsigned)ny, i, j, k);
   const T L = k2x[i] + k2y[j] + k2z[k];
   C v = F[q];
   const T s = L > T(0) ? -scale / L : T(0);
@@ -59,9 +70,10 @@ template <class T>
 __global__ __launch_bounds__(kCleanBlock) void k_clean_apply(BoxDev b, const T* __restrict__ phi,
                                                              T* __restrict__ bx, T* __restrict__ by,
                                                              T* __restrict__ bz) {
-  const long long q = (long long)blockIdx.x * kCleanBlock + threadIdx.x;
-  if (q >= b.ncell) return;
-  const int i = (int)(q % b.nx), j = (int)((q / b.nx) % b.ny), k = (int)(q / ((long long)b.nx * b.ny));
+  const unsigned q = blockIdx.x * kCleanBlock + threadIdx.x;
+  if ((long long)q >= b.ncell) return;
+  int i, j, k;
+  clean_coords(q, (unsigned)b.nx, (unsigned)b.ny, i, j, k);
   const Geo<T> g(b);
   auto at = [&](int x, int y, int z) {
     x = x < 0 ? x + b.nx : (x >= b.nx ? x - b.nx : x);

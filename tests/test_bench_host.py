@@ -33,6 +33,10 @@ def test_source_hash_ignores_comments_but_not_code(tmp_path):
     adj = dst / "mhd_adjoint.hip"
     adj.write_text(adj.read_text() + "\nstatic int another_value = 2;\n")
     assert bench.kernel_source_hash(str(tmp_path)) == base
+    # nor do the div B cleaning's (not part of the stage)
+    cln = dst / "mhd_clean.hip"
+    cln.write_text(cln.read_text() + "\nstatic int a_third_value = 3;\n")
+    assert bench.kernel_source_hash(str(tmp_path)) == base
 
 
 def test_counters_are_dropped_for_other_sources(monkeypatch):
