@@ -165,7 +165,7 @@ def run_gpu(size, dtype, steps, warmup, workload="stratified", tile=None, over=N
         ctx.set_launch(launch[0], launch[1])
         ctx.set_final_tile(launch[2])
     elif tile is None:
-        tune = ctx.autotune(f, reps=2)          # tile shape and launch mode
+        tune = ctx.autotune(f, reps=3)          # tile shape and launch mode
     else:
         ctx.set_launch(tile, 0)
     work = (ctx.empty(), ctx.empty(), ctx.empty())
@@ -212,7 +212,7 @@ def run_gpu(size, dtype, steps, warmup, workload="stratified", tile=None, over=N
     stage_ms = sum(prof[p][0] for p in STAGE_PASSES) / (3 * steps)
     return dict(ms_per_step=ms, value=ncell * steps / (t1 - t0), stage_ms=stage_ms,
                 launch={"tile": launch[0], "persistent": launch[1], "final_pass_tile": ftile},
-                autotune_ms_per_rhs=None if tune is None else {
+                autotune_ms_per_stage=None if tune is None else {
                     "%s/%s" % (k[0], "persistent" if k[1] else "grid"): round(v, 4)
                     for k, v in tune.items()},
                 passes={k: (v[0] / max(v[1], 1), v[1]) for k, v in prof.items() if v[1]},
@@ -322,7 +322,7 @@ def run_ensemble(nbox=96, nsteps=20, ncheck=None):
             "forward_ms": (t1 - t0) * 1e3, "rollout_forward_ms": (t2 - t1) * 1e3,
             "backward_ms": (t3 - t2) * 1e3, "adjoint_over_forward": (t3 - t2) / (t1 - t0),
             "launch": {"tile": tile, "persistent": mode, "final_pass_tile": ftile},
-            "autotune_ms_per_rhs": {"%s/%s" % (k[0], "persistent" if k[1] else "grid"): round(v, 4)
+            "autotune_ms_per_stage": {"%s/%s" % (k[0], "persistent" if k[1] else "grid"): round(v, 4)
                                     for k, v in tune.items()}}
 
 
@@ -568,10 +568,11 @@ def main():
                          "issue_frac_of_stage": valu * ncell / VALU_LANE_RATE * 1e3 / r32["stage_ms"],
                          "peak_lane_instr_per_s": VALU_LANE_RATE}},
         "launch": r32["launch"],
-        "autotune_ms_per_rhs": r32["autotune_ms_per_rhs"],
+        "autotune_ms_per_stage": r32["autotune_ms_per_stage"],
     }
     if r64 is not None:
         out["fp64"] = {"value": r64["value"], "ms_per_step": r64["ms_per_step"],
+                       "autotune_ms_per_stage": r64["autotune_ms_per_stage"],
                        "stage_ms": r64["stage_ms"], "launch": r64["launch"],
                        "frac": (2 * stage_bytes / (r64["stage_ms"] * 1e-3) / 1e9) / HBM_PEAK_GBS,
                        "passes_ms": {k: round(v[0], 4) for k, v in r64["passes"].items()}}

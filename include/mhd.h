@@ -348,14 +348,18 @@ int mhd_set_final_tile(mhd_ctx* ctx, int32_t tile);
 int mhd_get_final_tile(const mhd_ctx* ctx, int32_t* tile);
 
 
-/* Autotuner: times reps evaluations of mhd_rhs(f, dfdt) (after one warm-up)
- * in every tile shape and launch mode, keeps the fastest and, if ms is not
- * NULL, writes the milliseconds per evaluation to ms[2 * tile + persistent]
- * (12 entries; 0 for a shape not built for the context's dtype).  Then, with
- * that shape for the other passes, times every shape for pass F alone in
- * both modes, and keeps the fastest combination if it beats the uniform
- * launch by more than 2 % (mhd_get_launch, mhd_get_final_tile).  dfdt is overwritten; with walls the ghost
- * planes of f are filled.  Waits for the stream.                           */
+/* Autotuner: times reps RK stages of the kind a step repeats (the right-hand
+ * side of f with the stage update: dU read and written, the next state
+ * written to scratch; after one mhd_rhs(f, dfdt) as warm-up) in every tile
+ * shape and launch mode, in three rounds over all of them, keeps the
+ * fastest (each candidate's best round) and, if ms is not NULL, writes the
+ * milliseconds per stage to ms[2 * tile + persistent] (12 entries; 0 for a
+ * shape not built for the context's dtype).  Then, with that shape for the
+ * other passes, times every shape for pass F alone in both modes (three
+ * rounds again), and keeps the fastest combination if it beats the uniform
+ * launch by more than 1 % (mhd_get_launch, mhd_get_final_tile).  dfdt is
+ * overwritten; with walls the ghost planes of f are filled.  Allocates 8
+ * fields of scratch for the call (MHD_ENOMEM).  Waits for the stream.      */
 int mhd_autotune(mhd_ctx* ctx, void* const f[8], void* const dfdt[8], int32_t reps,
                  double* ms);
 

@@ -462,10 +462,10 @@ class Context:
 
 
     def autotune(self, f, reps=3, dfdt=None):
-        """Times every tile shape and launch mode on f and keeps the fastest
-        (then, possibly, another shape for pass F alone: get_final_tile);
-        returns {(tile, persistent): ms per right-hand side} of the uniform
-        launches."""
+        """Times RK stages of f in every tile shape and launch mode and keeps
+        the fastest (then, possibly, another shape for pass F alone:
+        get_final_tile); returns {(tile, persistent): ms per stage} of the
+        uniform launches."""
         dfdt = dfdt if dfdt is not None else self.empty()
         ms = mhd_autotune(self.ctx, f, dfdt, reps, dtype=self.dtype, n=self.n)
         names = {v: k for k, v in TILES.items()}
