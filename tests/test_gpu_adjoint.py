@@ -531,8 +531,12 @@ def test_energy_gradient_128_cubed_40_steps():
     print("max error over %d directions: float32 (of |grad|/sqrt(n)) %.2e, float64 (relative) %.2e; "
           "float32 vs float64 gradient (L2) %.2e"
           % (ndir, worst[torch.float32], worst[torch.float64], l2))
+    # float64 against central differences: the stated 1e-4 (2.4e-5 measured);
+    # float32 against the float64 gradient: the stated 1e-4 in L2 (8.7e-5
+    # measured; the float32 trajectory, not the adjoint, sets it), and per direction
+    # 3e-4 of the typical directional derivative (1.8e-4 measured)
     assert worst[torch.float64] <= 1e-4, worst
-    assert worst[torch.float32] <= 5e-4 and l2 <= 2e-4, (worst, l2)
+    assert worst[torch.float32] <= 3e-4 and l2 <= 1e-4, (worst, l2)
 
 
 def _plane_terms(name):
