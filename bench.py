@@ -18,14 +18,16 @@ and the vector-issue ceiling of the counted VALU instructions), the same
 float32 workload with each optional term on (Newtonian cooling, the Coriolis
 force, energy diffusion about the horizontal mean, the ln(P/P_aver) pressure
 gradient, div B diffusion, the Smagorinsky viscosity with the five-cell
-maximum, quenching, the second-order switch), the adjoint and ensemble legs,
-and the CPU oracle timed on a bounded sample: one RK step of a full-height
-column window of the same state, whose central columns the float32 step of
-the whole box is compared with, field by field.
+maximum, quenching, the second-order switch, a stretched z axis), div B
+cleaning of a 256^3 box, the adjoint and ensemble legs, and the CPU oracle
+timed on a bounded sample: one RK step of a full-height column window of the
+same state, whose central columns the float32 step of the whole box is
+compared with, field by field.
 
     python bench.py [--steps K] [--warmup W] [--size N] [--no-fp64]
                     [--no-cpu-baseline] [--no-adjoint] [--no-sources] [--tile TXxTY]
     python bench.py --adjoint-only  (the adjoint leg alone, for profiling)
+    python bench.py --clean-only    (the div B cleaning leg alone, for profiling)
     python bench.py --cpu-table     (the CPU oracle alone, 32^3..256^3)
 """
 import argparse
