@@ -30,19 +30,40 @@ __device__ __forceinline__ void clean_coords(unsigned q, unsigned nx, unsigned n
   k = (int)qy;
 }
 
+// The stencil kernels march along z: one thread per (x, y) column and
+// chunk of kCleanZ planes, the z operand in a register window of six
+// planes, so each plane of it is read once per chunk (plus the window's
+// warm-up) instead of six times.  A workgroup covers kCleanTX x kCleanTY
+// columns, so the rows of a y stencil are mostly shared within it.
+constexpr int kCleanZ = 32;
+constexpr int kCleanTX = 64, kCleanTY = kCleanBlock / kCleanTX;
+
+__device__ __forceinline__ int wrapz(int k, int n) { return k < 0 ? k + n : (k >= n ? k - n : k); }
+
 // div B at the centres of one box (box-local output index).
 template <class T>
 __global__ __launch_bounds__(kCleanBlock) void k_clean_div(BoxDev b, const T* __restrict__ bx,
                                                            const T* __restrict__ by,
                                                            const T* __restrict__ bz, T* __restrict__ div) {
-  const unsigned q = blockIdx.x * kCleanBlock + threadIdx.x;
-  if ((long long)q >= b.ncell) return;
-  int i, j, k;
-  clean_coords(q, (unsigned)b.nx, (unsigned)b.ny, i, j, k);
+  const int i = (int)(blockIdx.x * kCleanTX + threadIdx.x % kCleanTX);
+  const int j = (int)(blockIdx.y * kCleanTY + threadIdx.x / kCleanTX);
+  if (i >= b.nx || j >= b.ny) return;
+  const unsigned nxy = (unsigned)b.nx * (unsigned)b.ny;
+  const unsigned q = (unsigned)j * (unsigned)b.nx + (unsigned)i;
+  const int z0 = (int)blockIdx.z * kCleanZ, z1 = min(z0 + kCleanZ, b.nzt);
   const Geo<T> g(b);
-  div[q] = op6<1, 1, T>([&](int m) { return bx[g.at(i + m, j, k)]; }, g.hxi) +
-           op6<1, 1, T>([&](int m) { return by[g.at(i, j + m, k)]; }, g.hyi) +
-           op6<1, 1, T>([&](int m) { return bz[g.at(i, j, k + m)]; }, g.hzi);
+  // window of bz at planes k-2 .. k+3 (the up derivative's samples)
+  T w[6];
+#pragma unroll
+  for (int m = 0; m < 5; ++m) w[m] = bz[g.at(i, j, wrapz(z0 - 2 + m, b.nzt))];
+  for (int k = z0; k < z1; ++k) {
+    w[5] = bz[g.at(i, j, wrapz(k + 3, b.nzt))];
+    div[(long long)k * nxy + q] = op6<1, 1, T>([&](int m) { return bx[g.at(i + m, j, k)]; }, g.hxi) +
+                                  op6<1, 1, T>([&](int m) { return by[g.at(i, j + m, k)]; }, g.hyi) +
+                                  op6<1, 1, T>([&](int m) { return w[m + 2]; }, g.hzi);
+#pragma unroll
+    for (int m = 0; m < 5; ++m) w[m] = w[m + 1];
+  }
 }
 
 // phi^ = -div^ / (K_x^2 + K_y^2 + K_z^2) times `scale` (the 1/N of the
@@ -70,21 +91,31 @@ template <class T>
 __global__ __launch_bounds__(kCleanBlock) void k_clean_apply(BoxDev b, const T* __restrict__ phi,
                                                              T* __restrict__ bx, T* __restrict__ by,
                                                              T* __restrict__ bz) {
-  const unsigned q = blockIdx.x * kCleanBlock + threadIdx.x;
-  if ((long long)q >= b.ncell) return;
-  int i, j, k;
-  clean_coords(q, (unsigned)b.nx, (unsigned)b.ny, i, j, k);
+  const int i = (int)(blockIdx.x * kCleanTX + threadIdx.x % kCleanTX);
+  const int j = (int)(blockIdx.y * kCleanTY + threadIdx.x / kCleanTX);
+  if (i >= b.nx || j >= b.ny) return;
+  const unsigned nxy = (unsigned)b.nx * (unsigned)b.ny;
+  const unsigned q = (unsigned)j * (unsigned)b.nx + (unsigned)i;
+  const int z0 = (int)blockIdx.z * kCleanZ, z1 = min(z0 + kCleanZ, b.nzt);
   const Geo<T> g(b);
   auto at = [&](int x, int y, int z) {
     x = x < 0 ? x + b.nx : (x >= b.nx ? x - b.nx : x);
     y = y < 0 ? y + b.ny : (y >= b.ny ? y - b.ny : y);
-    z = z < 0 ? z + b.nzt : (z >= b.nzt ? z - b.nzt : z);
-    return phi[((long long)z * b.ny + y) * b.nx + x];
+    return phi[(long long)z * nxy + (long long)y * b.nx + x];
   };
-  const long long o = b.off + q;
-  bx[o] -= op6<1, 0, T>([&](int m) { return at(i + m, j, k); }, g.hxi);
-  by[o] -= op6<1, 0, T>([&](int m) { return at(i, j + m, k); }, g.hyi);
-  bz[o] -= op6<1, 0, T>([&](int m) { return at(i, j, k + m); }, g.hzi);
+  // window of phi at planes k-3 .. k+2 (the down derivative's samples)
+  T w[6];
+#pragma unroll
+  for (int m = 0; m < 5; ++m) w[m] = at(i, j, wrapz(z0 - 3 + m, b.nzt));
+  for (int k = z0; k < z1; ++k) {
+    w[5] = at(i, j, wrapz(k + 2, b.nzt));
+    const long long o = b.off + (long long)k * nxy + q;
+    bx[o] -= op6<1, 0, T>([&](int m) { return at(i + m, j, k); }, g.hxi);
+    by[o] -= op6<1, 0, T>([&](int m) { return at(i, j + m, k); }, g.hyi);
+    bz[o] -= op6<1, 0, T>([&](int m) { return w[m + 3]; }, g.hzi);
+#pragma unroll
+    for (int m = 0; m < 5; ++m) w[m] = w[m + 1];
+  }
 }
 
 // K(theta_m)^2 of the sixth-order staggered derivative (eq. deriv) for
@@ -209,7 +240,8 @@ int clean_boxes(CleanState** sp, const std::vector<BoxDev>& boxes, P8<T> f, hipS
     for (const auto& q : s->plans)
       if (q.nx == b.nx && q.ny == b.ny && q.nz == b.nzt) p = &q;
     const int nxh = b.nx / 2 + 1;
-    const dim3 gc((unsigned)((b.ncell + kCleanBlock - 1) / kCleanBlock));
+    const dim3 gc((unsigned)((b.nx + kCleanTX - 1) / kCleanTX), (unsigned)((b.ny + kCleanTY - 1) / kCleanTY),
+                  (unsigned)((b.nzt + kCleanZ - 1) / kCleanZ));
     const long long nc = (long long)nxh * b.ny * b.nzt;
     const dim3 gk((unsigned)((nc + kCleanBlock - 1) / kCleanBlock));
     hipLaunchKernelGGL(k_clean_div<T>, gc, dim3(kCleanBlock), 0, stream, b, f.p[5], f.p[6], f.p[7], real);
