@@ -95,6 +95,7 @@ def test_null_arguments():
     assert L.mhd_step(None, null8, null8, null8, null8, 1e-3, 1) == lib.MHD_EINVAL
     assert L.mhd_step_adjoint(None, null8, 1e-3, null8, null8) == lib.MHD_EINVAL
     assert L.mhd_rhs_adjoint(None, null8, null8, null8) == lib.MHD_EINVAL
+    assert L.mhd_divb_clean(None, null8) == lib.MHD_EINVAL
     assert L.mhd_set_launch(None, 0, 0) == lib.MHD_EINVAL
     t, m = ctypes.c_int32(), ctypes.c_int32()
     assert L.mhd_get_launch(None, ctypes.byref(t), ctypes.byref(m)) == lib.MHD_EINVAL
