@@ -28,6 +28,7 @@ compared with, field by field.
                     [--no-cpu-baseline] [--no-adjoint] [--no-sources] [--tile TXxTY]
     python bench.py --adjoint-only  (the adjoint leg alone, for profiling)
     python bench.py --clean-only    (the div B cleaning leg alone, for profiling)
+    python bench.py --fp64-only     (the float64 step alone, for profiling)
     python bench.py --cpu-table     (the CPU oracle alone, 32^3..256^3)
 """
 import argparse
@@ -142,7 +143,7 @@ def _window(f_np, box, x0, y0, width):
 
 
 def run_gpu(size, dtype, steps, warmup, workload="stratified", tile=None, over=None,
-            launch=None, window=None, state_kw=None):
+            launch=None, window=None, state_kw=None, final_tile=None):
     """Times `steps` RK steps.  over: parameters replacing the workload's;
     launch: a (tile, persistent, final-pass tile) to use instead of tuning;
     window: (x0, y0) of a column window: after the timing, one step of the
@@ -170,6 +171,8 @@ def run_gpu(size, dtype, steps, warmup, workload="stratified", tile=None, over=N
         tune = ctx.autotune(f, reps=3)          # tile shape and launch mode
     else:
         ctx.set_launch(tile, 0)
+        if final_tile is not None:
+            ctx.set_final_tile(final_tile)
     work = (ctx.empty(), ctx.empty(), ctx.empty())
     torch.cuda.synchronize()
     ncell = size ** 3
@@ -465,6 +468,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="only the adjoint leg, e.g. under a profiler")
+    ap.add_argument("--final-tile", default=None,
+                    help="with --tile: pass F's own tile shape, e.g. 64x8")
+    ap.add_argument("--fp64-only", action="store_true",
+                    help="only the float64 step (in the --tile launch if given), e.g. under a profiler")
     ap.add_argument("--clean-only", action="store_true",
                     help="only the div B cleaning leg, e.g. under a profiler")
     ap.add_argument("--adjoint-size", type=int, default=128)
@@ -496,6 +503,11 @@ def main():
         return
     if a.clean_only:
         print(json.dumps({"divb_clean": run_clean()}), flush=True)
+        return
+    if a.fp64_only:
+        r = run_gpu(a.size, torch.float64, a.steps, a.warmup, a.workload, a.tile, final_tile=a.final_tile)
+        print(json.dumps({"fp64": {"ms_per_step": r["ms_per_step"], "value": r["value"],
+                                   "stage_ms": r["stage_ms"], "launch": r["launch"]}}), flush=True)
         return
 
     window = None
@@ -573,8 +585,13 @@ def main():
         "autotune_ms_per_stage": r32["autotune_ms_per_stage"],
     }
     if r64 is not None:
+        t64 = measured_traffic("f64")
         out["fp64"] = {"value": r64["value"], "ms_per_step": r64["ms_per_step"],
                        "autotune_ms_per_stage": r64["autotune_ms_per_stage"],
+                       # HBM bytes per stage counted in the 16x16 grid launch with
+                       # pass F in 64x8 (the autotuner's usual pick for this box)
+                       "traffic": t64,
+                       "traffic_GBs": None if t64 is None else t64 / (r64["stage_ms"] * 1e-3) / 1e9,
                        "stage_ms": r64["stage_ms"], "launch": r64["launch"],
                        "frac": (2 * stage_bytes / (r64["stage_ms"] * 1e-3) / 1e9) / HBM_PEAK_GBS,
                        "passes_ms": {k: round(v[0], 4) for k, v in r64["passes"].items()}}
