@@ -12,6 +12,10 @@ anisotropic: each axis's spacing is scaled by a random factor in [0.6, 1.6],
 so the viscosity length factors dx_a and max(dx_a, dx_b), the Courant limits
 and the div B scale see dx != dy != dz.
 
+A second sweep draws periodic, closed-wall and stretched boxes with a
+random subset of every optional term and checks the right-hand side, one RK
+step and the step's adjoint in float64.
+
 Error measure: relative L2 per field, as in the other parity tests.  In a
 closed-wall box the atmosphere is hydrostatic, so the z momentum rate is the
 small residual of the pressure gradient and gravity, each several hundred to
@@ -211,3 +215,93 @@ def test_step_adjoint_random_sizes_f64(seed):
     errs = _rel(got, want)
     assert max(errs) < 1e-10, ((nx, ny, nz), errs)
     ctx.close()
+
+
+def _noisy_walled(nx, ny, nz, seed, zc=None, ngz=5):
+    """A closed-wall atmosphere with 5 % noise on rho and e, velocity noise
+    and a tilted noisy field, at uniform or given (stretched) heights."""
+    rng = np.random.default_rng(seed)
+    nzt = nz + 2 * ngz
+    H, g, gam = 0.25, 4.0, 5.0 / 3.0
+    z = (np.arange(nzt) - ngz + 0.5) / nz if zc is None else np.asarray(zc)
+    s = (nzt, ny, nx)
+    rho = np.exp(-z / H).reshape(-1, 1, 1) * np.exp(0.05 * rng.standard_normal(s))
+    e = rho * g * H / (gam - 1.0) * np.exp(0.05 * rng.standard_normal(s))
+    f = [rho, 0.05 * rng.standard_normal(s) * rho, 0.05 * rng.standard_normal(s) * rho,
+         0.05 * rng.standard_normal(s) * rho, e, 0.1 + 0.02 * rng.standard_normal(s),
+         -0.05 + 0.02 * rng.standard_normal(s), 0.3 + 0.02 * rng.standard_normal(s)]
+    box = dict(nx=nx, ny=ny, nz=nz, ngz=ngz, wall=True, Lx=nx / nz, Ly=ny / nz, Lz=1.0)
+    if zc is not None:
+        box["zc"] = tuple(float(v) for v in zc)
+    prm = dict(gamma=gam, gz=g, nu1=0.02, nu2=1.0, nu3=0.02, nuE=1.0, nuB=1.0, c1=0.0)
+    return [np.ascontiguousarray(a) for a in f], box, prm
+
+
+OPTIONAL = (O.T_COOL, O.T_CORI, O.T_EDIFFAV, O.T_LNP, O.T_DIVB, O.T_SMAG, O.T_MAX5, O.T_QUENCH, O.T_ORDER2)
+
+
+@pytest.mark.parametrize("case", range(12))
+def test_rhs_step_adjoint_random_kinds_f64(case):
+    """Random periodic, walled and stretched boxes (6-36 cells per axis,
+    anisotropic), a random subset of every optional term (the second-order
+    switch with every cell rough, so rounding cannot move its mask), a random
+    launch: the right-hand side and one RK step (1e-12) and the step's
+    adjoint (1e-10) against the oracle.  In walled boxes the z momentum rate
+    is judged against the gravity term's size, as above."""
+    from paper_2405_02483_amd.lib import Context, TILES
+    r = random.Random(88000 + case)
+    kind = ("per", "wall", "str")[case % 3]
+    nx, ny, nz = r.randint(6, 36), r.randint(6, 36), r.randint(6, 32)
+    if kind == "per":
+        n = max(nx, ny, nz)
+        f, box, prm = inputs.turbulent(n=n, seed=88000 + case, kmax=3.0)
+        f = [np.ascontiguousarray(a[:nz, :ny, :nx]) for a in f]
+        box = dict(box, nx=nx, ny=ny, nz=nz, Lx=nx / n, Ly=ny / n, Lz=nz / n)
+    else:
+        zc = None
+        if kind == "str":
+            nz = max(nz, 12)
+            a, b = r.uniform(-0.3, 0.3), r.uniform(-0.15, 0.15)
+            u = (np.arange(nz + 10) - 5 + 0.5) / nz
+            zc = u + a * u * (1 - u) + b * u * u * (1 - u)
+            assert np.all(np.diff(zc) > 0.2 / nz)
+        f, box, prm = _noisy_walled(nx, ny, nz, 88000 + case, zc=zc)
+    box = dict(box, Lx=box["Lx"] * r.uniform(0.7, 1.4), Ly=box["Ly"] * r.uniform(0.7, 1.4))
+    terms = O.T_ALL
+    for bit in OPTIONAL:
+        if r.random() < 0.4:
+            terms |= bit
+    over = dict(terms=terms, c_smag=r.uniform(0.05, 0.3), e_cool=r.uniform(0.8, 2.0), t_cool=r.uniform(0.3, 2.0),
+                rho_cool=r.uniform(0.2, 2.0), cool_cut=r.randrange(3), omega=tuple(r.uniform(-1, 1) for _ in range(3)),
+                c_divb=0.05, d2_lim=-1.0, q_max=r.uniform(3, 9), q_lim=r.uniform(1.5, 3))
+    if r.random() < 0.15:
+        over["nu_const"] = r.uniform(0.005, 0.02)
+    g, p = grid_params(box, prm, **over)
+    ft = O.ghost_fill(tuple(torch.from_numpy(a.copy()) for a in f), g)
+    want = O.rhs(ft, g, p)
+    wall = box.get("wall", False)
+    view = (lambda t: interior(t, box)) if wall else (lambda t: t)
+    norms = [float(torch.linalg.norm(t)) for t in view(want)]
+    scale = [max(nm, 1e-3 * max(norms)) for nm in norms]
+    if wall:
+        g2, p2 = grid_params(box, prm, terms=O.T_GRAV)
+        scale = [max(s, float(torch.linalg.norm(t))) for s, t in zip(scale, interior(O.rhs(ft, g2, p2), box))]
+    ctx = Context(box, dict(prm, **over), dtype=torch.float64)
+    names = list(TILES)
+    ctx.set_launch(r.choice(names), r.randrange(2))
+    ctx.set_final_tile(r.choice(names))
+    fn = [a.numpy() for a in ft]
+    errs = _errors(view(ctx.box_view(ctx.rhs(ctx.upload([fn])), 0)), view(want), scale)
+    assert max(errs) < 1e-12, ("rhs", kind, errs)
+    dt = 0.5 * O.courant(ft, g, p)[0]
+    fs = ctx.upload([fn])
+    ctx.step(fs, dt, 1)
+    want = O.step(ft, g, p, dt, 1)
+    errs = _errors(view(ctx.box_view(fs, 0)), view(want), [float(torch.linalg.norm(t)) for t in view(want)])
+    assert max(errs) < 1e-12, ("step", kind, errs)
+    gb = [np.random.default_rng(case).standard_normal(a.shape) for a in fn]
+    out = ctx.step_adjoint(ctx.upload([fn]), dt, ctx.upload([gb]))
+    want = O.step_vjp(ft, g, p, dt, tuple(torch.from_numpy(x) for x in gb))
+    errs = _errors(ctx.box_view(out, 0), want, [float(torch.linalg.norm(t)) for t in want])
+    ctx.close()
+    assert max(errs) < 1e-10, ("adjoint", kind, errs)
