@@ -249,8 +249,9 @@ int mhd_rhs(mhd_ctx* ctx, void* const f[8], void* const dfdt[8]);
  * tables, queue counters) lives in a static device array of 64 MiB that
  * each GPU holds from the first mhd_init on it until the process ends; the
  * context's tables come from mhd_init.  That fits about 490,000 cells of
- * float32 or 245,000 of float64 (ghost planes included; 34 arrays per cell
- * plus small per-plane tables).  MHD_EINVAL, with the bytes needed in
+ * float32 or 245,000 of float64 (ghost planes included; 34 arrays per cell,
+ * 40 with MHD_T_QUENCH, 42 with MHD_T_ORDER2, plus small per-plane
+ * tables).  MHD_EINVAL, with the bytes needed in
  * mhd_last_error, when the context's boxes need more; MHD_EHIP when the array is
  * not available on the device.  Every call on one GPU shares the one array
  * and overwrites its contents: calls that overlap on one GPU (other
