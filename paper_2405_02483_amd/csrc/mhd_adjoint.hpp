@@ -3,10 +3,14 @@
 // max/mean over three cells, pointwise arithmetic) in the order of the
 // equations of Sections 3-6 of the paper.  Running it forward keeps every
 // intermediate in its own slot; running it backward applies each
-// operation's transpose.  Periodic boxes only: on a periodic axis the
-// transpose of an interpolation is the interpolation of the opposite
-// stagger, and the transpose of a derivative is minus the derivative of the
-// opposite stagger.
+// operation's transpose.  On a periodic axis the transpose of an
+// interpolation is the interpolation of the opposite stagger, and the
+// transpose of a derivative is minus the derivative of the opposite
+// stagger; near the ends of a wall-bounded z axis, and on every plane of a
+// stretched one, the z operators and their transposes use the box's
+// coefficient tables (reduced orders, the end copy, the plane's Jacobian).
+// The ghost fill of a wall box is not part of the program: its transpose
+// is applied between the stages (vm_fill_vjp).
 #pragma once
 
 #include <vector>
@@ -31,11 +35,14 @@ enum VOp : int {
   V_RELU,       // out = max(0, a)            (derivative 0 at a <= 0)
   V_FLOOR,      // out = a > k ? a : k        (derivative 0 at a <= k)
   V_NORM3,      // out = |(a, b, c)|          (derivative 0 at the origin)
-  V_MAX3,       // out = max over cells i-1, i, i+1 along ax (first maximal one)
-  V_MEAN3,      // out = (f[i-1] + f[i] + f[i+1]) / 3 along ax
+  V_MAX3,       // out = max over cells i-1, i, i+1 along ax (first maximal one;
+                //   the available ones at the ends of a wall-bounded z axis)
+  V_MEAN3,      // out = (f[i-1] + f[i] + f[i+1]) / 3 along ax (the mean of the
+                //   available ones at the ends of a wall-bounded z axis)
   V_FILL,       // out = k * geo (or k / h with G_HINV)
   V_ABS,        // out = |a|                  (derivative 0 at a = 0)
-  V_D2,         // out = a[i+1] - 2 a[i] + a[i-1] along ax (periodic)
+  V_D2,         // out = a[i+1] - 2 a[i] + a[i-1] along ax (0 on the end
+                //   planes of a wall-bounded z axis)
   V_SDIV,       // out = b > 0 ? a / b : 0
   V_CAP,        // out = a < k ? a : k        (derivative 0 at a >= k)
   V_ROUGH,      // out = 1 if a cell touching position ax (0 centre, 1 x-, 2 y-,
