@@ -1,6 +1,8 @@
 // C ABI of libstaggermhd (declared in include/mhd.h): context set-up,
 // argument checks, workspace ownership and the sequencing of the kernel
-// passes for mhd_rhs, mhd_step, mhd_step_adjoint and mhd_reductions.
+// passes for mhd_rhs, mhd_step, mhd_step_adjoint, mhd_rhs_adjoint,
+// mhd_reductions and mhd_divb_clean; the spline intervals of a stretched z
+// axis and the per-plane and wall tables; the autotuner.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
