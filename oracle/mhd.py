@@ -82,6 +82,17 @@ garbled:
 * eq. mom, Coriolis force: -2 rho Omega x u = -2 Omega x p, with each
   momentum component carried to the face of the component it drives by the
   staggered interpolations (e.g. p_z at an x-face is xdn(zup(p_z))).
+* eq. clean1, eq. clean2 (div B cleaning): the potential solves the
+  Poisson equation of the discrete operators themselves, sum_a
+  ddaup(ddadn(phi)) = div B, in Fourier space (symbol -(K_x^2 + K_y^2 +
+  K_z^2) with K the sixth-order derivative symbol; the mean mode's phi is
+  0), so the cleaned field is discretely solenoidal; periodic boxes only.
+* Section 4.2 (stretched z axis): the grid interval is the derivative of
+  the not-a-knot cubic spline through the cell-centre heights against the
+  plane index, taken at each derivative's output (centre or face); z
+  derivatives are index-space stencils times its inverse, interpolations
+  and the ghost fill stay in index space, and every length factor takes
+  the spacing at its own height (see viscosity_lengths, z_face_length).
 """
 from dataclasses import dataclass, field, replace
 import math
