@@ -19,7 +19,8 @@ float32 workload with each optional term on (Newtonian cooling, the Coriolis
 force, energy diffusion about the horizontal mean, the ln(P/P_aver) pressure
 gradient, div B diffusion, the Smagorinsky viscosity with the five-cell
 maximum, quenching, the second-order switch, a stretched z axis), div B
-cleaning of a 256^3 box, the adjoint and ensemble legs, and the CPU oracle
+cleaning of a 256^3 box, the adjoint legs (the 128^3 turbulent box; a 64^3
+walled box with every optional term) and the ensemble leg, and the CPU oracle
 timed on a bounded sample: one RK step of a full-height column window of the
 same state, whose central columns the float32 step of the whole box is
 compared with, field by field.
@@ -246,16 +247,25 @@ def stream_copy_gbs(nbytes=1 << 30, reps=10):
     return 2 * nbytes / sec / 1e9
 
 
-def run_adjoint(n=128, nsteps=40, ncheck=None, dtype_name="f32"):
+def run_adjoint(n=128, nsteps=40, ncheck=None, dtype_name="f32", stratified=False):
     """Gradient of a linear functional of the state after nsteps RK steps on
     the n^3 turbulent box (seed 4): forward time vs checkpointed backward.
-    ncheck None: as many checkpoints as half the free device memory holds."""
+    ncheck None: as many checkpoints as half the free device memory holds.
+    stratified: the n^3 stratified box instead (closed walls, 2 x 5 ghost
+    planes) with every optional term on (the second-order switch at its
+    namelist limit)."""
     import torch
     from paper_2405_02483_amd import inputs
-    from paper_2405_02483_amd.lib import Context
+    from paper_2405_02483_amd.lib import (Context, T_ALL, T_COOL, T_CORI, T_EDIFFAV, T_LNP, T_DIVB,
+                                          T_SMAG, T_MAX5, T_QUENCH, T_ORDER2)
     from paper_2405_02483_amd.rollout import checkpoint_budget, reversal_cost, rollout
     dtype = torch.float32 if dtype_name == "f32" else torch.float64
-    f, box, prm = inputs.turbulent(n=n, seed=4)
+    if stratified:
+        f, box, prm = inputs.stratified(n, n, n, seed=3)
+        prm = dict(prm, **COOLING, **CORIOLIS, terms=T_ALL | T_COOL | T_CORI | T_EDIFFAV | T_LNP | T_DIVB | T_SMAG
+                   | T_MAX5 | T_QUENCH | T_ORDER2, c_divb=0.05, c_smag=0.15, q_max=8.0, q_lim=2.0, d2_lim=0.3)
+    else:
+        f, box, prm = inputs.turbulent(n=n, seed=4)
     ctx = Context(box, prm, dtype=dtype)
     x0 = ctx.upload([f])
     dt = ctx.reductions(x0)["dt"]
@@ -274,7 +284,8 @@ def run_adjoint(n=128, nsteps=40, ncheck=None, dtype_name="f32"):
     t2 = time.perf_counter()
     ctx.close()
     torch.cuda.empty_cache()
-    return {"workload": "turbulent_%d, %d RK steps, %s, %d checkpoints" % (n, nsteps, dtype_name, ncheck),
+    name = ("stratified_%d (walls, every optional term)" if stratified else "turbulent_%d") % n
+    return {"workload": "%s, %d RK steps, %s, %d checkpoints" % (name, nsteps, dtype_name, ncheck),
             "forward_ms": (t1 - t0) * 1e3, "backward_ms": (t2 - t1) * 1e3,
             "adjoint_over_forward": (t2 - t1) / (t1 - t0),
             "recomputed_steps": reversal_cost(nsteps, ncheck)}
@@ -624,6 +635,8 @@ def main():
     if not a.no_adjoint:
         log("adjoint leg")
         out["adjoint"] = run_adjoint(a.adjoint_size, a.adjoint_steps)
+        log("adjoint leg, walled box with every optional term")
+        out["adjoint_walls"] = run_adjoint(64, 20, stratified=True)
         log("ensemble leg")
         out["ensemble"] = run_ensemble()
     if not a.no_cpu_baseline and r32["window"] is not None:
