@@ -315,6 +315,9 @@ int mhd_reductions(mhd_ctx* ctx, void* const f[8], void* const dfdt[8],
  * K_z^2) with K the sixth-order derivative symbol (the mean mode's phi is
  * 0); then B_a -= ddadn(phi).  Afterwards the discrete div B is zero to
  * rounding; a discrete curl is unchanged; the other fields are untouched.
+ * The projection is orthogonal for the sum of squares over the faces (the
+ * down derivative is minus the transpose of the up one), so it is its own
+ * adjoint.
  * Needs periodic boxes (MHD_EUNSUPPORTED with walls).  The first call
  * makes rocFFT plans per box shape and allocates scratch for the largest
  * box (about 3 of its fields), kept until mhd_destroy (MHD_ENOMEM,

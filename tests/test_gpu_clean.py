@@ -107,3 +107,25 @@ def test_walls_are_refused():
         ctx.divb_clean(fd)
     assert ei.value.code == MHD_EUNSUPPORTED
     ctx.close()
+
+
+@pytest.mark.parametrize("case", ["ragged_aniso", "odd_min"])
+def test_cleaning_is_symmetric_f64(case):
+    """The projection is symmetric (its own adjoint): <P u, v> = <u, P v>
+    over the faces, for two unrelated fields u and v (float64)."""
+    f, box, prm = _case(case, seed=63)
+    rng = np.random.default_rng(64)
+    g = [a.copy() for a in f]
+    for v in (5, 6, 7):
+        g[v] = rng.standard_normal(f[v].shape)
+    ctx = _ctx(box, prm, torch.float64)
+    u = ctx.upload([f])
+    w = ctx.upload([g])
+    b_u = [t.clone() for t in u[5:]]
+    b_w = [t.clone() for t in w[5:]]
+    ctx.divb_clean(u)
+    ctx.divb_clean(w)
+    lhs = sum(float((a * b).sum()) for a, b in zip(u[5:], b_w))
+    rhs = sum(float((a * b).sum()) for a, b in zip(b_u, w[5:]))
+    ctx.close()
+    assert abs(lhs - rhs) < 1e-12 * max(abs(lhs), abs(rhs))

@@ -108,3 +108,24 @@ def test_symbol_is_the_operator_on_a_mode():
         f = torch.cos(2 * torch.pi * m * x / n + 0.3).view(1, 1, n).expand(6, 6, n).contiguous()
         lap = Ops.ddxup(Ops.ddxdn(f))
         assert torch.allclose(lap, -(K[m] ** 2) * f, rtol=0, atol=1e-11 * (1 + float(K[m] ** 2)))
+
+
+@pytest.mark.parametrize("shape,aniso", CASES)
+def test_cleaning_is_an_orthogonal_projection(shape, aniso):
+    """On a periodic grid the down derivative is minus the transpose of the
+    up derivative, so P = I - G (D G)^-1 D with D the divergence and G the
+    gradient is symmetric: <P u, v> = <u, P v> for the sum over faces, and
+    P u is orthogonal to every discrete gradient.  (Its adjoint is itself.)"""
+    g = _grid(shape, aniso)
+    Ops = g.ops()
+    u, v = _rand(g, 5, 3), _rand(g, 6, 3)
+    pu = O.divb_clean(_state(g, *u), g)[5:]
+    pv = O.divb_clean(_state(g, *v), g)[5:]
+    lhs = sum(float((a * b).sum()) for a, b in zip(pu, v))
+    rhs = sum(float((a * b).sum()) for a, b in zip(u, pv))
+    assert abs(lhs - rhs) < 1e-12 * max(abs(lhs), 1.0)
+    psi = _rand(g, 7, 1)[0]
+    grad = (Ops.ddxdn(psi), Ops.ddydn(psi), Ops.ddzdn(psi))
+    ip = sum(float((a * b).sum()) for a, b in zip(pu, grad))
+    scale = (sum(float((a * a).sum()) for a in pu) * sum(float((a * a).sum()) for a in grad)) ** 0.5
+    assert abs(ip) < 1e-12 * scale
