@@ -788,9 +788,10 @@ __global__ __launch_bounds__(TX * TY) void zQ(const BoxDev* __restrict__ boxes,
 // ---------------------------------------------------------------------------
 // P: everything that needs only x/y stencils, once per cell at its own
 // column: the z-directed edge (x-1/2, y-1/2) quantities Gxy, Gyx, Ez, Lxz,
-// Lyz, Qz (as in Q), the centre terms Gxx = tau_xx - xup(p_x) xup(u_x) - P,
-// Gyy, Qc = tau_xx S_xx + tau_yy S_yy - P div u, and the x/y-face energy
-// fluxes Hx, Hy (eq. ien, eq. ediffuse).
+// Lyz, Qz (as in Q), the centre terms Gxx = tau_xx - xup(p_x) xup(u_x),
+// Gyy, Qc = tau_xx S_xx + tau_yy S_yy - P div u, the x/y-face energy
+// fluxes Hx, Hy (eq. ien, eq. ediffuse) and the x/y-face pressure
+// gradients, kept out of the fluxes (face_dp).
 // TAU (quenching): only the raw stress components tau_xy, tau_xx, tau_yy,
 // into the workspace arrays q(TAU_*).
 template <class T, int TX, int TY, bool PERS, bool TAU = false>
@@ -822,9 +823,12 @@ __global__ __launch_bounds__(TX * TY) void zP(const BoxDev* __restrict__ boxes,
     load_plane(sR, f.p[0], b, i6, k);
     load_plane(&S(0, -3, -3), f.p[1], b, i3, k);
     load_plane(&S(1, -3, -3), f.p[2], b, i3, k);
-    load_plane(&S(2, -3, -3), f.p[4], b, i3, k);
-    load_plane(&S(3, -3, -3), f.p[5], b, i3, k);
-    load_plane(&S(4, -3, -3), f.p[6], b, i3, k);
+    // the stress alone (TAU) reads neither e nor the magnetic field
+    if constexpr (!TAU) {
+      load_plane(&S(2, -3, -3), f.p[4], b, i3, k);
+      load_plane(&S(3, -3, -3), f.p[5], b, i3, k);
+      load_plane(&S(4, -3, -3), f.p[6], b, i3, k);
+    }
     load_plane(&S(5, -3, -3), lntg, b, i3, k);
     __syncthreads();
     for (int t = threadIdx.x; t < P3::N; t += NT) {
@@ -836,9 +840,11 @@ __global__ __launch_bounds__(TX * TY) void zP(const BoxDev* __restrict__ boxes,
       s3[6 * P3::NP + t] = s3[0 * P3::NP + t] / rxd;
       s3[7 * P3::NP + t] = s3[1 * P3::NP + t] / ryd;
       s3[8 * P3::NP + t] = exp(s3[5 * P3::NP + t]);
-      const T emv = s3[2 * P3::NP + t] / rc;
-      s3[9 * P3::NP + t] = emv;
-      s3[10 * P3::NP + t] = log(emv);
+      if constexpr (!TAU) {
+        const T emv = s3[2 * P3::NP + t] / rc;
+        s3[9 * P3::NP + t] = emv;
+        s3[10 * P3::NP + t] = log(emv);
+      }
       s3[11 * P3::NP + t] = rxd;
       s3[12 * P3::NP + t] = ryd;
       // xdn(ln nu) is only needed on the own columns' y-strip
@@ -988,10 +994,12 @@ __global__ __launch_bounds__(TX * TY) void zRough(const BoxDev* __restrict__ box
 // (array WS_TQ0 + c): tau min(max of q over the 3x3x3 neighbourhood, q_lim),
 // q = D2 / (|tau| + D2 / q_max), D2 the sum over the axes of the absolute
 // second differences (none across the ends of a wall-bounded z axis), q = 0
-// where tau and D2 vanish.  The raw planes r-2, r-1, r sit in an LDS ring
-// (halo 2); q of plane r-1 on the tile and a one-cell rim goes to LDS, its
-// in-plane maximum over 3x3 cells into a z window (q >= 0, so a plane that
-// does not exist counts as 0), and plane r-2 is finished.
+// where tau and D2 vanish.  The raw planes sit in an LDS ring of four
+// (halo 2); each plane is fetched into registers one iteration ahead, so
+// its loads are in flight while the plane before it is worked on.  q of
+// plane r-1 on the tile and a one-cell rim goes to LDS, its in-plane
+// maximum over 3x3 cells into a z window (q >= 0, so a plane that does not
+// exist counts as 0), and plane r-2 is finished.
 template <class T, int TX, int TY>
 __global__ __launch_bounds__(TX * TY) void zQn(const BoxDev* __restrict__ boxes,
                                                const ZItem* __restrict__ items, int nitems,
@@ -1000,26 +1008,42 @@ __global__ __launch_bounds__(TX * TY) void zQn(const BoxDev* __restrict__ boxes,
   int* queue = nullptr;
   using P2 = Plane<TX, TY, 2>;
   using P1 = Plane<TX, TY, 1>;
+  using I2 = PlaneIdx<TX, TY, 2>;
+  static_assert(I2::NPER * I2::NT == P2::NP, "plane padding");
   constexpr int NT = TX * TY;
-  __shared__ T sT[3][P2::NP];
+  // ring slot of plane r: wrapm(r, 4).  Plane r overwrites plane r-4, last
+  // read two iterations earlier, with two barriers in between; so the
+  // writes need no barrier of their own.
+  __shared__ T sT[4][P2::NP];
   __shared__ T sQ[P1::NP];
   const int c = (int)blockIdx.y;
   const T* __restrict__ tin = ws.q(c);
   T* __restrict__ tout = ws.arr(WS_TQ0 + c);
   ZLOOP_BEGIN
-  PlaneIdx<TX, TY, 2> i2;
+  I2 i2;
   i2.init(b, it.x0, it.y0);
+  T pre[I2::NPER];
+  auto fetch = [&](int r) {
+    const T* __restrict__ s = tin + b.off + (long long)kk(r) * pstride;
+#pragma unroll
+    for (int i = 0; i < I2::NPER; ++i) pre[i] = s[i2.off[i]];
+  };
+  if (valid(it.z0 - 2)) fetch(it.z0 - 2);
   T wM[3] = {};   // slot m: in-plane maximum of q on plane r-3+m
   for (int r = it.z0 - 2; r <= it.z1 + 1; ++r) {
-    __syncthreads();
-    if (valid(r)) load_plane(sT[wrapm(r, 3)], tin, b, i2, kk(r));
+    if (valid(r)) {
+      T* __restrict__ dst = sT[wrapm(r, 4)];
+#pragma unroll
+      for (int i = 0; i < I2::NPER; ++i) dst[(int)threadIdx.x + i * NT] = pre[i];
+    }
+    if (r <= it.z1 && valid(r + 1)) fetch(r + 1);
     __syncthreads();
     const int p = r - 1;
     T m = T(0);
     if (r >= it.z0 && valid(p)) {
-      const T* A = sT[wrapm(p, 3)];
-      const T* Am = sT[wrapm(p - 1, 3)];
-      const T* Ap = sT[wrapm(p + 1, 3)];
+      const T* A = sT[wrapm(p, 4)];
+      const T* Am = sT[wrapm(p - 1, 4)];
+      const T* Ap = sT[wrapm(p + 1, 4)];
       const bool zok = valid(p - 1) && valid(p + 1);
       for (int t = threadIdx.x; t < P1::N; t += NT) {
         const int yy = t / P1::W, xx = t - yy * P1::W;
@@ -1042,7 +1066,7 @@ __global__ __launch_bounds__(TX * TY) void zQn(const BoxDev* __restrict__ boxes,
     if (own && oz >= it.z0 && oz < it.z1 && valid(oz)) {
       const T mz = fmax(fmax(wM[0], wM[1]), wM[2]);
       const T fac = mz < ph.q_lim ? mz : ph.q_lim;
-      tout[col(oz)] = sT[wrapm(oz, 3)][P2::at(tx, ty)] * fac;
+      tout[col(oz)] = sT[wrapm(oz, 4)][P2::at(tx, ty)] * fac;
     }
   }
   ZLOOP_END
