@@ -400,6 +400,20 @@ __global__ __launch_bounds__(TX * TY) void zA2(const BoxDev* __restrict__ boxes,
   ZLOOP_BEGIN
   PlaneIdx<TX, TY, MH + 1> i2;
   i2.init(b, it.x0, it.y0);
+  // plane r of nu_s is fetched into registers one iteration ahead (in
+  // flight while plane r-1 is worked on); the last fetch repeats the last
+  // valid plane
+  constexpr int NPF = PlaneIdx<TX, TY, MH + 1>::NPER;
+  static_assert(NPF * NT == PN::NP, "plane padding");
+  const int rfirst = wall ? max(it.z0 - MH - 1, 0) : it.z0 - MH - 1;
+  const int rlast = wall ? min(it.z1 + MH, N - 1) : it.z1 + MH;
+  T gN[NPF];
+  auto fetch = [&](int r_) {
+    const long long pk = b.off + (long long)kk(r_) * pstride;
+#pragma unroll
+    for (int i = 0; i < NPF; ++i) gN[i] = nus[pk + i2.off[i]];
+  };
+  fetch(rfirst);
   T wS[3] = {};
   double numax = 0.0;
   double rd = 0.0;
@@ -407,7 +421,9 @@ __global__ __launch_bounds__(TX * TY) void zA2(const BoxDev* __restrict__ boxes,
   for (int r = it.z0 - MH - 1; r <= it.z1 + MH; ++r) {
     if (valid(r)) {
       __syncthreads();
-      load_plane(sN, nus, b, i2, kk(r));
+#pragma unroll
+      for (int i = 0; i < NPF; ++i) sN[(int)threadIdx.x + i * NT] = gN[i];
+      fetch(r < rlast ? r + 1 : r);
       __syncthreads();
       T* dst = sMX[wrapm(r, MW)];
       for (int t = threadIdx.x; t < PM::N; t += NT) {
@@ -549,6 +565,27 @@ __global__ __launch_bounds__(TX * TY) void zQ(const BoxDev* __restrict__ boxes,
   constexpr bool kL = QM & QM_LNP;
   T wLq[6] = {}, wLpa[6] = {};
   const T inv_mu = ph.inv_mu;
+  // The ring planes (u_z; B_z and p_z) of plane r are fetched into
+  // registers one iteration ahead, after plane r-1's own-column loads, so
+  // that they are in flight while plane r-1 is worked on.  Planes past the
+  // last valid one are not fetched: the last fetch repeats that plane.
+  constexpr int N3 = PlaneIdx<TX, TY, 3>::NPER;
+  static_assert(N3 * TX * TY == P3::NP, "plane padding");
+  const int rfirst = wall ? max(it.z0 - 3, 0) : it.z0 - 3;
+  const int rlast = wall ? min(it.z1 + 2, N - 1) : it.z1 + 2;
+  T gU[N3], gB[N3], gP[N3];
+  auto fetch = [&](int r_) {
+    const long long pk = b.off + (long long)kk(r_) * pstride;
+#pragma unroll
+    for (int i = 0; i < N3; ++i) {
+      gU[i] = uzg[pk + i3.off[i]];
+      if constexpr (!kT) {
+        gB[i] = f.p[7][pk + i3.off[i]];
+        gP[i] = f.p[3][pk + i3.off[i]];
+      }
+    }
+  };
+  if constexpr (kE) fetch(rfirst);
   for (int r = it.z0 - 3; r <= it.z1 + 2; ++r) {
     T rx = T(0), lx = T(0), px = T(0), ux = T(0), bxv = T(0);
     T ry = T(0), ly = T(0), py = T(0), uy = T(0), byv = T(0);
@@ -561,24 +598,28 @@ __global__ __launch_bounds__(TX * TY) void zQ(const BoxDev* __restrict__ boxes,
         __syncthreads();
         load_plane(sR, f.p[0], b, i3, k);
         load_plane(sL, lntg, b, i3, k);
-        load_plane(sUZ[sl], uzg, b, i3, k);
-        if constexpr (!kT) {
-          load_plane(sBZ[sl], f.p[7], b, i3, k);
-          load_plane(sPZ[sl], f.p[3], b, i3, k);
+#pragma unroll
+        for (int i = 0; i < N3; ++i) {
+          sUZ[sl][(int)threadIdx.x + i * TX * TY] = gU[i];
+          if constexpr (!kT) {
+            sBZ[sl][(int)threadIdx.x + i * TX * TY] = gB[i];
+            sPZ[sl][(int)threadIdx.x + i * TX * TY] = gP[i];
+          }
         }
+        px = f.p[1][o];
+        py = f.p[2][o];
+        if constexpr (!kT) {
+          bxv = f.p[5][o];
+          byv = f.p[6][o];
+        }
+        fetch(r < rlast ? r + 1 : r);
         __syncthreads();
         rx = op6<0, 0, T>([&](int m) { return sR[P3::at(tx + m, ty)]; }, T(0));
         ry = op6<0, 0, T>([&](int m) { return sR[P3::at(tx, ty + m)]; }, T(0));
         lx = op6<0, 0, T>([&](int m) { return sL[P3::at(tx + m, ty)]; }, T(0));
         ly = op6<0, 0, T>([&](int m) { return sL[P3::at(tx, ty + m)]; }, T(0));
-        px = f.p[1][o];
-        py = f.p[2][o];
         ux = px / rx;
         uy = py / ry;
-        if constexpr (!kT) {
-          bxv = f.p[5][o];
-          byv = f.p[6][o];
-        }
       }
       if constexpr (kZ) {
         // own column only: from LDS when the planes are there
@@ -818,18 +859,44 @@ __global__ __launch_bounds__(TX * TY) void zP(const BoxDev* __restrict__ boxes,
   i3.init(b, it.x0, it.y0);
   const unsigned tm = ph.terms;
   auto S = [&](int q, int x, int y) -> T& { return s3[q * P3::NP + P3::at(x, y)]; };
+  // Some planes of z plane k are fetched into registers one iteration
+  // ahead, so that their loads are in flight while plane k-1 is worked on:
+  // B_x, B_y and ln <nu> (the stress alone, TAU, reads neither e nor the
+  // magnetic field: there p_x, p_y and ln <nu>).  The others are loaded in
+  // the iteration: fetching them too would cost the float32 64x8 launch a
+  // wave per SIMD.
+  constexpr int N3 = PlaneIdx<TX, TY, 3>::NPER;
+  static_assert(N3 * NT == P3::NP, "plane padding");
+  auto has3 = [](int q) { return !TAU || q < 2 || q == 5; };
+  auto ahead = [](int q) { return TAU ? (q < 2 || q == 5) : q >= 3; };
+  const T* __restrict__ src3[6] = {f.p[1], f.p[2], f.p[4], f.p[5], f.p[6], lntg};
+  T g3[6][N3];
+  auto fetch = [&](int k) {
+    const long long pk = b.off + (long long)k * pstride;
+#pragma unroll
+    for (int q = 0; q < 6; ++q)
+      if (ahead(q)) {
+#pragma unroll
+        for (int i = 0; i < N3; ++i) g3[q][i] = src3[q][pk + i3.off[i]];
+      }
+  };
+  fetch(it.z0);
   for (int k = it.z0; k < it.z1; ++k) {
     __syncthreads();
     load_plane(sR, f.p[0], b, i6, k);
-    load_plane(&S(0, -3, -3), f.p[1], b, i3, k);
-    load_plane(&S(1, -3, -3), f.p[2], b, i3, k);
-    // the stress alone (TAU) reads neither e nor the magnetic field
-    if constexpr (!TAU) {
-      load_plane(&S(2, -3, -3), f.p[4], b, i3, k);
-      load_plane(&S(3, -3, -3), f.p[5], b, i3, k);
-      load_plane(&S(4, -3, -3), f.p[6], b, i3, k);
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      if (ahead(q)) {
+#pragma unroll
+        for (int i = 0; i < N3; ++i) s3[q * P3::NP + (int)threadIdx.x + i * NT] = g3[q][i];
+      } else if (has3(q)) {
+        load_plane(&S(q, -3, -3), src3[q], b, i3, k);
+      }
     }
-    load_plane(&S(5, -3, -3), lntg, b, i3, k);
+    // this column's div u (an in-box address for every thread), then plane
+    // k + 1 (the last plane fetches itself again: no branch around loads)
+    const T Dc = Dg[colo + (long long)k * pstride];
+    fetch(k + 1 < it.z1 ? k + 1 : k);
     __syncthreads();
     for (int t = threadIdx.x; t < P3::N; t += NT) {
       const int yy = t / P3::W, xx = t - yy * P3::W;
@@ -855,7 +922,6 @@ __global__ __launch_bounds__(TX * TY) void zP(const BoxDev* __restrict__ boxes,
     if (!own) continue;
     const int x = tx, y = ty;
     const long long o = colo + (long long)k * pstride;
-    const T Dc = Dg[o];
     const T lpa = (tm & T_LNP) ? lnpav[b.poff + k] : T(0);
     // derived planes by id (mhd_zstage.hpp); ln(P / P_aver) on the fly
     auto SA = [&](int q, int xx, int yy) -> T {
