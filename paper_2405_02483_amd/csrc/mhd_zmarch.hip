@@ -586,7 +586,22 @@ __global__ __launch_bounds__(TX * TY) void zQ(const BoxDev* __restrict__ boxes,
     }
   };
   if constexpr (kE) fetch(rfirst);
+  // The z-face and centre launch likewise fetches plane r's own-column
+  // values one iteration ahead, and in every iteration div u of the next
+  // iteration's centre plane (at a valid plane whether or not that one is:
+  // unused then).
+  T zP_ = T(0), zU_ = T(0), zR_ = T(0), zL_ = T(0), zE_ = T(0), zD_ = T(0);
+  auto fetchz = [&](int r_) {
+    const long long o_ = col(r_);
+    zP_ = f.p[3][o_];
+    zU_ = uzg[o_];
+    zR_ = f.p[0][o_];
+    zL_ = lntg[o_];
+    zE_ = f.p[4][o_];
+  };
+  if constexpr (kZ && !kE) fetchz(rfirst);
   for (int r = it.z0 - 3; r <= it.z1 + 2; ++r) {
+    const T dq2 = zD_;   // div u at plane r - 3 (the centre plane below)
     T rx = T(0), lx = T(0), px = T(0), ux = T(0), bxv = T(0);
     T ry = T(0), ly = T(0), py = T(0), uy = T(0), byv = T(0);
     T pzv = T(0), uzv = T(0), ev = T(0), rhov = T(0), nuv = T(0), em = T(0), lem = T(0);
@@ -628,13 +643,15 @@ __global__ __launch_bounds__(TX * TY) void zQ(const BoxDev* __restrict__ boxes,
           uzv = sUZ[sl][P3::at(tx, ty)];
           rhov = sR[P3::at(tx, ty)];
           nuv = exp(sL[P3::at(tx, ty)]);
+          ev = f.p[4][o];
         } else {
-          pzv = f.p[3][o];
-          uzv = uzg[o];
-          rhov = f.p[0][o];
-          nuv = exp(lntg[o]);
+          pzv = zP_;
+          uzv = zU_;
+          rhov = zR_;
+          nuv = exp(zL_);
+          ev = zE_;
+          fetchz(r < rlast ? r + 1 : r);
         }
-        ev = f.p[4][o];
         em = ev / rhov;
         lem = log(em);
         // eq. ediffav: the z flux differentiates ln e_m - ln <e_m>
@@ -645,6 +662,7 @@ __global__ __launch_bounds__(TX * TY) void zQ(const BoxDev* __restrict__ boxes,
         }
       }
     }
+    if constexpr (kZ && !kE) zD_ = Dg[col(valid(r - 2) ? r - 2 : rfirst)];
     push(wRX, rx); push(wLX, lx); push(wPX, px); push(wUX, ux); push(wBX, bxv);
     push(wRY, ry); push(wLY, ly); push(wPY, py); push(wUY, uy); push(wBY, byv);
     push(wPZ, pzv); push(wUZ, uzv); push(wE, ev); push(wRho, rhov); push(wNu, nuv);
@@ -805,7 +823,7 @@ __global__ __launch_bounds__(TX * TY) void zQ(const BoxDev* __restrict__ boxes,
       const T jq2 = zj(q2, ZJ_C);
       const T szz = !o2 ? zwin<1, 1, 6, 2>(wUZ, q2, wall, N, jq2, zt)
                         : ((wall && q2 == N - 1) ? (wUZ[2] - wUZ[1]) * jq2 : (wUZ[3] - wUZ[2]) * jq2);
-      const T Dt = o2 ? ws.arr(WS_D2)[o] : Dg[o];
+      const T Dt = o2 ? ws.arr(WS_D2)[o] : (kE ? Dg[o] : dq2);
       if constexpr (kT) {
         if (own) ws.q(TAU_ZZ)[o] = wRho[2] * (zj(q2, ZJ_LZZ) * wNu[2]) * (szz + ph.c1 * Dt);
         continue;
