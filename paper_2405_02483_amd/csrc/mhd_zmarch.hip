@@ -75,23 +75,39 @@ __global__ __launch_bounds__(TX * TY) void zA1(const BoxDev* __restrict__ boxes,
   double rs[8] = {}, rdiv = 0.0, rbm = 0.0, rum = 0.0, rc = 0.0, rrate = 0.0;
   long long rca = 0x7fffffffffffffffLL, rra = 0x7fffffffffffffffLL, rnf = 0, rnp = 0;
   auto packed = [&](int k_) { return b.off + ((long long)k_ * b.ny + gy) * b.nx + gx; };
+  // rho (halo 5) of plane r is fetched into registers one iteration ahead;
+  // the last fetch repeats the last valid plane
+  constexpr int N5 = PlaneIdx<TX, TY, 5>::NPER;
+  static_assert(N5 * NT == PR::NP, "plane padding");
+  const int rfirst = wall ? max(it.z0 - 5, 0) : it.z0 - 5;
+  const int rlast = wall ? min(it.z1 + 4, N - 1) : it.z1 + 4;
+  T gR5[N5];
+  auto fetch = [&](int r_) {
+    const long long pk = b.off + (long long)kk(r_) * pstride;
+#pragma unroll
+    for (int i = 0; i < N5; ++i) gR5[i] = f.p[0][pk + i5.off[i]];
+  };
+  fetch(rfirst);
   for (int r = it.z0 - 5; r <= it.z1 + 4; ++r) {
     T rr = T(0), pz = T(0), e = T(0), bz = T(0);
     T ubx = T(0), uby = T(0), bbx = T(0), bby = T(0), dxy = T(0), dxb = T(0);
     if (valid(r)) {
       const int k = kk(r);
       __syncthreads();
-      load_plane(sR, f.p[0], b, i5, k);
+#pragma unroll
+      for (int i = 0; i < N5; ++i) sR[(int)threadIdx.x + i * NT] = gR5[i];
       load_plane(sPX, f.p[1], b, i3, k);
       load_plane(sPY, f.p[2], b, i3, k);
       load_plane(sBX, f.p[5], b, i3, k);
       load_plane(sBY, f.p[6], b, i3, k);
-      __syncthreads();
+      // the own column's values, in flight with the planes
       const long long o = col(r);
-      rr = sR[PR::at(tx, ty)];
       pz = f.p[3][o];
       e = f.p[4][o];
       bz = f.p[7][o];
+      fetch(r < rlast ? r + 1 : r);
+      __syncthreads();
+      rr = sR[PR::at(tx, ty)];
       // u_x = p_x / xdn(rho) on x-faces -2..3 of the own rows and u_y on
       // y-faces -2..3 of the own columns, one face per thread and pass
       for (int t = threadIdx.x; t < PP::N; t += NT) {
