@@ -1095,8 +1095,8 @@ __global__ __launch_bounds__(TX * TY) void zRough(const BoxDev* __restrict__ box
 // q = D2 / (|tau| + D2 / q_max), D2 the sum over the axes of the absolute
 // second differences (none across the ends of a wall-bounded z axis), q = 0
 // where tau and D2 vanish.  The raw planes sit in an LDS ring of four
-// (halo 2); each plane is fetched into registers one iteration ahead, so
-// its loads are in flight while the plane before it is worked on.  q of
+// (halo 2); each plane is fetched into registers two iterations ahead, so
+// its loads are in flight while the two planes before it are worked on.  q of
 // plane r-1 on the tile and a one-cell rim goes to LDS, its in-plane
 // maximum over 3x3 cells into a z window (q >= 0, so a plane that does not
 // exist counts as 0), and plane r-2 is finished.
@@ -1122,21 +1122,31 @@ __global__ __launch_bounds__(TX * TY) void zQn(const BoxDev* __restrict__ boxes,
   ZLOOP_BEGIN
   I2 i2;
   i2.init(b, it.x0, it.y0);
-  T pre[I2::NPER];
-  auto fetch = [&](int r) {
+  // two register sets, each holding a plane fetched two iterations ahead
+  T preA[I2::NPER], preB[I2::NPER];
+  auto fetch = [&](T (&d)[I2::NPER], int r) {
     const T* __restrict__ s = tin + b.off + (long long)kk(r) * pstride;
 #pragma unroll
-    for (int i = 0; i < I2::NPER; ++i) pre[i] = s[i2.off[i]];
+    for (int i = 0; i < I2::NPER; ++i) d[i] = s[i2.off[i]];
   };
-  if (valid(it.z0 - 2)) fetch(it.z0 - 2);
+  // planes outside a wall-bounded axis are not fetched: the fetches are
+  // clamped to the valid planes (unconditional, so that the compiler can
+  // count the loads in flight and wait for one set only)
+  const int r0 = it.z0 - 2;
+  const int rlo = wall ? max(r0, 0) : r0;
+  const int rhi = wall ? min(it.z1 + 1, N - 1) : it.z1 + 1;
+  auto clampr = [&](int r) { return r < rlo ? rlo : (r > rhi ? rhi : r); };
+  fetch(preA, clampr(r0));
+  fetch(preB, clampr(r0 + 1));
   T wM[3] = {};   // slot m: in-plane maximum of q on plane r-3+m
-  for (int r = it.z0 - 2; r <= it.z1 + 1; ++r) {
+  // iteration r: plane r (in cur) to its ring slot, plane r+2 into cur
+  auto body = [&](int r, T (&cur)[I2::NPER]) {
     if (valid(r)) {
       T* __restrict__ dst = sT[wrapm(r, 4)];
 #pragma unroll
-      for (int i = 0; i < I2::NPER; ++i) dst[(int)threadIdx.x + i * NT] = pre[i];
+      for (int i = 0; i < I2::NPER; ++i) dst[(int)threadIdx.x + i * NT] = cur[i];
     }
-    if (r <= it.z1 && valid(r + 1)) fetch(r + 1);
+    fetch(cur, clampr(r + 2));
     __syncthreads();
     const int p = r - 1;
     T m = T(0);
@@ -1168,6 +1178,10 @@ __global__ __launch_bounds__(TX * TY) void zQn(const BoxDev* __restrict__ boxes,
       const T fac = mz < ph.q_lim ? mz : ph.q_lim;
       tout[col(oz)] = sT[wrapm(oz, 4)][P2::at(tx, ty)] * fac;
     }
+  };
+  for (int r = r0; r <= it.z1 + 1; r += 2) {
+    body(r, preA);
+    if (r + 1 <= it.z1 + 1) body(r + 1, preB);
   }
   ZLOOP_END
 }
