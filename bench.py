@@ -221,7 +221,9 @@ def run_gpu(size, dtype, steps, warmup, workload="stratified", tile=None, over=N
                 autotune_ms_per_stage=None if tune is None else {
                     "%s/%s" % (k[0], "persistent" if k[1] else "grid"): round(v, 4)
                     for k, v in tune.items()},
-                passes={k: (v[0] / max(v[1], 1), v[1]) for k, v in prof.items() if v[1]},
+                # ms per RK stage of each pass (a pass may be timed in more
+                # than one interval of a stage: A2 around k_dt, Q around zRough)
+                passes={k: (v[0] / (3 * steps), v[1]) for k, v in prof.items() if v[1]},
                 dt_last=dt_last, mass=s_end["mass"], ncell=ncell, window=gpu_win)
 
 
