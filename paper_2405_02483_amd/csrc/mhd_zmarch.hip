@@ -1031,20 +1031,34 @@ __global__ __launch_bounds__(TX * TY) void zRough(const BoxDev* __restrict__ box
   ZLOOP_BEGIN
   I2 i2;
   i2.init(b, it.x0, it.y0);
+  // rho and e of plane r are fetched into registers one iteration ahead
+  // (clamped to the valid planes: the loads need no branch)
+  const int r0 = it.z0 - 2;
+  const int rlo = wall ? max(r0, 0) : r0;
+  const int rhi = wall ? min(it.z1, N - 1) : it.z1;
+  auto clampr = [&](int r_) { return r_ < rlo ? rlo : (r_ > rhi ? rhi : r_); };
+  T gr[I2::NPER], ge[I2::NPER];
+  auto fetch = [&](int r_) {
+    const long long pk = b.off + (long long)kk(r_) * pstride;
+#pragma unroll
+    for (int i = 0; i < I2::NPER; ++i) {
+      gr[i] = f.p[0][pk + i2.off[i]];
+      ge[i] = f.p[4][pk + i2.off[i]];
+    }
+  };
+  fetch(clampr(r0));
   for (int r = it.z0 - 2; r <= it.z1; ++r) {
     __syncthreads();
     if (valid(r)) {
       const int sl = wrapm(r, 3);
-      const T* __restrict__ pr = f.p[0] + b.off + (long long)kk(r) * pstride;
-      const T* __restrict__ pe = f.p[4] + b.off + (long long)kk(r) * pstride;
 #pragma unroll
       for (int i = 0; i < I2::NPER; ++i) {
         const int t = (int)threadIdx.x + i * NT;
-        const T rv = pr[i2.off[i]], ev = pe[i2.off[i]];
-        sLR[sl][t] = log(rv);
-        sLE[sl][t] = log(ev / rv);
+        sLR[sl][t] = log(gr[i]);
+        sLE[sl][t] = log(ge[i] / gr[i]);
       }
     }
+    fetch(clampr(r + 1));
     __syncthreads();
     const int p = r - 1;
     if (r < it.z0) continue;
