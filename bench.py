@@ -123,6 +123,19 @@ def measured_valu(dtype_name):
     return float(v) if v else None
 
 
+def stage_times(prof, steps):
+    """From the library's pass timings over `steps` RK steps ({pass: (total
+    ms, intervals)}): ms per RK stage of each pass that ran, with its
+    interval count, and the stage time (the sum over STAGE_PASSES).  A pass
+    may be timed in more than one interval of a stage (A2 on both sides of
+    the Courant dt kernel; Q on both sides of pass P with the second-order
+    switch), so the totals are divided by the stages, not the intervals."""
+    nst = 3 * steps
+    passes = {k: (v[0] / nst, v[1]) for k, v in prof.items() if v[1]}
+    stage = sum(prof[p][0] for p in STAGE_PASSES if p in prof) / nst
+    return passes, stage
+
+
 def make_state(workload, size, **kw):
     from paper_2405_02483_amd import inputs
     if workload == "stratified":
@@ -215,15 +228,13 @@ def run_gpu(size, dtype, steps, warmup, workload="stratified", tile=None, over=N
     del f, work
     torch.cuda.empty_cache()
     ms = (t1 - t0) * 1e3 / steps
-    stage_ms = sum(prof[p][0] for p in STAGE_PASSES) / (3 * steps)
+    passes, stage_ms = stage_times(prof, steps)
     return dict(ms_per_step=ms, value=ncell * steps / (t1 - t0), stage_ms=stage_ms,
                 launch={"tile": launch[0], "persistent": launch[1], "final_pass_tile": ftile},
                 autotune_ms_per_stage=None if tune is None else {
                     "%s/%s" % (k[0], "persistent" if k[1] else "grid"): round(v, 4)
                     for k, v in tune.items()},
-                # ms per RK stage of each pass (a pass may be timed in more
-                # than one interval of a stage: A2 around k_dt, Q around zRough)
-                passes={k: (v[0] / (3 * steps), v[1]) for k, v in prof.items() if v[1]},
+                passes=passes,
                 dt_last=dt_last, mass=s_end["mass"], ncell=ncell, window=gpu_win)
 
 

@@ -1,6 +1,6 @@
 """Host-side logic of bench.py (no GPU): the kernel-source hash that ties the
 committed HBM counters to the sources they were taken from, the counters'
-use, and the refusal of more than one GPU."""
+use, the per-stage pass times, and the refusal of more than one GPU."""
 import os
 import shutil
 import subprocess
@@ -50,3 +50,17 @@ def test_more_than_one_gpu_is_refused():
     assert r.returncode == 2
     assert "one GPU" in r.stderr
     assert r.stdout.strip() == ""
+
+
+def test_stage_times_are_per_stage_not_per_interval():
+    # two steps (six stages); A2 timed in 4 intervals per step, as around the
+    # Courant dt kernel in the first stage, one of them empty
+    prof = {"A1": (12.0, 6), "A2": (4.2, 8), "Q": (24.0, 6), "P": (18.0, 6),
+            "F": (45.0, 6), "ghost": (0.6, 8), "reduce": (0.02, 2), "unused": (0.0, 0)}
+    passes, stage = bench.stage_times(prof, 2)
+    assert set(passes) == {"A1", "A2", "Q", "P", "F", "ghost", "reduce"}
+    assert abs(passes["A2"][0] - 0.7) < 1e-12 and passes["A2"][1] == 8
+    assert abs(passes["A1"][0] - 2.0) < 1e-12
+    assert abs(stage - (12.0 + 4.2 + 24.0 + 18.0 + 45.0) / 6) < 1e-12
+    # the per-pass times of the stage passes add up to the stage time
+    assert abs(sum(passes[p][0] for p in bench.STAGE_PASSES) - stage) < 1e-12
